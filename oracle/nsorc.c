@@ -1,0 +1,967 @@
+/*
+ * Reference oracle: nested slice sampling with a TaylorF2 waveform and a
+ * Whittle likelihood, in plain double-precision C.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Used by the tests, the smoke check and the
+ * CPU-baseline leg of the benchmark to check the HIP library; it is never on
+ * the product path and shares no code with it.
+ *
+ * What the paper fixes (Sections 1-3):
+ *   - classic nested sampling whose particles are moved by a slice-sampling
+ *     MCMC walk; a static population; half of the live points deleted per
+ *     iteration; chains whose length is a multiple of the dimension; slice
+ *     directions tuned with the particle covariance (Section 2);
+ *   - a frequency-domain GW likelihood on a full grid or a coarse
+ *     heterodyned (relative-binning) grid (Sections 1 and 3);
+ *   - evidence estimates with error bars and the Kish effective sample size
+ *     of the weighted posterior samples (Sections 3 and 4).
+ * Everything else follows the textbook definitions of the cited methods
+ * (Skilling's nested sampling, Neal's slice sampling with stepping-out and
+ * shrinkage, the stationary-phase TaylorF2 waveform, the Whittle likelihood,
+ * relative binning); where the paper is silent the reading is stated at the
+ * function.
+ */
+#include "nsorc.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ---------------------------------------------------------------- constants */
+static const double PI = 3.14159265358979323846;
+static const double TSUN_S = 4.925490947641267e-6;        /* G Msun / c^3, s */
+static const double C_SI = 299792458.0;                    /* m / s */
+static const double PC_M = 3.0856775814913673e16;          /* parsec, m */
+static const double EULER_GAMMA = 0.57721566490153286061;
+
+/* RNG purposes (high 16 bits of the last counter word). */
+enum { P_INIT = 1, P_PICK = 2, P_DIR = 3, P_WIDTH = 4, P_SHRINK = 5, P_SIGMA = 7 };
+
+/* ------------------------------------------------------------ Philox4x64-10
+ * Counter-based generator of Salmon, Moraes, Dror and Shaw (SC'11): ten
+ * rounds of two 64x64->128 multiplications; the key is bumped by the Weyl
+ * constants between rounds. */
+static void mul128(uint64_t a, uint64_t b, uint64_t* hi, uint64_t* lo) {
+    unsigned __int128 p = (unsigned __int128)a * (unsigned __int128)b;
+    *hi = (uint64_t)(p >> 64);
+    *lo = (uint64_t)p;
+}
+
+void orc_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]) {
+    const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+    uint64_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint64_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) { k0 += W0; k1 += W1; }
+        uint64_t hi0, lo0, hi1, lo1;
+        mul128(M0, x0, &hi0, &lo0);
+        mul128(M1, x2, &hi1, &lo1);
+        uint64_t y0 = hi1 ^ x1 ^ k0, y1 = lo1, y2 = hi0 ^ x3 ^ k1, y3 = lo0;
+        x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* Uniform double in [0,1) from the top 53 bits. */
+static double to_unif(uint64_t x) { return (double)(x >> 11) * 0x1.0p-53; }
+
+typedef struct { uint64_t key[2]; } rngkey;
+
+static void draw(const rngkey* k, uint64_t c0, uint64_t c1, uint64_t c2, int purpose, uint64_t idx,
+                 uint64_t out[4]) {
+    uint64_t ctr[4] = {c0, c1, c2, ((uint64_t)purpose << 48) | idx};
+    orc_philox4x64(ctr, k->key, out);
+}
+
+/* ----------------------------------------------------------------- priors
+ * Unit-cube transforms: uniform; uniform in cos(theta) (isotropic
+ * inclination); uniform in sin(theta) (isotropic declination); uniform in
+ * volume (density proportional to d^2). */
+void orc_prior_transform(const orc_problem* p, const double* u, double* th) {
+    for (int i = 0; i < p->n_dim; ++i) {
+        double a = p->prior_lo[i], b = p->prior_hi[i], x = u[i];
+        switch (p->prior_kind[i]) {
+            case ORC_PRIOR_COS: th[i] = acos(cos(a) - x * (cos(a) - cos(b))); break;
+            case ORC_PRIOR_SIN: th[i] = asin(sin(a) + x * (sin(b) - sin(a))); break;
+            case ORC_PRIOR_VOLUME: th[i] = cbrt(a * a * a + x * (b * b * b - a * a * a)); break;
+            default: th[i] = a + (b - a) * x; break;
+        }
+    }
+}
+
+/* ------------------------------------------------------- detector response
+ * Long-wavelength response of an L-shaped interferometer: detector tensor
+ * D = (x x^T - y y^T)/2, polarisation tensors e+ = X X^T - Y Y^T and
+ * ex = X Y^T + Y X^T built from the wave-frame axes X, Y orthogonal to the
+ * source direction n; F+ = D:e+, Fx = D:ex.  The geocentre-to-detector
+ * arrival delay is dt = -(r . n)/c. */
+void orc_antenna(const double* g, double ra, double dec, double psi, double gmst,
+                 double* fplus, double* fcross, double* dt) {
+    double phi = ra - gmst;
+    double sp = sin(phi), cp = cos(phi), sd = sin(dec), cd = cos(dec), ss = sin(psi), cs = cos(psi);
+    double X[3] = {sp * cs - ss * cp * sd, -cp * cs - ss * sp * sd, ss * cd};
+    double Y[3] = {-sp * ss - cs * cp * sd, cp * ss - cs * sp * sd, cs * cd};
+    double D[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) D[i][j] = 0.5 * (g[3 + i] * g[3 + j] - g[6 + i] * g[6 + j]);
+    double fp = 0.0, fc = 0.0;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            fp += D[i][j] * (X[i] * X[j] - Y[i] * Y[j]);
+            fc += D[i][j] * (X[i] * Y[j] + Y[i] * X[j]);
+        }
+    double n[3] = {cd * cp, cd * sp, sd};
+    *fplus = fp;
+    *fcross = fc;
+    *dt = -(g[0] * n[0] + g[1] * n[1] + g[2] * n[2]) / C_SI;
+}
+
+/* --------------------------------------------------------------- TaylorF2
+ * Stationary-phase inspiral phase to 3.5PN with leading-order aligned-spin
+ * terms (spin-orbit beta at 1.5PN, spin-spin sigma at 2PN):
+ *   Psi(f) = 2 pi f t_c - phi_c - pi/4 + 3/(128 eta v^5) sum_k psi_k v^k,
+ *   v = (pi M f)^(1/3).
+ * ln v is used at 2.5PN (a constant offset from ln(v/v_lso) that phi_c
+ * absorbs). */
+double orc_tf2_phase(double f, double mc_msun, double eta, double beta, double sigma,
+                     double tc, double phic) {
+    double mc = mc_msun * TSUN_S;
+    double m = mc * pow(eta, -0.6);
+    double v = cbrt(PI * m * f);
+    double lv = log(v);
+    double e2 = eta * eta, e3 = e2 * eta;
+    double psi[8];
+    psi[0] = 1.0;
+    psi[1] = 0.0;
+    psi[2] = 3715.0 / 756.0 + 55.0 * eta / 9.0;
+    psi[3] = -16.0 * PI + 4.0 * beta;
+    psi[4] = 15293365.0 / 508032.0 + 27145.0 * eta / 504.0 + 3085.0 * e2 / 72.0 - 10.0 * sigma;
+    psi[5] = PI * (38645.0 / 756.0 - 65.0 * eta / 9.0) * (1.0 + 3.0 * lv);
+    psi[6] = 11583231236531.0 / 4694215680.0 - 640.0 * PI * PI / 3.0 - 6848.0 * EULER_GAMMA / 21.0
+             - (6848.0 / 21.0) * log(4.0 * v)
+             + (-15737765635.0 / 3048192.0 + 2255.0 * PI * PI / 12.0) * eta
+             + 76055.0 * e2 / 1728.0 - 127825.0 * e3 / 1296.0;
+    psi[7] = PI * (77096675.0 / 254016.0 + 378515.0 * eta / 1512.0 - 74045.0 * e2 / 756.0);
+    double sum = 0.0, vk = 1.0;
+    for (int k = 0; k < 8; ++k) { sum += psi[k] * vk; vk *= v; }
+    double v5 = v * v * v * v * v;
+    return 2.0 * PI * f * tc - phic - PI / 4.0 + 3.0 / (128.0 * eta * v5) * sum;
+}
+
+/* Source quantities shared by all frequencies for one parameter point. */
+typedef struct {
+    double mc_msun, eta, beta, sigma, tc, phic;
+    double amp;          /* sqrt(5/24) pi^(-2/3) Mc^(5/6) / D   (s) */
+    double f_isco;       /* 1 / (6^(3/2) pi M)                   (Hz) */
+    double hp_fac, hx_fac; /* plus: (1 + cos^2 i)/2, cross: cos i */
+    int one_det_optimal;   /* four-parameter model */
+    double ra, dec, psi;
+} source;
+
+static void make_source(const orc_problem* p, const double* th, source* s) {
+    memset(s, 0, sizeof(*s));
+    double dist_mpc;
+    if (p->model == ORC_MODEL_TF2_4P) {
+        s->mc_msun = th[0];
+        s->eta = th[1];
+        s->tc = th[2];
+        s->phic = th[3];
+        dist_mpc = p->fixed_dist_mpc;
+        s->hp_fac = 1.0;
+        s->hx_fac = 0.0;
+        s->one_det_optimal = 1;
+    } else {
+        double q = th[1], c1 = th[2], c2 = th[3];
+        s->mc_msun = th[0];
+        s->eta = q / ((1.0 + q) * (1.0 + q));
+        double m1 = 1.0 / (1.0 + q), m2 = q / (1.0 + q);   /* component masses / M */
+        s->beta = (c1 * (113.0 * m1 * m1 + 75.0 * s->eta) + c2 * (113.0 * m2 * m2 + 75.0 * s->eta)) / 12.0;
+        s->sigma = 79.0 / 8.0 * s->eta * c1 * c2;
+        dist_mpc = th[4];
+        double ci = cos(th[5]);
+        s->hp_fac = 0.5 * (1.0 + ci * ci);
+        s->hx_fac = ci;
+        s->psi = th[6];
+        s->ra = th[7];
+        s->dec = th[8];
+        s->tc = th[9];
+        s->phic = th[10];
+    }
+    double mc = s->mc_msun * TSUN_S;
+    double m = mc * pow(s->eta, -0.6);
+    double dist_s = dist_mpc * 1e6 * PC_M / C_SI;
+    s->amp = sqrt(5.0 / 24.0) * pow(PI, -2.0 / 3.0) * pow(mc, 5.0 / 6.0) / dist_s;
+    s->f_isco = 1.0 / (pow(6.0, 1.5) * PI * m);
+}
+
+/* Detector strain at one frequency, without the ISCO cut. */
+static void strain_at(const orc_problem* p, const source* s, double fp, double fc, double dt, double f,
+                      double* re, double* im) {
+    double psi = orc_tf2_phase(f, s->mc_msun, s->eta, s->beta, s->sigma, s->tc, s->phic);
+    double a = s->amp * pow(f, -7.0 / 6.0);
+    /* base = a e^{-i Psi} */
+    double br = a * cos(psi), bi = -a * sin(psi);
+    double hr, hi;
+    if (s->one_det_optimal) {
+        hr = br;
+        hi = bi;
+    } else {
+        /* h+ = hp_fac base, hx = -i hx_fac base; h = F+ h+ + Fx hx */
+        double pr = s->hp_fac * br, pi_ = s->hp_fac * bi;
+        double xr = s->hx_fac * bi, xi = -s->hx_fac * br;
+        double dr = fp * pr + fc * xr, di = fp * pi_ + fc * xi;
+        /* times e^{-2 pi i f dt} */
+        double ph = 2.0 * PI * f * dt;
+        double cr = cos(ph), ci = -sin(ph);
+        hr = dr * cr - di * ci;
+        hi = dr * ci + di * cr;
+    }
+    (void)p;
+    *re = hr;
+    *im = hi;
+}
+
+static void det_response(const orc_problem* p, const source* s, int det, double* fp, double* fc, double* dt) {
+    if (s->one_det_optimal) {
+        *fp = 1.0; *fc = 0.0; *dt = 0.0;
+        return;
+    }
+    orc_antenna(p->det_geom + 9 * det, s->ra, s->dec, s->psi, p->gmst, fp, fc, dt);
+}
+
+int orc_waveform(const orc_problem* p, const double* th, int det, int apply_cut, double* h_re, double* h_im) {
+    if (p->model != ORC_MODEL_TF2_4P && p->model != ORC_MODEL_TF2_11P) return -1;
+    if (det < 0 || det >= p->n_det) return -1;
+    source s;
+    make_source(p, th, &s);
+    double fp, fc, dt;
+    det_response(p, &s, det, &fp, &fc, &dt);
+    for (int k = 0; k < p->n_bins; ++k) {
+        double f = p->f_lo + k * p->df;
+        if (apply_cut && f > s.f_isco) {
+            h_re[k] = 0.0;
+            h_im[k] = 0.0;
+        } else {
+            strain_at(p, &s, fp, fc, dt, f, &h_re[k], &h_im[k]);
+        }
+    }
+    return 0;
+}
+
+/* ---------------------------------------------------------------- Whittle
+ * <a|b> = 4 df Re sum_k conj(a_k) b_k / S_k over the inclusive grid
+ * (rectangle rule).  The likelihood is reported as the log-likelihood ratio
+ * against the noise-only model: lambda = sum_det <d|h> - 1/2 <h|h>. */
+double orc_inner(const orc_problem* p, int det, const double* ar, const double* ai, const double* br,
+                 const double* bi) {
+    const double* S = p->psd + (long)det * p->n_bins;
+    double acc = 0.0;
+    for (int k = 0; k < p->n_bins; ++k) acc += (ar[k] * br[k] + ai[k] * bi[k]) / S[k];
+    return 4.0 * p->df * acc;
+}
+
+double orc_loglike_full(const orc_problem* p, const double* th) {
+    source s;
+    make_source(p, th, &s);
+    double lam = 0.0;
+    for (int det = 0; det < p->n_det; ++det) {
+        double fp, fc, dt;
+        det_response(p, &s, det, &fp, &fc, &dt);
+        const double* dr = p->data_re + (long)det * p->n_bins;
+        const double* di = p->data_im + (long)det * p->n_bins;
+        const double* S = p->psd + (long)det * p->n_bins;
+        double dh = 0.0, hh = 0.0;
+        for (int k = 0; k < p->n_bins; ++k) {
+            double f = p->f_lo + k * p->df;
+            if (f > s.f_isco) continue;   /* h = 0 above the ISCO frequency */
+            double hr, hi;
+            strain_at(p, &s, fp, fc, dt, f, &hr, &hi);
+            dh += 4.0 * p->df * (dr[k] * hr + di[k] * hi) / S[k];
+            hh += 4.0 * p->df * (hr * hr + hi * hi) / S[k];
+        }
+        lam += dh - 0.5 * hh;
+    }
+    return lam;
+}
+
+/* ------------------------------------------------------- relative binning
+ * Heterodyned likelihood: the ratio r(f) = h(f; theta) / h0(f) to a fiducial
+ * waveform h0 is modelled as linear inside each coarse bin,
+ * r(f) ~ r0_b + r1_b (f - fm_b), so <d|h> and <h|h> reduce to four summary
+ * sums per bin (A0, A1, B0, B1) precomputed once at the fiducial point.
+ * Readings: 128 geometric bins whose edges snap to the nearest fine-grid
+ * frequency; the fiducial is the untruncated waveform; bins above the ISCO
+ * frequency of theta are dropped and the straddling bin uses summary sums
+ * over its active fine bins only. */
+struct orc_rb {
+    const orc_problem* p;
+    int nb;
+    int* idx;         /* [nb+1] grid index of each edge */
+    double* fe;       /* [nb+1] edge frequency */
+    double* fm;       /* [nb] bin centre */
+    double* h0r;      /* [n_det][nb+1] fiducial strain at edges */
+    double* h0i;
+    double* a_r;      /* [n_det][n_bins] per fine bin 4 df conj(d) h0 / S */
+    double* a_i;
+    double* b;        /* [n_det][n_bins] per fine bin 4 df |h0|^2 / S */
+    double* A0r; double* A0i; double* A1r; double* A1i; double* B0; double* B1;  /* [n_det][nb] */
+};
+
+static int rb_last(const orc_rb* rb, int b) { return (b < rb->nb - 1) ? rb->idx[b + 1] - 1 : rb->idx[rb->nb]; }
+
+static void rb_sums(const orc_rb* rb, int det, int b, int k_end, double* a0r, double* a0i, double* a1r,
+                    double* a1i, double* b0, double* b1) {
+    const orc_problem* p = rb->p;
+    long off = (long)det * p->n_bins;
+    double s0r = 0, s0i = 0, s1r = 0, s1i = 0, t0 = 0, t1 = 0;
+    for (int k = rb->idx[b]; k <= k_end; ++k) {
+        double f = p->f_lo + k * p->df;
+        double x = f - rb->fm[b];
+        s0r += rb->a_r[off + k];
+        s0i += rb->a_i[off + k];
+        s1r += rb->a_r[off + k] * x;
+        s1i += rb->a_i[off + k] * x;
+        t0 += rb->b[off + k];
+        t1 += rb->b[off + k] * x;
+    }
+    *a0r = s0r; *a0i = s0i; *a1r = s1r; *a1i = s1i; *b0 = t0; *b1 = t1;
+}
+
+orc_rb* orc_rb_build(const orc_problem* p) {
+    if (p->model != ORC_MODEL_TF2_4P && p->model != ORC_MODEL_TF2_11P) return NULL;
+    int nb = p->rb_n_bins, nd = p->n_det, n = p->n_bins;
+    if (nb < 1 || nb >= n) return NULL;
+    orc_rb* rb = (orc_rb*)calloc(1, sizeof(orc_rb));
+    rb->p = p;
+    rb->nb = nb;
+    rb->idx = (int*)malloc(sizeof(int) * (nb + 1));
+    rb->fe = (double*)malloc(sizeof(double) * (nb + 1));
+    rb->fm = (double*)malloc(sizeof(double) * nb);
+    double f_hi = p->f_lo + (n - 1) * p->df;
+    for (int e = 0; e <= nb; ++e) {
+        double fe = p->f_lo * pow(f_hi / p->f_lo, (double)e / nb);
+        int k = (int)floor((fe - p->f_lo) / p->df + 0.5);
+        if (k < 0) k = 0;
+        if (k > n - 1) k = n - 1;
+        if (e == 0) k = 0;
+        if (e == nb) k = n - 1;
+        rb->idx[e] = k;
+        rb->fe[e] = p->f_lo + k * p->df;
+    }
+    for (int e = 0; e < nb; ++e)
+        if (rb->idx[e + 1] <= rb->idx[e]) { orc_rb_free(rb); return NULL; }
+    for (int b = 0; b < nb; ++b) rb->fm[b] = 0.5 * (rb->fe[b] + rb->fe[b + 1]);
+
+    rb->h0r = (double*)malloc(sizeof(double) * nd * (nb + 1));
+    rb->h0i = (double*)malloc(sizeof(double) * nd * (nb + 1));
+    rb->a_r = (double*)malloc(sizeof(double) * nd * n);
+    rb->a_i = (double*)malloc(sizeof(double) * nd * n);
+    rb->b = (double*)malloc(sizeof(double) * nd * n);
+    rb->A0r = (double*)malloc(sizeof(double) * nd * nb);
+    rb->A0i = (double*)malloc(sizeof(double) * nd * nb);
+    rb->A1r = (double*)malloc(sizeof(double) * nd * nb);
+    rb->A1i = (double*)malloc(sizeof(double) * nd * nb);
+    rb->B0 = (double*)malloc(sizeof(double) * nd * nb);
+    rb->B1 = (double*)malloc(sizeof(double) * nd * nb);
+    source s;
+    make_source(p, p->rb_fiducial, &s);
+    double* hr = (double*)malloc(sizeof(double) * n);
+    double* hi = (double*)malloc(sizeof(double) * n);
+    for (int det = 0; det < nd; ++det) {
+        double fp, fc, dt;
+        det_response(p, &s, det, &fp, &fc, &dt);
+        orc_waveform(p, p->rb_fiducial, det, 0, hr, hi);     /* untruncated fiducial */
+        long off = (long)det * n;
+        for (int k = 0; k < n; ++k) {
+            double S = p->psd[off + k];
+            double dr = p->data_re[off + k], di = p->data_im[off + k];
+            /* conj(d) h0 */
+            rb->a_r[off + k] = 4.0 * p->df * (dr * hr[k] + di * hi[k]) / S;
+            rb->a_i[off + k] = 4.0 * p->df * (dr * hi[k] - di * hr[k]) / S;
+            rb->b[off + k] = 4.0 * p->df * (hr[k] * hr[k] + hi[k] * hi[k]) / S;
+        }
+        for (int e = 0; e <= nb; ++e)
+            strain_at(p, &s, fp, fc, dt, rb->fe[e], &rb->h0r[det * (nb + 1) + e], &rb->h0i[det * (nb + 1) + e]);
+        for (int b = 0; b < nb; ++b) {
+            long o = (long)det * nb + b;
+            rb_sums(rb, det, b, rb_last(rb, b), &rb->A0r[o], &rb->A0i[o], &rb->A1r[o], &rb->A1i[o], &rb->B0[o],
+                    &rb->B1[o]);
+        }
+    }
+    free(hr);
+    free(hi);
+    return rb;
+}
+
+void orc_rb_free(orc_rb* rb) {
+    if (!rb) return;
+    free(rb->idx); free(rb->fe); free(rb->fm); free(rb->h0r); free(rb->h0i);
+    free(rb->a_r); free(rb->a_i); free(rb->b);
+    free(rb->A0r); free(rb->A0i); free(rb->A1r); free(rb->A1i); free(rb->B0); free(rb->B1);
+    free(rb);
+}
+
+int orc_rb_edges(const orc_rb* rb, int* edge_index) {
+    for (int e = 0; e <= rb->nb; ++e) edge_index[e] = rb->idx[e];
+    return rb->nb;
+}
+
+double orc_loglike_rb(const orc_rb* rb, const double* th) {
+    const orc_problem* p = rb->p;
+    int nb = rb->nb;
+    source s;
+    make_source(p, th, &s);
+    double lam = 0.0;
+    double* rr = (double*)malloc(sizeof(double) * (nb + 1));
+    double* ri = (double*)malloc(sizeof(double) * (nb + 1));
+    for (int det = 0; det < p->n_det; ++det) {
+        double fp, fc, dt;
+        det_response(p, &s, det, &fp, &fc, &dt);
+        for (int e = 0; e <= nb; ++e) {
+            double hr, hi;
+            strain_at(p, &s, fp, fc, dt, rb->fe[e], &hr, &hi);
+            double gr = rb->h0r[det * (nb + 1) + e], gi = rb->h0i[det * (nb + 1) + e];
+            double den = gr * gr + gi * gi;   /* r = h / h0 */
+            rr[e] = (hr * gr + hi * gi) / den;
+            ri[e] = (hi * gr - hr * gi) / den;
+        }
+        double dh = 0.0, hh = 0.0;
+        for (int b = 0; b < nb; ++b) {
+            int first = rb->idx[b], last = rb_last(rb, b);
+            if (p->f_lo + first * p->df > s.f_isco) break;   /* this and all later bins inactive */
+            long o = (long)det * nb + b;
+            double a0r, a0i, a1r, a1i, b0, b1;
+            if (p->f_lo + last * p->df <= s.f_isco) {
+                a0r = rb->A0r[o]; a0i = rb->A0i[o]; a1r = rb->A1r[o]; a1i = rb->A1i[o]; b0 = rb->B0[o]; b1 = rb->B1[o];
+            } else {
+                int ka = first;
+                while (ka + 1 <= last && p->f_lo + (ka + 1) * p->df <= s.f_isco) ++ka;
+                rb_sums(rb, det, b, ka, &a0r, &a0i, &a1r, &a1i, &b0, &b1);
+            }
+            double r0r = 0.5 * (rr[b] + rr[b + 1]), r0i = 0.5 * (ri[b] + ri[b + 1]);
+            double w = rb->fe[b + 1] - rb->fe[b];
+            double r1r = (rr[b + 1] - rr[b]) / w, r1i = (ri[b + 1] - ri[b]) / w;
+            /* Re(A0 r0 + A1 r1) */
+            dh += (a0r * r0r - a0i * r0i) + (a1r * r1r - a1i * r1i);
+            /* B0 |r0|^2 + 2 B1 Re(conj(r0) r1) */
+            hh += b0 * (r0r * r0r + r0i * r0i) + 2.0 * b1 * (r0r * r1r + r0i * r1i);
+        }
+        lam += dh - 0.5 * hh;
+    }
+    free(rr);
+    free(ri);
+    return lam;
+}
+
+/* ------------------------------------------------------ Gaussian test case
+ * lambda(u) = log N(u; mu, s^2 I): its evidence over the unit cube has the
+ * closed form sum_i log{[erf((1-mu_i)/(s sqrt 2)) + erf(mu_i/(s sqrt 2))]/2}. */
+double orc_loglike_gauss(const orc_problem* p, const double* u) {
+    double s = p->gauss_sigma, acc = 0.0;
+    for (int i = 0; i < p->n_dim; ++i) {
+        double z = (u[i] - p->gauss_mu[i]) / s;
+        acc += -0.5 * z * z - 0.5 * log(2.0 * PI * s * s);
+    }
+    return acc;
+}
+
+double orc_loglike_u(const orc_problem* p, const orc_rb* rb, const double* u) {
+    if (p->likelihood == ORC_LIKE_GAUSS) return orc_loglike_gauss(p, u);
+    double th[32];
+    orc_prior_transform(p, u, th);
+    if (p->likelihood == ORC_LIKE_RB) return orc_loglike_rb(rb, th);
+    return orc_loglike_full(p, th);
+}
+
+int orc_loglike_batch(const orc_problem* p, const double* u, long n, double* out, int n_threads) {
+    orc_rb* rb = NULL;
+    if (p->likelihood == ORC_LIKE_RB) {
+        rb = orc_rb_build(p);
+        if (!rb) return -1;
+    }
+    if (n_threads < 1) n_threads = 1;
+#pragma omp parallel for schedule(dynamic, 16) num_threads(n_threads)
+    for (long i = 0; i < n; ++i) out[i] = orc_loglike_u(p, rb, u + i * p->n_dim);
+    orc_rb_free(rb);
+    return 0;
+}
+
+/* -------------------------------------------------------------- selection
+ * Total order of the live points: by log-likelihood ascending, NaN treated
+ * as -inf, -0 equal to +0, ties broken by the lower slot.  The first k in
+ * that order die; L* is the k-th lowest value. */
+typedef struct { double v; int slot; } keyed;
+
+static double order_value(double x) {
+    if (isnan(x)) return -INFINITY;
+    if (x == 0.0) return 0.0;
+    return x;
+}
+
+static int cmp_keyed(const void* a, const void* b) {
+    const keyed* x = (const keyed*)a;
+    const keyed* y = (const keyed*)b;
+    if (x->v < y->v) return -1;
+    if (x->v > y->v) return 1;
+    return (x->slot > y->slot) - (x->slot < y->slot);
+}
+
+int orc_select(int n, const double* logl, int k, int* dead_idx, double* lstar) {
+    if (k < 1 || k > n) return -1;
+    keyed* a = (keyed*)malloc(sizeof(keyed) * n);
+    for (int i = 0; i < n; ++i) { a[i].v = order_value(logl[i]); a[i].slot = i; }
+    qsort(a, n, sizeof(keyed), cmp_keyed);
+    for (int j = 0; j < k; ++j) dead_idx[j] = a[j].slot;
+    *lstar = a[k - 1].v;
+    free(a);
+    return 0;
+}
+
+/* ------------------------------------------------------------ the sampler */
+struct orc_run {
+    orc_problem p;
+    orc_opts o;
+    orc_rb* rb;
+    rngkey key;
+    int d, n, k;
+    double* u;       /* [n][d] live points */
+    double* lam;     /* [n] */
+    double logX, logZ, H;
+    int iter, done;
+    long n_evals;
+    long cap, n_dead;
+    double* du; double* dlam; double* dlogx; double* dlogw;
+    int* diter; int* dslot; int* dnlive;
+};
+
+static double logaddexp(double a, double b) {
+    if (a == -INFINITY) return b;
+    if (b == -INFINITY) return a;
+    double m = a > b ? a : b;
+    return m + log(exp(a - m) + exp(b - m));
+}
+
+static double lam_at(const orc_run* r, const double* u, long* evals) {
+    ++*evals;
+    return orc_loglike_u(&r->p, r->rb, u);
+}
+
+/* Membership in the constrained slice: inside the unit cube first (no
+ * likelihood call outside it), then lambda > L* strictly. */
+static int in_slice(const orc_run* r, const double* y, double lstar, double* lam_out, long* evals) {
+    for (int i = 0; i < r->d; ++i)
+        if (!(y[i] >= 0.0 && y[i] <= 1.0)) return 0;
+    double l = lam_at(r, y, evals);
+    *lam_out = l;
+    return l > lstar;
+}
+
+static void along(int d, const double* x, double t, const double* dir, double* y) {
+    for (int i = 0; i < d; ++i) y[i] = fma(t, dir[i], x[i]);
+}
+
+/* One hit-and-run slice update (Neal 2003, stepping out and shrinkage) of
+ * chain state (x, lx) along direction dir with initial width w.  The step-out
+ * budget M is split between the two sides by the uniform uj (J = floor(M uj)
+ * steps left, M-1-J right), which keeps the capped procedure exact.  Shrink
+ * candidate a uses uniform ushr(a). */
+typedef double (*ushr_fn)(void* ctx, int a);
+
+static void slice_update(const orc_run* r, double* x, double* lx, const double* dir, double lstar, double w,
+                         double uw, double uj, ushr_fn ushr, void* uctx, long* evals) {
+    int d = r->d;
+    double y[32], ly = 0.0;
+    double lo = -w * uw, hi = lo + w;
+    int J = (int)floor(r->o.max_stepout * uj);
+    int K = r->o.max_stepout - 1 - J;
+    while (J > 0) {
+        along(d, x, lo, dir, y);
+        if (!in_slice(r, y, lstar, &ly, evals)) break;
+        lo -= w;
+        --J;
+    }
+    while (K > 0) {
+        along(d, x, hi, dir, y);
+        if (!in_slice(r, y, lstar, &ly, evals)) break;
+        hi += w;
+        --K;
+    }
+    for (int a = 0; a < r->o.max_shrink; ++a) {
+        double t = fma(ushr(uctx, a), hi - lo, lo);
+        along(d, x, t, dir, y);
+        if (in_slice(r, y, lstar, &ly, evals)) {
+            memcpy(x, y, sizeof(double) * d);
+            *lx = ly;
+            return;
+        }
+        if (t < 0.0) lo = t; else hi = t;
+    }
+}
+
+typedef struct { const rngkey* key; uint64_t t, j, s; } shrink_ctx;
+
+static double shrink_uniform(void* vctx, int a) {
+    shrink_ctx* c = (shrink_ctx*)vctx;
+    uint64_t o[4];
+    draw(c->key, c->t, c->j, c->s, P_SHRINK, (uint64_t)a >> 2, o);
+    return to_unif(o[a & 3]);
+}
+
+/* d standard normals for chain j, step s of iteration t (Box-Muller pairs). */
+static void normals(const rngkey* key, uint64_t t, uint64_t j, uint64_t s, int d, double* z) {
+    for (int i = 0; i < d; i += 2) {
+        uint64_t o[4];
+        draw(key, t, j, s, P_DIR, (uint64_t)(i >> 2), o);
+        int pr = (i & 3) >> 1;
+        double ua = to_unif(o[2 * pr]), ub = to_unif(o[2 * pr + 1]);
+        double rad = sqrt(-2.0 * log(1.0 - ua));
+        z[i] = rad * cos(2.0 * PI * ub);
+        if (i + 1 < d) z[i + 1] = rad * sin(2.0 * PI * ub);
+    }
+}
+
+static int cholesky(int d, const double* A, double* L) {
+    memset(L, 0, sizeof(double) * d * d);
+    for (int i = 0; i < d; ++i) {
+        for (int j = 0; j <= i; ++j) {
+            double s = A[i * d + j];
+            for (int q = 0; q < j; ++q) s -= L[i * d + q] * L[j * d + q];
+            if (i == j) {
+                if (!(s > 0.0)) return -1;
+                L[i * d + i] = sqrt(s);
+            } else {
+                L[i * d + j] = s / L[j * d + j];
+            }
+        }
+    }
+    return 0;
+}
+
+int orc_init(orc_run** out, const orc_problem* p, const orc_opts* o) {
+    *out = NULL;
+    if (p->n_dim < 1 || p->n_dim > 32 || o->n_live < 2 || o->n_delete < 1 || o->n_delete >= o->n_live) return -1;
+    orc_run* r = (orc_run*)calloc(1, sizeof(orc_run));
+    r->p = *p;
+    r->o = *o;
+    r->d = p->n_dim;
+    r->n = o->n_live;
+    r->k = o->n_delete;
+    r->key.key[0] = o->seed;
+    r->key.key[1] = o->run_id;
+    if (p->likelihood == ORC_LIKE_RB) {
+        r->rb = orc_rb_build(&r->p);
+        if (!r->rb) { free(r); return -2; }
+    }
+    r->u = (double*)malloc(sizeof(double) * r->n * r->d);
+    r->lam = (double*)malloc(sizeof(double) * r->n);
+    int nt = o->n_threads < 1 ? 1 : o->n_threads;
+    long evals = 0;
+#pragma omp parallel for schedule(dynamic, 4) num_threads(nt) reduction(+ : evals)
+    for (int j = 0; j < r->n; ++j) {
+        for (int i = 0; i < r->d; i += 4) {
+            uint64_t w[4];
+            draw(&r->key, 0, (uint64_t)j, 0, P_INIT, (uint64_t)(i >> 2), w);
+            for (int q = 0; q < 4 && i + q < r->d; ++q) r->u[j * r->d + i + q] = to_unif(w[q]);
+        }
+        long e = 0;
+        r->lam[j] = lam_at(r, r->u + j * r->d, &e);
+        evals += e;
+    }
+    r->n_evals = evals;
+    r->logX = 0.0;
+    r->logZ = -INFINITY;
+    r->H = 0.0;
+    int max_iter = o->max_iter > 0 ? o->max_iter : 1000;
+    r->cap = (long)max_iter * r->k;
+    r->du = (double*)malloc(sizeof(double) * r->cap * r->d);
+    r->dlam = (double*)malloc(sizeof(double) * r->cap);
+    r->dlogx = (double*)malloc(sizeof(double) * r->cap);
+    r->dlogw = (double*)malloc(sizeof(double) * r->cap);
+    r->diter = (int*)malloc(sizeof(int) * r->cap);
+    r->dslot = (int*)malloc(sizeof(int) * r->cap);
+    r->dnlive = (int*)malloc(sizeof(int) * r->cap);
+    *out = r;
+    return 0;
+}
+
+/* One "replace the k lowest" iteration. */
+static void iterate(orc_run* r) {
+    int n = r->n, k = r->k, d = r->d;
+    uint64_t t = (uint64_t)r->iter;
+    int* dead = (int*)malloc(sizeof(int) * k);
+    double lstar;
+    orc_select(n, r->lam, k, dead, &lstar);
+
+    /* Evidence: the j-th death of the batch shrinks the prior volume by the
+     * expected log-shrinkage -1/(n-j) of the largest of n-j uniforms; its
+     * weight is the volume between consecutive shells (rectangle rule). */
+    for (int j = 0; j < k; ++j) {
+        int nj = n - j;
+        double l = r->lam[dead[j]];
+        double logx_new = r->logX - 1.0 / nj;
+        double logw = order_value(l) + r->logX + log(-expm1(-1.0 / nj));
+        double logz_new = logaddexp(r->logZ, logw);
+        if (logw > -INFINITY) {
+            double h = exp(logw - logz_new) * order_value(l);
+            if (r->logZ > -INFINITY) h += exp(r->logZ - logz_new) * (r->H + r->logZ);
+            r->H = h - logz_new;
+        }
+        long q = r->n_dead++;
+        memcpy(r->du + q * d, r->u + dead[j] * d, sizeof(double) * d);
+        r->dlam[q] = l;
+        r->dlogx[q] = logx_new;
+        r->dlogw[q] = logw;
+        r->diter[q] = r->iter;
+        r->dslot[q] = dead[j];
+        r->dnlive[q] = nj;
+        r->logX = logx_new;
+        r->logZ = logz_new;
+    }
+
+    /* Direction tuning: covariance of all n live points (before removal),
+     * normalised by n-1, and its Cholesky factor. */
+    double mean[32] = {0}, cov[32 * 32], L[32 * 32];
+    for (int j = 0; j < n; ++j)
+        for (int i = 0; i < d; ++i) mean[i] += r->u[j * d + i];
+    for (int i = 0; i < d; ++i) mean[i] /= n;
+    for (int a = 0; a < d; ++a)
+        for (int b = 0; b < d; ++b) {
+            double s = 0.0;
+            for (int j = 0; j < n; ++j) s += (r->u[j * d + a] - mean[a]) * (r->u[j * d + b] - mean[b]);
+            cov[a * d + b] = s / (n - 1);
+        }
+    if (cholesky(d, cov, L) != 0) {
+        double tr = 0.0;
+        for (int i = 0; i < d; ++i) tr += cov[i * d + i];
+        for (int i = 0; i < d; ++i) cov[i * d + i] += 1e-12 * tr / d;
+        if (cholesky(d, cov, L) != 0) {
+            memset(L, 0, sizeof(L));
+            for (int i = 0; i < d; ++i) L[i * d + i] = 1e-6;
+        }
+    }
+
+    /* Survivors in ascending slot order; chain j starts from
+     * survivors[floor(u (n-k))]. */
+    char* is_dead = (char*)calloc(n, 1);
+    for (int j = 0; j < k; ++j) is_dead[dead[j]] = 1;
+    int* surv = (int*)malloc(sizeof(int) * (n - k));
+    int ns = 0;
+    for (int i = 0; i < n; ++i)
+        if (!is_dead[i]) surv[ns++] = i;
+
+    double* newu = (double*)malloc(sizeof(double) * k * d);
+    double* newl = (double*)malloc(sizeof(double) * k);
+    int nt = r->o.n_threads < 1 ? 1 : r->o.n_threads;
+    long evals = 0;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nt) reduction(+ : evals)
+    for (int j = 0; j < k; ++j) {
+        uint64_t w[4];
+        draw(&r->key, t, (uint64_t)j, 0, P_PICK, 0, w);
+        int start = surv[(int)floor(to_unif(w[0]) * (n - k))];
+        double x[32], lx = r->lam[start];
+        memcpy(x, r->u + start * d, sizeof(double) * d);
+        long e = 0;
+        for (int s = 0; s < r->o.n_steps; ++s) {
+            double z[32], dir[32], nrm = 0.0;
+            normals(&r->key, t, (uint64_t)j, (uint64_t)s, d, z);
+            for (int i = 0; i < d; ++i) nrm += z[i] * z[i];
+            nrm = sqrt(nrm);
+            for (int a = 0; a < d; ++a) {
+                double acc = 0.0;
+                for (int b = 0; b <= a; ++b) acc += L[a * d + b] * z[b];
+                dir[a] = acc / nrm;
+            }
+            uint64_t ww[4];
+            draw(&r->key, t, (uint64_t)j, (uint64_t)s, P_WIDTH, 0, ww);
+            shrink_ctx sc = {&r->key, t, (uint64_t)j, (uint64_t)s};
+            slice_update(r, x, &lx, dir, lstar, r->o.slice_width, to_unif(ww[0]), to_unif(ww[1]), shrink_uniform,
+                         &sc, &e);
+        }
+        memcpy(newu + j * d, x, sizeof(double) * d);
+        newl[j] = lx;
+        evals += e;
+    }
+    r->n_evals += evals;
+    /* Refill: chain j's final state replaces the j-th lowest dead slot. */
+    for (int j = 0; j < k; ++j) {
+        memcpy(r->u + dead[j] * d, newu + j * d, sizeof(double) * d);
+        r->lam[dead[j]] = newl[j];
+    }
+    free(newu); free(newl); free(surv); free(is_dead); free(dead);
+    r->iter++;
+
+    /* Termination: the evidence still held by the live points,
+     * logX + log mean exp(lambda_live), relative to the accumulated log Z. */
+    if (r->o.term_frac > 0.0) {
+        double m = -INFINITY;
+        for (int i = 0; i < n; ++i) if (order_value(r->lam[i]) > m) m = order_value(r->lam[i]);
+        double s = 0.0;
+        for (int i = 0; i < n; ++i) s += exp(order_value(r->lam[i]) - m);
+        double logz_live = r->logX + m + log(s / n);
+        if (logz_live - r->logZ < log(r->o.term_frac)) r->done = 1;
+    }
+    if (r->n_dead + r->k > r->cap) r->done = 1;
+}
+
+int orc_step(orc_run* r, int max_iters, int* done) {
+    for (int i = 0; i < max_iters && !r->done; ++i) iterate(r);
+    if (done) *done = r->done;
+    return 0;
+}
+
+int orc_state(const orc_run* r, double* logX, double* logZ, double* H, int* iter, long* n_dead, long* n_evals) {
+    if (logX) *logX = r->logX;
+    if (logZ) *logZ = r->logZ;
+    if (H) *H = r->H;
+    if (iter) *iter = r->iter;
+    if (n_dead) *n_dead = r->n_dead;
+    if (n_evals) *n_evals = r->n_evals;
+    return 0;
+}
+
+int orc_live(const orc_run* r, double* u, double* logl) {
+    if (u) memcpy(u, r->u, sizeof(double) * r->n * r->d);
+    if (logl) memcpy(logl, r->lam, sizeof(double) * r->n);
+    return 0;
+}
+
+int orc_dead(const orc_run* r, long cap, double* u, double* logl, double* logx, double* logw, int* iter, int* slot,
+             long* n_out) {
+    *n_out = r->n_dead;
+    if (cap < r->n_dead) return -3;
+    long nd = r->n_dead;
+    if (u) memcpy(u, r->du, sizeof(double) * nd * r->d);
+    if (logl) memcpy(logl, r->dlam, sizeof(double) * nd);
+    if (logx) memcpy(logx, r->dlogx, sizeof(double) * nd);
+    if (logw) memcpy(logw, r->dlogw, sizeof(double) * nd);
+    if (iter) memcpy(iter, r->diter, sizeof(int) * nd);
+    if (slot) memcpy(slot, r->dslot, sizeof(int) * nd);
+    return 0;
+}
+
+/* Final evidence: each remaining live point takes an equal share X_end / n
+ * of the remaining prior volume.  The error bar is the spread of log Z over
+ * n_sim replicas in which every log-shrinkage is redrawn from its
+ * distribution (log t = log U / n_j), beside Skilling's sqrt(H / n). */
+static double final_logz(const orc_run* r, double* logw_live) {
+    double z = r->logZ;
+    for (int i = 0; i < r->n; ++i) {
+        double lw = order_value(r->lam[i]) + r->logX - log((double)r->n);
+        if (logw_live) logw_live[i] = lw;
+        z = logaddexp(z, lw);
+    }
+    return z;
+}
+
+int orc_logZ(const orc_run* r, int n_sim, double* logZ, double* sigma_sim, double* sigma_h, double* ess) {
+    double z = final_logz(r, NULL);
+    if (logZ) *logZ = z;
+    if (sigma_h) {
+        /* H including the final live points */
+        double h = 0.0;
+        for (long q = 0; q < r->n_dead; ++q)
+            if (r->dlogw[q] > -INFINITY) h += exp(r->dlogw[q] - z) * order_value(r->dlam[q]);
+        for (int i = 0; i < r->n; ++i) {
+            double lw = order_value(r->lam[i]) + r->logX - log((double)r->n);
+            if (lw > -INFINITY) h += exp(lw - z) * order_value(r->lam[i]);
+        }
+        h -= z;
+        *sigma_h = sqrt(h > 0 ? h / r->n : 0.0);
+    }
+    if (ess) {
+        double s2 = 0.0;
+        for (long q = 0; q < r->n_dead; ++q) { double pq = exp(r->dlogw[q] - z); s2 += pq * pq; }
+        for (int i = 0; i < r->n; ++i) {
+            double pq = exp(order_value(r->lam[i]) + r->logX - log((double)r->n) - z);
+            s2 += pq * pq;
+        }
+        *ess = 1.0 / s2;
+    }
+    if (sigma_sim) {
+        if (n_sim < 2) { *sigma_sim = 0.0; return 0; }
+        double* zs = (double*)malloc(sizeof(double) * n_sim);
+        for (int rep = 0; rep < n_sim; ++rep) {
+            double lx = 0.0, zz = -INFINITY;
+            for (long q = 0; q < r->n_dead; ++q) {
+                uint64_t w[4];
+                draw(&r->key, (uint64_t)rep, (uint64_t)q, 0, P_SIGMA, 0, w);
+                double logt = log(1.0 - to_unif(w[0])) / r->dnlive[q];
+                double lw = order_value(r->dlam[q]) + lx + log(-expm1(logt));
+                zz = logaddexp(zz, lw);
+                lx += logt;
+            }
+            for (int i = 0; i < r->n; ++i) zz = logaddexp(zz, order_value(r->lam[i]) + lx - log((double)r->n));
+            zs[rep] = zz;
+        }
+        double m = 0.0;
+        for (int rep = 0; rep < n_sim; ++rep) m += zs[rep];
+        m /= n_sim;
+        double v = 0.0;
+        for (int rep = 0; rep < n_sim; ++rep) v += (zs[rep] - m) * (zs[rep] - m);
+        *sigma_sim = sqrt(v / (n_sim - 1));
+        free(zs);
+    }
+    return 0;
+}
+
+int orc_samples(const orc_run* r, long cap, double* theta, double* logl, double* logw, long* n_out) {
+    long total = r->n_dead + r->n;
+    *n_out = total;
+    if (cap < total) return -3;
+    double z = final_logz(r, NULL);
+    int d = r->d;
+    for (long q = 0; q < r->n_dead; ++q) {
+        if (theta) {
+            if (r->p.likelihood == ORC_LIKE_GAUSS) memcpy(theta + q * d, r->du + q * d, sizeof(double) * d);
+            else orc_prior_transform(&r->p, r->du + q * d, theta + q * d);
+        }
+        if (logl) logl[q] = r->dlam[q];
+        if (logw) logw[q] = r->dlogw[q] - z;
+    }
+    for (int i = 0; i < r->n; ++i) {
+        long q = r->n_dead + i;
+        if (theta) {
+            if (r->p.likelihood == ORC_LIKE_GAUSS) memcpy(theta + q * d, r->u + i * d, sizeof(double) * d);
+            else orc_prior_transform(&r->p, r->u + i * d, theta + q * d);
+        }
+        if (logl) logl[q] = r->lam[i];
+        if (logw) logw[q] = order_value(r->lam[i]) + r->logX - log((double)r->n) - z;
+    }
+    return 0;
+}
+
+void orc_free(orc_run* r) {
+    if (!r) return;
+    orc_rb_free(r->rb);
+    free(r->u); free(r->lam);
+    free(r->du); free(r->dlam); free(r->dlogx); free(r->dlogw); free(r->diter); free(r->dslot); free(r->dnlive);
+    free(r);
+}
+
+/* -------------------------------------------------------- test entry point
+ * One slice update with caller-supplied direction and uniforms, on the
+ * problem's likelihood, for hand-checked bracket and shrink sequences. */
+typedef struct { const double* u; int n; } fixed_u;
+
+static double fixed_uniform(void* vctx, int a) {
+    fixed_u* c = (fixed_u*)vctx;
+    return a < c->n ? c->u[a] : 0.5;
+}
+
+int orc_slice_update_fixed(const orc_problem* p, const orc_opts* o, double* x, double* lx, const double* dir,
+                           double lstar, double uw, double uj, const double* ushr, int n_ushr, long* evals) {
+    orc_run r;
+    memset(&r, 0, sizeof(r));
+    r.p = *p;
+    r.o = *o;
+    r.d = p->n_dim;
+    if (p->likelihood == ORC_LIKE_RB) return -1;
+    fixed_u c = {ushr, n_ushr};
+    *evals = 0;
+    slice_update(&r, x, lx, dir, lstar, o->slice_width, uw, uj, fixed_uniform, &c, evals);
+    return 0;
+}
