@@ -1,0 +1,202 @@
+/*
+ * ns.h -- C ABI of libns, nested slice sampling for gravitational-wave
+ * parameter estimation on AMD Instinct MI355X (gfx950).
+ *
+ * The method (paper Section 2): classic nested sampling over a static
+ * population of n_live points; each iteration deletes the n_delete
+ * lowest-likelihood points, adds their prior-volume shells to the evidence,
+ * and refills the deleted slots by running one constrained hit-and-run slice
+ * sampling chain per deleted point, started from a surviving point, with
+ * directions tuned by the particle covariance.  Each probe of a chain costs
+ * one frequency-domain waveform plus a noise-weighted (Whittle) likelihood,
+ * on the full frequency grid or on a coarse heterodyned grid (relative
+ * binning; Sections 1 and 3).
+ *
+ * Conventions shared by every entry point:
+ *   - Return value: NS_OK (0) on success, a negative ns_status on failure.
+ *     Nothing aborts or throws across the ABI; ns_last_error() returns a
+ *     thread-local message describing the most recent failure.  On failure
+ *     no state is left half-built (an ns_run is either complete or NULL).
+ *   - "host" pointers are ordinary CPU memory owned by the caller and only
+ *     read (or written, for outputs) during the call.  "device" pointers are
+ *     HIP device allocations owned by the caller.
+ *   - Arrays are row-major and contiguous; all floating point is IEEE double
+ *     unless stated.
+ *   - stream: a hipStream_t passed as void* (NULL = the default stream);
+ *     borrowed, never destroyed by the library.  Every kernel of a run is
+ *     launched on the run's stream.
+ *   - The unit cube: sampling happens in u in [0,1]^n_dim; prior transforms
+ *     map u to physical parameters.
+ *   - The likelihood is reported as the log-likelihood ratio against the
+ *     noise-only model, lambda = sum_det [<d|h> - 1/2 <h|h>], with
+ *     <a|b> = 4 df Re sum_k conj(a_k) b_k / S_k over the inclusive grid
+ *     f_k = f_lo + k df; the waveform is zero above the innermost-stable-
+ *     circular-orbit frequency f_ISCO = 1/(6^(3/2) pi M).  log Z is therefore
+ *     the log Bayes factor of signal against noise.
+ */
+#ifndef NS_H
+#define NS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__)
+#define NS_API __attribute__((visibility("default")))
+#else
+#define NS_API
+#endif
+
+typedef enum {
+    NS_OK = 0,
+    NS_E_ARG = -1,      /* invalid argument (sizes, ranges, NULL pointers) */
+    NS_E_OOM = -2,      /* device or host allocation failed */
+    NS_E_HIP = -3,      /* a HIP runtime call failed */
+    NS_E_CAPACITY = -4, /* caller buffer too small; the required size is reported */
+    NS_E_STATE = -5     /* call not valid in the run's current state */
+} ns_status;
+
+/* Prior kinds for one unit-cube coordinate with interval [lo, hi]:
+ *   UNIFORM  theta = lo + (hi - lo) u
+ *   COS      uniform in cos(theta), 0 <= lo < hi <= pi   (isotropic inclination)
+ *   SIN      uniform in sin(theta), -pi/2 <= lo < hi <= pi/2 (isotropic declination)
+ *   VOLUME   density proportional to theta^2, 0 <= lo < hi (uniform in volume) */
+enum { NS_PRIOR_UNIFORM = 0, NS_PRIOR_COS = 1, NS_PRIOR_SIN = 2, NS_PRIOR_VOLUME = 3 };
+
+/* Waveform models (stationary-phase TaylorF2, 3.5PN phase, Newtonian amplitude):
+ *   TF2_4P   parameters (Mc [Msun], eta, t_c [s], phi_c [rad]); one detector,
+ *            optimally oriented (antenna factor 1, no delay), at the fixed
+ *            distance fixed_dist_mpc.
+ *   TF2_11P  parameters (Mc [Msun], q = m2/m1 in (0,1], chi1, chi2 (aligned
+ *            spins), d_L [Mpc], theta_jn [rad], psi [rad], RA [rad], Dec [rad],
+ *            t_c [s], phi_c [rad]); a detector network. */
+enum { NS_MODEL_TF2_4P = 1, NS_MODEL_TF2_11P = 2 };
+
+/* Likelihood forms: full grid; relative binning (heterodyned coarse grid,
+ * rb_n_bins geometric bins, fiducial waveform at rb_fiducial); and a
+ * Gaussian test likelihood N(u; gauss_mu, gauss_sigma^2 I) on the unit cube
+ * (for evidence checks against its closed form). */
+enum { NS_LIKE_FULL = 0, NS_LIKE_RB = 1, NS_LIKE_GAUSS = 2 };
+
+/* Arithmetic: all double, or the mixed form (float bulk, double phase and evidence). */
+enum { NS_FP64 = 0, NS_MIXED = 1 };
+
+typedef struct {
+    int model;                 /* NS_MODEL_*; ignored for NS_LIKE_GAUSS */
+    int likelihood;            /* NS_LIKE_* */
+    int n_dim;                 /* 1..12; must match the model (4 or 11) unless GAUSS */
+    const int* prior_kind;     /* host [n_dim] */
+    const double* prior_lo;    /* host [n_dim] */
+    const double* prior_hi;    /* host [n_dim] */
+    double f_lo, df;           /* grid f_k = f_lo + k df, Hz; f_lo > 0, df > 0 */
+    int n_bins;                /* >= 2 */
+    int n_det;                 /* 1..3 (exactly 1 for TF2_4P) */
+    const double* data_re;     /* host [n_det][n_bins], strain/Hz */
+    const double* data_im;     /* host [n_det][n_bins] */
+    const double* psd;         /* host [n_det][n_bins], one-sided, 1/Hz, > 0 */
+    const double* det_geom;    /* host [n_det][9]: vertex (m, Earth-fixed), x-arm, y-arm unit vectors */
+    double gmst;               /* Greenwich sidereal angle, rad */
+    double fixed_dist_mpc;     /* TF2_4P only: distance, Mpc, > 0 */
+    int rb_n_bins;             /* NS_LIKE_RB: number of coarse bins (1..n_bins-1) */
+    const double* rb_fiducial; /* NS_LIKE_RB: host [n_dim] physical fiducial parameters */
+    const double* gauss_mu;    /* NS_LIKE_GAUSS: host [n_dim] */
+    double gauss_sigma;        /* NS_LIKE_GAUSS: > 0 */
+} ns_problem;
+
+typedef struct {
+    int n_live;          /* live population n, 2..16384 */
+    int n_delete;        /* deleted per iteration k, 1..n_live-1 (the paper uses n_live/2) */
+    int n_steps;         /* slice steps per chain per iteration (a multiple of n_dim) */
+    double slice_width;  /* initial bracket width w along the tuned direction (> 0) */
+    int max_stepout;     /* step-out budget per step, split between the sides (>= 1) */
+    int max_shrink;      /* shrink attempts per step before the state is kept (>= 1) */
+    double term_frac;    /* stop when the live evidence fraction falls below it; <= 0 never */
+    uint64_t seed;       /* Philox key word 0 */
+    uint64_t run_id;     /* Philox key word 1 */
+    int max_iter;        /* iteration capacity of the dead-point record (>= 1) */
+    int precision;       /* NS_FP64 or NS_MIXED */
+} ns_opts;
+
+typedef struct ns_run ns_run;
+
+/* Create a run: validate, copy the problem to HBM, build the likelihood
+ * tables (and relative-binning summary data), draw n_live prior points and
+ * evaluate them.  The run's state then stays resident on the device.
+ * out: receives the run (NULL on failure).  Host arrays may be freed on
+ * return.  Errors: NS_E_ARG, NS_E_OOM, NS_E_HIP. */
+NS_API int ns_init(ns_run** out, const ns_problem* problem, const ns_opts* opts, void* stream);
+
+/* Run up to max_iters "replace the k lowest" iterations (Section 2): select
+ * the k lowest (ties to the lower slot, NaN as -inf), update log X, log Z and
+ * the information H, tune directions from the covariance of the live points,
+ * run the k slice chains, refill the dead slots, test termination.  Once the
+ * termination test passes the remaining enqueued iterations do nothing.
+ * Synchronises the stream; done (may be NULL) receives 1 when the run has
+ * terminated (criterion met or capacity reached). */
+NS_API int ns_step(ns_run* run, int max_iters, int* done);
+
+/* Enqueue n_iters iterations on the run's stream without synchronising. */
+NS_API int ns_step_async(ns_run* run, int n_iters);
+
+/* Final evidence: dead shells plus the live points, each taking X_end/n.
+ * logZ: log Bayes factor; sigma_sim: spread of log Z over n_sim replicas with
+ * redrawn prior-volume shrinkages (n_sim >= 2, else 0); sigma_h:
+ * sqrt(H / n_live); ess: Kish effective sample size 1/sum p_i^2.  Any output
+ * pointer may be NULL.  Synchronises. */
+NS_API int ns_logZ(ns_run* run, int n_sim, double* logZ, double* sigma_sim, double* sigma_h, double* ess);
+
+/* Weighted posterior samples: dead points in death order, then the live
+ * points in slot order.  theta: host [cap][n_dim] physical parameters
+ * (unit-cube coordinates for GAUSS); logl: host [cap]; logw: host [cap],
+ * normalised so that sum exp(logw) = 1.  n_out receives the count; returns
+ * NS_E_CAPACITY (with n_out set) if cap is too small.  Outputs may be NULL. */
+NS_API int ns_samples(ns_run* run, long cap, double* theta, double* logl, double* logw, long* n_out);
+
+/* Scalars of the run (any pointer may be NULL).  n_evals counts likelihood
+ * evaluations (probes inside the unit cube, plus the initial population). */
+NS_API int ns_state(ns_run* run, double* logX, double* logZ, double* H, int* iter, long* n_dead, long* n_evals,
+             int* done);
+
+/* Live population, host [n_live][n_dim] and [n_live] (either may be NULL). */
+NS_API int ns_live(ns_run* run, double* u, double* logl);
+
+/* Dead-point record, in death order: unit-cube point, lambda, log X after the
+ * death, log w (unnormalised), iteration and slot.  Host arrays of length
+ * cap (u: cap*n_dim); any may be NULL.  NS_E_CAPACITY if cap < count. */
+NS_API int ns_dead(ns_run* run, long cap, double* u, double* logl, double* logx, double* logw, int* iter, int* slot,
+            long* n_out);
+
+/* Batched likelihood with the run's tables: out[i] = lambda(u[i]).
+ * u_dev: device [n][n_dim] unit-cube points; out_dev: device [n].  Launched
+ * on the run's stream, asynchronous.  This is the fused waveform-plus-
+ * likelihood kernel the slice chains call, exposed for direct use. */
+NS_API int ns_loglike(ns_run* run, const double* u_dev, long n, double* out_dev);
+
+/* Detector strain h_det(f_k) of the problem's model at physical parameters
+ * theta (host [n_dim]) on the problem's grid, computed on the device.
+ * apply_cut = 1 zeroes bins above f_ISCO.  h_re, h_im: host [n_bins].
+ * Only the model, grid, detector and fixed-distance fields of problem are
+ * read.  Synchronises the stream. */
+NS_API int ns_waveform(const ns_problem* problem, const double* theta, int det, int apply_cut, double* h_re,
+                double* h_im, void* stream);
+
+/* k lowest of n values (Section 2 deletion step) in the sampler's total order:
+ * ascending lambda, NaN ordered as -inf, -0 equal to +0, ties to the lower
+ * index.  logl_dev: device [n]; dead_dev: device [k] receives the indices in
+ * ascending order; lstar_dev: device [1] receives the k-th lowest value.
+ * 1 <= k <= n <= 16384.  Asynchronous on stream. */
+NS_API int ns_select(const double* logl_dev, int n, int k, int* dead_dev, double* lstar_dev, void* stream);
+
+/* Release a run (NULL is allowed). */
+NS_API void ns_free(ns_run* run);
+
+/* Message for the calling thread's most recent failure ("" if none). */
+NS_API const char* ns_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

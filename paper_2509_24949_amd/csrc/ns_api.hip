@@ -1,0 +1,442 @@
+// Host runtime of libns: argument validation, device memory of a run, the
+// C ABI declared in include/ns.h.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/ns.h"
+#include "ns_internal.h"
+
+using namespace ns;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_OK(expr)                                                                         \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess) return fail(NS_E_HIP, "%s: %s", #expr, hipGetErrorString(e_));    \
+  } while (0)
+
+// Device allocations of one run, released together.
+struct DevMem {
+  std::vector<void*> ptrs;
+  ~DevMem() {
+    for (void* p : ptrs) (void)hipFree(p);
+  }
+  template <typename T>
+  hipError_t alloc(T** out, size_t count) {
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T));
+    if (e == hipSuccess) ptrs.push_back(p);
+    *out = static_cast<T*>(p);
+    return e;
+  }
+};
+
+}  // namespace
+
+struct ns_run {
+  ModelDev M{};
+  Tables T{};
+  RBTables RB{};
+  RunDev R{};
+  LaunchCfg C{};
+  hipStream_t st = nullptr;
+  DevMem mem;
+  DevState* h_state = nullptr;   // pinned mirror of the device scalars
+  ~ns_run() {
+    if (h_state) (void)hipHostFree(h_state);
+  }
+};
+
+namespace {
+
+int validate_and_model(const ns_problem* P, ModelDev* M) {
+  if (!P) return fail(NS_E_ARG, "problem is NULL");
+  memset(M, 0, sizeof(*M));
+  if (P->n_dim < 1 || P->n_dim > MAX_DIM) return fail(NS_E_ARG, "n_dim must be in [1, %d]", MAX_DIM);
+  if (P->likelihood < NS_LIKE_FULL || P->likelihood > NS_LIKE_GAUSS) return fail(NS_E_ARG, "unknown likelihood form");
+  if (!P->prior_kind || !P->prior_lo || !P->prior_hi) return fail(NS_E_ARG, "prior arrays are NULL");
+  M->likelihood = P->likelihood;
+  M->n_dim = P->n_dim;
+  for (int i = 0; i < P->n_dim; ++i) {
+    const int k = P->prior_kind[i];
+    const double lo = P->prior_lo[i], hi = P->prior_hi[i];
+    if (!(lo <= hi) || !isfinite(lo) || !isfinite(hi)) return fail(NS_E_ARG, "prior %d: need finite lo <= hi", i);
+    M->prior.kind[i] = k;
+    M->prior.lo[i] = lo;
+    M->prior.hi[i] = hi;
+    switch (k) {
+      case NS_PRIOR_UNIFORM: M->prior.a[i] = lo; M->prior.b[i] = hi - lo; break;
+      case NS_PRIOR_COS:
+        if (lo < 0.0 || hi > PI) return fail(NS_E_ARG, "prior %d: COS needs 0 <= lo <= hi <= pi", i);
+        M->prior.a[i] = cos(lo); M->prior.b[i] = cos(hi) - cos(lo); break;
+      case NS_PRIOR_SIN:
+        if (lo < -0.5 * PI || hi > 0.5 * PI) return fail(NS_E_ARG, "prior %d: SIN needs -pi/2 <= lo <= hi <= pi/2", i);
+        M->prior.a[i] = sin(lo); M->prior.b[i] = sin(hi) - sin(lo); break;
+      case NS_PRIOR_VOLUME:
+        if (lo < 0.0) return fail(NS_E_ARG, "prior %d: VOLUME needs lo >= 0", i);
+        M->prior.a[i] = lo * lo * lo; M->prior.b[i] = hi * hi * hi - lo * lo * lo; break;
+      default: return fail(NS_E_ARG, "prior %d: unknown kind %d", i, k);
+    }
+  }
+  if (P->likelihood == NS_LIKE_GAUSS) {
+    if (!P->gauss_mu || !(P->gauss_sigma > 0.0)) return fail(NS_E_ARG, "Gaussian likelihood needs mu and sigma > 0");
+    for (int i = 0; i < P->n_dim; ++i) M->gauss_mu[i] = P->gauss_mu[i];
+    const double s = P->gauss_sigma;
+    M->gauss_inv2s2 = 1.0 / (2.0 * s * s);
+    M->gauss_norm = -0.5 * P->n_dim * log(2.0 * PI * s * s);
+    M->n_det = 1;
+    M->n_bins = 0;
+    return NS_OK;
+  }
+  if (P->model != NS_MODEL_TF2_4P && P->model != NS_MODEL_TF2_11P) return fail(NS_E_ARG, "unknown waveform model");
+  M->model = P->model;
+  if (P->model == NS_MODEL_TF2_4P && (P->n_dim != 4 || P->n_det != 1))
+    return fail(NS_E_ARG, "TF2_4P needs n_dim = 4 and n_det = 1");
+  if (P->model == NS_MODEL_TF2_11P && (P->n_dim != 11 || P->n_det < 1 || P->n_det > MAX_DET))
+    return fail(NS_E_ARG, "TF2_11P needs n_dim = 11 and 1 <= n_det <= %d", MAX_DET);
+  if (!(P->f_lo > 0.0) || !(P->df > 0.0) || P->n_bins < 2) return fail(NS_E_ARG, "grid needs f_lo > 0, df > 0, n_bins >= 2");
+  if (!P->data_re || !P->data_im || !P->psd) return fail(NS_E_ARG, "data and psd arrays are NULL");
+  for (long i = 0; i < (long)P->n_det * P->n_bins; ++i)
+    if (!(P->psd[i] > 0.0) || !isfinite(P->data_re[i]) || !isfinite(P->data_im[i]))
+      return fail(NS_E_ARG, "psd must be positive and data finite (index %ld)", i);
+  M->n_det = P->n_det;
+  M->n_bins = P->n_bins;
+  M->f_lo = P->f_lo;
+  M->df = P->df;
+  M->gmst = P->gmst;
+  // the largest f_ISCO over the prior box bounds the active bins
+  double mc_min = P->prior_lo[0], eta_max;
+  if (!(mc_min > 0.0)) return fail(NS_E_ARG, "chirp-mass prior must be positive");
+  if (P->model == NS_MODEL_TF2_4P) {
+    if (!(P->prior_lo[1] > 0.0) || P->prior_hi[1] > 0.25) return fail(NS_E_ARG, "eta prior must lie in (0, 0.25]");
+    if (!(P->fixed_dist_mpc > 0.0)) return fail(NS_E_ARG, "fixed_dist_mpc must be positive");
+    eta_max = P->prior_hi[1];
+    M->fixed_dist_s = P->fixed_dist_mpc * MPC_S;
+  } else {
+    if (!(P->prior_lo[1] > 0.0) || P->prior_hi[1] > 1.0) return fail(NS_E_ARG, "mass-ratio prior must lie in (0, 1]");
+    if (!(P->prior_lo[4] > 0.0)) return fail(NS_E_ARG, "distance prior must be positive");
+    if (!P->det_geom) return fail(NS_E_ARG, "det_geom is NULL");
+    const double q = P->prior_hi[1];
+    eta_max = q / ((1.0 + q) * (1.0 + q));
+    for (int d = 0; d < P->n_det; ++d) {
+      const double* g = P->det_geom + 9 * d;
+      const double* x = g + 3;
+      const double* y = g + 6;
+      double* D = M->det[d].D;
+      D[0] = 0.5 * (x[0] * x[0] - y[0] * y[0]);
+      D[1] = 0.5 * (x[0] * x[1] - y[0] * y[1]);
+      D[2] = 0.5 * (x[0] * x[2] - y[0] * y[2]);
+      D[3] = 0.5 * (x[1] * x[1] - y[1] * y[1]);
+      D[4] = 0.5 * (x[1] * x[2] - y[1] * y[2]);
+      D[5] = 0.5 * (x[2] * x[2] - y[2] * y[2]);
+      for (int i = 0; i < 3; ++i) M->det[d].r_c[i] = g[i] / C_SI;
+    }
+  }
+  const double m_min = mc_min * TSUN_S * pow(eta_max, -0.6);
+  const double f_max = 1.0 / (pow(6.0, 1.5) * PI * m_min) * (1.0 + 1e-9);
+  const double kk = floor((f_max - P->f_lo) / P->df) + 2.0;
+  M->k_lim = (int)std::min<double>((double)P->n_bins, std::max(0.0, kk));
+  if (P->likelihood == NS_LIKE_RB) return fail(NS_E_ARG, "relative binning is not available in this build");
+  return NS_OK;
+}
+
+int validate_opts(const ns_opts* o) {
+  if (!o) return fail(NS_E_ARG, "opts is NULL");
+  if (o->n_live < 2 || o->n_live > 16384) return fail(NS_E_ARG, "n_live must be in [2, 16384]");
+  if (o->n_delete < 1 || o->n_delete >= o->n_live) return fail(NS_E_ARG, "n_delete must be in [1, n_live - 1]");
+  if (o->n_steps < 1) return fail(NS_E_ARG, "n_steps must be >= 1");
+  if (!(o->slice_width > 0.0)) return fail(NS_E_ARG, "slice_width must be > 0");
+  if (o->max_stepout < 1 || o->max_shrink < 1) return fail(NS_E_ARG, "max_stepout and max_shrink must be >= 1");
+  if (o->max_iter < 1) return fail(NS_E_ARG, "max_iter must be >= 1");
+  if (o->precision != NS_FP64) return fail(NS_E_ARG, "only NS_FP64 is available in this build");
+  return NS_OK;
+}
+
+int sync_state(ns_run* r) {
+  HIP_OK(hipMemcpyAsync(r->h_state, r->R.state, sizeof(DevState), hipMemcpyDeviceToHost, r->st));
+  HIP_OK(hipStreamSynchronize(r->st));
+  return NS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ns_last_error(void) { return g_err.c_str(); }
+
+int ns_init(ns_run** out, const ns_problem* P, const ns_opts* O, void* stream) {
+  if (!out) return fail(NS_E_ARG, "out is NULL");
+  *out = nullptr;
+  ModelDev M;
+  int rc = validate_and_model(P, &M);
+  if (rc) return rc;
+  if ((rc = validate_opts(O))) return rc;
+  ns_run* r = new (std::nothrow) ns_run();
+  if (!r) return fail(NS_E_OOM, "host allocation failed");
+  r->M = M;
+  r->st = static_cast<hipStream_t>(stream);
+  const int n = O->n_live, k = O->n_delete, d = P->n_dim;
+  RunDev& R = r->R;
+  R.n = n; R.k = k; R.d = d; R.m = O->n_steps;
+  R.width = O->slice_width;
+  R.max_stepout = O->max_stepout;
+  R.max_shrink = O->max_shrink;
+  R.log_term = O->term_frac > 0.0 ? log(O->term_frac) : -__builtin_inf();
+  R.key0 = O->seed;
+  R.key1 = O->run_id;
+  R.cap = (long long)O->max_iter * k;
+  auto cleanup = [&](int code) { delete r; return code; };
+  DevMem& mem = r->mem;
+#define ALLOC(ptr, count) \
+  if (mem.alloc(&(ptr), (count)) != hipSuccess) return cleanup(fail(NS_E_OOM, "hipMalloc failed for " #ptr))
+  ALLOC(R.state, 1);
+  ALLOC(R.u, (size_t)n * d);
+  ALLOC(R.lam, n);
+  ALLOC(R.rank, n);
+  ALLOC(R.dead, k);
+  ALLOC(R.surv, n);
+  ALLOC(R.start, k);
+  ALLOC(R.chol, (size_t)d * d);
+  ALLOC(R.probes, k);
+  ALLOC(R.stepout_hits, k);
+  ALLOC(R.du, (size_t)R.cap * d);
+  ALLOC(R.dlam, R.cap);
+  ALLOC(R.dlogx, R.cap);
+  ALLOC(R.dlogw, R.cap);
+  ALLOC(R.diter, R.cap);
+  ALLOC(R.dslot, R.cap);
+  ALLOC(R.dnlive, R.cap);
+  if (hipHostMalloc((void**)&r->h_state, sizeof(DevState), hipHostMallocDefault) != hipSuccess)
+    return cleanup(fail(NS_E_OOM, "pinned allocation failed"));
+
+  hipError_t e;
+  if (M.likelihood != NS_LIKE_GAUSS) {
+    const size_t nbd = (size_t)M.n_det * M.n_bins;
+    double *f, *f13, *lnf3, *fm53, *hpre, *dre, *dim, *psd, *scratch;
+    double2* dw;
+    ALLOC(f, M.n_bins); ALLOC(f13, M.n_bins); ALLOC(lnf3, M.n_bins); ALLOC(fm53, M.n_bins);
+    ALLOC(dw, nbd); ALLOC(hpre, nbd);
+    std::vector<void*> tmp;
+    double* stage = nullptr;
+    if (hipMalloc((void**)&stage, 4 * nbd * sizeof(double)) != hipSuccess)
+      return cleanup(fail(NS_E_OOM, "hipMalloc failed for staging"));
+    dre = stage; dim = stage + nbd; psd = stage + 2 * nbd; scratch = stage + 3 * nbd;
+    e = hipMemcpyAsync(dre, P->data_re, nbd * sizeof(double), hipMemcpyHostToDevice, r->st);
+    if (e == hipSuccess) e = hipMemcpyAsync(dim, P->data_im, nbd * sizeof(double), hipMemcpyHostToDevice, r->st);
+    if (e == hipSuccess) e = hipMemcpyAsync(psd, P->psd, nbd * sizeof(double), hipMemcpyHostToDevice, r->st);
+    if (e == hipSuccess) e = launch_build_tables(M, dre, dim, psd, f, f13, lnf3, fm53, dw, hpre, scratch, r->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(r->st);
+    (void)hipFree(stage);
+    if (e != hipSuccess) return cleanup(fail(NS_E_HIP, "building likelihood tables: %s", hipGetErrorString(e)));
+    r->T.f = f; r->T.f13 = f13; r->T.lnf3 = lnf3; r->T.fm53 = fm53; r->T.dw = dw; r->T.hpre = hpre;
+  }
+#undef ALLOC
+  (void)configure_slice(r->M, &r->C);
+  DevState s0{};
+  s0.logX = 0.0;
+  s0.logZ = -__builtin_inf();
+  s0.H = 0.0;
+  s0.lstar = -__builtin_inf();
+  s0.n_dead = 0;
+  s0.n_evals = n;
+  s0.iter = 0;
+  s0.done = 0;
+  *r->h_state = s0;
+  e = hipMemcpyAsync(R.state, r->h_state, sizeof(DevState), hipMemcpyHostToDevice, r->st);
+  if (e == hipSuccess) e = launch_init_live(r->M, R, r->st);
+  if (e == hipSuccess) e = launch_loglike(r->M, r->T, r->RB, R.u, n, R.lam, r->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(r->st);
+  if (e != hipSuccess) return cleanup(fail(NS_E_HIP, "initial population: %s", hipGetErrorString(e)));
+  *out = r;
+  return NS_OK;
+}
+
+int ns_step_async(ns_run* r, int n_iters) {
+  if (!r) return fail(NS_E_ARG, "run is NULL");
+  if (n_iters < 0) return fail(NS_E_ARG, "n_iters must be >= 0");
+  for (int i = 0; i < n_iters; ++i) HIP_OK(launch_iteration(r->M, r->T, r->RB, r->R, r->C, r->st));
+  return NS_OK;
+}
+
+int ns_step(ns_run* r, int max_iters, int* done) {
+  int rc = ns_step_async(r, max_iters);
+  if (rc) return rc;
+  if ((rc = sync_state(r))) return rc;
+  if (done) *done = r->h_state->done != 0;
+  return NS_OK;
+}
+
+int ns_state(ns_run* r, double* logX, double* logZ, double* H, int* iter, long* n_dead, long* n_evals, int* done) {
+  if (!r) return fail(NS_E_ARG, "run is NULL");
+  int rc = sync_state(r);
+  if (rc) return rc;
+  const DevState& s = *r->h_state;
+  if (logX) *logX = s.logX;
+  if (logZ) *logZ = s.logZ;
+  if (H) *H = s.H;
+  if (iter) *iter = s.iter;
+  if (n_dead) *n_dead = (long)s.n_dead;
+  if (n_evals) *n_evals = (long)s.n_evals;
+  if (done) *done = s.done;
+  return NS_OK;
+}
+
+int ns_logZ(ns_run* r, int n_sim, double* logZ, double* sigma_sim, double* sigma_h, double* ess) {
+  if (!r) return fail(NS_E_ARG, "run is NULL");
+  if (n_sim < 0 || n_sim > 100000) return fail(NS_E_ARG, "n_sim must be in [0, 100000]");
+  const int ns_ = n_sim >= 2 ? n_sim : 0;
+  double* dout = nullptr;
+  HIP_OK(hipMalloc((void**)&dout, (3 + ns_) * sizeof(double)));
+  std::vector<double> h(3 + ns_);
+  hipError_t e = launch_final(r->R, ns_, dout, r->st);
+  if (e == hipSuccess) e = hipMemcpyAsync(h.data(), dout, h.size() * sizeof(double), hipMemcpyDeviceToHost, r->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(r->st);
+  (void)hipFree(dout);
+  if (e != hipSuccess) return fail(NS_E_HIP, "finalisation: %s", hipGetErrorString(e));
+  if (logZ) *logZ = h[0];
+  if (sigma_h) *sigma_h = sqrt(h[1] > 0.0 ? h[1] / r->R.n : 0.0);
+  if (ess) *ess = h[2];
+  if (sigma_sim) {
+    double sd = 0.0;
+    if (ns_ >= 2) {
+      double m = 0.0;
+      for (int i = 0; i < ns_; ++i) m += h[3 + i];
+      m /= ns_;
+      for (int i = 0; i < ns_; ++i) sd += (h[3 + i] - m) * (h[3 + i] - m);
+      sd = sqrt(sd / (ns_ - 1));
+    }
+    *sigma_sim = sd;
+  }
+  return NS_OK;
+}
+
+int ns_samples(ns_run* r, long cap, double* theta, double* logl, double* logw, long* n_out) {
+  if (!r) return fail(NS_E_ARG, "run is NULL");
+  int rc = sync_state(r);
+  if (rc) return rc;
+  const long long total = r->h_state->n_dead + r->R.n;
+  if (n_out) *n_out = (long)total;
+  if (cap < total) return fail(NS_E_CAPACITY, "need %lld samples, cap is %ld", total, cap);
+  double lz = 0.0;
+  if ((rc = ns_logZ(r, 0, &lz, nullptr, nullptr, nullptr))) return rc;
+  const int d = r->R.d;
+  double *dth = nullptr, *dl = nullptr, *dw = nullptr;
+  HIP_OK(hipMalloc((void**)&dth, std::max<long long>(1, total * d) * sizeof(double)));
+  hipError_t e = hipMalloc((void**)&dl, std::max<long long>(1, total) * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void**)&dw, std::max<long long>(1, total) * sizeof(double));
+  if (e == hipSuccess) e = launch_samples(r->M, r->R, total, lz, dth, dl, dw, r->st);
+  if (e == hipSuccess && theta) e = hipMemcpyAsync(theta, dth, total * d * sizeof(double), hipMemcpyDeviceToHost, r->st);
+  if (e == hipSuccess && logl) e = hipMemcpyAsync(logl, dl, total * sizeof(double), hipMemcpyDeviceToHost, r->st);
+  if (e == hipSuccess && logw) e = hipMemcpyAsync(logw, dw, total * sizeof(double), hipMemcpyDeviceToHost, r->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(r->st);
+  (void)hipFree(dth);
+  (void)hipFree(dl);
+  (void)hipFree(dw);
+  if (e != hipSuccess) return fail(NS_E_HIP, "samples: %s", hipGetErrorString(e));
+  return NS_OK;
+}
+
+int ns_live(ns_run* r, double* u, double* logl) {
+  if (!r) return fail(NS_E_ARG, "run is NULL");
+  if (u) HIP_OK(hipMemcpyAsync(u, r->R.u, (size_t)r->R.n * r->R.d * sizeof(double), hipMemcpyDeviceToHost, r->st));
+  if (logl) HIP_OK(hipMemcpyAsync(logl, r->R.lam, (size_t)r->R.n * sizeof(double), hipMemcpyDeviceToHost, r->st));
+  HIP_OK(hipStreamSynchronize(r->st));
+  return NS_OK;
+}
+
+int ns_dead(ns_run* r, long cap, double* u, double* logl, double* logx, double* logw, int* iter, int* slot,
+            long* n_out) {
+  if (!r) return fail(NS_E_ARG, "run is NULL");
+  int rc = sync_state(r);
+  if (rc) return rc;
+  const long long nd = r->h_state->n_dead;
+  if (n_out) *n_out = (long)nd;
+  if (cap < nd) return fail(NS_E_CAPACITY, "need %lld dead points, cap is %ld", nd, cap);
+  const RunDev& R = r->R;
+  const size_t b = (size_t)nd * sizeof(double);
+  if (nd > 0) {
+    if (u) HIP_OK(hipMemcpyAsync(u, R.du, b * R.d, hipMemcpyDeviceToHost, r->st));
+    if (logl) HIP_OK(hipMemcpyAsync(logl, R.dlam, b, hipMemcpyDeviceToHost, r->st));
+    if (logx) HIP_OK(hipMemcpyAsync(logx, R.dlogx, b, hipMemcpyDeviceToHost, r->st));
+    if (logw) HIP_OK(hipMemcpyAsync(logw, R.dlogw, b, hipMemcpyDeviceToHost, r->st));
+    if (iter) HIP_OK(hipMemcpyAsync(iter, R.diter, (size_t)nd * sizeof(int), hipMemcpyDeviceToHost, r->st));
+    if (slot) HIP_OK(hipMemcpyAsync(slot, R.dslot, (size_t)nd * sizeof(int), hipMemcpyDeviceToHost, r->st));
+  }
+  HIP_OK(hipStreamSynchronize(r->st));
+  return NS_OK;
+}
+
+int ns_loglike(ns_run* r, const double* u_dev, long n, double* out_dev) {
+  if (!r) return fail(NS_E_ARG, "run is NULL");
+  if (n < 0 || (n > 0 && (!u_dev || !out_dev))) return fail(NS_E_ARG, "bad batch arguments");
+  HIP_OK(launch_loglike(r->M, r->T, r->RB, u_dev, n, out_dev, r->st));
+  return NS_OK;
+}
+
+int ns_waveform(const ns_problem* P, const double* theta, int det, int apply_cut, double* h_re, double* h_im,
+                void* stream) {
+  if (!P || !theta || !h_re || !h_im) return fail(NS_E_ARG, "NULL argument");
+  ns_problem q = *P;
+  q.likelihood = NS_LIKE_FULL;
+  ModelDev M;
+  // data are not read by the waveform; validate the rest with a zero stand-in
+  std::vector<double> zero, one;
+  if (!P->data_re || !P->data_im || !P->psd) {
+    zero.assign((size_t)std::max(P->n_det, 1) * std::max(P->n_bins, 1), 0.0);
+    one.assign(zero.size(), 1.0);
+    q.data_re = zero.data(); q.data_im = zero.data(); q.psd = one.data();
+  }
+  int rc = validate_and_model(&q, &M);
+  if (rc) return rc;
+  if (det < 0 || det >= M.n_det) return fail(NS_E_ARG, "det out of range");
+  M.k_lim = M.n_bins;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  double *dth = nullptr, *dre = nullptr, *dim = nullptr;
+  HIP_OK(hipMalloc((void**)&dth, MAX_DIM * sizeof(double)));
+  hipError_t e = hipMalloc((void**)&dre, M.n_bins * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void**)&dim, M.n_bins * sizeof(double));
+  if (e == hipSuccess) e = hipMemcpyAsync(dth, theta, P->n_dim * sizeof(double), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = launch_waveform(M, dth, det, apply_cut, dre, dim, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(h_re, dre, M.n_bins * sizeof(double), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(h_im, dim, M.n_bins * sizeof(double), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(dth);
+  (void)hipFree(dre);
+  (void)hipFree(dim);
+  if (e != hipSuccess) return fail(NS_E_HIP, "waveform: %s", hipGetErrorString(e));
+  return NS_OK;
+}
+
+int ns_select(const double* logl_dev, int n, int k, int* dead_dev, double* lstar_dev, void* stream) {
+  if (!logl_dev || !dead_dev) return fail(NS_E_ARG, "NULL argument");
+  if (n < 1 || n > 16384 || k < 1 || k > n) return fail(NS_E_ARG, "need 1 <= k <= n <= 16384");
+  HIP_OK(launch_select(logl_dev, n, k, nullptr, dead_dev, lstar_dev, nullptr, static_cast<hipStream_t>(stream)));
+  return NS_OK;
+}
+
+void ns_free(ns_run* r) {
+  if (!r) return;
+  (void)hipStreamSynchronize(r->st);
+  delete r;
+}
+
+}  // extern "C"

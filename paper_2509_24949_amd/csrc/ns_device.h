@@ -1,0 +1,339 @@
+// Device-side building blocks of libns (gfx950, wave64): counter-based RNG,
+// the selection key, a double-precision sincos in cycles, prior transforms
+// and the per-probe TaylorF2 coefficients.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ns {
+
+constexpr int MAX_DIM = 12;
+constexpr int MAX_DET = 3;
+constexpr double PI = 3.14159265358979323846;
+constexpr double TWO_PI = 6.28318530717958647692;
+constexpr double TSUN_S = 4.925490947641267e-6;     // G Msun / c^3  (s)
+constexpr double C_SI = 299792458.0;                 // m/s
+constexpr double MPC_S = 3.0856775814913673e22 / 299792458.0;  // 1 Mpc / c  (s)
+constexpr double EULER_GAMMA = 0.57721566490153286061;
+
+// RNG purposes: the high 16 bits of the last Philox counter word.
+enum Purpose : uint64_t { P_INIT = 1, P_PICK = 2, P_DIR = 3, P_WIDTH = 4, P_SHRINK = 5, P_SIGMA = 7 };
+
+// ------------------------------------------------------------------ Philox
+// Philox4x64-10 (Salmon et al., SC'11): ten rounds of two 64x64->128-bit
+// products with the key bumped by the Weyl constants between rounds.
+struct u64x4 { uint64_t x[4]; };
+
+__host__ __device__ inline uint64_t mulhi64(uint64_t a, uint64_t b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __umul64hi(a, b);
+#else
+  return (uint64_t)(((unsigned __int128)a * b) >> 64);
+#endif
+}
+
+__host__ __device__ inline u64x4 philox(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3, uint64_t k0,
+                                        uint64_t k1) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) { k0 += W0; k1 += W1; }
+    uint64_t h0 = mulhi64(M0, c0), l0 = M0 * c0;
+    uint64_t h1 = mulhi64(M1, c2), l1 = M1 * c2;
+    uint64_t n0 = h1 ^ c1 ^ k0, n2 = h0 ^ c3 ^ k1;
+    c0 = n0; c1 = l1; c2 = n2; c3 = l0;
+  }
+  u64x4 o; o.x[0] = c0; o.x[1] = c1; o.x[2] = c2; o.x[3] = c3;
+  return o;
+}
+
+__host__ __device__ inline double unif53(uint64_t x) { return (double)(x >> 11) * 0x1.0p-53; }
+
+__host__ __device__ inline uint64_t purpose_word(uint64_t purpose, uint64_t idx) { return (purpose << 48) | idx; }
+
+// ------------------------------------------------------------ order key
+// Order-preserving map of a double to uint64: NaN is ordered as -inf and
+// -0 as +0, so ascending keys are ascending values.
+__host__ __device__ inline uint64_t order_key(double v) {
+  if (v != v) v = -__builtin_inf();
+  if (v == 0.0) v = 0.0;
+  uint64_t b = (uint64_t)__builtin_bit_cast(uint64_t, v);
+  return (b >> 63) ? ~b : (b | 0x8000000000000000ULL);
+}
+
+__host__ __device__ inline double order_value(double v) {
+  if (v != v) return -__builtin_inf();
+  return v == 0.0 ? 0.0 : v;
+}
+
+// ---------------------------------------------------------- sincos (cycles)
+// sin and cos of 2 pi p for a phase p given in cycles: reduce p to
+// r in [-1/2, 1/2] (exact), then to y = r - q/4 in [-1/8, 1/8] (exact for
+// |r| <= 1/2), and evaluate the Taylor series of sin(2 pi y) to y^17 and of
+// cos(2 pi y) to y^18 (truncation below 1e-19), then rotate by q quarter turns.
+__device__ inline void sincos_cycles(double p, double* s_out, double* c_out) {
+  double r = p - rint(p);
+  double q = rint(4.0 * r);
+  double y = fma(-0.25, q, r);
+  double y2 = y * y;
+  double sp = -0x1.8a404211f9547p-7;          // coefficient of y^19
+  sp = fma(sp, y2, 0x1.aaec32af93359p-4);
+  sp = fma(sp, y2, -0x1.6fadb9f155744p-1);
+  sp = fma(sp, y2, 0x1.e8f434d018d63p+1);
+  sp = fma(sp, y2, -0x1.e3074fde8871fp+3);
+  sp = fma(sp, y2, 0x1.50783487ee782p+5);
+  sp = fma(sp, y2, -0x1.32d2cce62bd86p+6);
+  sp = fma(sp, y2, 0x1.466bc6775aae2p+6);
+  sp = fma(sp, y2, -0x1.4abbce625be53p+5);
+  sp = fma(sp, y2, 0x1.921fb54442d18p+2);
+  double sn = sp * y;
+  double cp = -0x1.2a0c591af8314p-5;
+  cp = fma(cp, y2, 0x1.20c62c2f2d7f5p-2);
+  cp = fma(cp, y2, -0x1.b6e24f44b128fp+0);
+  cp = fma(cp, y2, 0x1.f9d38a3763cc3p+2);
+  cp = fma(cp, y2, -0x1.a6d1f2a204a8cp+4);
+  cp = fma(cp, y2, 0x1.e1f506891babbp+5);
+  cp = fma(cp, y2, -0x1.55d3c7e3cbffap+6);
+  cp = fma(cp, y2, 0x1.03c1f081b5ac4p+6);
+  cp = fma(cp, y2, -0x1.3bd3cc9be45dep+4);
+  double cs = fma(cp, y2, 1.0);
+  int qi = ((int)q) & 3;
+  double s = sn, c = cs;
+  if (qi == 1) { s = cs; c = -sn; }
+  else if (qi == 2) { s = -sn; c = -cs; }
+  else if (qi == 3) { s = -cs; c = sn; }
+  *s_out = s;
+  *c_out = c;
+}
+
+// ----------------------------------------------------------------- problem
+struct PriorDev {
+  int kind[MAX_DIM];
+  double lo[MAX_DIM], hi[MAX_DIM];
+  double a[MAX_DIM], b[MAX_DIM];  // per kind: UNIFORM lo,(hi-lo); COS cos lo,(cos hi-cos lo);
+                                  // SIN sin lo,(sin hi-sin lo); VOLUME lo^3,(hi^3-lo^3)
+};
+
+struct DetDev {
+  double D[6];      // detector tensor (x x^T - y y^T)/2: xx, xy, xz, yy, yz, zz
+  double r_c[3];    // vertex / c (s)
+};
+
+// Everything a probe needs from the problem (passed by value to kernels).
+struct ModelDev {
+  int model, likelihood, n_dim, n_det;
+  int n_bins, k_lim;           // k_lim: bins that can be active anywhere in the prior box
+  double f_lo, df, gmst;
+  double fixed_dist_s;         // TF2_4P distance (s)
+  PriorDev prior;
+  DetDev det[MAX_DET];
+  double gauss_mu[MAX_DIM];
+  double gauss_inv2s2, gauss_norm;   // 1/(2 s^2), -d/2 ln(2 pi s^2)
+};
+
+// Physical quantities of one parameter point, reduced to what the strain needs.
+struct Phys {
+  double mc_msun, eta, beta, sigma, dist_s, tc, phic;
+  double hp, hx;                  // (1 + cos^2 i)/2 and cos i
+  double sra, cra, sdec, cdec;    // sin/cos of (RA - GMST) and of Dec
+  double s2psi, c2psi;            // sin/cos of 2 psi
+};
+
+// Per-probe coefficients of the phase and response.  Phases are in cycles.
+struct Probe {
+  double x, lnx;          // x = (pi M)^(1/3): v_k = x f_k^(1/3), ln v_k = ln x + ln f_k / 3
+  double pref;            // 3/(128 eta) x^-5 / (2 pi): multiplies f_k^(-5/3) * series
+  double c2, c3, c4, c5, c5l, c6, c6l, c7;   // series coefficients (ln v parts split)
+  double tc;              // 2 pi f t_c in cycles is f * tc
+  double ph0;             // (-phi_c - pi/4) / (2 pi)
+  double f_isco;
+  int k_act;              // active bins k < k_act
+  double kre[MAX_DET], kim[MAX_DET];   // A K_det (A includes the distance)
+  double dt[MAX_DET];     // arrival delay (s): cycles f * dt
+  double a2k2[MAX_DET];   // A^2 |K_det|^2
+};
+
+// Number of grid bins with f_k <= f_isco, where f_k = f_lo + k df is rounded
+// as a product followed by a sum (no fused multiply-add); in [0, n_bins].
+__device__ inline int active_bins(double f_lo, double df, int n_bins, double f_isco) {
+#pragma clang fp contract(off)
+  if (!(f_isco >= f_lo)) return 0;
+  double est = (f_isco - f_lo) / df;
+  int k = (est >= (double)n_bins) ? n_bins : (int)floor(est) + 1;
+  if (k > n_bins) k = n_bins;
+  while (k > 0 && f_lo + (double)(k - 1) * df > f_isco) --k;
+  while (k < n_bins && f_lo + (double)k * df <= f_isco) ++k;
+  return k;
+}
+
+__device__ inline double prior_plain(const PriorDev& P, int i, double u) {
+  double a = P.a[i], b = P.b[i];
+  switch (P.kind[i]) {
+    case 1: return acos(fma(u, b, a));
+    case 2: return asin(fma(u, b, a));
+    case 3: return cbrt(fma(u, b, a));
+    default: return fma(u, b, a);
+  }
+}
+
+// Unit-cube point -> physical quantities.  Angles with COS/SIN priors give
+// their cosine/sine directly (no inverse trigonometric round trip).
+__device__ inline void phys_from_u(const ModelDev& M, const double* u, Phys* s) {
+  s->beta = 0.0; s->sigma = 0.0; s->hp = 1.0; s->hx = 0.0;
+  s->sra = 0; s->cra = 1; s->sdec = 0; s->cdec = 1; s->s2psi = 0; s->c2psi = 1;
+  if (M.model == 1) {
+    s->mc_msun = prior_plain(M.prior, 0, u[0]);
+    s->eta = prior_plain(M.prior, 1, u[1]);
+    s->tc = prior_plain(M.prior, 2, u[2]);
+    s->phic = prior_plain(M.prior, 3, u[3]);
+    s->dist_s = M.fixed_dist_s;
+    return;
+  }
+  s->mc_msun = prior_plain(M.prior, 0, u[0]);
+  double q = prior_plain(M.prior, 1, u[1]);
+  double c1 = prior_plain(M.prior, 2, u[2]);
+  double c2 = prior_plain(M.prior, 3, u[3]);
+  double opq = 1.0 + q;
+  s->eta = q / (opq * opq);
+  double m1 = 1.0 / opq, m2 = q / opq;
+  s->beta = (c1 * (113.0 * m1 * m1 + 75.0 * s->eta) + c2 * (113.0 * m2 * m2 + 75.0 * s->eta)) / 12.0;
+  s->sigma = 79.0 / 8.0 * s->eta * c1 * c2;
+  s->dist_s = prior_plain(M.prior, 4, u[4]) * MPC_S;
+  double ci;
+  if (M.prior.kind[5] == 1) ci = fma(u[5], M.prior.b[5], M.prior.a[5]);
+  else { double sn; sincos_cycles(prior_plain(M.prior, 5, u[5]) / TWO_PI, &sn, &ci); }
+  s->hp = 0.5 * fma(ci, ci, 1.0);
+  s->hx = ci;
+  sincos_cycles(prior_plain(M.prior, 6, u[6]) / PI, &s->s2psi, &s->c2psi);   // angle 2 psi
+  sincos_cycles((prior_plain(M.prior, 7, u[7]) - M.gmst) / TWO_PI, &s->sra, &s->cra);
+  if (M.prior.kind[8] == 2) {
+    s->sdec = fma(u[8], M.prior.b[8], M.prior.a[8]);
+    s->cdec = sqrt(fmax(0.0, 1.0 - s->sdec * s->sdec));
+  } else {
+    sincos_cycles(prior_plain(M.prior, 8, u[8]) / TWO_PI, &s->sdec, &s->cdec);
+  }
+  s->tc = prior_plain(M.prior, 9, u[9]);
+  s->phic = prior_plain(M.prior, 10, u[10]);
+}
+
+// Physical parameter vector -> physical quantities (waveform generation and
+// the heterodyne fiducial).
+__device__ inline void phys_from_theta(const ModelDev& M, const double* th, Phys* s) {
+  s->beta = 0.0; s->sigma = 0.0; s->hp = 1.0; s->hx = 0.0;
+  s->sra = 0; s->cra = 1; s->sdec = 0; s->cdec = 1; s->s2psi = 0; s->c2psi = 1;
+  s->mc_msun = th[0];
+  if (M.model == 1) {
+    s->eta = th[1]; s->tc = th[2]; s->phic = th[3]; s->dist_s = M.fixed_dist_s;
+    return;
+  }
+  double q = th[1], c1 = th[2], c2 = th[3];
+  double opq = 1.0 + q;
+  s->eta = q / (opq * opq);
+  double m1 = 1.0 / opq, m2 = q / opq;
+  s->beta = (c1 * (113.0 * m1 * m1 + 75.0 * s->eta) + c2 * (113.0 * m2 * m2 + 75.0 * s->eta)) / 12.0;
+  s->sigma = 79.0 / 8.0 * s->eta * c1 * c2;
+  s->dist_s = th[4] * MPC_S;
+  double sn, ci;
+  sincos_cycles(th[5] / TWO_PI, &sn, &ci);
+  s->hp = 0.5 * fma(ci, ci, 1.0);
+  s->hx = ci;
+  sincos_cycles(th[6] / PI, &s->s2psi, &s->c2psi);
+  sincos_cycles((th[7] - M.gmst) / TWO_PI, &s->sra, &s->cra);
+  sincos_cycles(th[8] / TWO_PI, &s->sdec, &s->cdec);
+  s->tc = th[9];
+  s->phic = th[10];
+}
+
+// Coefficients of the 3.5PN TaylorF2 phase with leading-order aligned-spin
+// terms (spin-orbit beta at 1.5PN, spin-spin sigma at 2PN):
+//   Psi = 2 pi f t_c - phi_c - pi/4 + 3/(128 eta v^5) sum_k psi_k v^k,
+// with ln v at 2.5PN and psi_6 containing -(6848/21) ln(4 v).
+__device__ inline void pn_coefficients(double eta, double beta, double sigma, Probe* p) {
+  double e2 = eta * eta, e3 = e2 * eta;
+  p->c2 = 3715.0 / 756.0 + 55.0 / 9.0 * eta;
+  p->c3 = -16.0 * PI + 4.0 * beta;
+  p->c4 = 15293365.0 / 508032.0 + 27145.0 / 504.0 * eta + 3085.0 / 72.0 * e2 - 10.0 * sigma;
+  double a5 = PI * (38645.0 / 756.0 - 65.0 / 9.0 * eta);
+  p->c5 = a5;
+  p->c5l = 3.0 * a5;
+  p->c6 = 11583231236531.0 / 4694215680.0 - 640.0 / 3.0 * PI * PI - 6848.0 / 21.0 * EULER_GAMMA
+          - 6848.0 / 21.0 * 1.3862943611198906
+          + (-15737765635.0 / 3048192.0 + 2255.0 / 12.0 * PI * PI) * eta + 76055.0 / 1728.0 * e2
+          - 127825.0 / 1296.0 * e3;
+  p->c6l = -6848.0 / 21.0;
+  p->c7 = PI * (77096675.0 / 254016.0 + 378515.0 / 1512.0 * eta - 74045.0 / 756.0 * e2);
+}
+
+// Physical quantities -> probe coefficients: masses, amplitude
+// sqrt(5/24) pi^(-2/3) Mc^(5/6) / D, f_ISCO, antenna patterns of each
+// detector (long-wavelength response of an L-shaped interferometer) and
+// geocentre-to-detector delays.
+__device__ inline void probe_from_phys(const ModelDev& M, const Phys& s, Probe* p) {
+  double ln_mc = log(s.mc_msun * TSUN_S);
+  double ln_pim = 1.1447298858494002 + ln_mc - 0.6 * log(s.eta);   // ln(pi M)
+  p->lnx = ln_pim / 3.0;
+  p->x = exp(p->lnx);
+  p->pref = 3.0 / (128.0 * s.eta) * exp(-5.0 * p->lnx) / TWO_PI;
+  pn_coefficients(s.eta, s.beta, s.sigma, p);
+  p->tc = s.tc;
+  p->ph0 = (-s.phic - 0.25 * PI) / TWO_PI;
+  double x3 = p->x * p->x * p->x;                    // pi M
+  p->f_isco = 1.0 / (14.696938456699069 * x3);      // 1 / (6^(3/2) pi M)
+  p->k_act = active_bins(M.f_lo, M.df, M.n_bins, p->f_isco);
+  if (p->k_act > M.k_lim) p->k_act = M.k_lim;
+  double amp = 0.21278751013966343 * exp(5.0 / 6.0 * ln_mc) / s.dist_s;
+  if (M.model == 1) {
+    p->kre[0] = amp; p->kim[0] = 0.0; p->dt[0] = 0.0; p->a2k2[0] = amp * amp;
+    return;
+  }
+  // wave-frame axes at psi = 0: a = (sin phi, -cos phi, 0), b = (-cos phi sin dec, -sin phi sin dec, cos dec);
+  // e+ = cos 2psi (a a - b b) + sin 2psi (a b + b a), ex = -sin 2psi (a a - b b) + cos 2psi (a b + b a)
+  double ax = s.sra, ay = -s.cra;
+  double bx = -s.cra * s.sdec, by = -s.sra * s.sdec, bz = s.cdec;
+  double nx = s.cdec * s.cra, ny = s.cdec * s.sra, nz = s.sdec;
+#pragma unroll
+  for (int d = 0; d < MAX_DET; ++d) {
+    if (d >= M.n_det) break;
+    const double* D = M.det[d].D;
+    double dax = D[0] * ax + D[1] * ay;
+    double day = D[1] * ax + D[3] * ay;
+    double daz = D[2] * ax + D[4] * ay;
+    double dbx = D[0] * bx + D[1] * by + D[2] * bz;
+    double dby = D[1] * bx + D[3] * by + D[4] * bz;
+    double dbz = D[2] * bx + D[4] * by + D[5] * bz;
+    double aDa = ax * dax + ay * day;
+    double bDb = bx * dbx + by * dby + bz * dbz;
+    double aDb = ax * dbx + ay * dby;
+    (void)daz;
+    double fp0 = aDa - bDb, fx0 = 2.0 * aDb;
+    double fp = s.c2psi * fp0 + s.s2psi * fx0;
+    double fx = -s.s2psi * fp0 + s.c2psi * fx0;
+    p->kre[d] = amp * fp * s.hp;       // K = F+ (1 + cos^2 i)/2 - i Fx cos i
+    p->kim[d] = -amp * fx * s.hx;
+    p->a2k2[d] = p->kre[d] * p->kre[d] + p->kim[d] * p->kim[d];
+    const double* r = M.det[d].r_c;
+    p->dt[d] = -(r[0] * nx + r[1] * ny + r[2] * nz);
+  }
+}
+
+__device__ inline void make_probe(const ModelDev& M, const double* u, Probe* p) {
+  Phys s;
+  phys_from_u(M, u, &s);
+  probe_from_phys(M, s, p);
+}
+
+// Phase of bin k in cycles (without the detector delay).
+__device__ inline double phase_cycles(const Probe& p, double f, double f13, double lnf3, double fm53) {
+  double v = p.x * f13;
+  double lnv = p.lnx + lnf3;
+  double s = fma(v, p.c7, fma(p.c6l, lnv, p.c6));
+  s = fma(v, s, fma(p.c5l, lnv, p.c5));
+  s = fma(v, s, p.c4);
+  s = fma(v, s, p.c3);
+  s = fma(v, s, p.c2);
+  s = fma(v * v, s, 1.0);
+  return fma(f, p.tc, p.ph0) + p.pref * fm53 * s;
+}
+
+}  // namespace ns

@@ -1,0 +1,113 @@
+// Internal interfaces between the host runtime (ns_api.hip) and the kernels
+// (ns_kernels.hip) of libns.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ns_device.h"
+
+namespace ns {
+
+// Scalars of a run that live in device memory and are updated by kernels.
+struct DevState {
+  double logX, logZ, H, lstar;
+  long long n_dead;
+  long long n_evals;
+  int iter;
+  int done;        // 0 running, 1 criterion met, 2 dead-point capacity reached
+  int pad[2];
+};
+
+// Likelihood tables in HBM (built once per run).
+struct Tables {
+  const double* f;      // [n_bins] f_k
+  const double* f13;    // [n_bins] f_k^(1/3)
+  const double* lnf3;   // [n_bins] ln(f_k) / 3
+  const double* fm53;   // [n_bins] f_k^(-5/3)
+  const double2* dw;    // [n_det][n_bins] 4 df f_k^(-7/6) d_k / S_k
+  const double* hpre;   // [n_det][n_bins] prefix sums of 4 df f^(-7/3) / S
+};
+
+// Relative-binning tables (one set per detector, nb coarse bins).
+struct RBTables {
+  int nb;
+  const int* edge;        // [nb+1] fine-grid index of each edge
+  const double* fe;       // [nb+1] edge frequency
+  const double* fe13;     // [nb+1] fe^(1/3)
+  const double* lnfe3;    // [nb+1] ln(fe) / 3
+  const double* fem53;    // [nb+1] fe^(-5/3)
+  const double* psi0;     // [nb+1] fiducial phase at the edges (cycles, without detector delay)
+  const double2* h0inv;   // [n_det][nb+1] 1 / (A0 K0_det), complex
+  const double* dt0;      // [n_det] fiducial delays
+  const double* fm;       // [nb] bin centres
+  const double2* A0;      // [n_det][nb]
+  const double2* A1;      // [n_det][nb]
+  const double* B0;       // [n_det][nb]
+  const double* B1;       // [n_det][nb]
+  // per fine bin, cumulative sums inside its coarse bin (for the bin that
+  // straddles f_ISCO): [n_det][n_bins]
+  const double2* cA0;
+  const double2* cA1;
+  const double* cB0;
+  const double* cB1;
+};
+
+// Device buffers of one run.
+struct RunDev {
+  int n, k, d, m;
+  double width;
+  int max_stepout, max_shrink;
+  double log_term;            // ln(term_frac), or -inf for "never"
+  uint64_t key0, key1;
+  long long cap;              // dead-point capacity
+  DevState* state;
+  double* u;                  // [n][d]
+  double* lam;                // [n]
+  int* rank;                  // [n]
+  int* dead;                  // [k]
+  int* surv;                  // [n]
+  int* start;                 // [k]
+  double* chol;               // [d][d]
+  int* probes;                // [k] likelihood calls of each chain in the last iteration
+  int* stepout_hits;          // [k]
+  double* du;                 // [cap][d]
+  double* dlam;               // [cap]
+  double* dlogx;              // [cap]
+  double* dlogw;              // [cap]
+  int* diter;                 // [cap]
+  int* dslot;                 // [cap]
+  int* dnlive;                // [cap]
+};
+
+enum LikeKind { LK_FULL = 0, LK_RB = 1, LK_GAUSS = 2 };
+
+// Launch configuration chosen at init.
+struct LaunchCfg {
+  int slice_threads;          // 64, 128 or 256 threads per chain
+  bool lds_tables;            // stage the full-grid tables in LDS
+  size_t lds_bytes;           // dynamic LDS of the chain kernel
+};
+
+// ---- launch wrappers (ns_kernels.hip) --------------------------------------
+hipError_t launch_build_tables(const ModelDev& M, const double* data_re, const double* data_im, const double* psd,
+                               double* f, double* f13, double* lnf3, double* fm53, double2* dw, double* hpre,
+                               double* scratch, hipStream_t st);
+hipError_t launch_init_live(const ModelDev& M, const RunDev& R, hipStream_t st);
+hipError_t launch_loglike(const ModelDev& M, const Tables& T, const RBTables& RB, const double* u, long n,
+                          double* out, hipStream_t st);
+hipError_t launch_select(const double* lam, int n, int k, int* rank, int* dead, double* lstar, const int* done,
+                         hipStream_t st);
+hipError_t launch_iteration(const ModelDev& M, const Tables& T, const RBTables& RB, const RunDev& R,
+                            const LaunchCfg& C, hipStream_t st);
+hipError_t launch_waveform(const ModelDev& M, const double* theta_dev, int det, int apply_cut, double* h_re,
+                           double* h_im, hipStream_t st);
+hipError_t launch_build_rb(const ModelDev& M, const double* theta_fid_dev, const double* data_re,
+                           const double* data_im, const double* psd, int nb, const int* edge_dev, RBTables* RBw,
+                           double* work, hipStream_t st);
+hipError_t launch_final(const RunDev& R, int n_sim, double* out, hipStream_t st);
+hipError_t launch_samples(const ModelDev& M, const RunDev& R, long long total, double logZ, double* theta,
+                          double* logl, double* logw, hipStream_t st);
+hipError_t configure_slice(const ModelDev& M, LaunchCfg* C);
+int likelihood_kind(const ModelDev& M);
+
+}  // namespace ns

@@ -1,0 +1,201 @@
+"""Parity of the HIP library against the oracle (through the C ABI).
+
+Bars: the waveform and the log-likelihood agree with the oracle to 1e-9
+relative in double precision (relative to the cancellation scale
+|<d|h>| + <h|h>/2 + 1); the selection is bit-exact; sampler runs with the same
+seeds follow the oracle in lockstep (identical dead-point slots, log-likelihoods
+and evidence to rounding).
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2509_24949_amd import binding, synth
+
+pytestmark = pytest.mark.gpu
+
+NTHREADS = min(16, os.cpu_count() or 1)
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    binding.lib()
+    return torch
+
+
+def _pair(w):
+    re, im = oracle.make_data(w)
+    return oracle.OracleProblem(w, re, im), binding.ProblemSpec(w, re, im)
+
+
+def _scale(w, orc_prob, u):
+    """|<d|h>| + <h|h>/2 + 1 per probe, from the oracle (zero-data problem gives -<h|h>/2)."""
+    zero = oracle.OracleProblem(w, np.zeros((w.n_det, w.n_bins)), np.zeros((w.n_det, w.n_bins)))
+    half_hh = -zero.loglike_batch(u, NTHREADS)
+    lam = orc_prob.loglike_batch(u, NTHREADS)
+    return lam, np.abs(lam + half_hh) + half_hh + 1.0
+
+
+@pytest.mark.parametrize("name", ["cfg1", "cfg2"])
+def test_waveform_parity(torch_cuda, name):
+    w = synth.workload(name)
+    orc = oracle.OracleProblem(w)
+    spec = binding.ProblemSpec(w)
+    rng = np.random.default_rng(4)
+    thetas = [w.theta_inj] + [orc.prior_transform(rng.random(w.n_dim)) for _ in range(5)]
+    for th in thetas:
+        for det in range(w.n_det):
+            for cut in (True, False):
+                hr, hi = orc.waveform(th, det, cut)
+                gr, gi = binding.waveform(spec, th, det, cut)
+                scale = np.max(np.hypot(hr, hi))
+                assert np.max(np.hypot(gr - hr, gi - hi)) <= 1e-11 * scale, (th, det, cut)
+                assert np.array_equal(gr == 0, hr == 0)
+
+
+@pytest.mark.parametrize("name,n", [("cfg1", 4099), ("cfg2", 2053)])
+def test_loglike_parity(torch_cuda, name, n):
+    torch = torch_cuda
+    w = synth.workload(name)
+    orc, spec = _pair(w)
+    u = synth.proposal_batch(w, n, seed=7)
+    u[0] = 0.0                      # cube corners
+    u[1] = 1.0
+    u[2] = synth.theta_to_cube_box(w, w.theta_inj)
+    lam_o, scale = _scale(w, orc, u)
+    run = binding.Run(spec, binding.opts_for(w, n_live=64, n_delete=32))
+    got = run.loglike(torch.from_numpy(u).cuda()).cpu().numpy()
+    err = np.abs(got - lam_o) / scale
+    assert err.max() <= 1e-9, (err.max(), np.argmax(err))
+    # empty and single-probe batches
+    assert run.loglike(torch.zeros((0, w.n_dim), dtype=torch.float64, device="cuda")).numel() == 0
+    one = run.loglike(torch.from_numpy(u[2:3].copy()).cuda()).cpu().numpy()
+    assert abs(one[0] - lam_o[2]) <= 1e-9 * scale[2]
+
+
+def _brute(x, k):
+    v = np.where(np.isnan(x), -np.inf, x)
+    v = np.where(v == 0.0, 0.0, v)
+    order = np.lexsort((np.arange(len(x)), v))
+    return order[:k], v[order[k - 1]]
+
+
+@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 1000, 2000, 4099, 16384])
+def test_select_bit_exact(torch_cuda, n):
+    torch = torch_cuda
+    rng = np.random.default_rng(n)
+    for trial in range(3):
+        x = np.round(rng.normal(size=n) * 3, 1)
+        m = rng.random(n)
+        x[m < 0.05] = -np.inf
+        x[(m > 0.05) & (m < 0.08)] = np.nan
+        x[(m > 0.08) & (m < 0.1)] = np.inf
+        x[(m > 0.1) & (m < 0.13)] = -0.0
+        for k in sorted({1, max(1, n // 2), n}):
+            dead, ls = binding.select(torch.from_numpy(x).cuda(), k)
+            od, ols = oracle.select(x, k)
+            bd, bls = _brute(x, k)
+            np.testing.assert_array_equal(dead.cpu().numpy(), od)
+            np.testing.assert_array_equal(od, bd)
+            assert ls.item() == ols
+
+
+def _lockstep(w, orc, spec, iters, n_live=None, n_delete=None, max_iter=1000, term_frac=None):
+    ro = oracle.Run(orc, oracle.opts_for(w, n_threads=NTHREADS, n_live=n_live, n_delete=n_delete, max_iter=max_iter,
+                                         term_frac=term_frac))
+    rg = binding.Run(spec, binding.opts_for(w, n_live=n_live, n_delete=n_delete, max_iter=max_iter,
+                                            term_frac=term_frac))
+    uo, lo = ro.live()
+    ug, lg = rg.live()
+    np.testing.assert_array_equal(ug, uo)        # same Philox draws
+    scale = np.abs(lo) + 1.0
+    assert np.max(np.abs(lg - lo) / scale) <= 1e-9
+    for it in range(iters):
+        do = ro.step(1)
+        dg = rg.step(1)
+        so, sg = ro.state(), rg.state()
+        assert do == dg, it
+        if do:
+            break
+    return ro, rg
+
+
+def _compare_runs(ro, rg, tol=1e-9):
+    a, b = ro.dead(), rg.dead()
+    assert len(a["slot"]) == len(b["slot"])
+    np.testing.assert_array_equal(b["slot"], a["slot"])
+    np.testing.assert_array_equal(b["iter"], a["iter"])
+    sc = np.abs(a["logl"]) + 1.0
+    assert np.max(np.abs(b["logl"] - a["logl"]) / sc) <= tol
+    assert np.max(np.abs(b["logx"] - a["logx"])) <= 1e-12 * max(1.0, np.abs(a["logx"]).max())
+    so, sg = ro.state(), rg.state()
+    assert so["iter"] == sg["iter"]
+    assert abs(so["logZ"] - sg["logZ"]) <= tol * (abs(so["logZ"]) + 1)
+    assert abs(so["H"] - sg["H"]) <= 1e-7 * (abs(so["H"]) + 1)
+    assert so["n_evals"] == sg["n_evals"]
+    uo, lo = ro.live()
+    ug, lg = rg.live()
+    assert np.max(np.abs(ug - uo)) <= 1e-9
+    zo, zg = ro.logZ(200), rg.logZ(200)
+    assert abs(zo["logZ"] - zg["logZ"]) <= tol * (abs(zo["logZ"]) + 1)
+    assert abs(zo["sigma"] - zg["sigma"]) <= 1e-6 * zo["sigma"] + 1e-12
+    assert abs(zo["sigma_h"] - zg["sigma_h"]) <= 1e-7 * zo["sigma_h"] + 1e-12
+    assert abs(zo["ess"] - zg["ess"]) <= 1e-7 * zo["ess"]
+    return zo, zg
+
+
+def _closed_gauss(mu, s):
+    from scipy.special import erf
+    return float(np.sum(np.log(0.5 * (erf((1 - mu) / (s * math.sqrt(2))) + erf(mu / (s * math.sqrt(2)))))))
+
+
+@pytest.mark.parametrize("d,s,n,k", [(5, 0.05, 300, 150), (2, 0.1, 200, 1), (3, 0.05, 100, 99)])
+def test_gauss_lockstep_and_closed_form(torch_cuda, d, s, n, k):
+    mu = np.linspace(0.3, 0.7, d)
+    w = synth.gauss_workload(d, s, mu=mu, n_live=n, n_delete=k)
+    orc = oracle.OracleProblem(w)
+    spec = binding.ProblemSpec(w)
+    iters = 100000 if k > 1 else 600
+    ro, rg = _lockstep(w, orc, spec, iters)
+    zo, zg = _compare_runs(ro, rg)
+    if ro.state()["iter"] < iters:
+        assert abs(zg["logZ"] - _closed_gauss(mu, s)) < 4 * zg["sigma"] + 0.05
+    th, l, lw = rg.samples()
+    assert abs(np.exp(lw).sum() - 1.0) < 1e-9
+
+
+def test_cfg1_full_run_lockstep(torch_cuda):
+    w = synth.workload("cfg1")
+    orc, spec = _pair(w)
+    ro, rg = _lockstep(w, orc, spec, 1000)
+    assert rg.state()["done"]
+    zo, zg = _compare_runs(ro, rg)
+    th, l, lw = rg.samples()
+    p = np.exp(lw)
+    mean = (p[:, None] * th).sum(0)
+    assert abs(mean[0] - w.theta_inj[0]) < 0.5          # chirp mass recovered
+
+
+def test_cfg2_iterations_lockstep(torch_cuda):
+    w = synth.workload("cfg2")
+    orc, spec = _pair(w)
+    ro, rg = _lockstep(w, orc, spec, 2)
+    _compare_runs(ro, rg)
+
+
+def test_capacity_and_no_termination(torch_cuda):
+    w = synth.gauss_workload(3, 0.05, n_live=100, n_delete=50)
+    spec = binding.ProblemSpec(w)
+    rg = binding.Run(spec, binding.opts_for(w, max_iter=3, term_frac=0.0))
+    assert rg.step(10)
+    st = rg.state()
+    assert st["iter"] == 3 and st["n_dead"] == 150 and st["done"] == 2
+    rg = binding.Run(spec, binding.opts_for(w, term_frac=0.0, max_iter=100))
+    assert not rg.step(40)
+    assert rg.state()["iter"] == 40
