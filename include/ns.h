@@ -63,7 +63,10 @@ typedef enum {
  *   UNIFORM  theta = lo + (hi - lo) u
  *   COS      uniform in cos(theta), 0 <= lo < hi <= pi   (isotropic inclination)
  *   SIN      uniform in sin(theta), -pi/2 <= lo < hi <= pi/2 (isotropic declination)
- *   VOLUME   density proportional to theta^2, 0 <= lo < hi (uniform in volume) */
+ *   VOLUME   density proportional to theta^2, 0 <= lo < hi (uniform in volume)
+ * The waveform models accept UNIFORM for every coordinate, and in addition
+ * VOLUME for d_L, COS for theta_jn and SIN for Dec (TF2_11P); the Gaussian
+ * test likelihood ignores the kinds (it works on u directly). */
 enum { NS_PRIOR_UNIFORM = 0, NS_PRIOR_COS = 1, NS_PRIOR_SIN = 2, NS_PRIOR_VOLUME = 3 };
 
 /* Waveform models (stationary-phase TaylorF2, 3.5PN phase, Newtonian amplitude):
@@ -189,6 +192,26 @@ NS_API int ns_waveform(const ns_problem* problem, const double* theta, int det, 
  * ascending order; lstar_dev: device [1] receives the k-th lowest value.
  * 1 <= k <= n <= 16384.  Asynchronous on stream. */
 NS_API int ns_select(const double* logl_dev, int n, int k, int* dead_dev, double* lstar_dev, void* stream);
+
+/* Per-kernel timing of a run's iterations (hipEvents recorded on the run's
+ * stream around every kernel of every iteration while enabled).  Enabling
+ * clears the accumulated statistics. */
+NS_API int ns_profile(ns_run* run, int enable);
+
+typedef struct {
+    long iterations;         /* iterations enqueued while profiling */
+    double ms_select;        /* summed kernel durations, milliseconds */
+    double ms_prep;
+    double ms_slice;
+    double ms_term;
+    long long evals;         /* likelihood evaluations of the whole run so far */
+    long long bin_terms;     /* sum over evaluations of the active frequency bins (full grid) */
+    int slice_threads;       /* threads per chain workgroup */
+    int lds_tables;          /* 1 if the likelihood tables are staged in LDS */
+} ns_stats_t;
+
+/* Statistics of the profiled iterations (synchronises the stream). */
+NS_API int ns_stats(ns_run* run, ns_stats_t* out);
 
 /* Release a run (NULL is allowed). */
 NS_API void ns_free(ns_run* run);

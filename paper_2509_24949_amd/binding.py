@@ -49,6 +49,14 @@ class Opts(C.Structure):
     ]
 
 
+class Stats(C.Structure):
+    _fields_ = [
+        ("iterations", C.c_long), ("ms_select", C.c_double), ("ms_prep", C.c_double),
+        ("ms_slice", C.c_double), ("ms_term", C.c_double), ("evals", C.c_longlong),
+        ("bin_terms", C.c_longlong), ("slice_threads", C.c_int), ("lds_tables", C.c_int),
+    ]
+
+
 # Every entry point of include/ns.h with its ctypes signature.
 SIGNATURES = {
     "ns_init": (C.c_int, [C.POINTER(C.c_void_p), C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -62,6 +70,8 @@ SIGNATURES = {
     "ns_loglike": (C.c_int, [C.c_void_p, C.c_void_p, C.c_long, C.c_void_p]),
     "ns_waveform": (C.c_int, [C.c_void_p, _dp, C.c_int, C.c_int, _dp, _dp, C.c_void_p]),
     "ns_select": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "ns_profile": (C.c_int, [C.c_void_p, C.c_int]),
+    "ns_stats": (C.c_int, [C.c_void_p, C.POINTER(Stats)]),
     "ns_free": (None, [C.c_void_p]),
     "ns_last_error": (C.c_char_p, []),
 }
@@ -255,6 +265,14 @@ class Run:
         out = torch.empty(u.shape[0], dtype=torch.float64, device=u.device)
         _check(lib().ns_loglike(self.h, C.c_void_p(u.data_ptr()), u.shape[0], C.c_void_p(out.data_ptr())))
         return out
+
+    def profile(self, enable: bool = True):
+        _check(lib().ns_profile(self.h, 1 if enable else 0))
+
+    def stats(self) -> dict:
+        st = Stats()
+        _check(lib().ns_stats(self.h, C.byref(st)))
+        return {name: getattr(st, name) for name, _ in Stats._fields_}
 
     def close(self):
         if getattr(self, "h", None):

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <array>
 #include <string>
 #include <vector>
 
@@ -54,6 +55,7 @@ struct DevMem {
 
 struct ns_run {
   ModelDev M{};
+  ModelDev* Md = nullptr;        // device copy of M
   Tables T{};
   RBTables RB{};
   RunDev R{};
@@ -61,7 +63,15 @@ struct ns_run {
   hipStream_t st = nullptr;
   DevMem mem;
   DevState* h_state = nullptr;   // pinned mirror of the device scalars
+  bool profiling = false;
+  std::vector<std::array<hipEvent_t, 5>> events;   // per profiled iteration
+  void release_events() {
+    for (auto& a : events)
+      for (hipEvent_t e : a) (void)hipEventDestroy(e);
+    events.clear();
+  }
   ~ns_run() {
+    release_events();
     if (h_state) (void)hipHostFree(h_state);
   }
 };
@@ -151,6 +161,15 @@ int validate_and_model(const ns_problem* P, ModelDev* M) {
       for (int i = 0; i < 3; ++i) M->det[d].r_c[i] = g[i] / C_SI;
     }
   }
+  // prior kinds each coordinate of the model supports
+  for (int i = 0; i < P->n_dim; ++i) {
+    const int k = P->prior_kind[i];
+    bool ok = (k == NS_PRIOR_UNIFORM);
+    if (P->model == NS_MODEL_TF2_11P && i == 4) ok = ok || k == NS_PRIOR_VOLUME;
+    if (P->model == NS_MODEL_TF2_11P && i == 5) ok = ok || k == NS_PRIOR_COS;
+    if (P->model == NS_MODEL_TF2_11P && i == 8) ok = ok || k == NS_PRIOR_SIN;
+    if (!ok) return fail(NS_E_ARG, "prior %d: kind %d is not supported for this model coordinate", i, k);
+  }
   const double m_min = mc_min * TSUN_S * pow(eta_max, -0.6);
   const double f_max = 1.0 / (pow(6.0, 1.5) * PI * m_min) * (1.0 + 1e-9);
   const double kk = floor((f_max - P->f_lo) / P->df) + 2.0;
@@ -208,6 +227,7 @@ int ns_init(ns_run** out, const ns_problem* P, const ns_opts* O, void* stream) {
   DevMem& mem = r->mem;
 #define ALLOC(ptr, count) \
   if (mem.alloc(&(ptr), (count)) != hipSuccess) return cleanup(fail(NS_E_OOM, "hipMalloc failed for " #ptr))
+  ALLOC(r->Md, 1);
   ALLOC(R.state, 1);
   ALLOC(R.u, (size_t)n * d);
   ALLOC(R.lam, n);
@@ -217,7 +237,7 @@ int ns_init(ns_run** out, const ns_problem* P, const ns_opts* O, void* stream) {
   ALLOC(R.start, k);
   ALLOC(R.chol, (size_t)d * d);
   ALLOC(R.probes, k);
-  ALLOC(R.stepout_hits, k);
+  ALLOC(R.bins, k);
   ALLOC(R.du, (size_t)R.cap * d);
   ALLOC(R.dlam, R.cap);
   ALLOC(R.dlogx, R.cap);
@@ -228,7 +248,8 @@ int ns_init(ns_run** out, const ns_problem* P, const ns_opts* O, void* stream) {
   if (hipHostMalloc((void**)&r->h_state, sizeof(DevState), hipHostMallocDefault) != hipSuccess)
     return cleanup(fail(NS_E_OOM, "pinned allocation failed"));
 
-  hipError_t e;
+  hipError_t e = hipMemcpyAsync(r->Md, &r->M, sizeof(ModelDev), hipMemcpyHostToDevice, r->st);
+  if (e != hipSuccess) return cleanup(fail(NS_E_HIP, "copying the model: %s", hipGetErrorString(e)));
   if (M.likelihood != NS_LIKE_GAUSS) {
     const size_t nbd = (size_t)M.n_det * M.n_bins;
     double *f, *f13, *lnf3, *fm53, *hpre, *dre, *dim, *psd, *scratch;
@@ -243,7 +264,8 @@ int ns_init(ns_run** out, const ns_problem* P, const ns_opts* O, void* stream) {
     e = hipMemcpyAsync(dre, P->data_re, nbd * sizeof(double), hipMemcpyHostToDevice, r->st);
     if (e == hipSuccess) e = hipMemcpyAsync(dim, P->data_im, nbd * sizeof(double), hipMemcpyHostToDevice, r->st);
     if (e == hipSuccess) e = hipMemcpyAsync(psd, P->psd, nbd * sizeof(double), hipMemcpyHostToDevice, r->st);
-    if (e == hipSuccess) e = launch_build_tables(M, dre, dim, psd, f, f13, lnf3, fm53, dw, hpre, scratch, r->st);
+    if (e == hipSuccess)
+      e = launch_build_tables(M, r->Md, dre, dim, psd, f, f13, lnf3, fm53, dw, hpre, scratch, r->st);
     if (e == hipSuccess) e = hipStreamSynchronize(r->st);
     (void)hipFree(stage);
     if (e != hipSuccess) return cleanup(fail(NS_E_HIP, "building likelihood tables: %s", hipGetErrorString(e)));
@@ -262,8 +284,8 @@ int ns_init(ns_run** out, const ns_problem* P, const ns_opts* O, void* stream) {
   s0.done = 0;
   *r->h_state = s0;
   e = hipMemcpyAsync(R.state, r->h_state, sizeof(DevState), hipMemcpyHostToDevice, r->st);
-  if (e == hipSuccess) e = launch_init_live(r->M, R, r->st);
-  if (e == hipSuccess) e = launch_loglike(r->M, r->T, r->RB, R.u, n, R.lam, r->st);
+  if (e == hipSuccess) e = launch_init_live(R, r->st);
+  if (e == hipSuccess) e = launch_loglike(r->M, r->Md, r->T, r->RB, R.u, n, R.lam, r->st);
   if (e == hipSuccess) e = hipStreamSynchronize(r->st);
   if (e != hipSuccess) return cleanup(fail(NS_E_HIP, "initial population: %s", hipGetErrorString(e)));
   *out = r;
@@ -273,7 +295,45 @@ int ns_init(ns_run** out, const ns_problem* P, const ns_opts* O, void* stream) {
 int ns_step_async(ns_run* r, int n_iters) {
   if (!r) return fail(NS_E_ARG, "run is NULL");
   if (n_iters < 0) return fail(NS_E_ARG, "n_iters must be >= 0");
-  for (int i = 0; i < n_iters; ++i) HIP_OK(launch_iteration(r->M, r->T, r->RB, r->R, r->C, r->st));
+  for (int i = 0; i < n_iters; ++i) {
+    hipEvent_t* ev = nullptr;
+    if (r->profiling) {
+      std::array<hipEvent_t, 5> a{};
+      for (auto& e : a) HIP_OK(hipEventCreate(&e));
+      r->events.push_back(a);
+      ev = r->events.back().data();
+    }
+    HIP_OK(launch_iteration(r->M, r->Md, r->T, r->RB, r->R, r->C, r->st, ev));
+  }
+  return NS_OK;
+}
+
+int ns_profile(ns_run* r, int enable) {
+  if (!r) return fail(NS_E_ARG, "run is NULL");
+  HIP_OK(hipStreamSynchronize(r->st));
+  r->release_events();
+  r->profiling = enable != 0;
+  return NS_OK;
+}
+
+int ns_stats(ns_run* r, ns_stats_t* out) {
+  if (!r || !out) return fail(NS_E_ARG, "NULL argument");
+  int rc = sync_state(r);
+  if (rc) return rc;
+  memset(out, 0, sizeof(*out));
+  for (auto& a : r->events) {
+    float t[4];
+    for (int i = 0; i < 4; ++i) HIP_OK(hipEventElapsedTime(&t[i], a[i], a[i + 1]));
+    out->ms_select += t[0];
+    out->ms_prep += t[1];
+    out->ms_slice += t[2];
+    out->ms_term += t[3];
+  }
+  out->iterations = (long)r->events.size();
+  out->evals = r->h_state->n_evals;
+  out->bin_terms = r->h_state->n_bin_terms;
+  out->slice_threads = r->C.slice_threads;
+  out->lds_tables = r->C.lds_tables ? 1 : 0;
   return NS_OK;
 }
 
@@ -343,7 +403,7 @@ int ns_samples(ns_run* r, long cap, double* theta, double* logl, double* logw, l
   HIP_OK(hipMalloc((void**)&dth, std::max<long long>(1, total * d) * sizeof(double)));
   hipError_t e = hipMalloc((void**)&dl, std::max<long long>(1, total) * sizeof(double));
   if (e == hipSuccess) e = hipMalloc((void**)&dw, std::max<long long>(1, total) * sizeof(double));
-  if (e == hipSuccess) e = launch_samples(r->M, r->R, total, lz, dth, dl, dw, r->st);
+  if (e == hipSuccess) e = launch_samples(r->Md, r->R, total, lz, dth, dl, dw, r->st);
   if (e == hipSuccess && theta) e = hipMemcpyAsync(theta, dth, total * d * sizeof(double), hipMemcpyDeviceToHost, r->st);
   if (e == hipSuccess && logl) e = hipMemcpyAsync(logl, dl, total * sizeof(double), hipMemcpyDeviceToHost, r->st);
   if (e == hipSuccess && logw) e = hipMemcpyAsync(logw, dw, total * sizeof(double), hipMemcpyDeviceToHost, r->st);
@@ -388,7 +448,7 @@ int ns_dead(ns_run* r, long cap, double* u, double* logl, double* logx, double* 
 int ns_loglike(ns_run* r, const double* u_dev, long n, double* out_dev) {
   if (!r) return fail(NS_E_ARG, "run is NULL");
   if (n < 0 || (n > 0 && (!u_dev || !out_dev))) return fail(NS_E_ARG, "bad batch arguments");
-  HIP_OK(launch_loglike(r->M, r->T, r->RB, u_dev, n, out_dev, r->st));
+  HIP_OK(launch_loglike(r->M, r->Md, r->T, r->RB, u_dev, n, out_dev, r->st));
   return NS_OK;
 }
 
@@ -411,17 +471,21 @@ int ns_waveform(const ns_problem* P, const double* theta, int det, int apply_cut
   M.k_lim = M.n_bins;
   hipStream_t st = static_cast<hipStream_t>(stream);
   double *dth = nullptr, *dre = nullptr, *dim = nullptr;
+  ModelDev* Md = nullptr;
   HIP_OK(hipMalloc((void**)&dth, MAX_DIM * sizeof(double)));
   hipError_t e = hipMalloc((void**)&dre, M.n_bins * sizeof(double));
   if (e == hipSuccess) e = hipMalloc((void**)&dim, M.n_bins * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void**)&Md, sizeof(ModelDev));
+  if (e == hipSuccess) e = hipMemcpyAsync(Md, &M, sizeof(ModelDev), hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipMemcpyAsync(dth, theta, P->n_dim * sizeof(double), hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = launch_waveform(M, dth, det, apply_cut, dre, dim, st);
+  if (e == hipSuccess) e = launch_waveform(M, Md, dth, det, apply_cut, dre, dim, st);
   if (e == hipSuccess) e = hipMemcpyAsync(h_re, dre, M.n_bins * sizeof(double), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipMemcpyAsync(h_im, dim, M.n_bins * sizeof(double), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   (void)hipFree(dth);
   (void)hipFree(dre);
   (void)hipFree(dim);
+  (void)hipFree(Md);
   if (e != hipSuccess) return fail(NS_E_HIP, "waveform: %s", hipGetErrorString(e));
   return NS_OK;
 }

@@ -68,43 +68,41 @@ __host__ __device__ inline double order_value(double v) {
 }
 
 // ---------------------------------------------------------- sincos (cycles)
-// sin and cos of 2 pi p for a phase p given in cycles: reduce p to
-// r in [-1/2, 1/2] (exact), then to y = r - q/4 in [-1/8, 1/8] (exact for
-// |r| <= 1/2), and evaluate the Taylor series of sin(2 pi y) to y^17 and of
-// cos(2 pi y) to y^18 (truncation below 1e-19), then rotate by q quarter turns.
+// sin and cos of 2 pi p for a phase p given in cycles.  p is reduced to
+// r = p - rint(p) in [-1/2, 1/2] and then to y = r - q/4 in [-1/8, 1/8]
+// (both subtractions are exact), sin(2 pi y) and cos(2 pi y) are evaluated
+// from their Taylor series through y^15 and y^16 (first omitted terms below
+// 5e-17), and the quarter turns q are applied by swapping and sign flips
+// without branches.
 __device__ inline void sincos_cycles(double p, double* s_out, double* c_out) {
-  double r = p - rint(p);
-  double q = rint(4.0 * r);
-  double y = fma(-0.25, q, r);
-  double y2 = y * y;
-  double sp = -0x1.8a404211f9547p-7;          // coefficient of y^19
-  sp = fma(sp, y2, 0x1.aaec32af93359p-4);
-  sp = fma(sp, y2, -0x1.6fadb9f155744p-1);
-  sp = fma(sp, y2, 0x1.e8f434d018d63p+1);
+  const double r = p - rint(p);
+  const double q = rint(4.0 * r);
+  const double y = fma(-0.25, q, r);
+  const double y2 = y * y;
+  double sp = fma(y2, -0x1.6fadb9f155744p-1, 0x1.e8f434d018d63p+1);
   sp = fma(sp, y2, -0x1.e3074fde8871fp+3);
   sp = fma(sp, y2, 0x1.50783487ee782p+5);
   sp = fma(sp, y2, -0x1.32d2cce62bd86p+6);
   sp = fma(sp, y2, 0x1.466bc6775aae2p+6);
   sp = fma(sp, y2, -0x1.4abbce625be53p+5);
   sp = fma(sp, y2, 0x1.921fb54442d18p+2);
-  double sn = sp * y;
-  double cp = -0x1.2a0c591af8314p-5;
-  cp = fma(cp, y2, 0x1.20c62c2f2d7f5p-2);
-  cp = fma(cp, y2, -0x1.b6e24f44b128fp+0);
+  const double sn = sp * y;
+  double cp = fma(y2, 0x1.20c62c2f2d7f5p-2, -0x1.b6e24f44b128fp+0);
   cp = fma(cp, y2, 0x1.f9d38a3763cc3p+2);
   cp = fma(cp, y2, -0x1.a6d1f2a204a8cp+4);
   cp = fma(cp, y2, 0x1.e1f506891babbp+5);
   cp = fma(cp, y2, -0x1.55d3c7e3cbffap+6);
   cp = fma(cp, y2, 0x1.03c1f081b5ac4p+6);
   cp = fma(cp, y2, -0x1.3bd3cc9be45dep+4);
-  double cs = fma(cp, y2, 1.0);
-  int qi = ((int)q) & 3;
-  double s = sn, c = cs;
-  if (qi == 1) { s = cs; c = -sn; }
-  else if (qi == 2) { s = -sn; c = -cs; }
-  else if (qi == 3) { s = -cs; c = sn; }
-  *s_out = s;
-  *c_out = c;
+  const double cs = fma(cp, y2, 1.0);
+  const int qi = (int)q;
+  const bool swap = qi & 1;
+  const double s1 = swap ? cs : sn;
+  const double c1 = swap ? sn : cs;
+  const uint64_t fs = (uint64_t)(qi & 2) << 62;         // sin negative for q = 2, 3 (mod 4)
+  const uint64_t fc = (uint64_t)((qi + 1) & 2) << 62;   // cos negative for q = 1, 2 (mod 4)
+  *s_out = __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, s1) ^ fs);
+  *c_out = __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, c1) ^ fc);
 }
 
 // ----------------------------------------------------------------- problem
@@ -147,11 +145,11 @@ struct Probe {
   double c2, c3, c4, c5, c5l, c6, c6l, c7;   // series coefficients (ln v parts split)
   double tc;              // 2 pi f t_c in cycles is f * tc
   double ph0;             // (-phi_c - pi/4) / (2 pi)
-  double f_isco;
-  int k_act;              // active bins k < k_act
   double kre[MAX_DET], kim[MAX_DET];   // A K_det (A includes the distance)
   double dt[MAX_DET];     // arrival delay (s): cycles f * dt
-  double a2k2[MAX_DET];   // A^2 |K_det|^2
+  double hh;              // <h|h> summed over the detectors (from the prefix table)
+  double f_isco;
+  int k_act;              // active bins k < k_act
 };
 
 // Number of grid bins with f_k <= f_isco, where f_k = f_lo + k df is rounded
@@ -177,44 +175,50 @@ __device__ inline double prior_plain(const PriorDev& P, int i, double u) {
   }
 }
 
-// Unit-cube point -> physical quantities.  Angles with COS/SIN priors give
-// their cosine/sine directly (no inverse trigonometric round trip).
+// Affine (uniform) transform of coordinate i.
+__device__ inline double prior_affine(const PriorDev& P, int i, double u) { return fma(u, P.b[i], P.a[i]); }
+
+// Unit-cube point -> physical quantities.  The model fixes which prior kinds
+// each coordinate may use (checked at run creation): uniform everywhere,
+// uniform-in-volume for the distance, isotropic (COS) for theta_jn and (SIN)
+// for the declination, whose cosine/sine then come straight from u.
 __device__ inline void phys_from_u(const ModelDev& M, const double* u, Phys* s) {
   s->beta = 0.0; s->sigma = 0.0; s->hp = 1.0; s->hx = 0.0;
   s->sra = 0; s->cra = 1; s->sdec = 0; s->cdec = 1; s->s2psi = 0; s->c2psi = 1;
+  const PriorDev& P = M.prior;
+  s->mc_msun = prior_affine(P, 0, u[0]);
   if (M.model == 1) {
-    s->mc_msun = prior_plain(M.prior, 0, u[0]);
-    s->eta = prior_plain(M.prior, 1, u[1]);
-    s->tc = prior_plain(M.prior, 2, u[2]);
-    s->phic = prior_plain(M.prior, 3, u[3]);
+    s->eta = prior_affine(P, 1, u[1]);
+    s->tc = prior_affine(P, 2, u[2]);
+    s->phic = prior_affine(P, 3, u[3]);
     s->dist_s = M.fixed_dist_s;
     return;
   }
-  s->mc_msun = prior_plain(M.prior, 0, u[0]);
-  double q = prior_plain(M.prior, 1, u[1]);
-  double c1 = prior_plain(M.prior, 2, u[2]);
-  double c2 = prior_plain(M.prior, 3, u[3]);
-  double opq = 1.0 + q;
+  const double q = prior_affine(P, 1, u[1]);
+  const double c1 = prior_affine(P, 2, u[2]);
+  const double c2 = prior_affine(P, 3, u[3]);
+  const double opq = 1.0 + q;
   s->eta = q / (opq * opq);
-  double m1 = 1.0 / opq, m2 = q / opq;
-  s->beta = (c1 * (113.0 * m1 * m1 + 75.0 * s->eta) + c2 * (113.0 * m2 * m2 + 75.0 * s->eta)) / 12.0;
+  const double m1 = 1.0 / opq, m2 = q / opq;
+  s->beta = (c1 * (113.0 * m1 * m1 + 75.0 * s->eta) + c2 * (113.0 * m2 * m2 + 75.0 * s->eta)) * (1.0 / 12.0);
   s->sigma = 79.0 / 8.0 * s->eta * c1 * c2;
-  s->dist_s = prior_plain(M.prior, 4, u[4]) * MPC_S;
-  double ci;
-  if (M.prior.kind[5] == 1) ci = fma(u[5], M.prior.b[5], M.prior.a[5]);
-  else { double sn; sincos_cycles(prior_plain(M.prior, 5, u[5]) / TWO_PI, &sn, &ci); }
+  const double dv = prior_affine(P, 4, u[4]);
+  s->dist_s = (P.kind[4] == 3 ? cbrt(dv) : dv) * MPC_S;
+  double ci, sn;
+  if (P.kind[5] == 1) ci = prior_affine(P, 5, u[5]);
+  else sincos_cycles(prior_affine(P, 5, u[5]) * (1.0 / TWO_PI), &sn, &ci);
   s->hp = 0.5 * fma(ci, ci, 1.0);
   s->hx = ci;
-  sincos_cycles(prior_plain(M.prior, 6, u[6]) / PI, &s->s2psi, &s->c2psi);   // angle 2 psi
-  sincos_cycles((prior_plain(M.prior, 7, u[7]) - M.gmst) / TWO_PI, &s->sra, &s->cra);
-  if (M.prior.kind[8] == 2) {
-    s->sdec = fma(u[8], M.prior.b[8], M.prior.a[8]);
+  sincos_cycles(prior_affine(P, 6, u[6]) * (1.0 / PI), &s->s2psi, &s->c2psi);   // angle 2 psi
+  sincos_cycles((prior_affine(P, 7, u[7]) - M.gmst) * (1.0 / TWO_PI), &s->sra, &s->cra);
+  if (P.kind[8] == 2) {
+    s->sdec = prior_affine(P, 8, u[8]);
     s->cdec = sqrt(fmax(0.0, 1.0 - s->sdec * s->sdec));
   } else {
-    sincos_cycles(prior_plain(M.prior, 8, u[8]) / TWO_PI, &s->sdec, &s->cdec);
+    sincos_cycles(prior_affine(P, 8, u[8]) * (1.0 / TWO_PI), &s->sdec, &s->cdec);
   }
-  s->tc = prior_plain(M.prior, 9, u[9]);
-  s->phic = prior_plain(M.prior, 10, u[10]);
+  s->tc = prior_affine(P, 9, u[9]);
+  s->phic = prior_affine(P, 10, u[10]);
 }
 
 // Physical parameter vector -> physical quantities (waveform generation and
@@ -269,24 +273,27 @@ __device__ inline void pn_coefficients(double eta, double beta, double sigma, Pr
 // sqrt(5/24) pi^(-2/3) Mc^(5/6) / D, f_ISCO, antenna patterns of each
 // detector (long-wavelength response of an L-shaped interferometer) and
 // geocentre-to-detector delays.
-__device__ inline void probe_from_phys(const ModelDev& M, const Phys& s, Probe* p) {
+__device__ inline void probe_from_phys(const ModelDev& M, const Phys& s, const double* hpre, Probe* p) {
   double ln_mc = log(s.mc_msun * TSUN_S);
   double ln_pim = 1.1447298858494002 + ln_mc - 0.6 * log(s.eta);   // ln(pi M)
-  p->lnx = ln_pim / 3.0;
+  p->lnx = ln_pim * (1.0 / 3.0);
   p->x = exp(p->lnx);
-  p->pref = 3.0 / (128.0 * s.eta) * exp(-5.0 * p->lnx) / TWO_PI;
+  p->pref = (3.0 / 128.0 / TWO_PI) / s.eta * exp(-5.0 * p->lnx);
   pn_coefficients(s.eta, s.beta, s.sigma, p);
   p->tc = s.tc;
-  p->ph0 = (-s.phic - 0.25 * PI) / TWO_PI;
+  p->ph0 = (-s.phic - 0.25 * PI) * (1.0 / TWO_PI);
   double x3 = p->x * p->x * p->x;                    // pi M
   p->f_isco = 1.0 / (14.696938456699069 * x3);      // 1 / (6^(3/2) pi M)
   p->k_act = active_bins(M.f_lo, M.df, M.n_bins, p->f_isco);
   if (p->k_act > M.k_lim) p->k_act = M.k_lim;
   double amp = 0.21278751013966343 * exp(5.0 / 6.0 * ln_mc) / s.dist_s;
+  const bool have_h = hpre != nullptr && p->k_act > 0;
   if (M.model == 1) {
-    p->kre[0] = amp; p->kim[0] = 0.0; p->dt[0] = 0.0; p->a2k2[0] = amp * amp;
+    p->kre[0] = amp; p->kim[0] = 0.0; p->dt[0] = 0.0;
+    p->hh = have_h ? amp * amp * hpre[p->k_act - 1] : 0.0;
     return;
   }
+  double hh = 0.0;
   // wave-frame axes at psi = 0: a = (sin phi, -cos phi, 0), b = (-cos phi sin dec, -sin phi sin dec, cos dec);
   // e+ = cos 2psi (a a - b b) + sin 2psi (a b + b a), ex = -sin 2psi (a a - b b) + cos 2psi (a b + b a)
   double ax = s.sra, ay = -s.cra;
@@ -311,16 +318,17 @@ __device__ inline void probe_from_phys(const ModelDev& M, const Phys& s, Probe* 
     double fx = -s.s2psi * fp0 + s.c2psi * fx0;
     p->kre[d] = amp * fp * s.hp;       // K = F+ (1 + cos^2 i)/2 - i Fx cos i
     p->kim[d] = -amp * fx * s.hx;
-    p->a2k2[d] = p->kre[d] * p->kre[d] + p->kim[d] * p->kim[d];
+    if (have_h) hh += (p->kre[d] * p->kre[d] + p->kim[d] * p->kim[d]) * hpre[(size_t)d * M.n_bins + p->k_act - 1];
     const double* r = M.det[d].r_c;
     p->dt[d] = -(r[0] * nx + r[1] * ny + r[2] * nz);
   }
+  p->hh = hh;
 }
 
-__device__ inline void make_probe(const ModelDev& M, const double* u, Probe* p) {
+__device__ inline void make_probe(const ModelDev& M, const double* hpre, const double* u, Probe* p) {
   Phys s;
   phys_from_u(M, u, &s);
-  probe_from_phys(M, s, p);
+  probe_from_phys(M, s, hpre, p);
 }
 
 // Phase of bin k in cycles (without the detector delay).

@@ -13,6 +13,7 @@ struct DevState {
   double logX, logZ, H, lstar;
   long long n_dead;
   long long n_evals;
+  long long n_bin_terms;   // sum over evaluations of the active bins
   int iter;
   int done;        // 0 running, 1 criterion met, 2 dead-point capacity reached
   int pad[2];
@@ -69,7 +70,7 @@ struct RunDev {
   int* start;                 // [k]
   double* chol;               // [d][d]
   int* probes;                // [k] likelihood calls of each chain in the last iteration
-  int* stepout_hits;          // [k]
+  long long* bins;            // [k] active bins summed over the chain's probes in the last iteration
   double* du;                 // [cap][d]
   double* dlam;               // [cap]
   double* dlogx;              // [cap]
@@ -89,23 +90,23 @@ struct LaunchCfg {
 };
 
 // ---- launch wrappers (ns_kernels.hip) --------------------------------------
-hipError_t launch_build_tables(const ModelDev& M, const double* data_re, const double* data_im, const double* psd,
-                               double* f, double* f13, double* lnf3, double* fm53, double2* dw, double* hpre,
-                               double* scratch, hipStream_t st);
-hipError_t launch_init_live(const ModelDev& M, const RunDev& R, hipStream_t st);
-hipError_t launch_loglike(const ModelDev& M, const Tables& T, const RBTables& RB, const double* u, long n,
-                          double* out, hipStream_t st);
+// M is the host copy of the model, Md the same struct in device memory.
+hipError_t launch_build_tables(const ModelDev& M, const ModelDev* Md, const double* data_re, const double* data_im,
+                               const double* psd, double* f, double* f13, double* lnf3, double* fm53, double2* dw,
+                               double* hpre, double* scratch, hipStream_t st);
+hipError_t launch_init_live(const RunDev& R, hipStream_t st);
+hipError_t launch_loglike(const ModelDev& M, const ModelDev* Md, const Tables& T, const RBTables& RB,
+                          const double* u, long n, double* out, hipStream_t st);
 hipError_t launch_select(const double* lam, int n, int k, int* rank, int* dead, double* lstar, const int* done,
                          hipStream_t st);
-hipError_t launch_iteration(const ModelDev& M, const Tables& T, const RBTables& RB, const RunDev& R,
-                            const LaunchCfg& C, hipStream_t st);
-hipError_t launch_waveform(const ModelDev& M, const double* theta_dev, int det, int apply_cut, double* h_re,
-                           double* h_im, hipStream_t st);
-hipError_t launch_build_rb(const ModelDev& M, const double* theta_fid_dev, const double* data_re,
-                           const double* data_im, const double* psd, int nb, const int* edge_dev, RBTables* RBw,
-                           double* work, hipStream_t st);
+// ev (optional): five events recorded before select, after select, after
+// prep, after the chains and after the termination kernel.
+hipError_t launch_iteration(const ModelDev& M, const ModelDev* Md, const Tables& T, const RBTables& RB,
+                            const RunDev& R, const LaunchCfg& C, hipStream_t st, hipEvent_t* ev = nullptr);
+hipError_t launch_waveform(const ModelDev& M, const ModelDev* Md, const double* theta_dev, int det, int apply_cut,
+                           double* h_re, double* h_im, hipStream_t st);
 hipError_t launch_final(const RunDev& R, int n_sim, double* out, hipStream_t st);
-hipError_t launch_samples(const ModelDev& M, const RunDev& R, long long total, double logZ, double* theta,
+hipError_t launch_samples(const ModelDev* Md, const RunDev& R, long long total, double logZ, double* theta,
                           double* logl, double* logw, hipStream_t st);
 hipError_t configure_slice(const ModelDev& M, LaunchCfg* C);
 int likelihood_kind(const ModelDev& M);

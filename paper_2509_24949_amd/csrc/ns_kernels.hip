@@ -7,10 +7,16 @@
 //                 and its Cholesky factor, survivor list, chain start points.
 //  * k_slice      one workgroup per chain: the whole constrained slice walk
 //                 of the iteration with the chain state in registers and the
-//                 likelihood tables in LDS; every probe is a fused
-//                 waveform + Whittle evaluation reduced across the workgroup.
+//                 likelihood tables in LDS.  The per-probe source setup
+//                 (masses, amplitude, antenna patterns, PN coefficients) is
+//                 computed lane-parallel for a batch of candidate probes
+//                 whose positions are known in advance (the step-out points
+//                 and the shrink candidates), then each probe's bins are
+//                 spread over the workgroup and reduced once.
 //  * k_term       one workgroup: live evidence, termination flag, counters.
-//  * k_loglike    batched fused likelihood, one wavefront per probe.
+//  * k_loglike    batched fused likelihood: each wavefront sets up 64 probes
+//                 (one per lane) and then evaluates them one after another
+//                 with all 64 lanes over the frequency bins.
 #include <float.h>
 #include <math.h>
 
@@ -40,8 +46,17 @@ __device__ inline long long wave_sum_ll(long long v) {
   return v;
 }
 
-// Block-wide reductions for 1024-thread (16-wave) workgroups; every thread
-// receives the result, summed in a fixed order.
+// Value of lane `src` of this wavefront (src uniform), as a scalar.
+__device__ inline double lane_d(double v, int src) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ inline int lane_i(int v, int src) { return __builtin_amdgcn_readlane(v, src); }
+
+// Block-wide reductions for NT-thread workgroups; every thread receives the
+// result, combined in a fixed order.
 template <int NT>
 __device__ inline double block_sum(double v, double* sbuf) {
   constexpr int NW = NT / 64;
@@ -124,12 +139,45 @@ __device__ inline TabView stage_tables(const ModelDev& M, const Tables& T, bool 
   return V;
 }
 
-// Accumulate sum_k conj(Dw_k) e^{-i Phi_k} per detector over the active bins
-// k = lane, lane + nl, ...: acc[2d] real part, acc[2d+1] imaginary part.
+// The coefficients of the probe held by lane `src`, broadcast to the wave.
 template <int NDET>
-__device__ inline void fullgrid_accumulate(const Probe& p, const TabView& V, int lane, int nl, double* acc) {
+__device__ inline Probe probe_from_lane(const Probe& p, int src) {
+  Probe b;
+  b.x = lane_d(p.x, src);
+  b.lnx = lane_d(p.lnx, src);
+  b.pref = lane_d(p.pref, src);
+  b.c2 = lane_d(p.c2, src);
+  b.c3 = lane_d(p.c3, src);
+  b.c4 = lane_d(p.c4, src);
+  b.c5 = lane_d(p.c5, src);
+  b.c5l = lane_d(p.c5l, src);
+  b.c6 = lane_d(p.c6, src);
+  b.c6l = lane_d(p.c6l, src);
+  b.c7 = lane_d(p.c7, src);
+  b.tc = lane_d(p.tc, src);
+  b.ph0 = lane_d(p.ph0, src);
 #pragma unroll
-  for (int q = 0; q < 2 * NDET; ++q) acc[q] = 0.0;
+  for (int d = 0; d < NDET; ++d) {
+    b.kre[d] = lane_d(p.kre[d], src);
+    b.kim[d] = lane_d(p.kim[d], src);
+    b.dt[d] = lane_d(p.dt[d], src);
+  }
+  b.hh = lane_d(p.hh, src);
+  b.f_isco = 0.0;
+  b.k_act = lane_i(p.k_act, src);
+  return b;
+}
+
+// This thread's share of <d|h> summed over detectors, for the active bins
+// k = lane, lane + nl, ...:  sum_d Re[A K_d sum_k conj(Dw_dk) e^{-i Phi_dk}].
+// Per detector the bin sums a_d = sum (Dr c - Di s) and b_d = sum (Dr s + Di c)
+// are folded with A K_d = (kre, kim) as kre a_d + kim b_d before returning, so a
+// probe needs a single reduction.
+template <int NDET>
+__device__ inline double fullgrid_partial(const Probe& p, const TabView& V, int lane, int nl) {
+  double a[NDET], b[NDET];
+#pragma unroll
+  for (int d = 0; d < NDET; ++d) { a[d] = 0.0; b[d] = 0.0; }
   for (int k = lane; k < p.k_act; k += nl) {
     const double f = V.f[k];
     const double psi = phase_cycles(p, f, V.f13[k], V.lnf3[k], V.fm53[k]);
@@ -138,25 +186,14 @@ __device__ inline void fullgrid_accumulate(const Probe& p, const TabView& V, int
       double sn, cs;
       sincos_cycles(fma(f, p.dt[d], psi), &sn, &cs);
       const double2 D = V.dw[d * V.dstride + k];
-      acc[2 * d] = fma(D.x, cs, fma(-D.y, sn, acc[2 * d]));
-      acc[2 * d + 1] = fma(-D.x, sn, fma(-D.y, cs, acc[2 * d + 1]));
+      a[d] = fma(D.x, cs, fma(-D.y, sn, a[d]));
+      b[d] = fma(D.x, sn, fma(D.y, cs, b[d]));
     }
   }
-}
-
-// lambda from the reduced sums: sum_d Re[A K_d S_d] - 1/2 sum_d A^2 |K_d|^2 P_d(k_act).
-template <int NDET>
-__device__ inline double fullgrid_lambda(const ModelDev& M, const Tables& T, const Probe& p, const double* tot) {
-  double lam = 0.0;
+  double part = 0.0;
 #pragma unroll
-  for (int d = 0; d < NDET; ++d) lam += p.kre[d] * tot[2 * d] - p.kim[d] * tot[2 * d + 1];
-  if (p.k_act > 0) {
-    double hh = 0.0;
-#pragma unroll
-    for (int d = 0; d < NDET; ++d) hh += p.a2k2[d] * T.hpre[(size_t)d * M.n_bins + p.k_act - 1];
-    lam -= 0.5 * hh;
-  }
-  return lam;
+  for (int d = 0; d < NDET; ++d) part = fma(p.kre[d], a[d], fma(p.kim[d], b[d], part));
+  return part;
 }
 
 __device__ inline double gauss_lambda(const ModelDev& M, const double* u) {
@@ -171,8 +208,10 @@ __device__ inline double gauss_lambda(const ModelDev& M, const double* u) {
 }
 
 // ------------------------------------------------------------ build tables
-__global__ void k_build_tables(ModelDev M, const double* dre, const double* dim, const double* psd, double* f,
-                               double* f13, double* lnf3, double* fm53, double2* dw, double* hw) {
+__global__ void k_build_tables(const ModelDev* __restrict__ Mp, const double* dre, const double* dim,
+                               const double* psd, double* f, double* f13, double* lnf3, double* fm53, double2* dw,
+                               double* hw) {
+  const ModelDev& M = *Mp;
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= M.n_bins) return;
   const double fk = fma((double)k, M.df, M.f_lo);
@@ -219,33 +258,41 @@ __global__ void k_init_live(int n, int d, uint64_t k0, uint64_t k1, double* u) {
 }
 
 // ---------------------------------------------------------- batched lambda
+// Each wavefront takes 64 consecutive probes: lane l sets up probe base + l,
+// then the wave evaluates the probes one at a time over the bins.
 template <int NDET, int LK, bool LDS>
-__global__ __launch_bounds__(256) void k_loglike(ModelDev M, Tables T, RBTables RB, const double* __restrict__ u,
-                                                 long n, double* __restrict__ out) {
+__global__ __launch_bounds__(256) void k_loglike(const ModelDev* __restrict__ Mp, Tables T, RBTables RB,
+                                                 const double* __restrict__ u, long n, double* __restrict__ out) {
   extern __shared__ double smem[];
+  const ModelDev& M = *Mp;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   TabView V{};
   if (LK == LK_FULL) {
     V = stage_tables<NDET>(M, T, LDS, smem, tid, 256);
     if (LDS) __syncthreads();
   }
-  for (long i = (long)blockIdx.x * 4 + wv; i < n; i += (long)gridDim.x * 4) {
+  const int d = M.n_dim;
+  for (long base = ((long)blockIdx.x * 4 + wv) * 64; base < n; base += (long)gridDim.x * 256) {
+    const long i = base + lane;
+    const long src = i < n ? i : base;
     double y[MAX_DIM];
 #pragma unroll
-    for (int q = 0; q < MAX_DIM; ++q) y[q] = (q < M.n_dim) ? u[i * M.n_dim + q] : 0.0;
-    double lam;
+    for (int q = 0; q < MAX_DIM; ++q) y[q] = (q < d) ? u[src * d + q] : 0.0;
+    double mine;
     if (LK == LK_GAUSS) {
-      lam = gauss_lambda(M, y);
+      mine = gauss_lambda(M, y);
     } else {
-      Probe p;
-      make_probe(M, y, &p);
-      double acc[2 * NDET];
-      fullgrid_accumulate<NDET>(p, V, lane, 64, acc);
-#pragma unroll
-      for (int q = 0; q < 2 * NDET; ++q) acc[q] = wave_sum(acc[q]);
-      lam = fullgrid_lambda<NDET>(M, T, p, acc);
+      Probe pr;
+      make_probe(M, T.hpre, y, &pr);
+      mine = 0.0;
+      const int cnt = (n - base) < 64 ? (int)(n - base) : 64;
+      for (int p = 0; p < cnt; ++p) {
+        const Probe pb = probe_from_lane<NDET>(pr, p);
+        const double tot = wave_sum(fullgrid_partial<NDET>(pb, V, lane, 64));
+        if (lane == p) mine = tot - 0.5 * pb.hh;
+      }
     }
-    if (lane == 0) out[i] = lam;
+    if (i < n) out[i] = mine;
   }
 }
 
@@ -436,12 +483,17 @@ __global__ __launch_bounds__(1024) void k_prep(RunDev R) {
 
 // ------------------------------------------------------------ slice chains
 // One workgroup of NT threads runs chain j = blockIdx.x for all n_steps
-// steps.  State, direction and bracket are uniform across the workgroup;
-// each probe's bins are split over all NT threads.
+// steps.  State, direction and bracket are uniform across the workgroup and
+// every wavefront computes the same candidate batches, so probe coefficients
+// are broadcast within a wave with readlane.  A probe's bins are spread over
+// all NT threads; one value is reduced per probe.
 template <int NDET, int NT, int LK, bool LDS>
-__global__ __launch_bounds__(NT) void k_slice(ModelDev M, Tables T, RBTables RB, RunDev R) {
+__global__ __launch_bounds__(NT) void k_slice(const ModelDev* __restrict__ Mp, Tables T, RBTables RB, RunDev R) {
   constexpr int NW = NT / 64;
+  constexpr int SOB = 32;          // step-out candidates per side and batch
+  constexpr int SHB = 8;           // shrink candidates per batch
   extern __shared__ double smem[];
+  const ModelDev& M = *Mp;
   DevState* S = R.state;
   if (S->done) return;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -449,9 +501,9 @@ __global__ __launch_bounds__(NT) void k_slice(ModelDev M, Tables T, RBTables RB,
   const int d = R.d;
   const uint64_t t = (uint64_t)S->iter;
   const double lstar = S->lstar;
-  double* sL = smem;                                   // [MAX_DIM*MAX_DIM]
-  double* sred = sL + MAX_DIM * MAX_DIM;               // [2][NW][2*MAX_DET]
-  double* stab = sred + 2 * NW * 2 * MAX_DET;
+  double* sL = smem;                         // [MAX_DIM * MAX_DIM]
+  double* sred = sL + MAX_DIM * MAX_DIM;     // [2][NW]
+  double* stab = sred + 2 * 8;
   for (int i = tid; i < d * d; i += NT) sL[i] = R.chol[i];
   TabView V{};
   if (LK == LK_FULL) V = stage_tables<NDET>(M, T, LDS, stab, tid, NT);
@@ -459,40 +511,44 @@ __global__ __launch_bounds__(NT) void k_slice(ModelDev M, Tables T, RBTables RB,
 
   int buf = 0;
   int nprobe = 0;
-  auto eval = [&](const double* y) -> double {
-    if (LK == LK_GAUSS) return gauss_lambda(M, y);
-    Probe p;
-    make_probe(M, y, &p);
-    double acc[2 * NDET];
-    fullgrid_accumulate<NDET>(p, V, tid, NT, acc);
+  long long nbins = 0;
+  // this lane's candidate of the current batch
+  Probe pr;
+  double glam = 0.0;            // Gaussian test likelihood of the candidate
+  bool cin = false;             // candidate inside the unit cube
+
+  auto setup = [&](double tt, const double* x, const double* dir) {
+    double y[MAX_DIM];
+    cin = true;
 #pragma unroll
-    for (int q = 0; q < 2 * NDET; ++q) acc[q] = wave_sum(acc[q]);
+    for (int i = 0; i < MAX_DIM; ++i) {
+      y[i] = (i < d) ? fma(tt, dir[i], x[i]) : 0.0;
+      if (i < d && !(y[i] >= 0.0 && y[i] <= 1.0)) cin = false;
+    }
+    if (!cin) {
+#pragma unroll
+      for (int i = 0; i < MAX_DIM; ++i) y[i] = 0.5;   // a harmless point; never evaluated
+    }
+    if (LK == LK_GAUSS) glam = gauss_lambda(M, y);
+    else make_probe(M, T.hpre, y, &pr);
+  };
+  // lambda of the candidate held by lane src of every wavefront
+  auto eval = [&](int src) -> double {
+    ++nprobe;
+    if (LK == LK_GAUSS) return lane_d(glam, src);
+    const Probe pb = probe_from_lane<NDET>(pr, src);
+    nbins += pb.k_act;
+    double tot = wave_sum(fullgrid_partial<NDET>(pb, V, tid, NT));
     if constexpr (NW > 1) {
-      double* rb = sred + buf * NW * 2 * MAX_DET;
-      if (lane == 0) {
-#pragma unroll
-        for (int q = 0; q < 2 * NDET; ++q) rb[wv * 2 * MAX_DET + q] = acc[q];
-      }
+      double* rb = sred + buf * NW;
+      if (lane == 0) rb[wv] = tot;
       __syncthreads();
+      tot = 0.0;
 #pragma unroll
-      for (int q = 0; q < 2 * NDET; ++q) {
-        double s = 0.0;
-#pragma unroll
-        for (int w = 0; w < NW; ++w) s += rb[w * 2 * MAX_DET + q];
-        acc[q] = s;
-      }
+      for (int w = 0; w < NW; ++w) tot += rb[w];
       buf ^= 1;
     }
-    return fullgrid_lambda<NDET>(M, T, p, acc);
-  };
-  // membership of the constrained slice: inside the cube, then lambda > L*
-  auto in_slice = [&](const double* y, double* ly) -> bool {
-#pragma unroll
-    for (int i = 0; i < MAX_DIM; ++i)
-      if (i < d && !(y[i] >= 0.0 && y[i] <= 1.0)) return false;
-    ++nprobe;
-    *ly = eval(y);
-    return *ly > lstar;
+    return tot - 0.5 * pb.hh;
   };
 
   const int start = R.start[j];
@@ -527,15 +583,9 @@ __global__ __launch_bounds__(NT) void k_slice(ModelDev M, Tables T, RBTables RB,
 #pragma unroll
     for (int i = 0; i < MAX_DIM; ++i) {
       const double v = ((i & 3) == 0) ? r0 : ((i & 3) == 1) ? r1 : ((i & 3) == 2) ? r2 : r3;
-      z[i] = (i < d) ? __shfl(v, i >> 2, 64) : 0.0;
+      z[i] = (i < d) ? lane_d(v, i >> 2) : 0.0;
     }
-    const double uw = __shfl(r0, nbd, 64), uj = __shfl(r1, nbd, 64);
-    double ush[8];
-#pragma unroll
-    for (int a = 0; a < 8; ++a) {
-      const double v = ((a & 3) == 0) ? r0 : ((a & 3) == 1) ? r1 : ((a & 3) == 2) ? r2 : r3;
-      ush[a] = __shfl(v, nbd + 1 + (a >> 2), 64);
-    }
+    const double uw = lane_d(r0, nbd), uj = lane_d(r1, nbd);
     // direction L z / |z|
     double nrm = 0.0;
 #pragma unroll
@@ -551,43 +601,83 @@ __global__ __launch_bounds__(NT) void k_slice(ModelDev M, Tables T, RBTables RB,
         if (b <= a && a < d) acc += sL[a * d + b] * z[b];
       dir[a] = acc / nrm;
     }
-    double y[MAX_DIM], ly = 0.0;
-    auto along = [&](double tt) {
-#pragma unroll
-      for (int i = 0; i < MAX_DIM; ++i) y[i] = (i < d) ? fma(tt, dir[i], x[i]) : 0.0;
-    };
+
+    // ---- step out.  Candidate positions are fixed before any is evaluated:
+    // lane l < 32 holds the left point after l successful steps, lane 32 + l
+    // the right one, so the sequential walk only reads results.
     double lo = -w * uw, hi = lo + w;
     int J = (int)floor(R.max_stepout * uj);
     int K = R.max_stepout - 1 - J;
-    while (J > 0) {
-      along(lo);
-      if (!in_slice(y, &ly)) break;
-      lo -= w;
-      --J;
-    }
-    while (K > 0) {
-      along(hi);
-      if (!in_slice(y, &ly)) break;
-      hi += w;
-      --K;
-    }
-    for (int a = 0; a < R.max_shrink; ++a) {
-      double ua;
-      if (a < 8) {
-        ua = ush[a];
-      } else {
-        u64x4 b = philox(t, (uint64_t)j, (uint64_t)s, purpose_word(P_SHRINK, (uint64_t)(a >> 2)), R.key0, R.key1);
-        ua = unif53(b.x[a & 3]);
+    for (int jl = 0, jh = 0; J > 0 || K > 0;) {
+      {
+        const bool left = lane < SOB;
+        const int steps = left ? jl + lane : jh + lane - SOB;   // further steps beyond the current end
+        double tt = left ? lo : hi;
+        for (int q = (left ? jl : jh); q < steps; ++q) tt = left ? tt - w : tt + w;
+        setup(tt, x, dir);
       }
-      const double tt = fma(ua, hi - lo, lo);
-      along(tt);
-      if (in_slice(y, &ly)) {
+      const unsigned long long inb = __ballot(cin);
+      int q = 0;
+      while (J > 0 && q < SOB) {
+        if (!((inb >> q) & 1ull)) { J = 0; break; }
+        if (!(eval(q) > lstar)) { J = 0; break; }
+        lo -= w;
+        --J;
+        ++q;
+      }
+      jl += q;
+      q = 0;
+      while (K > 0 && q < SOB) {
+        if (!((inb >> (SOB + q)) & 1ull)) { K = 0; break; }
+        if (!(eval(SOB + q) > lstar)) { K = 0; break; }
+        hi += w;
+        --K;
+        ++q;
+      }
+      jh += q;
+    }
+
+    // ---- shrink.  Under the hypothesis that every earlier candidate was
+    // rejected the candidate sequence is fixed, so batches of SHB candidates
+    // are set up together; the first accepted one ends the step.
+    for (int a0 = 0; a0 < R.max_shrink; a0 += SHB) {
+      double tl = 0.0;          // candidate of lane a - a0
+      {
+        double l2 = lo, h2 = hi;
+        for (int q = 0; q < SHB; ++q) {
+          const int a = a0 + q;
+          double ua;
+          if (a < 8) {
+            const double v0 = ((a & 3) == 0) ? r0 : ((a & 3) == 1) ? r1 : ((a & 3) == 2) ? r2 : r3;
+            ua = lane_d(v0, nbd + 1 + (a >> 2));
+          } else {
+            u64x4 b = philox(t, (uint64_t)j, (uint64_t)s, purpose_word(P_SHRINK, (uint64_t)(a >> 2)), R.key0,
+                             R.key1);
+            ua = unif53(b.x[a & 3]);
+          }
+          const double tt = fma(ua, h2 - l2, l2);
+          if (lane == q) tl = tt;
+          if (tt < 0.0) l2 = tt; else h2 = tt;
+        }
+      }
+      setup(tl, x, dir);
+      const unsigned long long inb = __ballot(cin);
+      bool accepted = false;
+      for (int q = 0; q < SHB && a0 + q < R.max_shrink; ++q) {
+        const double tt = lane_d(tl, q);
+        if ((inb >> q) & 1ull) {
+          const double ly = eval(q);
+          if (ly > lstar) {
 #pragma unroll
-        for (int i = 0; i < MAX_DIM; ++i) x[i] = y[i];
-        lx = ly;
-        break;
+            for (int i = 0; i < MAX_DIM; ++i) x[i] = (i < d) ? fma(tt, dir[i], x[i]) : 0.0;
+            lx = ly;
+            accepted = true;
+            break;
+          }
+        }
+        if (tt < 0.0) lo = tt; else hi = tt;
       }
-      if (tt < 0.0) lo = tt; else hi = tt;
+      if (accepted) break;
     }
   }
   if (tid == 0) {
@@ -595,6 +685,7 @@ __global__ __launch_bounds__(NT) void k_slice(ModelDev M, Tables T, RBTables RB,
     for (int i = 0; i < d; ++i) R.u[(size_t)slot * d + i] = x[i];
     R.lam[slot] = lx;
     R.probes[j] = nprobe;
+    R.bins[j] = nbins;
   }
 }
 
@@ -610,28 +701,35 @@ __global__ __launch_bounds__(1024) void k_term(RunDev R) {
   double s = 0.0;
   for (int i = tid; i < n; i += 1024) s += exp(order_value(R.lam[i]) - m);
   s = block_sum<1024>(s, sbuf);
-  double pe = 0.0;
-  for (int j = tid; j < R.k; j += 1024) pe += (double)R.probes[j];
+  double pe = 0.0, pb = 0.0;
+  for (int j = tid; j < R.k; j += 1024) {
+    pe += (double)R.probes[j];
+    pb += (double)R.bins[j];
+  }
   pe = block_sum<1024>(pe, sbuf);
+  pb = block_sum<1024>(pb, sbuf);
   if (tid == 0) {
     const double logz_live = S->logX + m + log(s / n);
     int done = 0;
     if (R.log_term > NEG_INF && logz_live - S->logZ < R.log_term) done = 1;
     if (S->n_dead + R.k > R.cap) done = 2;
     S->n_evals += (long long)pe;
+    S->n_bin_terms += (long long)pb;
     S->iter += 1;
     S->done = done;
   }
 }
 
 // ---------------------------------------------------------------- waveform
-__global__ void k_waveform(ModelDev M, const double* theta, int det, int apply_cut, double* hre, double* him) {
+__global__ void k_waveform(const ModelDev* __restrict__ Mp, const double* theta, int det, int apply_cut, double* hre,
+                           double* him) {
+  const ModelDev& M = *Mp;
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= M.n_bins) return;
   Phys s;
   phys_from_theta(M, theta, &s);
   Probe p;
-  probe_from_phys(M, s, &p);
+  probe_from_phys(M, s, nullptr, &p);
   const double f = fma((double)k, M.df, M.f_lo);
   if (apply_cut && k >= p.k_act) {
     hre[k] = 0.0;
@@ -737,7 +835,9 @@ __global__ __launch_bounds__(1024) void k_final(RunDev R, int n_sim, double* out
 
 // Weighted samples: dead points then live points, physical parameters and
 // log-weights normalised by the final log Z.
-__global__ void k_samples(ModelDev M, RunDev R, double logZ, double* theta, double* logl, double* logw) {
+__global__ void k_samples(const ModelDev* __restrict__ Mp, RunDev R, double logZ, double* theta, double* logl,
+                          double* logw) {
+  const ModelDev& M = *Mp;
   const long long nd = R.state->n_dead;
   const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= nd + R.n) return;
@@ -763,41 +863,41 @@ __global__ void k_samples(ModelDev M, RunDev R, double logZ, double* theta, doub
 }
 
 template <int NDET, int LK, bool LDS>
-hipError_t launch_loglike_t(const ModelDev& M, const Tables& T, const RBTables& RB, const double* u, long n,
-                            double* out, hipStream_t st) {
+hipError_t launch_loglike_t(const ModelDev& M, const ModelDev* Md, const Tables& T, const RBTables& RB,
+                            const double* u, long n, double* out, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   const size_t lds = LDS ? (size_t)M.k_lim * (4 * sizeof(double) + NDET * sizeof(double2)) : 0;
-  long blocks = (n + 3) / 4;
-  if (blocks > 2048 * 8) blocks = 2048 * 8;
-  hipLaunchKernelGGL((k_loglike<NDET, LK, LDS>), dim3((unsigned)blocks), dim3(256), lds, st, M, T, RB, u, n, out);
+  long blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL((k_loglike<NDET, LK, LDS>), dim3((unsigned)blocks), dim3(256), lds, st, Md, T, RB, u, n, out);
   return hipGetLastError();
 }
 
 template <int NDET, int NT, int LK, bool LDS>
-hipError_t launch_slice_t(const ModelDev& M, const Tables& T, const RBTables& RB, const RunDev& R, size_t lds,
+hipError_t launch_slice_t(const ModelDev* Md, const Tables& T, const RBTables& RB, const RunDev& R, size_t lds,
                           hipStream_t st) {
-  hipLaunchKernelGGL((k_slice<NDET, NT, LK, LDS>), dim3(R.k), dim3(NT), lds, st, M, T, RB, R);
+  hipLaunchKernelGGL((k_slice<NDET, NT, LK, LDS>), dim3(R.k), dim3(NT), lds, st, Md, T, RB, R);
   return hipGetLastError();
 }
 
 template <int NDET, int NT>
-hipError_t launch_slice_nt(const ModelDev& M, const Tables& T, const RBTables& RB, const RunDev& R,
+hipError_t launch_slice_nt(const ModelDev* Md, const Tables& T, const RBTables& RB, const RunDev& R,
                            const LaunchCfg& C, hipStream_t st) {
-  if (C.lds_tables) return launch_slice_t<NDET, NT, LK_FULL, true>(M, T, RB, R, C.lds_bytes, st);
-  return launch_slice_t<NDET, NT, LK_FULL, false>(M, T, RB, R, C.lds_bytes, st);
+  if (C.lds_tables) return launch_slice_t<NDET, NT, LK_FULL, true>(Md, T, RB, R, C.lds_bytes, st);
+  return launch_slice_t<NDET, NT, LK_FULL, false>(Md, T, RB, R, C.lds_bytes, st);
 }
 
 template <int NDET>
-hipError_t launch_slice_det(const ModelDev& M, const Tables& T, const RBTables& RB, const RunDev& R,
+hipError_t launch_slice_det(const ModelDev* Md, const Tables& T, const RBTables& RB, const RunDev& R,
                             const LaunchCfg& C, hipStream_t st) {
   switch (C.slice_threads) {
-    case 64: return launch_slice_nt<NDET, 64>(M, T, RB, R, C, st);
-    case 128: return launch_slice_nt<NDET, 128>(M, T, RB, R, C, st);
-    default: return launch_slice_nt<NDET, 256>(M, T, RB, R, C, st);
+    case 64: return launch_slice_nt<NDET, 64>(Md, T, RB, R, C, st);
+    case 128: return launch_slice_nt<NDET, 128>(Md, T, RB, R, C, st);
+    default: return launch_slice_nt<NDET, 256>(Md, T, RB, R, C, st);
   }
 }
 
-size_t slice_lds_fixed(int nt) { return (size_t)(MAX_DIM * MAX_DIM + 2 * (nt / 64) * 2 * MAX_DET) * sizeof(double); }
+size_t slice_lds_fixed() { return (size_t)(MAX_DIM * MAX_DIM + 16) * sizeof(double); }
 
 }  // namespace
 
@@ -807,22 +907,22 @@ hipError_t configure_slice(const ModelDev& M, LaunchCfg* C) {
   if (M.likelihood == LK_GAUSS) {
     C->slice_threads = 64;
     C->lds_tables = false;
-    C->lds_bytes = slice_lds_fixed(64);
+    C->lds_bytes = slice_lds_fixed();
     return hipSuccess;
   }
   const long work = (long)M.k_lim * M.n_det;   // (bin, detector) terms of the widest probe
   C->slice_threads = work <= 96 ? 64 : (work <= 320 ? 128 : 256);
   const size_t tab = (size_t)M.k_lim * (4 * sizeof(double) + M.n_det * sizeof(double2));
   C->lds_tables = tab <= 64 * 1024;
-  C->lds_bytes = slice_lds_fixed(C->slice_threads) + (C->lds_tables ? tab : 0);
+  C->lds_bytes = slice_lds_fixed() + (C->lds_tables ? tab : 0);
   return hipSuccess;
 }
 
-hipError_t launch_build_tables(const ModelDev& M, const double* dre, const double* dim, const double* psd,
-                               double* f, double* f13, double* lnf3, double* fm53, double2* dw, double* hpre,
-                               double* scratch, hipStream_t st) {
+hipError_t launch_build_tables(const ModelDev& M, const ModelDev* Md, const double* dre, const double* dim,
+                               const double* psd, double* f, double* f13, double* lnf3, double* fm53, double2* dw,
+                               double* hpre, double* scratch, hipStream_t st) {
   const int nb = (M.n_bins + 255) / 256;
-  hipLaunchKernelGGL(k_build_tables, dim3(nb), dim3(256), 0, st, M, dre, dim, psd, f, f13, lnf3, fm53, dw,
+  hipLaunchKernelGGL(k_build_tables, dim3(nb), dim3(256), 0, st, Md, dre, dim, psd, f, f13, lnf3, fm53, dw,
                      scratch);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -830,23 +930,23 @@ hipError_t launch_build_tables(const ModelDev& M, const double* dre, const doubl
   return hipGetLastError();
 }
 
-hipError_t launch_init_live(const ModelDev& M, const RunDev& R, hipStream_t st) {
+hipError_t launch_init_live(const RunDev& R, hipStream_t st) {
   hipLaunchKernelGGL(k_init_live, dim3((R.n + 255) / 256), dim3(256), 0, st, R.n, R.d, R.key0, R.key1, R.u);
   return hipGetLastError();
 }
 
-hipError_t launch_loglike(const ModelDev& M, const Tables& T, const RBTables& RB, const double* u, long n,
-                          double* out, hipStream_t st) {
-  if (M.likelihood == LK_GAUSS) return launch_loglike_t<1, LK_GAUSS, false>(M, T, RB, u, n, out, st);
+hipError_t launch_loglike(const ModelDev& M, const ModelDev* Md, const Tables& T, const RBTables& RB,
+                          const double* u, long n, double* out, hipStream_t st) {
+  if (M.likelihood == LK_GAUSS) return launch_loglike_t<1, LK_GAUSS, false>(M, Md, T, RB, u, n, out, st);
   const size_t tab = (size_t)M.k_lim * (4 * sizeof(double) + M.n_det * sizeof(double2));
   const bool lds = tab <= 64 * 1024;
   switch (M.n_det) {
-    case 1: return lds ? launch_loglike_t<1, LK_FULL, true>(M, T, RB, u, n, out, st)
-                       : launch_loglike_t<1, LK_FULL, false>(M, T, RB, u, n, out, st);
-    case 2: return lds ? launch_loglike_t<2, LK_FULL, true>(M, T, RB, u, n, out, st)
-                       : launch_loglike_t<2, LK_FULL, false>(M, T, RB, u, n, out, st);
-    default: return lds ? launch_loglike_t<3, LK_FULL, true>(M, T, RB, u, n, out, st)
-                        : launch_loglike_t<3, LK_FULL, false>(M, T, RB, u, n, out, st);
+    case 1: return lds ? launch_loglike_t<1, LK_FULL, true>(M, Md, T, RB, u, n, out, st)
+                       : launch_loglike_t<1, LK_FULL, false>(M, Md, T, RB, u, n, out, st);
+    case 2: return lds ? launch_loglike_t<2, LK_FULL, true>(M, Md, T, RB, u, n, out, st)
+                       : launch_loglike_t<2, LK_FULL, false>(M, Md, T, RB, u, n, out, st);
+    default: return lds ? launch_loglike_t<3, LK_FULL, true>(M, Md, T, RB, u, n, out, st)
+                        : launch_loglike_t<3, LK_FULL, false>(M, Md, T, RB, u, n, out, st);
   }
 }
 
@@ -856,29 +956,36 @@ hipError_t launch_select(const double* lam, int n, int k, int* rank, int* dead, 
   return hipGetLastError();
 }
 
-hipError_t launch_iteration(const ModelDev& M, const Tables& T, const RBTables& RB, const RunDev& R,
-                            const LaunchCfg& C, hipStream_t st) {
-  hipError_t e = launch_select(R.lam, R.n, R.k, R.rank, R.dead, nullptr, &R.state->done, st);
+hipError_t launch_iteration(const ModelDev& M, const ModelDev* Md, const Tables& T, const RBTables& RB,
+                            const RunDev& R, const LaunchCfg& C, hipStream_t st, hipEvent_t* ev) {
+  hipError_t e;
+  if (ev && (e = hipEventRecord(ev[0], st)) != hipSuccess) return e;
+  e = launch_select(R.lam, R.n, R.k, R.rank, R.dead, nullptr, &R.state->done, st);
   if (e != hipSuccess) return e;
+  if (ev && (e = hipEventRecord(ev[1], st)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_prep, dim3(1), dim3(1024), (size_t)R.n * sizeof(int), st, R);
   if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (ev && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;
   if (M.likelihood == LK_GAUSS) {
-    e = launch_slice_t<1, 64, LK_GAUSS, false>(M, T, RB, R, C.lds_bytes, st);
+    e = launch_slice_t<1, 64, LK_GAUSS, false>(Md, T, RB, R, C.lds_bytes, st);
   } else {
     switch (M.n_det) {
-      case 1: e = launch_slice_det<1>(M, T, RB, R, C, st); break;
-      case 2: e = launch_slice_det<2>(M, T, RB, R, C, st); break;
-      default: e = launch_slice_det<3>(M, T, RB, R, C, st); break;
+      case 1: e = launch_slice_det<1>(Md, T, RB, R, C, st); break;
+      case 2: e = launch_slice_det<2>(Md, T, RB, R, C, st); break;
+      default: e = launch_slice_det<3>(Md, T, RB, R, C, st); break;
     }
   }
   if (e != hipSuccess) return e;
+  if (ev && (e = hipEventRecord(ev[3], st)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_term, dim3(1), dim3(1024), 0, st, R);
-  return hipGetLastError();
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (ev && (e = hipEventRecord(ev[4], st)) != hipSuccess) return e;
+  return hipSuccess;
 }
 
-hipError_t launch_waveform(const ModelDev& M, const double* theta_dev, int det, int apply_cut, double* h_re,
-                           double* h_im, hipStream_t st) {
-  hipLaunchKernelGGL(k_waveform, dim3((M.n_bins + 255) / 256), dim3(256), 0, st, M, theta_dev, det, apply_cut,
+hipError_t launch_waveform(const ModelDev& M, const ModelDev* Md, const double* theta_dev, int det, int apply_cut,
+                           double* h_re, double* h_im, hipStream_t st) {
+  hipLaunchKernelGGL(k_waveform, dim3((M.n_bins + 255) / 256), dim3(256), 0, st, Md, theta_dev, det, apply_cut,
                      h_re, h_im);
   return hipGetLastError();
 }
@@ -888,17 +995,12 @@ hipError_t launch_final(const RunDev& R, int n_sim, double* out, hipStream_t st)
   return hipGetLastError();
 }
 
-hipError_t launch_samples(const ModelDev& M, const RunDev& R, long long total, double logZ, double* theta,
+hipError_t launch_samples(const ModelDev* Md, const RunDev& R, long long total, double logZ, double* theta,
                           double* logl, double* logw, hipStream_t st) {
   if (total <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_samples, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, M, R, logZ, theta, logl,
+  hipLaunchKernelGGL(k_samples, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, Md, R, logZ, theta, logl,
                      logw);
   return hipGetLastError();
-}
-
-hipError_t launch_build_rb(const ModelDev&, const double*, const double*, const double*, const double*, int,
-                           const int*, RBTables*, double*, hipStream_t) {
-  return hipErrorNotSupported;
 }
 
 }  // namespace ns
