@@ -26,15 +26,28 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6          # MI355X vector FP64
+FP32_PEAK_TFLOPS = 157.3         # MI355X vector FP32 (packed)
 SINCOS_FLOPS = 44                # flops of the double-precision sincos in cycles
 PHASE_FLOPS = 24                 # per (probe, bin): PN phase series, shared by the detectors
 DET_FLOPS = 2 + SINCOS_FLOPS + 8 # per (probe, bin, detector): delay, sincos, complex accumulate
+# mixed form per (probe, bin, detector): delay and reduction in double (4), two
+# transcendental float ops (sin, cos), complex accumulate (8)
+DET_FLOPS_MIXED = 4 + 2 + 8
+# relative binning per (probe, edge): the phase (24) and per detector delay,
+# sincos and the complex ratio (2 + sincos + 6); per (probe, coarse bin,
+# detector) the linear-model terms (27), counted per edge as nb/(nb+1) of it
+RB_EDGE_DET = 2 + SINCOS_FLOPS + 6
+RB_EDGE_DET_MIXED = 4 + 2 + 6
+RB_BIN_DET = 27
 
+_GRID2 = "3-detector aligned-spin TaylorF2 (11 parameters), 4017 bins/detector (20-1024 Hz, df 0.25 Hz), network SNR 20"
 WORKLOADS = {
-    "cfg2": "3-detector aligned-spin TaylorF2 (11 parameters), full-grid Whittle, 4017 bins/detector "
-            "(20-1024 Hz, df 0.25 Hz), network SNR 20, n_live 1000, n_delete 500, 55 slice steps, FP64",
+    "cfg2": _GRID2 + ", full-grid Whittle, n_live 1000, n_delete 500, 55 slice steps, FP64",
     "cfg1": "1-detector TaylorF2 (4 parameters), full-grid Whittle, 473 bins (20-256 Hz, df 0.5 Hz), "
             "SNR 15, n_live 500, n_delete 250, 20 slice steps, FP64",
+    "cfg3": _GRID2 + ", relative binning (128 geometric bins), n_live 1000, n_delete 500, 55 slice steps, FP64",
+    "cfg4": _GRID2 + ", full-grid Whittle, n_live 2000, n_delete 1000, 55 slice steps, mixed precision",
+    "cfg4rb": _GRID2 + ", relative binning (128 bins), n_live 2000, n_delete 1000, 55 slice steps, mixed precision",
 }
 
 
@@ -42,8 +55,17 @@ def log(msg: str):
     print(msg, file=sys.stderr, flush=True)
 
 
-def flops_per_bin(n_det: int) -> int:
-    return PHASE_FLOPS + n_det * DET_FLOPS
+def flops_per_term(w) -> float:
+    """Algorithmic flops per counted term (full grid: one active bin of one
+    probe; relative binning: one edge of one probe)."""
+    from paper_2509_24949_amd import synth
+
+    mixed = w.precision == 1
+    if w.likelihood == synth.LIKE_RB:
+        nb = w.rb_n_bins
+        edge = RB_EDGE_DET_MIXED if mixed else RB_EDGE_DET
+        return PHASE_FLOPS + w.n_det * edge + w.n_det * RB_BIN_DET * nb / (nb + 1)
+    return PHASE_FLOPS + w.n_det * (DET_FLOPS_MIXED if mixed else DET_FLOPS)
 
 
 def cpu_baseline(name: str, seconds: float, threads: int):
@@ -79,7 +101,20 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-run", action="store_true", help="skip the complete-run timing")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "slice_kernel_traffic.json"))
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (reference for HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+
+        n = args.copy_calibration * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_mib": args.copy_calibration, "launches": 3}))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
               "(the sampler runs on a single GPU)", file=sys.stderr)
@@ -135,9 +170,11 @@ def main():
         f"{stats['ms_slice'] / K:.3f} ms/iter, select {stats['ms_select'] / K:.3f}, prep {stats['ms_prep'] / K:.3f}, "
         f"term {stats['ms_term'] / K:.3f}")
     r.close()
-    flops_launch = bins_timed / K * flops_per_bin(w.n_det)
+    flops_launch = bins_timed / K * flops_per_term(w)
     slice_s = stats["ms_slice"] / K * 1e-3
     achieved = flops_launch / slice_s / 1e12
+    mixed = w.precision == 1
+    peak = FP32_PEAK_TFLOPS if mixed else FP64_PEAK_TFLOPS
     traffic = None
     if os.path.exists(args.traffic):
         try:
@@ -158,13 +195,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32+f64" if mixed else "f64",
         "data": "synthetic (seeded Gaussian noise plus an injected TaylorF2 signal; no real detector data)",
         "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}", "n_live": w.n_live,
                    "n_delete": w.n_delete, "n_steps": w.n_steps, "n_bins": w.n_bins, "n_det": w.n_det,
-                   "n_dim": w.n_dim},
-        "roofline": {"bound": "alu", "kernel": "k_slice", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
+                   "n_dim": w.n_dim, "likelihood": "relative binning" if w.likelihood == 1 else "full grid",
+                   "precision": "mixed" if mixed else "fp64"},
+        "roofline": {"bound": "alu", "kernel": "k_slice", "achieved": achieved, "peak": peak,
+                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
                      "flops_per_launch": flops_launch, "launch_ms": slice_s * 1e3,
                      "bin_terms_per_launch": bins_timed / K},
         **run_info,

@@ -103,7 +103,7 @@ typedef struct {
     const double* det_geom;    /* host [n_det][9]: vertex (m, Earth-fixed), x-arm, y-arm unit vectors */
     double gmst;               /* Greenwich sidereal angle, rad */
     double fixed_dist_mpc;     /* TF2_4P only: distance, Mpc, > 0 */
-    int rb_n_bins;             /* NS_LIKE_RB: number of coarse bins (1..n_bins-1) */
+    int rb_n_bins;             /* NS_LIKE_RB: number of coarse bins (1..min(n_bins-1, 1024)) */
     const double* rb_fiducial; /* NS_LIKE_RB: host [n_dim] physical fiducial parameters */
     const double* gauss_mu;    /* NS_LIKE_GAUSS: host [n_dim] */
     double gauss_sigma;        /* NS_LIKE_GAUSS: > 0 */

@@ -275,9 +275,9 @@ class Run:
         return {name: getattr(st, name) for name, _ in Stats._fields_}
 
     def close(self):
-        if getattr(self, "h", None):
-            lib().ns_free(self.h)
-            self.h = None
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.ns_free(self.h)
+        self.h = None
 
     def __del__(self):
         self.close()

@@ -174,7 +174,18 @@ int validate_and_model(const ns_problem* P, ModelDev* M) {
   const double f_max = 1.0 / (pow(6.0, 1.5) * PI * m_min) * (1.0 + 1e-9);
   const double kk = floor((f_max - P->f_lo) / P->df) + 2.0;
   M->k_lim = (int)std::min<double>((double)P->n_bins, std::max(0.0, kk));
-  if (P->likelihood == NS_LIKE_RB) return fail(NS_E_ARG, "relative binning is not available in this build");
+  if (P->likelihood == NS_LIKE_RB) {
+    if (P->rb_n_bins < 1 || P->rb_n_bins >= P->n_bins || P->rb_n_bins > 1024)
+      return fail(NS_E_ARG, "rb_n_bins must be in [1, min(n_bins - 1, 1024)]");
+    if (!P->rb_fiducial) return fail(NS_E_ARG, "rb_fiducial is NULL");
+    const double* th = P->rb_fiducial;
+    for (int i = 0; i < P->n_dim; ++i)
+      if (!isfinite(th[i])) return fail(NS_E_ARG, "rb_fiducial[%d] is not finite", i);
+    if (!(th[0] > 0.0)) return fail(NS_E_ARG, "fiducial chirp mass must be positive");
+    if (P->model == NS_MODEL_TF2_4P && !(th[1] > 0.0 && th[1] <= 0.25)) return fail(NS_E_ARG, "fiducial eta must lie in (0, 0.25]");
+    if (P->model == NS_MODEL_TF2_11P && !(th[1] > 0.0 && th[1] <= 1.0 && th[4] > 0.0))
+      return fail(NS_E_ARG, "fiducial needs q in (0, 1] and a positive distance");
+  }
   return NS_OK;
 }
 
@@ -186,7 +197,7 @@ int validate_opts(const ns_opts* o) {
   if (!(o->slice_width > 0.0)) return fail(NS_E_ARG, "slice_width must be > 0");
   if (o->max_stepout < 1 || o->max_shrink < 1) return fail(NS_E_ARG, "max_stepout and max_shrink must be >= 1");
   if (o->max_iter < 1) return fail(NS_E_ARG, "max_iter must be >= 1");
-  if (o->precision != NS_FP64) return fail(NS_E_ARG, "only NS_FP64 is available in this build");
+  if (o->precision != NS_FP64 && o->precision != NS_MIXED) return fail(NS_E_ARG, "precision must be NS_FP64 or NS_MIXED");
   return NS_OK;
 }
 
@@ -211,6 +222,20 @@ int ns_init(ns_run** out, const ns_problem* P, const ns_opts* O, void* stream) {
   if ((rc = validate_opts(O))) return rc;
   ns_run* r = new (std::nothrow) ns_run();
   if (!r) return fail(NS_E_OOM, "host allocation failed");
+  M.mixed = (O->precision == NS_MIXED && M.likelihood != NS_LIKE_GAUSS) ? 1 : 0;
+  M.dw_scale = 1.0;
+  if (M.mixed && M.likelihood == NS_LIKE_FULL) {
+    // a power of two that brings the largest whitened data value near 1 (exact in float)
+    double mx = 0.0;
+    for (int d = 0; d < M.n_det; ++d)
+      for (int k = 0; k < M.n_bins; ++k) {
+        const size_t o = (size_t)d * M.n_bins + k;
+        const double f = M.f_lo + k * M.df;
+        const double a = 4.0 * M.df * pow(f, -7.0 / 6.0) / P->psd[o];
+        mx = std::max(mx, a * std::max(fabs(P->data_re[o]), fabs(P->data_im[o])));
+      }
+    if (mx > 0.0 && isfinite(mx)) M.dw_scale = ldexp(1.0, -ilogb(mx));
+  }
   r->M = M;
   r->st = static_cast<hipStream_t>(stream);
   const int n = O->n_live, k = O->n_delete, d = P->n_dim;
@@ -267,12 +292,73 @@ int ns_init(ns_run** out, const ns_problem* P, const ns_opts* O, void* stream) {
     if (e == hipSuccess)
       e = launch_build_tables(M, r->Md, dre, dim, psd, f, f13, lnf3, fm53, dw, hpre, scratch, r->st);
     if (e == hipSuccess) e = hipStreamSynchronize(r->st);
+    r->T.f = f; r->T.f13 = f13; r->T.lnf3 = lnf3; r->T.fm53 = fm53; r->T.dw = dw; r->T.hpre = hpre;
+    if (e == hipSuccess && M.mixed && M.likelihood == NS_LIKE_FULL) {
+      float2* dw32;
+      if (mem.alloc(&dw32, nbd) != hipSuccess) {
+        (void)hipFree(stage);
+        return cleanup(fail(NS_E_OOM, "hipMalloc failed for the float data table"));
+      }
+      e = launch_to_float(dw, dw32, nbd, M.dw_scale, r->st);
+      r->T.dw32 = dw32;
+    }
+    if (e == hipSuccess && M.likelihood == NS_LIKE_RB) {
+      // relative binning: edges, fiducial phases, summary sums (scratch holds the weights 4 df f^(-7/3) / S)
+      const int nb = P->rb_n_bins;
+      const size_t ne = nb + 1, nbin = (size_t)M.n_det * nb;
+      RBBuffers B{};
+      double* th = nullptr;
+      bool ok = mem.alloc(&B.edge, ne) == hipSuccess && mem.alloc(&B.fe, ne) == hipSuccess &&
+                mem.alloc(&B.fe13, ne) == hipSuccess && mem.alloc(&B.lnfe3, ne) == hipSuccess &&
+                mem.alloc(&B.fem53, ne) == hipSuccess && mem.alloc(&B.phi0, (size_t)M.n_det * ne) == hipSuccess &&
+                mem.alloc(&B.fm, nb) == hipSuccess && mem.alloc(&B.inv_w, nb) == hipSuccess &&
+                mem.alloc(&B.g0, M.n_det) == hipSuccess && mem.alloc(&B.A0, nbin) == hipSuccess &&
+                mem.alloc(&B.A1, nbin) == hipSuccess && mem.alloc(&B.B0, nbin) == hipSuccess &&
+                mem.alloc(&B.B1, nbin) == hipSuccess && mem.alloc(&B.cA0, nbd) == hipSuccess &&
+                mem.alloc(&B.cA1, nbd) == hipSuccess && mem.alloc(&B.cB0, nbd) == hipSuccess &&
+                mem.alloc(&B.cB1, nbd) == hipSuccess && mem.alloc(&th, MAX_DIM) == hipSuccess;
+      if (!ok) {
+        (void)hipFree(stage);
+        return cleanup(fail(NS_E_OOM, "hipMalloc failed for relative-binning tables"));
+      }
+      std::vector<int> edges(ne);
+      e = hipMemcpyAsync(th, P->rb_fiducial, P->n_dim * sizeof(double), hipMemcpyHostToDevice, r->st);
+      if (e == hipSuccess) e = launch_build_rb_edges(r->Md, nb, B, r->st);
+      if (e == hipSuccess) e = hipMemcpyAsync(edges.data(), B.edge, ne * sizeof(int), hipMemcpyDeviceToHost, r->st);
+      if (e == hipSuccess) e = hipStreamSynchronize(r->st);
+      if (e == hipSuccess) {
+        for (int i = 0; i < nb; ++i)
+          if (edges[i + 1] <= edges[i]) {
+            (void)hipFree(stage);
+            return cleanup(fail(NS_E_ARG, "rb_n_bins = %d gives empty coarse bins on this grid (edge %d)", nb, i + 1));
+          }
+      }
+      if (e == hipSuccess) e = launch_build_rb_sums(M, r->Md, r->T, scratch, th, nb, B, r->st);
+      if (e == hipSuccess && M.mixed) {
+        if (mem.alloc(&B.A0f, nbin) != hipSuccess || mem.alloc(&B.A1f, nbin) != hipSuccess ||
+            mem.alloc(&B.B0f, nbin) != hipSuccess || mem.alloc(&B.B1f, nbin) != hipSuccess) {
+          (void)hipFree(stage);
+          return cleanup(fail(NS_E_OOM, "hipMalloc failed for the float bin sums"));
+        }
+        e = launch_to_float(B.A0, B.A0f, nbin, 1.0, r->st);
+        if (e == hipSuccess) e = launch_to_float(B.A1, B.A1f, nbin, 1.0, r->st);
+        if (e == hipSuccess) e = launch_to_float(B.B0, B.B0f, nbin, 1.0, r->st);
+        if (e == hipSuccess) e = launch_to_float(B.B1, B.B1f, nbin, 1.0, r->st);
+      }
+      if (e == hipSuccess) e = hipStreamSynchronize(r->st);
+      RBTables& RB = r->RB;
+      RB.nb = nb;
+      RB.edge = B.edge; RB.fe = B.fe; RB.fe13 = B.fe13; RB.lnfe3 = B.lnfe3; RB.fem53 = B.fem53;
+      RB.phi0 = B.phi0; RB.g0 = B.g0; RB.fm = B.fm; RB.inv_w = B.inv_w;
+      RB.A0 = B.A0; RB.A1 = B.A1; RB.B0 = B.B0; RB.B1 = B.B1;
+      RB.cA0 = B.cA0; RB.cA1 = B.cA1; RB.cB0 = B.cB0; RB.cB1 = B.cB1;
+      RB.A0f = B.A0f; RB.A1f = B.A1f; RB.B0f = B.B0f; RB.B1f = B.B1f;
+    }
     (void)hipFree(stage);
     if (e != hipSuccess) return cleanup(fail(NS_E_HIP, "building likelihood tables: %s", hipGetErrorString(e)));
-    r->T.f = f; r->T.f13 = f13; r->T.lnf3 = lnf3; r->T.fm53 = fm53; r->T.dw = dw; r->T.hpre = hpre;
   }
 #undef ALLOC
-  (void)configure_slice(r->M, &r->C);
+  (void)configure_slice(r->M, r->RB.nb, &r->C);
   DevState s0{};
   s0.logX = 0.0;
   s0.logZ = -__builtin_inf();

@@ -68,13 +68,13 @@ __host__ __device__ inline double order_value(double v) {
 }
 
 // ---------------------------------------------------------- sincos (cycles)
-// sin and cos of 2 pi p for a phase p given in cycles.  p is reduced to
+// (sin, cos) of 2 pi p for a phase p given in cycles.  p is reduced to
 // r = p - rint(p) in [-1/2, 1/2] and then to y = r - q/4 in [-1/8, 1/8]
 // (both subtractions are exact), sin(2 pi y) and cos(2 pi y) are evaluated
 // from their Taylor series through y^15 and y^16 (first omitted terms below
 // 5e-17), and the quarter turns q are applied by swapping and sign flips
 // without branches.
-__device__ inline void sincos_cycles(double p, double* s_out, double* c_out) {
+__device__ inline double2 sincos_cycles(double p) {
   const double r = p - rint(p);
   const double q = rint(4.0 * r);
   const double y = fma(-0.25, q, r);
@@ -101,8 +101,8 @@ __device__ inline void sincos_cycles(double p, double* s_out, double* c_out) {
   const double c1 = swap ? sn : cs;
   const uint64_t fs = (uint64_t)(qi & 2) << 62;         // sin negative for q = 2, 3 (mod 4)
   const uint64_t fc = (uint64_t)((qi + 1) & 2) << 62;   // cos negative for q = 1, 2 (mod 4)
-  *s_out = __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, s1) ^ fs);
-  *c_out = __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, c1) ^ fc);
+  return make_double2(__builtin_bit_cast(double, __builtin_bit_cast(uint64_t, s1) ^ fs),
+                      __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, c1) ^ fc));
 }
 
 // ----------------------------------------------------------------- problem
@@ -128,6 +128,8 @@ struct ModelDev {
   DetDev det[MAX_DET];
   double gauss_mu[MAX_DIM];
   double gauss_inv2s2, gauss_norm;   // 1/(2 s^2), -d/2 ln(2 pi s^2)
+  int mixed;                   // float bulk arithmetic (double phase, setup and evidence)
+  double dw_scale;             // power of two: the float data table holds dw * dw_scale
 };
 
 // Physical quantities of one parameter point, reduced to what the strain needs.
@@ -204,18 +206,23 @@ __device__ inline void phys_from_u(const ModelDev& M, const double* u, Phys* s) 
   s->sigma = 79.0 / 8.0 * s->eta * c1 * c2;
   const double dv = prior_affine(P, 4, u[4]);
   s->dist_s = (P.kind[4] == 3 ? cbrt(dv) : dv) * MPC_S;
-  double ci, sn;
-  if (P.kind[5] == 1) ci = prior_affine(P, 5, u[5]);
-  else sincos_cycles(prior_affine(P, 5, u[5]) * (1.0 / TWO_PI), &sn, &ci);
+  const double ci = (P.kind[5] == 1) ? prior_affine(P, 5, u[5])
+                                     : sincos_cycles(prior_affine(P, 5, u[5]) * (1.0 / TWO_PI)).y;
   s->hp = 0.5 * fma(ci, ci, 1.0);
   s->hx = ci;
-  sincos_cycles(prior_affine(P, 6, u[6]) * (1.0 / PI), &s->s2psi, &s->c2psi);   // angle 2 psi
-  sincos_cycles((prior_affine(P, 7, u[7]) - M.gmst) * (1.0 / TWO_PI), &s->sra, &s->cra);
+  const double2 p2 = sincos_cycles(prior_affine(P, 6, u[6]) * (1.0 / PI));   // angle 2 psi
+  s->s2psi = p2.x;
+  s->c2psi = p2.y;
+  const double2 ra = sincos_cycles((prior_affine(P, 7, u[7]) - M.gmst) * (1.0 / TWO_PI));
+  s->sra = ra.x;
+  s->cra = ra.y;
   if (P.kind[8] == 2) {
     s->sdec = prior_affine(P, 8, u[8]);
     s->cdec = sqrt(fmax(0.0, 1.0 - s->sdec * s->sdec));
   } else {
-    sincos_cycles(prior_affine(P, 8, u[8]) * (1.0 / TWO_PI), &s->sdec, &s->cdec);
+    const double2 de = sincos_cycles(prior_affine(P, 8, u[8]) * (1.0 / TWO_PI));
+    s->sdec = de.x;
+    s->cdec = de.y;
   }
   s->tc = prior_affine(P, 9, u[9]);
   s->phic = prior_affine(P, 10, u[10]);
@@ -238,13 +245,18 @@ __device__ inline void phys_from_theta(const ModelDev& M, const double* th, Phys
   s->beta = (c1 * (113.0 * m1 * m1 + 75.0 * s->eta) + c2 * (113.0 * m2 * m2 + 75.0 * s->eta)) / 12.0;
   s->sigma = 79.0 / 8.0 * s->eta * c1 * c2;
   s->dist_s = th[4] * MPC_S;
-  double sn, ci;
-  sincos_cycles(th[5] / TWO_PI, &sn, &ci);
+  const double ci = sincos_cycles(th[5] / TWO_PI).y;
   s->hp = 0.5 * fma(ci, ci, 1.0);
   s->hx = ci;
-  sincos_cycles(th[6] / PI, &s->s2psi, &s->c2psi);
-  sincos_cycles((th[7] - M.gmst) / TWO_PI, &s->sra, &s->cra);
-  sincos_cycles(th[8] / TWO_PI, &s->sdec, &s->cdec);
+  const double2 p2 = sincos_cycles(th[6] / PI);
+  s->s2psi = p2.x;
+  s->c2psi = p2.y;
+  const double2 ra = sincos_cycles((th[7] - M.gmst) / TWO_PI);
+  s->sra = ra.x;
+  s->cra = ra.y;
+  const double2 de = sincos_cycles(th[8] / TWO_PI);
+  s->sdec = de.x;
+  s->cdec = de.y;
   s->tc = th[9];
   s->phic = th[10];
 }

@@ -27,9 +27,11 @@ struct Tables {
   const double* fm53;   // [n_bins] f_k^(-5/3)
   const double2* dw;    // [n_det][n_bins] 4 df f_k^(-7/6) d_k / S_k
   const double* hpre;   // [n_det][n_bins] prefix sums of 4 df f^(-7/3) / S
+  const float2* dw32;   // mixed form: dw * dw_scale in float (else null)
 };
 
-// Relative-binning tables (one set per detector, nb coarse bins).
+// Relative-binning tables: nb coarse bins whose nb+1 edges sit on grid
+// frequencies; summary sums of the data against the fiducial waveform h0.
 struct RBTables {
   int nb;
   const int* edge;        // [nb+1] fine-grid index of each edge
@@ -37,20 +39,25 @@ struct RBTables {
   const double* fe13;     // [nb+1] fe^(1/3)
   const double* lnfe3;    // [nb+1] ln(fe) / 3
   const double* fem53;    // [nb+1] fe^(-5/3)
-  const double* psi0;     // [nb+1] fiducial phase at the edges (cycles, without detector delay)
-  const double2* h0inv;   // [n_det][nb+1] 1 / (A0 K0_det), complex
-  const double* dt0;      // [n_det] fiducial delays
-  const double* fm;       // [nb] bin centres
-  const double2* A0;      // [n_det][nb]
-  const double2* A1;      // [n_det][nb]
-  const double* B0;       // [n_det][nb]
-  const double* B1;       // [n_det][nb]
-  // per fine bin, cumulative sums inside its coarse bin (for the bin that
-  // straddles f_ISCO): [n_det][n_bins]
+  const double* phi0;     // [n_det][nb+1] fiducial phase at the edges, detector delay included (cycles)
+  const double2* g0;      // [n_det] 1 / (A0 K0_det) of the fiducial
+  const double* fm;       // [nb] bin centres (fe_b + fe_{b+1}) / 2
+  const double* inv_w;    // [nb] 1 / (fe_{b+1} - fe_b)
+  const double2* A0;      // [n_det][nb] sum 4 df conj(d) h0 / S
+  const double2* A1;      // [n_det][nb] sum 4 df conj(d) h0 / S (f - fm)
+  const double* B0;       // [n_det][nb] sum 4 df |h0|^2 / S
+  const double* B1;       // [n_det][nb] sum 4 df |h0|^2 / S (f - fm)
+  // the same sums accumulated from each bin's first fine bin up to fine bin
+  // k (inclusive), for the bin that straddles f_ISCO: [n_det][n_bins]
   const double2* cA0;
   const double2* cA1;
   const double* cB0;
   const double* cB1;
+  // mixed form: the full-bin sums in float (else null)
+  const float2* A0f;
+  const float2* A1f;
+  const float* B0f;
+  const float* B1f;
 };
 
 // Device buffers of one run.
@@ -80,7 +87,13 @@ struct RunDev {
   int* dnlive;                // [cap]
 };
 
-enum LikeKind { LK_FULL = 0, LK_RB = 1, LK_GAUSS = 2 };
+// Likelihood kernels: full grid and relative binning, each in double
+// precision or in the mixed form (float sincos, products and bin sums;
+// double phase), and the Gaussian test likelihood.
+enum LikeKind { LK_FULL = 0, LK_RB = 1, LK_GAUSS = 2, LK_FULL32 = 3, LK_RB32 = 4 };
+__host__ __device__ constexpr bool lk_full(int lk) { return lk == LK_FULL || lk == LK_FULL32; }
+__host__ __device__ constexpr bool lk_rb(int lk) { return lk == LK_RB || lk == LK_RB32; }
+__host__ __device__ constexpr bool lk_mixed(int lk) { return lk == LK_FULL32 || lk == LK_RB32; }
 
 // Launch configuration chosen at init.
 struct LaunchCfg {
@@ -108,7 +121,21 @@ hipError_t launch_waveform(const ModelDev& M, const ModelDev* Md, const double* 
 hipError_t launch_final(const RunDev& R, int n_sim, double* out, hipStream_t st);
 hipError_t launch_samples(const ModelDev* Md, const RunDev& R, long long total, double logZ, double* theta,
                           double* logl, double* logw, hipStream_t st);
-hipError_t configure_slice(const ModelDev& M, LaunchCfg* C);
+// Relative-binning set-up: edges (edge_out receives a host copy for
+// validation), fiducial phases and the summary sums.  w is the scratch array
+// of per-bin weights 4 df f^(-7/3) / S written by launch_build_tables.
+struct RBBuffers {
+  int* edge; double *fe, *fe13, *lnfe3, *fem53, *phi0, *fm, *inv_w, *B0, *B1, *cB0, *cB1;
+  double2 *g0, *A0, *A1, *cA0, *cA1;
+  float2 *A0f, *A1f; float *B0f, *B1f;   // mixed form only
+};
+// Mixed form: float copies of the data table (scaled) and of the bin sums.
+hipError_t launch_to_float(const double2* src, float2* dst, size_t n, double scale, hipStream_t st);
+hipError_t launch_to_float(const double* src, float* dst, size_t n, double scale, hipStream_t st);
+hipError_t launch_build_rb_edges(const ModelDev* Md, int nb, const RBBuffers& B, hipStream_t st);
+hipError_t launch_build_rb_sums(const ModelDev& M, const ModelDev* Md, const Tables& T, const double* hw,
+                                const double* theta_fid_dev, int nb, const RBBuffers& B, hipStream_t st);
+hipError_t configure_slice(const ModelDev& M, int rb_nb, LaunchCfg* C);
 int likelihood_kind(const ModelDev& M);
 
 }  // namespace ns

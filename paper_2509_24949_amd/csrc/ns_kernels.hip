@@ -19,6 +19,9 @@
 //                 with all 64 lanes over the frequency bins.
 #include <float.h>
 #include <math.h>
+#include <stdlib.h>
+
+#include <type_traits>
 
 #include "ns_internal.h"
 
@@ -110,15 +113,24 @@ struct TabView {
   const double* lnf3;
   const double* fm53;
   const double2* dw;
+  const float2* dw32;
   int dstride;
+  double inv_scale;     // 1 / dw_scale of the float table
 };
 
-template <int NDET>
+// LDS bytes of the staged full-grid tables.
+__host__ __device__ inline size_t staged_table_bytes(int k_lim, int n_det, bool mixed) {
+  return (size_t)k_lim * (4 * sizeof(double) + n_det * (mixed ? sizeof(float2) : sizeof(double2)));
+}
+
+template <int NDET, bool MX>
 __device__ inline TabView stage_tables(const ModelDev& M, const Tables& T, bool use_lds, double* lds, int tid,
                                        int nt) {
   TabView V;
   if (!use_lds) {
-    V.f = T.f; V.f13 = T.f13; V.lnf3 = T.lnf3; V.fm53 = T.fm53; V.dw = T.dw; V.dstride = M.n_bins;
+    V.f = T.f; V.f13 = T.f13; V.lnf3 = T.lnf3; V.fm53 = T.fm53; V.dw = T.dw; V.dw32 = T.dw32;
+    V.dstride = M.n_bins;
+    V.inv_scale = MX ? 1.0 / M.dw_scale : 1.0;
     return V;
   }
   const int K = M.k_lim;
@@ -127,17 +139,39 @@ __device__ inline TabView stage_tables(const ModelDev& M, const Tables& T, bool 
   double* lnf3 = f13 + K;
   double* fm53 = lnf3 + K;
   double2* dw = reinterpret_cast<double2*>(fm53 + K);
+  float2* dw32 = reinterpret_cast<float2*>(fm53 + K);
   for (int k = tid; k < K; k += nt) {
     f[k] = T.f[k];
     f13[k] = T.f13[k];
     lnf3[k] = T.lnf3[k];
     fm53[k] = T.fm53[k];
 #pragma unroll
-    for (int d = 0; d < NDET; ++d) dw[d * K + k] = T.dw[(size_t)d * M.n_bins + k];
+    for (int d = 0; d < NDET; ++d) {
+      if (MX) dw32[d * K + k] = T.dw32[(size_t)d * M.n_bins + k];
+      else dw[d * K + k] = T.dw[(size_t)d * M.n_bins + k];
+    }
   }
-  V.f = f; V.f13 = f13; V.lnf3 = lnf3; V.fm53 = fm53; V.dw = dw; V.dstride = K;
+  V.f = f; V.f13 = f13; V.lnf3 = lnf3; V.fm53 = fm53; V.dw = dw; V.dw32 = dw32; V.dstride = K;
+  V.inv_scale = MX ? 1.0 / M.dw_scale : 1.0;
   return V;
 }
+
+// sin and cos of 2 pi r for |r| <= 1/2 cycles, single precision, on the
+// transcendental unit (whose sine and cosine take their argument in cycles).
+__device__ inline float2 sincos_cycles_f32(float r) {
+  return make_float2(__builtin_amdgcn_sinf(r), __builtin_amdgcn_cosf(r));
+}
+
+// Compensated (Kahan) accumulation in single precision.
+struct KahanF {
+  float s = 0.0f, c = 0.0f;
+  __device__ inline void add(float x) {
+    const float y = x - c;
+    const float t = s + y;
+    c = (t - s) - y;
+    s = t;
+  }
+};
 
 // The coefficients of the probe held by lane `src`, broadcast to the wave.
 template <int NDET>
@@ -173,27 +207,50 @@ __device__ inline Probe probe_from_lane(const Probe& p, int src) {
 // Per detector the bin sums a_d = sum (Dr c - Di s) and b_d = sum (Dr s + Di c)
 // are folded with A K_d = (kre, kim) as kre a_d + kim b_d before returning, so a
 // probe needs a single reduction.
-template <int NDET>
+template <int NDET, bool MX>
 __device__ inline double fullgrid_partial(const Probe& p, const TabView& V, int lane, int nl) {
-  double a[NDET], b[NDET];
+  if constexpr (MX) {
+    // mixed form: the phase in double, reduced to [-1/2, 1/2] cycles, then
+    // float sincos and compensated float sums of the scaled data
+    KahanF a[NDET], b[NDET];
+    for (int k = lane; k < p.k_act; k += nl) {
+      const double f = V.f[k];
+      const double psi = phase_cycles(p, f, V.f13[k], V.lnf3[k], V.fm53[k]);
 #pragma unroll
-  for (int d = 0; d < NDET; ++d) { a[d] = 0.0; b[d] = 0.0; }
-  for (int k = lane; k < p.k_act; k += nl) {
-    const double f = V.f[k];
-    const double psi = phase_cycles(p, f, V.f13[k], V.lnf3[k], V.fm53[k]);
-#pragma unroll
-    for (int d = 0; d < NDET; ++d) {
-      double sn, cs;
-      sincos_cycles(fma(f, p.dt[d], psi), &sn, &cs);
-      const double2 D = V.dw[d * V.dstride + k];
-      a[d] = fma(D.x, cs, fma(-D.y, sn, a[d]));
-      b[d] = fma(D.x, sn, fma(D.y, cs, b[d]));
+      for (int d = 0; d < NDET; ++d) {
+        const double ph = fma(f, p.dt[d], psi);
+        const float2 sc = sincos_cycles_f32((float)(ph - rint(ph)));
+        const float2 D = V.dw32[d * V.dstride + k];
+        a[d].add(fmaf(D.x, sc.y, -D.y * sc.x));
+        b[d].add(fmaf(D.x, sc.x, D.y * sc.y));
+      }
     }
-  }
-  double part = 0.0;
+    double part = 0.0;
 #pragma unroll
-  for (int d = 0; d < NDET; ++d) part = fma(p.kre[d], a[d], fma(p.kim[d], b[d], part));
-  return part;
+    for (int d = 0; d < NDET; ++d)
+      part = fma(p.kre[d], (double)a[d].s, fma(p.kim[d], (double)b[d].s, part));
+    return part * V.inv_scale;
+  } else {
+    double a[NDET], b[NDET];
+#pragma unroll
+    for (int d = 0; d < NDET; ++d) { a[d] = 0.0; b[d] = 0.0; }
+    for (int k = lane; k < p.k_act; k += nl) {
+      const double f = V.f[k];
+      const double psi = phase_cycles(p, f, V.f13[k], V.lnf3[k], V.fm53[k]);
+#pragma unroll
+      for (int d = 0; d < NDET; ++d) {
+        const double2 sc_ = sincos_cycles(fma(f, p.dt[d], psi));
+        const double sn = sc_.x, cs = sc_.y;
+        const double2 D = V.dw[d * V.dstride + k];
+        a[d] = fma(D.x, cs, fma(-D.y, sn, a[d]));
+        b[d] = fma(D.x, sn, fma(D.y, cs, b[d]));
+      }
+    }
+    double part = 0.0;
+#pragma unroll
+    for (int d = 0; d < NDET; ++d) part = fma(p.kre[d], a[d], fma(p.kim[d], b[d], part));
+    return part;
+  }
 }
 
 __device__ inline double gauss_lambda(const ModelDev& M, const double* u) {
@@ -257,6 +314,228 @@ __global__ void k_init_live(int n, int d, uint64_t k0, uint64_t k1, double* u) {
   }
 }
 
+// ------------------------------------------------------- relative binning
+// Grid frequency f_lo + k df as a product followed by a sum (no fused
+// multiply-add), the rounding the edge snapping is defined with.
+__device__ inline double grid_freq(double f_lo, double df, int k) {
+#pragma clang fp contract(off)
+  return f_lo + (double)k * df;
+}
+
+// Edges e_b = f_lo (f_hi / f_lo)^(b / nb), snapped to the nearest grid
+// frequency, the first and last pinned to the ends of the grid.
+__global__ void k_rb_edges(const ModelDev* __restrict__ Mp, int nb, int* edge, double* fe, double* fe13,
+                           double* lnfe3, double* fem53) {
+  const ModelDev& M = *Mp;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e > nb) return;
+  const double f_hi = grid_freq(M.f_lo, M.df, M.n_bins - 1);
+  const double raw = M.f_lo * pow(f_hi / M.f_lo, (double)e / nb);
+  int k = (int)floor((raw - M.f_lo) / M.df + 0.5);
+  k = k < 0 ? 0 : (k > M.n_bins - 1 ? M.n_bins - 1 : k);
+  if (e == 0) k = 0;
+  if (e == nb) k = M.n_bins - 1;
+  const double f = grid_freq(M.f_lo, M.df, k);
+  const double lf = log(f);
+  edge[e] = k;
+  fe[e] = f;
+  fe13[e] = cbrt(f);
+  lnfe3[e] = lf / 3.0;
+  fem53[e] = exp(-5.0 / 3.0 * lf);
+}
+
+// Fiducial phases at the edges, bin centres and widths, 1 / (A0 K0_det).
+__global__ void k_rb_fiducial(const ModelDev* __restrict__ Mp, const double* theta, int nb, const double* fe,
+                              const double* fe13, const double* lnfe3, const double* fem53, double* phi0,
+                              double2* g0, double* fm, double* inv_w) {
+  const ModelDev& M = *Mp;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e > nb) return;
+  Phys s;
+  phys_from_theta(M, theta, &s);
+  Probe P;
+  probe_from_phys(M, s, nullptr, &P);
+  const double psi = phase_cycles(P, fe[e], fe13[e], lnfe3[e], fem53[e]);
+  for (int d = 0; d < M.n_det; ++d) phi0[d * (nb + 1) + e] = fma(fe[e], P.dt[d], psi);
+  if (e < nb) {
+    fm[e] = 0.5 * (fe[e] + fe[e + 1]);
+    inv_w[e] = 1.0 / (fe[e + 1] - fe[e]);
+  }
+  if (e == 0) {
+    for (int d = 0; d < M.n_det; ++d) {
+      const double den = P.kre[d] * P.kre[d] + P.kim[d] * P.kim[d];
+      g0[d] = make_double2(P.kre[d] / den, -P.kim[d] / den);
+    }
+  }
+}
+
+// Summary sums, one thread per (detector, coarse bin), accumulated over the
+// bin's fine bins in frequency order; the running sums are kept per fine bin.
+__global__ void k_rb_sums(const ModelDev* __restrict__ Mp, Tables T, const double* hw, const double* theta, int nb,
+                          const int* edge, const double* fm, double2* A0, double2* A1, double* B0, double* B1,
+                          double2* cA0, double2* cA1, double* cB0, double* cB1) {
+  const ModelDev& M = *Mp;
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  const int d = blockIdx.y;
+  if (b >= nb) return;
+  Phys s;
+  phys_from_theta(M, theta, &s);
+  Probe P;
+  probe_from_phys(M, s, nullptr, &P);
+  const double kr = P.kre[d], ki = P.kim[d];
+  const double k2 = kr * kr + ki * ki;
+  const int first = edge[b], last = (b < nb - 1) ? edge[b + 1] - 1 : edge[nb];
+  const double fmb = fm[b];
+  double s0r = 0, s0i = 0, s1r = 0, s1i = 0, t0 = 0, t1 = 0;
+  for (int k = first; k <= last; ++k) {
+    const size_t o = (size_t)d * M.n_bins + k;
+    const double f = T.f[k];
+    const double ph = fma(f, P.dt[d], phase_cycles(P, f, T.f13[k], T.lnf3[k], T.fm53[k]));
+    const double2 sc_ = sincos_cycles(ph);
+    const double sn = sc_.x, cs = sc_.y;
+    // A0 K0 e^{-i Phi0}: the fiducial strain without f^(-7/6) (carried by dw)
+    const double er = kr * cs + ki * sn, ei = ki * cs - kr * sn;
+    const double2 D = T.dw[o];
+    const double ar = D.x * er + D.y * ei, ai = D.x * ei - D.y * er;   // conj(dw) * K0 e^{-i Phi0}
+    const double bk = k2 * hw[o];
+    const double x = f - fmb;
+    s0r += ar; s0i += ai;
+    s1r += ar * x; s1i += ai * x;
+    t0 += bk; t1 += bk * x;
+    cA0[o] = make_double2(s0r, s0i);
+    cA1[o] = make_double2(s1r, s1i);
+    cB0[o] = t0;
+    cB1[o] = t1;
+  }
+  const size_t q = (size_t)d * nb + b;
+  A0[q] = make_double2(s0r, s0i);
+  A1[q] = make_double2(s1r, s1i);
+  B0[q] = t0;
+  B1[q] = t1;
+}
+
+// This thread's share of lambda for one probe under relative binning.  Phase
+// 1: the ratio r_d(e) = h(e) / h0(e) = A K_d / (A0 K0_d) e^{-i (Phi_d - Phi0_d)}
+// at the edges e = tid, tid + nt, ... into LDS.  Phase 2: per coarse bin
+// b = tid, ...: r0 = (r_b + r_{b+1}) / 2, r1 = (r_{b+1} - r_b) / (e_{b+1} - e_b),
+// Re(A0 r0 + A1 r1) - 1/2 [B0 |r0|^2 + 2 B1 Re(conj(r0) r1)]; bins whose first
+// fine bin is above f_ISCO are skipped and the straddling bin uses the sums
+// up to its last active fine bin.  Contains one workgroup barrier.
+template <int NDET, bool MX>
+__device__ inline double rb_partial(const Probe& p, const RBTables& B, int n_bins, void* lds, int tid, int nt) {
+  using CT = typename std::conditional<MX, float2, double2>::type;
+  CT* sr = reinterpret_cast<CT*>(lds);
+  const int nb = B.nb;
+  for (int e = tid; e <= nb; e += nt) {
+    const double f = B.fe[e];
+    const double psi = phase_cycles(p, f, B.fe13[e], B.lnfe3[e], B.fem53[e]);
+#pragma unroll
+    for (int d = 0; d < NDET; ++d) {
+      const double dph = fma(f, p.dt[d], psi) - B.phi0[d * (nb + 1) + e];
+      const double2 g = B.g0[d];
+      const double gr = p.kre[d] * g.x - p.kim[d] * g.y, gi = p.kre[d] * g.y + p.kim[d] * g.x;
+      if constexpr (MX) {
+        const float2 sc = sincos_cycles_f32((float)(dph - rint(dph)));
+        const float fr = (float)gr, fi = (float)gi;
+        sr[d * (nb + 1) + e] = make_float2(fmaf(fr, sc.y, fi * sc.x), fmaf(fi, sc.y, -fr * sc.x));
+      } else {
+        const double2 sc = sincos_cycles(dph);
+        sr[d * (nb + 1) + e] = make_double2(gr * sc.y + gi * sc.x, gi * sc.y - gr * sc.x);
+      }
+    }
+  }
+  __syncthreads();
+  double part = 0.0;
+  for (int b = tid; b < nb; b += nt) {
+    const int first = B.edge[b];
+    if (first >= p.k_act) continue;
+    const int last = (b < nb - 1) ? B.edge[b + 1] - 1 : B.edge[nb];
+    const bool full = last < p.k_act;
+#pragma unroll
+    for (int d = 0; d < NDET; ++d) {
+      if constexpr (MX) {
+        float2 a0, a1;
+        float b0, b1;
+        if (full) {
+          const size_t q = (size_t)d * nb + b;
+          a0 = B.A0f[q]; a1 = B.A1f[q]; b0 = B.B0f[q]; b1 = B.B1f[q];
+        } else {
+          const size_t q = (size_t)d * n_bins + p.k_act - 1;
+          a0 = make_float2((float)B.cA0[q].x, (float)B.cA0[q].y);
+          a1 = make_float2((float)B.cA1[q].x, (float)B.cA1[q].y);
+          b0 = (float)B.cB0[q]; b1 = (float)B.cB1[q];
+        }
+        const float iw = (float)B.inv_w[b];
+        const float2 ra = sr[d * (nb + 1) + b], rb = sr[d * (nb + 1) + b + 1];
+        const float r0r = 0.5f * (ra.x + rb.x), r0i = 0.5f * (ra.y + rb.y);
+        const float r1r = (rb.x - ra.x) * iw, r1i = (rb.y - ra.y) * iw;
+        const float dh = (a0.x * r0r - a0.y * r0i) + (a1.x * r1r - a1.y * r1i);
+        const float hh = b0 * (r0r * r0r + r0i * r0i) + 2.0f * b1 * (r0r * r1r + r0i * r1i);
+        part += (double)(dh - 0.5f * hh);
+      } else {
+        double2 a0, a1;
+        double b0, b1;
+        if (full) {
+          const size_t q = (size_t)d * nb + b;
+          a0 = B.A0[q]; a1 = B.A1[q]; b0 = B.B0[q]; b1 = B.B1[q];
+        } else {
+          const size_t q = (size_t)d * n_bins + p.k_act - 1;
+          a0 = B.cA0[q]; a1 = B.cA1[q]; b0 = B.cB0[q]; b1 = B.cB1[q];
+        }
+        const double iw = B.inv_w[b];
+        const double2 ra = sr[d * (nb + 1) + b], rb = sr[d * (nb + 1) + b + 1];
+        const double r0r = 0.5 * (ra.x + rb.x), r0i = 0.5 * (ra.y + rb.y);
+        const double r1r = (rb.x - ra.x) * iw, r1i = (rb.y - ra.y) * iw;
+        const double dh = (a0.x * r0r - a0.y * r0i) + (a1.x * r1r - a1.y * r1i);
+        const double hh = b0 * (r0r * r0r + r0i * r0i) + 2.0 * b1 * (r0r * r1r + r0i * r1i);
+        part += dh - 0.5 * hh;
+      }
+    }
+  }
+  return part;
+}
+
+// Batched relative-binning likelihood: one wavefront per workgroup, 64
+// probes set up per pass (one per lane), evaluated one after another.
+template <int NDET, bool MX>
+__global__ __launch_bounds__(64) void k_loglike_rb(const ModelDev* __restrict__ Mp, RBTables RB,
+                                                   const double* __restrict__ u, long n, double* __restrict__ out) {
+  extern __shared__ double smem[];
+  void* sr = smem;
+  const ModelDev& M = *Mp;
+  const int lane = threadIdx.x;
+  const int d = M.n_dim;
+  for (long base = (long)blockIdx.x * 64; base < n; base += (long)gridDim.x * 64) {
+    const long i = base + lane;
+    const long src = i < n ? i : base;
+    double y[MAX_DIM];
+#pragma unroll
+    for (int q = 0; q < MAX_DIM; ++q) y[q] = (q < d) ? u[src * d + q] : 0.0;
+    Probe pr;
+    make_probe(M, nullptr, y, &pr);
+    double mine = 0.0;
+    const int cnt = (n - base) < 64 ? (int)(n - base) : 64;
+    for (int p = 0; p < cnt; ++p) {
+      const Probe pb = probe_from_lane<NDET>(pr, p);
+      const double tot = wave_sum(rb_partial<NDET, MX>(pb, RB, M.n_bins, sr, lane, 64));
+      if (lane == p) mine = tot;
+      __syncthreads();   // the ratios in LDS are rewritten by the next probe
+    }
+    if (i < n) out[i] = mine;
+  }
+}
+
+// Float copies for the mixed form.
+__global__ void k_to_float2(const double2* src, float2* dst, size_t n, double scale) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = make_float2((float)(src[i].x * scale), (float)(src[i].y * scale));
+}
+
+__global__ void k_to_float1(const double* src, float* dst, size_t n, double scale) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = (float)(src[i] * scale);
+}
+
 // ---------------------------------------------------------- batched lambda
 // Each wavefront takes 64 consecutive probes: lane l sets up probe base + l,
 // then the wave evaluates the probes one at a time over the bins.
@@ -267,8 +546,8 @@ __global__ __launch_bounds__(256) void k_loglike(const ModelDev* __restrict__ Mp
   const ModelDev& M = *Mp;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   TabView V{};
-  if (LK == LK_FULL) {
-    V = stage_tables<NDET>(M, T, LDS, smem, tid, 256);
+  if (lk_full(LK)) {
+    V = stage_tables<NDET, lk_mixed(LK)>(M, T, LDS, smem, tid, 256);
     if (LDS) __syncthreads();
   }
   const int d = M.n_dim;
@@ -288,7 +567,7 @@ __global__ __launch_bounds__(256) void k_loglike(const ModelDev* __restrict__ Mp
       const int cnt = (n - base) < 64 ? (int)(n - base) : 64;
       for (int p = 0; p < cnt; ++p) {
         const Probe pb = probe_from_lane<NDET>(pr, p);
-        const double tot = wave_sum(fullgrid_partial<NDET>(pb, V, lane, 64));
+        const double tot = wave_sum(fullgrid_partial<NDET, lk_mixed(LK)>(pb, V, lane, 64));
         if (lane == p) mine = tot - 0.5 * pb.hh;
       }
     }
@@ -482,16 +761,42 @@ __global__ __launch_bounds__(1024) void k_prep(RunDev R) {
 }
 
 // ------------------------------------------------------------ slice chains
+// Candidate batches of the chain kernel: NT candidates per batch, one per
+// thread.  Slots [0, SO) hold left step-out points, [SO, 2 SO) right ones,
+// the rest the first SC shrink candidates of each bracket the step-out can
+// end in with at most H-1 steps per side.
+template <int NT> struct SliceBatch {
+  static constexpr int SO = NT / 8;
+  static constexpr int H = NT >= 256 ? 6 : 4;
+  static constexpr int SC = NT >= 256 ? 5 : (NT >= 128 ? 6 : 3);
+  static_assert(2 * SO + H * H * SC <= NT, "batch layout");
+};
+
+// Dynamic LDS of the chain kernel (doubles), in order: Cholesky factor,
+// reduction slots, directions and uniforms of a chunk of steps, the batch
+// (probe coefficients, positions, Gaussian values, in-cube masks), the chain
+// position, then the likelihood tables (full grid, when they fit) or the
+// edge ratios (relative binning).
+constexpr int SL_CHUNK = 16;                          // steps drawn per chunk
+constexpr int SL_PSTRIDE = (int)((sizeof(Probe) + 15) / 16) * 2;   // doubles per stored probe
+constexpr int SL_NU = 10;                             // uniforms per step: width, split, 8 shrink
+__host__ __device__ constexpr size_t slice_fixed_doubles(int nt) {
+  return MAX_DIM * MAX_DIM + 16 + SL_CHUNK * MAX_DIM + SL_CHUNK * SL_NU + (size_t)nt * SL_PSTRIDE + nt + nt + 4 + 16;
+}
+
 // One workgroup of NT threads runs chain j = blockIdx.x for all n_steps
-// steps.  State, direction and bracket are uniform across the workgroup and
-// every wavefront computes the same candidate batches, so probe coefficients
-// are broadcast within a wave with readlane.  A probe's bins are spread over
-// all NT threads; one value is reduced per probe.
+// steps.  The random numbers and tuned directions of a chunk of steps are
+// drawn up front, lane-parallel.  Each step then sets up one batch of NT
+// candidates in parallel (one per thread, each fixed in advance: the
+// step-out points and, under the hypothesis that earlier candidates are
+// rejected, the shrink sequence of every likely bracket); all threads then
+// walk the batch in the sequential order of the algorithm and split every
+// probe's frequency bins.  Rarer outcomes fall back to further batches.
 template <int NDET, int NT, int LK, bool LDS>
 __global__ __launch_bounds__(NT) void k_slice(const ModelDev* __restrict__ Mp, Tables T, RBTables RB, RunDev R) {
   constexpr int NW = NT / 64;
-  constexpr int SOB = 32;          // step-out candidates per side and batch
-  constexpr int SHB = 8;           // shrink candidates per batch
+  constexpr int FB = 32;             // candidates per fallback batch
+  using BL = SliceBatch<NT>;
   extern __shared__ double smem[];
   const ModelDev& M = *Mp;
   DevState* S = R.state;
@@ -501,188 +806,274 @@ __global__ __launch_bounds__(NT) void k_slice(const ModelDev* __restrict__ Mp, T
   const int d = R.d;
   const uint64_t t = (uint64_t)S->iter;
   const double lstar = S->lstar;
-  double* sL = smem;                         // [MAX_DIM * MAX_DIM]
-  double* sred = sL + MAX_DIM * MAX_DIM;     // [2][NW]
-  double* stab = sred + 2 * 8;
+  double* sL = smem;
+  double* sred = sL + MAX_DIM * MAX_DIM;
+  double* sDir = sred + 16;
+  double* sU = sDir + SL_CHUNK * MAX_DIM;
+  double* sP = sU + SL_CHUNK * SL_NU;
+  double* sT = sP + NT * SL_PSTRIDE;
+  double* sG = sT + NT;
+  unsigned long long* sMask = reinterpret_cast<unsigned long long*>(sG + NT);
+  double* sX = sG + NT + 4;          // chain position
+  double* stab = sX + 16;
   for (int i = tid; i < d * d; i += NT) sL[i] = R.chol[i];
   TabView V{};
-  if (LK == LK_FULL) V = stage_tables<NDET>(M, T, LDS, stab, tid, NT);
-  __syncthreads();
+  if (lk_full(LK)) V = stage_tables<NDET, lk_mixed(LK)>(M, T, LDS, stab, tid, NT);
 
   int buf = 0;
   int nprobe = 0;
   long long nbins = 0;
-  // this lane's candidate of the current batch
-  Probe pr;
-  double glam = 0.0;            // Gaussian test likelihood of the candidate
-  bool cin = false;             // candidate inside the unit cube
+  const int start = R.start[j];
+  for (int i = tid; i < d; i += NT) sX[i] = R.u[(size_t)start * d + i];
+  double lx = R.lam[start];
+  const int nbd = (d + 3) >> 2;      // DIR blocks per step
+  const double w = R.width;
 
-  auto setup = [&](double tt, const double* x, const double* dir) {
+  // this thread's candidate of a batch, at position tt along dir (valid:
+  // the slot is used; unused slots are marked outside the cube)
+  auto setup = [&](bool valid, double tt, const double* dir) {
     double y[MAX_DIM];
-    cin = true;
+    bool cin = valid;
 #pragma unroll
     for (int i = 0; i < MAX_DIM; ++i) {
-      y[i] = (i < d) ? fma(tt, dir[i], x[i]) : 0.0;
+      y[i] = (i < d) ? fma(tt, dir[i], sX[i]) : 0.0;
       if (i < d && !(y[i] >= 0.0 && y[i] <= 1.0)) cin = false;
     }
     if (!cin) {
 #pragma unroll
       for (int i = 0; i < MAX_DIM; ++i) y[i] = 0.5;   // a harmless point; never evaluated
     }
-    if (LK == LK_GAUSS) glam = gauss_lambda(M, y);
-    else make_probe(M, T.hpre, y, &pr);
+    if (LK == LK_GAUSS) {
+      sG[tid] = gauss_lambda(M, y);
+    } else {
+      Probe pr;
+      make_probe(M, lk_full(LK) ? T.hpre : nullptr, y, &pr);
+      *reinterpret_cast<Probe*>(sP + tid * SL_PSTRIDE) = pr;
+    }
+    sT[tid] = tt;
+    const unsigned long long m = __ballot(cin);
+    if (lane == 0) sMask[wv] = m;
   };
-  // lambda of the candidate held by lane src of every wavefront
-  auto eval = [&](int src) -> double {
+  auto inside = [&](int q) -> bool { return (sMask[q >> 6] >> (q & 63)) & 1ull; };
+  // lambda of batch candidate q (all threads; contains workgroup barriers)
+  auto eval = [&](int q) -> double {
     ++nprobe;
-    if (LK == LK_GAUSS) return lane_d(glam, src);
-    const Probe pb = probe_from_lane<NDET>(pr, src);
-    nbins += pb.k_act;
-    double tot = wave_sum(fullgrid_partial<NDET>(pb, V, tid, NT));
+    if (LK == LK_GAUSS) return sG[q];
+    const Probe pb = *reinterpret_cast<const Probe*>(sP + q * SL_PSTRIDE);
+    nbins += lk_full(LK) ? pb.k_act : RB.nb + 1;
+    double tot;
+    if (lk_rb(LK)) tot = wave_sum(rb_partial<NDET, lk_mixed(LK)>(pb, RB, M.n_bins, stab, tid, NT));
+    else tot = wave_sum(fullgrid_partial<NDET, lk_mixed(LK)>(pb, V, tid, NT));
     if constexpr (NW > 1) {
       double* rb = sred + buf * NW;
       if (lane == 0) rb[wv] = tot;
       __syncthreads();
       tot = 0.0;
 #pragma unroll
-      for (int w = 0; w < NW; ++w) tot += rb[w];
+      for (int w2 = 0; w2 < NW; ++w2) tot += rb[w2];
       buf ^= 1;
+    } else if (lk_rb(LK)) {
+      __syncthreads();   // the edge ratios in LDS are rewritten by the next probe
     }
-    return tot - 0.5 * pb.hh;
+    return lk_rb(LK) ? tot : tot - 0.5 * pb.hh;
   };
 
-  const int start = R.start[j];
-  double x[MAX_DIM];
-#pragma unroll
-  for (int i = 0; i < MAX_DIM; ++i) x[i] = (i < d) ? R.u[(size_t)start * d + i] : 0.0;
-  double lx = R.lam[start];
-  const int nbd = (d + 3) >> 2;      // DIR blocks
-  const double w = R.width;
-
-  for (int s = 0; s < R.m; ++s) {
-    // lanes 0..nbd-1: direction blocks (two Box-Muller pairs each); lane nbd:
-    // the width block; lanes nbd+1, nbd+2: the first eight shrink uniforms
-    double r0 = 0, r1 = 0, r2 = 0, r3 = 0;
-    if (lane < nbd + 3) {
+  for (int s0 = 0; s0 < R.m; s0 += SL_CHUNK) {
+    const int cs = (R.m - s0) < SL_CHUNK ? (R.m - s0) : SL_CHUNK;
+    // ---- draw the chunk: per step nbd direction blocks (two Box-Muller
+    // pairs each), the width block and two shrink blocks
+    __syncthreads();
+    const int per = nbd + 3;
+    for (int bI = tid; bI < cs * per; bI += NT) {
+      const int sl = bI / per, r = bI - sl * per;
+      const uint64_t s = (uint64_t)(s0 + sl);
       uint64_t pw;
-      if (lane < nbd) pw = purpose_word(P_DIR, (uint64_t)lane);
-      else if (lane == nbd) pw = purpose_word(P_WIDTH, 0);
-      else pw = purpose_word(P_SHRINK, (uint64_t)(lane - nbd - 1));
-      u64x4 b = philox(t, (uint64_t)j, (uint64_t)s, pw, R.key0, R.key1);
-      r0 = unif53(b.x[0]); r1 = unif53(b.x[1]); r2 = unif53(b.x[2]); r3 = unif53(b.x[3]);
-      if (lane < nbd) {
-        double sa, ca, sb, cb;
-        const double ra = sqrt(-2.0 * log(1.0 - r0));
-        sincos_cycles(r1, &sa, &ca);
-        const double rb = sqrt(-2.0 * log(1.0 - r2));
-        sincos_cycles(r3, &sb, &cb);
-        r0 = ra * ca; r1 = ra * sa; r2 = rb * cb; r3 = rb * sb;
+      if (r < nbd) pw = purpose_word(P_DIR, (uint64_t)r);
+      else if (r == nbd) pw = purpose_word(P_WIDTH, 0);
+      else pw = purpose_word(P_SHRINK, (uint64_t)(r - nbd - 1));
+      const u64x4 b = philox(t, (uint64_t)j, s, pw, R.key0, R.key1);
+      const double u0 = unif53(b.x[0]), u1 = unif53(b.x[1]), u2 = unif53(b.x[2]), u3 = unif53(b.x[3]);
+      if (r < nbd) {
+        const double ra = sqrt(-2.0 * log(1.0 - u0));
+        const double2 ea = sincos_cycles(u1);
+        const double rb = sqrt(-2.0 * log(1.0 - u2));
+        const double2 eb = sincos_cycles(u3);
+        double* zr = sDir + sl * MAX_DIM + 4 * r;
+        if (4 * r + 0 < d) zr[0] = ra * ea.y;
+        if (4 * r + 1 < d) zr[1] = ra * ea.x;
+        if (4 * r + 2 < d) zr[2] = rb * eb.y;
+        if (4 * r + 3 < d) zr[3] = rb * eb.x;
+      } else if (r == nbd) {
+        sU[sl * SL_NU + 0] = u0;
+        sU[sl * SL_NU + 1] = u1;
+      } else {
+        double* ur = sU + sl * SL_NU + 2 + 4 * (r - nbd - 1);
+        ur[0] = u0; ur[1] = u1; ur[2] = u2; ur[3] = u3;
       }
     }
-    double z[MAX_DIM];
+    __syncthreads();
+    // directions L z / |z|, one thread per step (the thread owns the row)
+    for (int sl = tid; sl < cs; sl += NT) {
+      double z[MAX_DIM];
 #pragma unroll
-    for (int i = 0; i < MAX_DIM; ++i) {
-      const double v = ((i & 3) == 0) ? r0 : ((i & 3) == 1) ? r1 : ((i & 3) == 2) ? r2 : r3;
-      z[i] = (i < d) ? lane_d(v, i >> 2) : 0.0;
-    }
-    const double uw = lane_d(r0, nbd), uj = lane_d(r1, nbd);
-    // direction L z / |z|
-    double nrm = 0.0;
+      for (int i = 0; i < MAX_DIM; ++i) z[i] = (i < d) ? sDir[sl * MAX_DIM + i] : 0.0;
+      double nrm = 0.0;
 #pragma unroll
-    for (int i = 0; i < MAX_DIM; ++i)
-      if (i < d) nrm += z[i] * z[i];
-    nrm = sqrt(nrm);
-    double dir[MAX_DIM];
+      for (int i = 0; i < MAX_DIM; ++i)
+        if (i < d) nrm += z[i] * z[i];
+      nrm = sqrt(nrm);
 #pragma unroll
-    for (int a = 0; a < MAX_DIM; ++a) {
-      double acc = 0.0;
+      for (int a = 0; a < MAX_DIM; ++a) {
+        if (a < d) {
+          double acc = 0.0;
 #pragma unroll
-      for (int b = 0; b < MAX_DIM; ++b)
-        if (b <= a && a < d) acc += sL[a * d + b] * z[b];
-      dir[a] = acc / nrm;
-    }
-
-    // ---- step out.  Candidate positions are fixed before any is evaluated:
-    // lane l < 32 holds the left point after l successful steps, lane 32 + l
-    // the right one, so the sequential walk only reads results.
-    double lo = -w * uw, hi = lo + w;
-    int J = (int)floor(R.max_stepout * uj);
-    int K = R.max_stepout - 1 - J;
-    for (int jl = 0, jh = 0; J > 0 || K > 0;) {
-      {
-        const bool left = lane < SOB;
-        const int steps = left ? jl + lane : jh + lane - SOB;   // further steps beyond the current end
-        double tt = left ? lo : hi;
-        for (int q = (left ? jl : jh); q < steps; ++q) tt = left ? tt - w : tt + w;
-        setup(tt, x, dir);
-      }
-      const unsigned long long inb = __ballot(cin);
-      int q = 0;
-      while (J > 0 && q < SOB) {
-        if (!((inb >> q) & 1ull)) { J = 0; break; }
-        if (!(eval(q) > lstar)) { J = 0; break; }
-        lo -= w;
-        --J;
-        ++q;
-      }
-      jl += q;
-      q = 0;
-      while (K > 0 && q < SOB) {
-        if (!((inb >> (SOB + q)) & 1ull)) { K = 0; break; }
-        if (!(eval(SOB + q) > lstar)) { K = 0; break; }
-        hi += w;
-        --K;
-        ++q;
-      }
-      jh += q;
-    }
-
-    // ---- shrink.  Under the hypothesis that every earlier candidate was
-    // rejected the candidate sequence is fixed, so batches of SHB candidates
-    // are set up together; the first accepted one ends the step.
-    for (int a0 = 0; a0 < R.max_shrink; a0 += SHB) {
-      double tl = 0.0;          // candidate of lane a - a0
-      {
-        double l2 = lo, h2 = hi;
-        for (int q = 0; q < SHB; ++q) {
-          const int a = a0 + q;
-          double ua;
-          if (a < 8) {
-            const double v0 = ((a & 3) == 0) ? r0 : ((a & 3) == 1) ? r1 : ((a & 3) == 2) ? r2 : r3;
-            ua = lane_d(v0, nbd + 1 + (a >> 2));
-          } else {
-            u64x4 b = philox(t, (uint64_t)j, (uint64_t)s, purpose_word(P_SHRINK, (uint64_t)(a >> 2)), R.key0,
-                             R.key1);
-            ua = unif53(b.x[a & 3]);
-          }
-          const double tt = fma(ua, h2 - l2, l2);
-          if (lane == q) tl = tt;
-          if (tt < 0.0) l2 = tt; else h2 = tt;
+          for (int b = 0; b < MAX_DIM; ++b)
+            if (b <= a) acc += sL[a * d + b] * z[b];
+          sDir[sl * MAX_DIM + a] = acc / nrm;
         }
       }
-      setup(tl, x, dir);
-      const unsigned long long inb = __ballot(cin);
+    }
+    __syncthreads();
+
+    for (int sl = 0; sl < cs; ++sl) {
+      const int s = s0 + sl;
+      const double* dir = sDir + sl * MAX_DIM;
+      const double* su = sU + sl * SL_NU;
+      double lo = -w * su[0], hi = lo + w;
+      int J = (int)floor(R.max_stepout * su[1]);
+      int K = R.max_stepout - 1 - J;
+
+      // ---- the combined batch
+      __syncthreads();
+      {
+        double tt = 0.0;
+        bool valid = true;
+        if (tid < 2 * BL::SO) {
+          const bool left = tid < BL::SO;
+          const int steps = left ? tid : tid - BL::SO;
+          tt = left ? lo : hi;
+          for (int q = 0; q < steps; ++q) tt = left ? tt - w : tt + w;
+        } else if (tid < 2 * BL::SO + BL::H * BL::H * BL::SC) {
+          const int h = (tid - 2 * BL::SO) / BL::SC, c = (tid - 2 * BL::SO) - BL::SC * h;
+          const int na = h / BL::H, nbh = h - BL::H * na;
+          double l2 = lo, h2 = hi;
+          for (int q = 0; q < na; ++q) l2 -= w;
+          for (int q = 0; q < nbh; ++q) h2 += w;
+          for (int q = 0; q <= c; ++q) {
+            tt = fma(su[2 + q], h2 - l2, l2);
+            if (tt < 0.0) l2 = tt; else h2 = tt;
+          }
+        } else {
+          valid = false;
+        }
+        setup(valid, tt, dir);
+      }
+      __syncthreads();
+      bool combined = true;        // the batch in LDS is the combined one
+
+      // ---- step out, left then right (the order of the sequential algorithm)
+      int na = 0, nh = 0;          // successful steps per side
+      for (int side = 0; side < 2; ++side) {
+        int& budget = side == 0 ? J : K;
+        int& done_steps = side == 0 ? na : nh;
+        int first = side == 0 ? 0 : BL::SO;   // batch slot of this side's next candidate
+        int have = combined ? BL::SO : 0;     // candidates of this side in the batch in LDS
+        int used = 0;
+        while (budget > 0) {
+          if (used == have) {
+            // further step-out points of this side: a batch of FB
+            __syncthreads();
+            double tt = side == 0 ? lo : hi;
+            if (tid < FB)
+              for (int q = 0; q < tid; ++q) tt = side == 0 ? tt - w : tt + w;
+            setup(tid < FB, tt, dir);
+            __syncthreads();
+            combined = false;
+            first = 0;
+            have = FB;
+            used = 0;
+          }
+          const int q = first + used;
+          if (!inside(q)) { budget = 0; break; }
+          if (!(eval(q) > lstar)) { budget = 0; break; }
+          if (side == 0) lo -= w; else hi += w;
+          --budget;
+          ++done_steps;
+          ++used;
+        }
+      }
+
+      // ---- shrink
+      int a = 0;                   // attempts made
       bool accepted = false;
-      for (int q = 0; q < SHB && a0 + q < R.max_shrink; ++q) {
-        const double tt = lane_d(tl, q);
-        if ((inb >> q) & 1ull) {
-          const double ly = eval(q);
-          if (ly > lstar) {
-#pragma unroll
-            for (int i = 0; i < MAX_DIM; ++i) x[i] = (i < d) ? fma(tt, dir[i], x[i]) : 0.0;
-            lx = ly;
-            accepted = true;
-            break;
+      if (combined && na < BL::H && nh < BL::H) {
+        const int base = 2 * BL::SO + BL::SC * (BL::H * na + nh);
+        for (; a < BL::SC && a < R.max_shrink; ++a) {
+          const int q = base + a;
+          const double tt = sT[q];
+          if (inside(q)) {
+            const double ly = eval(q);
+            if (ly > lstar) {
+              if (tid < d) sX[tid] = fma(tt, dir[tid], sX[tid]);
+              lx = ly;
+              accepted = true;
+              break;
+            }
           }
+          if (tt < 0.0) lo = tt; else hi = tt;
         }
-        if (tt < 0.0) lo = tt; else hi = tt;
       }
-      if (accepted) break;
+      while (!accepted && a < R.max_shrink) {
+        // a batch of FB shrink candidates from the current bracket: the
+        // uniforms of attempts a .. a+FB-1 are drawn lane-parallel, then the
+        // bracket recursion under rejection is walked once
+        __syncthreads();
+        if (tid < FB) {
+          const int aa = a + tid;
+          double ua;
+          if (aa < 8) {
+            ua = su[2 + aa];
+          } else {
+            const u64x4 b = philox(t, (uint64_t)j, (uint64_t)s, purpose_word(P_SHRINK, (uint64_t)(aa >> 2)),
+                                   R.key0, R.key1);
+            const int ws = aa & 3;
+            ua = unif53(ws == 0 ? b.x[0] : ws == 1 ? b.x[1] : ws == 2 ? b.x[2] : b.x[3]);
+          }
+          sG[tid] = ua;
+        }
+        __syncthreads();
+        {
+          double l2 = lo, h2 = hi, tl = 0.0;
+          for (int q = 0; q < FB; ++q) {
+            const double tq = fma(sG[q], h2 - l2, l2);
+            if (q == tid) tl = tq;
+            if (tq < 0.0) l2 = tq; else h2 = tq;
+          }
+          __syncthreads();   // sG is reused by the Gaussian test likelihood
+          setup(tid < FB, tl, dir);
+        }
+        __syncthreads();
+        for (int q = 0; q < FB && a < R.max_shrink; ++q, ++a) {
+          const double tt = sT[q];
+          if (inside(q)) {
+            const double ly = eval(q);
+            if (ly > lstar) {
+              if (tid < d) sX[tid] = fma(tt, dir[tid], sX[tid]);
+              lx = ly;
+              accepted = true;
+              ++a;
+              break;
+            }
+          }
+          if (tt < 0.0) lo = tt; else hi = tt;
+        }
+      }
     }
   }
+  __syncthreads();
+  const int slot = R.dead[j];
+  for (int i = tid; i < d; i += NT) R.u[(size_t)slot * d + i] = sX[i];
   if (tid == 0) {
-    const int slot = R.dead[j];
-    for (int i = 0; i < d; ++i) R.u[(size_t)slot * d + i] = x[i];
     R.lam[slot] = lx;
     R.probes[j] = nprobe;
     R.bins[j] = nbins;
@@ -738,8 +1129,8 @@ __global__ void k_waveform(const ModelDev* __restrict__ Mp, const double* theta,
   }
   const double lf = log(f);
   const double psi = phase_cycles(p, f, cbrt(f), lf / 3.0, exp(-5.0 / 3.0 * lf));
-  double sn, cs;
-  sincos_cycles(fma(f, p.dt[det], psi), &sn, &cs);
+  const double2 sc_ = sincos_cycles(fma(f, p.dt[det], psi));
+  const double sn = sc_.x, cs = sc_.y;
   const double a = exp(-7.0 / 6.0 * lf);
   // h = A K f^(-7/6) e^{-i Phi}
   hre[k] = a * (p.kre[det] * cs + p.kim[det] * sn);
@@ -866,7 +1257,7 @@ template <int NDET, int LK, bool LDS>
 hipError_t launch_loglike_t(const ModelDev& M, const ModelDev* Md, const Tables& T, const RBTables& RB,
                             const double* u, long n, double* out, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  const size_t lds = LDS ? (size_t)M.k_lim * (4 * sizeof(double) + NDET * sizeof(double2)) : 0;
+  const size_t lds = LDS ? staged_table_bytes(M.k_lim, NDET, lk_mixed(LK)) : 0;
   long blocks = (n + 255) / 256;
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL((k_loglike<NDET, LK, LDS>), dim3((unsigned)blocks), dim3(256), lds, st, Md, T, RB, u, n, out);
@@ -881,40 +1272,65 @@ hipError_t launch_slice_t(const ModelDev* Md, const Tables& T, const RBTables& R
 }
 
 template <int NDET, int NT>
-hipError_t launch_slice_nt(const ModelDev* Md, const Tables& T, const RBTables& RB, const RunDev& R,
-                           const LaunchCfg& C, hipStream_t st) {
+hipError_t launch_slice_nt(const ModelDev& M, const ModelDev* Md, const Tables& T, const RBTables& RB,
+                           const RunDev& R, const LaunchCfg& C, hipStream_t st) {
+  if (M.likelihood == LK_RB) {
+    if (M.mixed) return launch_slice_t<NDET, NT, LK_RB32, false>(Md, T, RB, R, C.lds_bytes, st);
+    return launch_slice_t<NDET, NT, LK_RB, false>(Md, T, RB, R, C.lds_bytes, st);
+  }
+  if (M.mixed) {
+    if (C.lds_tables) return launch_slice_t<NDET, NT, LK_FULL32, true>(Md, T, RB, R, C.lds_bytes, st);
+    return launch_slice_t<NDET, NT, LK_FULL32, false>(Md, T, RB, R, C.lds_bytes, st);
+  }
   if (C.lds_tables) return launch_slice_t<NDET, NT, LK_FULL, true>(Md, T, RB, R, C.lds_bytes, st);
   return launch_slice_t<NDET, NT, LK_FULL, false>(Md, T, RB, R, C.lds_bytes, st);
 }
 
 template <int NDET>
-hipError_t launch_slice_det(const ModelDev* Md, const Tables& T, const RBTables& RB, const RunDev& R,
-                            const LaunchCfg& C, hipStream_t st) {
+hipError_t launch_slice_det(const ModelDev& M, const ModelDev* Md, const Tables& T, const RBTables& RB,
+                            const RunDev& R, const LaunchCfg& C, hipStream_t st) {
   switch (C.slice_threads) {
-    case 64: return launch_slice_nt<NDET, 64>(Md, T, RB, R, C, st);
-    case 128: return launch_slice_nt<NDET, 128>(Md, T, RB, R, C, st);
-    default: return launch_slice_nt<NDET, 256>(Md, T, RB, R, C, st);
+    case 64: return launch_slice_nt<NDET, 64>(M, Md, T, RB, R, C, st);
+    case 128: return launch_slice_nt<NDET, 128>(M, Md, T, RB, R, C, st);
+    default: return launch_slice_nt<NDET, 256>(M, Md, T, RB, R, C, st);
   }
 }
 
-size_t slice_lds_fixed() { return (size_t)(MAX_DIM * MAX_DIM + 16) * sizeof(double); }
+size_t slice_lds_fixed(int nt) { return slice_fixed_doubles(nt) * sizeof(double); }
 
 }  // namespace
 
 int likelihood_kind(const ModelDev& M) { return M.likelihood; }
 
-hipError_t configure_slice(const ModelDev& M, LaunchCfg* C) {
+hipError_t configure_slice(const ModelDev& M, int rb_nb, LaunchCfg* C) {
   if (M.likelihood == LK_GAUSS) {
     C->slice_threads = 64;
     C->lds_tables = false;
-    C->lds_bytes = slice_lds_fixed();
+    C->lds_bytes = slice_lds_fixed(64);
+    return hipSuccess;
+  }
+  if (M.likelihood == LK_RB) {
+    C->slice_threads = rb_nb < 96 ? 64 : (rb_nb < 192 ? 128 : 256);
+    if (const char* ev = getenv("NS_SLICE_THREADS")) {
+      const int v = atoi(ev);
+      if (v == 64 || v == 128 || v == 256) C->slice_threads = v;
+    }
+    C->lds_tables = false;
+    C->lds_bytes = slice_lds_fixed(C->slice_threads) +
+                   (size_t)M.n_det * (rb_nb + 1) * (M.mixed ? sizeof(float2) : sizeof(double2));
     return hipSuccess;
   }
   const long work = (long)M.k_lim * M.n_det;   // (bin, detector) terms of the widest probe
   C->slice_threads = work <= 96 ? 64 : (work <= 320 ? 128 : 256);
-  const size_t tab = (size_t)M.k_lim * (4 * sizeof(double) + M.n_det * sizeof(double2));
-  C->lds_tables = tab <= 64 * 1024;
-  C->lds_bytes = slice_lds_fixed() + (C->lds_tables ? tab : 0);
+  const size_t tab = staged_table_bytes(M.k_lim, M.n_det, M.mixed != 0);
+  if (const char* ev = getenv("NS_SLICE_THREADS")) {      // tuning override: 64, 128 or 256
+    const int v = atoi(ev);
+    if (v == 64 || v == 128 || v == 256) C->slice_threads = v;
+  }
+  // stage the tables in LDS only while two chain workgroups still fit a CU
+  C->lds_tables = slice_lds_fixed(C->slice_threads) + tab <= 80 * 1024;
+  if (const char* ev = getenv("NS_LDS_TABLES")) C->lds_tables = C->lds_tables && atoi(ev) != 0;   // tuning override
+  C->lds_bytes = slice_lds_fixed(C->slice_threads) + (C->lds_tables ? tab : 0);
   return hipSuccess;
 }
 
@@ -935,11 +1351,45 @@ hipError_t launch_init_live(const RunDev& R, hipStream_t st) {
   return hipGetLastError();
 }
 
+template <int NDET, bool MX>
+hipError_t launch_loglike_rb_t(const ModelDev* Md, const RBTables& RB, const double* u, long n, double* out,
+                               hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  long blocks = (n + 63) / 64;
+  if (blocks > 8192) blocks = 8192;
+  const size_t lds = (size_t)NDET * (RB.nb + 1) * (MX ? sizeof(float2) : sizeof(double2));
+  hipLaunchKernelGGL((k_loglike_rb<NDET, MX>), dim3((unsigned)blocks), dim3(64), lds, st, Md, RB, u, n, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_loglike(const ModelDev& M, const ModelDev* Md, const Tables& T, const RBTables& RB,
                           const double* u, long n, double* out, hipStream_t st) {
   if (M.likelihood == LK_GAUSS) return launch_loglike_t<1, LK_GAUSS, false>(M, Md, T, RB, u, n, out, st);
-  const size_t tab = (size_t)M.k_lim * (4 * sizeof(double) + M.n_det * sizeof(double2));
-  const bool lds = tab <= 64 * 1024;
+  if (M.likelihood == LK_RB) {
+    if (M.mixed) {
+      switch (M.n_det) {
+        case 1: return launch_loglike_rb_t<1, true>(Md, RB, u, n, out, st);
+        case 2: return launch_loglike_rb_t<2, true>(Md, RB, u, n, out, st);
+        default: return launch_loglike_rb_t<3, true>(Md, RB, u, n, out, st);
+      }
+    }
+    switch (M.n_det) {
+      case 1: return launch_loglike_rb_t<1, false>(Md, RB, u, n, out, st);
+      case 2: return launch_loglike_rb_t<2, false>(Md, RB, u, n, out, st);
+      default: return launch_loglike_rb_t<3, false>(Md, RB, u, n, out, st);
+    }
+  }
+  const bool lds = staged_table_bytes(M.k_lim, M.n_det, M.mixed != 0) <= 64 * 1024;
+  if (M.mixed) {
+    switch (M.n_det) {
+      case 1: return lds ? launch_loglike_t<1, LK_FULL32, true>(M, Md, T, RB, u, n, out, st)
+                         : launch_loglike_t<1, LK_FULL32, false>(M, Md, T, RB, u, n, out, st);
+      case 2: return lds ? launch_loglike_t<2, LK_FULL32, true>(M, Md, T, RB, u, n, out, st)
+                         : launch_loglike_t<2, LK_FULL32, false>(M, Md, T, RB, u, n, out, st);
+      default: return lds ? launch_loglike_t<3, LK_FULL32, true>(M, Md, T, RB, u, n, out, st)
+                          : launch_loglike_t<3, LK_FULL32, false>(M, Md, T, RB, u, n, out, st);
+    }
+  }
   switch (M.n_det) {
     case 1: return lds ? launch_loglike_t<1, LK_FULL, true>(M, Md, T, RB, u, n, out, st)
                        : launch_loglike_t<1, LK_FULL, false>(M, Md, T, RB, u, n, out, st);
@@ -970,9 +1420,9 @@ hipError_t launch_iteration(const ModelDev& M, const ModelDev* Md, const Tables&
     e = launch_slice_t<1, 64, LK_GAUSS, false>(Md, T, RB, R, C.lds_bytes, st);
   } else {
     switch (M.n_det) {
-      case 1: e = launch_slice_det<1>(Md, T, RB, R, C, st); break;
-      case 2: e = launch_slice_det<2>(Md, T, RB, R, C, st); break;
-      default: e = launch_slice_det<3>(Md, T, RB, R, C, st); break;
+      case 1: e = launch_slice_det<1>(M, Md, T, RB, R, C, st); break;
+      case 2: e = launch_slice_det<2>(M, Md, T, RB, R, C, st); break;
+      default: e = launch_slice_det<3>(M, Md, T, RB, R, C, st); break;
     }
   }
   if (e != hipSuccess) return e;
@@ -987,6 +1437,35 @@ hipError_t launch_waveform(const ModelDev& M, const ModelDev* Md, const double* 
                            double* h_re, double* h_im, hipStream_t st) {
   hipLaunchKernelGGL(k_waveform, dim3((M.n_bins + 255) / 256), dim3(256), 0, st, Md, theta_dev, det, apply_cut,
                      h_re, h_im);
+  return hipGetLastError();
+}
+
+hipError_t launch_build_rb_edges(const ModelDev* Md, int nb, const RBBuffers& B, hipStream_t st) {
+  hipLaunchKernelGGL(k_rb_edges, dim3((nb + 1 + 255) / 256), dim3(256), 0, st, Md, nb, B.edge, B.fe, B.fe13, B.lnfe3,
+                     B.fem53);
+  return hipGetLastError();
+}
+
+hipError_t launch_build_rb_sums(const ModelDev& M, const ModelDev* Md, const Tables& T, const double* hw,
+                                const double* theta_fid_dev, int nb, const RBBuffers& B, hipStream_t st) {
+  hipLaunchKernelGGL(k_rb_fiducial, dim3((nb + 1 + 255) / 256), dim3(256), 0, st, Md, theta_fid_dev, nb, B.fe, B.fe13,
+                     B.lnfe3, B.fem53, B.phi0, B.g0, B.fm, B.inv_w);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_rb_sums, dim3((nb + 63) / 64, M.n_det), dim3(64), 0, st, Md, T, hw, theta_fid_dev, nb, B.edge,
+                     B.fm, B.A0, B.A1, B.B0, B.B1, B.cA0, B.cA1, B.cB0, B.cB1);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_float(const double2* src, float2* dst, size_t n, double scale, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_to_float2, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, dst, n, scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_float(const double* src, float* dst, size_t n, double scale, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_to_float1, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, dst, n, scale);
   return hipGetLastError();
 }
 

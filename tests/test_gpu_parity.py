@@ -199,3 +199,86 @@ def test_capacity_and_no_termination(torch_cuda):
     rg = binding.Run(spec, binding.opts_for(w, term_frac=0.0, max_iter=100))
     assert not rg.step(40)
     assert rg.state()["iter"] == 40
+
+
+@pytest.mark.parametrize("n", [1031])
+def test_rb_loglike_parity(torch_cuda, n):
+    """Relative-binning likelihood (cfg3) against the oracle's, to 1e-9 of the
+    cancellation scale, including the fiducial point and cube corners."""
+    torch = torch_cuda
+    w = synth.workload("cfg3")
+    orc, spec = _pair(w)
+    u = synth.proposal_batch(w, n, seed=11)
+    u[0] = 0.0
+    u[1] = 1.0
+    u[2] = synth.theta_to_cube_box(w, w.theta_inj)
+    wf = synth.workload("cfg2")
+    orc_full = oracle.OracleProblem(wf, orc.dre, orc.dim)
+    _, scale = _scale(wf, orc_full, u)
+    lam_o = orc.loglike_batch(u, NTHREADS)
+    run = binding.Run(spec, binding.opts_for(w, n_live=64, n_delete=32))
+    got = run.loglike(torch.from_numpy(u).cuda()).cpu().numpy()
+    err = np.abs(got - lam_o) / scale
+    assert err.max() <= 1e-9, (err.max(), np.argmax(err))
+    # at the fiducial the heterodyned likelihood equals the full-grid one
+    full = orc_full.loglike_theta(w.theta_inj)
+    one = run.loglike(torch.from_numpy(synth.theta_to_cube_box(w, w.theta_inj)[None, :].copy()).cuda())
+    th = orc.prior_transform(synth.theta_to_cube_box(w, w.theta_inj))
+    assert abs(one.item() - orc_full.loglike_theta(th)) <= 1e-9 * (abs(full) + 1)
+
+
+def test_rb_iterations_lockstep(torch_cuda):
+    w = synth.workload("cfg3")
+    orc, spec = _pair(w)
+    ro, rg = _lockstep(w, orc, spec, 2)
+    _compare_runs(ro, rg)
+
+
+def test_rb_rejects_degenerate_binning(torch_cuda):
+    w = synth.workload("cfg3")
+    w.rb_n_bins = 1000                  # more coarse bins than the grid can separate at low frequency
+    spec = binding.ProblemSpec(w)
+    with pytest.raises(binding.NSError):
+        binding.Run(spec, binding.opts_for(w, n_live=16, n_delete=8))
+
+
+@pytest.mark.parametrize("name", ["cfg4", "cfg4rb"])
+def test_mixed_precision_loglike_error(torch_cuda, name):
+    """Mixed form (float sincos and sums, double phase): the error against the
+    double-precision oracle stays below 2e-5 of the cancellation scale."""
+    torch = torch_cuda
+    w = synth.workload(name)
+    orc, spec = _pair(w)
+    u = synth.proposal_batch(w, 2053, seed=13)
+    wf = synth.workload("cfg2")
+    orc_full = oracle.OracleProblem(wf, orc.dre, orc.dim)
+    _, scale = _scale(wf, orc_full, u)
+    lam_o = orc.loglike_batch(u, NTHREADS)
+    run = binding.Run(spec, binding.opts_for(w, n_live=64, n_delete=32))
+    got = run.loglike(torch.from_numpy(u).cuda()).cpu().numpy()
+    err = np.abs(got - lam_o)
+    print(f"{name}: max |dlogL| = {err.max():.3e}, max relative {np.max(err / scale):.3e}")
+    assert np.max(err / scale) <= 2e-5
+
+
+def test_mixed_precision_evidence_statistics(torch_cuda):
+    """Mixed-form runs against double-precision oracle runs over 8 seed pairs
+    (trajectories differ, so the check is statistical): the mean log Z
+    difference is below 0.1 plus its standard error and every pair agrees
+    within 2 sigma."""
+    w = synth.workload("cfg1")
+    orc, spec = _pair(w)
+    diffs, sig = [], []
+    for r in range(8):
+        ro = oracle.Run(orc, oracle.opts_for(w, n_threads=NTHREADS, seed=1001 + r))
+        ro.run()
+        rg = binding.Run(spec, binding.opts_for(w, seed=1001 + r, precision=binding.NS_MIXED))
+        rg.run()
+        zo, zg = ro.logZ(200), rg.logZ(200)
+        diffs.append(zg["logZ"] - zo["logZ"])
+        s = math.hypot(zo["sigma"], zg["sigma"])
+        sig.append(s)
+        assert abs(diffs[-1]) <= 2 * s + 1e-9, (r, zo, zg)
+    diffs = np.array(diffs)
+    print("mixed - oracle log Z:", diffs)
+    assert abs(diffs.mean()) <= 0.1 + 2 * np.mean(sig) / math.sqrt(len(diffs))
