@@ -216,6 +216,67 @@ NS_API int ns_stats(ns_run* run, ns_stats_t* out);
 /* Release a run (NULL is allowed). */
 NS_API void ns_free(ns_run* run);
 
+/* ---- Serving -------------------------------------------------------------
+ * A server keeps many runs resident on one device and advances them
+ * together: every tick runs one iteration (Section 2) of each resident run,
+ * with one packed launch per kernel over the chains of all resident runs
+ * that share a likelihood form and precision.  Requests (one per event) wait
+ * in a queue until a run slot and device memory are free; a request that
+ * does not fit may be overtaken by later ones that do, at most 16 times.
+ * Each run's arithmetic is the same alone and in any mix: its results are
+ * bit-identical whatever else is resident (they may differ in the last bits
+ * from ns_init's, which picks the chain-workgroup size per problem). */
+typedef struct ns_server ns_server;
+
+enum { NS_SERVER_GRAPH = 1 };   /* replay each tick's launches from a captured HIP graph */
+
+typedef struct {
+    long long ticket;
+    int status;          /* NS_OK, or the error code of the run's construction */
+    int done;            /* termination code: 1 criterion met, 2 capacity reached */
+    int iterations;
+    double t_submit;     /* seconds since the server was created */
+    double t_admit;      /* construction started */
+    double t_finish;     /* the tick that saw the run terminate returned */
+    size_t bytes;        /* device bytes the run holds until it is taken */
+} ns_ticket_info;
+
+/* Create a server.  hbm_budget: device bytes the resident runs may hold
+ * (0: 90% of the free memory now); max_runs: resident-run slots, 1..4096;
+ * flags: 0 or NS_SERVER_GRAPH (needs a stream other than the null stream).
+ * Runs are built and advanced on stream, which the caller keeps alive until
+ * ns_server_free and while it uses runs taken from the server.
+ * Errors: NS_E_ARG, NS_E_OOM, NS_E_HIP. */
+NS_API int ns_server_create(ns_server** out, size_t hbm_budget, int max_runs, int flags, void* stream);
+
+/* Queue a request.  problem and opts are validated now and copied (the
+ * caller may free its arrays on return); likelihood must be NS_LIKE_FULL or
+ * NS_LIKE_RB.  ticket receives the request's handle.  NS_E_OOM if the run
+ * alone would exceed the budget. */
+NS_API int ns_server_submit(ns_server* server, const ns_problem* problem, const ns_opts* opts, long long* ticket);
+
+/* Admit what fits, run n_iters (1..1000) iterations of every resident run,
+ * retire the runs that terminated, admit again.  Synchronises the stream
+ * once.  Outputs (may be NULL): resident, queued, and finished-but-not-yet-
+ * polled counts. */
+NS_API int ns_server_tick(ns_server* server, int n_iters, int* n_running, int* n_queued, int* n_finished);
+
+/* Report finished requests not reported before, up to cap, in the order
+ * they finished; n_out receives the count. */
+NS_API int ns_server_poll(ns_server* server, ns_ticket_info* out, int cap, int* n_out);
+
+/* Hand a finished run to the caller, who then owns it (ns_logZ, ns_samples,
+ * ns_dead, ..., ns_free) and whose bytes leave the server's budget.
+ * NS_E_STATE while the ticket is queued or running, or if its construction
+ * failed (the ticket is then forgotten). */
+NS_API int ns_server_take(ns_server* server, long long ticket, ns_run** out);
+
+/* Budget, bytes held, resident and queued counts (any pointer may be NULL). */
+NS_API int ns_server_info(ns_server* server, size_t* budget, size_t* used, int* n_running, int* n_queued);
+
+/* Release the server with every run it still holds (NULL is allowed). */
+NS_API void ns_server_free(ns_server* server);
+
 /* Message for the calling thread's most recent failure ("" if none). */
 NS_API const char* ns_last_error(void);
 

@@ -3,7 +3,8 @@
 Calls only the oracle.  For each workload the injected waveform is computed
 at 1 Mpc, its optimal network SNR rho_1 = sqrt(sum_det <h|h>) is taken, and
 the distance that gives the target SNR is rho_1 / rho_target (the amplitude
-is inversely proportional to distance).  Writes
+is inversely proportional to distance).  The serving events get one
+distance each.  Writes
 ``paper_2509_24949_amd/injections.json``.
 
     python -m oracle.derive_injections
@@ -44,6 +45,14 @@ def derive() -> dict:
     rho1 = optimal_snr(w2, th)
     out["cfg2"] = {"distance_mpc": rho1 / w2.snr_target, "snr": w2.snr_target,
                    "note": "luminosity distance of the H1/L1/V1 injection"}
+    dist, snr = [], []
+    for i in range(synth.SERVING_EVENTS):
+        w = synth.serving_event(i, distance=1.0)
+        rho1 = optimal_snr(w, np.array(w.theta_inj, dtype=np.float64))
+        dist.append(rho1 / w.snr_target)
+        snr.append(w.snr_target)
+    out["cfg5"] = {"distance_mpc": dist, "snr": snr,
+                   "note": "luminosity distances of the serving events, in event order"}
     return out
 
 

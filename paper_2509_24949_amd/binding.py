@@ -58,6 +58,15 @@ class Stats(C.Structure):
 
 
 # Every entry point of include/ns.h with its ctypes signature.
+class TicketInfo(C.Structure):
+    _fields_ = [
+        ("ticket", C.c_longlong), ("status", C.c_int), ("done", C.c_int), ("iterations", C.c_int),
+        ("t_submit", C.c_double), ("t_admit", C.c_double), ("t_finish", C.c_double), ("bytes", C.c_size_t),
+    ]
+
+
+NS_SERVER_GRAPH = 1
+
 SIGNATURES = {
     "ns_init": (C.c_int, [C.POINTER(C.c_void_p), C.c_void_p, C.c_void_p, C.c_void_p]),
     "ns_step": (C.c_int, [C.c_void_p, C.c_int, _ip]),
@@ -73,6 +82,13 @@ SIGNATURES = {
     "ns_profile": (C.c_int, [C.c_void_p, C.c_int]),
     "ns_stats": (C.c_int, [C.c_void_p, C.POINTER(Stats)]),
     "ns_free": (None, [C.c_void_p]),
+    "ns_server_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_size_t, C.c_int, C.c_int, C.c_void_p]),
+    "ns_server_submit": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_longlong)]),
+    "ns_server_tick": (C.c_int, [C.c_void_p, C.c_int, _ip, _ip, _ip]),
+    "ns_server_poll": (C.c_int, [C.c_void_p, C.POINTER(TicketInfo), C.c_int, _ip]),
+    "ns_server_take": (C.c_int, [C.c_void_p, C.c_longlong, C.POINTER(C.c_void_p)]),
+    "ns_server_info": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t), _ip, _ip]),
+    "ns_server_free": (None, [C.c_void_p]),
     "ns_last_error": (C.c_char_p, []),
 }
 
@@ -203,6 +219,13 @@ class Run:
         _check(lib().ns_init(C.byref(h), spec.ref, C.byref(opts), _stream(stream)))
         self.h = h
 
+    @classmethod
+    def adopt(cls, h: C.c_void_p, spec: ProblemSpec, opts: Opts) -> "Run":
+        """Wrap a run handed over by a server (ns_server_take)."""
+        r = cls.__new__(cls)
+        r.spec, r.opts, r.h = spec, opts, h
+        return r
+
     def step(self, max_iters: int = 1) -> bool:
         done = C.c_int()
         _check(lib().ns_step(self.h, max_iters, C.byref(done)))
@@ -277,6 +300,55 @@ class Run:
     def close(self):
         if getattr(self, "h", None) and _lib is not None:
             _lib.ns_free(self.h)
+        self.h = None
+
+    def __del__(self):
+        self.close()
+
+
+class Server:
+    """An ns_server: queued requests, memory-based admission, packed ticks."""
+
+    def __init__(self, hbm_budget: int = 0, max_runs: int = 8, graph: bool = False, stream=None):
+        h = C.c_void_p()
+        _check(lib().ns_server_create(C.byref(h), hbm_budget, max_runs, NS_SERVER_GRAPH if graph else 0,
+                                      _stream(stream)))
+        self.h = h
+        self.requests = {}
+
+    def submit(self, spec: ProblemSpec, opts: Opts) -> int:
+        t = C.c_longlong()
+        _check(lib().ns_server_submit(self.h, spec.ref, C.byref(opts), C.byref(t)))
+        self.requests[t.value] = (spec, opts)
+        return t.value
+
+    def tick(self, n_iters: int = 1):
+        """(resident, queued, finished-not-yet-polled) after the tick."""
+        a, b, c = C.c_int(), C.c_int(), C.c_int()
+        _check(lib().ns_server_tick(self.h, n_iters, C.byref(a), C.byref(b), C.byref(c)))
+        return a.value, b.value, c.value
+
+    def poll(self, cap: int = 256):
+        buf = (TicketInfo * cap)()
+        n = C.c_int()
+        _check(lib().ns_server_poll(self.h, buf, cap, C.byref(n)))
+        return [{name: getattr(buf[i], name) for name, _ in TicketInfo._fields_} for i in range(n.value)]
+
+    def take(self, ticket: int) -> Run:
+        h = C.c_void_p()
+        _check(lib().ns_server_take(self.h, ticket, C.byref(h)))
+        spec, opts = self.requests.pop(ticket)
+        return Run.adopt(h, spec, opts)
+
+    def info(self) -> dict:
+        b, u = C.c_size_t(), C.c_size_t()
+        r, q = C.c_int(), C.c_int()
+        _check(lib().ns_server_info(self.h, C.byref(b), C.byref(u), C.byref(r), C.byref(q)))
+        return dict(budget=b.value, used=u.value, running=r.value, queued=q.value)
+
+    def close(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.ns_server_free(self.h)
         self.h = None
 
     def __del__(self):

@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libns.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("ns_api.hip", "ns_kernels.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("ns_api.hip", "ns_server.hip", "ns_kernels.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

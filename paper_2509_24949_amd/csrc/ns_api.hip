@@ -11,11 +11,11 @@
 #include <vector>
 
 #include "../../include/ns.h"
-#include "ns_internal.h"
+#include "ns_runtime.h"
 
 using namespace ns;
 
-namespace {
+namespace ns {
 
 thread_local std::string g_err;
 
@@ -28,55 +28,6 @@ int fail(int code, const char* fmt, ...) {
   g_err = buf;
   return code;
 }
-
-#define HIP_OK(expr)                                                                         \
-  do {                                                                                       \
-    hipError_t e_ = (expr);                                                                  \
-    if (e_ != hipSuccess) return fail(NS_E_HIP, "%s: %s", #expr, hipGetErrorString(e_));    \
-  } while (0)
-
-// Device allocations of one run, released together.
-struct DevMem {
-  std::vector<void*> ptrs;
-  ~DevMem() {
-    for (void* p : ptrs) (void)hipFree(p);
-  }
-  template <typename T>
-  hipError_t alloc(T** out, size_t count) {
-    void* p = nullptr;
-    hipError_t e = hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T));
-    if (e == hipSuccess) ptrs.push_back(p);
-    *out = static_cast<T*>(p);
-    return e;
-  }
-};
-
-}  // namespace
-
-struct ns_run {
-  ModelDev M{};
-  ModelDev* Md = nullptr;        // device copy of M
-  Tables T{};
-  RBTables RB{};
-  RunDev R{};
-  LaunchCfg C{};
-  hipStream_t st = nullptr;
-  DevMem mem;
-  DevState* h_state = nullptr;   // pinned mirror of the device scalars
-  bool profiling = false;
-  std::vector<std::array<hipEvent_t, 5>> events;   // per profiled iteration
-  void release_events() {
-    for (auto& a : events)
-      for (hipEvent_t e : a) (void)hipEventDestroy(e);
-    events.clear();
-  }
-  ~ns_run() {
-    release_events();
-    if (h_state) (void)hipHostFree(h_state);
-  }
-};
-
-namespace {
 
 int validate_and_model(const ns_problem* P, ModelDev* M) {
   if (!P) return fail(NS_E_ARG, "problem is NULL");
@@ -207,13 +158,35 @@ int sync_state(ns_run* r) {
   return NS_OK;
 }
 
+namespace {
+size_t rounded(size_t bytes) { return (std::max<size_t>(bytes, 1) + 4095) / 4096 * 4096; }
 }  // namespace
 
-extern "C" {
+void run_footprint(const ns_problem* P, const ns_opts* O, size_t* resident, size_t* transient) {
+  const size_t n = O->n_live, k = O->n_delete, d = P->n_dim;
+  const size_t cap = (size_t)O->max_iter * k;
+  size_t b = rounded(sizeof(ModelDev)) + rounded(sizeof(DevState)) + rounded(n * d * 8) + rounded(n * 8) +
+             2 * rounded(n * 4) + 2 * rounded(k * 4) + rounded(d * d * 8) + rounded(k * 4) + rounded(k * 8) +
+             rounded(cap * d * 8) + 3 * rounded(cap * 8) + 3 * rounded(cap * 4);
+  size_t t = 0;
+  if (P->likelihood != NS_LIKE_GAUSS) {
+    const size_t nb = P->n_bins, nbd = (size_t)P->n_det * P->n_bins;
+    b += 4 * rounded(nb * 8) + rounded(nbd * 16) + rounded(nbd * 8);
+    if (O->precision == NS_MIXED && P->likelihood == NS_LIKE_FULL) b += rounded(nbd * 8);
+    if (P->likelihood == NS_LIKE_RB) {
+      const size_t q = std::max(P->rb_n_bins, 1), ne = q + 1, nbin = (size_t)P->n_det * q;
+      b += rounded(ne * 4) + 4 * rounded(ne * 8) + rounded((size_t)P->n_det * ne * 8) + 2 * rounded(q * 8) +
+           rounded((size_t)P->n_det * 16) + 2 * rounded(nbin * 16) + 2 * rounded(nbin * 8) + 2 * rounded(nbd * 16) +
+           2 * rounded(nbd * 8) + rounded(MAX_DIM * 8);
+      if (O->precision == NS_MIXED) b += 2 * rounded(nbin * 8) + 2 * rounded(nbin * 4);
+    }
+    t = rounded(4 * nbd * 8);
+  }
+  *resident = b;
+  *transient = t;
+}
 
-const char* ns_last_error(void) { return g_err.c_str(); }
-
-int ns_init(ns_run** out, const ns_problem* P, const ns_opts* O, void* stream) {
+int run_create(ns_run** out, const ns_problem* P, const ns_opts* O, hipStream_t stream, bool packed) {
   if (!out) return fail(NS_E_ARG, "out is NULL");
   *out = nullptr;
   ModelDev M;
@@ -237,7 +210,8 @@ int ns_init(ns_run** out, const ns_problem* P, const ns_opts* O, void* stream) {
     if (mx > 0.0 && isfinite(mx)) M.dw_scale = ldexp(1.0, -ilogb(mx));
   }
   r->M = M;
-  r->st = static_cast<hipStream_t>(stream);
+  r->st = stream;
+  r->packed = packed;
   const int n = O->n_live, k = O->n_delete, d = P->n_dim;
   RunDev& R = r->R;
   R.n = n; R.k = k; R.d = d; R.m = O->n_steps;
@@ -358,7 +332,8 @@ int ns_init(ns_run** out, const ns_problem* P, const ns_opts* O, void* stream) {
     if (e != hipSuccess) return cleanup(fail(NS_E_HIP, "building likelihood tables: %s", hipGetErrorString(e)));
   }
 #undef ALLOC
-  (void)configure_slice(r->M, r->RB.nb, &r->C);
+  if (packed) (void)configure_slice_packed(r->M, r->RB.nb, &r->C);
+  else (void)configure_slice(r->M, r->RB.nb, &r->C);
   DevState s0{};
   s0.logX = 0.0;
   s0.logZ = -__builtin_inf();
@@ -376,6 +351,16 @@ int ns_init(ns_run** out, const ns_problem* P, const ns_opts* O, void* stream) {
   if (e != hipSuccess) return cleanup(fail(NS_E_HIP, "initial population: %s", hipGetErrorString(e)));
   *out = r;
   return NS_OK;
+}
+
+}  // namespace ns
+
+extern "C" {
+
+const char* ns_last_error(void) { return g_err.c_str(); }
+
+int ns_init(ns_run** out, const ns_problem* P, const ns_opts* O, void* stream) {
+  return run_create(out, P, O, static_cast<hipStream_t>(stream), false);
 }
 
 int ns_step_async(ns_run* r, int n_iters) {

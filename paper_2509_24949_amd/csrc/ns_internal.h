@@ -102,6 +102,14 @@ struct LaunchCfg {
   size_t lds_bytes;           // dynamic LDS of the chain kernel
 };
 
+// A resident run as the packed (serving) kernels see it.
+struct PackedRun {
+  const ModelDev* M;
+  Tables T;
+  RBTables RB;
+  RunDev R;
+};
+
 // ---- launch wrappers (ns_kernels.hip) --------------------------------------
 // M is the host copy of the model, Md the same struct in device memory.
 hipError_t launch_build_tables(const ModelDev& M, const ModelDev* Md, const double* data_re, const double* data_im,
@@ -136,6 +144,19 @@ hipError_t launch_build_rb_edges(const ModelDev* Md, int nb, const RBBuffers& B,
 hipError_t launch_build_rb_sums(const ModelDev& M, const ModelDev* Md, const Tables& T, const double* hw,
                                 const double* theta_fid_dev, int nb, const RBBuffers& B, hipStream_t st);
 hipError_t configure_slice(const ModelDev& M, int rb_nb, LaunchCfg* C);
+// Chain-kernel set-up of runs that take part in packed launches: 256
+// threads per chain, tables read from HBM/L2 (as in the packed kernel).
+hipError_t configure_slice_packed(const ModelDev& M, int rb_nb, LaunchCfg* C);
+// One iteration of every run in `runs` (device array of nr descriptors):
+// packed selection (rank_off: prefix of ceil(n_r/4) blocks), preparation,
+// chain kernel (slice_off: prefix of k_r blocks) and termination.  lk is the
+// shared likelihood kind (LK_FULL, LK_FULL32, LK_RB or LK_RB32), max_n the
+// largest n_live, slice_lds the largest chain-kernel LDS of the runs.
+hipError_t launch_iteration_packed(const PackedRun* runs, const int* rank_off, const int* slice_off, int nr,
+                                   int rank_blocks, int slice_blocks, int lk, int max_n, size_t slice_lds,
+                                   hipStream_t st);
+// done flag of every run into out[nr].
+hipError_t launch_gather_done(const PackedRun* runs, int nr, int* out, hipStream_t st);
 int likelihood_kind(const ModelDev& M);
 
 }  // namespace ns

@@ -576,11 +576,9 @@ __global__ __launch_bounds__(256) void k_loglike(const ModelDev* __restrict__ Mp
 }
 
 // ---------------------------------------------------------------- select
-__global__ __launch_bounds__(256) void k_rank(const double* __restrict__ lam, int n, int k, int* rank, int* dead,
-                                              double* lstar, const int* done) {
-  if (done && *done) return;
-  const int i = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-  if (i >= n) return;
+// Rank of element i in the total order (order key, index), one wavefront.
+__device__ inline void rank_element(const double* __restrict__ lam, int n, int k, int* rank, int* dead, double* lstar,
+                                    int i, int lane) {
   const uint64_t ki = order_key(lam[i]);
   int cnt = 0;
   for (int j = lane; j < n; j += 64) {
@@ -595,13 +593,21 @@ __global__ __launch_bounds__(256) void k_rank(const double* __restrict__ lam, in
   }
 }
 
+__global__ __launch_bounds__(256) void k_rank(const double* __restrict__ lam, int n, int k, int* rank, int* dead,
+                                              double* lstar, const int* done) {
+  if (done && *done) return;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (i >= n) return;
+  rank_element(lam, n, k, rank, dead, lstar, i, lane);
+}
+
 // ------------------------------------------------------------- iteration prep
-// One workgroup of 1024 threads.  Dynamic LDS: n ints (survivor list).
-__global__ __launch_bounds__(1024) void k_prep(RunDev R) {
-  extern __shared__ int s_surv[];
+// One workgroup of 1024 threads; s_surv: n ints of LDS (survivor list).
+__device__ void prep_body(const RunDev& R, int* s_surv) {
   __shared__ double sbuf[1024];
   __shared__ double smean[MAX_DIM];
   __shared__ double scov[MAX_DIM * MAX_DIM];
+  __shared__ double schol[MAX_DIM * MAX_DIM];
   __shared__ int sint[1024];
   DevState* S = R.state;
   const int done0 = S->done;
@@ -717,7 +723,7 @@ __global__ __launch_bounds__(1024) void k_prep(RunDev R) {
   __syncthreads();
   if (tid == 0) {
     // Cholesky factor; on failure add 1e-12 tr/d to the diagonal and retry
-    double L[MAX_DIM * MAX_DIM];
+    double* L = schol;
     bool ok = false;
     for (int attempt = 0; attempt < 2 && !ok; ++attempt) {
       if (attempt == 1) {
@@ -760,6 +766,12 @@ __global__ __launch_bounds__(1024) void k_prep(RunDev R) {
   }
 }
 
+__global__ __launch_bounds__(1024) void k_prep(RunDev R) {
+  extern __shared__ int s_surv[];
+  prep_body(R, s_surv);
+}
+
+
 // ------------------------------------------------------------ slice chains
 // Candidate batches of the chain kernel: NT candidates per batch, one per
 // thread.  Slots [0, SO) hold left step-out points, [SO, 2 SO) right ones,
@@ -793,16 +805,14 @@ __host__ __device__ constexpr size_t slice_fixed_doubles(int nt) {
 // walk the batch in the sequential order of the algorithm and split every
 // probe's frequency bins.  Rarer outcomes fall back to further batches.
 template <int NDET, int NT, int LK, bool LDS>
-__global__ __launch_bounds__(NT) void k_slice(const ModelDev* __restrict__ Mp, Tables T, RBTables RB, RunDev R) {
+__device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& RB, const RunDev& R, int j,
+                           double* smem) {
   constexpr int NW = NT / 64;
   constexpr int FB = 32;             // candidates per fallback batch
   using BL = SliceBatch<NT>;
-  extern __shared__ double smem[];
-  const ModelDev& M = *Mp;
   DevState* S = R.state;
   if (S->done) return;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int j = blockIdx.x;
   const int d = R.d;
   const uint64_t t = (uint64_t)S->iter;
   const double lstar = S->lstar;
@@ -1080,8 +1090,15 @@ __global__ __launch_bounds__(NT) void k_slice(const ModelDev* __restrict__ Mp, T
   }
 }
 
+template <int NDET, int NT, int LK, bool LDS>
+__global__ __launch_bounds__(NT, 2) void k_slice(const ModelDev* __restrict__ Mp, Tables T, RBTables RB, RunDev R) {
+  extern __shared__ double smem[];
+  slice_body<NDET, NT, LK, LDS>(*Mp, T, RB, R, blockIdx.x, smem);
+}
+
+
 // ------------------------------------------------------------- termination
-__global__ __launch_bounds__(1024) void k_term(RunDev R) {
+__device__ void term_body(const RunDev& R) {
   __shared__ double sbuf[1024];
   DevState* S = R.state;
   if (S->done) return;
@@ -1109,6 +1126,60 @@ __global__ __launch_bounds__(1024) void k_term(RunDev R) {
     S->iter += 1;
     S->done = done;
   }
+}
+
+__global__ __launch_bounds__(1024) void k_term(RunDev R) { term_body(R); }
+
+
+// ---------------------------------------------------------------- packed
+// Serving: one launch per kernel covers every resident run.  Blocks are
+// assigned to runs by prefix offsets (off[r] = first block of run r).
+__device__ inline int packed_run_of(const int* __restrict__ off, int nr, int b) {
+  int lo = 0, hi = nr - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(256) void k_rank_packed(const PackedRun* __restrict__ runs,
+                                                     const int* __restrict__ off, int nr) {
+  const int r = packed_run_of(off, nr, blockIdx.x);
+  const RunDev& R = runs[r].R;
+  if (R.state->done) return;
+  const int i = (blockIdx.x - off[r]) * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (i >= R.n) return;
+  rank_element(R.lam, R.n, R.k, R.rank, R.dead, nullptr, i, lane);
+}
+
+__global__ __launch_bounds__(1024) void k_prep_packed(const PackedRun* __restrict__ runs) {
+  extern __shared__ int s_surv[];
+  prep_body(runs[blockIdx.x].R, s_surv);
+}
+
+__global__ __launch_bounds__(1024) void k_term_packed(const PackedRun* __restrict__ runs) {
+  term_body(runs[blockIdx.x].R);
+}
+
+template <int NT, int LK>
+__global__ __launch_bounds__(NT, 2) void k_slice_packed(const PackedRun* __restrict__ runs, const int* __restrict__ off,
+                                                     int nr) {
+  extern __shared__ double smem[];
+  const int r = packed_run_of(off, nr, blockIdx.x);
+  const PackedRun& P = runs[r];
+  const int j = blockIdx.x - off[r];
+  switch (P.M->n_det) {
+    case 1: slice_body<1, NT, LK, false>(*P.M, P.T, P.RB, P.R, j, smem); break;
+    case 2: slice_body<2, NT, LK, false>(*P.M, P.T, P.RB, P.R, j, smem); break;
+    default: slice_body<3, NT, LK, false>(*P.M, P.T, P.RB, P.R, j, smem); break;
+  }
+}
+
+__global__ void k_gather_done(const PackedRun* __restrict__ runs, int nr, int* out) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < nr) out[r] = runs[r].R.state->done;
 }
 
 // ---------------------------------------------------------------- waveform
@@ -1431,6 +1502,50 @@ hipError_t launch_iteration(const ModelDev& M, const ModelDev* Md, const Tables&
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (ev && (e = hipEventRecord(ev[4], st)) != hipSuccess) return e;
   return hipSuccess;
+}
+
+hipError_t configure_slice_packed(const ModelDev& M, int rb_nb, LaunchCfg* C) {
+  C->slice_threads = 256;
+  C->lds_tables = false;
+  C->lds_bytes = slice_lds_fixed(256);
+  if (M.likelihood == LK_RB) C->lds_bytes += (size_t)M.n_det * (rb_nb + 1) * (M.mixed ? sizeof(float2) : sizeof(double2));
+  return hipSuccess;
+}
+
+hipError_t launch_iteration_packed(const PackedRun* runs, const int* rank_off, const int* slice_off, int nr,
+                                   int rank_blocks, int slice_blocks, int lk, int max_n, size_t slice_lds,
+                                   hipStream_t st) {
+  if (nr <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rank_packed, dim3(rank_blocks), dim3(256), 0, st, runs, rank_off, nr);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_prep_packed, dim3(nr), dim3(1024), (size_t)max_n * sizeof(int), st, runs);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  switch (lk) {
+    case LK_FULL:
+      hipLaunchKernelGGL((k_slice_packed<256, LK_FULL>), dim3(slice_blocks), dim3(256), slice_lds, st, runs, slice_off, nr);
+      break;
+    case LK_FULL32:
+      hipLaunchKernelGGL((k_slice_packed<256, LK_FULL32>), dim3(slice_blocks), dim3(256), slice_lds, st, runs, slice_off,
+                         nr);
+      break;
+    case LK_RB:
+      hipLaunchKernelGGL((k_slice_packed<256, LK_RB>), dim3(slice_blocks), dim3(256), slice_lds, st, runs, slice_off, nr);
+      break;
+    default:
+      hipLaunchKernelGGL((k_slice_packed<256, LK_RB32>), dim3(slice_blocks), dim3(256), slice_lds, st, runs, slice_off,
+                         nr);
+      break;
+  }
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_term_packed, dim3(nr), dim3(1024), 0, st, runs);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_done(const PackedRun* runs, int nr, int* out, hipStream_t st) {
+  if (nr <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_done, dim3((nr + 255) / 256), dim3(256), 0, st, runs, nr, out);
+  return hipGetLastError();
 }
 
 hipError_t launch_waveform(const ModelDev& M, const ModelDev* Md, const double* theta_dev, int det, int apply_cut,

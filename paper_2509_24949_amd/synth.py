@@ -207,6 +207,68 @@ def workload(name: str, distance: float | None = None) -> Workload:
     raise KeyError(name)
 
 
+# Serving workload: events of uneven duration, network and size.
+SERVING_EVENTS = 64
+SERVING_DURATIONS = (4, 8, 16, 32)            # seconds of data: 4017 ... 32129 bins per detector
+SERVING_NETWORKS = (("H1",), ("H1", "L1"), ("H1", "L1", "V1"))
+SERVING_N_LIVE = (500, 1000, 2000)
+# total mass (solar masses) whose innermost-stable-orbit frequency is 30 Hz;
+# heavier draws are rejected because they leave almost no signal in band
+SERVING_MAX_TOTAL_MASS = 146.6
+
+
+def serving_event(i: int, distance: float | None = None) -> Workload:
+    """Event ``i`` of the serving workload (parameters seeded by 5000+i,
+    noise by 6000+i, sampler by 7000+i).  Duration T in {4, 8, 16, 32} s
+    (grid 20-1024 Hz with df = 1/T), 1-3 detectors, network SNR U[8, 40],
+    Mc U[5, 60], q U[0.125, 1], n_live in {500, 1000, 2000} with
+    n_delete = n_live / 2; chirp-mass prior [0.7, 1.3] Mc clipped to
+    [5, 60], the other priors as the 3-detector workload.  ``distance``
+    overrides the stored SNR-scaled injection distance."""
+    rng = np.random.Generator(np.random.PCG64(5000 + i))
+    T = int(rng.choice(SERVING_DURATIONS))
+    dets = SERVING_NETWORKS[int(rng.integers(0, 3))]
+    snr = float(rng.uniform(8.0, 40.0))
+    while True:
+        mc = float(rng.uniform(5.0, 60.0))
+        q = float(rng.uniform(0.125, 1.0))
+        eta = q / (1.0 + q) ** 2
+        if mc * eta ** -0.6 <= SERVING_MAX_TOTAL_MASS:
+            break
+    n_live = int(rng.choice(SERVING_N_LIVE))
+    chi1, chi2 = (float(x) for x in rng.uniform(-0.5, 0.5, size=2))
+    theta_jn = math.acos(float(rng.uniform(-1.0, 1.0)))
+    psi = float(rng.uniform(0.0, math.pi))
+    ra = float(rng.uniform(0.0, 2.0 * math.pi))
+    dec = math.asin(float(rng.uniform(-1.0, 1.0)))
+    phi_c = float(rng.uniform(0.0, 2.0 * math.pi))
+    if distance is None:
+        stored = _load_injections().get("cfg5", {}).get("distance_mpc", [])
+        distance = stored[i] if i < len(stored) else 0.0
+    d = float(distance)
+    two_pi = 2.0 * math.pi
+    return Workload(
+        name=f"cfg5/{i}", model=MODEL_TF2_11P, likelihood=LIKE_FULL, f_lo=20.0, df=1.0 / T,
+        n_bins=1004 * T + 1, detectors=dets,
+        prior_kind=_kinds(0, 0, 0, 0, 3, 1, 0, 0, 2, 0, 0),
+        prior_lo=np.array([max(5.0, 0.7 * mc), 0.125, -0.8, -0.8, 0.25 * d, 0.0, 0.0, 0.0, -0.5 * math.pi, -0.1, 0.0]),
+        prior_hi=np.array([min(60.0, 1.3 * mc), 1.0, 0.8, 0.8, 3.0 * d, math.pi, math.pi, two_pi, 0.5 * math.pi, 0.1,
+                           two_pi]),
+        theta_inj=np.array([mc, q, chi1, chi2, d, theta_jn, psi, ra, dec, 0.0, phi_c]),
+        noise_seed=6000 + i, snr_target=snr,
+        n_live=n_live, n_delete=n_live // 2, n_steps=55, sampler_seed=7000 + i,
+    )
+
+
+def serving_arrivals(n: int = SERVING_EVENTS, seed: int = 5999) -> np.ndarray:
+    """Arrival times of a unit-rate Poisson process (first arrival at 0);
+    scale by 1/rate for a given arrival rate."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    gaps = rng.exponential(1.0, size=n)
+    gaps[0] = 0.0
+    return np.cumsum(gaps)
+
+
 def gauss_workload(d: int, sigma: float, mu=None, n_live: int = 500, n_delete: int = 250,
                    n_steps: int | None = None, seed: int = 11) -> Workload:
     """Gaussian likelihood N(u; mu, sigma^2 I) inside the unit cube (an evidence test problem)."""

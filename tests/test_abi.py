@@ -74,3 +74,21 @@ def test_select_and_waveform_argument_checks():
     rc = lib.ns_waveform(spec.ref, th.ctypes.data_as(binding._dp), 3, 1, h.ctypes.data_as(binding._dp),
                          h.ctypes.data_as(binding._dp), None)
     assert rc == binding.NS_E_ARG
+
+
+def test_server_argument_checks():
+    lib = binding.lib()
+    out = C.c_void_p()
+    assert lib.ns_server_create(C.byref(out), 0, 0, 0, None) == binding.NS_E_ARG
+    assert b"max_runs" in lib.ns_last_error()
+    assert lib.ns_server_create(C.byref(out), 0, 4, 8, None) == binding.NS_E_ARG
+    assert lib.ns_server_create(C.byref(out), 0, 4, binding.NS_SERVER_GRAPH, None) == binding.NS_E_ARG
+    assert b"null stream" in lib.ns_last_error()
+    assert out.value is None
+    t = C.c_longlong()
+    assert lib.ns_server_submit(None, None, None, C.byref(t)) == binding.NS_E_ARG
+    assert lib.ns_server_tick(None, 1, None, None, None) == binding.NS_E_ARG
+    assert lib.ns_server_poll(None, None, 0, None) == binding.NS_E_ARG
+    assert lib.ns_server_take(None, 1, C.byref(out)) == binding.NS_E_ARG
+    assert lib.ns_server_info(None, None, None, None, None) == binding.NS_E_ARG
+    lib.ns_server_free(None)
