@@ -213,6 +213,26 @@ typedef struct {
 /* Statistics of the profiled iterations (synchronises the stream). */
 NS_API int ns_stats(ns_run* run, ns_stats_t* out);
 
+/* Log-likelihood of the data under the noise-only model (Whittle: in every
+ * bin the real and imaginary parts are Gaussian with variance S/(4 df)),
+ * computed on the device at ns_init.  logZ from ns_logZ plus this value is
+ * the absolute log evidence of the signal model.  NS_E_STATE for the
+ * Gaussian test likelihood. */
+NS_API int ns_noise_loglike(ns_run* run, double* out);
+
+/* Checkpoint: serialise the run (problem, options, live points, evidence
+ * state and dead-point record) into buf[cap].  n_out receives the size;
+ * NS_E_CAPACITY (nothing written) if cap is too small, so a first call with
+ * buf = NULL, cap = 0 asks for the size.  Synchronises the run's stream.
+ * Random numbers are counter-based (iteration, chain, step), so a run
+ * restored with ns_load continues bit-identically to the uninterrupted one. */
+NS_API int ns_save(ns_run* run, void* buf, size_t cap, size_t* n_out);
+
+/* Restore a checkpoint written by ns_save of this library version into a
+ * new run on stream (tables are rebuilt from the stored problem).
+ * NS_E_ARG if buf[size] is not a well-formed checkpoint. */
+NS_API int ns_load(ns_run** out, const void* buf, size_t size, void* stream);
+
 /* Release a run (NULL is allowed). */
 NS_API void ns_free(ns_run* run);
 

@@ -66,6 +66,8 @@ def lib():
         L.orc_tf2_phase.restype = C.c_double
         L.orc_inner.argtypes = [C.c_void_p, C.c_int, _dp, _dp, _dp, _dp]
         L.orc_inner.restype = C.c_double
+        L.orc_noise_loglike.argtypes = [C.c_void_p]
+        L.orc_noise_loglike.restype = C.c_double
         L.orc_loglike_full.argtypes = [C.c_void_p, _dp]
         L.orc_loglike_full.restype = C.c_double
         L.orc_rb_build.argtypes = [C.c_void_p]
@@ -141,6 +143,9 @@ class OracleProblem:
         if rc:
             raise ValueError("orc_waveform failed")
         return hr, hi
+
+    def noise_loglike(self) -> float:
+        return lib().orc_noise_loglike(self.ref)
 
     def inner(self, det, a_re, a_im, b_re, b_im):
         a_re, a_im, b_re, b_im = (np.ascontiguousarray(x, dtype=np.float64) for x in (a_re, a_im, b_re, b_im))

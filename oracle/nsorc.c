@@ -264,6 +264,17 @@ double orc_inner(const orc_problem* p, int det, const double* ar, const double* 
     return 4.0 * p->df * acc;
 }
 
+double orc_noise_loglike(const orc_problem* p) {
+    /* sum over bins of log N(Re; 0, v) + log N(Im; 0, v), v = S / (4 df) */
+    double acc = 0.0;
+    for (long i = 0; i < (long)p->n_det * p->n_bins; ++i) {
+        const double v = p->psd[i] / (4.0 * p->df);
+        const double r2 = p->data_re[i] * p->data_re[i] + p->data_im[i] * p->data_im[i];
+        acc += -log(2.0 * PI * v) - r2 / (2.0 * v);
+    }
+    return acc;
+}
+
 double orc_loglike_full(const orc_problem* p, const double* th) {
     source s;
     make_source(p, th, &s);

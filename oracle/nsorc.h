@@ -75,6 +75,12 @@ double orc_tf2_phase(double f, double mc_msun, double eta, double beta, double s
 double orc_inner(const orc_problem* p, int det, const double* a_re, const double* a_im,
                  const double* b_re, const double* b_im);
 
+/* Log-likelihood of the data under the noise-only model: every bin of every
+ * detector holds a complex Gaussian whose real and imaginary parts each have
+ * variance S_k / (4 df).  Adding it to the log Bayes factor gives the
+ * absolute log evidence of the signal model. */
+double orc_noise_loglike(const orc_problem* p);
+
 /* Log-likelihood ratio lambda(theta) = sum_det <d|h> - 1/2 <h|h>, full grid. */
 double orc_loglike_full(const orc_problem* p, const double* theta);
 

@@ -81,6 +81,9 @@ SIGNATURES = {
     "ns_select": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
     "ns_profile": (C.c_int, [C.c_void_p, C.c_int]),
     "ns_stats": (C.c_int, [C.c_void_p, C.POINTER(Stats)]),
+    "ns_noise_loglike": (C.c_int, [C.c_void_p, _dp]),
+    "ns_save": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.POINTER(C.c_size_t)]),
+    "ns_load": (C.c_int, [C.POINTER(C.c_void_p), C.c_void_p, C.c_size_t, C.c_void_p]),
     "ns_free": (None, [C.c_void_p]),
     "ns_server_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_size_t, C.c_int, C.c_int, C.c_void_p]),
     "ns_server_submit": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_longlong)]),
@@ -288,6 +291,29 @@ class Run:
         out = torch.empty(u.shape[0], dtype=torch.float64, device=u.device)
         _check(lib().ns_loglike(self.h, C.c_void_p(u.data_ptr()), u.shape[0], C.c_void_p(out.data_ptr())))
         return out
+
+    def noise_loglike(self) -> float:
+        v = C.c_double()
+        _check(lib().ns_noise_loglike(self.h, C.byref(v)))
+        return v.value
+
+    def save(self) -> bytes:
+        """ns_save into a bytes object."""
+        n = C.c_size_t()
+        rc = lib().ns_save(self.h, None, 0, C.byref(n))
+        if rc != NS_E_CAPACITY:
+            _check(rc)
+        buf = C.create_string_buffer(n.value)
+        _check(lib().ns_save(self.h, buf, n.value, C.byref(n)))
+        return buf.raw[:n.value]
+
+    @classmethod
+    def load(cls, blob: bytes, spec: ProblemSpec, opts: Opts, stream=None) -> "Run":
+        """ns_load of a checkpoint (spec and opts describe the same run)."""
+        h = C.c_void_p()
+        buf = C.create_string_buffer(blob, len(blob))
+        _check(lib().ns_load(C.byref(h), buf, len(blob), _stream(stream)))
+        return cls.adopt(h, spec, opts)
 
     def profile(self, enable: bool = True):
         _check(lib().ns_profile(self.h, 1 if enable else 0))

@@ -195,6 +195,8 @@ int run_create(ns_run** out, const ns_problem* P, const ns_opts* O, hipStream_t 
   if ((rc = validate_opts(O))) return rc;
   ns_run* r = new (std::nothrow) ns_run();
   if (!r) return fail(NS_E_OOM, "host allocation failed");
+  r->prob.own(*P);
+  r->opts = *O;
   M.mixed = (O->precision == NS_MIXED && M.likelihood != NS_LIKE_GAUSS) ? 1 : 0;
   M.dw_scale = 1.0;
   if (M.mixed && M.likelihood == NS_LIKE_FULL) {
@@ -263,8 +265,13 @@ int run_create(ns_run** out, const ns_problem* P, const ns_opts* O, hipStream_t 
     e = hipMemcpyAsync(dre, P->data_re, nbd * sizeof(double), hipMemcpyHostToDevice, r->st);
     if (e == hipSuccess) e = hipMemcpyAsync(dim, P->data_im, nbd * sizeof(double), hipMemcpyHostToDevice, r->st);
     if (e == hipSuccess) e = hipMemcpyAsync(psd, P->psd, nbd * sizeof(double), hipMemcpyHostToDevice, r->st);
+    double* d_noise = nullptr;
+    ALLOC(d_noise, 1);
     if (e == hipSuccess)
       e = launch_build_tables(M, r->Md, dre, dim, psd, f, f13, lnf3, fm53, dw, hpre, scratch, r->st);
+    if (e == hipSuccess) e = launch_noise_loglike(dre, dim, psd, (long)nbd, M.df, d_noise, r->st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(&r->noise_loglike, d_noise, sizeof(double), hipMemcpyDeviceToHost, r->st);
     if (e == hipSuccess) e = hipStreamSynchronize(r->st);
     r->T.f = f; r->T.f13 = f13; r->T.lnf3 = lnf3; r->T.fm53 = fm53; r->T.dw = dw; r->T.hpre = hpre;
     if (e == hipSuccess && M.mixed && M.likelihood == NS_LIKE_FULL) {
@@ -565,6 +572,208 @@ int ns_select(const double* logl_dev, int n, int k, int* dead_dev, double* lstar
   if (!logl_dev || !dead_dev) return fail(NS_E_ARG, "NULL argument");
   if (n < 1 || n > 16384 || k < 1 || k > n) return fail(NS_E_ARG, "need 1 <= k <= n <= 16384");
   HIP_OK(launch_select(logl_dev, n, k, nullptr, dead_dev, lstar_dev, nullptr, static_cast<hipStream_t>(stream)));
+  return NS_OK;
+}
+
+int ns_noise_loglike(ns_run* r, double* out) {
+  if (!r || !out) return fail(NS_E_ARG, "NULL argument");
+  if (r->M.likelihood == NS_LIKE_GAUSS) return fail(NS_E_STATE, "the Gaussian test likelihood has no noise model");
+  *out = r->noise_loglike;
+  return NS_OK;
+}
+
+}  // extern "C"
+
+// ---- checkpoint format ------------------------------------------------------
+namespace {
+
+constexpr char kMagic[8] = {'N', 'S', 'R', 'U', 'N', 'v', '1', '\0'};
+
+struct Writer {
+  unsigned char* buf;
+  size_t cap, n = 0;
+  void raw(const void* p, size_t b) {
+    if (buf && n + b <= cap) memcpy(buf + n, p, b);
+    n += b;
+  }
+  template <typename T>
+  void val(const T& v) { raw(&v, sizeof(T)); }
+  template <typename T>
+  void vec(const std::vector<T>& v) {
+    val<uint64_t>(v.size());
+    raw(v.data(), v.size() * sizeof(T));
+  }
+};
+
+struct Reader {
+  const unsigned char* buf;
+  size_t size, n = 0;
+  bool ok = true;
+  void raw(void* p, size_t b) {
+    if (!ok || b > size - n) { ok = false; return; }
+    memcpy(p, buf + n, b);
+    n += b;
+  }
+  template <typename T>
+  T val() { T v{}; raw(&v, sizeof(T)); return v; }
+  template <typename T>
+  std::vector<T> vec(size_t max_count) {
+    const uint64_t c = val<uint64_t>();
+    std::vector<T> v;
+    if (!ok || c > max_count || c * sizeof(T) > size - n) { ok = false; return v; }
+    v.resize(c);
+    raw(v.data(), c * sizeof(T));
+    return v;
+  }
+};
+
+// Problem scalars stored in a checkpoint (pointers are written as arrays).
+struct ProblemScalars {
+  int model, likelihood, n_dim, n_bins, n_det, rb_n_bins;
+  double f_lo, df, gmst, fixed_dist_mpc, gauss_sigma;
+};
+
+}  // namespace
+
+extern "C" {
+
+int ns_save(ns_run* r, void* buf, size_t cap, size_t* n_out) {
+  if (!r) return fail(NS_E_ARG, "run is NULL");
+  int rc = sync_state(r);
+  if (rc) return rc;
+  const RunDev& R = r->R;
+  const DevState st = *r->h_state;
+  const size_t nd = (size_t)st.n_dead;
+  std::vector<double> u((size_t)R.n * R.d), lam(R.n), du(nd * R.d), dlam(nd), dlogx(nd), dlogw(nd);
+  std::vector<int> diter(nd), dslot(nd), dnlive(nd);
+  const bool fetch = buf != nullptr;
+  Writer w{nullptr, 0};   // the first pass only measures
+  const ns_problem& P = r->prob.P;
+  ProblemScalars ps{P.model, P.likelihood, P.n_dim, P.n_bins, P.n_det, P.rb_n_bins,
+                    P.f_lo, P.df, P.gmst, P.fixed_dist_mpc, P.gauss_sigma};
+  // size first: the record is written only if it fits
+  for (int pass = 0; pass < 2; ++pass) {
+    if (pass == 1) {
+      if (!fetch || w.n > cap) break;
+      HIP_OK(hipMemcpyAsync(u.data(), R.u, u.size() * sizeof(double), hipMemcpyDeviceToHost, r->st));
+      HIP_OK(hipMemcpyAsync(lam.data(), R.lam, lam.size() * sizeof(double), hipMemcpyDeviceToHost, r->st));
+      if (nd) {
+        HIP_OK(hipMemcpyAsync(du.data(), R.du, du.size() * sizeof(double), hipMemcpyDeviceToHost, r->st));
+        HIP_OK(hipMemcpyAsync(dlam.data(), R.dlam, nd * sizeof(double), hipMemcpyDeviceToHost, r->st));
+        HIP_OK(hipMemcpyAsync(dlogx.data(), R.dlogx, nd * sizeof(double), hipMemcpyDeviceToHost, r->st));
+        HIP_OK(hipMemcpyAsync(dlogw.data(), R.dlogw, nd * sizeof(double), hipMemcpyDeviceToHost, r->st));
+        HIP_OK(hipMemcpyAsync(diter.data(), R.diter, nd * sizeof(int), hipMemcpyDeviceToHost, r->st));
+        HIP_OK(hipMemcpyAsync(dslot.data(), R.dslot, nd * sizeof(int), hipMemcpyDeviceToHost, r->st));
+        HIP_OK(hipMemcpyAsync(dnlive.data(), R.dnlive, nd * sizeof(int), hipMemcpyDeviceToHost, r->st));
+      }
+      HIP_OK(hipStreamSynchronize(r->st));
+      w = Writer{static_cast<unsigned char*>(buf), cap};
+    }
+    w.raw(kMagic, sizeof kMagic);
+    w.val<int>(r->packed ? 1 : 0);
+    w.val(ps);
+    w.val(r->opts);
+    w.vec(r->prob.kind);
+    w.vec(r->prob.lo);
+    w.vec(r->prob.hi);
+    w.vec(r->prob.dre);
+    w.vec(r->prob.dim);
+    w.vec(r->prob.psd);
+    w.vec(r->prob.geom);
+    w.vec(r->prob.fid);
+    w.vec(r->prob.mu);
+    w.val(st);
+    w.vec(u);
+    w.vec(lam);
+    w.vec(du);
+    w.vec(dlam);
+    w.vec(dlogx);
+    w.vec(dlogw);
+    w.vec(diter);
+    w.vec(dslot);
+    w.vec(dnlive);
+  }
+  if (n_out) *n_out = w.n;
+  if (!buf || w.n > cap) return fail(NS_E_CAPACITY, "the checkpoint needs %zu bytes, cap is %zu", w.n, buf ? cap : 0);
+  return NS_OK;
+}
+
+int ns_load(ns_run** out, const void* buf, size_t size, void* stream) {
+  if (!out || !buf) return fail(NS_E_ARG, "NULL argument");
+  *out = nullptr;
+  Reader rd{static_cast<const unsigned char*>(buf), size};
+  char magic[8];
+  rd.raw(magic, sizeof magic);
+  if (!rd.ok || memcmp(magic, kMagic, sizeof magic) != 0) return fail(NS_E_ARG, "not a run checkpoint");
+  const int packed = rd.val<int>();
+  const ProblemScalars ps = rd.val<ProblemScalars>();
+  const ns_opts O = rd.val<ns_opts>();
+  if (!rd.ok) return fail(NS_E_ARG, "truncated checkpoint");
+  const size_t big = size / sizeof(double) + 1;
+  ProblemCopy pc;
+  pc.kind = rd.vec<int>(MAX_DIM);
+  pc.lo = rd.vec<double>(MAX_DIM);
+  pc.hi = rd.vec<double>(MAX_DIM);
+  pc.dre = rd.vec<double>(big);
+  pc.dim = rd.vec<double>(big);
+  pc.psd = rd.vec<double>(big);
+  pc.geom = rd.vec<double>(9 * MAX_DET);
+  pc.fid = rd.vec<double>(MAX_DIM);
+  pc.mu = rd.vec<double>(MAX_DIM);
+  const DevState st = rd.val<DevState>();
+  auto u = rd.vec<double>(big), lam = rd.vec<double>(big), du = rd.vec<double>(big), dlam = rd.vec<double>(big),
+       dlogx = rd.vec<double>(big), dlogw = rd.vec<double>(big);
+  auto diter = rd.vec<int>(big), dslot = rd.vec<int>(big), dnlive = rd.vec<int>(big);
+  if (!rd.ok || rd.n != size) return fail(NS_E_ARG, "malformed checkpoint");
+  ns_problem P{};
+  P.model = ps.model; P.likelihood = ps.likelihood; P.n_dim = ps.n_dim; P.n_bins = ps.n_bins; P.n_det = ps.n_det;
+  P.rb_n_bins = ps.rb_n_bins; P.f_lo = ps.f_lo; P.df = ps.df; P.gmst = ps.gmst;
+  P.fixed_dist_mpc = ps.fixed_dist_mpc; P.gauss_sigma = ps.gauss_sigma;
+  const size_t nd = (size_t)std::max(ps.n_dim, 0);
+  const size_t nbd = ps.likelihood == NS_LIKE_GAUSS ? 0 : (size_t)std::max(ps.n_det, 0) * std::max(ps.n_bins, 0);
+  if (pc.kind.size() != nd || pc.lo.size() != nd || pc.hi.size() != nd || pc.dre.size() != nbd ||
+      pc.dim.size() != nbd || pc.psd.size() != nbd)
+    return fail(NS_E_ARG, "checkpoint arrays do not match the problem sizes");
+  P.prior_kind = pc.kind.data(); P.prior_lo = pc.lo.data(); P.prior_hi = pc.hi.data();
+  P.data_re = nbd ? pc.dre.data() : nullptr;
+  P.data_im = nbd ? pc.dim.data() : nullptr;
+  P.psd = nbd ? pc.psd.data() : nullptr;
+  P.det_geom = pc.geom.empty() ? nullptr : pc.geom.data();
+  P.rb_fiducial = pc.fid.empty() ? nullptr : pc.fid.data();
+  P.gauss_mu = pc.mu.empty() ? nullptr : pc.mu.data();
+  if (P.det_geom && pc.geom.size() != 9 * (size_t)P.n_det) return fail(NS_E_ARG, "checkpoint detector geometry size");
+  if (P.rb_fiducial && pc.fid.size() != nd) return fail(NS_E_ARG, "checkpoint fiducial size");
+  if (P.gauss_mu && pc.mu.size() != nd) return fail(NS_E_ARG, "checkpoint Gaussian mean size");
+  const size_t n = (size_t)std::max(O.n_live, 0), d = nd;
+  const long long ndead = st.n_dead;
+  if (ndead < 0 || u.size() != n * d || lam.size() != n || du.size() != (size_t)ndead * d ||
+      dlam.size() != (size_t)ndead || dlogx.size() != (size_t)ndead || dlogw.size() != (size_t)ndead ||
+      diter.size() != (size_t)ndead || dslot.size() != (size_t)ndead || dnlive.size() != (size_t)ndead ||
+      ndead > (long long)O.max_iter * O.n_delete)
+    return fail(NS_E_ARG, "checkpoint state does not match the run sizes");
+  ns_run* r = nullptr;
+  int rc = run_create(&r, &P, &O, static_cast<hipStream_t>(stream), packed != 0);
+  if (rc) return rc;
+  const RunDev& R = r->R;
+  *r->h_state = st;
+  hipError_t e = hipMemcpyAsync(R.state, r->h_state, sizeof(DevState), hipMemcpyHostToDevice, r->st);
+  if (e == hipSuccess) e = hipMemcpyAsync(R.u, u.data(), u.size() * sizeof(double), hipMemcpyHostToDevice, r->st);
+  if (e == hipSuccess) e = hipMemcpyAsync(R.lam, lam.data(), n * sizeof(double), hipMemcpyHostToDevice, r->st);
+  if (e == hipSuccess && ndead) {
+    e = hipMemcpyAsync(R.du, du.data(), du.size() * sizeof(double), hipMemcpyHostToDevice, r->st);
+    if (e == hipSuccess) e = hipMemcpyAsync(R.dlam, dlam.data(), ndead * sizeof(double), hipMemcpyHostToDevice, r->st);
+    if (e == hipSuccess) e = hipMemcpyAsync(R.dlogx, dlogx.data(), ndead * sizeof(double), hipMemcpyHostToDevice, r->st);
+    if (e == hipSuccess) e = hipMemcpyAsync(R.dlogw, dlogw.data(), ndead * sizeof(double), hipMemcpyHostToDevice, r->st);
+    if (e == hipSuccess) e = hipMemcpyAsync(R.diter, diter.data(), ndead * sizeof(int), hipMemcpyHostToDevice, r->st);
+    if (e == hipSuccess) e = hipMemcpyAsync(R.dslot, dslot.data(), ndead * sizeof(int), hipMemcpyHostToDevice, r->st);
+    if (e == hipSuccess) e = hipMemcpyAsync(R.dnlive, dnlive.data(), ndead * sizeof(int), hipMemcpyHostToDevice, r->st);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(r->st);
+  if (e != hipSuccess) {
+    ns_free(r);
+    return fail(NS_E_HIP, "restoring the checkpoint: %s", hipGetErrorString(e));
+  }
+  *out = r;
   return NS_OK;
 }
 

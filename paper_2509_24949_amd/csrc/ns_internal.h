@@ -115,6 +115,11 @@ struct PackedRun {
 hipError_t launch_build_tables(const ModelDev& M, const ModelDev* Md, const double* data_re, const double* data_im,
                                const double* psd, double* f, double* f13, double* lnf3, double* fm53, double2* dw,
                                double* hpre, double* scratch, hipStream_t st);
+// Log-likelihood of the data under the noise-only model into out[0]
+// (device): sum over the n values of the Gaussian log-densities of the real
+// and imaginary parts, each of variance psd / (4 df).
+hipError_t launch_noise_loglike(const double* dre, const double* dim, const double* psd, long n, double df,
+                                double* out, hipStream_t st);
 hipError_t launch_init_live(const RunDev& R, hipStream_t st);
 hipError_t launch_loglike(const ModelDev& M, const ModelDev* Md, const Tables& T, const RBTables& RB,
                           const double* u, long n, double* out, hipStream_t st);

@@ -526,6 +526,19 @@ __global__ __launch_bounds__(64) void k_loglike_rb(const ModelDev* __restrict__ 
 }
 
 // Float copies for the mixed form.
+__global__ __launch_bounds__(1024) void k_noise_loglike(const double* __restrict__ dre, const double* __restrict__ dim,
+                                                       const double* __restrict__ psd, long n, double df,
+                                                       double* out) {
+  __shared__ double sbuf[1024];
+  double acc = 0.0;
+  for (long i = threadIdx.x; i < n; i += 1024) {
+    const double v = psd[i] / (4.0 * df);
+    acc += -log(2.0 * PI * v) - (dre[i] * dre[i] + dim[i] * dim[i]) / (2.0 * v);
+  }
+  acc = block_sum<1024>(acc, sbuf);
+  if (threadIdx.x == 0) *out = acc;
+}
+
 __global__ void k_to_float2(const double2* src, float2* dst, size_t n, double scale) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) dst[i] = make_float2((float)(src[i].x * scale), (float)(src[i].y * scale));
@@ -1414,6 +1427,12 @@ hipError_t launch_build_tables(const ModelDev& M, const ModelDev* Md, const doub
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_prefix_rows, dim3(M.n_det), dim3(1024), 0, st, scratch, hpre, M.n_bins);
+  return hipGetLastError();
+}
+
+hipError_t launch_noise_loglike(const double* dre, const double* dim, const double* psd, long n, double df,
+                                double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_noise_loglike, dim3(1), dim3(1024), 0, st, dre, dim, psd, n, df, out);
   return hipGetLastError();
 }
 

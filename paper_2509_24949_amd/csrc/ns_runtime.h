@@ -39,6 +39,47 @@ struct DevMem {
   }
 };
 
+// A problem with private copies of every host array it references.
+struct ProblemCopy {
+  ns_problem P{};
+  std::vector<int> kind;
+  std::vector<double> lo, hi, dre, dim, psd, geom, fid, mu;
+
+  // p must have passed validation (array lengths follow from its sizes).
+  void own(const ns_problem& p) {
+    P = p;
+    const size_t nd = p.n_dim;
+    const size_t nbd = p.likelihood == NS_LIKE_GAUSS ? 0 : (size_t)p.n_det * p.n_bins;
+    kind.assign(p.prior_kind, p.prior_kind + nd);
+    lo.assign(p.prior_lo, p.prior_lo + nd);
+    hi.assign(p.prior_hi, p.prior_hi + nd);
+    P.prior_kind = kind.data();
+    P.prior_lo = lo.data();
+    P.prior_hi = hi.data();
+    P.data_re = P.data_im = P.psd = P.det_geom = P.rb_fiducial = P.gauss_mu = nullptr;
+    if (nbd) {
+      dre.assign(p.data_re, p.data_re + nbd);
+      dim.assign(p.data_im, p.data_im + nbd);
+      psd.assign(p.psd, p.psd + nbd);
+      P.data_re = dre.data();
+      P.data_im = dim.data();
+      P.psd = psd.data();
+    }
+    if (p.likelihood != NS_LIKE_GAUSS && p.model == NS_MODEL_TF2_11P && p.det_geom) {
+      geom.assign(p.det_geom, p.det_geom + 9 * (size_t)p.n_det);
+      P.det_geom = geom.data();
+    }
+    if (p.likelihood == NS_LIKE_RB && p.rb_fiducial) {
+      fid.assign(p.rb_fiducial, p.rb_fiducial + nd);
+      P.rb_fiducial = fid.data();
+    }
+    if (p.likelihood == NS_LIKE_GAUSS && p.gauss_mu) {
+      mu.assign(p.gauss_mu, p.gauss_mu + nd);
+      P.gauss_mu = mu.data();
+    }
+  }
+};
+
 int validate_and_model(const ns_problem* P, ModelDev* M);
 int validate_opts(const ns_opts* o);
 
@@ -58,6 +99,9 @@ struct ns_run {
   ns::LaunchCfg C{};
   hipStream_t st = nullptr;
   bool packed = false;               // launch configuration of the packed serving kernels
+  ns::ProblemCopy prob;              // the problem as given (for ns_save)
+  ns_opts opts{};
+  double noise_loglike = 0.0;        // log-likelihood of the data under the noise-only model
   ns::DevMem mem;
   ns::DevState* h_state = nullptr;   // pinned mirror of the device scalars
   bool profiling = false;

@@ -31,42 +31,11 @@ int lk_of(const ModelDev& M) {
 // A submitted request with private copies of every host array it references.
 struct Request {
   long long ticket = 0;
-  ns_problem P{};
+  ProblemCopy prob;
   ns_opts O{};
-  std::vector<int> kind;
-  std::vector<double> lo, hi, dre, dim, psd, geom, fid;
   size_t resident = 0, transient = 0;
   double t_submit = 0.0;
   int bypassed = 0;
-
-  void own(const ns_problem& p, const ns_opts& o) {
-    P = p;
-    O = o;
-    const size_t nd = P.n_dim, nbd = (size_t)P.n_det * P.n_bins;
-    kind.assign(p.prior_kind, p.prior_kind + nd);
-    lo.assign(p.prior_lo, p.prior_lo + nd);
-    hi.assign(p.prior_hi, p.prior_hi + nd);
-    dre.assign(p.data_re, p.data_re + nbd);
-    dim.assign(p.data_im, p.data_im + nbd);
-    psd.assign(p.psd, p.psd + nbd);
-    P.prior_kind = kind.data();
-    P.prior_lo = lo.data();
-    P.prior_hi = hi.data();
-    P.data_re = dre.data();
-    P.data_im = dim.data();
-    P.psd = psd.data();
-    if (p.det_geom) {
-      geom.assign(p.det_geom, p.det_geom + 9 * (size_t)P.n_det);
-      P.det_geom = geom.data();
-    }
-    if (p.rb_fiducial && p.likelihood == NS_LIKE_RB) {
-      fid.assign(p.rb_fiducial, p.rb_fiducial + nd);
-      P.rb_fiducial = fid.data();
-    } else {
-      P.rb_fiducial = nullptr;
-    }
-    P.gauss_mu = nullptr;
-  }
 };
 
 struct Resident {
@@ -155,7 +124,7 @@ int admit(ns_server* s) {
     if (head_blocked) s->queue.front()->bypassed += 1;
     ns_run* r = nullptr;
     const double ta = s->now();
-    const int rc = run_create(&r, &q.P, &q.O, s->st, true);
+    const int rc = run_create(&r, &q.prob.P, &q.O, s->st, true);
     if (rc != NS_OK) {
       Finished f{};
       f.info.ticket = q.ticket;
@@ -292,7 +261,8 @@ int ns_server_submit(ns_server* s, const ns_problem* P, const ns_opts* O, long l
   if (q->resident + q->transient > s->budget)
     return fail(NS_E_OOM, "the run needs %zu device bytes, the server's budget is %zu", q->resident + q->transient,
                 s->budget);
-  q->own(*P, *O);
+  q->prob.own(*P);
+  q->O = *O;
   q->ticket = s->next_ticket++;
   q->t_submit = s->now();
   if (ticket) *ticket = q->ticket;

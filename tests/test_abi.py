@@ -92,3 +92,19 @@ def test_server_argument_checks():
     assert lib.ns_server_take(None, 1, C.byref(out)) == binding.NS_E_ARG
     assert lib.ns_server_info(None, None, None, None, None) == binding.NS_E_ARG
     lib.ns_server_free(None)
+
+
+def test_checkpoint_argument_checks():
+    lib = binding.lib()
+    out = C.c_void_p()
+    n = C.c_size_t()
+    assert lib.ns_save(None, None, 0, C.byref(n)) == binding.NS_E_ARG
+    assert lib.ns_load(C.byref(out), None, 0, None) == binding.NS_E_ARG
+    junk = C.create_string_buffer(b"not a checkpoint at all", 23)
+    assert lib.ns_load(C.byref(out), junk, 23, None) == binding.NS_E_ARG
+    assert b"checkpoint" in lib.ns_last_error()
+    head = C.create_string_buffer(b"NSRUNv1\x00" + b"\x01" * 12, 20)
+    assert lib.ns_load(C.byref(out), head, 20, None) == binding.NS_E_ARG
+    assert out.value is None
+    v = C.c_double()
+    assert lib.ns_noise_loglike(None, C.byref(v)) == binding.NS_E_ARG

@@ -1,0 +1,85 @@
+"""Checkpoint and resume, and the noise-model constant, through the C ABI.
+
+Bars: a run restored from a checkpoint continues bit-identically to the
+uninterrupted run (the random numbers are counter-based); the noise-model
+log-likelihood equals the oracle's to 1e-12 relative.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2509_24949_amd import binding, synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    binding.lib()
+    return torch
+
+
+def _record(run):
+    d = run.dead()
+    st = run.state()
+    u, l = run.live()
+    return dict(d, live_u=u, live_l=l, logZ=st["logZ"], H=st["H"], logX=st["logX"], n_evals=st["n_evals"],
+                iterations=st["iter"], done=st["done"], final=run.logZ(200))
+
+
+def _identical(a, b):
+    for key in ("u", "logl", "logx", "logw", "iter", "slot", "live_u", "live_l"):
+        np.testing.assert_array_equal(a[key], b[key], err_msg=key)
+    for key in ("logZ", "H", "logX", "n_evals", "iterations", "done", "final"):
+        assert a[key] == b[key], key
+
+
+@pytest.mark.parametrize("name,first,then", [("cfg1", 5, 200), ("cfg3", 2, 2), ("cfg4", 1, 2)])
+def test_resume_is_bit_identical(torch_cuda, name, first, then):
+    w = synth.workload(name)
+    re, im = binding.make_data(w)
+    spec = binding.ProblemSpec(w, re, im)
+    opts = binding.opts_for(w, max_iter=first + then)
+    a = binding.Run(spec, opts)
+    a.step(first)
+    blob = a.save()
+    a.step(then)
+    ra = _record(a)
+    a.close()
+    b = binding.Run.load(blob, spec, opts)
+    assert b.state()["iter"] == first
+    b.step(then)
+    _identical(ra, _record(b))
+    # a checkpoint of the finished run restores the same evidence
+    blob2 = b.save()
+    c = binding.Run.load(blob2, spec, opts)
+    _identical(ra, _record(c))
+    b.close()
+    c.close()
+
+
+def test_truncated_checkpoint_is_rejected(torch_cuda):
+    w = synth.workload("cfg1")
+    spec = binding.ProblemSpec(w, *binding.make_data(w))
+    opts = binding.opts_for(w)
+    a = binding.Run(spec, opts)
+    a.step(2)
+    blob = a.save()
+    a.close()
+    with pytest.raises(binding.NSError) as e:
+        binding.Run.load(blob[:-8], spec, opts)
+    assert e.value.code == binding.NS_E_ARG
+
+
+@pytest.mark.parametrize("name", ["cfg1", "cfg2"])
+def test_noise_loglike_parity(torch_cuda, name):
+    w = synth.workload(name)
+    re, im = oracle.make_data(w)
+    want = oracle.OracleProblem(w, re, im).noise_loglike()
+    r = binding.Run(binding.ProblemSpec(w, re, im), binding.opts_for(w))
+    got = r.noise_loglike()
+    r.close()
+    assert abs(got - want) <= 1e-12 * abs(want)

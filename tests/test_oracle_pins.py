@@ -242,6 +242,31 @@ def test_noise_only_gamma():
     assert stats.kstest(vals, stats.gamma(w.n_bins).cdf).pvalue > 1e-3
 
 
+def test_noise_loglike_is_the_gaussian_density():
+    """The noise-model log-likelihood equals the sum of scipy's normal
+    log-densities of every real and imaginary part (variance S/(4 df)),
+    and the absolute signal log-likelihood (noise term plus lambda) equals
+    the same density of the residual d - h (catches a dropped 1/2, a wrong
+    variance or a missing detector)."""
+    w = synth.workload("cfg2")
+    re, im = oracle.make_data(w)
+    p = oracle.OracleProblem(w, re, im)
+    sd = np.sqrt(w.psd() / (4.0 * w.df))
+    ref = float(np.sum(stats.norm.logpdf(re, scale=sd)) + np.sum(stats.norm.logpdf(im, scale=sd)))
+    got = p.noise_loglike()
+    assert abs(got - ref) <= 1e-11 * abs(ref)
+    th = np.array(w.theta_inj, dtype=np.float64)
+    th[0] += 0.01
+    lam = p.loglike_theta(th)
+    rr, ri = re.copy(), im.copy()
+    for det in range(w.n_det):
+        hr, hi = p.waveform(th, det, cut=True)
+        rr[det] -= hr
+        ri[det] -= hi
+    ref_sig = float(np.sum(stats.norm.logpdf(rr, scale=sd)) + np.sum(stats.norm.logpdf(ri, scale=sd)))
+    assert abs((got + lam) - ref_sig) <= 1e-9 * abs(ref_sig)
+
+
 def test_zero_signal_limit():
     """As the distance grows the signal vanishes and lambda -> 0 like 1/D."""
     w = synth.workload("cfg2")
