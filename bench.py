@@ -101,7 +101,7 @@ def _pct(x, q):
     return float(np.percentile(np.asarray(x, dtype=float), q))
 
 
-def serving(args):
+def serving(args) -> dict:
     """Serving benchmark: the events run one at a time (service times), then
     arrive as a Poisson process at twice the sequential service rate and are
     served by the packed scheduler.  Time-to-posterior runs from an event's
@@ -239,7 +239,40 @@ def serving(args):
                      "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": None},
     }
-    print(json.dumps(out), flush=True)
+    return out
+
+
+def standalone_loglike(w, spec, n_probes: int = 65536, reps: int = 20) -> dict:
+    """The fused waveform-plus-likelihood kernel alone on a batch of probes,
+    half prior draws and half around the injection; HIP events on the
+    stream the kernel runs on."""
+    import torch
+
+    from paper_2509_24949_amd import binding, synth
+
+    r = binding.Run(spec, binding.opts_for(w, max_iter=2))
+    u = torch.from_numpy(synth.proposal_batch(w, n_probes, seed=77)).cuda()
+    out = torch.empty(n_probes, dtype=torch.float64, device="cuda")
+    terms = torch.zeros(n_probes, dtype=torch.int32, device="cuda")
+    r.loglike(u, out, terms)
+    for _ in range(3):
+        r.loglike(u, out)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        r.loglike(u, out)
+    b.record()
+    torch.cuda.synchronize()
+    launch_s = a.elapsed_time(b) / reps * 1e-3
+    n_terms = int(terms.sum().item())
+    r.close()
+    flops = n_terms * flops_per_term(w)
+    peak = FP32_PEAK_TFLOPS if w.precision == 1 else FP64_PEAK_TFLOPS
+    achieved = flops / launch_s / 1e12
+    return {"kernel": "k_loglike_rb" if w.likelihood == 1 else "k_loglike", "probes": n_probes,
+            "probe_mix": "half prior draws, half Gaussian (0.02) around the injection in the unit cube",
+            "evals_per_s": n_probes / launch_s, "launch_ms": launch_s * 1e3, "terms_per_launch": n_terms,
+            "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak}
 
 
 def main():
@@ -251,9 +284,11 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-run", action="store_true", help="skip the complete-run timing")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving summary")
+    ap.add_argument("--no-standalone", action="store_true", help="skip the standalone likelihood kernel")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "slice_kernel_traffic.json"))
     ap.add_argument("--events", type=int, default=64, help="serving: number of events")
-    ap.add_argument("--max-runs", type=int, default=8, help="serving: resident-run slots")
+    ap.add_argument("--max-runs", type=int, default=16, help="serving: resident-run slots")
     ap.add_argument("--tick-iters", type=int, default=1, help="serving: iterations per tick")
     ap.add_argument("--graph", action="store_true", help="serving: replay ticks from a captured graph")
     ap.add_argument("--load", type=float, default=2.0, help="serving: arrival rate / sequential service rate")
@@ -288,7 +323,7 @@ def main():
     torch.cuda.set_device(0)
     binding.lib()
     if args.workload == "cfg5":
-        serving(args)
+        print(json.dumps(serving(args)), flush=True)
         return
     w = synth.workload(args.workload)
     log(f"bench: workload {args.workload}: building data (library-injected waveform)")
@@ -368,6 +403,15 @@ def main():
                      "bin_terms_per_launch": bins_timed / K},
         **run_info,
     }
+    if not args.no_standalone:
+        out["standalone_loglike"] = standalone_loglike(w, spec)
+        log(f"bench: standalone likelihood: {out['standalone_loglike']['evals_per_s'] / 1e6:.0f} M evals/s, "
+            f"{out['standalone_loglike']['frac'] * 100:.1f}% of peak")
+    if not args.no_serving and args.workload == "cfg2":
+        sv = serving(args)
+        out["serving"] = {k: sv[k] for k in ("value", "unit", "latency_p50_s", "latency_p99_s", "makespan_s",
+                                             "evals_per_s", "sequential", "logZ_served_vs_sequential")}
+        out["serving"]["config"] = sv["config"]
     if not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)
         log(f"bench: timing the oracle on {threads} host threads for about {args.cpu_seconds:.0f} s")

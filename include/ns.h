@@ -173,10 +173,13 @@ NS_API int ns_dead(ns_run* run, long cap, double* u, double* logl, double* logx,
             long* n_out);
 
 /* Batched likelihood with the run's tables: out[i] = lambda(u[i]).
- * u_dev: device [n][n_dim] unit-cube points; out_dev: device [n].  Launched
- * on the run's stream, asynchronous.  This is the fused waveform-plus-
- * likelihood kernel the slice chains call, exposed for direct use. */
-NS_API int ns_loglike(ns_run* run, const double* u_dev, long n, double* out_dev);
+ * u_dev: device [n][n_dim] unit-cube points; out_dev: device [n];
+ * terms_dev (may be NULL): device [n] receives the terms each probe costs
+ * (full grid: its active bins k with f_k <= f_ISCO; relative binning: the
+ * nb + 1 edges; Gaussian: 0).  Launched on the run's stream, asynchronous.
+ * This is the fused waveform-plus-likelihood kernel the slice chains call,
+ * exposed for direct use. */
+NS_API int ns_loglike(ns_run* run, const double* u_dev, long n, double* out_dev, int* terms_dev);
 
 /* Detector strain h_det(f_k) of the problem's model at physical parameters
  * theta (host [n_dim]) on the problem's grid, computed on the device.

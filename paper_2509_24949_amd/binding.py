@@ -76,7 +76,7 @@ SIGNATURES = {
     "ns_state": (C.c_int, [C.c_void_p, _dp, _dp, _dp, _ip, _lp, _lp, _ip]),
     "ns_live": (C.c_int, [C.c_void_p, _dp, _dp]),
     "ns_dead": (C.c_int, [C.c_void_p, C.c_long, _dp, _dp, _dp, _dp, _ip, _ip, _lp]),
-    "ns_loglike": (C.c_int, [C.c_void_p, C.c_void_p, C.c_long, C.c_void_p]),
+    "ns_loglike": (C.c_int, [C.c_void_p, C.c_void_p, C.c_long, C.c_void_p, C.c_void_p]),
     "ns_waveform": (C.c_int, [C.c_void_p, _dp, C.c_int, C.c_int, _dp, _dp, C.c_void_p]),
     "ns_select": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
     "ns_profile": (C.c_int, [C.c_void_p, C.c_int]),
@@ -284,12 +284,21 @@ class Run:
         _check(lib().ns_samples(self.h, tot, _d(th), _d(l), _d(lw), C.byref(n_out)))
         return th, l, lw
 
-    def loglike(self, u):
-        """ns_loglike on a CUDA float64 tensor [n, n_dim]; returns a tensor [n]."""
+    def loglike(self, u, out=None, terms=None):
+        """ns_loglike on a CUDA float64 tensor [n, n_dim]; returns the tensor
+        [n] of log-likelihoods (written into ``out`` when given).  ``terms``:
+        an optional CUDA int32 tensor [n] that receives each probe's terms."""
         import torch
         assert u.is_cuda and u.dtype == torch.float64 and u.is_contiguous()
-        out = torch.empty(u.shape[0], dtype=torch.float64, device=u.device)
-        _check(lib().ns_loglike(self.h, C.c_void_p(u.data_ptr()), u.shape[0], C.c_void_p(out.data_ptr())))
+        n = u.shape[0]
+        if out is None:
+            out = torch.empty(n, dtype=torch.float64, device=u.device)
+        assert out.is_cuda and out.dtype == torch.float64 and out.numel() >= n
+        tp = None
+        if terms is not None:
+            assert terms.is_cuda and terms.dtype == torch.int32 and terms.numel() >= n
+            tp = C.c_void_p(terms.data_ptr())
+        _check(lib().ns_loglike(self.h, C.c_void_p(u.data_ptr()), n, C.c_void_p(out.data_ptr()), tp))
         return out
 
     def noise_loglike(self) -> float:

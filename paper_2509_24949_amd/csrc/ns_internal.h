@@ -121,8 +121,10 @@ hipError_t launch_build_tables(const ModelDev& M, const ModelDev* Md, const doub
 hipError_t launch_noise_loglike(const double* dre, const double* dim, const double* psd, long n, double df,
                                 double* out, hipStream_t st);
 hipError_t launch_init_live(const RunDev& R, hipStream_t st);
+// Batched likelihood; terms (optional, device [n]) receives each probe's
+// counted terms (full grid: active bins; relative binning: edges; Gaussian: 0).
 hipError_t launch_loglike(const ModelDev& M, const ModelDev* Md, const Tables& T, const RBTables& RB,
-                          const double* u, long n, double* out, hipStream_t st);
+                          const double* u, long n, double* out, int* terms, hipStream_t st);
 hipError_t launch_select(const double* lam, int n, int k, int* rank, int* dead, double* lstar, const int* done,
                          hipStream_t st);
 // ev (optional): five events recorded before select, after select, after
@@ -149,16 +151,18 @@ hipError_t launch_build_rb_edges(const ModelDev* Md, int nb, const RBBuffers& B,
 hipError_t launch_build_rb_sums(const ModelDev& M, const ModelDev* Md, const Tables& T, const double* hw,
                                 const double* theta_fid_dev, int nb, const RBBuffers& B, hipStream_t st);
 hipError_t configure_slice(const ModelDev& M, int rb_nb, LaunchCfg* C);
-// Chain-kernel set-up of runs that take part in packed launches: 256
-// threads per chain, tables read from HBM/L2 (as in the packed kernel).
+// Chain-kernel set-up of runs that take part in packed launches: 128
+// threads per chain (64 or 256 through NS_PACKED_THREADS, for tuning),
+// tables read through the caches (as in the packed kernel).
 hipError_t configure_slice_packed(const ModelDev& M, int rb_nb, LaunchCfg* C);
 // One iteration of every run in `runs` (device array of nr descriptors):
 // packed selection (rank_off: prefix of ceil(n_r/4) blocks), preparation,
 // chain kernel (slice_off: prefix of k_r blocks) and termination.  lk is the
-// shared likelihood kind (LK_FULL, LK_FULL32, LK_RB or LK_RB32), max_n the
-// largest n_live, slice_lds the largest chain-kernel LDS of the runs.
+// shared likelihood kind (LK_FULL, LK_FULL32, LK_RB or LK_RB32), nt the shared
+// threads per chain, max_n the largest n_live, slice_lds the largest
+// chain-kernel LDS of the runs.
 hipError_t launch_iteration_packed(const PackedRun* runs, const int* rank_off, const int* slice_off, int nr,
-                                   int rank_blocks, int slice_blocks, int lk, int max_n, size_t slice_lds,
+                                   int rank_blocks, int slice_blocks, int lk, int nt, int max_n, size_t slice_lds,
                                    hipStream_t st);
 // done flag of every run into out[nr].
 hipError_t launch_gather_done(const PackedRun* runs, int nr, int* out, hipStream_t st);

@@ -499,7 +499,8 @@ __device__ inline double rb_partial(const Probe& p, const RBTables& B, int n_bin
 // probes set up per pass (one per lane), evaluated one after another.
 template <int NDET, bool MX>
 __global__ __launch_bounds__(64) void k_loglike_rb(const ModelDev* __restrict__ Mp, RBTables RB,
-                                                   const double* __restrict__ u, long n, double* __restrict__ out) {
+                                                   const double* __restrict__ u, long n, double* __restrict__ out,
+                                                   int* __restrict__ terms) {
   extern __shared__ double smem[];
   void* sr = smem;
   const ModelDev& M = *Mp;
@@ -522,6 +523,7 @@ __global__ __launch_bounds__(64) void k_loglike_rb(const ModelDev* __restrict__ 
       __syncthreads();   // the ratios in LDS are rewritten by the next probe
     }
     if (i < n) out[i] = mine;
+    if (terms && i < n) terms[i] = RB.nb + 1;
   }
 }
 
@@ -554,7 +556,8 @@ __global__ void k_to_float1(const double* src, float* dst, size_t n, double scal
 // then the wave evaluates the probes one at a time over the bins.
 template <int NDET, int LK, bool LDS>
 __global__ __launch_bounds__(256) void k_loglike(const ModelDev* __restrict__ Mp, Tables T, RBTables RB,
-                                                 const double* __restrict__ u, long n, double* __restrict__ out) {
+                                                 const double* __restrict__ u, long n, double* __restrict__ out,
+                                                 int* __restrict__ terms) {
   extern __shared__ double smem[];
   const ModelDev& M = *Mp;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -571,6 +574,7 @@ __global__ __launch_bounds__(256) void k_loglike(const ModelDev* __restrict__ Mp
 #pragma unroll
     for (int q = 0; q < MAX_DIM; ++q) y[q] = (q < d) ? u[src * d + q] : 0.0;
     double mine;
+    int nterm = 0;
     if (LK == LK_GAUSS) {
       mine = gauss_lambda(M, y);
     } else {
@@ -583,8 +587,10 @@ __global__ __launch_bounds__(256) void k_loglike(const ModelDev* __restrict__ Mp
         const double tot = wave_sum(fullgrid_partial<NDET, lk_mixed(LK)>(pb, V, lane, 64));
         if (lane == p) mine = tot - 0.5 * pb.hh;
       }
+      nterm = pr.k_act;
     }
     if (i < n) out[i] = mine;
+    if (terms && i < n) terms[i] = nterm;
   }
 }
 
@@ -1339,12 +1345,13 @@ __global__ void k_samples(const ModelDev* __restrict__ Mp, RunDev R, double logZ
 
 template <int NDET, int LK, bool LDS>
 hipError_t launch_loglike_t(const ModelDev& M, const ModelDev* Md, const Tables& T, const RBTables& RB,
-                            const double* u, long n, double* out, hipStream_t st) {
+                            const double* u, long n, double* out, int* terms, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   const size_t lds = LDS ? staged_table_bytes(M.k_lim, NDET, lk_mixed(LK)) : 0;
   long blocks = (n + 255) / 256;
   if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL((k_loglike<NDET, LK, LDS>), dim3((unsigned)blocks), dim3(256), lds, st, Md, T, RB, u, n, out);
+  hipLaunchKernelGGL((k_loglike<NDET, LK, LDS>), dim3((unsigned)blocks), dim3(256), lds, st, Md, T, RB, u, n, out,
+                     terms);
   return hipGetLastError();
 }
 
@@ -1443,50 +1450,50 @@ hipError_t launch_init_live(const RunDev& R, hipStream_t st) {
 
 template <int NDET, bool MX>
 hipError_t launch_loglike_rb_t(const ModelDev* Md, const RBTables& RB, const double* u, long n, double* out,
-                               hipStream_t st) {
+                               int* terms, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   long blocks = (n + 63) / 64;
   if (blocks > 8192) blocks = 8192;
   const size_t lds = (size_t)NDET * (RB.nb + 1) * (MX ? sizeof(float2) : sizeof(double2));
-  hipLaunchKernelGGL((k_loglike_rb<NDET, MX>), dim3((unsigned)blocks), dim3(64), lds, st, Md, RB, u, n, out);
+  hipLaunchKernelGGL((k_loglike_rb<NDET, MX>), dim3((unsigned)blocks), dim3(64), lds, st, Md, RB, u, n, out, terms);
   return hipGetLastError();
 }
 
 hipError_t launch_loglike(const ModelDev& M, const ModelDev* Md, const Tables& T, const RBTables& RB,
-                          const double* u, long n, double* out, hipStream_t st) {
-  if (M.likelihood == LK_GAUSS) return launch_loglike_t<1, LK_GAUSS, false>(M, Md, T, RB, u, n, out, st);
+                          const double* u, long n, double* out, int* terms, hipStream_t st) {
+  if (M.likelihood == LK_GAUSS) return launch_loglike_t<1, LK_GAUSS, false>(M, Md, T, RB, u, n, out, terms, st);
   if (M.likelihood == LK_RB) {
     if (M.mixed) {
       switch (M.n_det) {
-        case 1: return launch_loglike_rb_t<1, true>(Md, RB, u, n, out, st);
-        case 2: return launch_loglike_rb_t<2, true>(Md, RB, u, n, out, st);
-        default: return launch_loglike_rb_t<3, true>(Md, RB, u, n, out, st);
+        case 1: return launch_loglike_rb_t<1, true>(Md, RB, u, n, out, terms, st);
+        case 2: return launch_loglike_rb_t<2, true>(Md, RB, u, n, out, terms, st);
+        default: return launch_loglike_rb_t<3, true>(Md, RB, u, n, out, terms, st);
       }
     }
     switch (M.n_det) {
-      case 1: return launch_loglike_rb_t<1, false>(Md, RB, u, n, out, st);
-      case 2: return launch_loglike_rb_t<2, false>(Md, RB, u, n, out, st);
-      default: return launch_loglike_rb_t<3, false>(Md, RB, u, n, out, st);
+      case 1: return launch_loglike_rb_t<1, false>(Md, RB, u, n, out, terms, st);
+      case 2: return launch_loglike_rb_t<2, false>(Md, RB, u, n, out, terms, st);
+      default: return launch_loglike_rb_t<3, false>(Md, RB, u, n, out, terms, st);
     }
   }
   const bool lds = staged_table_bytes(M.k_lim, M.n_det, M.mixed != 0) <= 64 * 1024;
   if (M.mixed) {
     switch (M.n_det) {
-      case 1: return lds ? launch_loglike_t<1, LK_FULL32, true>(M, Md, T, RB, u, n, out, st)
-                         : launch_loglike_t<1, LK_FULL32, false>(M, Md, T, RB, u, n, out, st);
-      case 2: return lds ? launch_loglike_t<2, LK_FULL32, true>(M, Md, T, RB, u, n, out, st)
-                         : launch_loglike_t<2, LK_FULL32, false>(M, Md, T, RB, u, n, out, st);
-      default: return lds ? launch_loglike_t<3, LK_FULL32, true>(M, Md, T, RB, u, n, out, st)
-                          : launch_loglike_t<3, LK_FULL32, false>(M, Md, T, RB, u, n, out, st);
+      case 1: return lds ? launch_loglike_t<1, LK_FULL32, true>(M, Md, T, RB, u, n, out, terms, st)
+                         : launch_loglike_t<1, LK_FULL32, false>(M, Md, T, RB, u, n, out, terms, st);
+      case 2: return lds ? launch_loglike_t<2, LK_FULL32, true>(M, Md, T, RB, u, n, out, terms, st)
+                         : launch_loglike_t<2, LK_FULL32, false>(M, Md, T, RB, u, n, out, terms, st);
+      default: return lds ? launch_loglike_t<3, LK_FULL32, true>(M, Md, T, RB, u, n, out, terms, st)
+                          : launch_loglike_t<3, LK_FULL32, false>(M, Md, T, RB, u, n, out, terms, st);
     }
   }
   switch (M.n_det) {
-    case 1: return lds ? launch_loglike_t<1, LK_FULL, true>(M, Md, T, RB, u, n, out, st)
-                       : launch_loglike_t<1, LK_FULL, false>(M, Md, T, RB, u, n, out, st);
-    case 2: return lds ? launch_loglike_t<2, LK_FULL, true>(M, Md, T, RB, u, n, out, st)
-                       : launch_loglike_t<2, LK_FULL, false>(M, Md, T, RB, u, n, out, st);
-    default: return lds ? launch_loglike_t<3, LK_FULL, true>(M, Md, T, RB, u, n, out, st)
-                        : launch_loglike_t<3, LK_FULL, false>(M, Md, T, RB, u, n, out, st);
+    case 1: return lds ? launch_loglike_t<1, LK_FULL, true>(M, Md, T, RB, u, n, out, terms, st)
+                       : launch_loglike_t<1, LK_FULL, false>(M, Md, T, RB, u, n, out, terms, st);
+    case 2: return lds ? launch_loglike_t<2, LK_FULL, true>(M, Md, T, RB, u, n, out, terms, st)
+                       : launch_loglike_t<2, LK_FULL, false>(M, Md, T, RB, u, n, out, terms, st);
+    default: return lds ? launch_loglike_t<3, LK_FULL, true>(M, Md, T, RB, u, n, out, terms, st)
+                        : launch_loglike_t<3, LK_FULL, false>(M, Md, T, RB, u, n, out, terms, st);
   }
 }
 
@@ -1524,15 +1531,45 @@ hipError_t launch_iteration(const ModelDev& M, const ModelDev* Md, const Tables&
 }
 
 hipError_t configure_slice_packed(const ModelDev& M, int rb_nb, LaunchCfg* C) {
-  C->slice_threads = 256;
+  // a resident mix already holds thousands of chains: two waves per chain
+  // leave more chains in flight than four and waste fewer lanes on short probes
+  C->slice_threads = 128;
+  if (const char* ev = getenv("NS_PACKED_THREADS")) {     // tuning override: 64, 128 or 256
+    const int v = atoi(ev);
+    if (v == 64 || v == 128 || v == 256) C->slice_threads = v;
+  }
   C->lds_tables = false;
-  C->lds_bytes = slice_lds_fixed(256);
+  C->lds_bytes = slice_lds_fixed(C->slice_threads);
   if (M.likelihood == LK_RB) C->lds_bytes += (size_t)M.n_det * (rb_nb + 1) * (M.mixed ? sizeof(float2) : sizeof(double2));
   return hipSuccess;
 }
 
+namespace {
+template <int NT>
+hipError_t launch_slice_packed_nt(const PackedRun* runs, const int* slice_off, int nr, int slice_blocks, int lk,
+                                  size_t slice_lds, hipStream_t st) {
+  switch (lk) {
+    case LK_FULL:
+      hipLaunchKernelGGL((k_slice_packed<NT, LK_FULL>), dim3(slice_blocks), dim3(NT), slice_lds, st, runs, slice_off, nr);
+      break;
+    case LK_FULL32:
+      hipLaunchKernelGGL((k_slice_packed<NT, LK_FULL32>), dim3(slice_blocks), dim3(NT), slice_lds, st, runs, slice_off,
+                         nr);
+      break;
+    case LK_RB:
+      hipLaunchKernelGGL((k_slice_packed<NT, LK_RB>), dim3(slice_blocks), dim3(NT), slice_lds, st, runs, slice_off, nr);
+      break;
+    default:
+      hipLaunchKernelGGL((k_slice_packed<NT, LK_RB32>), dim3(slice_blocks), dim3(NT), slice_lds, st, runs, slice_off,
+                         nr);
+      break;
+  }
+  return hipGetLastError();
+}
+}  // namespace
+
 hipError_t launch_iteration_packed(const PackedRun* runs, const int* rank_off, const int* slice_off, int nr,
-                                   int rank_blocks, int slice_blocks, int lk, int max_n, size_t slice_lds,
+                                   int rank_blocks, int slice_blocks, int lk, int nt, int max_n, size_t slice_lds,
                                    hipStream_t st) {
   if (nr <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_rank_packed, dim3(rank_blocks), dim3(256), 0, st, runs, rank_off, nr);
@@ -1540,23 +1577,12 @@ hipError_t launch_iteration_packed(const PackedRun* runs, const int* rank_off, c
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_prep_packed, dim3(nr), dim3(1024), (size_t)max_n * sizeof(int), st, runs);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  switch (lk) {
-    case LK_FULL:
-      hipLaunchKernelGGL((k_slice_packed<256, LK_FULL>), dim3(slice_blocks), dim3(256), slice_lds, st, runs, slice_off, nr);
-      break;
-    case LK_FULL32:
-      hipLaunchKernelGGL((k_slice_packed<256, LK_FULL32>), dim3(slice_blocks), dim3(256), slice_lds, st, runs, slice_off,
-                         nr);
-      break;
-    case LK_RB:
-      hipLaunchKernelGGL((k_slice_packed<256, LK_RB>), dim3(slice_blocks), dim3(256), slice_lds, st, runs, slice_off, nr);
-      break;
-    default:
-      hipLaunchKernelGGL((k_slice_packed<256, LK_RB32>), dim3(slice_blocks), dim3(256), slice_lds, st, runs, slice_off,
-                         nr);
-      break;
+  switch (nt) {
+    case 64: e = launch_slice_packed_nt<64>(runs, slice_off, nr, slice_blocks, lk, slice_lds, st); break;
+    case 128: e = launch_slice_packed_nt<128>(runs, slice_off, nr, slice_blocks, lk, slice_lds, st); break;
+    default: e = launch_slice_packed_nt<256>(runs, slice_off, nr, slice_blocks, lk, slice_lds, st); break;
   }
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_term_packed, dim3(nr), dim3(1024), 0, st, runs);
   return hipGetLastError();
 }

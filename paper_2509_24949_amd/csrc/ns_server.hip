@@ -4,7 +4,7 @@
 // chains of all resident runs that share a likelihood form, so small runs
 // fill the device together instead of one after another.
 //
-// Every resident run is built with the packed launch configuration (256
+// Every resident run is built with the packed launch configuration (128
 // threads per chain, tables read through the caches) and each workgroup of a
 // packed launch computes exactly what the same workgroup computes when the run
 // is alone, so a run's results do not depend on what else is resident.
@@ -43,7 +43,8 @@ struct Resident {
   ns_run* run;
   size_t bytes;
   double t_submit, t_admit;
-  int lk;
+  int lk;        // likelihood kind and threads per chain: runs that share
+  int nt;        // both share a packed launch
 };
 
 struct Finished {
@@ -53,7 +54,7 @@ struct Finished {
 };
 
 struct Group {
-  int first, count, lk, rank_blocks, slice_blocks, max_n;
+  int first, count, lk, nt, rank_blocks, slice_blocks, max_n;
   size_t lds;
 };
 
@@ -136,7 +137,7 @@ int admit(ns_server* s) {
       f.reported = false;
       s->finished.push_back(f);
     } else {
-      s->running.push_back(Resident{q.ticket, r, q.resident, q.t_submit, ta, lk_of(r->M)});
+      s->running.push_back(Resident{q.ticket, r, q.resident, q.t_submit, ta, lk_of(r->M), r->C.slice_threads});
       s->used += q.resident;
       s->dirty = true;
     }
@@ -145,11 +146,13 @@ int admit(ns_server* s) {
   return NS_OK;
 }
 
-// Group the resident runs by likelihood form and upload the descriptors.
+// Group the resident runs by likelihood form and chain-workgroup size and
+// upload the descriptors.
 int rebuild(ns_server* s) {
   s->drop_graph();
-  std::stable_sort(s->running.begin(), s->running.end(),
-                   [](const Resident& a, const Resident& b) { return a.lk < b.lk; });
+  std::stable_sort(s->running.begin(), s->running.end(), [](const Resident& a, const Resident& b) {
+    return a.lk != b.lk ? a.lk < b.lk : a.nt < b.nt;
+  });
   s->groups.clear();
   const int nr = (int)s->running.size();
   int* slice_off = s->h_off;
@@ -157,8 +160,8 @@ int rebuild(ns_server* s) {
   for (int i = 0; i < nr; ++i) {
     const ns_run* r = s->running[i].run;
     s->h_runs[i] = PackedRun{r->Md, r->T, r->RB, r->R};
-    if (s->groups.empty() || s->groups.back().lk != s->running[i].lk)
-      s->groups.push_back(Group{i, 0, s->running[i].lk, 0, 0, 0, 0});
+    if (s->groups.empty() || s->groups.back().lk != s->running[i].lk || s->groups.back().nt != s->running[i].nt)
+      s->groups.push_back(Group{i, 0, s->running[i].lk, s->running[i].nt, 0, 0, 0, 0});
     Group& g = s->groups.back();
     slice_off[i] = g.slice_blocks;
     rank_off[i] = g.rank_blocks;
@@ -181,7 +184,7 @@ hipError_t enqueue_iterations(ns_server* s, int n_iters) {
     for (const Group& g : s->groups) {
       hipError_t e = launch_iteration_packed(s->d_runs + g.first, s->d_off + s->max_runs + g.first,
                                              s->d_off + g.first, g.count, g.rank_blocks, g.slice_blocks, g.lk,
-                                             g.max_n, g.lds, s->st);
+                                             g.nt, g.max_n, g.lds, s->st);
       if (e != hipSuccess) return e;
     }
   return hipSuccess;

@@ -1,0 +1,116 @@
+"""Complete runs on the GPU against complete oracle runs stored in
+tests/golden/full_runs.json (written by tests/golden/make_full_runs.py,
+which calls only the oracle).
+
+Bars: in double precision the GPU run follows the oracle in lockstep to the
+end (same iteration count, evaluation count and dead-point sequence; log Z
+and the log-likelihoods of sampled dead points to 1e-9 relative, so
+|delta log Z| is far inside 0.1 and the sampler's 2 sigma); the mixed form
+agrees with the double-precision form over seeds within the spread of
+their means; served events match the oracle like single runs.
+"""
+import hashlib
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2509_24949_amd import binding, synth
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "full_runs.json")
+
+
+@pytest.fixture(scope="module")
+def golden():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    binding.lib()
+    with open(GOLDEN) as fh:
+        return json.load(fh)
+
+
+def _digest(slot, it):
+    h = hashlib.sha256()
+    h.update(np.ascontiguousarray(slot, dtype=np.int32).tobytes())
+    h.update(np.ascontiguousarray(it, dtype=np.int32).tobytes())
+    return h.hexdigest()
+
+
+def _check(g, run):
+    st = run.state()
+    z = run.logZ(200)
+    d = run.dead()
+    assert st["iter"] == g["iterations"] and st["n_evals"] == g["n_evals"] and st["n_dead"] == g["n_dead"]
+    assert _digest(d["slot"], d["iter"]) == g["dead_digest"]
+    idx = np.array(g["logl_index"])
+    want = np.array(g["logl_at"])
+    assert np.max(np.abs(d["logl"][idx] - want) / (np.abs(want) + 1.0)) <= 1e-9
+    assert abs(z["logZ"] - g["logZ"]) <= 1e-9 * (abs(g["logZ"]) + 1.0)
+    assert abs(z["logZ"] - g["logZ"]) <= min(0.1, 2.0 * g["sigma"])
+    assert abs(z["sigma"] - g["sigma"]) <= 1e-6 * g["sigma"]
+    assert abs(z["ess"] - g["ess"]) <= 1e-6 * g["ess"]
+
+
+def _data(w):
+    # the same data the stored oracle runs saw (the oracle's own injection)
+    re, im = oracle.make_data(w)
+    return binding.ProblemSpec(w, re, im)
+
+
+@pytest.mark.parametrize("name", ["cfg2", "cfg3"])
+def test_complete_run_matches_oracle(golden, name):
+    w = synth.workload(name)
+    run = binding.Run(_data(w), binding.opts_for(w))
+    assert run.run(1000)
+    _check(golden[name], run)
+    run.close()
+
+
+def test_served_events_match_oracle(golden):
+    keys = sorted(k for k in golden if k.startswith("cfg5/"))
+    assert len(keys) >= 4
+    srv = binding.Server(max_runs=len(keys))
+    tick = {}
+    for k in keys:
+        w = synth.serving_event(int(k.split("/")[1]))
+        tick[srv.submit(_data(w), binding.opts_for(w))] = k
+    done = {}
+    for _ in range(10000):
+        running, queued, _ = srv.tick(1)
+        for info in srv.poll():
+            done[tick[info["ticket"]]] = srv.take(info["ticket"])
+        if running == 0 and queued == 0 and len(done) == len(keys):
+            break
+    for k in keys:
+        _check(golden[k], done[k])
+        done[k].close()
+    srv.close()
+
+
+def test_mixed_precision_agrees_with_double(golden):
+    """Large-population workload: eight seeds in each precision; the means
+    of log Z agree within twice the spread of their difference, and both sit
+    within reach of the oracle's double-precision run."""
+    w = synth.workload("cfg4")
+    spec = _data(w)
+    z = {0: [], 1: []}
+    sig = {0: [], 1: []}
+    for prec in (0, 1):
+        for s in range(8):
+            run = binding.Run(spec, binding.opts_for(w, seed=9100 + s, precision=prec))
+            assert run.run(1000)
+            r = run.logZ(200)
+            z[prec].append(r["logZ"])
+            sig[prec].append(r["sigma"])
+            run.close()
+    m64, m32 = np.mean(z[0]), np.mean(z[1])
+    spread = math.sqrt(np.var(z[0], ddof=1) / 8 + np.var(z[1], ddof=1) / 8)
+    assert abs(m32 - m64) <= max(2.0 * spread, 0.05), (m32, m64, spread)
+    g = golden["cfg4_fp64"]
+    assert abs(m32 - g["logZ"]) <= 2.0 * math.sqrt(g["sigma"] ** 2 + np.mean(sig[1]) ** 2 / 8)

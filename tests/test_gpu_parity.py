@@ -77,6 +77,13 @@ def test_loglike_parity(torch_cuda, name, n):
     assert run.loglike(torch.zeros((0, w.n_dim), dtype=torch.float64, device="cuda")).numel() == 0
     one = run.loglike(torch.from_numpy(u[2:3].copy()).cuda()).cpu().numpy()
     assert abs(one[0] - lam_o[2]) <= 1e-9 * scale[2]
+    # per-probe term counts: the bins the oracle's ISCO-cut waveform leaves nonzero
+    terms = torch.zeros(n, dtype=torch.int32, device="cuda")
+    run.loglike(torch.from_numpy(u).cuda(), terms=terms)
+    terms = terms.cpu().numpy()
+    for i in range(0, n, max(1, n // 40)):
+        hr, hi = orc.waveform(orc.prior_transform(u[i]), 0, cut=True)
+        assert terms[i] == int(np.count_nonzero((hr != 0.0) | (hi != 0.0))), i
 
 
 def _brute(x, k):
