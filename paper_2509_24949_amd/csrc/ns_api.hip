@@ -353,7 +353,7 @@ int run_create(ns_run** out, const ns_problem* P, const ns_opts* O, hipStream_t 
   *r->h_state = s0;
   e = hipMemcpyAsync(R.state, r->h_state, sizeof(DevState), hipMemcpyHostToDevice, r->st);
   if (e == hipSuccess) e = launch_init_live(R, r->st);
-  if (e == hipSuccess) e = launch_loglike(r->M, r->Md, r->T, r->RB, R.u, n, R.lam, nullptr, r->st);
+  if (e == hipSuccess) e = launch_loglike(r->M, r->Md, r->T, r->RB, R.u, n, R.lam, nullptr, nullptr, r->st);
   if (e == hipSuccess) e = hipStreamSynchronize(r->st);
   if (e != hipSuccess) return cleanup(fail(NS_E_HIP, "initial population: %s", hipGetErrorString(e)));
   *out = r;
@@ -526,7 +526,17 @@ int ns_dead(ns_run* r, long cap, double* u, double* logl, double* logx, double* 
 int ns_loglike(ns_run* r, const double* u_dev, long n, double* out_dev, int* terms_dev) {
   if (!r) return fail(NS_E_ARG, "run is NULL");
   if (n < 0 || (n > 0 && (!u_dev || !out_dev))) return fail(NS_E_ARG, "bad batch arguments");
-  HIP_OK(launch_loglike(r->M, r->Md, r->T, r->RB, u_dev, n, out_dev, terms_dev, r->st));
+  if (r->M.likelihood == NS_LIKE_FULL && n > r->probe_cap) {
+    HIP_OK(hipStreamSynchronize(r->st));   // the old buffer may still be read
+    if (r->probe_buf) (void)hipFree(r->probe_buf);
+    r->probe_buf = nullptr;
+    r->probe_cap = 0;
+    const long cap = std::max<long>(n, 4096);
+    HIP_OK(hipMalloc((void**)&r->probe_buf, cap * sizeof(Probe)));
+    r->probe_cap = cap;
+  }
+  HIP_OK(launch_loglike(r->M, r->Md, r->T, r->RB, u_dev, n, out_dev, terms_dev,
+                        r->M.likelihood == NS_LIKE_FULL ? r->probe_buf : nullptr, r->st));
   return NS_OK;
 }
 

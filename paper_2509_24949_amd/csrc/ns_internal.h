@@ -123,8 +123,10 @@ hipError_t launch_noise_loglike(const double* dre, const double* dim, const doub
 hipError_t launch_init_live(const RunDev& R, hipStream_t st);
 // Batched likelihood; terms (optional, device [n]) receives each probe's
 // counted terms (full grid: active bins; relative binning: edges; Gaussian: 0).
+// pbuf (optional, device [n]): probe coefficients, which select the two-pass
+// full-grid form (set-up pass, then one wavefront per probe).
 hipError_t launch_loglike(const ModelDev& M, const ModelDev* Md, const Tables& T, const RBTables& RB,
-                          const double* u, long n, double* out, int* terms, hipStream_t st);
+                          const double* u, long n, double* out, int* terms, Probe* pbuf, hipStream_t st);
 hipError_t launch_select(const double* lam, int n, int k, int* rank, int* dead, double* lstar, const int* done,
                          hipStream_t st);
 // ev (optional): five events recorded before select, after select, after

@@ -31,16 +31,45 @@ namespace {
 
 constexpr double NEG_INF = -__builtin_inf();
 
+// Value of lane i ^ 1, i ^ 2 (quad permutations), of the mirrored lane in
+// the half row (8 lanes) and in the row (16 lanes), through DPP.
+template <int CTRL>
+__device__ inline double dpp_d(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
+  return __hiloint2double(hi, lo);
+}
+constexpr int DPP_XOR1 = 0xB1;          // quad_perm [1, 0, 3, 2]
+constexpr int DPP_XOR2 = 0x4E;          // quad_perm [2, 3, 0, 1]
+constexpr int DPP_HALF_MIRROR = 0x141;
+constexpr int DPP_MIRROR = 0x140;
+
+// Value of lane `src` (uniform) as a scalar.
+__device__ inline double row_value(double v, int src) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), src),
+                          __builtin_amdgcn_readlane(__double2loint(v), src));
+}
+
+// Wavefront sum with every lane active: a butterfly inside each row of 16
+// lanes (both partners of a pair add the same two values, so every lane of
+// a row holds the same row sum), then (r0 + r1) + (r2 + r3) over the rows.
+// The order is fixed, so the result is reproducible and uniform.
 __device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v += dpp_d<DPP_XOR1>(v);
+  v += dpp_d<DPP_XOR2>(v);
+  v += dpp_d<DPP_HALF_MIRROR>(v);
+  v += dpp_d<DPP_MIRROR>(v);
+  const double r0 = row_value(v, 0), r1 = row_value(v, 16), r2 = row_value(v, 32), r3 = row_value(v, 48);
+  return (r0 + r1) + (r2 + r3);
 }
 
 __device__ inline double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
+  v = fmax(v, dpp_d<DPP_XOR1>(v));
+  v = fmax(v, dpp_d<DPP_XOR2>(v));
+  v = fmax(v, dpp_d<DPP_HALF_MIRROR>(v));
+  v = fmax(v, dpp_d<DPP_MIRROR>(v));
+  const double r0 = row_value(v, 0), r1 = row_value(v, 16), r2 = row_value(v, 32), r3 = row_value(v, 48);
+  return fmax(fmax(r0, r1), fmax(r2, r3));
 }
 
 __device__ inline long long wave_sum_ll(long long v) {
@@ -591,6 +620,43 @@ __global__ __launch_bounds__(256) void k_loglike(const ModelDev* __restrict__ Mp
     }
     if (i < n) out[i] = mine;
     if (terms && i < n) terms[i] = nterm;
+  }
+}
+
+// Two-pass form of the batched full-grid likelihood: the per-probe source
+// set-up runs one thread per probe and stores the coefficients; the bin
+// pass then runs one wavefront per probe with the coefficients in scalar
+// registers, so the bin loop keeps few vector registers and many waves
+// per SIMD hide its latency.
+__global__ __launch_bounds__(256) void k_probe_setup(const ModelDev* __restrict__ Mp, const double* __restrict__ hpre,
+                                                     const double* __restrict__ u, long n, Probe* __restrict__ P,
+                                                     int* __restrict__ terms) {
+  const ModelDev& M = *Mp;
+  const long i = (long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const int d = M.n_dim;
+  double y[MAX_DIM];
+#pragma unroll
+  for (int q = 0; q < MAX_DIM; ++q) y[q] = (q < d) ? u[i * d + q] : 0.0;
+  Probe pr;
+  make_probe(M, hpre, y, &pr);
+  P[i] = pr;
+  if (terms) terms[i] = pr.k_act;
+}
+
+template <int NDET, int LK, bool LDS>
+__global__ __launch_bounds__(256) void k_probe_bins(const ModelDev* __restrict__ Mp, Tables T,
+                                                    const Probe* __restrict__ P, long n, double* __restrict__ out) {
+  extern __shared__ double smem[];
+  const ModelDev& M = *Mp;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const TabView V = stage_tables<NDET, lk_mixed(LK)>(M, T, LDS, smem, tid, 256);
+  if (LDS) __syncthreads();
+  for (long p = (long)blockIdx.x * 4 + wv; p < n; p += (long)gridDim.x * 4) {
+    const Probe pb = P[p];
+    const double tot = wave_sum(fullgrid_partial<NDET, lk_mixed(LK)>(pb, V, lane, 64));
+    if (lane == 0) out[p] = tot - 0.5 * pb.hh;
   }
 }
 
@@ -1345,8 +1411,20 @@ __global__ void k_samples(const ModelDev* __restrict__ Mp, RunDev R, double logZ
 
 template <int NDET, int LK, bool LDS>
 hipError_t launch_loglike_t(const ModelDev& M, const ModelDev* Md, const Tables& T, const RBTables& RB,
-                            const double* u, long n, double* out, int* terms, hipStream_t st) {
+                            const double* u, long n, double* out, int* terms, Probe* pbuf, hipStream_t st) {
   if (n <= 0) return hipSuccess;
+  if (LK != LK_GAUSS && pbuf) {
+    hipLaunchKernelGGL(k_probe_setup, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, Md, T.hpre, u, n, pbuf,
+                       terms);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const size_t lds = LDS ? staged_table_bytes(M.k_lim, NDET, lk_mixed(LK)) : 0;
+    long blocks = (n + 3) / 4;
+    if (blocks > 256 * 8) blocks = 256 * 8;
+    hipLaunchKernelGGL((k_probe_bins<NDET, LK, LDS>), dim3((unsigned)blocks), dim3(256), lds, st, Md, T, pbuf, n,
+                       out);
+    return hipGetLastError();
+  }
   const size_t lds = LDS ? staged_table_bytes(M.k_lim, NDET, lk_mixed(LK)) : 0;
   long blocks = (n + 255) / 256;
   if (blocks > 4096) blocks = 4096;
@@ -1460,8 +1538,8 @@ hipError_t launch_loglike_rb_t(const ModelDev* Md, const RBTables& RB, const dou
 }
 
 hipError_t launch_loglike(const ModelDev& M, const ModelDev* Md, const Tables& T, const RBTables& RB,
-                          const double* u, long n, double* out, int* terms, hipStream_t st) {
-  if (M.likelihood == LK_GAUSS) return launch_loglike_t<1, LK_GAUSS, false>(M, Md, T, RB, u, n, out, terms, st);
+                          const double* u, long n, double* out, int* terms, Probe* pbuf, hipStream_t st) {
+  if (M.likelihood == LK_GAUSS) return launch_loglike_t<1, LK_GAUSS, false>(M, Md, T, RB, u, n, out, terms, pbuf, st);
   if (M.likelihood == LK_RB) {
     if (M.mixed) {
       switch (M.n_det) {
@@ -1479,21 +1557,21 @@ hipError_t launch_loglike(const ModelDev& M, const ModelDev* Md, const Tables& T
   const bool lds = staged_table_bytes(M.k_lim, M.n_det, M.mixed != 0) <= 64 * 1024;
   if (M.mixed) {
     switch (M.n_det) {
-      case 1: return lds ? launch_loglike_t<1, LK_FULL32, true>(M, Md, T, RB, u, n, out, terms, st)
-                         : launch_loglike_t<1, LK_FULL32, false>(M, Md, T, RB, u, n, out, terms, st);
-      case 2: return lds ? launch_loglike_t<2, LK_FULL32, true>(M, Md, T, RB, u, n, out, terms, st)
-                         : launch_loglike_t<2, LK_FULL32, false>(M, Md, T, RB, u, n, out, terms, st);
-      default: return lds ? launch_loglike_t<3, LK_FULL32, true>(M, Md, T, RB, u, n, out, terms, st)
-                          : launch_loglike_t<3, LK_FULL32, false>(M, Md, T, RB, u, n, out, terms, st);
+      case 1: return lds ? launch_loglike_t<1, LK_FULL32, true>(M, Md, T, RB, u, n, out, terms, pbuf, st)
+                         : launch_loglike_t<1, LK_FULL32, false>(M, Md, T, RB, u, n, out, terms, pbuf, st);
+      case 2: return lds ? launch_loglike_t<2, LK_FULL32, true>(M, Md, T, RB, u, n, out, terms, pbuf, st)
+                         : launch_loglike_t<2, LK_FULL32, false>(M, Md, T, RB, u, n, out, terms, pbuf, st);
+      default: return lds ? launch_loglike_t<3, LK_FULL32, true>(M, Md, T, RB, u, n, out, terms, pbuf, st)
+                          : launch_loglike_t<3, LK_FULL32, false>(M, Md, T, RB, u, n, out, terms, pbuf, st);
     }
   }
   switch (M.n_det) {
-    case 1: return lds ? launch_loglike_t<1, LK_FULL, true>(M, Md, T, RB, u, n, out, terms, st)
-                       : launch_loglike_t<1, LK_FULL, false>(M, Md, T, RB, u, n, out, terms, st);
-    case 2: return lds ? launch_loglike_t<2, LK_FULL, true>(M, Md, T, RB, u, n, out, terms, st)
-                       : launch_loglike_t<2, LK_FULL, false>(M, Md, T, RB, u, n, out, terms, st);
-    default: return lds ? launch_loglike_t<3, LK_FULL, true>(M, Md, T, RB, u, n, out, terms, st)
-                        : launch_loglike_t<3, LK_FULL, false>(M, Md, T, RB, u, n, out, terms, st);
+    case 1: return lds ? launch_loglike_t<1, LK_FULL, true>(M, Md, T, RB, u, n, out, terms, pbuf, st)
+                       : launch_loglike_t<1, LK_FULL, false>(M, Md, T, RB, u, n, out, terms, pbuf, st);
+    case 2: return lds ? launch_loglike_t<2, LK_FULL, true>(M, Md, T, RB, u, n, out, terms, pbuf, st)
+                       : launch_loglike_t<2, LK_FULL, false>(M, Md, T, RB, u, n, out, terms, pbuf, st);
+    default: return lds ? launch_loglike_t<3, LK_FULL, true>(M, Md, T, RB, u, n, out, terms, pbuf, st)
+                        : launch_loglike_t<3, LK_FULL, false>(M, Md, T, RB, u, n, out, terms, pbuf, st);
   }
 }
 

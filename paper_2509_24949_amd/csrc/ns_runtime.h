@@ -102,6 +102,8 @@ struct ns_run {
   ns::ProblemCopy prob;              // the problem as given (for ns_save)
   ns_opts opts{};
   double noise_loglike = 0.0;        // log-likelihood of the data under the noise-only model
+  ns::Probe* probe_buf = nullptr;    // coefficients of a batched likelihood call (grown on demand)
+  long probe_cap = 0;
   ns::DevMem mem;
   ns::DevState* h_state = nullptr;   // pinned mirror of the device scalars
   bool profiling = false;
@@ -114,6 +116,7 @@ struct ns_run {
   ~ns_run() {
     release_events();
     if (h_state) (void)hipHostFree(h_state);
+    if (probe_buf) (void)hipFree(probe_buf);
   }
 };
 
