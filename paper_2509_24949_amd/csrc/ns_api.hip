@@ -83,6 +83,7 @@ int validate_and_model(const ns_problem* P, ModelDev* M) {
   M->n_bins = P->n_bins;
   M->f_lo = P->f_lo;
   M->df = P->df;
+  M->inv_df = 1.0 / P->df;
   M->gmst = P->gmst;
   // the largest f_ISCO over the prior box bounds the active bins
   double mc_min = P->prior_lo[0], eta_max;

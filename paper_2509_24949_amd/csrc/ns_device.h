@@ -123,6 +123,7 @@ struct ModelDev {
   int model, likelihood, n_dim, n_det;
   int n_bins, k_lim;           // k_lim: bins that can be active anywhere in the prior box
   double f_lo, df, gmst;
+  double inv_df;               // 1 / df
   double fixed_dist_s;         // TF2_4P distance (s)
   PriorDev prior;
   DetDev det[MAX_DET];
@@ -156,10 +157,11 @@ struct Probe {
 
 // Number of grid bins with f_k <= f_isco, where f_k = f_lo + k df is rounded
 // as a product followed by a sum (no fused multiply-add); in [0, n_bins].
-__device__ inline int active_bins(double f_lo, double df, int n_bins, double f_isco) {
+// inv_df only seeds the estimate, which the two loops then make exact.
+__device__ inline int active_bins(double f_lo, double df, double inv_df, int n_bins, double f_isco) {
 #pragma clang fp contract(off)
   if (!(f_isco >= f_lo)) return 0;
-  double est = (f_isco - f_lo) / df;
+  double est = (f_isco - f_lo) * inv_df;
   int k = (est >= (double)n_bins) ? n_bins : (int)floor(est) + 1;
   if (k > n_bins) k = n_bins;
   while (k > 0 && f_lo + (double)(k - 1) * df > f_isco) --k;
@@ -296,7 +298,7 @@ __device__ inline void probe_from_phys(const ModelDev& M, const Phys& s, const d
   p->ph0 = (-s.phic - 0.25 * PI) * (1.0 / TWO_PI);
   double x3 = p->x * p->x * p->x;                    // pi M
   p->f_isco = 1.0 / (14.696938456699069 * x3);      // 1 / (6^(3/2) pi M)
-  p->k_act = active_bins(M.f_lo, M.df, M.n_bins, p->f_isco);
+  p->k_act = active_bins(M.f_lo, M.df, M.inv_df, M.n_bins, p->f_isco);
   if (p->k_act > M.k_lim) p->k_act = M.k_lim;
   double amp = 0.21278751013966343 * exp(5.0 / 6.0 * ln_mc) / s.dist_s;
   const bool have_h = hpre != nullptr && p->k_act > 0;
@@ -341,6 +343,131 @@ __device__ inline void make_probe(const ModelDev& M, const double* hpre, const d
   Phys s;
   phys_from_u(M, u, &s);
   probe_from_phys(M, s, hpre, p);
+}
+
+// ---- probe set-up split over two threads (chain kernel) ---------------------
+// A candidate's set-up divides into an intrinsic half (masses, spins, phase
+// coefficients, f_ISCO, active bins, the mass factor of the amplitude) and an
+// extrinsic half (distance, inclination, antenna patterns, delays), which
+// two threads compute side by side.  The halves meet in a ProbeRec; the
+// evaluating threads assemble the Probe from it.
+struct ProbeRec {
+  double x, lnx, pref, c2, c3, c4, c5, c5l, c6, c6l, c7, tc, ph0;   // intrinsic
+  double amp_mc;                    // sqrt(5/24) pi^(-2/3) Mc^(5/6) (intrinsic)
+  double f_isco;                    // intrinsic
+  int k_act, pad;                   // intrinsic
+  double inv_dist;                  // 1 / D (extrinsic)
+  double gre[MAX_DET], gim[MAX_DET];   // F+ (1 + cos^2 i)/2 and -Fx cos i (extrinsic)
+  double dt[MAX_DET];               // arrival delays (extrinsic)
+};
+
+__device__ inline void probe_intrinsic(const ModelDev& M, const double* u, ProbeRec* r) {
+  const PriorDev& P = M.prior;
+  const double mc_msun = prior_affine(P, 0, u[0]);
+  double eta, beta = 0.0, sigma = 0.0, tc, phic;
+  if (M.model == 1) {
+    eta = prior_affine(P, 1, u[1]);
+    tc = prior_affine(P, 2, u[2]);
+    phic = prior_affine(P, 3, u[3]);
+  } else {
+    const double q = prior_affine(P, 1, u[1]);
+    const double c1 = prior_affine(P, 2, u[2]);
+    const double c2 = prior_affine(P, 3, u[3]);
+    const double m1 = 1.0 / (1.0 + q), m2 = q * m1;   // component masses over M
+    eta = m1 * m2;
+    beta = (c1 * (113.0 * m1 * m1 + 75.0 * eta) + c2 * (113.0 * m2 * m2 + 75.0 * eta)) * (1.0 / 12.0);
+    sigma = 79.0 / 8.0 * eta * c1 * c2;
+    tc = prior_affine(P, 9, u[9]);
+    phic = prior_affine(P, 10, u[10]);
+  }
+  const double ln_mc = log(mc_msun * TSUN_S);
+  const double ln_pim = 1.1447298858494002 + ln_mc - 0.6 * log(eta);   // ln(pi M)
+  Probe p;
+  p.lnx = ln_pim * (1.0 / 3.0);
+  p.x = exp(p.lnx);
+  const double x2 = p.x * p.x;
+  p.pref = (3.0 / 128.0 / TWO_PI) / (eta * (x2 * x2 * p.x));
+  pn_coefficients(eta, beta, sigma, &p);
+  r->x = p.x; r->lnx = p.lnx; r->pref = p.pref;
+  r->c2 = p.c2; r->c3 = p.c3; r->c4 = p.c4; r->c5 = p.c5; r->c5l = p.c5l; r->c6 = p.c6; r->c6l = p.c6l; r->c7 = p.c7;
+  r->tc = tc;
+  r->ph0 = (-phic - 0.25 * PI) * (1.0 / TWO_PI);
+  const double x3 = p.x * p.x * p.x;                 // pi M
+  r->f_isco = 1.0 / (14.696938456699069 * x3);      // 1 / (6^(3/2) pi M)
+  int k = active_bins(M.f_lo, M.df, M.inv_df, M.n_bins, r->f_isco);
+  r->k_act = k > M.k_lim ? M.k_lim : k;
+  r->amp_mc = 0.21278751013966343 * exp(5.0 / 6.0 * ln_mc);
+}
+
+__device__ inline void probe_extrinsic(const ModelDev& M, const double* u, ProbeRec* r) {
+  if (M.model == 1) {
+    r->inv_dist = 1.0 / M.fixed_dist_s;
+    r->gre[0] = 1.0; r->gim[0] = 0.0; r->dt[0] = 0.0;
+    return;
+  }
+  const PriorDev& P = M.prior;
+  const double dv = prior_affine(P, 4, u[4]);
+  r->inv_dist = 1.0 / ((P.kind[4] == 3 ? cbrt(dv) : dv) * MPC_S);
+  const double ci = (P.kind[5] == 1) ? prior_affine(P, 5, u[5])
+                                     : sincos_cycles(prior_affine(P, 5, u[5]) * (1.0 / TWO_PI)).y;
+  const double hp = 0.5 * fma(ci, ci, 1.0), hx = ci;
+  const double2 p2 = sincos_cycles(prior_affine(P, 6, u[6]) * (1.0 / PI));   // angle 2 psi
+  const double2 ra = sincos_cycles((prior_affine(P, 7, u[7]) - M.gmst) * (1.0 / TWO_PI));
+  double sdec, cdec;
+  if (P.kind[8] == 2) {
+    sdec = prior_affine(P, 8, u[8]);
+    cdec = sqrt(fmax(0.0, 1.0 - sdec * sdec));
+  } else {
+    const double2 de = sincos_cycles(prior_affine(P, 8, u[8]) * (1.0 / TWO_PI));
+    sdec = de.x;
+    cdec = de.y;
+  }
+  // wave-frame axes at psi = 0 (see probe_from_phys)
+  const double ax = ra.x, ay = -ra.y;
+  const double bx = -ra.y * sdec, by = -ra.x * sdec, bz = cdec;
+  const double nx = cdec * ra.y, ny = cdec * ra.x, nz = sdec;
+#pragma unroll
+  for (int d = 0; d < MAX_DET; ++d) {
+    if (d >= M.n_det) break;
+    const double* D = M.det[d].D;
+    const double dax = D[0] * ax + D[1] * ay;
+    const double day = D[1] * ax + D[3] * ay;
+    const double dbx = D[0] * bx + D[1] * by + D[2] * bz;
+    const double dby = D[1] * bx + D[3] * by + D[4] * bz;
+    const double dbz = D[2] * bx + D[4] * by + D[5] * bz;
+    const double aDa = ax * dax + ay * day;
+    const double bDb = bx * dbx + by * dby + bz * dbz;
+    const double aDb = ax * dbx + ay * dby;
+    const double fp0 = aDa - bDb, fx0 = 2.0 * aDb;
+    const double fp = p2.y * fp0 + p2.x * fx0;
+    const double fx = -p2.x * fp0 + p2.y * fx0;
+    r->gre[d] = fp * hp;
+    r->gim[d] = -fx * hx;
+    const double* rc = M.det[d].r_c;
+    r->dt[d] = -(rc[0] * nx + rc[1] * ny + rc[2] * nz);
+  }
+}
+
+// The Probe of a record; hpre (may be null; rows of length hstride) gives
+// <h|h> from the prefix table.
+template <int NDET>
+__device__ inline Probe probe_from_rec(const ProbeRec& r, const double* hpre, int hstride) {
+  Probe p;
+  p.x = r.x; p.lnx = r.lnx; p.pref = r.pref;
+  p.c2 = r.c2; p.c3 = r.c3; p.c4 = r.c4; p.c5 = r.c5; p.c5l = r.c5l; p.c6 = r.c6; p.c6l = r.c6l; p.c7 = r.c7;
+  p.tc = r.tc; p.ph0 = r.ph0; p.f_isco = r.f_isco; p.k_act = r.k_act;
+  const double amp = r.amp_mc * r.inv_dist;
+  double hh = 0.0;
+#pragma unroll
+  for (int d = 0; d < NDET; ++d) {
+    p.kre[d] = amp * r.gre[d];
+    p.kim[d] = amp * r.gim[d];
+    p.dt[d] = r.dt[d];
+    if (hpre && r.k_act > 0)
+      hh += (p.kre[d] * p.kre[d] + p.kim[d] * p.kim[d]) * hpre[(size_t)d * hstride + r.k_act - 1];
+  }
+  p.hh = hh;
+  return p;
 }
 
 // Phase of bin k in cycles (without the detector delay).

@@ -143,13 +143,14 @@ struct TabView {
   const double* fm53;
   const double2* dw;
   const float2* dw32;
-  int dstride;
+  const double* hpre;   // prefix sums of 4 df f^(-7/3) / S per detector
+  int dstride;          // row stride of dw, dw32 and hpre
   double inv_scale;     // 1 / dw_scale of the float table
 };
 
 // LDS bytes of the staged full-grid tables.
 __host__ __device__ inline size_t staged_table_bytes(int k_lim, int n_det, bool mixed) {
-  return (size_t)k_lim * (4 * sizeof(double) + n_det * (mixed ? sizeof(float2) : sizeof(double2)));
+  return (size_t)k_lim * (4 * sizeof(double) + n_det * (sizeof(double) + (mixed ? sizeof(float2) : sizeof(double2))));
 }
 
 template <int NDET, bool MX>
@@ -157,7 +158,7 @@ __device__ inline TabView stage_tables(const ModelDev& M, const Tables& T, bool 
                                        int nt) {
   TabView V;
   if (!use_lds) {
-    V.f = T.f; V.f13 = T.f13; V.lnf3 = T.lnf3; V.fm53 = T.fm53; V.dw = T.dw; V.dw32 = T.dw32;
+    V.f = T.f; V.f13 = T.f13; V.lnf3 = T.lnf3; V.fm53 = T.fm53; V.dw = T.dw; V.dw32 = T.dw32; V.hpre = T.hpre;
     V.dstride = M.n_bins;
     V.inv_scale = MX ? 1.0 / M.dw_scale : 1.0;
     return V;
@@ -167,8 +168,10 @@ __device__ inline TabView stage_tables(const ModelDev& M, const Tables& T, bool 
   double* f13 = f + K;
   double* lnf3 = f13 + K;
   double* fm53 = lnf3 + K;
+  // the complex data first (16-byte aligned: 4 K doubles in), then the prefix table
   double2* dw = reinterpret_cast<double2*>(fm53 + K);
   float2* dw32 = reinterpret_cast<float2*>(fm53 + K);
+  double* hp = MX ? reinterpret_cast<double*>(dw32 + NDET * K) : reinterpret_cast<double*>(dw + NDET * K);
   for (int k = tid; k < K; k += nt) {
     f[k] = T.f[k];
     f13[k] = T.f13[k];
@@ -176,11 +179,12 @@ __device__ inline TabView stage_tables(const ModelDev& M, const Tables& T, bool 
     fm53[k] = T.fm53[k];
 #pragma unroll
     for (int d = 0; d < NDET; ++d) {
+      hp[d * K + k] = T.hpre[(size_t)d * M.n_bins + k];
       if (MX) dw32[d * K + k] = T.dw32[(size_t)d * M.n_bins + k];
       else dw[d * K + k] = T.dw[(size_t)d * M.n_bins + k];
     }
   }
-  V.f = f; V.f13 = f13; V.lnf3 = lnf3; V.fm53 = fm53; V.dw = dw; V.dw32 = dw32; V.dstride = K;
+  V.f = f; V.f13 = f13; V.lnf3 = lnf3; V.fm53 = fm53; V.dw = dw; V.dw32 = dw32; V.hpre = hp; V.dstride = K;
   V.inv_scale = MX ? 1.0 / M.dw_scale : 1.0;
   return V;
 }
@@ -858,43 +862,48 @@ __global__ __launch_bounds__(1024) void k_prep(RunDev R) {
 
 
 // ------------------------------------------------------------ slice chains
-// Candidate batches of the chain kernel: NT candidates per batch, one per
-// thread.  Slots [0, SO) hold left step-out points, [SO, 2 SO) right ones,
-// the rest the first SC shrink candidates of each bracket the step-out can
-// end in with at most H-1 steps per side.
-template <int NT> struct SliceBatch {
-  static constexpr int SO = NT / 8;
-  static constexpr int H = NT >= 256 ? 6 : 4;
-  static constexpr int SC = NT >= 256 ? 5 : (NT >= 128 ? 6 : 3);
-  static_assert(2 * SO + H * H * SC <= NT, "batch layout");
+// Candidate batches of the chain kernel: NC candidates per batch, each set
+// up by two threads (the intrinsic and the extrinsic half of the probe).
+// Slots [0, SO) hold left step-out points, [SO, 2 SO) right ones, the rest
+// the first SC shrink candidates of each bracket the step-out can end in
+// with at most H-1 steps per side.
+template <int NC> struct SliceBatch {
+  static constexpr int SO = NC / 8;
+  static constexpr int H = NC >= 64 ? 4 : 2;
+  static constexpr int SC = NC >= 128 ? 6 : (NC >= 64 ? 3 : 6);
+  static_assert(2 * SO + H * H * SC <= NC, "batch layout");
 };
 
 // Dynamic LDS of the chain kernel (doubles), in order: Cholesky factor,
 // reduction slots, directions and uniforms of a chunk of steps, the batch
-// (probe coefficients, positions, Gaussian values, in-cube masks), the chain
-// position, then the likelihood tables (full grid, when they fit) or the
-// edge ratios (relative binning).
+// (probe records, positions, Gaussian values or fallback uniforms, in-cube
+// flags), the chain position, then the likelihood tables (full grid, when
+// they fit) or the edge ratios (relative binning).
 constexpr int SL_CHUNK = 16;                          // steps drawn per chunk
-constexpr int SL_PSTRIDE = (int)((sizeof(Probe) + 15) / 16) * 2;   // doubles per stored probe
+constexpr int SL_PSTRIDE = (int)((sizeof(ProbeRec) + 15) / 16) * 2;   // doubles per stored record
 constexpr int SL_NU = 10;                             // uniforms per step: width, split, 8 shrink
 __host__ __device__ constexpr size_t slice_fixed_doubles(int nt) {
-  return MAX_DIM * MAX_DIM + 16 + SL_CHUNK * MAX_DIM + SL_CHUNK * SL_NU + (size_t)nt * SL_PSTRIDE + nt + nt + 4 + 16;
+  return MAX_DIM * MAX_DIM + 16 + SL_CHUNK * MAX_DIM + SL_CHUNK * SL_NU + (size_t)(nt / 2) * SL_PSTRIDE + nt + nt +
+         nt / 4 + 16;
 }
 
 // One workgroup of NT threads runs chain j = blockIdx.x for all n_steps
 // steps.  The random numbers and tuned directions of a chunk of steps are
-// drawn up front, lane-parallel.  Each step then sets up one batch of NT
-// candidates in parallel (one per thread, each fixed in advance: the
-// step-out points and, under the hypothesis that earlier candidates are
-// rejected, the shrink sequence of every likely bracket); all threads then
-// walk the batch in the sequential order of the algorithm and split every
-// probe's frequency bins.  Rarer outcomes fall back to further batches.
+// drawn up front, lane-parallel.  Each step then sets up one batch of NT/2
+// candidates in parallel (each fixed in advance: the step-out points and,
+// under the hypothesis that earlier candidates are rejected, the shrink
+// sequence of every likely bracket); the first half of the workgroup
+// computes the intrinsic half of every candidate's probe while the second
+// half computes the extrinsic one.  All threads then walk the batch in the
+// sequential order of the algorithm and split every probe's frequency bins.
+// Rarer outcomes fall back to further batches.
 template <int NDET, int NT, int LK, bool LDS>
 __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& RB, const RunDev& R, int j,
                            double* smem) {
   constexpr int NW = NT / 64;
-  constexpr int FB = 32;             // candidates per fallback batch
-  using BL = SliceBatch<NT>;
+  constexpr int NC = NT / 2;         // candidates per batch
+  constexpr int FB = NC < 32 ? NC : 32;   // candidates per fallback batch
+  using BL = SliceBatch<NC>;
   DevState* S = R.state;
   if (S->done) return;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -906,10 +915,10 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
   double* sDir = sred + 16;
   double* sU = sDir + SL_CHUNK * MAX_DIM;
   double* sP = sU + SL_CHUNK * SL_NU;
-  double* sT = sP + NT * SL_PSTRIDE;
+  double* sT = sP + NC * SL_PSTRIDE;
   double* sG = sT + NT;
-  unsigned long long* sMask = reinterpret_cast<unsigned long long*>(sG + NT);
-  double* sX = sG + NT + 4;          // chain position
+  int* sIn = reinterpret_cast<int*>(sG + NT);   // in-cube flag per candidate
+  double* sX = sG + NT + NT / 4;     // chain position
   double* stab = sX + 16;
   for (int i = tid; i < d * d; i += NT) sL[i] = R.chol[i];
   TabView V{};
@@ -924,8 +933,12 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
   const int nbd = (d + 3) >> 2;      // DIR blocks per step
   const double w = R.width;
 
-  // this thread's candidate of a batch, at position tt along dir (valid:
-  // the slot is used; unused slots are marked outside the cube)
+  // candidate c = tid mod NC of a batch, at position tt along dir (valid:
+  // the slot is used; unused slots are marked outside the cube); threads
+  // below NC compute the intrinsic half of its probe, the others the
+  // extrinsic half
+  const int cand = tid % NC;
+  const bool intrinsic_half = tid < NC;
   auto setup = [&](bool valid, double tt, const double* dir) {
     double y[MAX_DIM];
     bool cin = valid;
@@ -938,23 +951,23 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
 #pragma unroll
       for (int i = 0; i < MAX_DIM; ++i) y[i] = 0.5;   // a harmless point; never evaluated
     }
-    if (LK == LK_GAUSS) {
-      sG[tid] = gauss_lambda(M, y);
-    } else {
-      Probe pr;
-      make_probe(M, lk_full(LK) ? T.hpre : nullptr, y, &pr);
-      *reinterpret_cast<Probe*>(sP + tid * SL_PSTRIDE) = pr;
+    ProbeRec* rec = reinterpret_cast<ProbeRec*>(sP + cand * SL_PSTRIDE);
+    if (intrinsic_half) {
+      if (LK == LK_GAUSS) sG[cand] = gauss_lambda(M, y);
+      else probe_intrinsic(M, y, rec);
+      sT[cand] = tt;
+      sIn[cand] = cin ? 1 : 0;
+    } else if (LK != LK_GAUSS) {
+      probe_extrinsic(M, y, rec);
     }
-    sT[tid] = tt;
-    const unsigned long long m = __ballot(cin);
-    if (lane == 0) sMask[wv] = m;
   };
-  auto inside = [&](int q) -> bool { return (sMask[q >> 6] >> (q & 63)) & 1ull; };
+  auto inside = [&](int q) -> bool { return sIn[q] != 0; };
   // lambda of batch candidate q (all threads; contains workgroup barriers)
   auto eval = [&](int q) -> double {
     ++nprobe;
     if (LK == LK_GAUSS) return sG[q];
-    const Probe pb = *reinterpret_cast<const Probe*>(sP + q * SL_PSTRIDE);
+    const Probe pb = probe_from_rec<NDET>(*reinterpret_cast<const ProbeRec*>(sP + q * SL_PSTRIDE),
+                                          lk_full(LK) ? V.hpre : nullptr, V.dstride);
     nbins += lk_full(LK) ? pb.k_act : RB.nb + 1;
     double tot;
     if (lk_rb(LK)) tot = wave_sum(rb_partial<NDET, lk_mixed(LK)>(pb, RB, M.n_bins, stab, tid, NT));
@@ -1043,13 +1056,13 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
       {
         double tt = 0.0;
         bool valid = true;
-        if (tid < 2 * BL::SO) {
-          const bool left = tid < BL::SO;
-          const int steps = left ? tid : tid - BL::SO;
+        if (cand < 2 * BL::SO) {
+          const bool left = cand < BL::SO;
+          const int steps = left ? cand : cand - BL::SO;
           tt = left ? lo : hi;
           for (int q = 0; q < steps; ++q) tt = left ? tt - w : tt + w;
-        } else if (tid < 2 * BL::SO + BL::H * BL::H * BL::SC) {
-          const int h = (tid - 2 * BL::SO) / BL::SC, c = (tid - 2 * BL::SO) - BL::SC * h;
+        } else if (cand < 2 * BL::SO + BL::H * BL::H * BL::SC) {
+          const int h = (cand - 2 * BL::SO) / BL::SC, c = (cand - 2 * BL::SO) - BL::SC * h;
           const int na = h / BL::H, nbh = h - BL::H * na;
           double l2 = lo, h2 = hi;
           for (int q = 0; q < na; ++q) l2 -= w;
@@ -1079,9 +1092,9 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
             // further step-out points of this side: a batch of FB
             __syncthreads();
             double tt = side == 0 ? lo : hi;
-            if (tid < FB)
-              for (int q = 0; q < tid; ++q) tt = side == 0 ? tt - w : tt + w;
-            setup(tid < FB, tt, dir);
+            if (cand < FB)
+              for (int q = 0; q < cand; ++q) tt = side == 0 ? tt - w : tt + w;
+            setup(cand < FB, tt, dir);
             __syncthreads();
             combined = false;
             first = 0;
@@ -1141,11 +1154,11 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
           double l2 = lo, h2 = hi, tl = 0.0;
           for (int q = 0; q < FB; ++q) {
             const double tq = fma(sG[q], h2 - l2, l2);
-            if (q == tid) tl = tq;
+            if (q == cand) tl = tq;
             if (tq < 0.0) l2 = tq; else h2 = tq;
           }
           __syncthreads();   // sG is reused by the Gaussian test likelihood
-          setup(tid < FB, tl, dir);
+          setup(cand < FB, tl, dir);
         }
         __syncthreads();
         for (int q = 0; q < FB && a < R.max_shrink; ++q, ++a) {
