@@ -973,7 +973,7 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
     if (lk_rb(LK)) tot = wave_sum(rb_partial<NDET, lk_mixed(LK)>(pb, RB, M.n_bins, stab, tid, NT));
     else tot = wave_sum(fullgrid_partial<NDET, lk_mixed(LK)>(pb, V, tid, NT));
     if constexpr (NW > 1) {
-      double* rb = sred + buf * NW;
+      double* rb = sred + buf * (NW + 2);
       if (lane == 0) rb[wv] = tot;
       __syncthreads();
       tot = 0.0;
@@ -984,6 +984,41 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
       __syncthreads();   // the edge ratios in LDS are rewritten by the next probe
     }
     return lk_rb(LK) ? tot : tot - 0.5 * pb.hh;
+  };
+  // Full grid with two or more waves: lambdas of two candidates at once
+  // (q < 0: none), the first half of the workgroup summing the bins of q1,
+  // the second those of q2, one barrier for both.  Nothing is counted here:
+  // the walk counts the evaluations the sequential algorithm makes.
+  constexpr bool PAIR = lk_full(LK) && NW >= 2;
+  auto rec = [&](int q) -> const ProbeRec& { return *reinterpret_cast<const ProbeRec*>(sP + q * SL_PSTRIDE); };
+  auto count = [&](int q) {
+    ++nprobe;
+    nbins += rec(q).k_act;
+  };
+  auto eval2 = [&](int q1, int q2, double* l1, double* l2) {
+    constexpr int HW = NW / 2;
+    const bool second = tid >= NT / 2;
+    const int q = second ? q2 : q1;
+    double part = 0.0, hh = 0.0;
+    if (q >= 0) {
+      const Probe pb = probe_from_rec<NDET>(rec(q), V.hpre, V.dstride);
+      part = fullgrid_partial<NDET, lk_mixed(LK)>(pb, V, second ? tid - NT / 2 : tid, NT / 2);
+      hh = pb.hh;
+    }
+    const double tot = wave_sum(part);
+    double* rb = sred + buf * (NW + 2);
+    if (lane == 0) rb[wv] = tot;
+    if (lane == 0 && wv % HW == 0) rb[NW + (second ? 1 : 0)] = hh;
+    __syncthreads();
+    double t1 = 0.0, t2 = 0.0;
+#pragma unroll
+    for (int w2 = 0; w2 < HW; ++w2) {
+      t1 += rb[w2];
+      t2 += rb[HW + w2];
+    }
+    *l1 = t1 - 0.5 * rb[NW];
+    *l2 = t2 - 0.5 * rb[NW + 1];
+    buf ^= 1;
   };
 
   for (int s0 = 0; s0 < R.m; s0 += SL_CHUNK) {
@@ -1081,12 +1116,35 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
 
       // ---- step out, left then right (the order of the sequential algorithm)
       int na = 0, nh = 0;          // successful steps per side
+      int uL = 0, uR = 0;          // batch points of each side already walked
+      if constexpr (PAIR) {
+        // the two sides are independent: walk them together, one pair of
+        // probes per round, while their next points are in the batch; the
+        // probes evaluated are exactly those of the left-then-right walk
+        for (;;) {
+          int qL = (J > 0 && uL < BL::SO) ? uL : -1;
+          int qR = (K > 0 && uR < BL::SO) ? BL::SO + uR : -1;
+          if (qL >= 0 && !inside(qL)) { J = 0; qL = -1; }
+          if (qR >= 0 && !inside(qR)) { K = 0; qR = -1; }
+          if (qL < 0 && qR < 0) break;
+          double lL, lR;
+          eval2(qL, qR, &lL, &lR);
+          if (qL >= 0) {
+            count(qL);
+            if (lL > lstar) { lo -= w; --J; ++na; ++uL; } else { J = 0; }
+          }
+          if (qR >= 0) {
+            count(qR);
+            if (lR > lstar) { hi += w; --K; ++nh; ++uR; } else { K = 0; }
+          }
+        }
+      }
       for (int side = 0; side < 2; ++side) {
         int& budget = side == 0 ? J : K;
         int& done_steps = side == 0 ? na : nh;
         int first = side == 0 ? 0 : BL::SO;   // batch slot of this side's next candidate
         int have = combined ? BL::SO : 0;     // candidates of this side in the batch in LDS
-        int used = 0;
+        int used = combined ? (side == 0 ? uL : uR) : 0;
         while (budget > 0) {
           if (used == have) {
             // further step-out points of this side: a batch of FB
@@ -1114,7 +1172,44 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
       // ---- shrink
       int a = 0;                   // attempts made
       bool accepted = false;
-      if (combined && na < BL::H && nh < BL::H) {
+      if (PAIR && combined && na < BL::H && nh < BL::H) {
+        // attempts a and a+1 together (a+1 under the hypothesis that a is
+        // rejected); a probe is counted only where the sequential walk makes it
+        const int base = 2 * BL::SO + BL::SC * (BL::H * na + nh);
+        while (a < BL::SC && a < R.max_shrink) {
+          const int q1 = base + a;
+          const bool two = a + 1 < BL::SC && a + 1 < R.max_shrink;
+          const int q2 = two ? q1 + 1 : -1;
+          const bool in1 = inside(q1), in2 = two && inside(q2);
+          double l1 = NEG_INF, l2 = NEG_INF;
+          if (in1 || in2) eval2(in1 ? q1 : -1, in2 ? q2 : -1, &l1, &l2);
+          const double t1 = sT[q1];
+          if (in1) {
+            count(q1);
+            if (l1 > lstar) {
+              if (tid < d) sX[tid] = fma(t1, dir[tid], sX[tid]);
+              lx = l1;
+              accepted = true;
+              break;
+            }
+          }
+          if (t1 < 0.0) lo = t1; else hi = t1;
+          ++a;
+          if (!two) continue;
+          const double t2 = sT[q2];
+          if (in2) {
+            count(q2);
+            if (l2 > lstar) {
+              if (tid < d) sX[tid] = fma(t2, dir[tid], sX[tid]);
+              lx = l2;
+              accepted = true;
+              break;
+            }
+          }
+          if (t2 < 0.0) lo = t2; else hi = t2;
+          ++a;
+        }
+      } else if (combined && na < BL::H && nh < BL::H) {
         const int base = 2 * BL::SO + BL::SC * (BL::H * na + nh);
         for (; a < BL::SC && a < R.max_shrink; ++a) {
           const int q = base + a;
