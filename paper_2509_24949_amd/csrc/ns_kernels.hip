@@ -117,6 +117,53 @@ __device__ inline double block_max(double v, double* sbuf) {
   return t;
 }
 
+// Inclusive prefix sum over the NT threads in thread order (wave shuffles,
+// then the wave totals); *total receives the sum of all.  Two barriers;
+// sbuf holds NT/64 values.
+template <int NT, typename T>
+__device__ inline T block_scan(T v, T* sbuf, T* total) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const T u = __shfl_up(v, o, 64);
+    if (lane >= o) v += u;
+  }
+  __syncthreads();
+  if (lane == 63) sbuf[wv] = v;
+  __syncthreads();
+  T off = T(0), all = T(0);
+#pragma unroll
+  for (int w = 0; w < NT / 64; ++w) {
+    if (w < wv) off += sbuf[w];
+    all += sbuf[w];
+  }
+  *total = all;
+  return v + off;
+}
+
+// K block-wide sums at once (two barriers); every thread receives them.
+// sbuf holds K * NT/64 values.
+template <int NT, int K>
+__device__ inline void block_sum_k(double (&v)[K], double* sbuf) {
+  constexpr int NW = NT / 64;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < K; ++q) v[q] = wave_sum(v[q]);
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < K; ++q) sbuf[q * NW + wv] = v[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) t += sbuf[q * NW + w];
+    v[q] = t;
+  }
+}
+
 // Inclusive Hillis-Steele scan over NT values held one per thread.
 template <int NT, typename T>
 __device__ inline T block_inclusive_scan(T v, T* sbuf) {
@@ -696,7 +743,6 @@ __device__ void prep_body(const RunDev& R, int* s_surv) {
   __shared__ double sbuf[1024];
   __shared__ double smean[MAX_DIM];
   __shared__ double scov[MAX_DIM * MAX_DIM];
-  __shared__ double schol[MAX_DIM * MAX_DIM];
   __shared__ int sint[1024];
   DevState* S = R.state;
   const int done0 = S->done;
@@ -717,7 +763,8 @@ __device__ void prep_body(const RunDev& R, int* s_surv) {
   const int jb = tid * C, je = min(k, jb + C);
   double csum = 0.0;
   for (int j = jb; j < je; ++j) csum += 1.0 / (double)(n - j);
-  double incl = block_inclusive_scan<1024, double>(csum, sbuf);
+  double total;                                        // sum of 1/(n-j) over the batch
+  const double incl = block_scan<1024, double>(csum, sbuf, &total);
   double lx = logX0 - (incl - csum);
   double mloc = NEG_INF;
   for (int j = jb; j < je; ++j) {
@@ -738,22 +785,21 @@ __device__ void prep_body(const RunDev& R, int* s_surv) {
     mloc = fmax(mloc, lw);
     lx = lxn;
   }
-  const double total = block_sum<1024>(csum, sbuf);   // sum of 1/(n-j) over the batch
   double m = block_max<1024>(mloc, sbuf);
   m = fmax(m, logZ0);
-  double s1 = 0.0, s2 = 0.0;
+  double s12[2] = {0.0, 0.0};
   if (m > NEG_INF) {
     for (int j = jb; j < je; ++j) {
       const double lw = R.dlogw[nd0 + j];
       if (lw > NEG_INF) {
         const double e = exp(lw - m);
-        s1 += e;
-        s2 += e * order_value(R.dlam[nd0 + j]);
+        s12[0] += e;
+        s12[1] += e * order_value(R.dlam[nd0 + j]);
       }
     }
   }
-  s1 = block_sum<1024>(s1, sbuf);
-  s2 = block_sum<1024>(s2, sbuf);
+  block_sum_k<1024, 2>(s12, sbuf);
+  const double s1 = s12[0], s2 = s12[1];
   if (tid == 0) {
     double logZ1 = logZ0, H1 = H0;
     if (m > NEG_INF) {
@@ -778,63 +824,59 @@ __device__ void prep_body(const RunDev& R, int* s_surv) {
     for (int i = 0; i < MAX_DIM; ++i)
       if (i < d) part[i] += R.u[(size_t)j * d + i];
   }
-#pragma unroll
-  for (int i = 0; i < MAX_DIM; ++i) {
-    if (i < d) {
-      const double t = block_sum<1024>(part[i], sbuf);
-      if (tid == 0) smean[i] = t / n;
+  block_sum_k<1024, MAX_DIM>(part, sbuf);
+  if (tid < d) smean[tid] = part[tid] / n;
+  __syncthreads();
+  // lower-triangle entry e -> (a, b), a >= b, row-major; wave w sums the
+  // entries e = w, w + 16, ... over all points, one point per lane at a time
+  const int E = d * (d + 1) / 2;
+  const int lane = tid & 63, wv = tid >> 6;
+  for (int e = wv; e < E; e += 16) {
+    int ea = 0, r = e;
+    while (r > ea) { r -= ea + 1; ++ea; }
+    const int eb = r;
+    const double ma = smean[ea], mb = smean[eb];
+    double cs = 0.0;
+    for (int j = lane; j < n; j += 64) cs += (R.u[(size_t)j * d + ea] - ma) * (R.u[(size_t)j * d + eb] - mb);
+    cs = wave_sum(cs) / (double)(n - 1);
+    if (lane == 0) {
+      scov[ea * d + eb] = cs;
+      scov[eb * d + ea] = cs;
     }
   }
   __syncthreads();
-  const int E = d * (d + 1) / 2;
-  const int G = 1024 / E;
-  const int e = tid % E, g = tid / E;
-  int ea = 0, eb = 0;
-  {
-    int r = e;
-    while (r > ea) { r -= ea + 1; ++ea; }   // e -> (a, b) with a >= b, row-major lower triangle
-    eb = r;
-  }
-  double cs = 0.0;
-  if (g < G)
-    for (int j = g; j < n; j += G)
-      cs += (R.u[(size_t)j * d + ea] - smean[ea]) * (R.u[(size_t)j * d + eb] - smean[eb]);
-  __syncthreads();
-  sbuf[tid] = cs;
-  __syncthreads();
-  if (tid < E) {
-    double t = 0.0;
-    for (int gg = 0; gg < G; ++gg) t += sbuf[tid + gg * E];
-    t /= (double)(n - 1);
-    scov[ea * d + eb] = t;
-    scov[eb * d + ea] = t;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    // Cholesky factor; on failure add 1e-12 tr/d to the diagonal and retry
-    double* L = schol;
+  if (wv == 0) {
+    // Cholesky factor, one row per lane (row j broadcast from lane j); on
+    // failure add 1e-12 tr/d to the diagonal and retry
+    double L[MAX_DIM];
     bool ok = false;
     for (int attempt = 0; attempt < 2 && !ok; ++attempt) {
       if (attempt == 1) {
         double tr = 0.0;
         for (int i = 0; i < d; ++i) tr += scov[i * d + i];
-        for (int i = 0; i < d; ++i) scov[i * d + i] += 1e-12 * tr / d;
+        if (lane < d) scov[lane * d + lane] += 1e-12 * tr / d;
       }
       ok = true;
-      for (int i = 0; i < d && ok; ++i)
-        for (int j = 0; j <= i; ++j) {
-          double s = scov[i * d + j];
-          for (int q = 0; q < j; ++q) s -= L[i * d + q] * L[j * d + q];
-          if (i == j) {
-            if (!(s > 0.0)) { ok = false; break; }
-            L[i * d + i] = sqrt(s);
-          } else {
-            L[i * d + j] = s / L[j * d + j];
-          }
+#pragma unroll
+      for (int q = 0; q < MAX_DIM; ++q) L[q] = 0.0;
+#pragma unroll
+      for (int j = 0; j < MAX_DIM; ++j) {
+        if (j < d) {
+          double s = lane < d ? scov[lane * d + j] : 0.0;
+#pragma unroll
+          for (int q = 0; q < j; ++q) s -= L[q] * lane_d(L[q], j);
+          const double diag = lane_d(s, j);
+          ok = ok && diag > 0.0;
+          const double ljj = sqrt(fmax(diag, 0.0));
+          L[j] = (lane == j) ? ljj : (lane > j && ljj > 0.0 ? s / ljj : 0.0);
         }
+      }
     }
-    for (int i = 0; i < d; ++i)
-      for (int j = 0; j < d; ++j) R.chol[i * d + j] = ok ? (j <= i ? L[i * d + j] : 0.0) : (i == j ? 1e-6 : 0.0);
+    if (lane < d) {
+#pragma unroll
+      for (int q = 0; q < MAX_DIM; ++q)
+        if (q < d) R.chol[lane * d + q] = ok ? (q <= lane ? L[q] : 0.0) : (q == lane ? 1e-6 : 0.0);
+    }
   }
 
   // ---- survivors in ascending slot order, then the chain start points
@@ -842,7 +884,8 @@ __device__ void prep_body(const RunDev& R, int* s_surv) {
   const int ib = tid * C2, ie = min(n, ib + C2);
   int cnt = 0;
   for (int i = ib; i < ie; ++i) cnt += (R.rank[i] >= k);
-  int icl = block_inclusive_scan<1024, int>(cnt, sint);
+  int all_surv;
+  const int icl = block_scan<1024, int>(cnt, sint, &all_surv);
   int pos = icl - cnt;
   for (int i = ib; i < ie; ++i)
     if (R.rank[i] >= k) s_surv[pos++] = i;
@@ -1299,16 +1342,14 @@ __device__ void term_body(const RunDev& R) {
   double m = NEG_INF;
   for (int i = tid; i < n; i += 1024) m = fmax(m, order_value(R.lam[i]));
   m = block_max<1024>(m, sbuf);
-  double s = 0.0;
-  for (int i = tid; i < n; i += 1024) s += exp(order_value(R.lam[i]) - m);
-  s = block_sum<1024>(s, sbuf);
-  double pe = 0.0, pb = 0.0;
+  double v[3] = {0.0, 0.0, 0.0};   // sum exp(lambda - max), probes, bins
+  for (int i = tid; i < n; i += 1024) v[0] += exp(order_value(R.lam[i]) - m);
   for (int j = tid; j < R.k; j += 1024) {
-    pe += (double)R.probes[j];
-    pb += (double)R.bins[j];
+    v[1] += (double)R.probes[j];
+    v[2] += (double)R.bins[j];
   }
-  pe = block_sum<1024>(pe, sbuf);
-  pb = block_sum<1024>(pb, sbuf);
+  block_sum_k<1024, 3>(v, sbuf);
+  const double s = v[0], pe = v[1], pb = v[2];
   if (tid == 0) {
     const double logz_live = S->logX + m + log(s / n);
     int done = 0;
