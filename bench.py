@@ -26,19 +26,18 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-FP64_PEAK_TFLOPS = 78.6          # MI355X vector FP64
-FP32_PEAK_TFLOPS = 157.3         # MI355X vector FP32 (packed)
+# MI355X vector units: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz
+LANE_OPS = 256 * 4 * 16 * 2.4e9            # 39.3e12 lane-instructions/s
+FP64_PEAK_TFLOPS = 2 * LANE_OPS / 1e12     # FMA: 78.6 TFLOP/s
+FP32_PEAK_TFLOPS = 4 * LANE_OPS / 1e12     # packed FMA: 157.3 TFLOP/s
+TRANS_PEAK_TOPS = LANE_OPS / 4 / 1e12      # single-precision sin/cos/exp/log: quarter rate, 9.8 Tops/s
 SINCOS_FLOPS = 44                # flops of the double-precision sincos in cycles
 PHASE_FLOPS = 24                 # per (probe, bin): PN phase series, shared by the detectors
 DET_FLOPS = 2 + SINCOS_FLOPS + 8 # per (probe, bin, detector): delay, sincos, complex accumulate
-# mixed form per (probe, bin, detector): delay and reduction in double (4), two
-# transcendental float ops (sin, cos), complex accumulate (8)
-DET_FLOPS_MIXED = 4 + 2 + 8
 # relative binning per (probe, edge): the phase (24) and per detector delay,
 # sincos and the complex ratio (2 + sincos + 6); per (probe, coarse bin,
 # detector) the linear-model terms (27), counted per edge as nb/(nb+1) of it
 RB_EDGE_DET = 2 + SINCOS_FLOPS + 6
-RB_EDGE_DET_MIXED = 4 + 2 + 6
 RB_BIN_DET = 27
 
 _GRID2 = "3-detector aligned-spin TaylorF2 (11 parameters), 4017 bins/detector (20-1024 Hz, df 0.25 Hz), network SNR 20"
@@ -59,17 +58,45 @@ def log(msg: str):
     print(msg, file=sys.stderr, flush=True)
 
 
-def flops_per_term(w) -> float:
-    """Algorithmic flops per counted term (full grid: one active bin of one
-    probe; relative binning: one edge of one probe)."""
+def op_mix(w):
+    """Algorithmic work of one counted term (full grid: one active bin of one
+    probe; relative binning: one edge of one probe) as (double-precision
+    flops, single-precision flops, single-precision transcendental ops).
+    The mixed form keeps the phase, the delay and the cycle reduction in
+    double (4 flops per detector) and takes sin and cos on the transcendental
+    unit."""
     from paper_2509_24949_amd import synth
 
-    mixed = w.precision == 1
+    nd = w.n_det
     if w.likelihood == synth.LIKE_RB:
-        nb = w.rb_n_bins
-        edge = RB_EDGE_DET_MIXED if mixed else RB_EDGE_DET
-        return PHASE_FLOPS + w.n_det * edge + w.n_det * RB_BIN_DET * nb / (nb + 1)
-    return PHASE_FLOPS + w.n_det * (DET_FLOPS_MIXED if mixed else DET_FLOPS)
+        bins = nd * RB_BIN_DET * w.rb_n_bins / (w.rb_n_bins + 1)
+        if w.precision == 1:
+            return PHASE_FLOPS + 4 * nd, 6 * nd + bins, 2 * nd
+        return PHASE_FLOPS + nd * RB_EDGE_DET + bins, 0.0, 0.0
+    if w.precision == 1:
+        return PHASE_FLOPS + 4 * nd, 8 * nd, 2 * nd
+    return PHASE_FLOPS + nd * DET_FLOPS, 0.0, 0.0
+
+
+def seconds_per_term(w) -> float:
+    """Shortest time the vector units need for one term of this workload."""
+    f64, f32, tr = op_mix(w)
+    return (f64 / FP64_PEAK_TFLOPS + f32 / FP32_PEAK_TFLOPS + tr / TRANS_PEAK_TOPS) * 1e-12
+
+
+def flops_per_term(w) -> float:
+    """Algorithmic operations per counted term (all kinds together)."""
+    return sum(op_mix(w))
+
+
+def peak_tflops(w) -> float:
+    """Rate of the vector units on this workload's operation mix: its
+    operations over the shortest time the units need for them (double FMA at
+    78.6 TFLOP/s, packed single FMA at 157.3, transcendentals at 9.8 Tops/s).
+    Equals the double-precision peak for the double-precision forms."""
+    f64, f32, tr = op_mix(w)
+    t = f64 / FP64_PEAK_TFLOPS + f32 / FP32_PEAK_TFLOPS + tr / TRANS_PEAK_TOPS
+    return (f64 + f32 + tr) / t
 
 
 def cpu_baseline(name: str, seconds: float, threads: int):
@@ -174,7 +201,7 @@ def serving(args) -> dict:
     srv = binding.Server(max_runs=args.max_runs, graph=args.graph, stream=stream.cuda_stream)
     t0 = time.perf_counter()
     nxt, tickets, lat, srv_logz = 0, {}, {}, {}
-    srv_evals, srv_flops, ticks = 0, 0.0, 0
+    srv_evals, srv_flops, srv_tmin, ticks = 0, 0.0, 0.0, 0
     while len(lat) < n_ev:
         now = time.perf_counter() - t0
         while nxt < n_ev and arrivals[nxt] <= now:
@@ -199,6 +226,7 @@ def serving(args) -> dict:
             srv_logz[i] = (z["logZ"], z["sigma"])
             srv_evals += st["n_evals"]
             srv_flops += stats["bin_terms"] * flops_per_term(events[i])
+            srv_tmin += stats["bin_terms"] * seconds_per_term(events[i])
     span = time.perf_counter() - t0
     srv.close()
     lat_v = [lat[i] for i in range(n_ev)]
@@ -206,7 +234,7 @@ def serving(args) -> dict:
           for i in range(n_ev)]
     log(f"bench: served {n_ev} events in {span:.2f} s over {ticks} ticks; p50 {_pct(lat_v, 50):.2f} s, "
         f"p99 {_pct(lat_v, 99):.2f} s")
-    peak = FP32_PEAK_TFLOPS if precision else FP64_PEAK_TFLOPS
+    peak = srv_flops / srv_tmin / 1e12       # the events' operation mix at the unit rates
     achieved = srv_flops / span / 1e12
     out = {
         "metric": "events/hour",
@@ -267,7 +295,7 @@ def standalone_loglike(w, spec, n_probes: int = 65536, reps: int = 20) -> dict:
     n_terms = int(terms.sum().item())
     r.close()
     flops = n_terms * flops_per_term(w)
-    peak = FP32_PEAK_TFLOPS if w.precision == 1 else FP64_PEAK_TFLOPS
+    peak = peak_tflops(w)
     achieved = flops / launch_s / 1e12
     return {"kernel": "k_loglike_rb" if w.likelihood == 1 else "k_loglike", "probes": n_probes,
             "probe_mix": "half prior draws, half Gaussian (0.02) around the injection in the unit cube",
@@ -370,7 +398,7 @@ def main():
     slice_s = stats["ms_slice"] / K * 1e-3
     achieved = flops_launch / slice_s / 1e12
     mixed = w.precision == 1
-    peak = FP32_PEAK_TFLOPS if mixed else FP64_PEAK_TFLOPS
+    peak = peak_tflops(w)
     traffic = None
     if os.path.exists(args.traffic):
         try:
