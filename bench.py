@@ -42,13 +42,13 @@ RB_BIN_DET = 27
 
 _GRID2 = "3-detector aligned-spin TaylorF2 (11 parameters), 4017 bins/detector (20-1024 Hz, df 0.25 Hz), network SNR 20"
 WORKLOADS = {
-    "cfg2": _GRID2 + ", full-grid Whittle, n_live 1000, n_delete 500, 55 slice steps, FP64",
-    "cfg1": "1-detector TaylorF2 (4 parameters), full-grid Whittle, 473 bins (20-256 Hz, df 0.5 Hz), "
+    "tf2_3det": _GRID2 + ", full-grid Whittle, n_live 1000, n_delete 500, 55 slice steps, FP64",
+    "tf2_1det": "1-detector TaylorF2 (4 parameters), full-grid Whittle, 473 bins (20-256 Hz, df 0.5 Hz), "
             "SNR 15, n_live 500, n_delete 250, 20 slice steps, FP64",
-    "cfg3": _GRID2 + ", relative binning (128 geometric bins), n_live 1000, n_delete 500, 55 slice steps, FP64",
-    "cfg4": _GRID2 + ", full-grid Whittle, n_live 2000, n_delete 1000, 55 slice steps, mixed precision",
-    "cfg4rb": _GRID2 + ", relative binning (128 bins), n_live 2000, n_delete 1000, 55 slice steps, mixed precision",
-    "cfg5": "serving: 64 Poisson-arriving events, 4/8/16/32 s (4017-32129 bins per detector), 1-3 detectors, "
+    "tf2_3det_rb": _GRID2 + ", relative binning (128 geometric bins), n_live 1000, n_delete 500, 55 slice steps, FP64",
+    "tf2_3det_mixed": _GRID2 + ", full-grid Whittle, n_live 2000, n_delete 1000, 55 slice steps, mixed precision",
+    "tf2_3det_rb_mixed": _GRID2 + ", relative binning (128 bins), n_live 2000, n_delete 1000, 55 slice steps, mixed precision",
+    "serving": "serving: 64 Poisson-arriving events, 4/8/16/32 s (4017-32129 bins per detector), 1-3 detectors, "
             "SNR U[8,40], Mc U[5,60], q U[0.125,1], 11 parameters, n_live U{500,1000,2000}, n_delete n_live/2, "
             "full-grid Whittle",
 }
@@ -249,7 +249,7 @@ def serving(args) -> dict:
         "vs_baseline": None,
         "dtype": "f32+f64" if precision else "f64",
         "data": "synthetic (seeded Gaussian noise plus injected TaylorF2 signals; no real detector data)",
-        "config": {"workload": f"cfg5: {WORKLOADS['cfg5']}", "events": n_ev, "max_runs": args.max_runs,
+        "config": {"workload": f"serving: {WORKLOADS['serving']}", "events": n_ev, "max_runs": args.max_runs,
                    "tick_iters": args.tick_iters, "graph": bool(args.graph), "load": args.load,
                    "precision": args.precision},
         "latency_p50_s": _pct(lat_v, 50),
@@ -308,7 +308,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="cfg2", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="tf2_3det", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-run", action="store_true", help="skip the complete-run timing")
@@ -337,8 +337,8 @@ def main():
         print(json.dumps({"copy_mib": args.copy_calibration, "launches": 3}))
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
-              "(the sampler runs on a single GPU)", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              "(the sampler and the server each run on a single GPU)", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -350,7 +350,7 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
     binding.lib()
-    if args.workload == "cfg5":
+    if args.workload == "serving":
         print(json.dumps(serving(args)), flush=True)
         return
     w = synth.workload(args.workload)
@@ -435,7 +435,7 @@ def main():
         out["standalone_loglike"] = standalone_loglike(w, spec)
         log(f"bench: standalone likelihood: {out['standalone_loglike']['evals_per_s'] / 1e6:.0f} M evals/s, "
             f"{out['standalone_loglike']['frac'] * 100:.1f}% of peak")
-    if not args.no_serving and args.workload == "cfg2":
+    if not args.no_serving and args.workload == "tf2_3det":
         sv = serving(args)
         out["serving"] = {k: sv[k] for k in ("value", "unit", "latency_p50_s", "latency_p99_s", "makespan_s",
                                              "evals_per_s", "sequential", "logZ_served_vs_sequential")}

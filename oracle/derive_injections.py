@@ -35,15 +35,15 @@ def optimal_snr(w, theta, fixed_dist_mpc=None) -> float:
 
 def derive() -> dict:
     out = {}
-    w1 = synth.workload("cfg1", distance=1.0)
+    w1 = synth.workload("tf2_1det", distance=1.0)
     rho1 = optimal_snr(w1, w1.theta_inj, fixed_dist_mpc=1.0)
-    out["cfg1"] = {"distance_mpc": rho1 / w1.snr_target, "snr": w1.snr_target,
+    out["tf2_1det"] = {"distance_mpc": rho1 / w1.snr_target, "snr": w1.snr_target,
                    "note": "effective distance of the optimally oriented single-detector injection"}
-    w2 = synth.workload("cfg2", distance=1.0)
+    w2 = synth.workload("tf2_3det", distance=1.0)
     th = np.array(w2.theta_inj, dtype=np.float64)
     th[4] = 1.0
     rho1 = optimal_snr(w2, th)
-    out["cfg2"] = {"distance_mpc": rho1 / w2.snr_target, "snr": w2.snr_target,
+    out["tf2_3det"] = {"distance_mpc": rho1 / w2.snr_target, "snr": w2.snr_target,
                    "note": "luminosity distance of the H1/L1/V1 injection"}
     dist, snr = [], []
     for i in range(synth.SERVING_EVENTS):
@@ -51,7 +51,7 @@ def derive() -> dict:
         rho1 = optimal_snr(w, np.array(w.theta_inj, dtype=np.float64))
         dist.append(rho1 / w.snr_target)
         snr.append(w.snr_target)
-    out["cfg5"] = {"distance_mpc": dist, "snr": snr,
+    out["serving"] = {"distance_mpc": dist, "snr": snr,
                    "note": "luminosity distances of the serving events, in event order"}
     return out
 

@@ -160,19 +160,19 @@ def _kinds(*k):
 def workload(name: str, distance: float | None = None) -> Workload:
     """The named workload.
 
-    ``cfg1``  one detector, 473 bins (20-256 Hz, df 0.5), 4 parameters, FP64, n 500 / k 250.
-    ``cfg2``  H1/L1/V1, 4017 bins (20-1024 Hz, df 0.25), 11 parameters, FP64, n 1000 / k 500.
-    ``cfg3``  cfg2 with the relative-binning likelihood (128 geometric bins).
-    ``cfg4``  cfg2 in the mixed-precision form with n 2000 / k 1000.
-    ``cfg4rb`` cfg3 in the mixed-precision form with n 2000 / k 1000.
+    ``tf2_1det``  one detector, 473 bins (20-256 Hz, df 0.5), 4 parameters, FP64, n 500 / k 250.
+    ``tf2_3det``  H1/L1/V1, 4017 bins (20-1024 Hz, df 0.25), 11 parameters, FP64, n 1000 / k 500.
+    ``tf2_3det_rb``  tf2_3det with the relative-binning likelihood (128 geometric bins).
+    ``tf2_3det_mixed``  tf2_3det in the mixed-precision form with n 2000 / k 1000.
+    ``tf2_3det_rb_mixed`` tf2_3det_rb in the mixed-precision form with n 2000 / k 1000.
 
     ``distance`` overrides the stored SNR-scaled injection distance (used only
     by the script that derives those distances).
     """
     inj = _load_injections()
     two_pi = 2.0 * math.pi
-    if name == "cfg1":
-        d_eff = distance if distance is not None else inj.get("cfg1", {}).get("distance_mpc", 0.0)
+    if name == "tf2_1det":
+        d_eff = distance if distance is not None else inj.get("tf2_1det", {}).get("distance_mpc", 0.0)
         return Workload(
             name=name, model=MODEL_TF2_4P, likelihood=LIKE_FULL, f_lo=20.0, df=0.5, n_bins=473,
             detectors=("H1",),
@@ -183,8 +183,8 @@ def workload(name: str, distance: float | None = None) -> Workload:
             noise_seed=101, fixed_dist_mpc=d_eff, snr_target=15.0,
             n_live=500, n_delete=250, n_steps=20, sampler_seed=1001,
         )
-    if name in ("cfg2", "cfg3", "cfg4", "cfg4rb"):
-        d_inj = distance if distance is not None else inj.get("cfg2", {}).get("distance_mpc", 0.0)
+    if name in ("tf2_3det", "tf2_3det_rb", "tf2_3det_mixed", "tf2_3det_rb_mixed"):
+        d_inj = distance if distance is not None else inj.get("tf2_3det", {}).get("distance_mpc", 0.0)
         w = Workload(
             name=name, model=MODEL_TF2_11P, likelihood=LIKE_FULL, f_lo=20.0, df=0.25, n_bins=4017,
             detectors=("H1", "L1", "V1"),
@@ -195,13 +195,13 @@ def workload(name: str, distance: float | None = None) -> Workload:
             noise_seed=102, snr_target=20.0,
             n_live=1000, n_delete=500, n_steps=55, sampler_seed=2001,
         )
-        if name == "cfg3":
+        if name == "tf2_3det_rb":
             w.likelihood = LIKE_RB
             w.sampler_seed = 3001
-        if name in ("cfg4", "cfg4rb"):
+        if name in ("tf2_3det_mixed", "tf2_3det_rb_mixed"):
             w.n_live, w.n_delete, w.precision = 2000, 1000, 1
             w.sampler_seed = 4001
-            if name == "cfg4rb":
+            if name == "tf2_3det_rb_mixed":
                 w.likelihood = LIKE_RB
         return w
     raise KeyError(name)
@@ -243,12 +243,12 @@ def serving_event(i: int, distance: float | None = None) -> Workload:
     dec = math.asin(float(rng.uniform(-1.0, 1.0)))
     phi_c = float(rng.uniform(0.0, 2.0 * math.pi))
     if distance is None:
-        stored = _load_injections().get("cfg5", {}).get("distance_mpc", [])
+        stored = _load_injections().get("serving", {}).get("distance_mpc", [])
         distance = stored[i] if i < len(stored) else 0.0
     d = float(distance)
     two_pi = 2.0 * math.pi
     return Workload(
-        name=f"cfg5/{i}", model=MODEL_TF2_11P, likelihood=LIKE_FULL, f_lo=20.0, df=1.0 / T,
+        name=f"event/{i}", model=MODEL_TF2_11P, likelihood=LIKE_FULL, f_lo=20.0, df=1.0 / T,
         n_bins=1004 * T + 1, detectors=dets,
         prior_kind=_kinds(0, 0, 0, 0, 3, 1, 0, 0, 2, 0, 0),
         prior_lo=np.array([max(5.0, 0.7 * mc), 0.125, -0.8, -0.8, 0.25 * d, 0.0, 0.0, 0.0, -0.5 * math.pi, -0.1, 0.0]),

@@ -59,17 +59,17 @@ def full_run(w, n_threads: int, **kw) -> dict:
 def main():
     n_threads = int(sys.argv[1]) if len(sys.argv) > 1 else (os.cpu_count() or 1)
     out = {}
-    for name in ("cfg2", "cfg3"):
+    for name in ("tf2_3det", "tf2_3det_rb"):
         out[name] = full_run(synth.workload(name), n_threads)
         print(name, out[name]["iterations"], out[name]["logZ"], flush=True)
     # the large-population workload in double precision (the GPU's mixed form
     # is compared statistically against it)
-    w = synth.workload("cfg4")
+    w = synth.workload("tf2_3det_mixed")
     w.precision = 0
-    out["cfg4_fp64"] = full_run(w, n_threads)
-    print("cfg4_fp64", out["cfg4_fp64"]["logZ"], flush=True)
+    out["tf2_3det_n2000_fp64"] = full_run(w, n_threads)
+    print("tf2_3det_n2000_fp64", out["tf2_3det_n2000_fp64"]["logZ"], flush=True)
     for i in SERVING_SAMPLE:
-        key = f"cfg5/{i}"
+        key = f"event/{i}"
         out[key] = full_run(synth.serving_event(i), n_threads)
         print(key, out[key]["iterations"], out[key]["logZ"], flush=True)
     with open(OUT, "w") as fh:

@@ -49,16 +49,16 @@ def test_invalid_arguments_are_rejected_with_a_message():
 def test_model_validation():
     lib = binding.lib()
     out = C.c_void_p()
-    w = synth.workload("cfg2")
+    w = synth.workload("tf2_3det")
     spec = binding.ProblemSpec(w)
     spec.s.n_dim = 4
     assert lib.ns_init(C.byref(out), spec.ref, C.byref(binding.opts_for(w)), None) == binding.NS_E_ARG
-    w = synth.workload("cfg1")
+    w = synth.workload("tf2_1det")
     w.prior_hi[1] = 0.3          # eta above 1/4
     spec = binding.ProblemSpec(w)
     assert lib.ns_init(C.byref(out), spec.ref, C.byref(binding.opts_for(w)), None) == binding.NS_E_ARG
     assert b"eta" in lib.ns_last_error()
-    w = synth.workload("cfg1")
+    w = synth.workload("tf2_1det")
     psd = binding.ProblemSpec(w)
     psd.psd[0, 10] = 0.0
     assert lib.ns_init(C.byref(out), psd.ref, C.byref(binding.opts_for(w)), None) == binding.NS_E_ARG
@@ -67,7 +67,7 @@ def test_model_validation():
 def test_select_and_waveform_argument_checks():
     lib = binding.lib()
     assert lib.ns_select(None, 10, 3, None, None, None) == binding.NS_E_ARG
-    w = synth.workload("cfg1")
+    w = synth.workload("tf2_1det")
     spec = binding.ProblemSpec(w)
     th = np.array(w.theta_inj)
     h = np.zeros(w.n_bins)

@@ -37,7 +37,7 @@ def _identical(a, b):
         assert a[key] == b[key], key
 
 
-@pytest.mark.parametrize("name,first,then", [("cfg1", 5, 200), ("cfg3", 2, 2), ("cfg4", 1, 2)])
+@pytest.mark.parametrize("name,first,then", [("tf2_1det", 5, 200), ("tf2_3det_rb", 2, 2), ("tf2_3det_mixed", 1, 2)])
 def test_resume_is_bit_identical(torch_cuda, name, first, then):
     w = synth.workload(name)
     re, im = binding.make_data(w)
@@ -62,7 +62,7 @@ def test_resume_is_bit_identical(torch_cuda, name, first, then):
 
 
 def test_truncated_checkpoint_is_rejected(torch_cuda):
-    w = synth.workload("cfg1")
+    w = synth.workload("tf2_1det")
     spec = binding.ProblemSpec(w, *binding.make_data(w))
     opts = binding.opts_for(w)
     a = binding.Run(spec, opts)
@@ -74,7 +74,7 @@ def test_truncated_checkpoint_is_rejected(torch_cuda):
     assert e.value.code == binding.NS_E_ARG
 
 
-@pytest.mark.parametrize("name", ["cfg1", "cfg2"])
+@pytest.mark.parametrize("name", ["tf2_1det", "tf2_3det"])
 def test_noise_loglike_parity(torch_cuda, name):
     w = synth.workload(name)
     re, im = oracle.make_data(w)

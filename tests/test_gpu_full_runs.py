@@ -63,7 +63,7 @@ def _data(w):
     return binding.ProblemSpec(w, re, im)
 
 
-@pytest.mark.parametrize("name", ["cfg2", "cfg3"])
+@pytest.mark.parametrize("name", ["tf2_3det", "tf2_3det_rb"])
 def test_complete_run_matches_oracle(golden, name):
     w = synth.workload(name)
     run = binding.Run(_data(w), binding.opts_for(w))
@@ -73,7 +73,7 @@ def test_complete_run_matches_oracle(golden, name):
 
 
 def test_served_events_match_oracle(golden):
-    keys = sorted(k for k in golden if k.startswith("cfg5/"))
+    keys = sorted(k for k in golden if k.startswith("event/"))
     assert len(keys) >= 4
     srv = binding.Server(max_runs=len(keys))
     tick = {}
@@ -97,7 +97,7 @@ def test_mixed_precision_agrees_with_double(golden):
     """Large-population workload: eight seeds in each precision; the means
     of log Z agree within twice the spread of their difference, and both sit
     within reach of the oracle's double-precision run."""
-    w = synth.workload("cfg4")
+    w = synth.workload("tf2_3det_mixed")
     spec = _data(w)
     z = {0: [], 1: []}
     sig = {0: [], 1: []}
@@ -112,5 +112,5 @@ def test_mixed_precision_agrees_with_double(golden):
     m64, m32 = np.mean(z[0]), np.mean(z[1])
     spread = math.sqrt(np.var(z[0], ddof=1) / 8 + np.var(z[1], ddof=1) / 8)
     assert abs(m32 - m64) <= max(2.0 * spread, 0.05), (m32, m64, spread)
-    g = golden["cfg4_fp64"]
+    g = golden["tf2_3det_n2000_fp64"]
     assert abs(m32 - g["logZ"]) <= 2.0 * math.sqrt(g["sigma"] ** 2 + np.mean(sig[1]) ** 2 / 8)

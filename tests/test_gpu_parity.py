@@ -42,7 +42,7 @@ def _scale(w, orc_prob, u):
     return lam, np.abs(lam + half_hh) + half_hh + 1.0
 
 
-@pytest.mark.parametrize("name", ["cfg1", "cfg2"])
+@pytest.mark.parametrize("name", ["tf2_1det", "tf2_3det"])
 def test_waveform_parity(torch_cuda, name):
     w = synth.workload(name)
     orc = oracle.OracleProblem(w)
@@ -59,7 +59,7 @@ def test_waveform_parity(torch_cuda, name):
                 assert np.array_equal(gr == 0, hr == 0)
 
 
-@pytest.mark.parametrize("name,n", [("cfg1", 4099), ("cfg2", 2053)])
+@pytest.mark.parametrize("name,n", [("tf2_1det", 4099), ("tf2_3det", 2053)])
 def test_loglike_parity(torch_cuda, name, n):
     torch = torch_cuda
     w = synth.workload(name)
@@ -177,8 +177,8 @@ def test_gauss_lockstep_and_closed_form(torch_cuda, d, s, n, k):
     assert abs(np.exp(lw).sum() - 1.0) < 1e-9
 
 
-def test_cfg1_full_run_lockstep(torch_cuda):
-    w = synth.workload("cfg1")
+def test_one_detector_full_run_lockstep(torch_cuda):
+    w = synth.workload("tf2_1det")
     orc, spec = _pair(w)
     ro, rg = _lockstep(w, orc, spec, 1000)
     assert rg.state()["done"]
@@ -189,8 +189,8 @@ def test_cfg1_full_run_lockstep(torch_cuda):
     assert abs(mean[0] - w.theta_inj[0]) < 0.5          # chirp mass recovered
 
 
-def test_cfg2_iterations_lockstep(torch_cuda):
-    w = synth.workload("cfg2")
+def test_three_detector_iterations_lockstep(torch_cuda):
+    w = synth.workload("tf2_3det")
     orc, spec = _pair(w)
     ro, rg = _lockstep(w, orc, spec, 2)
     _compare_runs(ro, rg)
@@ -210,16 +210,16 @@ def test_capacity_and_no_termination(torch_cuda):
 
 @pytest.mark.parametrize("n", [1031])
 def test_rb_loglike_parity(torch_cuda, n):
-    """Relative-binning likelihood (cfg3) against the oracle's, to 1e-9 of the
+    """Relative-binning likelihood (tf2_3det_rb) against the oracle's, to 1e-9 of the
     cancellation scale, including the fiducial point and cube corners."""
     torch = torch_cuda
-    w = synth.workload("cfg3")
+    w = synth.workload("tf2_3det_rb")
     orc, spec = _pair(w)
     u = synth.proposal_batch(w, n, seed=11)
     u[0] = 0.0
     u[1] = 1.0
     u[2] = synth.theta_to_cube_box(w, w.theta_inj)
-    wf = synth.workload("cfg2")
+    wf = synth.workload("tf2_3det")
     orc_full = oracle.OracleProblem(wf, orc.dre, orc.dim)
     _, scale = _scale(wf, orc_full, u)
     lam_o = orc.loglike_batch(u, NTHREADS)
@@ -235,21 +235,21 @@ def test_rb_loglike_parity(torch_cuda, n):
 
 
 def test_rb_iterations_lockstep(torch_cuda):
-    w = synth.workload("cfg3")
+    w = synth.workload("tf2_3det_rb")
     orc, spec = _pair(w)
     ro, rg = _lockstep(w, orc, spec, 2)
     _compare_runs(ro, rg)
 
 
 def test_rb_rejects_degenerate_binning(torch_cuda):
-    w = synth.workload("cfg3")
+    w = synth.workload("tf2_3det_rb")
     w.rb_n_bins = 1000                  # more coarse bins than the grid can separate at low frequency
     spec = binding.ProblemSpec(w)
     with pytest.raises(binding.NSError):
         binding.Run(spec, binding.opts_for(w, n_live=16, n_delete=8))
 
 
-@pytest.mark.parametrize("name", ["cfg4", "cfg4rb"])
+@pytest.mark.parametrize("name", ["tf2_3det_mixed", "tf2_3det_rb_mixed"])
 def test_mixed_precision_loglike_error(torch_cuda, name):
     """Mixed form (float sincos and sums, double phase): the error against the
     double-precision oracle stays below 2e-5 of the cancellation scale."""
@@ -257,7 +257,7 @@ def test_mixed_precision_loglike_error(torch_cuda, name):
     w = synth.workload(name)
     orc, spec = _pair(w)
     u = synth.proposal_batch(w, 2053, seed=13)
-    wf = synth.workload("cfg2")
+    wf = synth.workload("tf2_3det")
     orc_full = oracle.OracleProblem(wf, orc.dre, orc.dim)
     _, scale = _scale(wf, orc_full, u)
     lam_o = orc.loglike_batch(u, NTHREADS)
@@ -273,7 +273,7 @@ def test_mixed_precision_evidence_statistics(torch_cuda):
     (trajectories differ, so the check is statistical): the mean log Z
     difference is below 0.1 plus its standard error and every pair agrees
     within 2 sigma."""
-    w = synth.workload("cfg1")
+    w = synth.workload("tf2_1det")
     orc, spec = _pair(w)
     diffs, sig = [], []
     for r in range(8):

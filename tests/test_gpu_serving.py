@@ -37,15 +37,15 @@ def _requests():
     """Runs of different sizes, networks and likelihood forms, each bounded
     to a few iterations (capacity) except the small complete one."""
     out = []
-    w = synth.workload("cfg1")
-    out.append(("cfg1", _spec(w), binding.opts_for(w)))
-    out.append(("cfg1-b", out[0][1], binding.opts_for(w, seed=77, n_live=300, n_delete=100)))
-    w = synth.workload("cfg2")
-    out.append(("cfg2", _spec(w), binding.opts_for(w, max_iter=3)))
-    w = synth.workload("cfg3")
-    out.append(("cfg3", _spec(w), binding.opts_for(w, max_iter=3)))
-    w = synth.workload("cfg4")
-    out.append(("cfg4", _spec(w), binding.opts_for(w, max_iter=2)))
+    w = synth.workload("tf2_1det")
+    out.append(("tf2_1det", _spec(w), binding.opts_for(w)))
+    out.append(("tf2_1det-b", out[0][1], binding.opts_for(w, seed=77, n_live=300, n_delete=100)))
+    w = synth.workload("tf2_3det")
+    out.append(("tf2_3det", _spec(w), binding.opts_for(w, max_iter=3)))
+    w = synth.workload("tf2_3det_rb")
+    out.append(("tf2_3det_rb", _spec(w), binding.opts_for(w, max_iter=3)))
+    w = synth.workload("tf2_3det_mixed")
+    out.append(("tf2_3det_mixed", _spec(w), binding.opts_for(w, max_iter=2)))
     w = synth.serving_event(1)                 # one detector, 4 s, n_live 2000
     out.append(("event1", _spec(w), binding.opts_for(w, max_iter=2)))
     return out
@@ -86,12 +86,12 @@ def _assert_identical(a, b, name):
 
 
 def test_served_run_matches_oracle(torch_cuda):
-    w = synth.workload("cfg1")
+    w = synth.workload("tf2_1det")
     re, im = oracle.make_data(w)
     orc = oracle.OracleProblem(w, re, im)
     spec = binding.ProblemSpec(w, re, im)
-    res = _serve([("cfg1", spec, binding.opts_for(w))], max_runs=1)
-    info, g = res["cfg1"]
+    res = _serve([("tf2_1det", spec, binding.opts_for(w))], max_runs=1)
+    info, g = res["tf2_1det"]
     ro = oracle.Run(orc, oracle.opts_for(w, n_threads=NTHREADS))
     ro.step(1000)
     a = ro.dead()
@@ -105,7 +105,7 @@ def test_served_run_matches_oracle(torch_cuda):
     assert abs(g["logZ"] - so["logZ"]) <= 1e-9 * (abs(so["logZ"]) + 1.0)
 
 
-@pytest.mark.parametrize("name", ["cfg2", "cfg3"])
+@pytest.mark.parametrize("name", ["tf2_3det", "tf2_3det_rb"])
 def test_served_iterations_match_oracle(torch_cuda, name):
     w = synth.workload(name)
     re, im = oracle.make_data(w)
@@ -139,7 +139,7 @@ def test_result_same_alone_and_in_mix(torch_cuda):
 
 
 def test_admission_by_slots_and_memory(torch_cuda):
-    w = synth.workload("cfg1")
+    w = synth.workload("tf2_1det")
     spec = _spec(w)
     reqs = [(f"r{i}", spec, binding.opts_for(w, seed=500 + i, max_iter=4)) for i in range(4)]
     alone = _serve(reqs[:1], max_runs=1)
@@ -168,7 +168,7 @@ def test_admission_by_slots_and_memory(torch_cuda):
 
 
 def test_ticket_states(torch_cuda):
-    w = synth.workload("cfg1")
+    w = synth.workload("tf2_1det")
     spec = _spec(w)
     srv = binding.Server(max_runs=1)
     t1 = srv.submit(spec, binding.opts_for(w, max_iter=2))

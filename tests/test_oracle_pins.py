@@ -34,7 +34,7 @@ def test_philox_matches_numpy(key, ctr):
 def test_prior_transforms_ks():
     """Transformed uniforms follow the analytic prior CDFs (uniform, isotropic
     inclination, isotropic declination, uniform in volume)."""
-    w = synth.workload("cfg2")
+    w = synth.workload("tf2_3det")
     p = oracle.OracleProblem(w)
     rng = np.random.default_rng(3)
     u = rng.random((4000, w.n_dim))
@@ -56,7 +56,7 @@ def test_prior_transforms_ks():
 
 # ---------------------------------------------------------------- waveform
 def _w4():
-    return synth.workload("cfg1")
+    return synth.workload("tf2_1det")
 
 
 def test_amplitude_from_quadrupole_spa():
@@ -183,7 +183,7 @@ def test_colored_psd_snr_mpmath():
 def test_loglike_distance_and_phase_structure():
     """lambda is exactly a/D - b/D^2 in the distance and an exact sinusoid
     plus constant in phi_c (the waveform carries e^{i phi_c})."""
-    w = synth.workload("cfg2")
+    w = synth.workload("tf2_3det")
     re, im = oracle.make_data(w)
     p = oracle.OracleProblem(w, re, im)
     th = np.array(w.theta_inj, dtype=np.float64)
@@ -248,7 +248,7 @@ def test_noise_loglike_is_the_gaussian_density():
     and the absolute signal log-likelihood (noise term plus lambda) equals
     the same density of the residual d - h (catches a dropped 1/2, a wrong
     variance or a missing detector)."""
-    w = synth.workload("cfg2")
+    w = synth.workload("tf2_3det")
     re, im = oracle.make_data(w)
     p = oracle.OracleProblem(w, re, im)
     sd = np.sqrt(w.psd() / (4.0 * w.df))
@@ -269,7 +269,7 @@ def test_noise_loglike_is_the_gaussian_density():
 
 def test_zero_signal_limit():
     """As the distance grows the signal vanishes and lambda -> 0 like 1/D."""
-    w = synth.workload("cfg2")
+    w = synth.workload("tf2_3det")
     re, im = oracle.make_data(w)
     p = oracle.OracleProblem(w, re, im)
     th = np.array(w.theta_inj, dtype=np.float64)
@@ -282,7 +282,7 @@ def test_rb_exact_at_fiducial_and_for_extrinsic_shifts():
     """At the fiducial the heterodyne ratio is 1 and relative binning equals
     the full-grid likelihood; changing only distance and phase keeps the ratio
     constant, so relative binning stays exact."""
-    w = synth.workload("cfg3")
+    w = synth.workload("tf2_3det_rb")
     re, im = oracle.make_data(w)
     p = oracle.OracleProblem(w, re, im)
     rb = oracle.RB(p)
@@ -302,7 +302,7 @@ def test_rb_exact_at_fiducial_and_for_extrinsic_shifts():
 def test_rb_error_near_fiducial_is_small():
     """Measured, not exact: near the fiducial the relative-binning error stays
     well below one unit of log-likelihood."""
-    w = synth.workload("cfg3")
+    w = synth.workload("tf2_3det_rb")
     re, im = oracle.make_data(w)
     p = oracle.OracleProblem(w, re, im)
     rb = oracle.RB(p)
@@ -494,7 +494,7 @@ def test_two_dim_quadrature_evidence():
     """The first workload with eta and phi_c pinned (degenerate prior
     intervals) and (Mc, t_c) free: the sampler's log Z agrees with brute-force
     quadrature of the likelihood ratio over the prior box."""
-    w = synth.workload("cfg1")
+    w = synth.workload("tf2_1det")
     re, im = oracle.make_data(w)
     w.prior_lo = np.array([23.6, 0.2, -0.004, 1.0])
     w.prior_hi = np.array([24.4, 0.2, 0.004, 1.0])
