@@ -316,9 +316,10 @@ def main():
     ap.add_argument("--no-standalone", action="store_true", help="skip the standalone likelihood kernel")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "slice_kernel_traffic.json"))
     ap.add_argument("--events", type=int, default=64, help="serving: number of events")
-    ap.add_argument("--max-runs", type=int, default=16, help="serving: resident-run slots")
+    ap.add_argument("--max-runs", type=int, default=32, help="serving: resident-run slots")
     ap.add_argument("--tick-iters", type=int, default=1, help="serving: iterations per tick")
-    ap.add_argument("--graph", action="store_true", help="serving: replay ticks from a captured graph")
+    ap.add_argument("--no-graph", dest="graph", action="store_false",
+                    help="serving: launch each tick's kernels directly instead of replaying a captured graph")
     ap.add_argument("--load", type=float, default=2.0, help="serving: arrival rate / sequential service rate")
     ap.add_argument("--precision", default="fp64", choices=("fp64", "mixed"), help="serving: arithmetic")
     ap.add_argument("--max-iter", type=int, default=400, help="serving: iteration capacity per run")

@@ -153,8 +153,8 @@ hipError_t launch_build_rb_edges(const ModelDev* Md, int nb, const RBBuffers& B,
 hipError_t launch_build_rb_sums(const ModelDev& M, const ModelDev* Md, const Tables& T, const double* hw,
                                 const double* theta_fid_dev, int nb, const RBBuffers& B, hipStream_t st);
 hipError_t configure_slice(const ModelDev& M, int rb_nb, LaunchCfg* C);
-// Chain-kernel set-up of runs that take part in packed launches: 128
-// threads per chain (64 or 256 through NS_PACKED_THREADS, for tuning),
+// Chain-kernel set-up of runs that take part in packed launches: 64
+// threads per chain (128 or 256 through NS_PACKED_THREADS, for tuning),
 // tables read through the caches (as in the packed kernel).
 hipError_t configure_slice_packed(const ModelDev& M, int rb_nb, LaunchCfg* C);
 // One iteration of every run in `runs` (device array of nr descriptors):

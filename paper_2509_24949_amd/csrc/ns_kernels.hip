@@ -1758,9 +1758,9 @@ hipError_t launch_iteration(const ModelDev& M, const ModelDev* Md, const Tables&
 }
 
 hipError_t configure_slice_packed(const ModelDev& M, int rb_nb, LaunchCfg* C) {
-  // a resident mix already holds thousands of chains: two waves per chain
-  // leave more chains in flight than four and waste fewer lanes on short probes
-  C->slice_threads = 128;
+  // a resident mix already holds thousands of chains: one wave per chain
+  // keeps the most chains in flight and wastes the fewest lanes on short probes
+  C->slice_threads = 64;
   if (const char* ev = getenv("NS_PACKED_THREADS")) {     // tuning override: 64, 128 or 256
     const int v = atoi(ev);
     if (v == 64 || v == 128 || v == 256) C->slice_threads = v;

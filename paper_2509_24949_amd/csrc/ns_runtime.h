@@ -123,7 +123,7 @@ struct ns_run {
 namespace ns {
 // Validate, allocate and fill a run: tables, initial population and its
 // likelihoods, on stream st (synchronised before returning).  packed selects
-// the launch configuration of the packed serving kernels (128 threads per
+// the launch configuration of the packed serving kernels (64 threads per
 // chain, tables read through the caches), under which a run's arithmetic
 // is the same alone and in any mix.
 int run_create(ns_run** out, const ns_problem* P, const ns_opts* O, hipStream_t st, bool packed);

@@ -4,7 +4,7 @@
 // chains of all resident runs that share a likelihood form, so small runs
 // fill the device together instead of one after another.
 //
-// Every resident run is built with the packed launch configuration (128
+// Every resident run is built with the packed launch configuration (64
 // threads per chain, tables read through the caches) and each workgroup of a
 // packed launch computes exactly what the same workgroup computes when the run
 // is alone, so a run's results do not depend on what else is resident.
