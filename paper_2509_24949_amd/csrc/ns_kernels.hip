@@ -184,14 +184,16 @@ __device__ inline T block_inclusive_scan(T v, T* sbuf) {
 // Pointers of the full-grid tables as one chain or probe sees them: either
 // the HBM arrays or a copy of their active prefix in LDS.
 struct TabView {
-  const double* f;
+  const double* f;      // bin k of f, f13, lnf3, fm53 at [k * ts]
   const double* f13;
   const double* lnf3;
   const double* fm53;
-  const double2* dw;
-  const float2* dw32;
+  int ts;
+  const double2* dw;    // detector d, bin k at [k * dk + d * dd]
+  const float2* dw32;   // (the same strides in float2 units)
+  int dk, dd;
   const double* hpre;   // prefix sums of 4 df f^(-7/3) / S per detector
-  int dstride;          // row stride of dw, dw32 and hpre
+  int hstride;          // row stride of hpre
   double inv_scale;     // 1 / dw_scale of the float table
 };
 
@@ -206,32 +208,42 @@ __device__ inline TabView stage_tables(const ModelDev& M, const Tables& T, bool 
   TabView V;
   if (!use_lds) {
     V.f = T.f; V.f13 = T.f13; V.lnf3 = T.lnf3; V.fm53 = T.fm53; V.dw = T.dw; V.dw32 = T.dw32; V.hpre = T.hpre;
-    V.dstride = M.n_bins;
+    V.ts = 1;
+    V.dk = 1;
+    V.dd = M.n_bins;
+    V.hstride = M.n_bins;
     V.inv_scale = MX ? 1.0 / M.dw_scale : 1.0;
     return V;
   }
+  // one record per bin: f, f^(1/3), ln f / 3, f^(-5/3), then the detectors'
+  // data (double2 each, or float2 in the mixed form), so a bin is read from
+  // one base address; the prefix table follows the records
   const int K = M.k_lim;
-  double* f = lds;
-  double* f13 = f + K;
-  double* lnf3 = f13 + K;
-  double* fm53 = lnf3 + K;
-  // the complex data first (16-byte aligned: 4 K doubles in), then the prefix table
-  double2* dw = reinterpret_cast<double2*>(fm53 + K);
-  float2* dw32 = reinterpret_cast<float2*>(fm53 + K);
-  double* hp = MX ? reinterpret_cast<double*>(dw32 + NDET * K) : reinterpret_cast<double*>(dw + NDET * K);
+  constexpr int RD = MX ? 4 + NDET : 4 + 2 * NDET;   // doubles per record (even without MX: 16-byte aligned)
   for (int k = tid; k < K; k += nt) {
-    f[k] = T.f[k];
-    f13[k] = T.f13[k];
-    lnf3[k] = T.lnf3[k];
-    fm53[k] = T.fm53[k];
+    double* rec = lds + (size_t)k * RD;
+    rec[0] = T.f[k];
+    rec[1] = T.f13[k];
+    rec[2] = T.lnf3[k];
+    rec[3] = T.fm53[k];
 #pragma unroll
     for (int d = 0; d < NDET; ++d) {
-      hp[d * K + k] = T.hpre[(size_t)d * M.n_bins + k];
-      if (MX) dw32[d * K + k] = T.dw32[(size_t)d * M.n_bins + k];
-      else dw[d * K + k] = T.dw[(size_t)d * M.n_bins + k];
+      if (MX) reinterpret_cast<float2*>(rec + 4)[d] = T.dw32[(size_t)d * M.n_bins + k];
+      else reinterpret_cast<double2*>(rec + 4)[d] = T.dw[(size_t)d * M.n_bins + k];
     }
   }
-  V.f = f; V.f13 = f13; V.lnf3 = lnf3; V.fm53 = fm53; V.dw = dw; V.dw32 = dw32; V.hpre = hp; V.dstride = K;
+  double* hp = lds + (size_t)K * RD;
+  for (int i = tid; i < NDET * K; i += nt) {
+    const int d = i / K, k = i - d * K;
+    hp[i] = T.hpre[(size_t)d * M.n_bins + k];
+  }
+  V.f = lds; V.f13 = lds + 1; V.lnf3 = lds + 2; V.fm53 = lds + 3; V.ts = RD;
+  V.dw = reinterpret_cast<const double2*>(lds + 4);
+  V.dw32 = reinterpret_cast<const float2*>(lds + 4);
+  V.dk = MX ? RD : RD / 2;      // record stride in float2 or double2 units
+  V.dd = 1;
+  V.hpre = hp;
+  V.hstride = K;
   V.inv_scale = MX ? 1.0 / M.dw_scale : 1.0;
   return V;
 }
@@ -294,13 +306,14 @@ __device__ inline double fullgrid_partial(const Probe& p, const TabView& V, int 
     // float sincos and compensated float sums of the scaled data
     KahanF a[NDET], b[NDET];
     for (int k = lane; k < p.k_act; k += nl) {
-      const double f = V.f[k];
-      const double psi = phase_cycles(p, f, V.f13[k], V.lnf3[k], V.fm53[k]);
+      const size_t kt = (size_t)k * V.ts;
+      const double f = V.f[kt];
+      const double psi = phase_cycles(p, f, V.f13[kt], V.lnf3[kt], V.fm53[kt]);
 #pragma unroll
       for (int d = 0; d < NDET; ++d) {
         const double ph = fma(f, p.dt[d], psi);
         const float2 sc = sincos_cycles_f32((float)(ph - rint(ph)));
-        const float2 D = V.dw32[d * V.dstride + k];
+        const float2 D = V.dw32[(size_t)k * V.dk + d * V.dd];
         a[d].add(fmaf(D.x, sc.y, -D.y * sc.x));
         b[d].add(fmaf(D.x, sc.x, D.y * sc.y));
       }
@@ -315,13 +328,14 @@ __device__ inline double fullgrid_partial(const Probe& p, const TabView& V, int 
 #pragma unroll
     for (int d = 0; d < NDET; ++d) { a[d] = 0.0; b[d] = 0.0; }
     for (int k = lane; k < p.k_act; k += nl) {
-      const double f = V.f[k];
-      const double psi = phase_cycles(p, f, V.f13[k], V.lnf3[k], V.fm53[k]);
+      const size_t kt = (size_t)k * V.ts;
+      const double f = V.f[kt];
+      const double psi = phase_cycles(p, f, V.f13[kt], V.lnf3[kt], V.fm53[kt]);
 #pragma unroll
       for (int d = 0; d < NDET; ++d) {
         const double2 sc_ = sincos_cycles(fma(f, p.dt[d], psi));
         const double sn = sc_.x, cs = sc_.y;
-        const double2 D = V.dw[d * V.dstride + k];
+        const double2 D = V.dw[(size_t)k * V.dk + d * V.dd];
         a[d] = fma(D.x, cs, fma(-D.y, sn, a[d]));
         b[d] = fma(D.x, sn, fma(D.y, cs, b[d]));
       }
@@ -1010,7 +1024,7 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
     ++nprobe;
     if (LK == LK_GAUSS) return sG[q];
     const Probe pb = probe_from_rec<NDET>(*reinterpret_cast<const ProbeRec*>(sP + q * SL_PSTRIDE),
-                                          lk_full(LK) ? V.hpre : nullptr, V.dstride);
+                                          lk_full(LK) ? V.hpre : nullptr, V.hstride);
     nbins += lk_full(LK) ? pb.k_act : RB.nb + 1;
     double tot;
     if (lk_rb(LK)) tot = wave_sum(rb_partial<NDET, lk_mixed(LK)>(pb, RB, M.n_bins, stab, tid, NT));
@@ -1044,7 +1058,7 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
     const int q = second ? q2 : q1;
     double part = 0.0, hh = 0.0;
     if (q >= 0) {
-      const Probe pb = probe_from_rec<NDET>(rec(q), V.hpre, V.dstride);
+      const Probe pb = probe_from_rec<NDET>(rec(q), V.hpre, V.hstride);
       part = fullgrid_partial<NDET, lk_mixed(LK)>(pb, V, second ? tid - NT / 2 : tid, NT / 2);
       hh = pb.hh;
     }
