@@ -341,7 +341,7 @@ int run_create(ns_run** out, const ns_problem* P, const ns_opts* O, hipStream_t 
   }
 #undef ALLOC
   if (packed) (void)configure_slice_packed(r->M, r->RB.nb, &r->C);
-  else (void)configure_slice(r->M, r->RB.nb, &r->C);
+  else (void)configure_slice(r->M, r->RB.nb, R.k, &r->C);
   DevState s0{};
   s0.logX = 0.0;
   s0.logZ = -__builtin_inf();

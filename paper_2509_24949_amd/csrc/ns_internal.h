@@ -152,7 +152,10 @@ hipError_t launch_to_float(const double* src, float* dst, size_t n, double scale
 hipError_t launch_build_rb_edges(const ModelDev* Md, int nb, const RBBuffers& B, hipStream_t st);
 hipError_t launch_build_rb_sums(const ModelDev& M, const ModelDev* Md, const Tables& T, const double* hw,
                                 const double* theta_fid_dev, int nb, const RBBuffers& B, hipStream_t st);
-hipError_t configure_slice(const ModelDev& M, int rb_nb, LaunchCfg* C);
+// Chain-kernel set-up of a run with n_chains chains: staged tables if they
+// fit, then the widest workgroup (256, 128 or 64 threads) that keeps every
+// chain resident at once.
+hipError_t configure_slice(const ModelDev& M, int rb_nb, int n_chains, LaunchCfg* C);
 // Chain-kernel set-up of runs that take part in packed launches: 64
 // threads per chain (128 or 256 through NS_PACKED_THREADS, for tuning),
 // tables read through the caches (as in the packed kernel).

@@ -515,12 +515,73 @@ __global__ void k_rb_sums(const ModelDev* __restrict__ Mp, Tables T, const doubl
 // Re(A0 r0 + A1 r1) - 1/2 [B0 |r0|^2 + 2 B1 Re(conj(r0) r1)]; bins whose first
 // fine bin is above f_ISCO are skipped and the straddling bin uses the sums
 // up to its last active fine bin.  Contains one workgroup barrier.
+// Relative-binning tables staged in LDS by a chain workgroup (doubles from a
+// 16-byte aligned base): edge frequencies and their powers, fiducial phases,
+// 1 / bin width, edge indices, then the bin sums (double, or float in the
+// mixed form).  The cumulative sums of the straddling bin stay in HBM.
+__host__ __device__ inline size_t rb_stage_doubles(int nb, int n_det, bool mixed) {
+  const size_t ne = nb + 1, nbd = (size_t)n_det * nb;
+  size_t o = (4 + (size_t)n_det) * ne + nb + (ne + 1) / 2;
+  o += o & 1;
+  return o + (mixed ? 2 * nbd + 2 * ((nbd + 1) / 2) : 6 * nbd);
+}
+
 template <int NDET, bool MX>
-__device__ inline double rb_partial(const Probe& p, const RBTables& B, int n_bins, void* lds, int tid, int nt) {
+__device__ inline RBTables stage_rb(const RBTables& B, double* lds, int tid, int nt) {
+  RBTables V = B;
+  const int nb = B.nb, ne = nb + 1, nbd = NDET * nb;
+  double* fe = lds;
+  double* fe13 = fe + ne;
+  double* lnfe3 = fe13 + ne;
+  double* fem53 = lnfe3 + ne;
+  double* phi0 = fem53 + ne;
+  double* inv_w = phi0 + NDET * ne;
+  int* edge = reinterpret_cast<int*>(inv_w + nb);
+  size_t o = (size_t)(4 + NDET) * ne + nb + (ne + 1) / 2;
+  o += o & 1;
+  for (int e = tid; e < ne; e += nt) {
+    fe[e] = B.fe[e];
+    fe13[e] = B.fe13[e];
+    lnfe3[e] = B.lnfe3[e];
+    fem53[e] = B.fem53[e];
+    edge[e] = B.edge[e];
+#pragma unroll
+    for (int d = 0; d < NDET; ++d) phi0[d * ne + e] = B.phi0[d * ne + e];
+  }
+  for (int b = tid; b < nb; b += nt) inv_w[b] = B.inv_w[b];
+  V.fe = fe; V.fe13 = fe13; V.lnfe3 = lnfe3; V.fem53 = fem53; V.phi0 = phi0; V.inv_w = inv_w; V.edge = edge;
+  if constexpr (MX) {
+    float2* a0 = reinterpret_cast<float2*>(lds + o);
+    float2* a1 = a0 + nbd;
+    float* b0 = reinterpret_cast<float*>(a1 + nbd);
+    float* b1 = b0 + 2 * ((nbd + 1) / 2);
+    for (int i = tid; i < nbd; i += nt) {
+      a0[i] = B.A0f[i]; a1[i] = B.A1f[i]; b0[i] = B.B0f[i]; b1[i] = B.B1f[i];
+    }
+    V.A0f = a0; V.A1f = a1; V.B0f = b0; V.B1f = b1;
+  } else {
+    double2* a0 = reinterpret_cast<double2*>(lds + o);
+    double2* a1 = a0 + nbd;
+    double* b0 = reinterpret_cast<double*>(a1 + nbd);
+    double* b1 = b0 + nbd;
+    for (int i = tid; i < nbd; i += nt) {
+      a0[i] = B.A0[i]; a1[i] = B.A1[i]; b0[i] = B.B0[i]; b1[i] = B.B1[i];
+    }
+    V.A0 = a0; V.A1 = a1; V.B0 = b0; V.B1 = b1;
+  }
+  return V;
+}
+
+// This thread's share of a relative-binning likelihood; lds holds the edge
+// ratios of the probe.  Every thread of the workgroup calls it (it contains a
+// barrier); an inactive caller only takes part in the barrier.
+template <int NDET, bool MX>
+__device__ inline double rb_partial(const Probe& p, const RBTables& B, int n_bins, void* lds, int tid, int nt,
+                                    bool active = true) {
   using CT = typename std::conditional<MX, float2, double2>::type;
   CT* sr = reinterpret_cast<CT*>(lds);
   const int nb = B.nb;
-  for (int e = tid; e <= nb; e += nt) {
+  for (int e = active ? tid : nb + 1; e <= nb; e += nt) {
     const double f = B.fe[e];
     const double psi = phase_cycles(p, f, B.fe13[e], B.lnfe3[e], B.fem53[e]);
 #pragma unroll
@@ -540,7 +601,7 @@ __device__ inline double rb_partial(const Probe& p, const RBTables& B, int n_bin
   }
   __syncthreads();
   double part = 0.0;
-  for (int b = tid; b < nb; b += nt) {
+  for (int b = active ? tid : nb; b < nb; b += nt) {
     const int first = B.edge[b];
     if (first >= p.k_act) continue;
     const int last = (b < nb - 1) ? B.edge[b + 1] - 1 : B.edge[nb];
@@ -980,6 +1041,17 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
   for (int i = tid; i < d * d; i += NT) sL[i] = R.chol[i];
   TabView V{};
   if (lk_full(LK)) V = stage_tables<NDET, lk_mixed(LK)>(M, T, LDS, stab, tid, NT);
+  // relative binning: the tables (staged in LDS when LDS is set) and the edge
+  // ratios of up to two probes at once
+  RBTables RBv = RB;
+  double* sr0 = stab;
+  if constexpr (lk_rb(LK)) {
+    if constexpr (LDS) {
+      RBv = stage_rb<NDET, lk_mixed(LK)>(RB, stab, tid, NT);
+      sr0 = stab + rb_stage_doubles(RB.nb, NDET, lk_mixed(LK));
+    }
+  }
+  double* sr1 = sr0 + (size_t)NDET * (RB.nb + 1) * (lk_mixed(LK) ? 1 : 2);
 
   int buf = 0;
   int nprobe = 0;
@@ -1027,7 +1099,7 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
                                           lk_full(LK) ? V.hpre : nullptr, V.hstride);
     nbins += lk_full(LK) ? pb.k_act : RB.nb + 1;
     double tot;
-    if (lk_rb(LK)) tot = wave_sum(rb_partial<NDET, lk_mixed(LK)>(pb, RB, M.n_bins, stab, tid, NT));
+    if (lk_rb(LK)) tot = wave_sum(rb_partial<NDET, lk_mixed(LK)>(pb, RBv, M.n_bins, sr0, tid, NT));
     else tot = wave_sum(fullgrid_partial<NDET, lk_mixed(LK)>(pb, V, tid, NT));
     if constexpr (NW > 1) {
       double* rb = sred + buf * (NW + 2);
@@ -1046,18 +1118,23 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
   // (q < 0: none), the first half of the workgroup summing the bins of q1,
   // the second those of q2, one barrier for both.  Nothing is counted here:
   // the walk counts the evaluations the sequential algorithm makes.
-  constexpr bool PAIR = lk_full(LK) && NW >= 2;
+  constexpr bool PAIR = (lk_full(LK) || lk_rb(LK)) && NW >= 2;
   auto rec = [&](int q) -> const ProbeRec& { return *reinterpret_cast<const ProbeRec*>(sP + q * SL_PSTRIDE); };
   auto count = [&](int q) {
     ++nprobe;
-    nbins += rec(q).k_act;
+    nbins += lk_full(LK) ? rec(q).k_act : RB.nb + 1;
   };
   auto eval2 = [&](int q1, int q2, double* l1, double* l2) {
     constexpr int HW = NW / 2;
     const bool second = tid >= NT / 2;
     const int q = second ? q2 : q1;
     double part = 0.0, hh = 0.0;
-    if (q >= 0) {
+    if constexpr (lk_rb(LK)) {
+      // both halves pass the barrier inside rb_partial
+      const Probe pb = q >= 0 ? probe_from_rec<NDET>(rec(q), nullptr, 0) : Probe{};
+      part = rb_partial<NDET, lk_mixed(LK)>(pb, RBv, M.n_bins, second ? sr1 : sr0, second ? tid - NT / 2 : tid, NT / 2,
+                                            q >= 0);
+    } else if (q >= 0) {
       const Probe pb = probe_from_rec<NDET>(rec(q), V.hpre, V.hstride);
       part = fullgrid_partial<NDET, lk_mixed(LK)>(pb, V, second ? tid - NT / 2 : tid, NT / 2);
       hh = pb.hh;
@@ -1607,8 +1684,11 @@ template <int NDET, int NT>
 hipError_t launch_slice_nt(const ModelDev& M, const ModelDev* Md, const Tables& T, const RBTables& RB,
                            const RunDev& R, const LaunchCfg& C, hipStream_t st) {
   if (M.likelihood == LK_RB) {
-    if (M.mixed) return launch_slice_t<NDET, NT, LK_RB32, false>(Md, T, RB, R, C.lds_bytes, st);
-    return launch_slice_t<NDET, NT, LK_RB, false>(Md, T, RB, R, C.lds_bytes, st);
+    if (M.mixed)
+      return C.lds_tables ? launch_slice_t<NDET, NT, LK_RB32, true>(Md, T, RB, R, C.lds_bytes, st)
+                          : launch_slice_t<NDET, NT, LK_RB32, false>(Md, T, RB, R, C.lds_bytes, st);
+    return C.lds_tables ? launch_slice_t<NDET, NT, LK_RB, true>(Md, T, RB, R, C.lds_bytes, st)
+                        : launch_slice_t<NDET, NT, LK_RB, false>(Md, T, RB, R, C.lds_bytes, st);
   }
   if (M.mixed) {
     if (C.lds_tables) return launch_slice_t<NDET, NT, LK_FULL32, true>(Md, T, RB, R, C.lds_bytes, st);
@@ -1634,35 +1714,52 @@ size_t slice_lds_fixed(int nt) { return slice_fixed_doubles(nt) * sizeof(double)
 
 int likelihood_kind(const ModelDev& M) { return M.likelihood; }
 
-hipError_t configure_slice(const ModelDev& M, int rb_nb, LaunchCfg* C) {
+hipError_t configure_slice(const ModelDev& M, int rb_nb, int n_chains, LaunchCfg* C) {
   if (M.likelihood == LK_GAUSS) {
     C->slice_threads = 64;
     C->lds_tables = false;
     C->lds_bytes = slice_lds_fixed(64);
     return hipSuccess;
   }
-  if (M.likelihood == LK_RB) {
-    C->slice_threads = rb_nb < 96 ? 64 : (rb_nb < 192 ? 128 : 256);
-    if (const char* ev = getenv("NS_SLICE_THREADS")) {
-      const int v = atoi(ev);
-      if (v == 64 || v == 128 || v == 256) C->slice_threads = v;
-    }
-    C->lds_tables = false;
-    C->lds_bytes = slice_lds_fixed(C->slice_threads) +
-                   (size_t)M.n_det * (rb_nb + 1) * (M.mixed ? sizeof(float2) : sizeof(double2));
-    return hipSuccess;
-  }
-  const long work = (long)M.k_lim * M.n_det;   // (bin, detector) terms of the widest probe
-  C->slice_threads = work <= 96 ? 64 : (work <= 320 ? 128 : 256);
-  const size_t tab = staged_table_bytes(M.k_lim, M.n_det, M.mixed != 0);
+  const bool rb = M.likelihood == LK_RB;
+  // LDS of a chain workgroup: its own data, the relative-binning edge ratios
+  // of two probes, and the staged tables (optional)
+  const size_t ratios = rb ? 2 * (size_t)M.n_det * (rb_nb + 1) * (M.mixed ? sizeof(float2) : sizeof(double2)) : 0;
+  const size_t tab = rb ? rb_stage_doubles(rb_nb, M.n_det, M.mixed != 0) * sizeof(double)
+                        : staged_table_bytes(M.k_lim, M.n_det, M.mixed != 0);
+  auto lds_of = [&](int nt, bool stage) { return slice_lds_fixed(nt) + ratios + (stage ? tab : 0); };
+  // every chain should be resident at once: a CU holds eight waves of the
+  // chain kernel (its registers allow two per SIMD) and 160 KB of LDS
+  auto resident = [&](int nt, bool stage) {
+    const long by_waves = 8 / (nt / 64);
+    const long by_lds = (long)(160 * 1024 / lds_of(nt, stage));
+    return 256L * (by_waves < by_lds ? by_waves : by_lds);
+  };
+  int force_nt = 0;
   if (const char* ev = getenv("NS_SLICE_THREADS")) {      // tuning override: 64, 128 or 256
     const int v = atoi(ev);
-    if (v == 64 || v == 128 || v == 256) C->slice_threads = v;
+    if (v == 64 || v == 128 || v == 256) force_nt = v;
   }
-  // stage the tables in LDS only while two chain workgroups still fit a CU
-  C->lds_tables = slice_lds_fixed(C->slice_threads) + tab <= 80 * 1024;
-  if (const char* ev = getenv("NS_LDS_TABLES")) C->lds_tables = C->lds_tables && atoi(ev) != 0;   // tuning override
-  C->lds_bytes = slice_lds_fixed(C->slice_threads) + (C->lds_tables ? tab : 0);
+  bool allow_stage = true;
+  if (const char* ev = getenv("NS_LDS_TABLES")) allow_stage = atoi(ev) != 0;   // tuning override
+  // prefer staged tables, then the widest workgroup that keeps every chain resident
+  int nt = 64;
+  bool stage = false, found = false;
+  for (int pass = 0; pass < 2 && !found; ++pass) {
+    const bool st = pass == 0;
+    if (st && !allow_stage) continue;
+    for (int cand = 256; cand >= 64 && !found; cand /= 2) {
+      if (force_nt && cand != force_nt) continue;
+      if (resident(cand, st) >= n_chains) { nt = cand; stage = st; found = true; }
+    }
+  }
+  if (!found) {   // more chains than resident slots: the narrowest workgroup
+    nt = force_nt ? force_nt : 64;
+    stage = allow_stage && lds_of(nt, true) <= 80 * 1024;
+  }
+  C->slice_threads = nt;
+  C->lds_tables = stage;
+  C->lds_bytes = lds_of(nt, stage);
   return hipSuccess;
 }
 
@@ -1781,7 +1878,8 @@ hipError_t configure_slice_packed(const ModelDev& M, int rb_nb, LaunchCfg* C) {
   }
   C->lds_tables = false;
   C->lds_bytes = slice_lds_fixed(C->slice_threads);
-  if (M.likelihood == LK_RB) C->lds_bytes += (size_t)M.n_det * (rb_nb + 1) * (M.mixed ? sizeof(float2) : sizeof(double2));
+  if (M.likelihood == LK_RB)
+    C->lds_bytes += 2 * (size_t)M.n_det * (rb_nb + 1) * (M.mixed ? sizeof(float2) : sizeof(double2));
   return hipSuccess;
 }
 
