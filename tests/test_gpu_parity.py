@@ -289,3 +289,46 @@ def test_mixed_precision_evidence_statistics(torch_cuda):
     diffs = np.array(diffs)
     print("mixed - oracle log Z:", diffs)
     assert abs(diffs.mean()) <= 0.1 + 2 * np.mean(sig) / math.sqrt(len(diffs))
+
+
+_ORACLE_RUNS = {}
+
+
+def _oracle_two_iterations(name):
+    """The oracle's first two iterations of a workload (computed once)."""
+    if name not in _ORACLE_RUNS:
+        w = synth.workload(name)
+        orc, spec = _pair(w)
+        ro = oracle.Run(orc, oracle.opts_for(w, n_threads=NTHREADS))
+        ro.step(2)
+        _ORACLE_RUNS[name] = (w, spec, ro)
+    return _ORACLE_RUNS[name]
+
+
+@pytest.mark.parametrize("name", ["tf2_3det", "tf2_3det_rb"])
+@pytest.mark.parametrize("threads,stage", [(64, "1"), (128, "1"), (256, "1"), (64, "0"), (256, "0")])
+def test_chain_configurations_lockstep(torch_cuda, monkeypatch, name, threads, stage):
+    """Every chain-kernel configuration (workgroup size, paired or single
+    evaluation, tables staged in LDS or read through the caches) follows the
+    oracle in lockstep."""
+    monkeypatch.setenv("NS_SLICE_THREADS", str(threads))
+    monkeypatch.setenv("NS_LDS_TABLES", stage)
+    w, spec, ro = _oracle_two_iterations(name)
+    rg = binding.Run(spec, binding.opts_for(w))
+    rg.step(2)
+    st = rg.stats()
+    assert st["slice_threads"] == threads
+    if stage == "0":
+        assert st["lds_tables"] == 0
+    _compare_runs(ro, rg)
+    rg.close()
+
+
+@pytest.mark.parametrize("d,n,k", [(12, 400, 200), (4, 16384, 8192)])
+def test_gauss_extreme_sizes_lockstep(torch_cuda, d, n, k):
+    """The largest dimension and the largest population follow the oracle."""
+    w = synth.gauss_workload(d, 0.1, n_live=n, n_delete=k)
+    orc = oracle.OracleProblem(w)
+    spec = binding.ProblemSpec(w)
+    ro, rg = _lockstep(w, orc, spec, 3, n_live=n, n_delete=k)
+    _compare_runs(ro, rg)
