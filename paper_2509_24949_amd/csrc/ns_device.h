@@ -392,7 +392,9 @@ __device__ inline void probe_intrinsic(const ModelDev& M, const double* u, Probe
   r->f_isco = 1.0 / (14.696938456699069 * x3);      // 1 / (6^(3/2) pi M)
   int k = active_bins(M.f_lo, M.df, M.inv_df, M.n_bins, r->f_isco);
   r->k_act = k > M.k_lim ? M.k_lim : k;
-  r->amp_mc = 0.21278751013966343 * exp(5.0 / 6.0 * ln_mc);
+  // sqrt(5/24) pi^(-2/3) Mc^(5/6) with Mc^(5/6) = pi^(-5/6) (pi M)^(5/6) eta^(1/2)
+  // = pi^(-5/6) x^(5/2) eta^(1/2): one square root instead of an exponential
+  r->amp_mc = 0.08196993152115736 * (x2 * sqrt(p.x * eta));   // sqrt(5/24) pi^(-3/2)
 }
 
 __device__ inline void probe_extrinsic(const ModelDev& M, const double* u, ProbeRec* r) {

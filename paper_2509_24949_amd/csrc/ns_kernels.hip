@@ -771,15 +771,17 @@ __global__ __launch_bounds__(256) void k_probe_setup(const ModelDev* __restrict_
 }
 
 template <int NDET, int LK, bool LDS>
-__global__ __launch_bounds__(256) void k_probe_bins(const ModelDev* __restrict__ Mp, Tables T,
-                                                    const Probe* __restrict__ P, long n, double* __restrict__ out) {
+// 1024 threads share one staged copy of the tables, so a CU holds eight
+// waves per SIMD.
+__global__ __launch_bounds__(1024) void k_probe_bins(const ModelDev* __restrict__ Mp, Tables T,
+                                                     const Probe* __restrict__ P, long n, double* __restrict__ out) {
   extern __shared__ double smem[];
   const ModelDev& M = *Mp;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const TabView V = stage_tables<NDET, lk_mixed(LK)>(M, T, LDS, smem, tid, 256);
+  const TabView V = stage_tables<NDET, lk_mixed(LK)>(M, T, LDS, smem, tid, 1024);
   if (LDS) __syncthreads();
-  for (long p = (long)blockIdx.x * 4 + wv; p < n; p += (long)gridDim.x * 4) {
+  for (long p = (long)blockIdx.x * 16 + wv; p < n; p += (long)gridDim.x * 16) {
     const Probe pb = P[p];
     const double tot = wave_sum(fullgrid_partial<NDET, lk_mixed(LK)>(pb, V, lane, 64));
     if (lane == 0) out[p] = tot - 0.5 * pb.hh;
@@ -1659,9 +1661,9 @@ hipError_t launch_loglike_t(const ModelDev& M, const ModelDev* Md, const Tables&
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const size_t lds = LDS ? staged_table_bytes(M.k_lim, NDET, lk_mixed(LK)) : 0;
-    long blocks = (n + 3) / 4;
-    if (blocks > 256 * 8) blocks = 256 * 8;
-    hipLaunchKernelGGL((k_probe_bins<NDET, LK, LDS>), dim3((unsigned)blocks), dim3(256), lds, st, Md, T, pbuf, n,
+    long blocks = (n + 15) / 16;
+    if (blocks > 256 * 2) blocks = 256 * 2;
+    hipLaunchKernelGGL((k_probe_bins<NDET, LK, LDS>), dim3((unsigned)blocks), dim3(1024), lds, st, Md, T, pbuf, n,
                        out);
     return hipGetLastError();
   }
