@@ -1037,7 +1037,7 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
   double* sP = sU + SL_CHUNK * SL_NU;
   double* sT = sP + NC * SL_PSTRIDE;
   double* sG = sT + NT;
-  int* sIn = reinterpret_cast<int*>(sG + NT);   // in-cube flag per candidate
+  unsigned long long* sMask = reinterpret_cast<unsigned long long*>(sG + NT);   // in-cube bits per 64 candidates
   double* sX = sG + NT + NT / 4;     // chain position
   double* stab = sX + 16;
   for (int i = tid; i < d * d; i += NT) sL[i] = R.chol[i];
@@ -1082,17 +1082,32 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
 #pragma unroll
       for (int i = 0; i < MAX_DIM; ++i) y[i] = 0.5;   // a harmless point; never evaluated
     }
+    const unsigned long long m = __ballot(cin);
     ProbeRec* rec = reinterpret_cast<ProbeRec*>(sP + cand * SL_PSTRIDE);
     if (intrinsic_half) {
       if (LK == LK_GAUSS) sG[cand] = gauss_lambda(M, y);
       else probe_intrinsic(M, y, rec);
       sT[cand] = tt;
-      sIn[cand] = cin ? 1 : 0;
+      if (lane == 0) sMask[cand >> 6] = m;
     } else if (LK != LK_GAUSS) {
       probe_extrinsic(M, y, rec);
     }
   };
-  auto inside = [&](int q) -> bool { return sIn[q] != 0; };
+  // After a batch's barrier every wave keeps the in-cube bits and the
+  // positions of the batch in registers; the walk then reads a candidate's
+  // with scalar operations instead of LDS round trips.
+  unsigned long long mk0 = 0, mk1 = 0;
+  double tr0 = 0.0, tr1 = 0.0;
+  auto load_batch = [&]() {
+    mk0 = sMask[0];
+    tr0 = sT[lane];
+    if constexpr (NC > 64) {
+      mk1 = sMask[1];
+      tr1 = sT[64 + lane];
+    }
+  };
+  auto inside = [&](int q) -> bool { return ((q < 64 ? mk0 : mk1) >> (q & 63)) & 1ull; };
+  auto ttq = [&](int q) -> double { return lane_d(q < 64 ? tr0 : tr1, q & 63); };
   // lambda of batch candidate q (all threads; contains workgroup barriers)
   auto eval = [&](int q) -> double {
     ++nprobe;
@@ -1104,7 +1119,7 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
     if (lk_rb(LK)) tot = wave_sum(rb_partial<NDET, lk_mixed(LK)>(pb, RBv, M.n_bins, sr0, tid, NT));
     else tot = wave_sum(fullgrid_partial<NDET, lk_mixed(LK)>(pb, V, tid, NT));
     if constexpr (NW > 1) {
-      double* rb = sred + buf * (NW + 2);
+      double* rb = sred + buf * (NW + 4);
       if (lane == 0) rb[wv] = tot;
       __syncthreads();
       tot = 0.0;
@@ -1122,15 +1137,15 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
   // the walk counts the evaluations the sequential algorithm makes.
   constexpr bool PAIR = (lk_full(LK) || lk_rb(LK)) && NW >= 2;
   auto rec = [&](int q) -> const ProbeRec& { return *reinterpret_cast<const ProbeRec*>(sP + q * SL_PSTRIDE); };
-  auto count = [&](int q) {
+  auto count = [&](int kact) {
     ++nprobe;
-    nbins += lk_full(LK) ? rec(q).k_act : RB.nb + 1;
+    nbins += lk_full(LK) ? kact : RB.nb + 1;
   };
-  auto eval2 = [&](int q1, int q2, double* l1, double* l2) {
+  auto eval2 = [&](int q1, int q2, double* l1, double* l2, int* k1, int* k2) {
     constexpr int HW = NW / 2;
     const bool second = tid >= NT / 2;
     const int q = second ? q2 : q1;
-    double part = 0.0, hh = 0.0;
+    double part = 0.0, hh = 0.0, kact = 0.0;
     if constexpr (lk_rb(LK)) {
       // both halves pass the barrier inside rb_partial
       const Probe pb = q >= 0 ? probe_from_rec<NDET>(rec(q), nullptr, 0) : Probe{};
@@ -1140,11 +1155,15 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
       const Probe pb = probe_from_rec<NDET>(rec(q), V.hpre, V.hstride);
       part = fullgrid_partial<NDET, lk_mixed(LK)>(pb, V, second ? tid - NT / 2 : tid, NT / 2);
       hh = pb.hh;
+      kact = (double)pb.k_act;
     }
     const double tot = wave_sum(part);
-    double* rb = sred + buf * (NW + 2);
+    double* rb = sred + buf * (NW + 4);
     if (lane == 0) rb[wv] = tot;
-    if (lane == 0 && wv % HW == 0) rb[NW + (second ? 1 : 0)] = hh;
+    if (lane == 0 && wv % HW == 0) {
+      rb[NW + (second ? 1 : 0)] = hh;
+      rb[NW + 2 + (second ? 1 : 0)] = kact;
+    }
     __syncthreads();
     double t1 = 0.0, t2 = 0.0;
 #pragma unroll
@@ -1154,6 +1173,8 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
     }
     *l1 = t1 - 0.5 * rb[NW];
     *l2 = t2 - 0.5 * rb[NW + 1];
+    *k1 = (int)rb[NW + 2];
+    *k2 = (int)rb[NW + 3];
     buf ^= 1;
   };
 
@@ -1218,8 +1239,11 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
       const int s = s0 + sl;
       const double* dir = sDir + sl * MAX_DIM;
       const double* su = sU + sl * SL_NU;
-      double lo = -w * su[0], hi = lo + w;
-      int J = (int)floor(R.max_stepout * su[1]);
+      double sur[SL_NU];             // this step's uniforms, in registers
+#pragma unroll
+      for (int i = 0; i < SL_NU; ++i) sur[i] = su[i];
+      double lo = -w * sur[0], hi = lo + w;
+      int J = (int)floor(R.max_stepout * sur[1]);
       int K = R.max_stepout - 1 - J;
 
       // ---- the combined batch
@@ -1238,9 +1262,12 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
           double l2 = lo, h2 = hi;
           for (int q = 0; q < na; ++q) l2 -= w;
           for (int q = 0; q < nbh; ++q) h2 += w;
-          for (int q = 0; q <= c; ++q) {
-            tt = fma(su[2 + q], h2 - l2, l2);
-            if (tt < 0.0) l2 = tt; else h2 = tt;
+#pragma unroll
+          for (int q = 0; q < BL::SC; ++q) {
+            if (q <= c) {
+              tt = fma(sur[2 + q], h2 - l2, l2);
+              if (tt < 0.0) l2 = tt; else h2 = tt;
+            }
           }
         } else {
           valid = false;
@@ -1248,6 +1275,7 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
         setup(valid, tt, dir);
       }
       __syncthreads();
+      load_batch();
       bool combined = true;        // the batch in LDS is the combined one
 
       // ---- step out, left then right (the order of the sequential algorithm)
@@ -1264,13 +1292,14 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
           if (qR >= 0 && !inside(qR)) { K = 0; qR = -1; }
           if (qL < 0 && qR < 0) break;
           double lL, lR;
-          eval2(qL, qR, &lL, &lR);
+          int kL, kR;
+          eval2(qL, qR, &lL, &lR, &kL, &kR);
           if (qL >= 0) {
-            count(qL);
+            count(kL);
             if (lL > lstar) { lo -= w; --J; ++na; ++uL; } else { J = 0; }
           }
           if (qR >= 0) {
-            count(qR);
+            count(kR);
             if (lR > lstar) { hi += w; --K; ++nh; ++uR; } else { K = 0; }
           }
         }
@@ -1290,6 +1319,7 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
               for (int q = 0; q < cand; ++q) tt = side == 0 ? tt - w : tt + w;
             setup(cand < FB, tt, dir);
             __syncthreads();
+            load_batch();
             combined = false;
             first = 0;
             have = FB;
@@ -1318,10 +1348,11 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
           const int q2 = two ? q1 + 1 : -1;
           const bool in1 = inside(q1), in2 = two && inside(q2);
           double l1 = NEG_INF, l2 = NEG_INF;
-          if (in1 || in2) eval2(in1 ? q1 : -1, in2 ? q2 : -1, &l1, &l2);
-          const double t1 = sT[q1];
+          int k1 = 0, k2 = 0;
+          if (in1 || in2) eval2(in1 ? q1 : -1, in2 ? q2 : -1, &l1, &l2, &k1, &k2);
+          const double t1 = ttq(q1);
           if (in1) {
-            count(q1);
+            count(k1);
             if (l1 > lstar) {
               if (tid < d) sX[tid] = fma(t1, dir[tid], sX[tid]);
               lx = l1;
@@ -1332,9 +1363,9 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
           if (t1 < 0.0) lo = t1; else hi = t1;
           ++a;
           if (!two) continue;
-          const double t2 = sT[q2];
+          const double t2 = ttq(q2);
           if (in2) {
-            count(q2);
+            count(k2);
             if (l2 > lstar) {
               if (tid < d) sX[tid] = fma(t2, dir[tid], sX[tid]);
               lx = l2;
@@ -1349,7 +1380,7 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
         const int base = 2 * BL::SO + BL::SC * (BL::H * na + nh);
         for (; a < BL::SC && a < R.max_shrink; ++a) {
           const int q = base + a;
-          const double tt = sT[q];
+          const double tt = ttq(q);
           if (inside(q)) {
             const double ly = eval(q);
             if (ly > lstar) {
@@ -1392,8 +1423,9 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
           setup(cand < FB, tl, dir);
         }
         __syncthreads();
+        load_batch();
         for (int q = 0; q < FB && a < R.max_shrink; ++q, ++a) {
-          const double tt = sT[q];
+          const double tt = ttq(q);
           if (inside(q)) {
             const double ly = eval(q);
             if (ly > lstar) {
