@@ -6,17 +6,24 @@
 //                 deaths, dead-point record, covariance of the live points
 //                 and its Cholesky factor, survivor list, chain start points.
 //  * k_slice      one workgroup per chain: the whole constrained slice walk
-//                 of the iteration with the chain state in registers and the
-//                 likelihood tables in LDS.  The per-probe source setup
-//                 (masses, amplitude, antenna patterns, PN coefficients) is
-//                 computed lane-parallel for a batch of candidate probes
-//                 whose positions are known in advance (the step-out points
-//                 and the shrink candidates), then each probe's bins are
-//                 spread over the workgroup and reduced once.
+//                 of the iteration with the chain state uniform across the
+//                 workgroup and the likelihood tables in LDS.  Each step sets
+//                 up a batch of candidate probes whose positions are known in
+//                 advance (the step-out points and the shrink candidates), the
+//                 two halves of the workgroup computing the intrinsic and the
+//                 extrinsic half of every candidate's source; the walk then
+//                 evaluates independent probes in pairs, each probe's bins
+//                 spread over half the workgroup and reduced once.
 //  * k_term       one workgroup: live evidence, termination flag, counters.
-//  * k_loglike    batched fused likelihood: each wavefront sets up 64 probes
-//                 (one per lane) and then evaluates them one after another
-//                 with all 64 lanes over the frequency bins.
+//  * k_probe_setup, k_probe_bins
+//                 batched fused likelihood in two passes: one probe set-up per
+//                 thread, then one wavefront per probe over the frequency bins
+//                 with the coefficients in scalar registers.
+//  * k_loglike    batched likelihood in one pass (initial population,
+//                 Gaussian test likelihood); k_loglike_rb the relative-binning
+//                 batch.
+//  * k_*_packed   the serving forms: one launch covers the chains (and the
+//                 selection, preparation and termination) of every resident run.
 #include <float.h>
 #include <math.h>
 #include <stdlib.h>
