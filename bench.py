@@ -48,7 +48,7 @@ WORKLOADS = {
     "tf2_3det_rb": _GRID2 + ", relative binning (128 geometric bins), n_live 1000, n_delete 500, 55 slice steps, FP64",
     "tf2_3det_mixed": _GRID2 + ", full-grid Whittle, n_live 2000, n_delete 1000, 55 slice steps, mixed precision",
     "tf2_3det_rb_mixed": _GRID2 + ", relative binning (128 bins), n_live 2000, n_delete 1000, 55 slice steps, mixed precision",
-    "serving": "serving: 64 Poisson-arriving events, 4/8/16/32 s (4017-32129 bins per detector), 1-3 detectors, "
+    "serving": "64 Poisson-arriving events, 4/8/16/32 s (4017-32129 bins per detector), 1-3 detectors, "
             "SNR U[8,40], Mc U[5,60], q U[0.125,1], 11 parameters, n_live U{500,1000,2000}, n_delete n_live/2, "
             "full-grid Whittle",
 }
@@ -128,7 +128,10 @@ def _pct(x, q):
     return float(np.percentile(np.asarray(x, dtype=float), q))
 
 
-def serving(args) -> dict:
+_SERVING_DATA = {}
+
+
+def serving(args, precision_name=None) -> dict:
     """Serving benchmark: the events run one at a time (service times), then
     arrive as a Poisson process at twice the sequential service rate and are
     served by the packed scheduler.  Time-to-posterior runs from an event's
@@ -139,15 +142,19 @@ def serving(args) -> dict:
     from paper_2509_24949_amd import binding, synth
 
     n_ev = args.events
-    precision = 1 if args.precision == "mixed" else 0
+    precision_name = precision_name or args.precision
+    precision = 1 if precision_name == "mixed" else 0
     events = [synth.serving_event(i) for i in range(n_ev)]
     for w in events:
         w.precision = precision
-    log(f"bench: serving: building data of {n_ev} events")
-    specs = []
-    for w in events:
-        re, im = binding.make_data(w)
-        specs.append(binding.ProblemSpec(w, re, im))
+    if n_ev not in _SERVING_DATA:        # the data do not depend on the precision
+        log(f"bench: serving: building data of {n_ev} events")
+        specs = []
+        for w in events:
+            re, im = binding.make_data(w)
+            specs.append(binding.ProblemSpec(w, re, im))
+        _SERVING_DATA[n_ev] = specs
+    specs = _SERVING_DATA[n_ev]
     opts = [binding.opts_for(w, max_iter=args.max_iter) for w in events]
 
     # warm-up: load every code object the two modes use
@@ -251,7 +258,7 @@ def serving(args) -> dict:
         "data": "synthetic (seeded Gaussian noise plus injected TaylorF2 signals; no real detector data)",
         "config": {"workload": f"serving: {WORKLOADS['serving']}", "events": n_ev, "max_runs": args.max_runs,
                    "tick_iters": args.tick_iters, "graph": bool(args.graph), "load": args.load,
-                   "precision": args.precision},
+                   "precision": precision_name},
         "latency_p50_s": _pct(lat_v, 50),
         "latency_p99_s": _pct(lat_v, 99),
         "makespan_s": span,
@@ -375,6 +382,14 @@ def main():
                 f"logZ {z['logZ']:.3f} +- {z['sigma']:.3f}, done={done}")
         run_info = {"s_per_run": t_run, "run_iterations": st["iter"], "run_evals": st["n_evals"],
                     "logZ": z["logZ"], "sigma_logZ": z["sigma"], "ess_kish": z["ess"]}
+        golden = os.path.join(ROOT, "tests", "golden", "full_runs.json")
+        if os.path.exists(golden):
+            with open(golden) as fh:
+                g = json.load(fh).get(args.workload)
+            if g:   # the stored complete run of the double-precision oracle, same seeds
+                run_info["accuracy_vs_oracle"] = {
+                    "logZ_oracle": g["logZ"], "abs_delta_logZ": abs(z["logZ"] - g["logZ"]),
+                    "iterations_oracle": g["iterations"], "evals_oracle": g["n_evals"]}
 
     K, W = args.steps, args.warmup
     r = binding.Run(spec, binding.opts_for(w, term_frac=0.0, max_iter=W + K + 2))
@@ -437,10 +452,12 @@ def main():
         log(f"bench: standalone likelihood: {out['standalone_loglike']['evals_per_s'] / 1e6:.0f} M evals/s, "
             f"{out['standalone_loglike']['frac'] * 100:.1f}% of peak")
     if not args.no_serving and args.workload == "tf2_3det":
-        sv = serving(args)
-        out["serving"] = {k: sv[k] for k in ("value", "unit", "latency_p50_s", "latency_p99_s", "makespan_s",
-                                             "evals_per_s", "sequential", "logZ_served_vs_sequential")}
-        out["serving"]["config"] = sv["config"]
+        keys = ("value", "unit", "latency_p50_s", "latency_p99_s", "makespan_s", "evals_per_s", "sequential",
+                "logZ_served_vs_sequential", "config")
+        sv = serving(args, "fp64")
+        out["serving"] = {k: sv[k] for k in keys}
+        sv = serving(args, "mixed")
+        out["serving_mixed"] = {k: sv[k] for k in keys}
     if not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)
         log(f"bench: timing the oracle on {threads} host threads for about {args.cpu_seconds:.0f} s")
