@@ -527,7 +527,8 @@ int ns_dead(ns_run* r, long cap, double* u, double* logl, double* logx, double* 
 int ns_loglike(ns_run* r, const double* u_dev, long n, double* out_dev, int* terms_dev) {
   if (!r) return fail(NS_E_ARG, "run is NULL");
   if (n < 0 || (n > 0 && (!u_dev || !out_dev))) return fail(NS_E_ARG, "bad batch arguments");
-  if (r->M.likelihood == NS_LIKE_FULL && n > r->probe_cap) {
+  const bool two_pass = r->M.likelihood == NS_LIKE_FULL || r->M.likelihood == NS_LIKE_RB;
+  if (two_pass && n > r->probe_cap) {
     HIP_OK(hipStreamSynchronize(r->st));   // the old buffer may still be read
     if (r->probe_buf) (void)hipFree(r->probe_buf);
     r->probe_buf = nullptr;
@@ -537,7 +538,7 @@ int ns_loglike(ns_run* r, const double* u_dev, long n, double* out_dev, int* ter
     r->probe_cap = cap;
   }
   HIP_OK(launch_loglike(r->M, r->Md, r->T, r->RB, u_dev, n, out_dev, terms_dev,
-                        r->M.likelihood == NS_LIKE_FULL ? r->probe_buf : nullptr, r->st));
+                        two_pass ? r->probe_buf : nullptr, r->st));
   return NS_OK;
 }
 

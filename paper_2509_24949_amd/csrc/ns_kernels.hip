@@ -581,8 +581,9 @@ __device__ inline RBTables stage_rb(const RBTables& B, double* lds, int tid, int
 
 // This thread's share of a relative-binning likelihood; lds holds the edge
 // ratios of the probe.  Every thread of the workgroup calls it (it contains a
-// barrier); an inactive caller only takes part in the barrier.
-template <int NDET, bool MX>
+// barrier); an inactive caller only takes part in the barrier.  WAVE: the
+// probe belongs to one wavefront, which synchronises on its own.
+template <int NDET, bool MX, bool WAVE = false>
 __device__ inline double rb_partial(const Probe& p, const RBTables& B, int n_bins, void* lds, int tid, int nt,
                                     bool active = true) {
   using CT = typename std::conditional<MX, float2, double2>::type;
@@ -606,7 +607,13 @@ __device__ inline double rb_partial(const Probe& p, const RBTables& B, int n_bin
       }
     }
   }
-  __syncthreads();
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
   double part = 0.0;
   for (int b = active ? tid : nb; b < nb; b += nt) {
     const int first = B.edge[b];
@@ -792,6 +799,34 @@ __global__ __launch_bounds__(1024) void k_probe_bins(const ModelDev* __restrict_
     const Probe pb = P[p];
     const double tot = wave_sum(fullgrid_partial<NDET, lk_mixed(LK)>(pb, V, lane, 64));
     if (lane == 0) out[p] = tot - 0.5 * pb.hh;
+  }
+}
+
+// Relative-binning bin pass of the two-pass batch: the tables staged once
+// per 512-thread block, one wavefront per probe with its own edge-ratio
+// scratch, the coefficients read with scalar loads.
+template <int NDET, bool MX>
+__global__ __launch_bounds__(512) void k_rb_bins(RBTables RB, int n_bins, const Probe* __restrict__ P, long n,
+                                                 double* __restrict__ out, int* __restrict__ terms) {
+  extern __shared__ double smem[];
+  using CT = typename std::conditional<MX, float2, double2>::type;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const RBTables V = stage_rb<NDET, MX>(RB, smem, tid, 512);
+  const size_t ratio_doubles = (size_t)NDET * (RB.nb + 1) * sizeof(CT) / sizeof(double);
+  double* sr = smem + rb_stage_doubles(RB.nb, NDET, MX) + wv * ratio_doubles;
+  __syncthreads();
+  for (long p = (long)blockIdx.x * 8 + wv; p < n; p += (long)gridDim.x * 8) {
+    const Probe pb = P[p];
+    const double tot = wave_sum(rb_partial<NDET, MX, true>(pb, V, n_bins, sr, lane, 64));
+    if (lane == 0) {
+      out[p] = tot;
+      if (terms) terms[p] = RB.nb + 1;
+    }
+    // the next probe rewrites this wavefront's ratios
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
 }
 
@@ -1828,9 +1863,22 @@ hipError_t launch_init_live(const RunDev& R, hipStream_t st) {
 }
 
 template <int NDET, bool MX>
-hipError_t launch_loglike_rb_t(const ModelDev* Md, const RBTables& RB, const double* u, long n, double* out,
-                               int* terms, hipStream_t st) {
+hipError_t launch_loglike_rb_t(const ModelDev* Md, const RBTables& RB, int n_bins, const double* u, long n,
+                               double* out, int* terms, Probe* pbuf, hipStream_t st) {
   if (n <= 0) return hipSuccess;
+  if (pbuf) {
+    hipLaunchKernelGGL(k_probe_setup, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, Md, nullptr, u, n, pbuf,
+                       nullptr);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    using CT = typename std::conditional<MX, float2, double2>::type;
+    const size_t lds = rb_stage_doubles(RB.nb, NDET, MX) * sizeof(double) + 8 * (size_t)NDET * (RB.nb + 1) * sizeof(CT);
+    long blocks = (n + 7) / 8;
+    if (blocks > 256 * 2) blocks = 256 * 2;
+    hipLaunchKernelGGL((k_rb_bins<NDET, MX>), dim3((unsigned)blocks), dim3(512), lds, st, RB, n_bins, pbuf, n, out,
+                       terms);
+    return hipGetLastError();
+  }
   long blocks = (n + 63) / 64;
   if (blocks > 8192) blocks = 8192;
   const size_t lds = (size_t)NDET * (RB.nb + 1) * (MX ? sizeof(float2) : sizeof(double2));
@@ -1844,15 +1892,15 @@ hipError_t launch_loglike(const ModelDev& M, const ModelDev* Md, const Tables& T
   if (M.likelihood == LK_RB) {
     if (M.mixed) {
       switch (M.n_det) {
-        case 1: return launch_loglike_rb_t<1, true>(Md, RB, u, n, out, terms, st);
-        case 2: return launch_loglike_rb_t<2, true>(Md, RB, u, n, out, terms, st);
-        default: return launch_loglike_rb_t<3, true>(Md, RB, u, n, out, terms, st);
+        case 1: return launch_loglike_rb_t<1, true>(Md, RB, M.n_bins, u, n, out, terms, pbuf, st);
+        case 2: return launch_loglike_rb_t<2, true>(Md, RB, M.n_bins, u, n, out, terms, pbuf, st);
+        default: return launch_loglike_rb_t<3, true>(Md, RB, M.n_bins, u, n, out, terms, pbuf, st);
       }
     }
     switch (M.n_det) {
-      case 1: return launch_loglike_rb_t<1, false>(Md, RB, u, n, out, terms, st);
-      case 2: return launch_loglike_rb_t<2, false>(Md, RB, u, n, out, terms, st);
-      default: return launch_loglike_rb_t<3, false>(Md, RB, u, n, out, terms, st);
+      case 1: return launch_loglike_rb_t<1, false>(Md, RB, M.n_bins, u, n, out, terms, pbuf, st);
+      case 2: return launch_loglike_rb_t<2, false>(Md, RB, M.n_bins, u, n, out, terms, pbuf, st);
+      default: return launch_loglike_rb_t<3, false>(Md, RB, M.n_bins, u, n, out, terms, pbuf, st);
     }
   }
   const bool lds = staged_table_bytes(M.k_lim, M.n_det, M.mixed != 0) <= 64 * 1024;
