@@ -466,12 +466,18 @@ def main():
 
 
 def _kernel_sha() -> str:
+    """Hash of the kernel sources with line comments and blank lines removed,
+    so that stored counter readings stay valid across comment-only edits."""
     import hashlib
+    import re
 
     h = hashlib.sha256()
     for f in ("ns_device.h", "ns_kernels.hip", "ns_internal.h"):
-        with open(os.path.join(ROOT, "paper_2509_24949_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2509_24949_amd", "csrc", f), encoding="utf-8") as fh:
+            for line in fh:
+                code = re.sub(r"//.*", "", line).strip()
+                if code:
+                    h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

@@ -15,13 +15,14 @@
 //                 evaluates independent probes in pairs, each probe's bins
 //                 spread over half the workgroup and reduced once.
 //  * k_term       one workgroup: live evidence, termination flag, counters.
-//  * k_probe_setup, k_probe_bins
+//  * k_probe_setup, k_probe_bins, k_rb_bins
 //                 batched fused likelihood in two passes: one probe set-up per
 //                 thread, then one wavefront per probe over the frequency bins
-//                 with the coefficients in scalar registers.
+//                 (k_probe_bins) or the relative-binning bins (k_rb_bins) with
+//                 the coefficients in scalar registers.
 //  * k_loglike    batched likelihood in one pass (initial population,
-//                 Gaussian test likelihood); k_loglike_rb the relative-binning
-//                 batch.
+//                 Gaussian test likelihood); k_loglike_rb its relative-binning
+//                 form.
 //  * k_*_packed   the serving forms: one launch covers the chains (and the
 //                 selection, preparation and termination) of every resident run.
 #include <float.h>
