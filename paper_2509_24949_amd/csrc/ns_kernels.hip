@@ -302,26 +302,62 @@ __device__ inline Probe probe_from_lane(const Probe& p, int src) {
   return b;
 }
 
+// One bin's table entries: frequency terms and the detectors' whitened data.
+template <int NDET, bool MX>
+struct BinRow {
+  double f, f13, lnf3, fm53;
+  typename std::conditional<MX, float2, double2>::type D[NDET];
+};
+
+template <int NDET, bool MX>
+__device__ inline BinRow<NDET, MX> load_bin(const TabView& V, int k) {
+  BinRow<NDET, MX> r;
+  const size_t kt = (size_t)k * V.ts;
+  r.f = V.f[kt];
+  r.f13 = V.f13[kt];
+  r.lnf3 = V.lnf3[kt];
+  r.fm53 = V.fm53[kt];
+#pragma unroll
+  for (int d = 0; d < NDET; ++d) {
+    if constexpr (MX) r.D[d] = V.dw32[(size_t)k * V.dk + d * V.dd];
+    else r.D[d] = V.dw[(size_t)k * V.dk + d * V.dd];
+  }
+  return r;
+}
+
 // This thread's share of <d|h> summed over detectors, for the active bins
 // k = lane, lane + nl, ...:  sum_d Re[A K_d sum_k conj(Dw_dk) e^{-i Phi_dk}].
 // Per detector the bin sums a_d = sum (Dr c - Di s) and b_d = sum (Dr s + Di c)
 // are folded with A K_d = (kre, kim) as kre a_d + kim b_d before returning, so a
-// probe needs a single reduction.
-template <int NDET, bool MX>
+// probe needs a single reduction.  With PF the next bin's table entries are
+// loaded before the current bin is computed, so that their latency overlaps
+// the arithmetic (for kernels with few waves per SIMD).
+template <int NDET, bool MX, bool PF = false>
 __device__ inline double fullgrid_partial(const Probe& p, const TabView& V, int lane, int nl) {
+  using Row = BinRow<NDET, MX>;
+  [[maybe_unused]] Row nxt{};
+  if constexpr (PF) {
+    if (lane < p.k_act) nxt = load_bin<NDET, MX>(V, lane);
+  }
   if constexpr (MX) {
     // mixed form: the phase in double, reduced to [-1/2, 1/2] cycles, then
     // float sincos and compensated float sums of the scaled data
     KahanF a[NDET], b[NDET];
     for (int k = lane; k < p.k_act; k += nl) {
-      const size_t kt = (size_t)k * V.ts;
-      const double f = V.f[kt];
-      const double psi = phase_cycles(p, f, V.f13[kt], V.lnf3[kt], V.fm53[kt]);
+      Row r;
+      if constexpr (PF) {
+        r = nxt;
+        const int kn = k + nl < p.k_act ? k + nl : k;   // the last pass re-reads its own bin
+        nxt = load_bin<NDET, MX>(V, kn);
+      } else {
+        r = load_bin<NDET, MX>(V, k);
+      }
+      const double psi = phase_cycles(p, r.f, r.f13, r.lnf3, r.fm53);
 #pragma unroll
       for (int d = 0; d < NDET; ++d) {
-        const double ph = fma(f, p.dt[d], psi);
+        const double ph = fma(r.f, p.dt[d], psi);
         const float2 sc = sincos_cycles_f32((float)(ph - rint(ph)));
-        const float2 D = V.dw32[(size_t)k * V.dk + d * V.dd];
+        const float2 D = r.D[d];
         a[d].add(fmaf(D.x, sc.y, -D.y * sc.x));
         b[d].add(fmaf(D.x, sc.x, D.y * sc.y));
       }
@@ -336,14 +372,20 @@ __device__ inline double fullgrid_partial(const Probe& p, const TabView& V, int 
 #pragma unroll
     for (int d = 0; d < NDET; ++d) { a[d] = 0.0; b[d] = 0.0; }
     for (int k = lane; k < p.k_act; k += nl) {
-      const size_t kt = (size_t)k * V.ts;
-      const double f = V.f[kt];
-      const double psi = phase_cycles(p, f, V.f13[kt], V.lnf3[kt], V.fm53[kt]);
+      Row r;
+      if constexpr (PF) {
+        r = nxt;
+        const int kn = k + nl < p.k_act ? k + nl : k;
+        nxt = load_bin<NDET, MX>(V, kn);
+      } else {
+        r = load_bin<NDET, MX>(V, k);
+      }
+      const double psi = phase_cycles(p, r.f, r.f13, r.lnf3, r.fm53);
 #pragma unroll
       for (int d = 0; d < NDET; ++d) {
-        const double2 sc_ = sincos_cycles(fma(f, p.dt[d], psi));
+        const double2 sc_ = sincos_cycles(fma(r.f, p.dt[d], psi));
         const double sn = sc_.x, cs = sc_.y;
-        const double2 D = V.dw[(size_t)k * V.dk + d * V.dd];
+        const double2 D = r.D[d];
         a[d] = fma(D.x, cs, fma(-D.y, sn, a[d]));
         b[d] = fma(D.x, sn, fma(D.y, cs, b[d]));
       }
@@ -1114,12 +1156,23 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
   const int cand = tid % NC;
   const bool intrinsic_half = tid < NC;
   auto setup = [&](bool valid, double tt, const double* dir) {
+    // all MAX_DIM slots of the position and direction rows are read (slots
+    // from d on are masked), so the loads issue together instead of one
+    // dependent round trip per coordinate
+    double xr[MAX_DIM], dr[MAX_DIM];
+#pragma unroll
+    for (int i = 0; i < MAX_DIM; ++i) {
+      xr[i] = sX[i];
+      dr[i] = dir[i];
+    }
     double y[MAX_DIM];
     bool cin = valid;
 #pragma unroll
     for (int i = 0; i < MAX_DIM; ++i) {
-      y[i] = (i < d) ? fma(tt, dir[i], sX[i]) : 0.0;
-      if (i < d && !(y[i] >= 0.0 && y[i] <= 1.0)) cin = false;
+      const double yi = fma(tt, dr[i], xr[i]);
+      const bool act = i < d;
+      y[i] = act ? yi : 0.0;
+      cin = cin && (!act || (yi >= 0.0 && yi <= 1.0));
     }
     if (!cin) {
 #pragma unroll
@@ -1160,7 +1213,7 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
     nbins += lk_full(LK) ? pb.k_act : RB.nb + 1;
     double tot;
     if (lk_rb(LK)) tot = wave_sum(rb_partial<NDET, lk_mixed(LK)>(pb, RBv, M.n_bins, sr0, tid, NT));
-    else tot = wave_sum(fullgrid_partial<NDET, lk_mixed(LK)>(pb, V, tid, NT));
+    else tot = wave_sum(fullgrid_partial<NDET, lk_mixed(LK), true>(pb, V, tid, NT));
     if constexpr (NW > 1) {
       double* rb = sred + buf * (NW + 4);
       if (lane == 0) rb[wv] = tot;
@@ -1196,7 +1249,7 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
                                             q >= 0);
     } else if (q >= 0) {
       const Probe pb = probe_from_rec<NDET>(rec(q), V.hpre, V.hstride);
-      part = fullgrid_partial<NDET, lk_mixed(LK)>(pb, V, second ? tid - NT / 2 : tid, NT / 2);
+      part = fullgrid_partial<NDET, lk_mixed(LK), true>(pb, V, second ? tid - NT / 2 : tid, NT / 2);
       hh = pb.hh;
       kact = (double)pb.k_act;
     }
@@ -1257,9 +1310,14 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
     __syncthreads();
     // directions L z / |z|, one thread per step (the thread owns the row)
     for (int sl = tid; sl < cs; sl += NT) {
+      // whole rows are loaded (entries past d or past the diagonal are
+      // masked; every index stays below MAX_DIM^2), so each row's loads
+      // issue together
       double z[MAX_DIM];
 #pragma unroll
-      for (int i = 0; i < MAX_DIM; ++i) z[i] = (i < d) ? sDir[sl * MAX_DIM + i] : 0.0;
+      for (int i = 0; i < MAX_DIM; ++i) z[i] = sDir[sl * MAX_DIM + i];
+#pragma unroll
+      for (int i = 0; i < MAX_DIM; ++i) z[i] = (i < d) ? z[i] : 0.0;
       double nrm = 0.0;
 #pragma unroll
       for (int i = 0; i < MAX_DIM; ++i)
@@ -1268,10 +1326,13 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
 #pragma unroll
       for (int a = 0; a < MAX_DIM; ++a) {
         if (a < d) {
+          double lr[MAX_DIM];
+#pragma unroll
+          for (int b = 0; b < MAX_DIM; ++b) lr[b] = sL[a * d + b];
           double acc = 0.0;
 #pragma unroll
           for (int b = 0; b < MAX_DIM; ++b)
-            if (b <= a) acc += sL[a * d + b] * z[b];
+            if (b <= a) acc += lr[b] * z[b];
           sDir[sl * MAX_DIM + a] = acc / nrm;
         }
       }
