@@ -357,25 +357,28 @@ struct ProbeRec {
   double dt[MAX_DET];               // arrival delays (extrinsic)
 };
 
+// Both halves read every model constant they need before their first
+// branch, and choose between the models with selects, so that the constant
+// loads issue together instead of one round trip per use.
 __device__ inline void probe_intrinsic(const ModelDev& M, const double* u, ProbeRec* r) {
   const PriorDev& P = M.prior;
+  const bool m4p = M.model == 1;
+  const double f_lo = M.f_lo, df = M.df, inv_df = M.inv_df;
+  const int n_bins = M.n_bins, k_lim = M.k_lim;
   const double mc_msun = prior_affine(P, 0, u[0]);
-  double eta, beta = 0.0, sigma = 0.0, tc, phic;
-  if (M.model == 1) {
-    eta = prior_affine(P, 1, u[1]);
-    tc = prior_affine(P, 2, u[2]);
-    phic = prior_affine(P, 3, u[3]);
-  } else {
-    const double q = prior_affine(P, 1, u[1]);
-    const double c1 = prior_affine(P, 2, u[2]);
-    const double c2 = prior_affine(P, 3, u[3]);
-    const double m1 = 1.0 / (1.0 + q), m2 = q * m1;   // component masses over M
-    eta = m1 * m2;
-    beta = (c1 * (113.0 * m1 * m1 + 75.0 * eta) + c2 * (113.0 * m2 * m2 + 75.0 * eta)) * (1.0 / 12.0);
-    sigma = 79.0 / 8.0 * eta * c1 * c2;
-    tc = prior_affine(P, 9, u[9]);
-    phic = prior_affine(P, 10, u[10]);
-  }
+  const double v1 = prior_affine(P, 1, u[1]), v2 = prior_affine(P, 2, u[2]), v3 = prior_affine(P, 3, u[3]);
+  const double v9 = prior_affine(P, 9, u[9]), v10 = prior_affine(P, 10, u[10]);
+  // TF2_4P: (Mc, eta, t_c, phi_c); TF2_11P: (Mc, q, chi1, chi2, ..., t_c, phi_c)
+  const double q = v1, c1 = v2, c2 = v3;
+  const double m1 = 1.0 / (1.0 + q), m2 = q * m1;   // component masses over M
+  const double eta_q = m1 * m2;
+  const double beta_q = (c1 * (113.0 * m1 * m1 + 75.0 * eta_q) + c2 * (113.0 * m2 * m2 + 75.0 * eta_q)) * (1.0 / 12.0);
+  const double sigma_q = 79.0 / 8.0 * eta_q * c1 * c2;
+  const double eta = m4p ? v1 : eta_q;
+  const double beta = m4p ? 0.0 : beta_q;
+  const double sigma = m4p ? 0.0 : sigma_q;
+  const double tc = m4p ? v2 : v9;
+  const double phic = m4p ? v3 : v10;
   const double ln_mc = log(mc_msun * TSUN_S);
   const double ln_pim = 1.1447298858494002 + ln_mc - 0.6 * log(eta);   // ln(pi M)
   Probe p;
@@ -390,33 +393,37 @@ __device__ inline void probe_intrinsic(const ModelDev& M, const double* u, Probe
   r->ph0 = (-phic - 0.25 * PI) * (1.0 / TWO_PI);
   const double x3 = p.x * p.x * p.x;                 // pi M
   r->f_isco = 1.0 / (14.696938456699069 * x3);      // 1 / (6^(3/2) pi M)
-  int k = active_bins(M.f_lo, M.df, M.inv_df, M.n_bins, r->f_isco);
-  r->k_act = k > M.k_lim ? M.k_lim : k;
+  int k = active_bins(f_lo, df, inv_df, n_bins, r->f_isco);
+  r->k_act = k > k_lim ? k_lim : k;
   // sqrt(5/24) pi^(-2/3) Mc^(5/6) with Mc^(5/6) = pi^(-5/6) (pi M)^(5/6) eta^(1/2)
   // = pi^(-5/6) x^(5/2) eta^(1/2): one square root instead of an exponential
   r->amp_mc = 0.08196993152115736 * (x2 * sqrt(p.x * eta));   // sqrt(5/24) pi^(-3/2)
 }
 
+template <int NDET>
 __device__ inline void probe_extrinsic(const ModelDev& M, const double* u, ProbeRec* r) {
-  if (M.model == 1) {
-    r->inv_dist = 1.0 / M.fixed_dist_s;
+  const PriorDev& P = M.prior;
+  const bool m4p = M.model == 1;
+  const double fixed_dist_s = M.fixed_dist_s, gmst = M.gmst;
+  const int k4 = P.kind[4], k5 = P.kind[5], k8 = P.kind[8];
+  const double dv = prior_affine(P, 4, u[4]), v5 = prior_affine(P, 5, u[5]), v6 = prior_affine(P, 6, u[6]);
+  const double v7 = prior_affine(P, 7, u[7]), v8 = prior_affine(P, 8, u[8]);
+  if (m4p) {
+    r->inv_dist = 1.0 / fixed_dist_s;
     r->gre[0] = 1.0; r->gim[0] = 0.0; r->dt[0] = 0.0;
     return;
   }
-  const PriorDev& P = M.prior;
-  const double dv = prior_affine(P, 4, u[4]);
-  r->inv_dist = 1.0 / ((P.kind[4] == 3 ? cbrt(dv) : dv) * MPC_S);
-  const double ci = (P.kind[5] == 1) ? prior_affine(P, 5, u[5])
-                                     : sincos_cycles(prior_affine(P, 5, u[5]) * (1.0 / TWO_PI)).y;
+  r->inv_dist = 1.0 / ((k4 == 3 ? cbrt(dv) : dv) * MPC_S);
+  const double ci = (k5 == 1) ? v5 : sincos_cycles(v5 * (1.0 / TWO_PI)).y;
   const double hp = 0.5 * fma(ci, ci, 1.0), hx = ci;
-  const double2 p2 = sincos_cycles(prior_affine(P, 6, u[6]) * (1.0 / PI));   // angle 2 psi
-  const double2 ra = sincos_cycles((prior_affine(P, 7, u[7]) - M.gmst) * (1.0 / TWO_PI));
+  const double2 p2 = sincos_cycles(v6 * (1.0 / PI));   // angle 2 psi
+  const double2 ra = sincos_cycles((v7 - gmst) * (1.0 / TWO_PI));
   double sdec, cdec;
-  if (P.kind[8] == 2) {
-    sdec = prior_affine(P, 8, u[8]);
+  if (k8 == 2) {
+    sdec = v8;
     cdec = sqrt(fmax(0.0, 1.0 - sdec * sdec));
   } else {
-    const double2 de = sincos_cycles(prior_affine(P, 8, u[8]) * (1.0 / TWO_PI));
+    const double2 de = sincos_cycles(v8 * (1.0 / TWO_PI));
     sdec = de.x;
     cdec = de.y;
   }
@@ -425,8 +432,7 @@ __device__ inline void probe_extrinsic(const ModelDev& M, const double* u, Probe
   const double bx = -ra.y * sdec, by = -ra.x * sdec, bz = cdec;
   const double nx = cdec * ra.y, ny = cdec * ra.x, nz = sdec;
 #pragma unroll
-  for (int d = 0; d < MAX_DET; ++d) {
-    if (d >= M.n_det) break;
+  for (int d = 0; d < NDET; ++d) {
     const double* D = M.det[d].D;
     const double dax = D[0] * ax + D[1] * ay;
     const double day = D[1] * ax + D[3] * ay;

@@ -1186,7 +1186,7 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
       sT[cand] = tt;
       if (lane == 0) sMask[cand >> 6] = m;
     } else if (LK != LK_GAUSS) {
-      probe_extrinsic(M, y, rec);
+      probe_extrinsic<NDET>(M, y, rec);
     }
   };
   // After a batch's barrier every wave keeps the in-cube bits and the
@@ -1353,29 +1353,36 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
       // ---- the combined batch
       __syncthreads();
       {
-        double tt = 0.0;
-        bool valid = true;
-        if (cand < 2 * BL::SO) {
-          const bool left = cand < BL::SO;
-          const int steps = left ? cand : cand - BL::SO;
-          tt = left ? lo : hi;
-          for (int q = 0; q < steps; ++q) tt = left ? tt - w : tt + w;
-        } else if (cand < 2 * BL::SO + BL::H * BL::H * BL::SC) {
-          const int h = (cand - 2 * BL::SO) / BL::SC, c = (cand - 2 * BL::SO) - BL::SC * h;
-          const int na = h / BL::H, nbh = h - BL::H * na;
-          double l2 = lo, h2 = hi;
-          for (int q = 0; q < na; ++q) l2 -= w;
-          for (int q = 0; q < nbh; ++q) h2 += w;
+        // both kinds of position are formed branch-free (x + (-w) is x - w
+        // exactly), and each lane keeps the one its slot needs
+        const bool so = cand < 2 * BL::SO;
+        const bool valid = cand < 2 * BL::SO + BL::H * BL::H * BL::SC;
+        // step-out point: `steps` whole widths beyond the initial bracket
+        const bool left = cand < BL::SO;
+        const int steps = left ? cand : cand - BL::SO;
+        const double ws = left ? -w : w;
+        double ts = left ? lo : hi;
 #pragma unroll
-          for (int q = 0; q < BL::SC; ++q) {
-            if (q <= c) {
-              tt = fma(sur[2 + q], h2 - l2, l2);
-              if (tt < 0.0) l2 = tt; else h2 = tt;
-            }
-          }
-        } else {
-          valid = false;
+        for (int q = 0; q < BL::SO - 1; ++q) ts = q < steps ? ts + ws : ts;
+        // shrink point: attempt c of bracket hypothesis h
+        const int hc = so ? 0 : cand - 2 * BL::SO;
+        const int h = hc / BL::SC, c = hc - BL::SC * h;
+        const int na = h / BL::H, nbh = h - BL::H * na;
+        double l2 = lo, h2 = hi;
+#pragma unroll
+        for (int q = 0; q < BL::H - 1; ++q) {
+          l2 = q < na ? l2 + (-w) : l2;
+          h2 = q < nbh ? h2 + w : h2;
         }
+        double tsh = 0.0;
+#pragma unroll
+        for (int q = 0; q < BL::SC; ++q) {
+          if (q <= c) {
+            tsh = fma(sur[2 + q], h2 - l2, l2);
+            if (tsh < 0.0) l2 = tsh; else h2 = tsh;
+          }
+        }
+        const double tt = !valid ? 0.0 : (so ? ts : tsh);
         setup(valid, tt, dir);
       }
       __syncthreads();
