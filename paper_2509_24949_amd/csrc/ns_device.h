@@ -352,6 +352,7 @@ struct ProbeRec {
   double amp_mc;                    // sqrt(5/24) pi^(-2/3) Mc^(5/6) (intrinsic)
   double f_isco;                    // intrinsic
   int k_act, pad;                   // intrinsic
+  double hk[MAX_DET];               // prefix-table entries at bin k_act - 1 (intrinsic; 0 if none)
   double inv_dist;                  // 1 / D (extrinsic)
   double gre[MAX_DET], gim[MAX_DET];   // F+ (1 + cos^2 i)/2 and -Fx cos i (extrinsic)
   double dt[MAX_DET];               // arrival delays (extrinsic)
@@ -360,7 +361,7 @@ struct ProbeRec {
 // Both halves read every model constant they need before their first
 // branch, and choose between the models with selects, so that the constant
 // loads issue together instead of one round trip per use.
-__device__ inline void probe_intrinsic(const ModelDev& M, const double* u, ProbeRec* r) {
+__device__ inline int probe_intrinsic(const ModelDev& M, const double* u, ProbeRec* r) {
   const PriorDev& P = M.prior;
   const bool m4p = M.model == 1;
   const double f_lo = M.f_lo, df = M.df, inv_df = M.inv_df;
@@ -394,10 +395,12 @@ __device__ inline void probe_intrinsic(const ModelDev& M, const double* u, Probe
   const double x3 = p.x * p.x * p.x;                 // pi M
   r->f_isco = 1.0 / (14.696938456699069 * x3);      // 1 / (6^(3/2) pi M)
   int k = active_bins(f_lo, df, inv_df, n_bins, r->f_isco);
-  r->k_act = k > k_lim ? k_lim : k;
+  k = k > k_lim ? k_lim : k;
+  r->k_act = k;
   // sqrt(5/24) pi^(-2/3) Mc^(5/6) with Mc^(5/6) = pi^(-5/6) (pi M)^(5/6) eta^(1/2)
   // = pi^(-5/6) x^(5/2) eta^(1/2): one square root instead of an exponential
   r->amp_mc = 0.08196993152115736 * (x2 * sqrt(p.x * eta));   // sqrt(5/24) pi^(-3/2)
+  return k;
 }
 
 template <int NDET>
@@ -452,10 +455,10 @@ __device__ inline void probe_extrinsic(const ModelDev& M, const double* u, Probe
   }
 }
 
-// The Probe of a record; hpre (may be null; rows of length hstride) gives
-// <h|h> from the prefix table.
+// The Probe of a record; with_hh: <h|h> from the record's prefix-table
+// entries (else 0).
 template <int NDET>
-__device__ inline Probe probe_from_rec(const ProbeRec& r, const double* hpre, int hstride) {
+__device__ inline Probe probe_from_rec(const ProbeRec& r, bool with_hh) {
   Probe p;
   p.x = r.x; p.lnx = r.lnx; p.pref = r.pref;
   p.c2 = r.c2; p.c3 = r.c3; p.c4 = r.c4; p.c5 = r.c5; p.c5l = r.c5l; p.c6 = r.c6; p.c6l = r.c6l; p.c7 = r.c7;
@@ -467,8 +470,7 @@ __device__ inline Probe probe_from_rec(const ProbeRec& r, const double* hpre, in
     p.kre[d] = amp * r.gre[d];
     p.kim[d] = amp * r.gim[d];
     p.dt[d] = r.dt[d];
-    if (hpre && r.k_act > 0)
-      hh += (p.kre[d] * p.kre[d] + p.kim[d] * p.kim[d]) * hpre[(size_t)d * hstride + r.k_act - 1];
+    if (with_hh && r.k_act > 0) hh += (p.kre[d] * p.kre[d] + p.kim[d] * p.kim[d]) * r.hk[d];
   }
   p.hh = hh;
   return p;

@@ -1181,8 +1181,17 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
     const unsigned long long m = __ballot(cin);
     ProbeRec* rec = reinterpret_cast<ProbeRec*>(sP + cand * SL_PSTRIDE);
     if (intrinsic_half) {
-      if (LK == LK_GAUSS) sG[cand] = gauss_lambda(M, y);
-      else probe_intrinsic(M, y, rec);
+      if (LK == LK_GAUSS) {
+        sG[cand] = gauss_lambda(M, y);
+      } else {
+        const int ka = probe_intrinsic(M, y, rec);
+        if constexpr (lk_full(LK)) {
+          // the prefix-table entries <h|h> needs, read here once rather than
+          // by every evaluating thread
+#pragma unroll
+          for (int dd = 0; dd < NDET; ++dd) rec->hk[dd] = ka > 0 ? V.hpre[(size_t)dd * V.hstride + ka - 1] : 0.0;
+        }
+      }
       sT[cand] = tt;
       if (lane == 0) sMask[cand >> 6] = m;
     } else if (LK != LK_GAUSS) {
@@ -1208,8 +1217,7 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
   auto eval = [&](int q) -> double {
     ++nprobe;
     if (LK == LK_GAUSS) return sG[q];
-    const Probe pb = probe_from_rec<NDET>(*reinterpret_cast<const ProbeRec*>(sP + q * SL_PSTRIDE),
-                                          lk_full(LK) ? V.hpre : nullptr, V.hstride);
+    const Probe pb = probe_from_rec<NDET>(*reinterpret_cast<const ProbeRec*>(sP + q * SL_PSTRIDE), lk_full(LK));
     nbins += lk_full(LK) ? pb.k_act : RB.nb + 1;
     double tot;
     if (lk_rb(LK)) tot = wave_sum(rb_partial<NDET, lk_mixed(LK)>(pb, RBv, M.n_bins, sr0, tid, NT));
@@ -1244,11 +1252,11 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
     double part = 0.0, hh = 0.0, kact = 0.0;
     if constexpr (lk_rb(LK)) {
       // both halves pass the barrier inside rb_partial
-      const Probe pb = q >= 0 ? probe_from_rec<NDET>(rec(q), nullptr, 0) : Probe{};
+      const Probe pb = q >= 0 ? probe_from_rec<NDET>(rec(q), false) : Probe{};
       part = rb_partial<NDET, lk_mixed(LK)>(pb, RBv, M.n_bins, second ? sr1 : sr0, second ? tid - NT / 2 : tid, NT / 2,
                                             q >= 0);
     } else if (q >= 0) {
-      const Probe pb = probe_from_rec<NDET>(rec(q), V.hpre, V.hstride);
+      const Probe pb = probe_from_rec<NDET>(rec(q), true);
       part = fullgrid_partial<NDET, lk_mixed(LK), true>(pb, V, second ? tid - NT / 2 : tid, NT / 2);
       hh = pb.hh;
       kact = (double)pb.k_act;
