@@ -164,10 +164,9 @@ hipError_t configure_slice_packed(const ModelDev& M, int rb_nb, LaunchCfg* C);
 // packed selection (rank_off: prefix of ceil(n_r/4) blocks), preparation,
 // chain kernel (slice_off: prefix of k_r blocks) and termination.  lk is the
 // shared likelihood kind (LK_FULL, LK_FULL32, LK_RB or LK_RB32), nt the shared
-// threads per chain, max_n the largest n_live, slice_lds the largest
-// chain-kernel LDS of the runs.
+// threads per chain, slice_lds the largest chain-kernel LDS of the runs.
 hipError_t launch_iteration_packed(const PackedRun* runs, const int* rank_off, const int* slice_off, int nr,
-                                   int rank_blocks, int slice_blocks, int lk, int nt, int max_n, size_t slice_lds,
+                                   int rank_blocks, int slice_blocks, int lk, int nt, size_t slice_lds,
                                    hipStream_t st);
 // done flag of every run into out[nr].
 hipError_t launch_gather_done(const PackedRun* runs, int nr, int* out, hipStream_t st);

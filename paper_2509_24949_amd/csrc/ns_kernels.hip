@@ -901,8 +901,14 @@ __global__ __launch_bounds__(256) void k_rank(const double* __restrict__ lam, in
 
 // ------------------------------------------------------------- iteration prep
 // One workgroup of 1024 threads; s_surv: n ints of LDS (survivor list).
-__device__ void prep_body(const RunDev& R, int* s_surv) {
+constexpr int PCH = 1024;             // live points per chunk of the mean and covariance passes
+
+// One workgroup of 1024 threads.  spts holds a chunk of live points by
+// coordinate (all of them when n <= PCH) and afterwards the survivor list.
+__device__ void prep_body(const RunDev& R) {
   __shared__ double sbuf[1024];
+  __shared__ double spts[MAX_DIM * PCH];
+  int* s_surv = reinterpret_cast<int*>(spts);
   __shared__ double smean[MAX_DIM];
   __shared__ double scov[MAX_DIM * MAX_DIM];
   __shared__ int sint[1024];
@@ -937,7 +943,6 @@ __device__ void prep_body(const RunDev& R, int* s_surv) {
     const double lw = l + lx + log(-expm1(-inv));
     const double lxn = lx - inv;
     const long long q = nd0 + j;
-    for (int i = 0; i < d; ++i) R.du[q * d + i] = R.u[(size_t)slot * d + i];
     R.dlam[q] = lraw;
     R.dlogx[q] = lxn;
     R.dlogw[q] = lw;
@@ -946,6 +951,11 @@ __device__ void prep_body(const RunDev& R, int* s_surv) {
     R.dnlive[q] = n - j;
     mloc = fmax(mloc, lw);
     lx = lxn;
+  }
+  // the dead points' coordinates, copied with independent loads
+  for (int idx = tid; idx < k * d; idx += 1024) {
+    const int j = idx / d, i = idx - j * d;
+    R.du[(nd0 + j) * d + i] = R.u[(size_t)R.dead[j] * d + i];
   }
   double m = block_max<1024>(mloc, sbuf);
   m = fmax(m, logZ0);
@@ -978,33 +988,76 @@ __device__ void prep_body(const RunDev& R, int* s_surv) {
   }
 
   // ---- covariance of all n live points (before removal), 1/(n-1)
-  double part[MAX_DIM];
-#pragma unroll
-  for (int i = 0; i < MAX_DIM; ++i) part[i] = 0.0;
-  for (int j = tid; j < n; j += 1024) {
-#pragma unroll
-    for (int i = 0; i < MAX_DIM; ++i)
-      if (i < d) part[i] += R.u[(size_t)j * d + i];
-  }
-  block_sum_k<1024, MAX_DIM>(part, sbuf);
-  if (tid < d) smean[tid] = part[tid] / n;
-  __syncthreads();
-  // lower-triangle entry e -> (a, b), a >= b, row-major; wave w sums the
-  // entries e = w, w + 16, ... over all points, one point per lane at a time
-  const int E = d * (d + 1) / 2;
-  const int lane = tid & 63, wv = tid >> 6;
-  for (int e = wv; e < E; e += 16) {
-    int ea = 0, r = e;
-    while (r > ea) { r -= ea + 1; ++ea; }
-    const int eb = r;
-    const double ma = smean[ea], mb = smean[eb];
-    double cs = 0.0;
-    for (int j = lane; j < n; j += 64) cs += (R.u[(size_t)j * d + ea] - ma) * (R.u[(size_t)j * d + eb] - mb);
-    cs = wave_sum(cs) / (double)(n - 1);
-    if (lane == 0) {
-      scov[ea * d + eb] = cs;
-      scov[eb * d + ea] = cs;
+  // The points pass through LDS in chunks of PCH, one row per coordinate,
+  // read with coalesced loads: first for the mean (a group of 1024/d threads
+  // per coordinate), then, centred, for the covariance.
+  {
+    const int G1 = 1024 / d;
+    const int mi = tid / G1, msub = tid - mi * G1;
+    double ms = 0.0;
+    for (int j0 = 0; j0 < n; j0 += PCH) {
+      const int cnt = min(PCH, n - j0);
+      __syncthreads();                // the previous chunk has been read
+      for (int idx = tid; idx < cnt * d; idx += 1024) {
+        const int jj = idx / d, i = idx - jj * d;
+        spts[i * PCH + jj] = R.u[(size_t)j0 * d + idx];
+      }
+      __syncthreads();
+      if (mi < d)
+        for (int jj = msub; jj < cnt; jj += G1) ms += spts[mi * PCH + jj];
     }
+    sbuf[tid] = ms;
+    __syncthreads();
+    if (tid < d) {
+      double t = 0.0;
+      for (int q = 0; q < G1; ++q) t += sbuf[tid * G1 + q];
+      smean[tid] = t / n;
+    }
+    __syncthreads();
+  }
+  // lower-triangle entry e -> (a, b), a >= b, row-major: a group of G
+  // threads sums each entry over a strided share of every chunk (the chunk
+  // of the mean pass is still in LDS when n <= PCH), and the group's partial
+  // sums meet in LDS at the end
+  const int E = d * (d + 1) / 2;
+  const int G = 1024 / E;
+  const int lane = tid & 63, wv = tid >> 6;
+  const int eg = tid / G, sub = tid - eg * G;
+  int ea = 0, eb = 0;
+  if (eg < E) {
+    int r = eg;
+    while (r > ea) { r -= ea + 1; ++ea; }
+    eb = r;
+  }
+  const double ma = smean[ea], mb = smean[eb];
+  double cs = 0.0;
+  for (int j0 = 0; j0 < n; j0 += PCH) {
+    const int cnt = min(PCH, n - j0);
+    if (n > PCH) {
+      __syncthreads();                // the previous chunk has been read
+      for (int idx = tid; idx < cnt * d; idx += 1024) {
+        const int jj = idx / d, i = idx - jj * d;
+        spts[i * PCH + jj] = R.u[(size_t)j0 * d + idx];
+      }
+      __syncthreads();
+    }
+    if (eg < E) {
+      const double* ra = spts + ea * PCH;
+      const double* rb = spts + eb * PCH;
+      for (int jj = sub; jj < cnt; jj += G) cs += (ra[jj] - ma) * (rb[jj] - mb);
+    }
+  }
+  sbuf[tid] = cs;
+  __syncthreads();
+  if (tid < E) {
+    int a = 0, r = tid;
+    while (r > a) { r -= a + 1; ++a; }
+    const int b = r;
+    double c = 0.0;
+    for (int q = 0; q < G; ++q) c += sbuf[tid * G + q];
+    c /= (double)(n - 1);
+    scov[a * d + b] = c;
+    scov[b * d + a] = c;
   }
   __syncthreads();
   if (wv == 0) {
@@ -1060,10 +1113,7 @@ __device__ void prep_body(const RunDev& R, int* s_surv) {
   }
 }
 
-__global__ __launch_bounds__(1024) void k_prep(RunDev R) {
-  extern __shared__ int s_surv[];
-  prep_body(R, s_surv);
-}
+__global__ __launch_bounds__(1024) void k_prep(RunDev R) { prep_body(R); }
 
 
 // ------------------------------------------------------------ slice chains
@@ -1633,8 +1683,7 @@ __global__ __launch_bounds__(256) void k_rank_packed(const PackedRun* __restrict
 }
 
 __global__ __launch_bounds__(1024) void k_prep_packed(const PackedRun* __restrict__ runs) {
-  extern __shared__ int s_surv[];
-  prep_body(runs[blockIdx.x].R, s_surv);
+  prep_body(runs[blockIdx.x].R);
 }
 
 __global__ __launch_bounds__(1024) void k_term_packed(const PackedRun* __restrict__ runs) {
@@ -2014,7 +2063,7 @@ hipError_t launch_iteration(const ModelDev& M, const ModelDev* Md, const Tables&
   e = launch_select(R.lam, R.n, R.k, R.rank, R.dead, nullptr, &R.state->done, st);
   if (e != hipSuccess) return e;
   if (ev && (e = hipEventRecord(ev[1], st)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_prep, dim3(1), dim3(1024), (size_t)R.n * sizeof(int), st, R);
+  hipLaunchKernelGGL(k_prep, dim3(1), dim3(1024), 0, st, R);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (ev && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;
   if (M.likelihood == LK_GAUSS) {
@@ -2074,13 +2123,13 @@ hipError_t launch_slice_packed_nt(const PackedRun* runs, const int* slice_off, i
 }  // namespace
 
 hipError_t launch_iteration_packed(const PackedRun* runs, const int* rank_off, const int* slice_off, int nr,
-                                   int rank_blocks, int slice_blocks, int lk, int nt, int max_n, size_t slice_lds,
+                                   int rank_blocks, int slice_blocks, int lk, int nt, size_t slice_lds,
                                    hipStream_t st) {
   if (nr <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_rank_packed, dim3(rank_blocks), dim3(256), 0, st, runs, rank_off, nr);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_prep_packed, dim3(nr), dim3(1024), (size_t)max_n * sizeof(int), st, runs);
+  hipLaunchKernelGGL(k_prep_packed, dim3(nr), dim3(1024), 0, st, runs);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   switch (nt) {
     case 64: e = launch_slice_packed_nt<64>(runs, slice_off, nr, slice_blocks, lk, slice_lds, st); break;

@@ -54,7 +54,7 @@ struct Finished {
 };
 
 struct Group {
-  int first, count, lk, nt, rank_blocks, slice_blocks, max_n;
+  int first, count, lk, nt, rank_blocks, slice_blocks;
   size_t lds;
 };
 
@@ -161,14 +161,13 @@ int rebuild(ns_server* s) {
     const ns_run* r = s->running[i].run;
     s->h_runs[i] = PackedRun{r->Md, r->T, r->RB, r->R};
     if (s->groups.empty() || s->groups.back().lk != s->running[i].lk || s->groups.back().nt != s->running[i].nt)
-      s->groups.push_back(Group{i, 0, s->running[i].lk, s->running[i].nt, 0, 0, 0, 0});
+      s->groups.push_back(Group{i, 0, s->running[i].lk, s->running[i].nt, 0, 0, 0});
     Group& g = s->groups.back();
     slice_off[i] = g.slice_blocks;
     rank_off[i] = g.rank_blocks;
     g.count += 1;
     g.slice_blocks += r->R.k;
     g.rank_blocks += (r->R.n + 3) / 4;
-    g.max_n = std::max(g.max_n, r->R.n);
     g.lds = std::max(g.lds, r->C.lds_bytes);
   }
   if (nr > 0) {
@@ -184,7 +183,7 @@ hipError_t enqueue_iterations(ns_server* s, int n_iters) {
     for (const Group& g : s->groups) {
       hipError_t e = launch_iteration_packed(s->d_runs + g.first, s->d_off + s->max_runs + g.first,
                                              s->d_off + g.first, g.count, g.rank_blocks, g.slice_blocks, g.lk,
-                                             g.nt, g.max_n, g.lds, s->st);
+                                             g.nt, g.lds, s->st);
       if (e != hipSuccess) return e;
     }
   return hipSuccess;
