@@ -34,9 +34,11 @@ TRANS_PEAK_TOPS = LANE_OPS / 4 / 1e12      # single-precision sin/cos/exp/log: q
 SINCOS_FLOPS = 44                # flops of the double-precision sincos in cycles
 PHASE_FLOPS = 24                 # per (probe, bin): PN phase series, shared by the detectors
 DET_FLOPS = 2 + SINCOS_FLOPS + 8 # per (probe, bin, detector): delay, sincos, complex accumulate
-# relative binning per (probe, edge): the phase (24) and per detector delay,
-# sincos and the complex ratio (2 + sincos + 6); per (probe, coarse bin,
-# detector) the linear-model terms (27), counted per edge as nb/(nb+1) of it
+# relative binning per (probe, edge read): the phase (24) and per detector
+# delay, sincos and the complex ratio (2 + sincos + 6); per (probe, active
+# coarse bin, detector) the linear-model terms (27).  A probe reads the edges
+# of its active bins, one more than the bins, so the bins are counted per edge
+# as (edges - probes) / edges of it
 RB_EDGE_DET = 2 + SINCOS_FLOPS + 6
 RB_BIN_DET = 27
 
@@ -58,9 +60,10 @@ def log(msg: str):
     print(msg, file=sys.stderr, flush=True)
 
 
-def op_mix(w):
+def op_mix(w, bins_per_edge=None):
     """Algorithmic work of one counted term (full grid: one active bin of one
-    probe; relative binning: one edge of one probe) as (double-precision
+    probe; relative binning: one edge read by one probe, with bins_per_edge
+    active coarse bins per edge, by default nb/(nb+1)) as (double-precision
     flops, single-precision flops, single-precision transcendental ops).
     The mixed form keeps the phase, the delay and the cycle reduction in
     double (4 flops per detector) and takes sin and cos on the transcendental
@@ -69,7 +72,8 @@ def op_mix(w):
 
     nd = w.n_det
     if w.likelihood == synth.LIKE_RB:
-        bins = nd * RB_BIN_DET * w.rb_n_bins / (w.rb_n_bins + 1)
+        bpe = w.rb_n_bins / (w.rb_n_bins + 1) if bins_per_edge is None else bins_per_edge
+        bins = nd * RB_BIN_DET * bpe
         if w.precision == 1:
             return PHASE_FLOPS + 4 * nd, 6 * nd + bins, 2 * nd
         return PHASE_FLOPS + nd * RB_EDGE_DET + bins, 0.0, 0.0
@@ -78,23 +82,30 @@ def op_mix(w):
     return PHASE_FLOPS + nd * DET_FLOPS, 0.0, 0.0
 
 
-def seconds_per_term(w) -> float:
+def seconds_per_term(w, bins_per_edge=None) -> float:
     """Shortest time the vector units need for one term of this workload."""
-    f64, f32, tr = op_mix(w)
+    f64, f32, tr = op_mix(w, bins_per_edge)
     return (f64 / FP64_PEAK_TFLOPS + f32 / FP32_PEAK_TFLOPS + tr / TRANS_PEAK_TOPS) * 1e-12
 
 
-def flops_per_term(w) -> float:
+def flops_per_term(w, bins_per_edge=None) -> float:
     """Algorithmic operations per counted term (all kinds together)."""
-    return sum(op_mix(w))
+    return sum(op_mix(w, bins_per_edge))
 
 
-def peak_tflops(w) -> float:
+def bins_per_edge(terms: int, probes: int) -> float:
+    """Active coarse bins per edge read, from a batch's totals: each probe
+    reads one edge more than it has active bins (a probe with no active bin
+    reads none, so this errs low)."""
+    return max(terms - probes, 0) / terms if terms > 0 else 0.0
+
+
+def peak_tflops(w, bins_per_edge=None) -> float:
     """Rate of the vector units on this workload's operation mix: its
     operations over the shortest time the units need for them (double FMA at
     78.6 TFLOP/s, packed single FMA at 157.3, transcendentals at 9.8 Tops/s).
     Equals the double-precision peak for the double-precision forms."""
-    f64, f32, tr = op_mix(w)
+    f64, f32, tr = op_mix(w, bins_per_edge)
     t = f64 / FP64_PEAK_TFLOPS + f32 / FP32_PEAK_TFLOPS + tr / TRANS_PEAK_TOPS
     return (f64 + f32 + tr) / t
 
@@ -301,8 +312,9 @@ def standalone_loglike(w, spec, n_probes: int = 65536, reps: int = 20) -> dict:
     launch_s = a.elapsed_time(b) / reps * 1e-3
     n_terms = int(terms.sum().item())
     r.close()
-    flops = n_terms * flops_per_term(w)
-    peak = peak_tflops(w)
+    bpe = bins_per_edge(n_terms, n_probes)
+    flops = n_terms * flops_per_term(w, bpe)
+    peak = peak_tflops(w, bpe)
     achieved = flops / launch_s / 1e12
     return {"kernel": "k_loglike_rb" if w.likelihood == 1 else "k_loglike", "probes": n_probes,
             "probe_mix": "half prior draws, half Gaussian (0.02) around the injection in the unit cube",
@@ -410,11 +422,12 @@ def main():
         f"{stats['ms_slice'] / K:.3f} ms/iter, select {stats['ms_select'] / K:.3f}, prep {stats['ms_prep'] / K:.3f}, "
         f"term {stats['ms_term'] / K:.3f}")
     r.close()
-    flops_launch = bins_timed / K * flops_per_term(w)
+    bpe = bins_per_edge(bins_timed, evals)
+    flops_launch = bins_timed / K * flops_per_term(w, bpe)
     slice_s = stats["ms_slice"] / K * 1e-3
     achieved = flops_launch / slice_s / 1e12
     mixed = w.precision == 1
-    peak = peak_tflops(w)
+    peak = peak_tflops(w, bpe)
     traffic = None
     if os.path.exists(args.traffic):
         try:

@@ -176,7 +176,8 @@ NS_API int ns_dead(ns_run* run, long cap, double* u, double* logl, double* logx,
  * u_dev: device [n][n_dim] unit-cube points; out_dev: device [n];
  * terms_dev (may be NULL): device [n] receives the terms each probe costs
  * (full grid: its active bins k with f_k <= f_ISCO; relative binning: the
- * nb + 1 edges; Gaussian: 0).  Launched on the run's stream, asynchronous.
+ * edges its active coarse bins need, one more than those bins, or 0 if none
+ * is active; Gaussian: 0).  Launched on the run's stream, asynchronous.
  * This is the fused waveform-plus-likelihood kernel the slice chains call,
  * exposed for direct use. */
 NS_API int ns_loglike(ns_run* run, const double* u_dev, long n, double* out_dev, int* terms_dev);
@@ -208,7 +209,7 @@ typedef struct {
     double ms_slice;
     double ms_term;
     long long evals;         /* likelihood evaluations of the whole run so far */
-    long long bin_terms;     /* sum over evaluations of the active frequency bins (full grid) */
+    long long bin_terms;     /* sum over evaluations of the terms ns_loglike reports per probe */
     int slice_threads;       /* threads per chain workgroup */
     int lds_tables;          /* 1 if the likelihood tables are staged in LDS */
 } ns_stats_t;

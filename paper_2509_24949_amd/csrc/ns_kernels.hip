@@ -626,6 +626,19 @@ __device__ inline RBTables stage_rb(const RBTables& B, double* lds, int tid, int
 // ratios of the probe.  Every thread of the workgroup calls it (it contains a
 // barrier); an inactive caller only takes part in the barrier.  WAVE: the
 // probe belongs to one wavefront, which synchronises on its own.
+// Edges relative binning reads for a probe with k_act active grid bins: those
+// of its active coarse bins (bin b is active iff edge[b] < k_act), one more
+// than the bins, or none if bin 0 is inactive.  Counted with ballots over
+// the wavefront (every lane must take part); the result is uniform.
+__device__ inline int rb_edges_read(const RBTables& B, int k_act, int lane) {
+  int n_act = 0;
+  for (int b0 = 0; b0 < B.nb; b0 += 64) {
+    const int b = b0 + lane;
+    n_act += __popcll(__ballot(b < B.nb && B.edge[b] < k_act));
+  }
+  return n_act > 0 ? n_act + 1 : 0;
+}
+
 template <int NDET, bool MX, bool WAVE = false>
 __device__ inline double rb_partial(const Probe& p, const RBTables& B, int n_bins, void* lds, int tid, int nt,
                                     bool active = true) {
@@ -633,6 +646,9 @@ __device__ inline double rb_partial(const Probe& p, const RBTables& B, int n_bin
   CT* sr = reinterpret_cast<CT*>(lds);
   const int nb = B.nb;
   for (int e = active ? tid : nb + 1; e <= nb; e += nt) {
+    // edge e bounds bins e - 1 and e; with increasing edges it is read only
+    // if bin e - 1 (bin 0 for e = 0) starts below the active-bin count
+    if (B.edge[e > 0 ? e - 1 : 0] >= p.k_act) continue;
     const double f = B.fe[e];
     const double psi = phase_cycles(p, f, B.fe13[e], B.lnfe3[e], B.fem53[e]);
 #pragma unroll
@@ -727,15 +743,20 @@ __global__ __launch_bounds__(64) void k_loglike_rb(const ModelDev* __restrict__ 
     Probe pr;
     make_probe(M, nullptr, y, &pr);
     double mine = 0.0;
+    int mine_edges = 0;
     const int cnt = (n - base) < 64 ? (int)(n - base) : 64;
     for (int p = 0; p < cnt; ++p) {
       const Probe pb = probe_from_lane<NDET>(pr, p);
       const double tot = wave_sum(rb_partial<NDET, MX>(pb, RB, M.n_bins, sr, lane, 64));
-      if (lane == p) mine = tot;
+      const int ne = rb_edges_read(RB, pb.k_act, lane);
+      if (lane == p) {
+        mine = tot;
+        mine_edges = ne;
+      }
       __syncthreads();   // the ratios in LDS are rewritten by the next probe
     }
     if (i < n) out[i] = mine;
-    if (terms && i < n) terms[i] = RB.nb + 1;
+    if (terms && i < n) terms[i] = mine_edges;
   }
 }
 
@@ -862,9 +883,10 @@ __global__ __launch_bounds__(512) void k_rb_bins(RBTables RB, int n_bins, const 
   for (long p = (long)blockIdx.x * 8 + wv; p < n; p += (long)gridDim.x * 8) {
     const Probe pb = P[p];
     const double tot = wave_sum(rb_partial<NDET, MX, true>(pb, V, n_bins, sr, lane, 64));
+    const int ne = terms ? rb_edges_read(V, pb.k_act, lane) : 0;
     if (lane == 0) {
       out[p] = tot;
-      if (terms) terms[p] = RB.nb + 1;
+      if (terms) terms[p] = ne;
     }
     // the next probe rewrites this wavefront's ratios
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -1268,12 +1290,11 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
     ++nprobe;
     if (LK == LK_GAUSS) return sG[q];
     const Probe pb = probe_from_rec<NDET>(*reinterpret_cast<const ProbeRec*>(sP + q * SL_PSTRIDE), lk_full(LK));
-    nbins += lk_full(LK) ? pb.k_act : RB.nb + 1;
+    double* rb = sred + buf * (NW + 4);
     double tot;
     if (lk_rb(LK)) tot = wave_sum(rb_partial<NDET, lk_mixed(LK)>(pb, RBv, M.n_bins, sr0, tid, NT));
     else tot = wave_sum(fullgrid_partial<NDET, lk_mixed(LK), true>(pb, V, tid, NT));
     if constexpr (NW > 1) {
-      double* rb = sred + buf * (NW + 4);
       if (lane == 0) rb[wv] = tot;
       __syncthreads();
       tot = 0.0;
@@ -1283,6 +1304,8 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
     } else if (lk_rb(LK)) {
       __syncthreads();   // the edge ratios in LDS are rewritten by the next probe
     }
+    // terms: the active bins (full grid) or the edges read (relative binning)
+    nbins += lk_full(LK) ? pb.k_act : rb_edges_read(RBv, pb.k_act, lane);
     return lk_rb(LK) ? tot : tot - 0.5 * pb.hh;
   };
   // Full grid with two or more waves: lambdas of two candidates at once
@@ -1291,14 +1314,15 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
   // the walk counts the evaluations the sequential algorithm makes.
   constexpr bool PAIR = (lk_full(LK) || lk_rb(LK)) && NW >= 2;
   auto rec = [&](int q) -> const ProbeRec& { return *reinterpret_cast<const ProbeRec*>(sP + q * SL_PSTRIDE); };
-  auto count = [&](int kact) {
+  auto count = [&](int terms) {   // the probe's active bins or relative-binning edges
     ++nprobe;
-    nbins += lk_full(LK) ? kact : RB.nb + 1;
+    nbins += terms;
   };
   auto eval2 = [&](int q1, int q2, double* l1, double* l2, int* k1, int* k2) {
     constexpr int HW = NW / 2;
     const bool second = tid >= NT / 2;
     const int q = second ? q2 : q1;
+    double* rb = sred + buf * (NW + 4);
     double part = 0.0, hh = 0.0, kact = 0.0;
     if constexpr (lk_rb(LK)) {
       // both halves pass the barrier inside rb_partial
@@ -1312,11 +1336,10 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
       kact = (double)pb.k_act;
     }
     const double tot = wave_sum(part);
-    double* rb = sred + buf * (NW + 4);
     if (lane == 0) rb[wv] = tot;
     if (lane == 0 && wv % HW == 0) {
       rb[NW + (second ? 1 : 0)] = hh;
-      rb[NW + 2 + (second ? 1 : 0)] = kact;
+      if constexpr (lk_full(LK)) rb[NW + 2 + (second ? 1 : 0)] = kact;
     }
     __syncthreads();
     double t1 = 0.0, t2 = 0.0;
@@ -1327,8 +1350,14 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
     }
     *l1 = t1 - 0.5 * rb[NW];
     *l2 = t2 - 0.5 * rb[NW + 1];
-    *k1 = (int)rb[NW + 2];
-    *k2 = (int)rb[NW + 3];
+    if constexpr (lk_rb(LK)) {
+      // terms of a relative-binning probe: the edges it read
+      *k1 = q1 >= 0 ? rb_edges_read(RBv, rec(q1).k_act, lane) : 0;
+      *k2 = q2 >= 0 ? rb_edges_read(RBv, rec(q2).k_act, lane) : 0;
+    } else {
+      *k1 = (int)rb[NW + 2];
+      *k2 = (int)rb[NW + 3];
+    }
     buf ^= 1;
   };
 

@@ -232,6 +232,17 @@ def test_rb_loglike_parity(torch_cuda, n):
     one = run.loglike(torch.from_numpy(synth.theta_to_cube_box(w, w.theta_inj)[None, :].copy()).cuda())
     th = orc.prior_transform(synth.theta_to_cube_box(w, w.theta_inj))
     assert abs(one.item() - orc_full.loglike_theta(th)) <= 1e-9 * (abs(full) + 1)
+    # per-probe term counts: the edges its active coarse bins need (one more
+    # than those bins), active bins from the oracle's ISCO-cut waveform
+    terms = torch.zeros(n, dtype=torch.int32, device="cuda")
+    run.loglike(torch.from_numpy(u).cuda(), terms=terms)
+    terms = terms.cpu().numpy()
+    edges = oracle.RB(orc).edges()
+    for i in range(0, n, max(1, n // 40)):
+        hr, hi = orc.waveform(orc.prior_transform(u[i]), 0, cut=True)
+        k_act = int(np.count_nonzero((hr != 0.0) | (hi != 0.0)))
+        n_act = int(np.count_nonzero(edges[:-1] < k_act))
+        assert terms[i] == (n_act + 1 if n_act else 0), (i, k_act, n_act)
 
 
 def test_rb_iterations_lockstep(torch_cuda):
