@@ -20,6 +20,13 @@
  * shrinkage, the stationary-phase TaylorF2 waveform, the Whittle likelihood,
  * relative binning); where the paper is silent the reading is stated at the
  * function.
+ *
+ * Parity unpinned: the 3PN and 3.5PN phase coefficients and the aligned-spin
+ * terms of the TaylorF2 phase (psi[6], psi[7], and the beta and sigma parts
+ * of psi[3] and psi[4]) are checked only by double entry against the
+ * post-Newtonian literature.  The zero-spin phase through 2.5PN is pinned by
+ * the tests against energy balance with the post-Newtonian binding energy
+ * and flux.
  */
 #include "nsorc.h"
 

@@ -99,6 +99,57 @@ def test_phase_newtonian_chirp_time():
         assert abs(c2 - (743.0 / 252.0 + 11.0 * eta / 3.0)) < 0.01 * (743.0 / 252.0 + 11.0 * eta / 3.0), (eta, c2)
 
 
+def _tau_series_from_energy_balance(eta):
+    """Time to coalescence of a circular, non-spinning binary from energy
+    balance, dt/dv = -E'(v)/F(v), with the binding energy
+    E = -(M eta v^2/2)[1 - (3/4 + eta/12) v^2 - (27/8 - 19 eta/8 + eta^2/24) v^4]
+    and the flux F = (32/5) eta^2 v^10 [1 - (1247/336 + 35 eta/12) v^2 + 4 pi v^3
+    + (-44711/9072 + 9271 eta/504 + 65 eta^2/18) v^4 - (8191/672 + 583 eta/24) pi v^5]
+    (post-Newtonian results for point masses; the v^3 and v^5 flux terms are
+    the wave tails).  Expanding the ratio and integrating term by term gives
+    tau = (5 M/(256 eta v^8)) sum_k tau_k v^k; returns tau_0 .. tau_5."""
+    e = np.zeros(6)
+    e[0], e[2], e[4] = 1.0, -(3 / 4 + eta / 12), -(27 / 8 - 19 * eta / 8 + eta**2 / 24)
+    fl = np.zeros(6)
+    fl[0], fl[2], fl[3] = 1.0, -(1247 / 336 + 35 * eta / 12), 4 * math.pi
+    fl[4] = -44711 / 9072 + 9271 * eta / 504 + 65 * eta**2 / 18
+    fl[5] = -(8191 / 672 + 583 * eta / 24) * math.pi
+    num = np.array([e[k] * (k + 2) / 2 for k in range(6)])    # -E'(v) / (M eta v)
+    ratio = np.zeros(6)
+    for k in range(6):
+        ratio[k] = num[k] - sum(ratio[j] * fl[k - j] for j in range(k))
+    return [8 * ratio[k] / (8 - k) for k in range(6)]
+
+
+def test_phase_matches_energy_balance_to_2p5pn():
+    """The zero-spin phase's time to coalescence t_c - Psi'(f)/(2 pi), read
+    off the oracle by a least-squares fit in v = (pi M f)^(1/3) over the
+    powers the 3.5PN phase can produce (v^2 .. v^7 and v^6 ln v), has the
+    1PN, 1.5PN (tail), 2PN and 2.5PN coefficients that energy balance gives
+    from the binding energy and flux.  Catches a wrong or mistyped phase
+    coefficient through 2PN, in either its mass-ratio terms or its constant,
+    and a wrong 2.5PN logarithmic term.  The 3PN and 3.5PN terms and the spin
+    terms are not pinned here."""
+    mc_msun, tc, phic = 24.0, 0.013, 0.3
+    lib = oracle.lib()
+    for eta in (0.1, 0.2, 0.25):
+        m = mc_msun * TSUN * eta ** -0.6
+        vs = np.linspace(0.02, 0.3, 80)
+        r = []
+        for v in vs:
+            f = v**3 / (math.pi * m)
+            h = f * 1e-5
+            dpsi = (lib.orc_tf2_phase(f + h, mc_msun, eta, 0.0, 0.0, tc, phic)
+                    - lib.orc_tf2_phase(f - h, mc_msun, eta, 0.0, 0.0, tc, phic)) / (2 * h)
+            tau = tc - dpsi / (2 * math.pi)
+            r.append(tau / (5 * m / (256 * eta * v**8)) - 1.0)
+        basis = np.stack([vs**2, vs**3, vs**4, vs**5, vs**6, vs**6 * np.log(vs), vs**7], axis=1)
+        fit = np.linalg.lstsq(basis, np.array(r), rcond=None)[0]
+        expect = _tau_series_from_energy_balance(eta)
+        for k, tol in ((2, 1e-5), (3, 1e-4), (4, 1e-3), (5, 1e-3)):
+            assert abs(fit[k - 2] - expect[k]) <= tol * abs(expect[k]), (eta, k, fit[k - 2], expect[k])
+
+
 def test_phase_shift_structure():
     """Psi(t_c, phi_c) - Psi(0, 0) = 2 pi f t_c - phi_c at every frequency."""
     for f in (20.0, 55.5, 300.0):
