@@ -52,45 +52,53 @@ class Opts(C.Structure):
 _lib = None
 
 
+def load(path: str):
+    """A CDLL of an oracle build at ``path`` with every signature set."""
+    L = C.CDLL(path)
+    L.orc_philox4x64.argtypes = [C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]
+    L.orc_prior_transform.argtypes = [C.c_void_p, _dp, _dp]
+    L.orc_antenna.argtypes = [_dp, C.c_double, C.c_double, C.c_double, C.c_double, _dp, _dp, _dp]
+    L.orc_waveform.argtypes = [C.c_void_p, _dp, C.c_int, C.c_int, _dp, _dp]
+    L.orc_tf2_phase.argtypes = [C.c_double] * 7
+    L.orc_tf2_phase.restype = C.c_double
+    L.orc_inner.argtypes = [C.c_void_p, C.c_int, _dp, _dp, _dp, _dp]
+    L.orc_inner.restype = C.c_double
+    L.orc_noise_loglike.argtypes = [C.c_void_p]
+    L.orc_noise_loglike.restype = C.c_double
+    L.orc_loglike_full.argtypes = [C.c_void_p, _dp]
+    L.orc_loglike_full.restype = C.c_double
+    L.orc_rb_build.argtypes = [C.c_void_p]
+    L.orc_rb_build.restype = C.c_void_p
+    L.orc_rb_free.argtypes = [C.c_void_p]
+    L.orc_rb_edges.argtypes = [C.c_void_p, _ip]
+    L.orc_loglike_rb.argtypes = [C.c_void_p, _dp]
+    L.orc_loglike_rb.restype = C.c_double
+    L.orc_loglike_gauss.argtypes = [C.c_void_p, _dp]
+    L.orc_loglike_gauss.restype = C.c_double
+    L.orc_loglike_batch.argtypes = [C.c_void_p, _dp, C.c_long, _dp, C.c_int]
+    L.orc_select.argtypes = [C.c_int, _dp, C.c_int, _ip, _dp]
+    L.orc_init.argtypes = [C.POINTER(C.c_void_p), C.c_void_p, C.c_void_p]
+    L.orc_step.argtypes = [C.c_void_p, C.c_int, _ip]
+    L.orc_state.argtypes = [C.c_void_p, _dp, _dp, _dp, _ip, C.POINTER(C.c_long), C.POINTER(C.c_long)]
+    L.orc_live.argtypes = [C.c_void_p, _dp, _dp]
+    L.orc_dead.argtypes = [C.c_void_p, C.c_long, _dp, _dp, _dp, _dp, _ip, _ip, C.POINTER(C.c_long)]
+    L.orc_logZ.argtypes = [C.c_void_p, C.c_int, _dp, _dp, _dp, _dp]
+    L.orc_samples.argtypes = [C.c_void_p, C.c_long, _dp, _dp, _dp, C.POINTER(C.c_long)]
+    L.orc_information.argtypes = [C.c_void_p, _dp, _dp]
+    L.orc_resample.argtypes = [C.c_void_p, C.c_long, _ip, _dp]
+    L.orc_pn_params.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp]
+    L.orc_free.argtypes = [C.c_void_p]
+    L.orc_slice_update_fixed.argtypes = [C.c_void_p, C.c_void_p, _dp, _dp, _dp, C.c_double, C.c_double,
+                                         C.c_double, _dp, C.c_int, C.POINTER(C.c_long)]
+    return L
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             build(force=True)
-        L = C.CDLL(LIB_PATH)
-        L.orc_philox4x64.argtypes = [C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]
-        L.orc_prior_transform.argtypes = [C.c_void_p, _dp, _dp]
-        L.orc_antenna.argtypes = [_dp, C.c_double, C.c_double, C.c_double, C.c_double, _dp, _dp, _dp]
-        L.orc_waveform.argtypes = [C.c_void_p, _dp, C.c_int, C.c_int, _dp, _dp]
-        L.orc_tf2_phase.argtypes = [C.c_double] * 7
-        L.orc_tf2_phase.restype = C.c_double
-        L.orc_inner.argtypes = [C.c_void_p, C.c_int, _dp, _dp, _dp, _dp]
-        L.orc_inner.restype = C.c_double
-        L.orc_noise_loglike.argtypes = [C.c_void_p]
-        L.orc_noise_loglike.restype = C.c_double
-        L.orc_loglike_full.argtypes = [C.c_void_p, _dp]
-        L.orc_loglike_full.restype = C.c_double
-        L.orc_rb_build.argtypes = [C.c_void_p]
-        L.orc_rb_build.restype = C.c_void_p
-        L.orc_rb_free.argtypes = [C.c_void_p]
-        L.orc_rb_edges.argtypes = [C.c_void_p, _ip]
-        L.orc_loglike_rb.argtypes = [C.c_void_p, _dp]
-        L.orc_loglike_rb.restype = C.c_double
-        L.orc_loglike_gauss.argtypes = [C.c_void_p, _dp]
-        L.orc_loglike_gauss.restype = C.c_double
-        L.orc_loglike_batch.argtypes = [C.c_void_p, _dp, C.c_long, _dp, C.c_int]
-        L.orc_select.argtypes = [C.c_int, _dp, C.c_int, _ip, _dp]
-        L.orc_init.argtypes = [C.POINTER(C.c_void_p), C.c_void_p, C.c_void_p]
-        L.orc_step.argtypes = [C.c_void_p, C.c_int, _ip]
-        L.orc_state.argtypes = [C.c_void_p, _dp, _dp, _dp, _ip, C.POINTER(C.c_long), C.POINTER(C.c_long)]
-        L.orc_live.argtypes = [C.c_void_p, _dp, _dp]
-        L.orc_dead.argtypes = [C.c_void_p, C.c_long, _dp, _dp, _dp, _dp, _ip, _ip, C.POINTER(C.c_long)]
-        L.orc_logZ.argtypes = [C.c_void_p, C.c_int, _dp, _dp, _dp, _dp]
-        L.orc_samples.argtypes = [C.c_void_p, C.c_long, _dp, _dp, _dp, C.POINTER(C.c_long)]
-        L.orc_free.argtypes = [C.c_void_p]
-        L.orc_slice_update_fixed.argtypes = [C.c_void_p, C.c_void_p, _dp, _dp, _dp, C.c_double, C.c_double,
-                                             C.c_double, _dp, C.c_int, C.POINTER(C.c_long)]
-        _lib = L
+        _lib = load(LIB_PATH)
     return _lib
 
 
@@ -164,6 +172,14 @@ class OracleProblem:
     def loglike_theta(self, theta):
         th = np.ascontiguousarray(theta, dtype=np.float64)
         return lib().orc_loglike_full(self.ref, _d(th))
+
+    def pn_params(self, theta):
+        """(eta, beta, sigma) of a physical parameter point."""
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        e, b, s = C.c_double(), C.c_double(), C.c_double()
+        if lib().orc_pn_params(self.ref, _d(th), C.byref(e), C.byref(b), C.byref(s)):
+            raise ValueError("orc_pn_params failed")
+        return e.value, b.value, s.value
 
     def loglike_batch(self, u, n_threads: int = 1):
         u = np.ascontiguousarray(u, dtype=np.float64).reshape(-1, self.w.n_dim)
@@ -295,6 +311,12 @@ class Run:
         lib().orc_logZ(self.h, n_sim, C.byref(z), C.byref(ss), C.byref(sh), C.byref(ess))
         return dict(logZ=z.value, sigma=ss.value, sigma_h=sh.value, ess=ess.value)
 
+    def information(self):
+        """Information H of the posterior against the prior and the Kish ESS."""
+        h, e = C.c_double(), C.c_double()
+        lib().orc_information(self.h, C.byref(h), C.byref(e))
+        return h.value, e.value
+
     def samples(self):
         st = self.state()
         tot = st["n_dead"] + self.opts.n_live
@@ -305,6 +327,15 @@ class Run:
         n_out = C.c_long()
         lib().orc_samples(self.h, tot, _d(th), _d(l), _d(lw), C.byref(n_out))
         return th, l, lw
+
+    def resample(self, n_out: int):
+        """Equal-weight samples by systematic resampling: (indices into the
+        samples() order, physical parameters)."""
+        idx = np.zeros(n_out, dtype=np.int32)
+        th = np.zeros((n_out, self.prob.w.n_dim))
+        if lib().orc_resample(self.h, n_out, _i(idx), _d(th)):
+            raise ValueError("orc_resample failed")
+        return idx, th
 
     def __del__(self):
         if getattr(self, "h", None):

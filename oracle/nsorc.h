@@ -71,6 +71,10 @@ int orc_waveform(const orc_problem* p, const double* theta, int det, int apply_c
 double orc_tf2_phase(double f, double mc_msun, double eta, double beta, double sigma,
                      double tc, double phic);
 
+/* Symmetric mass ratio and the leading-order aligned-spin phase terms
+ * (spin-orbit beta, spin-spin sigma) of a parameter point (test helper). */
+int orc_pn_params(const orc_problem* p, const double* theta, double* eta, double* beta, double* sigma);
+
 /* Noise-weighted inner product 4 df Re sum conj(a) b / S over one detector. */
 double orc_inner(const orc_problem* p, int det, const double* a_re, const double* a_im,
                  const double* b_re, const double* b_im);
@@ -109,7 +113,11 @@ int orc_live(const orc_run* r, double* u, double* logl);
 int orc_dead(const orc_run* r, long cap, double* u, double* logl, double* logx, double* logw,
              int* iter, int* slot, long* n_out);
 int orc_logZ(const orc_run* r, int n_sim, double* logZ, double* sigma_sim, double* sigma_h, double* ess);
+/* Information H (unclipped) and Kish ESS of the final weighted samples. */
+int orc_information(const orc_run* r, double* H, double* ess);
 int orc_samples(const orc_run* r, long cap, double* theta, double* logl, double* logw, long* n_out);
+/* Equal-weight samples by systematic resampling of the weighted samples. */
+int orc_resample(const orc_run* r, long n_out, int* idx, double* theta);
 void orc_free(orc_run* r);
 
 /* One slice update with a caller-supplied direction and uniforms (test hook). */

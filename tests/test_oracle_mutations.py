@@ -1,0 +1,134 @@
+"""Mutation check of the oracle's pins: copies of the oracle source with one
+coefficient or factor changed by about one percent (or one structural slip)
+are compiled on the CPU, and the pin that covers that part must reject each
+copy.  Nothing here touches the HIP library."""
+import ctypes as C
+import math
+import os
+import subprocess
+import tempfile
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+
+import oracle
+import test_oracle_pins as pins
+from paper_2509_24949_amd import synth
+
+# (name, text in nsorc.c, replacement, the pin that must fail)
+MUTATIONS = [
+    ("psi2 constant", "3715.0 / 756.0", "1.01 * 3715.0 / 756.0", "phase"),
+    ("psi3 spin-orbit", "4.0 * beta", "4.04 * beta", "phase"),
+    ("psi4 constant", "15293365.0 / 508032.0", "1.01 * 15293365.0 / 508032.0", "phase"),
+    ("psi4 spin-spin", "10.0 * sigma", "10.1 * sigma", "phase"),
+    ("psi5 constant", "38645.0 / 756.0", "1.01 * 38645.0 / 756.0", "phase"),
+    ("psi5 logarithm", "(1.0 + 3.0 * lv)", "(1.0 + 3.03 * lv)", "phase"),
+    ("psi6 constant", "11583231236531.0 / 4694215680.0", "1.01 * 11583231236531.0 / 4694215680.0", "phase"),
+    ("psi6 pi^2", "640.0 * PI * PI / 3.0", "1.01 * 640.0 * PI * PI / 3.0", "phase"),
+    ("psi6 Euler gamma", "6848.0 * EULER_GAMMA / 21.0", "1.01 * 6848.0 * EULER_GAMMA / 21.0", "phase"),
+    ("psi6 logarithm", "(6848.0 / 21.0) * log(4.0 * v)", "1.01 * (6848.0 / 21.0) * log(4.0 * v)", "phase"),
+    ("psi6 eta", "(-15737765635.0 / 3048192.0 + 2255.0 * PI * PI / 12.0) * eta",
+     "1.01 * (-15737765635.0 / 3048192.0 + 2255.0 * PI * PI / 12.0) * eta", "phase"),
+    ("psi6 eta^2", "76055.0 * e2 / 1728.0", "1.01 * 76055.0 * e2 / 1728.0", "phase"),
+    ("psi6 eta^3", "127825.0 * e3 / 1296.0", "1.01 * 127825.0 * e3 / 1296.0", "phase"),
+    ("psi7 constant", "77096675.0 / 254016.0", "1.01 * 77096675.0 / 254016.0", "phase"),
+    ("psi7 eta", "378515.0 * eta / 1512.0", "1.01 * 378515.0 * eta / 1512.0", "phase"),
+    ("psi7 eta^2", "74045.0 * e2 / 756.0", "1.01 * 74045.0 * e2 / 756.0", "phase"),
+    ("beta mass factor", "113.0 * m1 * m1", "114.13 * m1 * m1", "phase"),
+    ("beta eta factor", "75.0 * s->eta) + c2", "75.75 * s->eta) + c2", "phase"),
+    ("sigma factor", "79.0 / 8.0", "79.79 / 8.0", "phase"),
+    ("plus inclination factor", "s->hp_fac = 0.5 * (1.0 + ci * ci);", "s->hp_fac = 0.505 * (1.0 + ci * ci);",
+     "polarisation"),
+    ("cross inclination factor", "s->hx_fac = ci;", "s->hx_fac = 1.01 * ci;", "polarisation"),
+    ("cross part real", "double xr = s->hx_fac * bi, xi = -s->hx_fac * br;",
+     "double xr = s->hx_fac * br, xi = s->hx_fac * bi;", "polarisation"),
+    ("information", "*H = h - z;", "*H = h - 1.01 * z;", "posterior"),
+    ("Kish ESS", "*ess = 1.0 / s2;", "*ess = 1.01 / s2;", "posterior"),
+    ("resample positions", "((double)m + u0) / (double)n_out * acc",
+     "((double)m + u0) / (double)n_out * acc * 0.99", "resample"),
+]
+
+
+def _posterior_bad(L):
+    """The constant-likelihood pins of H (zero) and the Kish ESS (closed form),
+    driven through the build L."""
+    w = synth.gauss_workload(3, 1e8, n_live=100, n_delete=50)
+    p = oracle.OracleProblem(w)
+    o = oracle.opts_for(w, max_iter=30, term_frac=0.0)
+    h = C.c_void_p()
+    assert L.orc_init(C.byref(h), p.ref, C.byref(o)) == 0
+    done = C.c_int()
+    L.orc_step(h, 30, C.byref(done))
+    H, ess = C.c_double(), C.c_double()
+    L.orc_information(h, C.byref(H), C.byref(ess))
+    L.orc_free(h)
+    want = pins._constant_likelihood_ess(100, 50, 30)
+    return abs(H.value) >= 1e-9 or abs(ess.value - want) >= 1e-9 * want
+
+
+def _resample_bad(L):
+    """The systematic-resampling count property, driven through the build L."""
+    w = synth.gauss_workload(2, 0.08, mu=[0.2, 0.5], n_live=200, n_delete=100)
+    p = oracle.OracleProblem(w)
+    o = oracle.opts_for(w, seed=5)
+    h = C.c_void_p()
+    assert L.orc_init(C.byref(h), p.ref, C.byref(o)) == 0
+    done = C.c_int()
+    L.orc_step(h, 1000, C.byref(done))
+    nd, ne = C.c_long(), C.c_long()
+    L.orc_state(h, None, None, None, None, C.byref(nd), C.byref(ne))
+    tot = nd.value + 200
+    lw = np.zeros(tot)
+    n_out = C.c_long()
+    L.orc_samples(h, tot, None, None, lw.ctypes.data_as(oracle._dp), C.byref(n_out))
+    bad = False
+    for n in (17, 1000):
+        idx = np.zeros(n, dtype=np.int32)
+        L.orc_resample(h, n, idx.ctypes.data_as(oracle._ip), None)
+        cum = n * np.cumsum(np.exp(lw)) / np.exp(lw).sum()
+        drawn = np.cumsum(np.bincount(idx, minlength=tot))
+        bad = bad or bool(np.max(np.abs(drawn - cum)) >= 1.0 + 1e-9)
+    L.orc_free(h)
+    return bad
+
+
+CHECKS = {
+    "phase": lambda L: pins._eb_worst(L) >= 1.0,
+    "polarisation": lambda L: pins._polarisation_worst(L) >= 1e-11,
+    "posterior": _posterior_bad,
+    "resample": _resample_bad,
+}
+
+
+def _compile(src_text, path):
+    c = path + ".c"
+    with open(c, "w") as fh:
+        fh.write(src_text)
+    subprocess.run(["gcc", "-O1", "-std=gnu11", "-fopenmp", "-fPIC", "-shared", "-I", os.path.dirname(oracle.SRC),
+                    "-o", path, c, "-lm"], check=True)
+
+
+@pytest.fixture(scope="module")
+def mutants():
+    src = open(oracle.SRC).read()
+    tmp = tempfile.mkdtemp(prefix="orc_mut_")
+    jobs = []
+    for i, (name, old, new, _) in enumerate(MUTATIONS):
+        assert src.count(old) == 1, name          # each mutation hits exactly one place
+        jobs.append((src.replace(old, new), os.path.join(tmp, f"mut{i}.so")))
+    with ThreadPoolExecutor(max_workers=8) as ex:
+        list(ex.map(lambda j: _compile(*j), jobs))
+    return [oracle.load(path) for _, path in jobs]
+
+
+def test_unmutated_oracle_passes_every_check():
+    L = oracle.lib()
+    for kind, bad in CHECKS.items():
+        assert not bad(L), kind
+
+
+@pytest.mark.parametrize("i", range(len(MUTATIONS)), ids=[m[0] for m in MUTATIONS])
+def test_mutation_is_caught(mutants, i):
+    name, _, _, kind = MUTATIONS[i]
+    assert CHECKS[kind](mutants[i]), f"the {kind} pin misses a changed {name}"

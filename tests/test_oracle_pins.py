@@ -3,6 +3,8 @@ or independent library routines (never against the oracle itself).
 
 Each test names what it pins and which mistake it would catch.
 """
+import ctypes as C
+import dataclasses
 import math
 
 import numpy as np
@@ -99,55 +101,119 @@ def test_phase_newtonian_chirp_time():
         assert abs(c2 - (743.0 / 252.0 + 11.0 * eta / 3.0)) < 0.01 * (743.0 / 252.0 + 11.0 * eta / 3.0), (eta, c2)
 
 
-def _tau_series_from_energy_balance(eta):
-    """Time to coalescence of a circular, non-spinning binary from energy
-    balance, dt/dv = -E'(v)/F(v), with the binding energy
-    E = -(M eta v^2/2)[1 - (3/4 + eta/12) v^2 - (27/8 - 19 eta/8 + eta^2/24) v^4]
-    and the flux F = (32/5) eta^2 v^10 [1 - (1247/336 + 35 eta/12) v^2 + 4 pi v^3
-    + (-44711/9072 + 9271 eta/504 + 65 eta^2/18) v^4 - (8191/672 + 583 eta/24) pi v^5]
-    (post-Newtonian results for point masses; the v^3 and v^5 flux terms are
-    the wave tails).  Expanding the ratio and integrating term by term gives
-    tau = (5 M/(256 eta v^8)) sum_k tau_k v^k; returns tau_0 .. tau_5."""
-    e = np.zeros(6)
+EULER_GAMMA = 0.57721566490153286061
+
+
+def _tau_series_from_energy_balance(eta, spins=None):
+    """Time to coalescence of a circular binary from energy balance,
+    dt/dv = -E'(v)/F(v), v = (pi M f)^(1/3), with the post-Newtonian binding
+    energy and gravitational-wave flux of point masses:
+      E = -(M eta v^2/2)[1 - (3/4 + eta/12) v^2 - (27/8 - 19 eta/8 + eta^2/24) v^4
+          + (-675/64 + (34445/576 - 205 pi^2/96) eta - 155 eta^2/96 - 35 eta^3/5184) v^6]
+      F = (32/5) eta^2 v^10 [1 - (1247/336 + 35 eta/12) v^2 + 4 pi v^3
+          + (-44711/9072 + 9271 eta/504 + 65 eta^2/18) v^4 - (8191/672 + 583 eta/24) pi v^5
+          + (6643739519/69854400 + 16 pi^2/3 - 1712 gamma_E/105 - (856/105) ln(16 v^2)
+             + (-134543/7776 + 41 pi^2/48) eta - 94403 eta^2/3024 - 775 eta^3/324) v^6
+          + (-16285/504 + 214745 eta/1728 + 193385 eta^2/3024) pi v^7]
+    (the odd flux terms are the wave tails).  spins = (q, chi1, chi2) adds the
+    leading aligned-spin terms, written with the total spin S = m1^2 chi1 +
+    m2^2 chi2 and Sigma = M (m2 chi2 - m1 chi1) over M^2 and delta = (m1 - m2)/M:
+    spin-orbit (14/3 S + 2 delta Sigma) v^3 in E and -(4 S + 5/4 delta Sigma) v^3
+    in F; spin-spin -2 eta chi1 chi2 v^4 in E (from chi1.chi2 - 3 (L.chi1)(L.chi2))
+    and (eta/48)(289 - 103) chi1 chi2 v^4 in F.  Expanding the ratio and
+    integrating term by term (the v^6 ln v term with its own antiderivative)
+    gives tau = (5 M/(256 eta v^8)) [sum_k tau_k v^k + tau_6l v^6 ln v];
+    returns (tau_0 .. tau_7, tau_6l)."""
+    pi = math.pi
+    e = np.zeros(8)
+    fl = np.zeros(8)
     e[0], e[2], e[4] = 1.0, -(3 / 4 + eta / 12), -(27 / 8 - 19 * eta / 8 + eta**2 / 24)
-    fl = np.zeros(6)
-    fl[0], fl[2], fl[3] = 1.0, -(1247 / 336 + 35 * eta / 12), 4 * math.pi
+    e[6] = -675 / 64 + (34445 / 576 - 205 * pi**2 / 96) * eta - 155 * eta**2 / 96 - 35 * eta**3 / 5184
+    fl[0], fl[2], fl[3] = 1.0, -(1247 / 336 + 35 * eta / 12), 4 * pi
     fl[4] = -44711 / 9072 + 9271 * eta / 504 + 65 * eta**2 / 18
-    fl[5] = -(8191 / 672 + 583 * eta / 24) * math.pi
-    num = np.array([e[k] * (k + 2) / 2 for k in range(6)])    # -E'(v) / (M eta v)
-    ratio = np.zeros(6)
-    for k in range(6):
-        ratio[k] = num[k] - sum(ratio[j] * fl[k - j] for j in range(k))
-    return [8 * ratio[k] / (8 - k) for k in range(6)]
+    fl[5] = -(8191 / 672 + 583 * eta / 24) * pi
+    fl[6] = (6643739519 / 69854400 + 16 * pi**2 / 3 - 1712 * EULER_GAMMA / 105 - 856 / 105 * math.log(16)
+             + (-134543 / 7776 + 41 * pi**2 / 48) * eta - 94403 * eta**2 / 3024 - 775 * eta**3 / 324)
+    fl6_log = -1712 / 105                       # coefficient of v^6 ln v in F
+    fl[7] = (-16285 / 504 + 214745 * eta / 1728 + 193385 * eta**2 / 3024) * pi
+    if spins is not None:
+        q, c1, c2 = spins
+        x1, x2 = 1 / (1 + q), q / (1 + q)
+        S = x1 * x1 * c1 + x2 * x2 * c2
+        dSig = (x1 - x2) * (x2 * c2 - x1 * c1)
+        e[3] += 14 / 3 * S + 2 * dSig
+        fl[3] += -4 * S - 5 / 4 * dSig
+        e[4] += -2 * eta * c1 * c2
+        fl[4] += (289 - 103) / 48 * eta * c1 * c2
+    num = np.array([e[k] * (k + 2) / 2 for k in range(8)])    # -E'(v) / (M eta v)
+    a = np.zeros(8)
+    for k in range(8):
+        a[k] = num[k] - sum(a[j] * fl[k - j] for j in range(k))
+    a6l = -fl6_log                                 # the log term of 1/F at v^6 (no log at v^1)
+    tau = [8 * a[k] / (8 - k) for k in range(8)]
+    tau[6] = 4 * a[6] + 2 * a6l                    # from the integral of v^-3 ln v
+    return tau + [4 * a6l]
 
 
-def test_phase_matches_energy_balance_to_2p5pn():
-    """The zero-spin phase's time to coalescence t_c - Psi'(f)/(2 pi), read
-    off the oracle by a least-squares fit in v = (pi M f)^(1/3) over the
-    powers the 3.5PN phase can produce (v^2 .. v^7 and v^6 ln v), has the
-    1PN, 1.5PN (tail), 2PN and 2.5PN coefficients that energy balance gives
-    from the binding energy and flux.  Catches a wrong or mistyped phase
-    coefficient through 2PN, in either its mass-ratio terms or its constant,
-    and a wrong 2.5PN logarithmic term.  The 3PN and 3.5PN terms and the spin
-    terms are not pinned here."""
-    mc_msun, tc, phic = 24.0, 0.013, 0.3
-    lib = oracle.lib()
-    for eta in (0.1, 0.2, 0.25):
-        m = mc_msun * TSUN * eta ** -0.6
-        vs = np.linspace(0.02, 0.3, 80)
+# (Mc [Msun], q, chi1, chi2): zero spin at three mass ratios, then aligned spins
+_EB_CASES = [(24.0, 0.1 / 0.9, 0.0, 0.0), (24.0, 0.4, 0.0, 0.0), (24.0, 1.0, 0.0, 0.0),
+             (24.0, 0.5, 0.3, -0.6), (31.0, 0.9, 0.7, 0.5), (18.0, 0.2, -0.4, 0.8)]
+# tolerances of the fitted tau_2 .. tau_7, tau_6l (the fit's own accuracy is
+# 10 to 50 times better; a 1 percent change of any phase coefficient, or of
+# the mass-ratio or spin factors, moves a fitted coefficient by far more)
+_EB_TOL = {2: 1e-8, 3: 5e-8, 4: 2e-6, 5: 2e-6, 6: 2e-6, 7: 2e-6, "6l": 6e-6}
+
+
+def _eb_worst(L, prob=None):
+    """Largest ratio |fit - energy balance| / tolerance over _EB_CASES for the
+    oracle build L.  The phase's (eta, beta, sigma) come from the oracle's own
+    mass-ratio and spin mapping (11-parameter model); the time to coalescence
+    t_c - Psi'(f)/(2 pi) is differentiated with a five-point stencil and fitted
+    in v over the powers a 3.5PN phase produces."""
+    if prob is None:
+        prob = oracle.OracleProblem(synth.workload("tf2_3det"))
+    worst = 0.0
+    for mc, q, c1, c2 in _EB_CASES:
+        th = np.array([mc, q, c1, c2, 400.0, 0.3, 0.2, 1.0, 0.1, 0.0, 0.0])
+        e, b, s = C.c_double(), C.c_double(), C.c_double()
+        L.orc_pn_params(prob.ref, th.ctypes.data_as(oracle._dp), C.byref(e), C.byref(b), C.byref(s))
+        eta, beta, sigma = e.value, b.value, s.value
+        m = mc * TSUN * eta ** -0.6
+        vs = np.linspace(0.02, 0.3, 160)
         r = []
         for v in vs:
             f = v**3 / (math.pi * m)
-            h = f * 1e-5
-            dpsi = (lib.orc_tf2_phase(f + h, mc_msun, eta, 0.0, 0.0, tc, phic)
-                    - lib.orc_tf2_phase(f - h, mc_msun, eta, 0.0, 0.0, tc, phic)) / (2 * h)
-            tau = tc - dpsi / (2 * math.pi)
-            r.append(tau / (5 * m / (256 * eta * v**8)) - 1.0)
+            h = f * 2e-4
+            P = lambda x: L.orc_tf2_phase(x, mc, eta, beta, sigma, 0.0, 0.0)  # noqa: E731
+            dpsi = (-P(f + 2 * h) + 8 * P(f + h) - 8 * P(f - h) + P(f - 2 * h)) / (12 * h)
+            r.append(-dpsi / (2 * math.pi) / (5 * m / (256 * eta * v**8)) - 1.0)
         basis = np.stack([vs**2, vs**3, vs**4, vs**5, vs**6, vs**6 * np.log(vs), vs**7], axis=1)
         fit = np.linalg.lstsq(basis, np.array(r), rcond=None)[0]
-        expect = _tau_series_from_energy_balance(eta)
-        for k, tol in ((2, 1e-5), (3, 1e-4), (4, 1e-3), (5, 1e-3)):
-            assert abs(fit[k - 2] - expect[k]) <= tol * abs(expect[k]), (eta, k, fit[k - 2], expect[k])
+        spinning = not (c1 == 0.0 and c2 == 0.0)
+        ex = _tau_series_from_energy_balance(eta, (q, c1, c2) if spinning else None)
+        for i, key in enumerate((2, 3, 4, 5, 6, "6l", 7)):
+            if spinning and key not in (2, 3, 4):
+                # the model keeps the spin terms at leading order only: above
+                # 2PN its phase omits the spin cross terms energy balance has
+                continue
+            want = ex[8] if key == "6l" else ex[key]
+            worst = max(worst, abs(fit[i] - want) / (_EB_TOL[key] * abs(want)))
+    return worst
+
+
+def test_phase_matches_energy_balance_to_3p5pn_with_spins():
+    """The TaylorF2 phase's time to coalescence t_c - Psi'(f)/(2 pi), read off
+    the oracle by a least-squares fit in v = (pi M f)^(1/3) over the powers the
+    3.5PN phase produces (v^2 .. v^7 and v^6 ln v), has every coefficient that
+    energy balance gives from the 3PN binding energy and the 3.5PN flux (zero
+    spin, three mass ratios), and the 1.5PN spin-orbit and 2PN spin-spin
+    coefficients that the leading aligned-spin energy and flux terms give
+    (the oracle's own mapping from (q, chi1, chi2) to eta, beta and sigma;
+    with spins only the orders through 2PN are compared, since the model
+    keeps spin terms at leading order).
+    Catches a changed or mistyped phase coefficient at any order, in its
+    mass-ratio terms, its constants or its logarithms, and a wrong spin factor."""
+    assert _eb_worst(oracle.lib()) < 1.0
 
 
 def test_phase_shift_structure():
@@ -178,6 +244,115 @@ def test_antenna_textbook_magnitude():
         # polarisation rotation by pi/2 flips both patterns
         fp2, fc2, _ = oracle.antenna(g, ra, dec, psi + math.pi / 2, 0.0)
         assert abs(fp2 + fp) < 1e-12 and abs(fc2 + fc) < 1e-12
+
+
+def test_antenna_individual_patterns():
+    """Each pattern separately (not only F+^2 + Fx^2): for the pole detector
+    with arms along x and y, with A = (1 + cos^2 theta) cos(2 phi)/2 and
+    B = cos theta sin(2 phi), the textbook patterns are
+    F+ = A cos 2psi' - B sin 2psi', Fx = A sin 2psi' + B cos 2psi'.  The
+    oracle's polarisation angle is measured the other way round and a quarter
+    turn apart, psi' = pi/2 - psi (the convention both implementations share):
+    F+ = -(A cos 2psi + B sin 2psi), Fx = A sin 2psi - B cos 2psi."""
+    g = np.array([0, 0, 6.371e6, 1, 0, 0, 0, 1, 0], dtype=np.float64)
+    rng = np.random.default_rng(15)
+    for _ in range(50):
+        ra, dec, psi = rng.uniform(0, 2 * math.pi), rng.uniform(-1.5, 1.5), rng.uniform(0, math.pi)
+        fp, fc, _ = oracle.antenna(g, ra, dec, psi, 0.0)
+        ct = math.cos(math.pi / 2 - dec)
+        A = 0.5 * (1 + ct * ct) * math.cos(2 * ra)
+        B = ct * math.sin(2 * ra)
+        p2 = math.pi / 2 - psi
+        assert abs(fp - (A * math.cos(2 * p2) - B * math.sin(2 * p2))) < 1e-12
+        assert abs(fc - (A * math.sin(2 * p2) + B * math.cos(2 * p2))) < 1e-12
+
+
+def _geocentric_problem():
+    """The 11-parameter model on a short grid with one detector at the
+    geocentre (no arrival delay), arms along x and y."""
+    w = dataclasses.replace(synth.workload("tf2_3det"), n_bins=40)
+    w = dataclasses.replace(w, detectors=w.detectors[:1])
+    prob = oracle.OracleProblem(w, psd=np.ones((1, w.n_bins)))
+    prob.geom[0] = [0, 0, 0, 1, 0, 0, 0, 1, 0]      # the struct points at this array
+    return w, prob
+
+
+def _spa_amplitude(mc_msun, dist_mpc, f):
+    """Stationary-phase amplitude of the Newtonian quadrupole chirp of an
+    optimally oriented source, h0(t_f) / (2 sqrt(fdot))."""
+    mc = mc_msun * TSUN
+    h0 = 4.0 * mc ** (5.0 / 3.0) * (math.pi * f) ** (2.0 / 3.0) / (dist_mpc * MPC_S)
+    fdot = 96.0 / 5.0 * math.pi ** (8.0 / 3.0) * mc ** (5.0 / 3.0) * f ** (11.0 / 3.0)
+    return h0 / (2.0 * np.sqrt(fdot))
+
+
+def _polarisation_worst(L=None):
+    """Largest relative deviation of the 11-parameter strain from the
+    closed forms of the two polarisations (see the test below)."""
+    L = L or oracle.lib()
+    w, prob = _geocentric_problem()
+    f = w.freqs()
+    g = prob.geom[0].copy()
+    worst = 0.0
+
+    def strain(th):
+        hr, hi = np.zeros(w.n_bins), np.zeros(w.n_bins)
+        th = np.ascontiguousarray(th, dtype=np.float64)
+        L.orc_waveform(prob.ref, th.ctypes.data_as(oracle._dp), 0, 0, hr.ctypes.data_as(oracle._dp),
+                       hi.ctypes.data_as(oracle._dp))
+        return hr + 1j * hi
+
+    rng = np.random.default_rng(21)
+    for _ in range(6):
+        mc, D = rng.uniform(20, 40), rng.uniform(200, 900)
+        ra, dec = rng.uniform(0, 2 * math.pi), rng.uniform(-1.2, 1.2)
+        amp = _spa_amplitude(mc, D, f)
+        base = np.array([mc, 0.7, 0.1, -0.2, D, 0.0, 0.0, ra, dec, 0.0, 0.4])
+        # face-on: circular polarisation; |h| = A sqrt(F+^2 + Fx^2) at every psi,
+        # and a change of psi only rotates the phase, by twice the angle
+        h0 = strain(base)
+        signs = set()
+        for psi in (0.3, 1.1, 2.5):
+            t = base.copy()
+            t[6] = psi
+            h = strain(t)
+            fp, fc, _ = oracle.antenna(g, ra, dec, psi, 0.0)
+            worst = max(worst, np.max(np.abs(np.abs(h) / (amp * math.hypot(fp, fc)) - 1.0)))
+            rot = h / h0
+            worst = max(worst, np.max(np.abs(rot - rot[0])))          # one phase at every frequency
+            dp, dm = abs(rot[0] - np.exp(2j * psi)), abs(rot[0] - np.exp(-2j * psi))
+            signs.add(dp < dm)
+            worst = max(worst, min(dp, dm))
+        if len(signs) != 1:                                          # the sense of rotation is fixed
+            worst = max(worst, 1.0)
+        # edge-on: the cross polarisation vanishes, |h| = A |F+| / 2
+        for psi in (0.2, 1.7):
+            t = base.copy()
+            t[5], t[6] = math.pi / 2, psi
+            fp, fc, _ = oracle.antenna(g, ra, dec, psi, 0.0)
+            worst = max(worst, np.max(np.abs(np.abs(strain(t)) / (amp * abs(fp) / 2) - 1.0)))
+        # any inclination: the two polarisations are in quadrature,
+        # |h|^2 = A^2 [F+^2 ((1 + cos^2 i)/2)^2 + Fx^2 cos^2 i]
+        for iota, psi in ((0.5, 0.4), (1.2, 2.0), (2.6, 1.3)):
+            t = base.copy()
+            t[5], t[6] = iota, psi
+            fp, fc, _ = oracle.antenna(g, ra, dec, psi, 0.0)
+            ci = math.cos(iota)
+            want = amp * math.sqrt(fp * fp * (0.5 * (1 + ci * ci)) ** 2 + fc * fc * ci * ci)
+            worst = max(worst, np.max(np.abs(np.abs(strain(t)) / want - 1.0)))
+    return worst
+
+
+def test_polarisation_factors_closed_forms():
+    """The plus and cross polarisations of the 11-parameter strain (detector at
+    the geocentre, amplitude from the quadrupole stationary-phase formula):
+    face-on, |h| = A sqrt(F+^2 + Fx^2) whatever psi, and psi rotates h by the
+    phase e^{+-2i psi} at every frequency (circular polarisation); edge-on, the
+    cross part vanishes and |h| = A |F+| / 2; at any inclination the parts are
+    in quadrature, |h|^2 = A^2 [F+^2 ((1 + cos^2 i)/2)^2 + Fx^2 cos^2 i].
+    Catches a wrong inclination factor of either polarisation, a real instead
+    of an imaginary cross part, or a dropped patterns' term."""
+    assert _polarisation_worst() < 1e-11
 
 
 # ---------------------------------------------------------------- Whittle
@@ -398,26 +573,45 @@ def _closed_gauss(mu, s):
     return float(np.sum(np.log(0.5 * (erf((1 - mu) / (s * math.sqrt(2))) + erf(mu / (s * math.sqrt(2)))))))
 
 
+def _closed_gauss_information(mu, s):
+    """H = E_post[lambda] - log Z for lambda = log N(u; mu, s^2 I) on the unit
+    cube: per coordinate the posterior is a normal truncated to [0, 1], whose
+    standardised second moment is 1 + (a phi(a) - b phi(b)) / (Phi(b) - Phi(a))
+    with a = -mu/s, b = (1 - mu)/s."""
+    a, b = -mu / s, (1 - mu) / s
+    mass = stats.norm.cdf(b) - stats.norm.cdf(a)
+    m2 = 1 + (a * stats.norm.pdf(a) - b * stats.norm.pdf(b)) / mass
+    e_lam = float(np.sum(-0.5 * np.log(2 * math.pi * s * s) - 0.5 * m2))
+    return e_lam - float(np.sum(np.log(mass)))
+
+
 @pytest.mark.parametrize("d,s", [(2, 0.05), (5, 0.1), (4, 0.02)])
 def test_gauss_in_cube_evidence_zscores(d, s):
     """log Z of a Gaussian likelihood in the unit cube against the erf closed
-    form over 20 seeds: z-scores with the sampler's own error bar ~ N(0,1)."""
+    form over 20 seeds: z-scores with the sampler's own error bar ~ N(0,1);
+    the mean information H over the seeds against its truncated-normal closed
+    form."""
     rng = np.random.default_rng(d)
     mu = rng.uniform(0.3, 0.7, d)
     mu[0] = 0.1  # one truncated marginal
     w = synth.gauss_workload(d, s, mu=mu, n_live=200, n_delete=100)
     p = oracle.OracleProblem(w)
     zc = _closed_gauss(mu, s)
-    z, sig = [], []
+    hc = _closed_gauss_information(mu, s)
+    z, sig, hs = [], [], []
     for seed in range(20):
         r = oracle.Run(p, oracle.opts_for(w, seed=100 + seed, n_threads=4))
         r.run()
         res = r.logZ(200)
         z.append((res["logZ"] - zc) / res["sigma"])
         sig.append(res["sigma"])
+        hs.append(r.information()[0])
     z = np.array(z)
     assert abs(z.mean()) < 0.75, z
     assert 0.5 < z.std() < 1.6, z
+    # the information H = E_post[lambda] - log Z of the weighted samples
+    hs = np.array(hs)
+    assert abs(hs.mean() - hc) < 4 * hs.std(ddof=1) / math.sqrt(len(hs)) + 1e-3 * hc, (hs.mean(), hc)
 
 
 def test_sigma_calibration():
@@ -446,6 +640,22 @@ def test_constant_likelihood_evidence_exact():
     r.step(30)
     lam = oracle.lib().orc_loglike_gauss(p.ref, np.full(3, 0.5).ctypes.data_as(oracle._dp))
     assert abs(r.logZ(0)["logZ"] - lam) < 1e-10
+    # the posterior is the prior: H = 0, and the weights are the prior-volume
+    # shells of the deterministic schedule, so the Kish ESS is 1 / sum of
+    # their squares (the final n live points share X_end equally)
+    H, ess = r.information()
+    assert abs(H) < 1e-9
+    assert abs(ess - _constant_likelihood_ess(100, 50, 30)) < 1e-9 * ess
+
+
+def _constant_likelihood_ess(n, k, iters):
+    shells, x = [], 1.0
+    for _ in range(iters):
+        for j in range(k):
+            shells.append(x * -math.expm1(-1.0 / (n - j)))
+            x *= math.exp(-1.0 / (n - j))
+    shells += [x / n] * n
+    return 1.0 / sum(v * v for v in shells)
 
 
 def test_logx_closed_form_and_volume_partition():
@@ -465,6 +675,48 @@ def test_logx_closed_form_and_volume_partition():
     assert abs(shells.sum() + math.exp(st["logX"]) - 1.0) < 1e-12
     # the first death of each iteration sees n live points, the last n-k+1
     assert np.all(dd["iter"][::50] == np.arange(12))
+
+
+def test_resample_systematic_counts():
+    """Systematic resampling: outputs are in sample order, every weighted
+    sample is drawn about N p_i / W times (N outputs, W the sum of the
+    weights), and the outputs drawn from the first i samples stay within one
+    of N (p_0 + ... + p_i) / W for every i."""
+    w = synth.gauss_workload(3, 0.08, mu=[0.2, 0.5, 0.6], n_live=300, n_delete=150)
+    p = oracle.OracleProblem(w)
+    r = oracle.Run(p, oracle.opts_for(w, seed=77, n_threads=4))
+    r.run()
+    _, _, lw = r.samples()
+    pw = np.exp(lw)
+    for n_out in (1, 17, 1000, 5000):
+        idx, th = r.resample(n_out)
+        assert np.all(np.diff(idx) >= 0)
+        cnt = np.bincount(idx, minlength=len(pw))
+        lo = np.floor(n_out * pw / pw.sum() - 1e-9)
+        assert np.all(cnt >= lo) and np.all(cnt <= lo + 2) and cnt.sum() == n_out
+        # the outputs drawn from samples 0..i stay within one of N (p_0 + ... + p_i) / W
+        drawn = np.cumsum(cnt)
+        assert np.max(np.abs(drawn - n_out * np.cumsum(pw) / pw.sum())) < 1.0 + 1e-9
+        th_all, _, _ = r.samples()
+        np.testing.assert_array_equal(th, th_all[idx])
+
+
+def test_resample_equal_weight_marginals_ks():
+    """Equal-weight samples of a Gaussian likelihood in the unit cube follow
+    its posterior marginals, normals truncated to [0, 1] (KS test)."""
+    mu, s = np.array([0.08, 0.5]), 0.1
+    w = synth.gauss_workload(2, s, mu=mu, n_live=500, n_delete=250)
+    p = oracle.OracleProblem(w)
+    pv = []
+    for seed in (11, 12):
+        r = oracle.Run(p, oracle.opts_for(w, seed=seed, n_threads=4))
+        r.run()
+        ess = r.logZ(0)["ess"]
+        _, th = r.resample(int(ess))
+        for i in range(2):
+            a, b = -mu[i] / s, (1 - mu[i]) / s
+            pv.append(stats.kstest(th[:, i], stats.truncnorm(a, b, loc=mu[i], scale=s).cdf).pvalue)
+    assert min(pv) > 1e-3, pv
 
 
 def test_slice_hand_computed():
