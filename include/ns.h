@@ -158,6 +158,16 @@ NS_API int ns_logZ(ns_run* run, int n_sim, double* logZ, double* sigma_sim, doub
  * NS_E_CAPACITY (with n_out set) if cap is too small.  Outputs may be NULL. */
 NS_API int ns_samples(ns_run* run, long cap, double* theta, double* logl, double* logw, long* n_out);
 
+/* Equal-weight posterior samples (the equal-weight sample count beside the
+ * Kish ESS in the paper's results table, Section 3): systematic resampling of
+ * the weighted samples of ns_samples (same order, weights normalised by the
+ * final log Z) with one uniform u0 of the run's random stream: output m is the
+ * first weighted sample whose running weight sum exceeds (m + u0) / n_out of
+ * the total.  idx: host [n_out] receives indices into ns_samples' order;
+ * theta: host [n_out][n_dim] physical parameters (unit-cube coordinates for
+ * GAUSS); either may be NULL.  1 <= n_out <= 2^30.  Synchronises. */
+NS_API int ns_resample(ns_run* run, long n_out, int* idx, double* theta);
+
 /* Scalars of the run (any pointer may be NULL).  n_evals counts likelihood
  * evaluations (probes inside the unit cube, plus the initial population). */
 NS_API int ns_state(ns_run* run, double* logX, double* logZ, double* H, int* iter, long* n_dead, long* n_evals,

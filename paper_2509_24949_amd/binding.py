@@ -73,6 +73,7 @@ SIGNATURES = {
     "ns_step_async": (C.c_int, [C.c_void_p, C.c_int]),
     "ns_logZ": (C.c_int, [C.c_void_p, C.c_int, _dp, _dp, _dp, _dp]),
     "ns_samples": (C.c_int, [C.c_void_p, C.c_long, _dp, _dp, _dp, _lp]),
+    "ns_resample": (C.c_int, [C.c_void_p, C.c_long, _ip, _dp]),
     "ns_state": (C.c_int, [C.c_void_p, _dp, _dp, _dp, _ip, _lp, _lp, _ip]),
     "ns_live": (C.c_int, [C.c_void_p, _dp, _dp]),
     "ns_dead": (C.c_int, [C.c_void_p, C.c_long, _dp, _dp, _dp, _dp, _ip, _ip, _lp]),
@@ -283,6 +284,14 @@ class Run:
         n_out = C.c_long()
         _check(lib().ns_samples(self.h, tot, _d(th), _d(l), _d(lw), C.byref(n_out)))
         return th, l, lw
+
+    def resample(self, n_out: int):
+        """ns_resample: (indices into ns_samples' order [n_out], physical
+        parameters [n_out, n_dim])."""
+        idx = np.zeros(n_out, dtype=np.int32)
+        th = np.zeros((n_out, self.spec.w.n_dim))
+        _check(lib().ns_resample(self.h, n_out, _i(idx), _d(th)))
+        return idx, th
 
     def loglike(self, u, out=None, terms=None):
         """ns_loglike on a CUDA float64 tensor [n, n_dim]; returns the tensor

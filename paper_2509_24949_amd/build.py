@@ -14,33 +14,47 @@ LIB = os.path.join(HERE, "libns.so")
 SOURCES = [os.path.join(HERE, "csrc", f) for f in ("ns_api.hip", "ns_server.hip", "ns_kernels.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
-    # no packed FP32 instructions anywhere in the device code
-    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+COMMON = [
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     "-fvisibility=hidden", "-Wall", "-Wno-unused-function",
     "-I", os.path.join(ROOT, "include"),
 ]
+# device pass only: no packed FP32 instructions anywhere in the device code
+DEVICE_ONLY = ["--cuda-device-only", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+
+
+def _objects(src: str, objdir: str) -> tuple[list[str], list[str], str]:
+    """The two compile commands of one source: the device pass writes the
+    code-object bundle, the host pass embeds it in the host object."""
+    base = os.path.join(objdir, os.path.basename(src))
+    fatbin, obj = base + ".hipfb", base + ".o"
+    dev = [HIPCC, *COMMON, *DEVICE_ONLY, "-c", "-o", fatbin, src]
+    host = [HIPCC, *COMMON, "--cuda-host-only", "-Xclang", "-fcuda-include-gpubinary", "-Xclang", fatbin,
+            "-c", "-o", obj, src]
+    return dev, host, obj
 
 
 def build(verbose: bool = False) -> str:
-    """Compile each source to an object in parallel, then link the library."""
+    """Compile each source (device pass, then host pass) in parallel, then
+    link the library."""
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
-    compile_flags = [f for f in FLAGS if f != "-shared"]
-    procs, objs = [], []
-    for src in SOURCES:
-        obj = os.path.join(objdir, os.path.basename(src) + ".o")
-        cmd = [HIPCC, *compile_flags, "-c", "-o", obj, src]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        procs.append(subprocess.Popen(cmd))
-        objs.append(obj)
-    for p in procs:
-        if p.wait() != 0:
-            raise subprocess.CalledProcessError(p.returncode, "hipcc")
+    jobs = [_objects(src, objdir) for src in SOURCES]
+
+    def run_all(cmds):
+        procs = []
+        for cmd in cmds:
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            procs.append(subprocess.Popen(cmd))
+        for p in procs:
+            if p.wait() != 0:
+                raise subprocess.CalledProcessError(p.returncode, "hipcc")
+
+    run_all([dev for dev, _, _ in jobs])
+    run_all([host for _, host, _ in jobs])
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *[obj for _, _, obj in jobs]]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

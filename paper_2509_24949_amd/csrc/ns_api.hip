@@ -494,6 +494,32 @@ int ns_samples(ns_run* r, long cap, double* theta, double* logl, double* logw, l
   return NS_OK;
 }
 
+int ns_resample(ns_run* r, long n_out, int* idx, double* theta) {
+  if (!r) return fail(NS_E_ARG, "run is NULL");
+  if (n_out < 1 || n_out > (1L << 30)) return fail(NS_E_ARG, "n_out must be in 1..2^30");
+  int rc = sync_state(r);
+  if (rc) return rc;
+  const long long total = r->h_state->n_dead + r->R.n;
+  double lz = 0.0;
+  if ((rc = ns_logZ(r, 0, &lz, nullptr, nullptr, nullptr))) return rc;
+  const int d = r->R.d;
+  double *cum = nullptr, *dth = nullptr;
+  int* di = nullptr;
+  HIP_OK(hipMalloc((void**)&cum, (total + 1) * sizeof(double)));
+  hipError_t e = hipMalloc((void**)&di, n_out * sizeof(int));
+  if (e == hipSuccess && theta) e = hipMalloc((void**)&dth, (size_t)n_out * d * sizeof(double));
+  if (e == hipSuccess) e = launch_resample(r->Md, r->R, total, lz, n_out, cum, di, dth, r->st);
+  if (e == hipSuccess && idx) e = hipMemcpyAsync(idx, di, n_out * sizeof(int), hipMemcpyDeviceToHost, r->st);
+  if (e == hipSuccess && theta)
+    e = hipMemcpyAsync(theta, dth, (size_t)n_out * d * sizeof(double), hipMemcpyDeviceToHost, r->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(r->st);
+  (void)hipFree(cum);
+  (void)hipFree(di);
+  (void)hipFree(dth);
+  if (e != hipSuccess) return fail(NS_E_HIP, "resample: %s", hipGetErrorString(e));
+  return NS_OK;
+}
+
 int ns_live(ns_run* r, double* u, double* logl) {
   if (!r) return fail(NS_E_ARG, "run is NULL");
   if (u) HIP_OK(hipMemcpyAsync(u, r->R.u, (size_t)r->R.n * r->R.d * sizeof(double), hipMemcpyDeviceToHost, r->st));

@@ -138,6 +138,10 @@ hipError_t launch_waveform(const ModelDev& M, const ModelDev* Md, const double* 
 hipError_t launch_final(const RunDev& R, int n_sim, double* out, hipStream_t st);
 hipError_t launch_samples(const ModelDev* Md, const RunDev& R, long long total, double logZ, double* theta,
                           double* logl, double* logw, hipStream_t st);
+// Systematic resampling into n_out equal-weight samples; cum: device
+// [total + 1] scratch; idx: device [n_out]; theta: device [n_out][d] or NULL.
+hipError_t launch_resample(const ModelDev* Md, const RunDev& R, long long total, double logZ, long long n_out,
+                           double* cum, int* idx, double* theta, hipStream_t st);
 // Relative-binning set-up: edges (edge_out receives a host copy for
 // validation), fiducial phases and the summary sums.  w is the scratch array
 // of per-bin weights 4 df f^(-7/3) / S written by launch_build_tables.

@@ -1319,46 +1319,48 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
     nbins += terms;
   };
   auto eval2 = [&](int q1, int q2, double* l1, double* l2, int* k1, int* k2) {
-    constexpr int HW = NW / 2;
-    const bool second = tid >= NT / 2;
-    const int q = second ? q2 : q1;
-    double* rb = sred + buf * (NW + 4);
-    double part = 0.0, hh = 0.0, kact = 0.0;
-    if constexpr (lk_rb(LK)) {
-      // both halves pass the barrier inside rb_partial
-      const Probe pb = q >= 0 ? probe_from_rec<NDET>(rec(q), false) : Probe{};
-      part = rb_partial<NDET, lk_mixed(LK)>(pb, RBv, M.n_bins, second ? sr1 : sr0, second ? tid - NT / 2 : tid, NT / 2,
-                                            q >= 0);
-    } else if (q >= 0) {
-      const Probe pb = probe_from_rec<NDET>(rec(q), true);
-      part = fullgrid_partial<NDET, lk_mixed(LK), true>(pb, V, second ? tid - NT / 2 : tid, NT / 2);
-      hh = pb.hh;
-      kact = (double)pb.k_act;
-    }
-    const double tot = wave_sum(part);
-    if (lane == 0) rb[wv] = tot;
-    if (lane == 0 && wv % HW == 0) {
-      rb[NW + (second ? 1 : 0)] = hh;
-      if constexpr (lk_full(LK)) rb[NW + 2 + (second ? 1 : 0)] = kact;
-    }
-    __syncthreads();
-    double t1 = 0.0, t2 = 0.0;
+    if constexpr (PAIR) {
+      constexpr int HW = NW / 2;
+      const bool second = tid >= NT / 2;
+      const int q = second ? q2 : q1;
+      double* rb = sred + buf * (NW + 4);
+      double part = 0.0, hh = 0.0, kact = 0.0;
+      if constexpr (lk_rb(LK)) {
+        // both halves pass the barrier inside rb_partial
+        const Probe pb = q >= 0 ? probe_from_rec<NDET>(rec(q), false) : Probe{};
+        part = rb_partial<NDET, lk_mixed(LK)>(pb, RBv, M.n_bins, second ? sr1 : sr0, second ? tid - NT / 2 : tid, NT / 2,
+                                              q >= 0);
+      } else if (q >= 0) {
+        const Probe pb = probe_from_rec<NDET>(rec(q), true);
+        part = fullgrid_partial<NDET, lk_mixed(LK), true>(pb, V, second ? tid - NT / 2 : tid, NT / 2);
+        hh = pb.hh;
+        kact = (double)pb.k_act;
+      }
+      const double tot = wave_sum(part);
+      if (lane == 0) rb[wv] = tot;
+      if (lane == 0 && wv % HW == 0) {
+        rb[NW + (second ? 1 : 0)] = hh;
+        if constexpr (lk_full(LK)) rb[NW + 2 + (second ? 1 : 0)] = kact;
+      }
+      __syncthreads();
+      double t1 = 0.0, t2 = 0.0;
 #pragma unroll
-    for (int w2 = 0; w2 < HW; ++w2) {
-      t1 += rb[w2];
-      t2 += rb[HW + w2];
+      for (int w2 = 0; w2 < HW; ++w2) {
+        t1 += rb[w2];
+        t2 += rb[HW + w2];
+      }
+      *l1 = t1 - 0.5 * rb[NW];
+      *l2 = t2 - 0.5 * rb[NW + 1];
+      if constexpr (lk_rb(LK)) {
+        // terms of a relative-binning probe: the edges it read
+        *k1 = q1 >= 0 ? rb_edges_read(RBv, rec(q1).k_act, lane) : 0;
+        *k2 = q2 >= 0 ? rb_edges_read(RBv, rec(q2).k_act, lane) : 0;
+      } else {
+        *k1 = (int)rb[NW + 2];
+        *k2 = (int)rb[NW + 3];
+      }
+      buf ^= 1;
     }
-    *l1 = t1 - 0.5 * rb[NW];
-    *l2 = t2 - 0.5 * rb[NW + 1];
-    if constexpr (lk_rb(LK)) {
-      // terms of a relative-binning probe: the edges it read
-      *k1 = q1 >= 0 ? rb_edges_read(RBv, rec(q1).k_act, lane) : 0;
-      *k2 = q2 >= 0 ? rb_edges_read(RBv, rec(q2).k_act, lane) : 0;
-    } else {
-      *k1 = (int)rb[NW + 2];
-      *k2 = (int)rb[NW + 3];
-    }
-    buf ^= 1;
   };
 
   for (int s0 = 0; s0 < R.m; s0 += SL_CHUNK) {
@@ -1880,6 +1882,61 @@ __global__ void k_samples(const ModelDev* __restrict__ Mp, RunDev R, double logZ
   if (logw) logw[q] = lw;
 }
 
+// Equal-weight samples by systematic resampling (the equal-weight count of
+// the paper's results table, Section 3).  Pass 1, one workgroup: the
+// normalised weights p_q = exp(log w_q - log Z) of the weighted samples (dead
+// points in death order, then the live points), their running sum cum[q]
+// (each thread sums a contiguous chunk, the chunk totals are scanned across
+// the workgroup), and the one uniform u0 of the RESAMPLE purpose.
+__global__ __launch_bounds__(1024) void k_resample_cum(RunDev R, long long total, double logZ, double* cum,
+                                                       double* u0) {
+  __shared__ double sscan[1024];
+  const long long nd = R.state->n_dead;
+  const int tid = threadIdx.x;
+  const double live_lw = R.state->logX - log((double)R.n) - logZ;
+  const long long C = (total + 1023) / 1024;
+  const long long qb = (long long)tid * C, qe = (qb + C < total) ? qb + C : total;
+  auto weight = [&](long long q) {
+    const double lw = q < nd ? R.dlogw[q] - logZ : order_value(R.lam[q - nd]) + live_lw;
+    return exp(lw);
+  };
+  double cs = 0.0;
+  for (long long q = qb; q < qe; ++q) cs += weight(q);
+  double acc = block_inclusive_scan<1024, double>(cs, sscan) - cs;
+  for (long long q = qb; q < qe; ++q) {
+    acc += weight(q);
+    cum[q] = acc;
+  }
+  if (tid == 0) {
+    const u64x4 b = philox(0, 0, 0, purpose_word(P_RESAMPLE, 0), R.key0, R.key1);
+    u0[0] = unif53(b.x[0]);
+  }
+}
+
+// Pass 2, one thread per output m: the position (m + u0) / n_out of the total
+// weight and the first sample whose running sum exceeds it (binary search;
+// the last sample if none does, which only rounding can cause).
+__global__ void k_resample_pick(const ModelDev* __restrict__ Mp, RunDev R, long long total, const double* cum,
+                                const double* u0, long long n_out, int* idx, double* theta) {
+  const ModelDev& M = *Mp;
+  const long long m = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= n_out) return;
+  const double pos = ((double)m + u0[0]) / (double)n_out * cum[total - 1];
+  long long lo = 0, hi = total - 1;   // the answer lies in [lo, hi]
+  while (lo < hi) {
+    const long long mid = lo + (hi - lo) / 2;
+    if (cum[mid] > pos) hi = mid; else lo = mid + 1;
+  }
+  idx[m] = (int)lo;
+  if (theta) {
+    const long long nd = R.state->n_dead;
+    const int d = R.d;
+    const double* u = lo < nd ? R.du + lo * d : R.u + (size_t)(lo - nd) * d;
+    for (int i = 0; i < d; ++i)
+      theta[m * d + i] = (M.likelihood == LK_GAUSS) ? u[i] : prior_plain(M.prior, i, u[i]);
+  }
+}
+
 template <int NDET, int LK, bool LDS>
 hipError_t launch_loglike_t(const ModelDev& M, const ModelDev* Md, const Tables& T, const RBTables& RB,
                             const double* u, long n, double* out, int* terms, Probe* pbuf, hipStream_t st) {
@@ -2214,6 +2271,18 @@ hipError_t launch_to_float(const double* src, float* dst, size_t n, double scale
 
 hipError_t launch_final(const RunDev& R, int n_sim, double* out, hipStream_t st) {
   hipLaunchKernelGGL(k_final, dim3(1 + (n_sim > 0 ? n_sim : 0)), dim3(1024), 0, st, R, n_sim, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_resample(const ModelDev* Md, const RunDev& R, long long total, double logZ, long long n_out,
+                           double* cum, int* idx, double* theta, hipStream_t st) {
+  if (total <= 0 || n_out <= 0) return hipSuccess;
+  double* u0 = cum + total;
+  hipLaunchKernelGGL(k_resample_cum, dim3(1), dim3(1024), 0, st, R, total, logZ, cum, u0);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_resample_pick, dim3((unsigned)((n_out + 255) / 256)), dim3(256), 0, st, Md, R, total, cum,
+                     u0, n_out, idx, theta);
   return hipGetLastError();
 }
 
