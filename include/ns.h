@@ -192,6 +192,20 @@ NS_API int ns_dead(ns_run* run, long cap, double* u, double* logl, double* logx,
  * exposed for direct use. */
 NS_API int ns_loglike(ns_run* run, const double* u_dev, long n, double* out_dev, int* terms_dev);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): ns_loglike
+ * with the same kernels and results, whose probe-record scratch is a
+ * fixed array of NS_LOGLIKE_NOALLOC_MAX records per device (about 3.3 MB,
+ * held from the first ns_init on that device until the process ends) instead
+ * of a buffer the run allocates.  It calls no allocator.  u_dev, out_dev,
+ * terms_dev as for ns_loglike; the current device must be the run's.
+ * Errors: NS_E_ARG if n > NS_LOGLIKE_NOALLOC_MAX or the arguments are bad,
+ * NS_E_HIP.  All calls on one device share the one array: calls that
+ * overlap in time on that device (other streams, other threads) race and
+ * must be serialised by the caller. */
+#define NS_LOGLIKE_NOALLOC_MAX 16384
+NS_API int ns_loglike_noalloc(ns_run* run, const double* u_dev, long n, double* out_dev, int* terms_dev);
+
 /* Detector strain h_det(f_k) of the problem's model at physical parameters
  * theta (host [n_dim]) on the problem's grid, computed on the device.
  * apply_cut = 1 zeroes bins above f_ISCO.  h_re, h_im: host [n_bins].

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libns.so")
 
 NS_OK, NS_E_ARG, NS_E_OOM, NS_E_HIP, NS_E_CAPACITY, NS_E_STATE = 0, -1, -2, -3, -4, -5
 NS_FP64, NS_MIXED = 0, 1
+NS_LOGLIKE_NOALLOC_MAX = 16384
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int)
@@ -78,6 +79,7 @@ SIGNATURES = {
     "ns_live": (C.c_int, [C.c_void_p, _dp, _dp]),
     "ns_dead": (C.c_int, [C.c_void_p, C.c_long, _dp, _dp, _dp, _dp, _ip, _ip, _lp]),
     "ns_loglike": (C.c_int, [C.c_void_p, C.c_void_p, C.c_long, C.c_void_p, C.c_void_p]),
+    "ns_loglike_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_long, C.c_void_p, C.c_void_p]),
     "ns_waveform": (C.c_int, [C.c_void_p, _dp, C.c_int, C.c_int, _dp, _dp, C.c_void_p]),
     "ns_select": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
     "ns_profile": (C.c_int, [C.c_void_p, C.c_int]),
@@ -293,10 +295,12 @@ class Run:
         _check(lib().ns_resample(self.h, n_out, _i(idx), _d(th)))
         return idx, th
 
-    def loglike(self, u, out=None, terms=None):
+    def loglike(self, u, out=None, terms=None, noalloc: bool = False):
         """ns_loglike on a CUDA float64 tensor [n, n_dim]; returns the tensor
         [n] of log-likelihoods (written into ``out`` when given).  ``terms``:
-        an optional CUDA int32 tensor [n] that receives each probe's terms."""
+        an optional CUDA int32 tensor [n] that receives each probe's terms.
+        ``noalloc`` calls ns_loglike_noalloc (the library's fixed per-device
+        scratch, at most NS_LOGLIKE_NOALLOC_MAX probes) instead."""
         import torch
         assert u.is_cuda and u.dtype == torch.float64 and u.is_contiguous()
         n = u.shape[0]
@@ -307,7 +311,8 @@ class Run:
         if terms is not None:
             assert terms.is_cuda and terms.dtype == torch.int32 and terms.numel() >= n
             tp = C.c_void_p(terms.data_ptr())
-        _check(lib().ns_loglike(self.h, C.c_void_p(u.data_ptr()), n, C.c_void_p(out.data_ptr()), tp))
+        fn = lib().ns_loglike_noalloc if noalloc else lib().ns_loglike
+        _check(fn(self.h, C.c_void_p(u.data_ptr()), n, C.c_void_p(out.data_ptr()), tp))
         return out
 
     def noise_loglike(self) -> float:

@@ -215,6 +215,16 @@ int run_create(ns_run** out, const ns_problem* P, const ns_opts* O, hipStream_t 
   r->M = M;
   r->st = stream;
   r->packed = packed;
+  {
+    // the device's no-allocation scratch is looked up once, at set-up
+    Probe* scratch_addr = nullptr;
+    hipError_t e = hipGetDevice(&r->device);
+    if (e == hipSuccess) e = noalloc_probe_scratch(r->device, &scratch_addr);
+    if (e != hipSuccess) {
+      delete r;
+      return fail(NS_E_HIP, "device set-up: %s", hipGetErrorString(e));
+    }
+  }
   const int n = O->n_live, k = O->n_delete, d = P->n_dim;
   RunDev& R = r->R;
   R.n = n; R.k = k; R.d = d; R.m = O->n_steps;
@@ -565,6 +575,21 @@ int ns_loglike(ns_run* r, const double* u_dev, long n, double* out_dev, int* ter
   }
   HIP_OK(launch_loglike(r->M, r->Md, r->T, r->RB, u_dev, n, out_dev, terms_dev,
                         two_pass ? r->probe_buf : nullptr, r->st));
+  return NS_OK;
+}
+
+int ns_loglike_noalloc(ns_run* r, const double* u_dev, long n, double* out_dev, int* terms_dev) {
+  if (!r) return fail(NS_E_ARG, "run is NULL");
+  if (n < 0 || (n > 0 && (!u_dev || !out_dev))) return fail(NS_E_ARG, "bad batch arguments");
+  if (n > NS_LOGLIKE_NOALLOC_MAX)
+    return fail(NS_E_ARG, "batch of %ld probes exceeds NS_LOGLIKE_NOALLOC_MAX (%d)", n, NS_LOGLIKE_NOALLOC_MAX);
+  int cur = -1;
+  HIP_OK(hipGetDevice(&cur));
+  if (cur != r->device) return fail(NS_E_ARG, "the current device (%d) is not the run's (%d)", cur, r->device);
+  const bool two_pass = r->M.likelihood == NS_LIKE_FULL || r->M.likelihood == NS_LIKE_RB;
+  Probe* buf = nullptr;
+  if (two_pass) HIP_OK(noalloc_probe_scratch(r->device, &buf));
+  HIP_OK(launch_loglike(r->M, r->Md, r->T, r->RB, u_dev, n, out_dev, terms_dev, buf, r->st));
   return NS_OK;
 }
 

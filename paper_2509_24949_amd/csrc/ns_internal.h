@@ -129,6 +129,11 @@ hipError_t launch_loglike(const ModelDev& M, const ModelDev* Md, const Tables& T
                           const double* u, long n, double* out, int* terms, Probe* pbuf, hipStream_t st);
 hipError_t launch_select(const double* lam, int n, int k, int* rank, int* dead, double* lstar, const int* done,
                          hipStream_t st);
+// Device address of this device's probe-record scratch of ns_loglike_noalloc
+// (NS_LOGLIKE_NOALLOC_MAX records, held by the library until the process
+// ends).  The current device must be `device`; the address is looked up once
+// per device (hipGetSymbolAddress) and cached.
+hipError_t noalloc_probe_scratch(int device, Probe** out);
 // ev (optional): five events recorded before select, after select, after
 // prep, after the chains and after the termination kernel.
 hipError_t launch_iteration(const ModelDev& M, const ModelDev* Md, const Tables& T, const RBTables& RB,

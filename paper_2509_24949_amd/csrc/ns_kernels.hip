@@ -29,8 +29,10 @@
 #include <math.h>
 #include <stdlib.h>
 
+#include <mutex>
 #include <type_traits>
 
+#include "../../include/ns.h"
 #include "ns_internal.h"
 
 namespace ns {
@@ -2096,6 +2098,29 @@ hipError_t launch_loglike_rb_t(const ModelDev* Md, const RBTables& RB, int n_bin
   const size_t lds = (size_t)NDET * (RB.nb + 1) * (MX ? sizeof(float2) : sizeof(double2));
   hipLaunchKernelGGL((k_loglike_rb<NDET, MX>), dim3((unsigned)blocks), dim3(64), lds, st, Md, RB, u, n, out, terms);
   return hipGetLastError();
+}
+
+// Probe records of ns_loglike_noalloc: every device holds its own copy of
+// this array from the first use of the library until the process ends.  In
+// host code its name is not a device address; kernels receive the address
+// hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) Probe scratch[NS_LOGLIKE_NOALLOC_MAX];
+
+hipError_t noalloc_probe_scratch(int device, Probe** out) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static Probe* addr[kMaxDevices] = {};
+  *out = nullptr;
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[device] = static_cast<Probe*>(p);
+  }
+  *out = addr[device];
+  return hipSuccess;
 }
 
 hipError_t launch_loglike(const ModelDev& M, const ModelDev* Md, const Tables& T, const RBTables& RB,

@@ -98,6 +98,7 @@ struct ns_run {
   ns::RunDev R{};
   ns::LaunchCfg C{};
   hipStream_t st = nullptr;
+  int device = -1;                   // the device current at construction
   bool packed = false;               // launch configuration of the packed serving kernels
   ns::ProblemCopy prob;              // the problem as given (for ns_save)
   ns_opts opts{};

@@ -108,3 +108,12 @@ def test_checkpoint_argument_checks():
     assert out.value is None
     v = C.c_double()
     assert lib.ns_noise_loglike(None, C.byref(v)) == binding.NS_E_ARG
+
+
+def test_noalloc_limit_and_null_run():
+    txt = open(os.path.join(ROOT, "include", "ns.h")).read()
+    m = re.search(r"#define\s+NS_LOGLIKE_NOALLOC_MAX\s+(\d+)", txt)
+    assert m and int(m.group(1)) == binding.NS_LOGLIKE_NOALLOC_MAX
+    lib = binding.lib()
+    assert lib.ns_loglike_noalloc(None, None, 0, None, None) == binding.NS_E_ARG
+    assert b"NULL" in lib.ns_last_error()
