@@ -485,7 +485,7 @@ def _kernel_sha() -> str:
     import re
 
     h = hashlib.sha256()
-    for f in ("ns_device.h", "ns_kernels.hip", "ns_internal.h"):
+    for f in ("ns_device.h", "ns_kernels.h", "ns_internal.h"):
         with open(os.path.join(ROOT, "paper_2509_24949_amd", "csrc", f), encoding="utf-8") as fh:
             for line in fh:
                 code = re.sub(r"//.*", "", line).strip()

@@ -11,7 +11,9 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libns.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("ns_api.hip", "ns_server.hip", "ns_kernels.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in (
+    "ns_api.hip", "ns_server.hip", "ns_kernels.hip", "ns_slice_d1.hip", "ns_slice_d2.hip", "ns_slice_d3.hip",
+    "ns_slice_p64.hip", "ns_slice_p128.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 COMMON = [

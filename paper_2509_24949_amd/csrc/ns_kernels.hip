@@ -1,2006 +1,11 @@
-// Kernels of libns for gfx950 (wave64).
-//
-//  * k_rank       bit-exact selection: the rank of every live point in the
-//                 total order (order key, slot); the k lowest die.
-//  * k_prep       one workgroup: evidence and prior-volume update of the k
-//                 deaths, dead-point record, covariance of the live points
-//                 and its Cholesky factor, survivor list, chain start points.
-//  * k_slice      one workgroup per chain: the whole constrained slice walk
-//                 of the iteration with the chain state uniform across the
-//                 workgroup and the likelihood tables in LDS.  Each step sets
-//                 up a batch of candidate probes whose positions are known in
-//                 advance (the step-out points and the shrink candidates), the
-//                 two halves of the workgroup computing the intrinsic and the
-//                 extrinsic half of every candidate's source; the walk then
-//                 evaluates independent probes in pairs, each probe's bins
-//                 spread over half the workgroup and reduced once.
-//  * k_term       one workgroup: live evidence, termination flag, counters.
-//  * k_probe_setup, k_probe_bins, k_rb_bins
-//                 batched fused likelihood in two passes: one probe set-up per
-//                 thread, then one wavefront per probe over the frequency bins
-//                 (k_probe_bins) or the relative-binning bins (k_rb_bins) with
-//                 the coefficients in scalar registers.
-//  * k_loglike    batched likelihood in one pass (initial population,
-//                 Gaussian test likelihood); k_loglike_rb its relative-binning
-//                 form.
-//  * k_*_packed   the serving forms: one launch covers the chains (and the
-//                 selection, preparation and termination) of every resident run.
-#include <float.h>
-#include <math.h>
-#include <stdlib.h>
-
+// Host-side launchers of libns and the instantiations of every kernel other
+// than the chain kernels (the device code is in ns_kernels.h).
 #include <mutex>
-#include <type_traits>
 
 #include "../../include/ns.h"
-#include "ns_internal.h"
+#include "ns_kernels.h"
 
 namespace ns {
-
-namespace {
-
-constexpr double NEG_INF = -__builtin_inf();
-
-// Value of lane i ^ 1, i ^ 2 (quad permutations), of the mirrored lane in
-// the half row (8 lanes) and in the row (16 lanes), through DPP.
-template <int CTRL>
-__device__ inline double dpp_d(double v) {
-  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
-  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
-  return __hiloint2double(hi, lo);
-}
-constexpr int DPP_XOR1 = 0xB1;          // quad_perm [1, 0, 3, 2]
-constexpr int DPP_XOR2 = 0x4E;          // quad_perm [2, 3, 0, 1]
-constexpr int DPP_HALF_MIRROR = 0x141;
-constexpr int DPP_MIRROR = 0x140;
-
-// Value of lane `src` (uniform) as a scalar.
-__device__ inline double row_value(double v, int src) {
-  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), src),
-                          __builtin_amdgcn_readlane(__double2loint(v), src));
-}
-
-// Wavefront sum with every lane active: a butterfly inside each row of 16
-// lanes (both partners of a pair add the same two values, so every lane of
-// a row holds the same row sum), then (r0 + r1) + (r2 + r3) over the rows.
-// The order is fixed, so the result is reproducible and uniform.
-__device__ inline double wave_sum(double v) {
-  v += dpp_d<DPP_XOR1>(v);
-  v += dpp_d<DPP_XOR2>(v);
-  v += dpp_d<DPP_HALF_MIRROR>(v);
-  v += dpp_d<DPP_MIRROR>(v);
-  const double r0 = row_value(v, 0), r1 = row_value(v, 16), r2 = row_value(v, 32), r3 = row_value(v, 48);
-  return (r0 + r1) + (r2 + r3);
-}
-
-__device__ inline double wave_max(double v) {
-  v = fmax(v, dpp_d<DPP_XOR1>(v));
-  v = fmax(v, dpp_d<DPP_XOR2>(v));
-  v = fmax(v, dpp_d<DPP_HALF_MIRROR>(v));
-  v = fmax(v, dpp_d<DPP_MIRROR>(v));
-  const double r0 = row_value(v, 0), r1 = row_value(v, 16), r2 = row_value(v, 32), r3 = row_value(v, 48);
-  return fmax(fmax(r0, r1), fmax(r2, r3));
-}
-
-__device__ inline long long wave_sum_ll(long long v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
-// Value of lane `src` of this wavefront (src uniform), as a scalar.
-__device__ inline double lane_d(double v, int src) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
-  return __hiloint2double(hi, lo);
-}
-
-__device__ inline int lane_i(int v, int src) { return __builtin_amdgcn_readlane(v, src); }
-
-// Block-wide reductions for NT-thread workgroups; every thread receives the
-// result, combined in a fixed order.
-template <int NT>
-__device__ inline double block_sum(double v, double* sbuf) {
-  constexpr int NW = NT / 64;
-  v = wave_sum(v);
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) sbuf[wv] = v;
-  __syncthreads();
-  double t = 0.0;
-#pragma unroll
-  for (int w = 0; w < NW; ++w) t += sbuf[w];
-  return t;
-}
-
-template <int NT>
-__device__ inline double block_max(double v, double* sbuf) {
-  constexpr int NW = NT / 64;
-  v = wave_max(v);
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) sbuf[wv] = v;
-  __syncthreads();
-  double t = NEG_INF;
-#pragma unroll
-  for (int w = 0; w < NW; ++w) t = fmax(t, sbuf[w]);
-  return t;
-}
-
-// Inclusive prefix sum over the NT threads in thread order (wave shuffles,
-// then the wave totals); *total receives the sum of all.  Two barriers;
-// sbuf holds NT/64 values.
-template <int NT, typename T>
-__device__ inline T block_scan(T v, T* sbuf, T* total) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const T u = __shfl_up(v, o, 64);
-    if (lane >= o) v += u;
-  }
-  __syncthreads();
-  if (lane == 63) sbuf[wv] = v;
-  __syncthreads();
-  T off = T(0), all = T(0);
-#pragma unroll
-  for (int w = 0; w < NT / 64; ++w) {
-    if (w < wv) off += sbuf[w];
-    all += sbuf[w];
-  }
-  *total = all;
-  return v + off;
-}
-
-// K block-wide sums at once (two barriers); every thread receives them.
-// sbuf holds K * NT/64 values.
-template <int NT, int K>
-__device__ inline void block_sum_k(double (&v)[K], double* sbuf) {
-  constexpr int NW = NT / 64;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-  for (int q = 0; q < K; ++q) v[q] = wave_sum(v[q]);
-  __syncthreads();
-  if (lane == 0) {
-#pragma unroll
-    for (int q = 0; q < K; ++q) sbuf[q * NW + wv] = v[q];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int q = 0; q < K; ++q) {
-    double t = 0.0;
-#pragma unroll
-    for (int w = 0; w < NW; ++w) t += sbuf[q * NW + w];
-    v[q] = t;
-  }
-}
-
-// Inclusive Hillis-Steele scan over NT values held one per thread.
-template <int NT, typename T>
-__device__ inline T block_inclusive_scan(T v, T* sbuf) {
-  __syncthreads();
-  sbuf[threadIdx.x] = v;
-  __syncthreads();
-  for (int o = 1; o < NT; o <<= 1) {
-    T add = (threadIdx.x >= (unsigned)o) ? sbuf[threadIdx.x - o] : T(0);
-    __syncthreads();
-    v += add;
-    sbuf[threadIdx.x] = v;
-    __syncthreads();
-  }
-  return v;
-}
-
-// ---------------------------------------------------------------- tables
-// Pointers of the full-grid tables as one chain or probe sees them: either
-// the HBM arrays or a copy of their active prefix in LDS.
-struct TabView {
-  const double* f;      // bin k of f, f13, lnf3, fm53 at [k * ts]
-  const double* f13;
-  const double* lnf3;
-  const double* fm53;
-  int ts;
-  const double2* dw;    // detector d, bin k at [k * dk + d * dd]
-  const float2* dw32;   // (the same strides in float2 units)
-  int dk, dd;
-  const double* hpre;   // prefix sums of 4 df f^(-7/3) / S per detector
-  int hstride;          // row stride of hpre
-  double inv_scale;     // 1 / dw_scale of the float table
-};
-
-// LDS bytes of the staged full-grid tables.
-__host__ __device__ inline size_t staged_table_bytes(int k_lim, int n_det, bool mixed) {
-  return (size_t)k_lim * (4 * sizeof(double) + n_det * (sizeof(double) + (mixed ? sizeof(float2) : sizeof(double2))));
-}
-
-template <int NDET, bool MX>
-__device__ inline TabView stage_tables(const ModelDev& M, const Tables& T, bool use_lds, double* lds, int tid,
-                                       int nt) {
-  TabView V;
-  if (!use_lds) {
-    V.f = T.f; V.f13 = T.f13; V.lnf3 = T.lnf3; V.fm53 = T.fm53; V.dw = T.dw; V.dw32 = T.dw32; V.hpre = T.hpre;
-    V.ts = 1;
-    V.dk = 1;
-    V.dd = M.n_bins;
-    V.hstride = M.n_bins;
-    V.inv_scale = MX ? 1.0 / M.dw_scale : 1.0;
-    return V;
-  }
-  // one record per bin: f, f^(1/3), ln f / 3, f^(-5/3), then the detectors'
-  // data (double2 each, or float2 in the mixed form), so a bin is read from
-  // one base address; the prefix table follows the records
-  const int K = M.k_lim;
-  constexpr int RD = MX ? 4 + NDET : 4 + 2 * NDET;   // doubles per record (even without MX: 16-byte aligned)
-  for (int k = tid; k < K; k += nt) {
-    double* rec = lds + (size_t)k * RD;
-    rec[0] = T.f[k];
-    rec[1] = T.f13[k];
-    rec[2] = T.lnf3[k];
-    rec[3] = T.fm53[k];
-#pragma unroll
-    for (int d = 0; d < NDET; ++d) {
-      if (MX) reinterpret_cast<float2*>(rec + 4)[d] = T.dw32[(size_t)d * M.n_bins + k];
-      else reinterpret_cast<double2*>(rec + 4)[d] = T.dw[(size_t)d * M.n_bins + k];
-    }
-  }
-  double* hp = lds + (size_t)K * RD;
-  for (int i = tid; i < NDET * K; i += nt) {
-    const int d = i / K, k = i - d * K;
-    hp[i] = T.hpre[(size_t)d * M.n_bins + k];
-  }
-  V.f = lds; V.f13 = lds + 1; V.lnf3 = lds + 2; V.fm53 = lds + 3; V.ts = RD;
-  V.dw = reinterpret_cast<const double2*>(lds + 4);
-  V.dw32 = reinterpret_cast<const float2*>(lds + 4);
-  V.dk = MX ? RD : RD / 2;      // record stride in float2 or double2 units
-  V.dd = 1;
-  V.hpre = hp;
-  V.hstride = K;
-  V.inv_scale = MX ? 1.0 / M.dw_scale : 1.0;
-  return V;
-}
-
-// sin and cos of 2 pi r for |r| <= 1/2 cycles, single precision, on the
-// transcendental unit (whose sine and cosine take their argument in cycles).
-__device__ inline float2 sincos_cycles_f32(float r) {
-  return make_float2(__builtin_amdgcn_sinf(r), __builtin_amdgcn_cosf(r));
-}
-
-// Compensated (Kahan) accumulation in single precision.
-struct KahanF {
-  float s = 0.0f, c = 0.0f;
-  __device__ inline void add(float x) {
-    const float y = x - c;
-    const float t = s + y;
-    c = (t - s) - y;
-    s = t;
-  }
-};
-
-// The coefficients of the probe held by lane `src`, broadcast to the wave.
-template <int NDET>
-__device__ inline Probe probe_from_lane(const Probe& p, int src) {
-  Probe b;
-  b.x = lane_d(p.x, src);
-  b.lnx = lane_d(p.lnx, src);
-  b.pref = lane_d(p.pref, src);
-  b.c2 = lane_d(p.c2, src);
-  b.c3 = lane_d(p.c3, src);
-  b.c4 = lane_d(p.c4, src);
-  b.c5 = lane_d(p.c5, src);
-  b.c5l = lane_d(p.c5l, src);
-  b.c6 = lane_d(p.c6, src);
-  b.c6l = lane_d(p.c6l, src);
-  b.c7 = lane_d(p.c7, src);
-  b.tc = lane_d(p.tc, src);
-  b.ph0 = lane_d(p.ph0, src);
-#pragma unroll
-  for (int d = 0; d < NDET; ++d) {
-    b.kre[d] = lane_d(p.kre[d], src);
-    b.kim[d] = lane_d(p.kim[d], src);
-    b.dt[d] = lane_d(p.dt[d], src);
-  }
-  b.hh = lane_d(p.hh, src);
-  b.f_isco = 0.0;
-  b.k_act = lane_i(p.k_act, src);
-  return b;
-}
-
-// One bin's table entries: frequency terms and the detectors' whitened data.
-template <int NDET, bool MX>
-struct BinRow {
-  double f, f13, lnf3, fm53;
-  typename std::conditional<MX, float2, double2>::type D[NDET];
-};
-
-template <int NDET, bool MX>
-__device__ inline BinRow<NDET, MX> load_bin(const TabView& V, int k) {
-  BinRow<NDET, MX> r;
-  const size_t kt = (size_t)k * V.ts;
-  r.f = V.f[kt];
-  r.f13 = V.f13[kt];
-  r.lnf3 = V.lnf3[kt];
-  r.fm53 = V.fm53[kt];
-#pragma unroll
-  for (int d = 0; d < NDET; ++d) {
-    if constexpr (MX) r.D[d] = V.dw32[(size_t)k * V.dk + d * V.dd];
-    else r.D[d] = V.dw[(size_t)k * V.dk + d * V.dd];
-  }
-  return r;
-}
-
-// This thread's share of <d|h> summed over detectors, for the active bins
-// k = lane, lane + nl, ...:  sum_d Re[A K_d sum_k conj(Dw_dk) e^{-i Phi_dk}].
-// Per detector the bin sums a_d = sum (Dr c - Di s) and b_d = sum (Dr s + Di c)
-// are folded with A K_d = (kre, kim) as kre a_d + kim b_d before returning, so a
-// probe needs a single reduction.  With PF the next bin's table entries are
-// loaded before the current bin is computed, so that their latency overlaps
-// the arithmetic (for kernels with few waves per SIMD).
-template <int NDET, bool MX, bool PF = false>
-__device__ inline double fullgrid_partial(const Probe& p, const TabView& V, int lane, int nl) {
-  using Row = BinRow<NDET, MX>;
-  [[maybe_unused]] Row nxt{};
-  if constexpr (PF) {
-    if (lane < p.k_act) nxt = load_bin<NDET, MX>(V, lane);
-  }
-  if constexpr (MX) {
-    // mixed form: the phase in double, reduced to [-1/2, 1/2] cycles, then
-    // float sincos and compensated float sums of the scaled data
-    KahanF a[NDET], b[NDET];
-    for (int k = lane; k < p.k_act; k += nl) {
-      Row r;
-      if constexpr (PF) {
-        r = nxt;
-        const int kn = k + nl < p.k_act ? k + nl : k;   // the last pass re-reads its own bin
-        nxt = load_bin<NDET, MX>(V, kn);
-      } else {
-        r = load_bin<NDET, MX>(V, k);
-      }
-      const double psi = phase_cycles(p, r.f, r.f13, r.lnf3, r.fm53);
-#pragma unroll
-      for (int d = 0; d < NDET; ++d) {
-        const double ph = fma(r.f, p.dt[d], psi);
-        const float2 sc = sincos_cycles_f32((float)(ph - rint(ph)));
-        const float2 D = r.D[d];
-        a[d].add(fmaf(D.x, sc.y, -D.y * sc.x));
-        b[d].add(fmaf(D.x, sc.x, D.y * sc.y));
-      }
-    }
-    double part = 0.0;
-#pragma unroll
-    for (int d = 0; d < NDET; ++d)
-      part = fma(p.kre[d], (double)a[d].s, fma(p.kim[d], (double)b[d].s, part));
-    return part * V.inv_scale;
-  } else {
-    double a[NDET], b[NDET];
-#pragma unroll
-    for (int d = 0; d < NDET; ++d) { a[d] = 0.0; b[d] = 0.0; }
-    for (int k = lane; k < p.k_act; k += nl) {
-      Row r;
-      if constexpr (PF) {
-        r = nxt;
-        const int kn = k + nl < p.k_act ? k + nl : k;
-        nxt = load_bin<NDET, MX>(V, kn);
-      } else {
-        r = load_bin<NDET, MX>(V, k);
-      }
-      const double psi = phase_cycles(p, r.f, r.f13, r.lnf3, r.fm53);
-#pragma unroll
-      for (int d = 0; d < NDET; ++d) {
-        const double2 sc_ = sincos_cycles(fma(r.f, p.dt[d], psi));
-        const double sn = sc_.x, cs = sc_.y;
-        const double2 D = r.D[d];
-        a[d] = fma(D.x, cs, fma(-D.y, sn, a[d]));
-        b[d] = fma(D.x, sn, fma(D.y, cs, b[d]));
-      }
-    }
-    double part = 0.0;
-#pragma unroll
-    for (int d = 0; d < NDET; ++d) part = fma(p.kre[d], a[d], fma(p.kim[d], b[d], part));
-    return part;
-  }
-}
-
-__device__ inline double gauss_lambda(const ModelDev& M, const double* u) {
-  double acc = 0.0;
-#pragma unroll
-  for (int i = 0; i < MAX_DIM; ++i)
-    if (i < M.n_dim) {
-      double z = u[i] - M.gauss_mu[i];
-      acc = fma(-z * z, M.gauss_inv2s2, acc);
-    }
-  return acc + M.gauss_norm;
-}
-
-// ------------------------------------------------------------ build tables
-__global__ void k_build_tables(const ModelDev* __restrict__ Mp, const double* dre, const double* dim,
-                               const double* psd, double* f, double* f13, double* lnf3, double* fm53, double2* dw,
-                               double* hw) {
-  const ModelDev& M = *Mp;
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= M.n_bins) return;
-  const double fk = fma((double)k, M.df, M.f_lo);
-  const double lf = log(fk);
-  f[k] = fk;
-  f13[k] = cbrt(fk);
-  lnf3[k] = lf / 3.0;
-  fm53[k] = exp(-5.0 / 3.0 * lf);
-  const double a = 4.0 * M.df * exp(-7.0 / 6.0 * lf);
-  const double b = 4.0 * M.df * exp(-7.0 / 3.0 * lf);
-  for (int d = 0; d < M.n_det; ++d) {
-    const size_t o = (size_t)d * M.n_bins + k;
-    const double s = psd[o];
-    dw[o] = make_double2(a * dre[o] / s, a * dim[o] / s);
-    hw[o] = b / s;
-  }
-}
-
-// Inclusive prefix sums of rows of length n (one workgroup per row).
-__global__ __launch_bounds__(1024) void k_prefix_rows(const double* in, double* out, int n) {
-  __shared__ double sbuf[1024];
-  const double* x = in + (size_t)blockIdx.x * n;
-  double* y = out + (size_t)blockIdx.x * n;
-  const int C = (n + 1023) / 1024;
-  const int b = threadIdx.x * C, e = min(n, b + C);
-  double s = 0.0;
-  for (int i = b; i < e; ++i) s += x[i];
-  double incl = block_inclusive_scan<1024, double>(s, sbuf);
-  double run = incl - s;
-  for (int i = b; i < e; ++i) {
-    run += x[i];
-    y[i] = run;
-  }
-}
-
-// ---------------------------------------------------------------- init
-__global__ void k_init_live(int n, int d, uint64_t k0, uint64_t k1, double* u) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
-  for (int i = 0; i < d; i += 4) {
-    u64x4 b = philox(0, (uint64_t)j, 0, purpose_word(P_INIT, (uint64_t)(i >> 2)), k0, k1);
-    for (int q = 0; q < 4 && i + q < d; ++q) u[(size_t)j * d + i + q] = unif53(b.x[q]);
-  }
-}
-
-// ------------------------------------------------------- relative binning
-// Grid frequency f_lo + k df as a product followed by a sum (no fused
-// multiply-add), the rounding the edge snapping is defined with.
-__device__ inline double grid_freq(double f_lo, double df, int k) {
-#pragma clang fp contract(off)
-  return f_lo + (double)k * df;
-}
-
-// Edges e_b = f_lo (f_hi / f_lo)^(b / nb), snapped to the nearest grid
-// frequency, the first and last pinned to the ends of the grid.
-__global__ void k_rb_edges(const ModelDev* __restrict__ Mp, int nb, int* edge, double* fe, double* fe13,
-                           double* lnfe3, double* fem53) {
-  const ModelDev& M = *Mp;
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e > nb) return;
-  const double f_hi = grid_freq(M.f_lo, M.df, M.n_bins - 1);
-  const double raw = M.f_lo * pow(f_hi / M.f_lo, (double)e / nb);
-  int k = (int)floor((raw - M.f_lo) / M.df + 0.5);
-  k = k < 0 ? 0 : (k > M.n_bins - 1 ? M.n_bins - 1 : k);
-  if (e == 0) k = 0;
-  if (e == nb) k = M.n_bins - 1;
-  const double f = grid_freq(M.f_lo, M.df, k);
-  const double lf = log(f);
-  edge[e] = k;
-  fe[e] = f;
-  fe13[e] = cbrt(f);
-  lnfe3[e] = lf / 3.0;
-  fem53[e] = exp(-5.0 / 3.0 * lf);
-}
-
-// Fiducial phases at the edges, bin centres and widths, 1 / (A0 K0_det).
-__global__ void k_rb_fiducial(const ModelDev* __restrict__ Mp, const double* theta, int nb, const double* fe,
-                              const double* fe13, const double* lnfe3, const double* fem53, double* phi0,
-                              double2* g0, double* fm, double* inv_w) {
-  const ModelDev& M = *Mp;
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e > nb) return;
-  Phys s;
-  phys_from_theta(M, theta, &s);
-  Probe P;
-  probe_from_phys(M, s, nullptr, &P);
-  const double psi = phase_cycles(P, fe[e], fe13[e], lnfe3[e], fem53[e]);
-  for (int d = 0; d < M.n_det; ++d) phi0[d * (nb + 1) + e] = fma(fe[e], P.dt[d], psi);
-  if (e < nb) {
-    fm[e] = 0.5 * (fe[e] + fe[e + 1]);
-    inv_w[e] = 1.0 / (fe[e + 1] - fe[e]);
-  }
-  if (e == 0) {
-    for (int d = 0; d < M.n_det; ++d) {
-      const double den = P.kre[d] * P.kre[d] + P.kim[d] * P.kim[d];
-      g0[d] = make_double2(P.kre[d] / den, -P.kim[d] / den);
-    }
-  }
-}
-
-// Summary sums, one thread per (detector, coarse bin), accumulated over the
-// bin's fine bins in frequency order; the running sums are kept per fine bin.
-__global__ void k_rb_sums(const ModelDev* __restrict__ Mp, Tables T, const double* hw, const double* theta, int nb,
-                          const int* edge, const double* fm, double2* A0, double2* A1, double* B0, double* B1,
-                          double2* cA0, double2* cA1, double* cB0, double* cB1) {
-  const ModelDev& M = *Mp;
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  const int d = blockIdx.y;
-  if (b >= nb) return;
-  Phys s;
-  phys_from_theta(M, theta, &s);
-  Probe P;
-  probe_from_phys(M, s, nullptr, &P);
-  const double kr = P.kre[d], ki = P.kim[d];
-  const double k2 = kr * kr + ki * ki;
-  const int first = edge[b], last = (b < nb - 1) ? edge[b + 1] - 1 : edge[nb];
-  const double fmb = fm[b];
-  double s0r = 0, s0i = 0, s1r = 0, s1i = 0, t0 = 0, t1 = 0;
-  for (int k = first; k <= last; ++k) {
-    const size_t o = (size_t)d * M.n_bins + k;
-    const double f = T.f[k];
-    const double ph = fma(f, P.dt[d], phase_cycles(P, f, T.f13[k], T.lnf3[k], T.fm53[k]));
-    const double2 sc_ = sincos_cycles(ph);
-    const double sn = sc_.x, cs = sc_.y;
-    // A0 K0 e^{-i Phi0}: the fiducial strain without f^(-7/6) (carried by dw)
-    const double er = kr * cs + ki * sn, ei = ki * cs - kr * sn;
-    const double2 D = T.dw[o];
-    const double ar = D.x * er + D.y * ei, ai = D.x * ei - D.y * er;   // conj(dw) * K0 e^{-i Phi0}
-    const double bk = k2 * hw[o];
-    const double x = f - fmb;
-    s0r += ar; s0i += ai;
-    s1r += ar * x; s1i += ai * x;
-    t0 += bk; t1 += bk * x;
-    cA0[o] = make_double2(s0r, s0i);
-    cA1[o] = make_double2(s1r, s1i);
-    cB0[o] = t0;
-    cB1[o] = t1;
-  }
-  const size_t q = (size_t)d * nb + b;
-  A0[q] = make_double2(s0r, s0i);
-  A1[q] = make_double2(s1r, s1i);
-  B0[q] = t0;
-  B1[q] = t1;
-}
-
-// This thread's share of lambda for one probe under relative binning.  Phase
-// 1: the ratio r_d(e) = h(e) / h0(e) = A K_d / (A0 K0_d) e^{-i (Phi_d - Phi0_d)}
-// at the edges e = tid, tid + nt, ... into LDS.  Phase 2: per coarse bin
-// b = tid, ...: r0 = (r_b + r_{b+1}) / 2, r1 = (r_{b+1} - r_b) / (e_{b+1} - e_b),
-// Re(A0 r0 + A1 r1) - 1/2 [B0 |r0|^2 + 2 B1 Re(conj(r0) r1)]; bins whose first
-// fine bin is above f_ISCO are skipped and the straddling bin uses the sums
-// up to its last active fine bin.  Contains one workgroup barrier.
-// Relative-binning tables staged in LDS by a chain workgroup (doubles from a
-// 16-byte aligned base): edge frequencies and their powers, fiducial phases,
-// 1 / bin width, edge indices, then the bin sums (double, or float in the
-// mixed form).  The cumulative sums of the straddling bin stay in HBM.
-__host__ __device__ inline size_t rb_stage_doubles(int nb, int n_det, bool mixed) {
-  const size_t ne = nb + 1, nbd = (size_t)n_det * nb;
-  size_t o = (4 + (size_t)n_det) * ne + nb + (ne + 1) / 2;
-  o += o & 1;
-  return o + (mixed ? 2 * nbd + 2 * ((nbd + 1) / 2) : 6 * nbd);
-}
-
-template <int NDET, bool MX>
-__device__ inline RBTables stage_rb(const RBTables& B, double* lds, int tid, int nt) {
-  RBTables V = B;
-  const int nb = B.nb, ne = nb + 1, nbd = NDET * nb;
-  double* fe = lds;
-  double* fe13 = fe + ne;
-  double* lnfe3 = fe13 + ne;
-  double* fem53 = lnfe3 + ne;
-  double* phi0 = fem53 + ne;
-  double* inv_w = phi0 + NDET * ne;
-  int* edge = reinterpret_cast<int*>(inv_w + nb);
-  size_t o = (size_t)(4 + NDET) * ne + nb + (ne + 1) / 2;
-  o += o & 1;
-  for (int e = tid; e < ne; e += nt) {
-    fe[e] = B.fe[e];
-    fe13[e] = B.fe13[e];
-    lnfe3[e] = B.lnfe3[e];
-    fem53[e] = B.fem53[e];
-    edge[e] = B.edge[e];
-#pragma unroll
-    for (int d = 0; d < NDET; ++d) phi0[d * ne + e] = B.phi0[d * ne + e];
-  }
-  for (int b = tid; b < nb; b += nt) inv_w[b] = B.inv_w[b];
-  V.fe = fe; V.fe13 = fe13; V.lnfe3 = lnfe3; V.fem53 = fem53; V.phi0 = phi0; V.inv_w = inv_w; V.edge = edge;
-  if constexpr (MX) {
-    float2* a0 = reinterpret_cast<float2*>(lds + o);
-    float2* a1 = a0 + nbd;
-    float* b0 = reinterpret_cast<float*>(a1 + nbd);
-    float* b1 = b0 + 2 * ((nbd + 1) / 2);
-    for (int i = tid; i < nbd; i += nt) {
-      a0[i] = B.A0f[i]; a1[i] = B.A1f[i]; b0[i] = B.B0f[i]; b1[i] = B.B1f[i];
-    }
-    V.A0f = a0; V.A1f = a1; V.B0f = b0; V.B1f = b1;
-  } else {
-    double2* a0 = reinterpret_cast<double2*>(lds + o);
-    double2* a1 = a0 + nbd;
-    double* b0 = reinterpret_cast<double*>(a1 + nbd);
-    double* b1 = b0 + nbd;
-    for (int i = tid; i < nbd; i += nt) {
-      a0[i] = B.A0[i]; a1[i] = B.A1[i]; b0[i] = B.B0[i]; b1[i] = B.B1[i];
-    }
-    V.A0 = a0; V.A1 = a1; V.B0 = b0; V.B1 = b1;
-  }
-  return V;
-}
-
-// This thread's share of a relative-binning likelihood; lds holds the edge
-// ratios of the probe.  Every thread of the workgroup calls it (it contains a
-// barrier); an inactive caller only takes part in the barrier.  WAVE: the
-// probe belongs to one wavefront, which synchronises on its own.
-// Edges relative binning reads for a probe with k_act active grid bins: those
-// of its active coarse bins (bin b is active iff edge[b] < k_act), one more
-// than the bins, or none if bin 0 is inactive.  Counted with ballots over
-// the wavefront (every lane must take part); the result is uniform.
-__device__ inline int rb_edges_read(const RBTables& B, int k_act, int lane) {
-  int n_act = 0;
-  for (int b0 = 0; b0 < B.nb; b0 += 64) {
-    const int b = b0 + lane;
-    n_act += __popcll(__ballot(b < B.nb && B.edge[b] < k_act));
-  }
-  return n_act > 0 ? n_act + 1 : 0;
-}
-
-template <int NDET, bool MX, bool WAVE = false>
-__device__ inline double rb_partial(const Probe& p, const RBTables& B, int n_bins, void* lds, int tid, int nt,
-                                    bool active = true) {
-  using CT = typename std::conditional<MX, float2, double2>::type;
-  CT* sr = reinterpret_cast<CT*>(lds);
-  const int nb = B.nb;
-  for (int e = active ? tid : nb + 1; e <= nb; e += nt) {
-    // edge e bounds bins e - 1 and e; with increasing edges it is read only
-    // if bin e - 1 (bin 0 for e = 0) starts below the active-bin count
-    if (B.edge[e > 0 ? e - 1 : 0] >= p.k_act) continue;
-    const double f = B.fe[e];
-    const double psi = phase_cycles(p, f, B.fe13[e], B.lnfe3[e], B.fem53[e]);
-#pragma unroll
-    for (int d = 0; d < NDET; ++d) {
-      const double dph = fma(f, p.dt[d], psi) - B.phi0[d * (nb + 1) + e];
-      const double2 g = B.g0[d];
-      const double gr = p.kre[d] * g.x - p.kim[d] * g.y, gi = p.kre[d] * g.y + p.kim[d] * g.x;
-      if constexpr (MX) {
-        const float2 sc = sincos_cycles_f32((float)(dph - rint(dph)));
-        const float fr = (float)gr, fi = (float)gi;
-        sr[d * (nb + 1) + e] = make_float2(fmaf(fr, sc.y, fi * sc.x), fmaf(fi, sc.y, -fr * sc.x));
-      } else {
-        const double2 sc = sincos_cycles(dph);
-        sr[d * (nb + 1) + e] = make_double2(gr * sc.y + gi * sc.x, gi * sc.y - gr * sc.x);
-      }
-    }
-  }
-  if constexpr (WAVE) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  } else {
-    __syncthreads();
-  }
-  double part = 0.0;
-  for (int b = active ? tid : nb; b < nb; b += nt) {
-    const int first = B.edge[b];
-    if (first >= p.k_act) continue;
-    const int last = (b < nb - 1) ? B.edge[b + 1] - 1 : B.edge[nb];
-    const bool full = last < p.k_act;
-#pragma unroll
-    for (int d = 0; d < NDET; ++d) {
-      if constexpr (MX) {
-        float2 a0, a1;
-        float b0, b1;
-        if (full) {
-          const size_t q = (size_t)d * nb + b;
-          a0 = B.A0f[q]; a1 = B.A1f[q]; b0 = B.B0f[q]; b1 = B.B1f[q];
-        } else {
-          const size_t q = (size_t)d * n_bins + p.k_act - 1;
-          a0 = make_float2((float)B.cA0[q].x, (float)B.cA0[q].y);
-          a1 = make_float2((float)B.cA1[q].x, (float)B.cA1[q].y);
-          b0 = (float)B.cB0[q]; b1 = (float)B.cB1[q];
-        }
-        const float iw = (float)B.inv_w[b];
-        const float2 ra = sr[d * (nb + 1) + b], rb = sr[d * (nb + 1) + b + 1];
-        const float r0r = 0.5f * (ra.x + rb.x), r0i = 0.5f * (ra.y + rb.y);
-        const float r1r = (rb.x - ra.x) * iw, r1i = (rb.y - ra.y) * iw;
-        const float dh = (a0.x * r0r - a0.y * r0i) + (a1.x * r1r - a1.y * r1i);
-        const float hh = b0 * (r0r * r0r + r0i * r0i) + 2.0f * b1 * (r0r * r1r + r0i * r1i);
-        part += (double)(dh - 0.5f * hh);
-      } else {
-        double2 a0, a1;
-        double b0, b1;
-        if (full) {
-          const size_t q = (size_t)d * nb + b;
-          a0 = B.A0[q]; a1 = B.A1[q]; b0 = B.B0[q]; b1 = B.B1[q];
-        } else {
-          const size_t q = (size_t)d * n_bins + p.k_act - 1;
-          a0 = B.cA0[q]; a1 = B.cA1[q]; b0 = B.cB0[q]; b1 = B.cB1[q];
-        }
-        const double iw = B.inv_w[b];
-        const double2 ra = sr[d * (nb + 1) + b], rb = sr[d * (nb + 1) + b + 1];
-        const double r0r = 0.5 * (ra.x + rb.x), r0i = 0.5 * (ra.y + rb.y);
-        const double r1r = (rb.x - ra.x) * iw, r1i = (rb.y - ra.y) * iw;
-        const double dh = (a0.x * r0r - a0.y * r0i) + (a1.x * r1r - a1.y * r1i);
-        const double hh = b0 * (r0r * r0r + r0i * r0i) + 2.0 * b1 * (r0r * r1r + r0i * r1i);
-        part += dh - 0.5 * hh;
-      }
-    }
-  }
-  return part;
-}
-
-// Batched relative-binning likelihood: one wavefront per workgroup, 64
-// probes set up per pass (one per lane), evaluated one after another.
-template <int NDET, bool MX>
-__global__ __launch_bounds__(64) void k_loglike_rb(const ModelDev* __restrict__ Mp, RBTables RB,
-                                                   const double* __restrict__ u, long n, double* __restrict__ out,
-                                                   int* __restrict__ terms) {
-  extern __shared__ double smem[];
-  void* sr = smem;
-  const ModelDev& M = *Mp;
-  const int lane = threadIdx.x;
-  const int d = M.n_dim;
-  for (long base = (long)blockIdx.x * 64; base < n; base += (long)gridDim.x * 64) {
-    const long i = base + lane;
-    const long src = i < n ? i : base;
-    double y[MAX_DIM];
-#pragma unroll
-    for (int q = 0; q < MAX_DIM; ++q) y[q] = (q < d) ? u[src * d + q] : 0.0;
-    Probe pr;
-    make_probe(M, nullptr, y, &pr);
-    double mine = 0.0;
-    int mine_edges = 0;
-    const int cnt = (n - base) < 64 ? (int)(n - base) : 64;
-    for (int p = 0; p < cnt; ++p) {
-      const Probe pb = probe_from_lane<NDET>(pr, p);
-      const double tot = wave_sum(rb_partial<NDET, MX>(pb, RB, M.n_bins, sr, lane, 64));
-      const int ne = rb_edges_read(RB, pb.k_act, lane);
-      if (lane == p) {
-        mine = tot;
-        mine_edges = ne;
-      }
-      __syncthreads();   // the ratios in LDS are rewritten by the next probe
-    }
-    if (i < n) out[i] = mine;
-    if (terms && i < n) terms[i] = mine_edges;
-  }
-}
-
-// Float copies for the mixed form.
-__global__ __launch_bounds__(1024) void k_noise_loglike(const double* __restrict__ dre, const double* __restrict__ dim,
-                                                       const double* __restrict__ psd, long n, double df,
-                                                       double* out) {
-  __shared__ double sbuf[1024];
-  double acc = 0.0;
-  for (long i = threadIdx.x; i < n; i += 1024) {
-    const double v = psd[i] / (4.0 * df);
-    acc += -log(2.0 * PI * v) - (dre[i] * dre[i] + dim[i] * dim[i]) / (2.0 * v);
-  }
-  acc = block_sum<1024>(acc, sbuf);
-  if (threadIdx.x == 0) *out = acc;
-}
-
-__global__ void k_to_float2(const double2* src, float2* dst, size_t n, double scale) {
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) dst[i] = make_float2((float)(src[i].x * scale), (float)(src[i].y * scale));
-}
-
-__global__ void k_to_float1(const double* src, float* dst, size_t n, double scale) {
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) dst[i] = (float)(src[i] * scale);
-}
-
-// ---------------------------------------------------------- batched lambda
-// Each wavefront takes 64 consecutive probes: lane l sets up probe base + l,
-// then the wave evaluates the probes one at a time over the bins.
-template <int NDET, int LK, bool LDS>
-__global__ __launch_bounds__(256) void k_loglike(const ModelDev* __restrict__ Mp, Tables T, RBTables RB,
-                                                 const double* __restrict__ u, long n, double* __restrict__ out,
-                                                 int* __restrict__ terms) {
-  extern __shared__ double smem[];
-  const ModelDev& M = *Mp;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  TabView V{};
-  if (lk_full(LK)) {
-    V = stage_tables<NDET, lk_mixed(LK)>(M, T, LDS, smem, tid, 256);
-    if (LDS) __syncthreads();
-  }
-  const int d = M.n_dim;
-  for (long base = ((long)blockIdx.x * 4 + wv) * 64; base < n; base += (long)gridDim.x * 256) {
-    const long i = base + lane;
-    const long src = i < n ? i : base;
-    double y[MAX_DIM];
-#pragma unroll
-    for (int q = 0; q < MAX_DIM; ++q) y[q] = (q < d) ? u[src * d + q] : 0.0;
-    double mine;
-    int nterm = 0;
-    if (LK == LK_GAUSS) {
-      mine = gauss_lambda(M, y);
-    } else {
-      Probe pr;
-      make_probe(M, T.hpre, y, &pr);
-      mine = 0.0;
-      const int cnt = (n - base) < 64 ? (int)(n - base) : 64;
-      for (int p = 0; p < cnt; ++p) {
-        const Probe pb = probe_from_lane<NDET>(pr, p);
-        const double tot = wave_sum(fullgrid_partial<NDET, lk_mixed(LK)>(pb, V, lane, 64));
-        if (lane == p) mine = tot - 0.5 * pb.hh;
-      }
-      nterm = pr.k_act;
-    }
-    if (i < n) out[i] = mine;
-    if (terms && i < n) terms[i] = nterm;
-  }
-}
-
-// Two-pass form of the batched full-grid likelihood: the per-probe source
-// set-up runs one thread per probe and stores the coefficients; the bin
-// pass then runs one wavefront per probe with the coefficients in scalar
-// registers, so the bin loop keeps few vector registers and many waves
-// per SIMD hide its latency.
-__global__ __launch_bounds__(256) void k_probe_setup(const ModelDev* __restrict__ Mp, const double* __restrict__ hpre,
-                                                     const double* __restrict__ u, long n, Probe* __restrict__ P,
-                                                     int* __restrict__ terms) {
-  const ModelDev& M = *Mp;
-  const long i = (long)blockIdx.x * 256 + threadIdx.x;
-  if (i >= n) return;
-  const int d = M.n_dim;
-  double y[MAX_DIM];
-#pragma unroll
-  for (int q = 0; q < MAX_DIM; ++q) y[q] = (q < d) ? u[i * d + q] : 0.0;
-  Probe pr;
-  make_probe(M, hpre, y, &pr);
-  P[i] = pr;
-  if (terms) terms[i] = pr.k_act;
-}
-
-template <int NDET, int LK, bool LDS>
-// 1024 threads share one staged copy of the tables, so a CU holds eight
-// waves per SIMD.
-__global__ __launch_bounds__(1024) void k_probe_bins(const ModelDev* __restrict__ Mp, Tables T,
-                                                     const Probe* __restrict__ P, long n, double* __restrict__ out) {
-  extern __shared__ double smem[];
-  const ModelDev& M = *Mp;
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const TabView V = stage_tables<NDET, lk_mixed(LK)>(M, T, LDS, smem, tid, 1024);
-  if (LDS) __syncthreads();
-  for (long p = (long)blockIdx.x * 16 + wv; p < n; p += (long)gridDim.x * 16) {
-    const Probe pb = P[p];
-    const double tot = wave_sum(fullgrid_partial<NDET, lk_mixed(LK)>(pb, V, lane, 64));
-    if (lane == 0) out[p] = tot - 0.5 * pb.hh;
-  }
-}
-
-// Relative-binning bin pass of the two-pass batch: the tables staged once
-// per 512-thread block, one wavefront per probe with its own edge-ratio
-// scratch, the coefficients read with scalar loads.
-template <int NDET, bool MX>
-__global__ __launch_bounds__(512) void k_rb_bins(RBTables RB, int n_bins, const Probe* __restrict__ P, long n,
-                                                 double* __restrict__ out, int* __restrict__ terms) {
-  extern __shared__ double smem[];
-  using CT = typename std::conditional<MX, float2, double2>::type;
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const RBTables V = stage_rb<NDET, MX>(RB, smem, tid, 512);
-  const size_t ratio_doubles = (size_t)NDET * (RB.nb + 1) * sizeof(CT) / sizeof(double);
-  double* sr = smem + rb_stage_doubles(RB.nb, NDET, MX) + wv * ratio_doubles;
-  __syncthreads();
-  for (long p = (long)blockIdx.x * 8 + wv; p < n; p += (long)gridDim.x * 8) {
-    const Probe pb = P[p];
-    const double tot = wave_sum(rb_partial<NDET, MX, true>(pb, V, n_bins, sr, lane, 64));
-    const int ne = terms ? rb_edges_read(V, pb.k_act, lane) : 0;
-    if (lane == 0) {
-      out[p] = tot;
-      if (terms) terms[p] = ne;
-    }
-    // the next probe rewrites this wavefront's ratios
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  }
-}
-
-// ---------------------------------------------------------------- select
-// Rank of element i in the total order (order key, index), one wavefront.
-__device__ inline void rank_element(const double* __restrict__ lam, int n, int k, int* rank, int* dead, double* lstar,
-                                    int i, int lane) {
-  const uint64_t ki = order_key(lam[i]);
-  int cnt = 0;
-  for (int j = lane; j < n; j += 64) {
-    const uint64_t kj = order_key(lam[j]);
-    cnt += (kj < ki) || (kj == ki && j < i);
-  }
-  cnt = (int)wave_sum_ll(cnt);
-  if (lane == 0) {
-    if (rank) rank[i] = cnt;
-    if (cnt < k) dead[cnt] = i;
-    if (cnt == k - 1 && lstar) *lstar = order_value(lam[i]);
-  }
-}
-
-__global__ __launch_bounds__(256) void k_rank(const double* __restrict__ lam, int n, int k, int* rank, int* dead,
-                                              double* lstar, const int* done) {
-  if (done && *done) return;
-  const int i = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-  if (i >= n) return;
-  rank_element(lam, n, k, rank, dead, lstar, i, lane);
-}
-
-// ------------------------------------------------------------- iteration prep
-// One workgroup of 1024 threads; s_surv: n ints of LDS (survivor list).
-constexpr int PCH = 1024;             // live points per chunk of the mean and covariance passes
-
-// One workgroup of 1024 threads.  spts holds a chunk of live points by
-// coordinate (all of them when n <= PCH) and afterwards the survivor list.
-__device__ void prep_body(const RunDev& R) {
-  __shared__ double sbuf[1024];
-  __shared__ double spts[MAX_DIM * PCH];
-  int* s_surv = reinterpret_cast<int*>(spts);
-  __shared__ double smean[MAX_DIM];
-  __shared__ double scov[MAX_DIM * MAX_DIM];
-  __shared__ int sint[1024];
-  DevState* S = R.state;
-  const int done0 = S->done;
-  if (done0) return;
-  const int n = R.n, k = R.k, d = R.d, tid = threadIdx.x;
-  const long long nd0 = S->n_dead;
-  const double logX0 = S->logX, logZ0 = S->logZ, H0 = S->H;
-  const int it = S->iter;
-  __syncthreads();
-  if (nd0 + k > R.cap) {
-    if (tid == 0) S->done = 2;
-    return;
-  }
-
-  // ---- evidence: the j-th death shrinks log X by 1/(n-j); its weight is the
-  // shell between consecutive volumes, X_{j-1} (1 - e^{-1/(n-j)}).
-  const int C = (k + 1023) / 1024;
-  const int jb = tid * C, je = min(k, jb + C);
-  double csum = 0.0;
-  for (int j = jb; j < je; ++j) csum += 1.0 / (double)(n - j);
-  double total;                                        // sum of 1/(n-j) over the batch
-  const double incl = block_scan<1024, double>(csum, sbuf, &total);
-  double lx = logX0 - (incl - csum);
-  double mloc = NEG_INF;
-  for (int j = jb; j < je; ++j) {
-    const int slot = R.dead[j];
-    const double lraw = R.lam[slot];
-    const double l = order_value(lraw);
-    const double inv = 1.0 / (double)(n - j);
-    const double lw = l + lx + log(-expm1(-inv));
-    const double lxn = lx - inv;
-    const long long q = nd0 + j;
-    R.dlam[q] = lraw;
-    R.dlogx[q] = lxn;
-    R.dlogw[q] = lw;
-    R.diter[q] = it;
-    R.dslot[q] = slot;
-    R.dnlive[q] = n - j;
-    mloc = fmax(mloc, lw);
-    lx = lxn;
-  }
-  // the dead points' coordinates, copied with independent loads
-  for (int idx = tid; idx < k * d; idx += 1024) {
-    const int j = idx / d, i = idx - j * d;
-    R.du[(nd0 + j) * d + i] = R.u[(size_t)R.dead[j] * d + i];
-  }
-  double m = block_max<1024>(mloc, sbuf);
-  m = fmax(m, logZ0);
-  double s12[2] = {0.0, 0.0};
-  if (m > NEG_INF) {
-    for (int j = jb; j < je; ++j) {
-      const double lw = R.dlogw[nd0 + j];
-      if (lw > NEG_INF) {
-        const double e = exp(lw - m);
-        s12[0] += e;
-        s12[1] += e * order_value(R.dlam[nd0 + j]);
-      }
-    }
-  }
-  block_sum_k<1024, 2>(s12, sbuf);
-  const double s1 = s12[0], s2 = s12[1];
-  if (tid == 0) {
-    double logZ1 = logZ0, H1 = H0;
-    if (m > NEG_INF) {
-      const double zold = (logZ0 > NEG_INF) ? exp(logZ0 - m) : 0.0;
-      logZ1 = m + log(zold + s1);
-      H1 = s2 * exp(m - logZ1) - logZ1;
-      if (logZ0 > NEG_INF) H1 += exp(logZ0 - logZ1) * (H0 + logZ0);
-    }
-    S->logX = logX0 - total;
-    S->logZ = logZ1;
-    S->H = H1;
-    S->lstar = order_value(R.lam[R.dead[k - 1]]);
-    S->n_dead = nd0 + k;
-  }
-
-  // ---- covariance of all n live points (before removal), 1/(n-1)
-  // The points pass through LDS in chunks of PCH, one row per coordinate,
-  // read with coalesced loads: first for the mean (a group of 1024/d threads
-  // per coordinate), then, centred, for the covariance.
-  {
-    const int G1 = 1024 / d;
-    const int mi = tid / G1, msub = tid - mi * G1;
-    double ms = 0.0;
-    for (int j0 = 0; j0 < n; j0 += PCH) {
-      const int cnt = min(PCH, n - j0);
-      __syncthreads();                // the previous chunk has been read
-      for (int idx = tid; idx < cnt * d; idx += 1024) {
-        const int jj = idx / d, i = idx - jj * d;
-        spts[i * PCH + jj] = R.u[(size_t)j0 * d + idx];
-      }
-      __syncthreads();
-      if (mi < d)
-        for (int jj = msub; jj < cnt; jj += G1) ms += spts[mi * PCH + jj];
-    }
-    sbuf[tid] = ms;
-    __syncthreads();
-    if (tid < d) {
-      double t = 0.0;
-      for (int q = 0; q < G1; ++q) t += sbuf[tid * G1 + q];
-      smean[tid] = t / n;
-    }
-    __syncthreads();
-  }
-  // lower-triangle entry e -> (a, b), a >= b, row-major: a group of G
-  // threads sums each entry over a strided share of every chunk (the chunk
-  // of the mean pass is still in LDS when n <= PCH), and the group's partial
-  // sums meet in LDS at the end
-  const int E = d * (d + 1) / 2;
-  const int G = 1024 / E;
-  const int lane = tid & 63, wv = tid >> 6;
-  const int eg = tid / G, sub = tid - eg * G;
-  int ea = 0, eb = 0;
-  if (eg < E) {
-    int r = eg;
-    while (r > ea) { r -= ea + 1; ++ea; }
-    eb = r;
-  }
-  const double ma = smean[ea], mb = smean[eb];
-  double cs = 0.0;
-  for (int j0 = 0; j0 < n; j0 += PCH) {
-    const int cnt = min(PCH, n - j0);
-    if (n > PCH) {
-      __syncthreads();                // the previous chunk has been read
-      for (int idx = tid; idx < cnt * d; idx += 1024) {
-        const int jj = idx / d, i = idx - jj * d;
-        spts[i * PCH + jj] = R.u[(size_t)j0 * d + idx];
-      }
-      __syncthreads();
-    }
-    if (eg < E) {
-      const double* ra = spts + ea * PCH;
-      const double* rb = spts + eb * PCH;
-      for (int jj = sub; jj < cnt; jj += G) cs += (ra[jj] - ma) * (rb[jj] - mb);
-    }
-  }
-  sbuf[tid] = cs;
-  __syncthreads();
-  if (tid < E) {
-    int a = 0, r = tid;
-    while (r > a) { r -= a + 1; ++a; }
-    const int b = r;
-    double c = 0.0;
-    for (int q = 0; q < G; ++q) c += sbuf[tid * G + q];
-    c /= (double)(n - 1);
-    scov[a * d + b] = c;
-    scov[b * d + a] = c;
-  }
-  __syncthreads();
-  if (wv == 0) {
-    // Cholesky factor, one row per lane (row j broadcast from lane j); on
-    // failure add 1e-12 tr/d to the diagonal and retry
-    double L[MAX_DIM];
-    bool ok = false;
-    for (int attempt = 0; attempt < 2 && !ok; ++attempt) {
-      if (attempt == 1) {
-        double tr = 0.0;
-        for (int i = 0; i < d; ++i) tr += scov[i * d + i];
-        if (lane < d) scov[lane * d + lane] += 1e-12 * tr / d;
-      }
-      ok = true;
-#pragma unroll
-      for (int q = 0; q < MAX_DIM; ++q) L[q] = 0.0;
-#pragma unroll
-      for (int j = 0; j < MAX_DIM; ++j) {
-        if (j < d) {
-          double s = lane < d ? scov[lane * d + j] : 0.0;
-#pragma unroll
-          for (int q = 0; q < j; ++q) s -= L[q] * lane_d(L[q], j);
-          const double diag = lane_d(s, j);
-          ok = ok && diag > 0.0;
-          const double ljj = sqrt(fmax(diag, 0.0));
-          L[j] = (lane == j) ? ljj : (lane > j && ljj > 0.0 ? s / ljj : 0.0);
-        }
-      }
-    }
-    if (lane < d) {
-#pragma unroll
-      for (int q = 0; q < MAX_DIM; ++q)
-        if (q < d) R.chol[lane * d + q] = ok ? (q <= lane ? L[q] : 0.0) : (q == lane ? 1e-6 : 0.0);
-    }
-  }
-
-  // ---- survivors in ascending slot order, then the chain start points
-  const int C2 = (n + 1023) / 1024;
-  const int ib = tid * C2, ie = min(n, ib + C2);
-  int cnt = 0;
-  for (int i = ib; i < ie; ++i) cnt += (R.rank[i] >= k);
-  int all_surv;
-  const int icl = block_scan<1024, int>(cnt, sint, &all_surv);
-  int pos = icl - cnt;
-  for (int i = ib; i < ie; ++i)
-    if (R.rank[i] >= k) s_surv[pos++] = i;
-  __syncthreads();
-  const int ns = n - k;
-  for (int j = tid; j < k; j += 1024) {
-    u64x4 b = philox((uint64_t)it, (uint64_t)j, 0, purpose_word(P_PICK, 0), R.key0, R.key1);
-    const int idx = (int)floor(unif53(b.x[0]) * (double)ns);
-    R.start[j] = s_surv[idx < ns ? idx : ns - 1];
-  }
-}
-
-__global__ __launch_bounds__(1024) void k_prep(RunDev R) { prep_body(R); }
-
-
-// ------------------------------------------------------------ slice chains
-// Candidate batches of the chain kernel: NC candidates per batch, each set
-// up by two threads (the intrinsic and the extrinsic half of the probe).
-// Slots [0, SO) hold left step-out points, [SO, 2 SO) right ones, the rest
-// the first SC shrink candidates of each bracket the step-out can end in
-// with at most H-1 steps per side.
-template <int NC> struct SliceBatch {
-  static constexpr int SO = NC / 8;
-  static constexpr int H = NC >= 64 ? 4 : 2;
-  static constexpr int SC = NC >= 128 ? 6 : (NC >= 64 ? 3 : 6);
-  static_assert(2 * SO + H * H * SC <= NC, "batch layout");
-};
-
-// Dynamic LDS of the chain kernel (doubles), in order: Cholesky factor,
-// reduction slots, directions and uniforms of a chunk of steps, the batch
-// (probe records, positions, Gaussian values or fallback uniforms, in-cube
-// flags), the chain position, then the likelihood tables (full grid, when
-// they fit) or the edge ratios (relative binning).
-constexpr int SL_CHUNK = 16;                          // steps drawn per chunk
-constexpr int SL_PSTRIDE = (int)((sizeof(ProbeRec) + 15) / 16) * 2;   // doubles per stored record
-constexpr int SL_NU = 10;                             // uniforms per step: width, split, 8 shrink
-__host__ __device__ constexpr size_t slice_fixed_doubles(int nt) {
-  return MAX_DIM * MAX_DIM + 16 + SL_CHUNK * MAX_DIM + SL_CHUNK * SL_NU + (size_t)(nt / 2) * SL_PSTRIDE + nt + nt +
-         nt / 4 + 16;
-}
-
-// One workgroup of NT threads runs chain j = blockIdx.x for all n_steps
-// steps.  The random numbers and tuned directions of a chunk of steps are
-// drawn up front, lane-parallel.  Each step then sets up one batch of NT/2
-// candidates in parallel (each fixed in advance: the step-out points and,
-// under the hypothesis that earlier candidates are rejected, the shrink
-// sequence of every likely bracket); the first half of the workgroup
-// computes the intrinsic half of every candidate's probe while the second
-// half computes the extrinsic one.  All threads then walk the batch in the
-// sequential order of the algorithm and split every probe's frequency bins.
-// Rarer outcomes fall back to further batches.
-template <int NDET, int NT, int LK, bool LDS>
-__device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& RB, const RunDev& R, int j,
-                           double* smem) {
-  constexpr int NW = NT / 64;
-  constexpr int NC = NT / 2;         // candidates per batch
-  constexpr int FB = NC < 32 ? NC : 32;   // candidates per fallback batch
-  using BL = SliceBatch<NC>;
-  DevState* S = R.state;
-  if (S->done) return;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int d = R.d;
-  const uint64_t t = (uint64_t)S->iter;
-  const double lstar = S->lstar;
-  double* sL = smem;
-  double* sred = sL + MAX_DIM * MAX_DIM;
-  double* sDir = sred + 16;
-  double* sU = sDir + SL_CHUNK * MAX_DIM;
-  double* sP = sU + SL_CHUNK * SL_NU;
-  double* sT = sP + NC * SL_PSTRIDE;
-  double* sG = sT + NT;
-  unsigned long long* sMask = reinterpret_cast<unsigned long long*>(sG + NT);   // in-cube bits per 64 candidates
-  double* sX = sG + NT + NT / 4;     // chain position
-  double* stab = sX + 16;
-  for (int i = tid; i < d * d; i += NT) sL[i] = R.chol[i];
-  TabView V{};
-  if (lk_full(LK)) V = stage_tables<NDET, lk_mixed(LK)>(M, T, LDS, stab, tid, NT);
-  // relative binning: the tables (staged in LDS when LDS is set) and the edge
-  // ratios of up to two probes at once
-  RBTables RBv = RB;
-  double* sr0 = stab;
-  if constexpr (lk_rb(LK)) {
-    if constexpr (LDS) {
-      RBv = stage_rb<NDET, lk_mixed(LK)>(RB, stab, tid, NT);
-      sr0 = stab + rb_stage_doubles(RB.nb, NDET, lk_mixed(LK));
-    }
-  }
-  double* sr1 = sr0 + (size_t)NDET * (RB.nb + 1) * (lk_mixed(LK) ? 1 : 2);
-
-  int buf = 0;
-  int nprobe = 0;
-  long long nbins = 0;
-  const int start = R.start[j];
-  for (int i = tid; i < d; i += NT) sX[i] = R.u[(size_t)start * d + i];
-  double lx = R.lam[start];
-  const int nbd = (d + 3) >> 2;      // DIR blocks per step
-  const double w = R.width;
-
-  // candidate c = tid mod NC of a batch, at position tt along dir (valid:
-  // the slot is used; unused slots are marked outside the cube); threads
-  // below NC compute the intrinsic half of its probe, the others the
-  // extrinsic half
-  const int cand = tid % NC;
-  const bool intrinsic_half = tid < NC;
-  auto setup = [&](bool valid, double tt, const double* dir) {
-    // all MAX_DIM slots of the position and direction rows are read (slots
-    // from d on are masked), so the loads issue together instead of one
-    // dependent round trip per coordinate
-    double xr[MAX_DIM], dr[MAX_DIM];
-#pragma unroll
-    for (int i = 0; i < MAX_DIM; ++i) {
-      xr[i] = sX[i];
-      dr[i] = dir[i];
-    }
-    double y[MAX_DIM];
-    bool cin = valid;
-#pragma unroll
-    for (int i = 0; i < MAX_DIM; ++i) {
-      const double yi = fma(tt, dr[i], xr[i]);
-      const bool act = i < d;
-      y[i] = act ? yi : 0.0;
-      cin = cin && (!act || (yi >= 0.0 && yi <= 1.0));
-    }
-    if (!cin) {
-#pragma unroll
-      for (int i = 0; i < MAX_DIM; ++i) y[i] = 0.5;   // a harmless point; never evaluated
-    }
-    const unsigned long long m = __ballot(cin);
-    ProbeRec* rec = reinterpret_cast<ProbeRec*>(sP + cand * SL_PSTRIDE);
-    if (intrinsic_half) {
-      if (LK == LK_GAUSS) {
-        sG[cand] = gauss_lambda(M, y);
-      } else {
-        const int ka = probe_intrinsic(M, y, rec);
-        if constexpr (lk_full(LK)) {
-          // the prefix-table entries <h|h> needs, read here once rather than
-          // by every evaluating thread
-#pragma unroll
-          for (int dd = 0; dd < NDET; ++dd) rec->hk[dd] = ka > 0 ? V.hpre[(size_t)dd * V.hstride + ka - 1] : 0.0;
-        }
-      }
-      sT[cand] = tt;
-      if (lane == 0) sMask[cand >> 6] = m;
-    } else if (LK != LK_GAUSS) {
-      probe_extrinsic<NDET>(M, y, rec);
-    }
-  };
-  // After a batch's barrier every wave keeps the in-cube bits and the
-  // positions of the batch in registers; the walk then reads a candidate's
-  // with scalar operations instead of LDS round trips.
-  unsigned long long mk0 = 0, mk1 = 0;
-  double tr0 = 0.0, tr1 = 0.0;
-  auto load_batch = [&]() {
-    mk0 = sMask[0];
-    tr0 = sT[lane];
-    if constexpr (NC > 64) {
-      mk1 = sMask[1];
-      tr1 = sT[64 + lane];
-    }
-  };
-  auto inside = [&](int q) -> bool { return ((q < 64 ? mk0 : mk1) >> (q & 63)) & 1ull; };
-  auto ttq = [&](int q) -> double { return lane_d(q < 64 ? tr0 : tr1, q & 63); };
-  // lambda of batch candidate q (all threads; contains workgroup barriers)
-  auto eval = [&](int q) -> double {
-    ++nprobe;
-    if (LK == LK_GAUSS) return sG[q];
-    const Probe pb = probe_from_rec<NDET>(*reinterpret_cast<const ProbeRec*>(sP + q * SL_PSTRIDE), lk_full(LK));
-    double* rb = sred + buf * (NW + 4);
-    double tot;
-    if (lk_rb(LK)) tot = wave_sum(rb_partial<NDET, lk_mixed(LK)>(pb, RBv, M.n_bins, sr0, tid, NT));
-    else tot = wave_sum(fullgrid_partial<NDET, lk_mixed(LK), true>(pb, V, tid, NT));
-    if constexpr (NW > 1) {
-      if (lane == 0) rb[wv] = tot;
-      __syncthreads();
-      tot = 0.0;
-#pragma unroll
-      for (int w2 = 0; w2 < NW; ++w2) tot += rb[w2];
-      buf ^= 1;
-    } else if (lk_rb(LK)) {
-      __syncthreads();   // the edge ratios in LDS are rewritten by the next probe
-    }
-    // terms: the active bins (full grid) or the edges read (relative binning)
-    nbins += lk_full(LK) ? pb.k_act : rb_edges_read(RBv, pb.k_act, lane);
-    return lk_rb(LK) ? tot : tot - 0.5 * pb.hh;
-  };
-  // Full grid with two or more waves: lambdas of two candidates at once
-  // (q < 0: none), the first half of the workgroup summing the bins of q1,
-  // the second those of q2, one barrier for both.  Nothing is counted here:
-  // the walk counts the evaluations the sequential algorithm makes.
-  constexpr bool PAIR = (lk_full(LK) || lk_rb(LK)) && NW >= 2;
-  auto rec = [&](int q) -> const ProbeRec& { return *reinterpret_cast<const ProbeRec*>(sP + q * SL_PSTRIDE); };
-  auto count = [&](int terms) {   // the probe's active bins or relative-binning edges
-    ++nprobe;
-    nbins += terms;
-  };
-  auto eval2 = [&](int q1, int q2, double* l1, double* l2, int* k1, int* k2) {
-    if constexpr (PAIR) {
-      constexpr int HW = NW / 2;
-      const bool second = tid >= NT / 2;
-      const int q = second ? q2 : q1;
-      double* rb = sred + buf * (NW + 4);
-      double part = 0.0, hh = 0.0, kact = 0.0;
-      if constexpr (lk_rb(LK)) {
-        // both halves pass the barrier inside rb_partial
-        const Probe pb = q >= 0 ? probe_from_rec<NDET>(rec(q), false) : Probe{};
-        part = rb_partial<NDET, lk_mixed(LK)>(pb, RBv, M.n_bins, second ? sr1 : sr0, second ? tid - NT / 2 : tid, NT / 2,
-                                              q >= 0);
-      } else if (q >= 0) {
-        const Probe pb = probe_from_rec<NDET>(rec(q), true);
-        part = fullgrid_partial<NDET, lk_mixed(LK), true>(pb, V, second ? tid - NT / 2 : tid, NT / 2);
-        hh = pb.hh;
-        kact = (double)pb.k_act;
-      }
-      const double tot = wave_sum(part);
-      if (lane == 0) rb[wv] = tot;
-      if (lane == 0 && wv % HW == 0) {
-        rb[NW + (second ? 1 : 0)] = hh;
-        if constexpr (lk_full(LK)) rb[NW + 2 + (second ? 1 : 0)] = kact;
-      }
-      __syncthreads();
-      double t1 = 0.0, t2 = 0.0;
-#pragma unroll
-      for (int w2 = 0; w2 < HW; ++w2) {
-        t1 += rb[w2];
-        t2 += rb[HW + w2];
-      }
-      *l1 = t1 - 0.5 * rb[NW];
-      *l2 = t2 - 0.5 * rb[NW + 1];
-      if constexpr (lk_rb(LK)) {
-        // terms of a relative-binning probe: the edges it read
-        *k1 = q1 >= 0 ? rb_edges_read(RBv, rec(q1).k_act, lane) : 0;
-        *k2 = q2 >= 0 ? rb_edges_read(RBv, rec(q2).k_act, lane) : 0;
-      } else {
-        *k1 = (int)rb[NW + 2];
-        *k2 = (int)rb[NW + 3];
-      }
-      buf ^= 1;
-    }
-  };
-
-  for (int s0 = 0; s0 < R.m; s0 += SL_CHUNK) {
-    const int cs = (R.m - s0) < SL_CHUNK ? (R.m - s0) : SL_CHUNK;
-    // ---- draw the chunk: per step nbd direction blocks (two Box-Muller
-    // pairs each), the width block and two shrink blocks
-    __syncthreads();
-    const int per = nbd + 3;
-    for (int bI = tid; bI < cs * per; bI += NT) {
-      const int sl = bI / per, r = bI - sl * per;
-      const uint64_t s = (uint64_t)(s0 + sl);
-      uint64_t pw;
-      if (r < nbd) pw = purpose_word(P_DIR, (uint64_t)r);
-      else if (r == nbd) pw = purpose_word(P_WIDTH, 0);
-      else pw = purpose_word(P_SHRINK, (uint64_t)(r - nbd - 1));
-      const u64x4 b = philox(t, (uint64_t)j, s, pw, R.key0, R.key1);
-      const double u0 = unif53(b.x[0]), u1 = unif53(b.x[1]), u2 = unif53(b.x[2]), u3 = unif53(b.x[3]);
-      if (r < nbd) {
-        const double ra = sqrt(-2.0 * log(1.0 - u0));
-        const double2 ea = sincos_cycles(u1);
-        const double rb = sqrt(-2.0 * log(1.0 - u2));
-        const double2 eb = sincos_cycles(u3);
-        double* zr = sDir + sl * MAX_DIM + 4 * r;
-        if (4 * r + 0 < d) zr[0] = ra * ea.y;
-        if (4 * r + 1 < d) zr[1] = ra * ea.x;
-        if (4 * r + 2 < d) zr[2] = rb * eb.y;
-        if (4 * r + 3 < d) zr[3] = rb * eb.x;
-      } else if (r == nbd) {
-        sU[sl * SL_NU + 0] = u0;
-        sU[sl * SL_NU + 1] = u1;
-      } else {
-        double* ur = sU + sl * SL_NU + 2 + 4 * (r - nbd - 1);
-        ur[0] = u0; ur[1] = u1; ur[2] = u2; ur[3] = u3;
-      }
-    }
-    __syncthreads();
-    // directions L z / |z|, one thread per step (the thread owns the row)
-    for (int sl = tid; sl < cs; sl += NT) {
-      // whole rows are loaded (entries past d or past the diagonal are
-      // masked; every index stays below MAX_DIM^2), so each row's loads
-      // issue together
-      double z[MAX_DIM];
-#pragma unroll
-      for (int i = 0; i < MAX_DIM; ++i) z[i] = sDir[sl * MAX_DIM + i];
-#pragma unroll
-      for (int i = 0; i < MAX_DIM; ++i) z[i] = (i < d) ? z[i] : 0.0;
-      double nrm = 0.0;
-#pragma unroll
-      for (int i = 0; i < MAX_DIM; ++i)
-        if (i < d) nrm += z[i] * z[i];
-      nrm = sqrt(nrm);
-#pragma unroll
-      for (int a = 0; a < MAX_DIM; ++a) {
-        if (a < d) {
-          double lr[MAX_DIM];
-#pragma unroll
-          for (int b = 0; b < MAX_DIM; ++b) lr[b] = sL[a * d + b];
-          double acc = 0.0;
-#pragma unroll
-          for (int b = 0; b < MAX_DIM; ++b)
-            if (b <= a) acc += lr[b] * z[b];
-          sDir[sl * MAX_DIM + a] = acc / nrm;
-        }
-      }
-    }
-    __syncthreads();
-
-    for (int sl = 0; sl < cs; ++sl) {
-      const int s = s0 + sl;
-      const double* dir = sDir + sl * MAX_DIM;
-      const double* su = sU + sl * SL_NU;
-      double sur[SL_NU];             // this step's uniforms, in registers
-#pragma unroll
-      for (int i = 0; i < SL_NU; ++i) sur[i] = su[i];
-      double lo = -w * sur[0], hi = lo + w;
-      int J = (int)floor(R.max_stepout * sur[1]);
-      int K = R.max_stepout - 1 - J;
-
-      // ---- the combined batch
-      __syncthreads();
-      {
-        // both kinds of position are formed branch-free (x + (-w) is x - w
-        // exactly), and each lane keeps the one its slot needs
-        const bool so = cand < 2 * BL::SO;
-        const bool valid = cand < 2 * BL::SO + BL::H * BL::H * BL::SC;
-        // step-out point: `steps` whole widths beyond the initial bracket
-        const bool left = cand < BL::SO;
-        const int steps = left ? cand : cand - BL::SO;
-        const double ws = left ? -w : w;
-        double ts = left ? lo : hi;
-#pragma unroll
-        for (int q = 0; q < BL::SO - 1; ++q) ts = q < steps ? ts + ws : ts;
-        // shrink point: attempt c of bracket hypothesis h
-        const int hc = so ? 0 : cand - 2 * BL::SO;
-        const int h = hc / BL::SC, c = hc - BL::SC * h;
-        const int na = h / BL::H, nbh = h - BL::H * na;
-        double l2 = lo, h2 = hi;
-#pragma unroll
-        for (int q = 0; q < BL::H - 1; ++q) {
-          l2 = q < na ? l2 + (-w) : l2;
-          h2 = q < nbh ? h2 + w : h2;
-        }
-        double tsh = 0.0;
-#pragma unroll
-        for (int q = 0; q < BL::SC; ++q) {
-          if (q <= c) {
-            tsh = fma(sur[2 + q], h2 - l2, l2);
-            if (tsh < 0.0) l2 = tsh; else h2 = tsh;
-          }
-        }
-        const double tt = !valid ? 0.0 : (so ? ts : tsh);
-        setup(valid, tt, dir);
-      }
-      __syncthreads();
-      load_batch();
-      bool combined = true;        // the batch in LDS is the combined one
-
-      // ---- step out, left then right (the order of the sequential algorithm)
-      int na = 0, nh = 0;          // successful steps per side
-      int uL = 0, uR = 0;          // batch points of each side already walked
-      if constexpr (PAIR) {
-        // the two sides are independent: walk them together, one pair of
-        // probes per round, while their next points are in the batch; the
-        // probes evaluated are exactly those of the left-then-right walk
-        for (;;) {
-          int qL = (J > 0 && uL < BL::SO) ? uL : -1;
-          int qR = (K > 0 && uR < BL::SO) ? BL::SO + uR : -1;
-          if (qL >= 0 && !inside(qL)) { J = 0; qL = -1; }
-          if (qR >= 0 && !inside(qR)) { K = 0; qR = -1; }
-          if (qL < 0 && qR < 0) break;
-          double lL, lR;
-          int kL, kR;
-          eval2(qL, qR, &lL, &lR, &kL, &kR);
-          if (qL >= 0) {
-            count(kL);
-            if (lL > lstar) { lo -= w; --J; ++na; ++uL; } else { J = 0; }
-          }
-          if (qR >= 0) {
-            count(kR);
-            if (lR > lstar) { hi += w; --K; ++nh; ++uR; } else { K = 0; }
-          }
-        }
-      }
-      for (int side = 0; side < 2; ++side) {
-        int& budget = side == 0 ? J : K;
-        int& done_steps = side == 0 ? na : nh;
-        int first = side == 0 ? 0 : BL::SO;   // batch slot of this side's next candidate
-        int have = combined ? BL::SO : 0;     // candidates of this side in the batch in LDS
-        int used = combined ? (side == 0 ? uL : uR) : 0;
-        while (budget > 0) {
-          if (used == have) {
-            // further step-out points of this side: a batch of FB
-            __syncthreads();
-            double tt = side == 0 ? lo : hi;
-            if (cand < FB)
-              for (int q = 0; q < cand; ++q) tt = side == 0 ? tt - w : tt + w;
-            setup(cand < FB, tt, dir);
-            __syncthreads();
-            load_batch();
-            combined = false;
-            first = 0;
-            have = FB;
-            used = 0;
-          }
-          const int q = first + used;
-          if (!inside(q)) { budget = 0; break; }
-          if (!(eval(q) > lstar)) { budget = 0; break; }
-          if (side == 0) lo -= w; else hi += w;
-          --budget;
-          ++done_steps;
-          ++used;
-        }
-      }
-
-      // ---- shrink
-      int a = 0;                   // attempts made
-      bool accepted = false;
-      if (PAIR && combined && na < BL::H && nh < BL::H) {
-        // attempts a and a+1 together (a+1 under the hypothesis that a is
-        // rejected); a probe is counted only where the sequential walk makes it
-        const int base = 2 * BL::SO + BL::SC * (BL::H * na + nh);
-        while (a < BL::SC && a < R.max_shrink) {
-          const int q1 = base + a;
-          const bool two = a + 1 < BL::SC && a + 1 < R.max_shrink;
-          const int q2 = two ? q1 + 1 : -1;
-          const bool in1 = inside(q1), in2 = two && inside(q2);
-          double l1 = NEG_INF, l2 = NEG_INF;
-          int k1 = 0, k2 = 0;
-          if (in1 || in2) eval2(in1 ? q1 : -1, in2 ? q2 : -1, &l1, &l2, &k1, &k2);
-          const double t1 = ttq(q1);
-          if (in1) {
-            count(k1);
-            if (l1 > lstar) {
-              if (tid < d) sX[tid] = fma(t1, dir[tid], sX[tid]);
-              lx = l1;
-              accepted = true;
-              break;
-            }
-          }
-          if (t1 < 0.0) lo = t1; else hi = t1;
-          ++a;
-          if (!two) continue;
-          const double t2 = ttq(q2);
-          if (in2) {
-            count(k2);
-            if (l2 > lstar) {
-              if (tid < d) sX[tid] = fma(t2, dir[tid], sX[tid]);
-              lx = l2;
-              accepted = true;
-              break;
-            }
-          }
-          if (t2 < 0.0) lo = t2; else hi = t2;
-          ++a;
-        }
-      } else if (combined && na < BL::H && nh < BL::H) {
-        const int base = 2 * BL::SO + BL::SC * (BL::H * na + nh);
-        for (; a < BL::SC && a < R.max_shrink; ++a) {
-          const int q = base + a;
-          const double tt = ttq(q);
-          if (inside(q)) {
-            const double ly = eval(q);
-            if (ly > lstar) {
-              if (tid < d) sX[tid] = fma(tt, dir[tid], sX[tid]);
-              lx = ly;
-              accepted = true;
-              break;
-            }
-          }
-          if (tt < 0.0) lo = tt; else hi = tt;
-        }
-      }
-      while (!accepted && a < R.max_shrink) {
-        // a batch of FB shrink candidates from the current bracket: the
-        // uniforms of attempts a .. a+FB-1 are drawn lane-parallel, then the
-        // bracket recursion under rejection is walked once
-        __syncthreads();
-        if (tid < FB) {
-          const int aa = a + tid;
-          double ua;
-          if (aa < 8) {
-            ua = su[2 + aa];
-          } else {
-            const u64x4 b = philox(t, (uint64_t)j, (uint64_t)s, purpose_word(P_SHRINK, (uint64_t)(aa >> 2)),
-                                   R.key0, R.key1);
-            const int ws = aa & 3;
-            ua = unif53(ws == 0 ? b.x[0] : ws == 1 ? b.x[1] : ws == 2 ? b.x[2] : b.x[3]);
-          }
-          sG[tid] = ua;
-        }
-        __syncthreads();
-        {
-          double l2 = lo, h2 = hi, tl = 0.0;
-          for (int q = 0; q < FB; ++q) {
-            const double tq = fma(sG[q], h2 - l2, l2);
-            if (q == cand) tl = tq;
-            if (tq < 0.0) l2 = tq; else h2 = tq;
-          }
-          __syncthreads();   // sG is reused by the Gaussian test likelihood
-          setup(cand < FB, tl, dir);
-        }
-        __syncthreads();
-        load_batch();
-        for (int q = 0; q < FB && a < R.max_shrink; ++q, ++a) {
-          const double tt = ttq(q);
-          if (inside(q)) {
-            const double ly = eval(q);
-            if (ly > lstar) {
-              if (tid < d) sX[tid] = fma(tt, dir[tid], sX[tid]);
-              lx = ly;
-              accepted = true;
-              ++a;
-              break;
-            }
-          }
-          if (tt < 0.0) lo = tt; else hi = tt;
-        }
-      }
-    }
-  }
-  __syncthreads();
-  const int slot = R.dead[j];
-  for (int i = tid; i < d; i += NT) R.u[(size_t)slot * d + i] = sX[i];
-  if (tid == 0) {
-    R.lam[slot] = lx;
-    R.probes[j] = nprobe;
-    R.bins[j] = nbins;
-  }
-}
-
-template <int NDET, int NT, int LK, bool LDS>
-__global__ __launch_bounds__(NT, 2) void k_slice(const ModelDev* __restrict__ Mp, Tables T, RBTables RB, RunDev R) {
-  extern __shared__ double smem[];
-  slice_body<NDET, NT, LK, LDS>(*Mp, T, RB, R, blockIdx.x, smem);
-}
-
-
-// ------------------------------------------------------------- termination
-__device__ void term_body(const RunDev& R) {
-  __shared__ double sbuf[1024];
-  DevState* S = R.state;
-  if (S->done) return;
-  const int n = R.n, tid = threadIdx.x;
-  double m = NEG_INF;
-  for (int i = tid; i < n; i += 1024) m = fmax(m, order_value(R.lam[i]));
-  m = block_max<1024>(m, sbuf);
-  double v[3] = {0.0, 0.0, 0.0};   // sum exp(lambda - max), probes, bins
-  for (int i = tid; i < n; i += 1024) v[0] += exp(order_value(R.lam[i]) - m);
-  for (int j = tid; j < R.k; j += 1024) {
-    v[1] += (double)R.probes[j];
-    v[2] += (double)R.bins[j];
-  }
-  block_sum_k<1024, 3>(v, sbuf);
-  const double s = v[0], pe = v[1], pb = v[2];
-  if (tid == 0) {
-    const double logz_live = S->logX + m + log(s / n);
-    int done = 0;
-    if (R.log_term > NEG_INF && logz_live - S->logZ < R.log_term) done = 1;
-    if (S->n_dead + R.k > R.cap) done = 2;
-    S->n_evals += (long long)pe;
-    S->n_bin_terms += (long long)pb;
-    S->iter += 1;
-    S->done = done;
-  }
-}
-
-__global__ __launch_bounds__(1024) void k_term(RunDev R) { term_body(R); }
-
-
-// ---------------------------------------------------------------- packed
-// Serving: one launch per kernel covers every resident run.  Blocks are
-// assigned to runs by prefix offsets (off[r] = first block of run r).
-__device__ inline int packed_run_of(const int* __restrict__ off, int nr, int b) {
-  int lo = 0, hi = nr - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (off[mid] <= b) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
-}
-
-__global__ __launch_bounds__(256) void k_rank_packed(const PackedRun* __restrict__ runs,
-                                                     const int* __restrict__ off, int nr) {
-  const int r = packed_run_of(off, nr, blockIdx.x);
-  const RunDev& R = runs[r].R;
-  if (R.state->done) return;
-  const int i = (blockIdx.x - off[r]) * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-  if (i >= R.n) return;
-  rank_element(R.lam, R.n, R.k, R.rank, R.dead, nullptr, i, lane);
-}
-
-__global__ __launch_bounds__(1024) void k_prep_packed(const PackedRun* __restrict__ runs) {
-  prep_body(runs[blockIdx.x].R);
-}
-
-__global__ __launch_bounds__(1024) void k_term_packed(const PackedRun* __restrict__ runs) {
-  term_body(runs[blockIdx.x].R);
-}
-
-template <int NT, int LK>
-__global__ __launch_bounds__(NT, 2) void k_slice_packed(const PackedRun* __restrict__ runs, const int* __restrict__ off,
-                                                     int nr) {
-  extern __shared__ double smem[];
-  const int r = packed_run_of(off, nr, blockIdx.x);
-  const PackedRun& P = runs[r];
-  const int j = blockIdx.x - off[r];
-  switch (P.M->n_det) {
-    case 1: slice_body<1, NT, LK, false>(*P.M, P.T, P.RB, P.R, j, smem); break;
-    case 2: slice_body<2, NT, LK, false>(*P.M, P.T, P.RB, P.R, j, smem); break;
-    default: slice_body<3, NT, LK, false>(*P.M, P.T, P.RB, P.R, j, smem); break;
-  }
-}
-
-__global__ void k_gather_done(const PackedRun* __restrict__ runs, int nr, int* out) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r < nr) out[r] = runs[r].R.state->done;
-}
-
-// ---------------------------------------------------------------- waveform
-__global__ void k_waveform(const ModelDev* __restrict__ Mp, const double* theta, int det, int apply_cut, double* hre,
-                           double* him) {
-  const ModelDev& M = *Mp;
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= M.n_bins) return;
-  Phys s;
-  phys_from_theta(M, theta, &s);
-  Probe p;
-  probe_from_phys(M, s, nullptr, &p);
-  const double f = fma((double)k, M.df, M.f_lo);
-  if (apply_cut && k >= p.k_act) {
-    hre[k] = 0.0;
-    him[k] = 0.0;
-    return;
-  }
-  const double lf = log(f);
-  const double psi = phase_cycles(p, f, cbrt(f), lf / 3.0, exp(-5.0 / 3.0 * lf));
-  const double2 sc_ = sincos_cycles(fma(f, p.dt[det], psi));
-  const double sn = sc_.x, cs = sc_.y;
-  const double a = exp(-7.0 / 6.0 * lf);
-  // h = A K f^(-7/6) e^{-i Phi}
-  hre[k] = a * (p.kre[det] * cs + p.kim[det] * sn);
-  him[k] = a * (p.kim[det] * cs - p.kre[det] * sn);
-}
-
-// ------------------------------------------------------------- finalisation
-// Block 0: the final evidence (each live point takes X_end / n), the
-// information H and the Kish effective sample size.  Block r >= 1: replica
-// r-1 of log Z with every log-shrinkage redrawn, log t = log U / n_j.
-// out: [0] log Z, [1] H, [2] ESS, [3 + r] replica log Z.
-__global__ __launch_bounds__(1024) void k_final(RunDev R, int n_sim, double* out) {
-  __shared__ double sbuf[1024];
-  const DevState* S = R.state;
-  const long long nd = S->n_dead;
-  const int n = R.n, tid = threadIdx.x;
-  const double logn = log((double)n);
-  double m = NEG_INF;
-  for (int i = tid; i < n; i += 1024) m = fmax(m, order_value(R.lam[i]));
-  m = block_max<1024>(m, sbuf);
-  if (blockIdx.x == 0) {
-    double s = 0.0;
-    if (m > NEG_INF)
-      for (int i = tid; i < n; i += 1024) s += exp(order_value(R.lam[i]) - m);
-    s = block_sum<1024>(s, sbuf);
-    const double zl = (m > NEG_INF) ? S->logX + m + log(s) - logn : NEG_INF;
-    double logZ = S->logZ;
-    if (zl > NEG_INF) logZ = (logZ > NEG_INF) ? fmax(logZ, zl) + log1p(exp(-fabs(logZ - zl))) : zl;
-    double h = 0.0, p2 = 0.0;
-    for (long long q = tid; q < nd; q += 1024) {
-      const double lw = R.dlogw[q];
-      if (lw > NEG_INF) {
-        const double pq = exp(lw - logZ);
-        h += pq * order_value(R.dlam[q]);
-        p2 += pq * pq;
-      }
-    }
-    for (int i = tid; i < n; i += 1024) {
-      const double l = order_value(R.lam[i]);
-      if (l > NEG_INF) {
-        const double pq = exp(l + S->logX - logn - logZ);
-        h += pq * l;
-        p2 += pq * pq;
-      }
-    }
-    h = block_sum<1024>(h, sbuf);
-    p2 = block_sum<1024>(p2, sbuf);
-    if (tid == 0) {
-      out[0] = logZ;
-      out[1] = h - logZ;
-      out[2] = 1.0 / p2;
-    }
-    return;
-  }
-  const uint64_t rep = (uint64_t)(blockIdx.x - 1);
-  const long long C = (nd + 1023) / 1024;
-  const long long qb = (long long)tid * C, qe = (qb + C < nd) ? qb + C : nd;
-  auto logt = [&](long long q) {
-    u64x4 b = philox(rep, (uint64_t)q, 0, purpose_word(P_SIGMA, 0), R.key0, R.key1);
-    return log(1.0 - unif53(b.x[0])) / (double)R.dnlive[q];
-  };
-  double cs = 0.0;
-  for (long long q = qb; q < qe; ++q) cs += logt(q);
-  __shared__ double sscan[1024];
-  const double incl = block_inclusive_scan<1024, double>(cs, sscan);
-  double lx = incl - cs;
-  double mloc = NEG_INF;
-  for (long long q = qb; q < qe; ++q) {
-    const double lt = logt(q);
-    const double lw = order_value(R.dlam[q]) + lx + log(-expm1(lt));
-    mloc = fmax(mloc, lw);
-    lx += lt;
-  }
-  const double lxend = block_sum<1024>(cs, sbuf);
-  double mm = block_max<1024>(mloc, sbuf);
-  const double live_top = (m > NEG_INF) ? m + lxend - logn : NEG_INF;
-  mm = fmax(mm, live_top);
-  double s = 0.0;
-  lx = incl - cs;
-  for (long long q = qb; q < qe; ++q) {
-    const double lt = logt(q);
-    const double lw = order_value(R.dlam[q]) + lx + log(-expm1(lt));
-    if (lw > NEG_INF) s += exp(lw - mm);
-    lx += lt;
-  }
-  for (int i = tid; i < n; i += 1024) {
-    const double l = order_value(R.lam[i]);
-    if (l > NEG_INF) s += exp(l + lxend - logn - mm);
-  }
-  s = block_sum<1024>(s, sbuf);
-  if (tid == 0) out[3 + rep] = mm + log(s);
-}
-
-// Weighted samples: dead points then live points, physical parameters and
-// log-weights normalised by the final log Z.
-__global__ void k_samples(const ModelDev* __restrict__ Mp, RunDev R, double logZ, double* theta, double* logl,
-                          double* logw) {
-  const ModelDev& M = *Mp;
-  const long long nd = R.state->n_dead;
-  const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= nd + R.n) return;
-  const int d = R.d;
-  const double* u;
-  double l, lw;
-  if (q < nd) {
-    u = R.du + q * d;
-    l = R.dlam[q];
-    lw = R.dlogw[q] - logZ;
-  } else {
-    const int i = (int)(q - nd);
-    u = R.u + (size_t)i * d;
-    l = R.lam[i];
-    lw = order_value(l) + R.state->logX - log((double)R.n) - logZ;
-  }
-  if (theta) {
-    for (int i = 0; i < d; ++i)
-      theta[q * d + i] = (M.likelihood == LK_GAUSS) ? u[i] : prior_plain(M.prior, i, u[i]);
-  }
-  if (logl) logl[q] = l;
-  if (logw) logw[q] = lw;
-}
-
-// Equal-weight samples by systematic resampling (the equal-weight count of
-// the paper's results table, Section 3).  Pass 1, one workgroup: the
-// normalised weights p_q = exp(log w_q - log Z) of the weighted samples (dead
-// points in death order, then the live points), their running sum cum[q]
-// (each thread sums a contiguous chunk, the chunk totals are scanned across
-// the workgroup), and the one uniform u0 of the RESAMPLE purpose.
-__global__ __launch_bounds__(1024) void k_resample_cum(RunDev R, long long total, double logZ, double* cum,
-                                                       double* u0) {
-  __shared__ double sscan[1024];
-  const long long nd = R.state->n_dead;
-  const int tid = threadIdx.x;
-  const double live_lw = R.state->logX - log((double)R.n) - logZ;
-  const long long C = (total + 1023) / 1024;
-  const long long qb = (long long)tid * C, qe = (qb + C < total) ? qb + C : total;
-  auto weight = [&](long long q) {
-    const double lw = q < nd ? R.dlogw[q] - logZ : order_value(R.lam[q - nd]) + live_lw;
-    return exp(lw);
-  };
-  double cs = 0.0;
-  for (long long q = qb; q < qe; ++q) cs += weight(q);
-  double acc = block_inclusive_scan<1024, double>(cs, sscan) - cs;
-  for (long long q = qb; q < qe; ++q) {
-    acc += weight(q);
-    cum[q] = acc;
-  }
-  if (tid == 0) {
-    const u64x4 b = philox(0, 0, 0, purpose_word(P_RESAMPLE, 0), R.key0, R.key1);
-    u0[0] = unif53(b.x[0]);
-  }
-}
-
-// Pass 2, one thread per output m: the position (m + u0) / n_out of the total
-// weight and the first sample whose running sum exceeds it (binary search;
-// the last sample if none does, which only rounding can cause).
-__global__ void k_resample_pick(const ModelDev* __restrict__ Mp, RunDev R, long long total, const double* cum,
-                                const double* u0, long long n_out, int* idx, double* theta) {
-  const ModelDev& M = *Mp;
-  const long long m = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= n_out) return;
-  const double pos = ((double)m + u0[0]) / (double)n_out * cum[total - 1];
-  long long lo = 0, hi = total - 1;   // the answer lies in [lo, hi]
-  while (lo < hi) {
-    const long long mid = lo + (hi - lo) / 2;
-    if (cum[mid] > pos) hi = mid; else lo = mid + 1;
-  }
-  idx[m] = (int)lo;
-  if (theta) {
-    const long long nd = R.state->n_dead;
-    const int d = R.d;
-    const double* u = lo < nd ? R.du + lo * d : R.u + (size_t)(lo - nd) * d;
-    for (int i = 0; i < d; ++i)
-      theta[m * d + i] = (M.likelihood == LK_GAUSS) ? u[i] : prior_plain(M.prior, i, u[i]);
-  }
-}
-
-template <int NDET, int LK, bool LDS>
-hipError_t launch_loglike_t(const ModelDev& M, const ModelDev* Md, const Tables& T, const RBTables& RB,
-                            const double* u, long n, double* out, int* terms, Probe* pbuf, hipStream_t st) {
-  if (n <= 0) return hipSuccess;
-  if (LK != LK_GAUSS && pbuf) {
-    hipLaunchKernelGGL(k_probe_setup, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, Md, T.hpre, u, n, pbuf,
-                       terms);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    const size_t lds = LDS ? staged_table_bytes(M.k_lim, NDET, lk_mixed(LK)) : 0;
-    long blocks = (n + 15) / 16;
-    if (blocks > 256 * 2) blocks = 256 * 2;
-    hipLaunchKernelGGL((k_probe_bins<NDET, LK, LDS>), dim3((unsigned)blocks), dim3(1024), lds, st, Md, T, pbuf, n,
-                       out);
-    return hipGetLastError();
-  }
-  const size_t lds = LDS ? staged_table_bytes(M.k_lim, NDET, lk_mixed(LK)) : 0;
-  long blocks = (n + 255) / 256;
-  if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL((k_loglike<NDET, LK, LDS>), dim3((unsigned)blocks), dim3(256), lds, st, Md, T, RB, u, n, out,
-                     terms);
-  return hipGetLastError();
-}
-
-template <int NDET, int NT, int LK, bool LDS>
-hipError_t launch_slice_t(const ModelDev* Md, const Tables& T, const RBTables& RB, const RunDev& R, size_t lds,
-                          hipStream_t st) {
-  hipLaunchKernelGGL((k_slice<NDET, NT, LK, LDS>), dim3(R.k), dim3(NT), lds, st, Md, T, RB, R);
-  return hipGetLastError();
-}
-
-template <int NDET, int NT>
-hipError_t launch_slice_nt(const ModelDev& M, const ModelDev* Md, const Tables& T, const RBTables& RB,
-                           const RunDev& R, const LaunchCfg& C, hipStream_t st) {
-  if (M.likelihood == LK_RB) {
-    if (M.mixed)
-      return C.lds_tables ? launch_slice_t<NDET, NT, LK_RB32, true>(Md, T, RB, R, C.lds_bytes, st)
-                          : launch_slice_t<NDET, NT, LK_RB32, false>(Md, T, RB, R, C.lds_bytes, st);
-    return C.lds_tables ? launch_slice_t<NDET, NT, LK_RB, true>(Md, T, RB, R, C.lds_bytes, st)
-                        : launch_slice_t<NDET, NT, LK_RB, false>(Md, T, RB, R, C.lds_bytes, st);
-  }
-  if (M.mixed) {
-    if (C.lds_tables) return launch_slice_t<NDET, NT, LK_FULL32, true>(Md, T, RB, R, C.lds_bytes, st);
-    return launch_slice_t<NDET, NT, LK_FULL32, false>(Md, T, RB, R, C.lds_bytes, st);
-  }
-  if (C.lds_tables) return launch_slice_t<NDET, NT, LK_FULL, true>(Md, T, RB, R, C.lds_bytes, st);
-  return launch_slice_t<NDET, NT, LK_FULL, false>(Md, T, RB, R, C.lds_bytes, st);
-}
-
-template <int NDET>
-hipError_t launch_slice_det(const ModelDev& M, const ModelDev* Md, const Tables& T, const RBTables& RB,
-                            const RunDev& R, const LaunchCfg& C, hipStream_t st) {
-  switch (C.slice_threads) {
-    case 64: return launch_slice_nt<NDET, 64>(M, Md, T, RB, R, C, st);
-    case 128: return launch_slice_nt<NDET, 128>(M, Md, T, RB, R, C, st);
-    default: return launch_slice_nt<NDET, 256>(M, Md, T, RB, R, C, st);
-  }
-}
-
-size_t slice_lds_fixed(int nt) { return slice_fixed_doubles(nt) * sizeof(double); }
-
-}  // namespace
 
 int likelihood_kind(const ModelDev& M) { return M.likelihood; }
 
@@ -2181,9 +186,9 @@ hipError_t launch_iteration(const ModelDev& M, const ModelDev* Md, const Tables&
     e = launch_slice_t<1, 64, LK_GAUSS, false>(Md, T, RB, R, C.lds_bytes, st);
   } else {
     switch (M.n_det) {
-      case 1: e = launch_slice_det<1>(M, Md, T, RB, R, C, st); break;
-      case 2: e = launch_slice_det<2>(M, Md, T, RB, R, C, st); break;
-      default: e = launch_slice_det<3>(M, Md, T, RB, R, C, st); break;
+      case 1: e = launch_slice_d1(M, Md, T, RB, R, C, st); break;
+      case 2: e = launch_slice_d2(M, Md, T, RB, R, C, st); break;
+      default: e = launch_slice_d3(M, Md, T, RB, R, C, st); break;
     }
   }
   if (e != hipSuccess) return e;
@@ -2209,29 +214,6 @@ hipError_t configure_slice_packed(const ModelDev& M, int rb_nb, LaunchCfg* C) {
   return hipSuccess;
 }
 
-namespace {
-template <int NT>
-hipError_t launch_slice_packed_nt(const PackedRun* runs, const int* slice_off, int nr, int slice_blocks, int lk,
-                                  size_t slice_lds, hipStream_t st) {
-  switch (lk) {
-    case LK_FULL:
-      hipLaunchKernelGGL((k_slice_packed<NT, LK_FULL>), dim3(slice_blocks), dim3(NT), slice_lds, st, runs, slice_off, nr);
-      break;
-    case LK_FULL32:
-      hipLaunchKernelGGL((k_slice_packed<NT, LK_FULL32>), dim3(slice_blocks), dim3(NT), slice_lds, st, runs, slice_off,
-                         nr);
-      break;
-    case LK_RB:
-      hipLaunchKernelGGL((k_slice_packed<NT, LK_RB>), dim3(slice_blocks), dim3(NT), slice_lds, st, runs, slice_off, nr);
-      break;
-    default:
-      hipLaunchKernelGGL((k_slice_packed<NT, LK_RB32>), dim3(slice_blocks), dim3(NT), slice_lds, st, runs, slice_off,
-                         nr);
-      break;
-  }
-  return hipGetLastError();
-}
-}  // namespace
 
 hipError_t launch_iteration_packed(const PackedRun* runs, const int* rank_off, const int* slice_off, int nr,
                                    int rank_blocks, int slice_blocks, int lk, int nt, size_t slice_lds,
@@ -2243,9 +225,9 @@ hipError_t launch_iteration_packed(const PackedRun* runs, const int* rank_off, c
   hipLaunchKernelGGL(k_prep_packed, dim3(nr), dim3(1024), 0, st, runs);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   switch (nt) {
-    case 64: e = launch_slice_packed_nt<64>(runs, slice_off, nr, slice_blocks, lk, slice_lds, st); break;
-    case 128: e = launch_slice_packed_nt<128>(runs, slice_off, nr, slice_blocks, lk, slice_lds, st); break;
-    default: e = launch_slice_packed_nt<256>(runs, slice_off, nr, slice_blocks, lk, slice_lds, st); break;
+    case 64: e = launch_slice_packed64(runs, slice_off, nr, slice_blocks, lk, slice_lds, st); break;
+    case 128: e = launch_slice_packed128(runs, slice_off, nr, slice_blocks, lk, slice_lds, st); break;
+    default: e = launch_slice_packed256(runs, slice_off, nr, slice_blocks, lk, slice_lds, st); break;
   }
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_term_packed, dim3(nr), dim3(1024), 0, st, runs);
