@@ -215,16 +215,6 @@ int run_create(ns_run** out, const ns_problem* P, const ns_opts* O, hipStream_t 
   r->M = M;
   r->st = stream;
   r->packed = packed;
-  {
-    // the device's no-allocation scratch is looked up once, at set-up
-    Probe* scratch_addr = nullptr;
-    hipError_t e = hipGetDevice(&r->device);
-    if (e == hipSuccess) e = noalloc_probe_scratch(r->device, &scratch_addr);
-    if (e != hipSuccess) {
-      delete r;
-      return fail(NS_E_HIP, "device set-up: %s", hipGetErrorString(e));
-    }
-  }
   const int n = O->n_live, k = O->n_delete, d = P->n_dim;
   RunDev& R = r->R;
   R.n = n; R.k = k; R.d = d; R.m = O->n_steps;
@@ -367,6 +357,12 @@ int run_create(ns_run** out, const ns_problem* P, const ns_opts* O, hipStream_t 
   if (e == hipSuccess) e = launch_loglike(r->M, r->Md, r->T, r->RB, R.u, n, R.lam, nullptr, nullptr, r->st);
   if (e == hipSuccess) e = hipStreamSynchronize(r->st);
   if (e != hipSuccess) return cleanup(fail(NS_E_HIP, "initial population: %s", hipGetErrorString(e)));
+  // the device of the run and its no-allocation scratch, looked up once per
+  // device (the runtime is initialised by now)
+  Probe* scratch_addr = nullptr;
+  e = hipGetDevice(&r->device);
+  if (e == hipSuccess) e = noalloc_probe_scratch(r->device, &scratch_addr);
+  if (e != hipSuccess) return cleanup(fail(NS_E_HIP, "device set-up: %s", hipGetErrorString(e)));
   *out = r;
   return NS_OK;
 }

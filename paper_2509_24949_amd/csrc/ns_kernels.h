@@ -626,105 +626,105 @@ __device__ inline RBTables stage_rb(const RBTables& B, double* lds, int tid, int
   return V;
 }
 
-// This thread's share of a relative-binning likelihood; lds holds the edge
-// ratios of the probe.  Every thread of the workgroup calls it (it contains a
-// barrier); an inactive caller only takes part in the barrier.  WAVE: the
-// probe belongs to one wavefront, which synchronises on its own.
-// Edges relative binning reads for a probe with k_act active grid bins: those
-// of its active coarse bins (bin b is active iff edge[b] < k_act), one more
-// than the bins, or none if bin 0 is inactive.  Counted with ballots over
-// the wavefront (every lane must take part); the result is uniform.
-__device__ inline int rb_edges_read(const RBTables& B, int k_act, int lane) {
+// Coarse bins a probe with k_act active grid bins reads: the bins b < nb
+// whose first fine bin edge[b] lies below k_act.  Edges increase, so a
+// ballot over the wavefront counts them 64 at a time and stops at the first
+// incomplete group (every lane takes part; the result is uniform).
+__device__ inline int rb_active_bins(const RBTables& B, int k_act, int lane) {
   int n_act = 0;
   for (int b0 = 0; b0 < B.nb; b0 += 64) {
     const int b = b0 + lane;
-    n_act += __popcll(__ballot(b < B.nb && B.edge[b] < k_act));
+    const int c = __popcll(__ballot(b < B.nb && B.edge[b] < k_act));
+    n_act += c;
+    if (c < 64) break;
   }
-  return n_act > 0 ? n_act + 1 : 0;
+  return n_act;
 }
 
-template <int NDET, bool MX, bool WAVE = false>
-__device__ inline double rb_partial(const Probe& p, const RBTables& B, int n_bins, void* lds, int tid, int nt,
-                                    bool active = true) {
-  using CT = typename std::conditional<MX, float2, double2>::type;
-  CT* sr = reinterpret_cast<CT*>(lds);
-  const int nb = B.nb;
-  for (int e = active ? tid : nb + 1; e <= nb; e += nt) {
-    // edge e bounds bins e - 1 and e; with increasing edges it is read only
-    // if bin e - 1 (bin 0 for e = 0) starts below the active-bin count
-    if (B.edge[e > 0 ? e - 1 : 0] >= p.k_act) continue;
-    const double f = B.fe[e];
-    const double psi = phase_cycles(p, f, B.fe13[e], B.lnfe3[e], B.fem53[e]);
-#pragma unroll
-    for (int d = 0; d < NDET; ++d) {
-      const double dph = fma(f, p.dt[d], psi) - B.phi0[d * (nb + 1) + e];
-      const double2 g = B.g0[d];
-      const double gr = p.kre[d] * g.x - p.kim[d] * g.y, gi = p.kre[d] * g.y + p.kim[d] * g.x;
-      if constexpr (MX) {
-        const float2 sc = sincos_cycles_f32((float)(dph - rint(dph)));
-        const float fr = (float)gr, fi = (float)gi;
-        sr[d * (nb + 1) + e] = make_float2(fmaf(fr, sc.y, fi * sc.x), fmaf(fi, sc.y, -fr * sc.x));
-      } else {
-        const double2 sc = sincos_cycles(dph);
-        sr[d * (nb + 1) + e] = make_double2(gr * sc.y + gi * sc.x, gi * sc.y - gr * sc.x);
-      }
-    }
-  }
-  if constexpr (WAVE) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  } else {
-    __syncthreads();
-  }
+// Relative-binning likelihood of one probe, evaluated by one wavefront
+// (every lane calls it; the result is uniform).  With n_act active coarse
+// bins the probe reads edges 0 .. n_act.  They are taken in chunks of 63
+// bins: lane l computes the ratio r_d(e) = h(e) / h0(e)
+// = A K_d / (A0 K0_d) e^{-2 pi i (Phi_d(e) - Phi0_d(e))} at edge e = c0 + l for
+// every detector, receives r_d(e + 1) from lane l + 1, and (l < 63) adds
+// coarse bin b = e:  r0 = (r_b + r_{b+1}) / 2, r1 = (r_{b+1} - r_b) / (f_{b+1} - f_b),
+// Re(A0 r0 + A1 r1) - 1/2 [B0 |r0|^2 + 2 B1 Re(conj(r0) r1)].  The bin that
+// straddles f_ISCO (its last fine bin at or above k_act) uses the sums
+// accumulated up to fine bin k_act - 1, loaded before the edge arithmetic.
+// *n_edges receives the edges read (n_act + 1, or 0 when no bin is active).
+template <int NDET, bool MX>
+__device__ inline double rb_wave(const Probe& p, const RBTables& B, int n_bins, int lane, int* n_edges) {
+  using RT = typename std::conditional<MX, float, double>::type;
+  const int nb = B.nb, ne = nb + 1;
+  const int n_act = rb_active_bins(B, p.k_act, lane);
+  *n_edges = n_act > 0 ? n_act + 1 : 0;
+  if (n_act == 0) return 0.0;
+  const int sb = n_act - 1;
+  const int sb_last = (sb < nb - 1) ? B.edge[sb + 1] - 1 : B.edge[nb];
+  const bool straddle = sb_last >= p.k_act;
   double part = 0.0;
-  for (int b = active ? tid : nb; b < nb; b += nt) {
-    const int first = B.edge[b];
-    if (first >= p.k_act) continue;
-    const int last = (b < nb - 1) ? B.edge[b + 1] - 1 : B.edge[nb];
-    const bool full = last < p.k_act;
+  for (int c0 = 0; c0 < n_act; c0 += 63) {
+    const int e = c0 + lane;
+    const bool has_edge = e <= n_act;
+    const bool has_bin = lane < 63 && e < n_act;
+    const bool cum = straddle && has_bin && e == sb;
+    // the phase at this lane's edge, shared by the detectors
+    double f = 0.0, psi = 0.0;
+    if (has_edge) {
+      f = B.fe[e];
+      psi = phase_cycles(p, f, B.fe13[e], B.lnfe3[e], B.fem53[e]);
+    }
+    const RT iw = has_bin ? (RT)B.inv_w[e] : (RT)0;
 #pragma unroll
     for (int d = 0; d < NDET; ++d) {
-      if constexpr (MX) {
-        float2 a0, a1;
-        float b0, b1;
-        if (full) {
-          const size_t q = (size_t)d * nb + b;
-          a0 = B.A0f[q]; a1 = B.A1f[q]; b0 = B.B0f[q]; b1 = B.B1f[q];
+      // ratio at this lane's edge ...
+      RT rr = (RT)0, ri = (RT)0;
+      if (has_edge) {
+        const double2 g = B.g0[d];
+        const double gr = p.kre[d] * g.x - p.kim[d] * g.y, gi = p.kre[d] * g.y + p.kim[d] * g.x;
+        const double dph = fma(f, p.dt[d], psi) - B.phi0[d * ne + e];
+        if constexpr (MX) {
+          const float2 sc = sincos_cycles_f32((float)(dph - rint(dph)));
+          const float fr = (float)gr, fi = (float)gi;
+          rr = fmaf(fr, sc.y, fi * sc.x);
+          ri = fmaf(fi, sc.y, -fr * sc.x);
         } else {
-          const size_t q = (size_t)d * n_bins + p.k_act - 1;
-          a0 = make_float2((float)B.cA0[q].x, (float)B.cA0[q].y);
-          a1 = make_float2((float)B.cA1[q].x, (float)B.cA1[q].y);
-          b0 = (float)B.cB0[q]; b1 = (float)B.cB1[q];
+          const double2 sc = sincos_cycles(dph);
+          rr = gr * sc.y + gi * sc.x;
+          ri = gi * sc.y - gr * sc.x;
         }
-        const float iw = (float)B.inv_w[b];
-        const float2 ra = sr[d * (nb + 1) + b], rb = sr[d * (nb + 1) + b + 1];
-        const float r0r = 0.5f * (ra.x + rb.x), r0i = 0.5f * (ra.y + rb.y);
-        const float r1r = (rb.x - ra.x) * iw, r1i = (rb.y - ra.y) * iw;
-        const float dh = (a0.x * r0r - a0.y * r0i) + (a1.x * r1r - a1.y * r1i);
-        const float hh = b0 * (r0r * r0r + r0i * r0i) + 2.0f * b1 * (r0r * r1r + r0i * r1i);
-        part += (double)(dh - 0.5f * hh);
-      } else {
-        double2 a0, a1;
-        double b0, b1;
-        if (full) {
-          const size_t q = (size_t)d * nb + b;
-          a0 = B.A0[q]; a1 = B.A1[q]; b0 = B.B0[q]; b1 = B.B1[q];
+      }
+      // ... and at the next edge, from the next lane
+      const RT nr = __shfl_down(rr, 1), ni = __shfl_down(ri, 1);
+      if (has_bin) {
+        RT a0r, a0i, a1r, a1i, b0, b1;
+        if (cum) {
+          // the straddling bin: the sums up to its last active fine bin
+          const size_t q = (size_t)d * n_bins + p.k_act - 1;
+          const double2 a0 = B.cA0[q], a1 = B.cA1[q];
+          a0r = (RT)a0.x; a0i = (RT)a0.y; a1r = (RT)a1.x; a1i = (RT)a1.y;
+          b0 = (RT)B.cB0[q]; b1 = (RT)B.cB1[q];
+        } else if constexpr (MX) {
+          const size_t q = (size_t)d * nb + e;
+          const float2 a0 = B.A0f[q], a1 = B.A1f[q];
+          a0r = a0.x; a0i = a0.y; a1r = a1.x; a1i = a1.y;
+          b0 = B.B0f[q]; b1 = B.B1f[q];
         } else {
-          const size_t q = (size_t)d * n_bins + p.k_act - 1;
-          a0 = B.cA0[q]; a1 = B.cA1[q]; b0 = B.cB0[q]; b1 = B.cB1[q];
+          const size_t q = (size_t)d * nb + e;
+          const double2 a0 = B.A0[q], a1 = B.A1[q];
+          a0r = a0.x; a0i = a0.y; a1r = a1.x; a1i = a1.y;
+          b0 = B.B0[q]; b1 = B.B1[q];
         }
-        const double iw = B.inv_w[b];
-        const double2 ra = sr[d * (nb + 1) + b], rb = sr[d * (nb + 1) + b + 1];
-        const double r0r = 0.5 * (ra.x + rb.x), r0i = 0.5 * (ra.y + rb.y);
-        const double r1r = (rb.x - ra.x) * iw, r1i = (rb.y - ra.y) * iw;
-        const double dh = (a0.x * r0r - a0.y * r0i) + (a1.x * r1r - a1.y * r1i);
-        const double hh = b0 * (r0r * r0r + r0i * r0i) + 2.0 * b1 * (r0r * r1r + r0i * r1i);
-        part += dh - 0.5 * hh;
+        const RT half = (RT)0.5, two = (RT)2;
+        const RT r0r = half * (rr + nr), r0i = half * (ri + ni);
+        const RT r1r = (nr - rr) * iw, r1i = (ni - ri) * iw;
+        const RT dh = (a0r * r0r - a0i * r0i) + (a1r * r1r - a1i * r1i);
+        const RT hh = b0 * (r0r * r0r + r0i * r0i) + two * b1 * (r0r * r1r + r0i * r1i);
+        part += (double)(dh - half * hh);
       }
     }
   }
-  return part;
+  return wave_sum(part);
 }
 
 // Batched relative-binning likelihood: one wavefront per workgroup, 64
@@ -733,8 +733,6 @@ template <int NDET, bool MX>
 __global__ __launch_bounds__(64) void k_loglike_rb(const ModelDev* __restrict__ Mp, RBTables RB,
                                                    const double* __restrict__ u, long n, double* __restrict__ out,
                                                    int* __restrict__ terms) {
-  extern __shared__ double smem[];
-  void* sr = smem;
   const ModelDev& M = *Mp;
   const int lane = threadIdx.x;
   const int d = M.n_dim;
@@ -751,13 +749,12 @@ __global__ __launch_bounds__(64) void k_loglike_rb(const ModelDev* __restrict__ 
     const int cnt = (n - base) < 64 ? (int)(n - base) : 64;
     for (int p = 0; p < cnt; ++p) {
       const Probe pb = probe_from_lane<NDET>(pr, p);
-      const double tot = wave_sum(rb_partial<NDET, MX>(pb, RB, M.n_bins, sr, lane, 64));
-      const int ne = rb_edges_read(RB, pb.k_act, lane);
+      int ne;
+      const double tot = rb_wave<NDET, MX>(pb, RB, M.n_bins, lane, &ne);
       if (lane == p) {
         mine = tot;
         mine_edges = ne;
       }
-      __syncthreads();   // the ratios in LDS are rewritten by the next probe
     }
     if (i < n) out[i] = mine;
     if (terms && i < n) terms[i] = mine_edges;
@@ -870,32 +867,25 @@ __global__ __launch_bounds__(1024) void k_probe_bins(const ModelDev* __restrict_
   }
 }
 
-// Relative-binning bin pass of the two-pass batch: the tables staged once
-// per 512-thread block, one wavefront per probe with its own edge-ratio
-// scratch, the coefficients read with scalar loads.
+// Relative-binning pass of the two-pass batch: the tables staged once per
+// 512-thread block, one wavefront per probe (rb_wave), the coefficients read
+// with scalar loads.
 template <int NDET, bool MX>
 __global__ __launch_bounds__(512) void k_rb_bins(RBTables RB, int n_bins, const Probe* __restrict__ P, long n,
                                                  double* __restrict__ out, int* __restrict__ terms) {
   extern __shared__ double smem[];
-  using CT = typename std::conditional<MX, float2, double2>::type;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const RBTables V = stage_rb<NDET, MX>(RB, smem, tid, 512);
-  const size_t ratio_doubles = (size_t)NDET * (RB.nb + 1) * sizeof(CT) / sizeof(double);
-  double* sr = smem + rb_stage_doubles(RB.nb, NDET, MX) + wv * ratio_doubles;
   __syncthreads();
   for (long p = (long)blockIdx.x * 8 + wv; p < n; p += (long)gridDim.x * 8) {
     const Probe pb = P[p];
-    const double tot = wave_sum(rb_partial<NDET, MX, true>(pb, V, n_bins, sr, lane, 64));
-    const int ne = terms ? rb_edges_read(V, pb.k_act, lane) : 0;
+    int ne;
+    const double tot = rb_wave<NDET, MX>(pb, V, n_bins, lane, &ne);
     if (lane == 0) {
       out[p] = tot;
       if (terms) terms[p] = ne;
     }
-    // the next probe rewrites this wavefront's ratios
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
 }
 
@@ -1204,17 +1194,9 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
   for (int i = tid; i < d * d; i += NT) sL[i] = R.chol[i];
   TabView V{};
   if (lk_full(LK)) V = stage_tables<NDET, lk_mixed(LK)>(M, T, LDS, stab, tid, NT);
-  // relative binning: the tables (staged in LDS when LDS is set) and the edge
-  // ratios of up to two probes at once
+  // relative binning: the tables, staged in LDS when LDS is set
   RBTables RBv = RB;
-  double* sr0 = stab;
-  if constexpr (lk_rb(LK)) {
-    if constexpr (LDS) {
-      RBv = stage_rb<NDET, lk_mixed(LK)>(RB, stab, tid, NT);
-      sr0 = stab + rb_stage_doubles(RB.nb, NDET, lk_mixed(LK));
-    }
-  }
-  double* sr1 = sr0 + (size_t)NDET * (RB.nb + 1) * (lk_mixed(LK) ? 1 : 2);
+  if constexpr (lk_rb(LK) && LDS) RBv = stage_rb<NDET, lk_mixed(LK)>(RB, stab, tid, NT);
 
   int buf = 0;
   int nprobe = 0;
@@ -1294,10 +1276,15 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
     ++nprobe;
     if (LK == LK_GAUSS) return sG[q];
     const Probe pb = probe_from_rec<NDET>(*reinterpret_cast<const ProbeRec*>(sP + q * SL_PSTRIDE), lk_full(LK));
+    if constexpr (lk_rb(LK)) {
+      // every wave evaluates the probe (no exchange needed); terms: the edges read
+      int ne;
+      const double tot = rb_wave<NDET, lk_mixed(LK)>(pb, RBv, M.n_bins, lane, &ne);
+      nbins += ne;
+      return tot;
+    }
     double* rb = sred + buf * (NW + 4);
-    double tot;
-    if (lk_rb(LK)) tot = wave_sum(rb_partial<NDET, lk_mixed(LK)>(pb, RBv, M.n_bins, sr0, tid, NT));
-    else tot = wave_sum(fullgrid_partial<NDET, lk_mixed(LK), true>(pb, V, tid, NT));
+    double tot = wave_sum(fullgrid_partial<NDET, lk_mixed(LK), true>(pb, V, tid, NT));
     if constexpr (NW > 1) {
       if (lane == 0) rb[wv] = tot;
       __syncthreads();
@@ -1305,18 +1292,19 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
 #pragma unroll
       for (int w2 = 0; w2 < NW; ++w2) tot += rb[w2];
       buf ^= 1;
-    } else if (lk_rb(LK)) {
-      __syncthreads();   // the edge ratios in LDS are rewritten by the next probe
     }
-    // terms: the active bins (full grid) or the edges read (relative binning)
-    nbins += lk_full(LK) ? pb.k_act : rb_edges_read(RBv, pb.k_act, lane);
-    return lk_rb(LK) ? tot : tot - 0.5 * pb.hh;
+    // terms: the active bins
+    nbins += pb.k_act;
+    return tot - 0.5 * pb.hh;
   };
   // Full grid with two or more waves: lambdas of two candidates at once
   // (q < 0: none), the first half of the workgroup summing the bins of q1,
-  // the second those of q2, one barrier for both.  Nothing is counted here:
-  // the walk counts the evaluations the sequential algorithm makes.
-  constexpr bool PAIR = (lk_full(LK) || lk_rb(LK)) && NW >= 2;
+  // the second those of q2, one barrier for both.  Relative binning with two
+  // or more waves: NW candidates at once, one per wavefront.  Nothing is
+  // counted here: the walk counts the evaluations the sequential algorithm
+  // makes.
+  constexpr bool PAIR = lk_full(LK) && NW >= 2;
+  constexpr bool MULTI = lk_rb(LK) && NW >= 2;
   auto rec = [&](int q) -> const ProbeRec& { return *reinterpret_cast<const ProbeRec*>(sP + q * SL_PSTRIDE); };
   auto count = [&](int terms) {   // the probe's active bins or relative-binning edges
     ++nprobe;
@@ -1329,12 +1317,7 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
       const int q = second ? q2 : q1;
       double* rb = sred + buf * (NW + 4);
       double part = 0.0, hh = 0.0, kact = 0.0;
-      if constexpr (lk_rb(LK)) {
-        // both halves pass the barrier inside rb_partial
-        const Probe pb = q >= 0 ? probe_from_rec<NDET>(rec(q), false) : Probe{};
-        part = rb_partial<NDET, lk_mixed(LK)>(pb, RBv, M.n_bins, second ? sr1 : sr0, second ? tid - NT / 2 : tid, NT / 2,
-                                              q >= 0);
-      } else if (q >= 0) {
+      if (q >= 0) {
         const Probe pb = probe_from_rec<NDET>(rec(q), true);
         part = fullgrid_partial<NDET, lk_mixed(LK), true>(pb, V, second ? tid - NT / 2 : tid, NT / 2);
         hh = pb.hh;
@@ -1344,7 +1327,7 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
       if (lane == 0) rb[wv] = tot;
       if (lane == 0 && wv % HW == 0) {
         rb[NW + (second ? 1 : 0)] = hh;
-        if constexpr (lk_full(LK)) rb[NW + 2 + (second ? 1 : 0)] = kact;
+        rb[NW + 2 + (second ? 1 : 0)] = kact;
       }
       __syncthreads();
       double t1 = 0.0, t2 = 0.0;
@@ -1355,16 +1338,32 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
       }
       *l1 = t1 - 0.5 * rb[NW];
       *l2 = t2 - 0.5 * rb[NW + 1];
-      if constexpr (lk_rb(LK)) {
-        // terms of a relative-binning probe: the edges it read
-        *k1 = q1 >= 0 ? rb_edges_read(RBv, rec(q1).k_act, lane) : 0;
-        *k2 = q2 >= 0 ? rb_edges_read(RBv, rec(q2).k_act, lane) : 0;
-      } else {
-        *k1 = (int)rb[NW + 2];
-        *k2 = (int)rb[NW + 3];
-      }
+      *k1 = (int)rb[NW + 2];
+      *k2 = (int)rb[NW + 3];
       buf ^= 1;
     }
+  };
+  // Relative binning: wave w evaluates candidate qof(w) (q < 0: none); one
+  // barrier shares the NW lambdas and term counts, which the caller reads
+  // from the returned LDS slots (res[w], res[NW + w]) until the next call
+  // but one (the slots alternate between two buffers).
+  auto evalw = [&](auto qof) -> const double* {
+    double* rb = sred + buf * (2 * NW);
+    if constexpr (MULTI) {
+      const int q = qof(wv);
+      if (q >= 0) {
+        const Probe pb = probe_from_rec<NDET>(rec(q), false);
+        int ne;
+        const double l = rb_wave<NDET, lk_mixed(LK)>(pb, RBv, M.n_bins, lane, &ne);
+        if (lane == 0) {
+          rb[wv] = l;
+          rb[NW + wv] = (double)ne;
+        }
+      }
+      __syncthreads();
+      buf ^= 1;
+    }
+    return rb;
   };
 
   for (int s0 = 0; s0 < R.m; s0 += SL_CHUNK) {
@@ -1485,7 +1484,35 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
       // ---- step out, left then right (the order of the sequential algorithm)
       int na = 0, nh = 0;          // successful steps per side
       int uL = 0, uR = 0;          // batch points of each side already walked
-      if constexpr (PAIR) {
+      if constexpr (MULTI) {
+        // up to NW points per round, shared between the sides (a side's later
+        // points under the hypothesis that its earlier ones are accepted);
+        // a side's points after its first rejection are not counted
+        for (;;) {
+          if (J > 0 && uL < BL::SO && !inside(uL)) J = 0;
+          if (K > 0 && uR < BL::SO && !inside(BL::SO + uR)) K = 0;
+          auto can_l = [&](int i) { return J > i && uL + i < BL::SO && inside(uL + i); };
+          auto can_r = [&](int i) { return K > i && uR + i < BL::SO && inside(BL::SO + uR + i); };
+          int nl = 0, nr = 0;
+          while (nl + nr < NW) {
+            const bool okl = can_l(nl), okr = can_r(nr);
+            if (!okl && !okr) break;
+            if (okl && (nl <= nr || !okr)) ++nl; else ++nr;
+          }
+          if (nl + nr == 0) break;
+          const double* res = evalw([&](int w2) {
+            return w2 < nl ? uL + w2 : (w2 < nl + nr ? BL::SO + uR + (w2 - nl) : -1);
+          });
+          for (int i = 0; i < nl; ++i) {
+            count((int)res[NW + i]);
+            if (res[i] > lstar) { lo -= w; --J; ++na; ++uL; } else { J = 0; break; }
+          }
+          for (int i = 0; i < nr; ++i) {
+            count((int)res[NW + nl + i]);
+            if (res[nl + i] > lstar) { hi += w; --K; ++nh; ++uR; } else { K = 0; break; }
+          }
+        }
+      } else if constexpr (PAIR) {
         // the two sides are independent: walk them together, one pair of
         // probes per round, while their next points are in the batch; the
         // probes evaluated are exactly those of the left-then-right walk
@@ -1542,7 +1569,35 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
       // ---- shrink
       int a = 0;                   // attempts made
       bool accepted = false;
-      if (PAIR && combined && na < BL::H && nh < BL::H) {
+      if (MULTI && combined && na < BL::H && nh < BL::H) {
+        // attempts a .. a+NW-1 together (each under the hypothesis that the
+        // earlier ones are rejected); a probe is counted only where the
+        // sequential walk makes it
+        const int base = 2 * BL::SO + BL::SC * (BL::H * na + nh);
+        while (!accepted && a < BL::SC && a < R.max_shrink) {
+          const int lim = (BL::SC < R.max_shrink ? BL::SC : R.max_shrink) - a;
+          const int nq = lim < NW ? lim : NW;
+          bool any = false;
+          for (int w2 = 0; w2 < nq; ++w2) any = any || inside(base + a + w2);
+          const double* res = nullptr;
+          if (any) res = evalw([&](int w2) { return (w2 < nq && inside(base + a + w2)) ? base + a + w2 : -1; });
+          for (int i = 0; i < nq; ++i) {
+            const double tq = ttq(base + a);
+            if (inside(base + a)) {
+              count((int)res[NW + i]);
+              const double li = res[i];
+              if (li > lstar) {
+                if (tid < d) sX[tid] = fma(tq, dir[tid], sX[tid]);
+                lx = li;
+                accepted = true;
+                break;
+              }
+            }
+            if (tq < 0.0) lo = tq; else hi = tq;
+            ++a;
+          }
+        }
+      } else if (PAIR && combined && na < BL::H && nh < BL::H) {
         // attempts a and a+1 together (a+1 under the hypothesis that a is
         // rejected); a probe is counted only where the sequential walk makes it
         const int base = 2 * BL::SO + BL::SC * (BL::H * na + nh);

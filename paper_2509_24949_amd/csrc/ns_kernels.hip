@@ -17,12 +17,10 @@ hipError_t configure_slice(const ModelDev& M, int rb_nb, int n_chains, LaunchCfg
     return hipSuccess;
   }
   const bool rb = M.likelihood == LK_RB;
-  // LDS of a chain workgroup: its own data, the relative-binning edge ratios
-  // of two probes, and the staged tables (optional)
-  const size_t ratios = rb ? 2 * (size_t)M.n_det * (rb_nb + 1) * (M.mixed ? sizeof(float2) : sizeof(double2)) : 0;
+  // LDS of a chain workgroup: its own data and the staged tables (optional)
   const size_t tab = rb ? rb_stage_doubles(rb_nb, M.n_det, M.mixed != 0) * sizeof(double)
                         : staged_table_bytes(M.k_lim, M.n_det, M.mixed != 0);
-  auto lds_of = [&](int nt, bool stage) { return slice_lds_fixed(nt) + ratios + (stage ? tab : 0); };
+  auto lds_of = [&](int nt, bool stage) { return slice_lds_fixed(nt) + (stage ? tab : 0); };
   // every chain should be resident at once: a CU holds eight waves of the
   // chain kernel (its registers allow two per SIMD) and 160 KB of LDS
   auto resident = [&](int nt, bool stage) {
@@ -85,13 +83,14 @@ template <int NDET, bool MX>
 hipError_t launch_loglike_rb_t(const ModelDev* Md, const RBTables& RB, int n_bins, const double* u, long n,
                                double* out, int* terms, Probe* pbuf, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  if (pbuf) {
+  // the two-pass form stages the tables in LDS; coarse grids too large for
+  // a CU's 160 KB take the one-pass form, which reads them through the caches
+  const size_t lds = rb_stage_doubles(RB.nb, NDET, MX) * sizeof(double);
+  if (pbuf && lds <= 160 * 1024) {
     hipLaunchKernelGGL(k_probe_setup, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, Md, nullptr, u, n, pbuf,
                        nullptr);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    using CT = typename std::conditional<MX, float2, double2>::type;
-    const size_t lds = rb_stage_doubles(RB.nb, NDET, MX) * sizeof(double) + 8 * (size_t)NDET * (RB.nb + 1) * sizeof(CT);
     long blocks = (n + 7) / 8;
     if (blocks > 256 * 2) blocks = 256 * 2;
     hipLaunchKernelGGL((k_rb_bins<NDET, MX>), dim3((unsigned)blocks), dim3(512), lds, st, RB, n_bins, pbuf, n, out,
@@ -100,8 +99,7 @@ hipError_t launch_loglike_rb_t(const ModelDev* Md, const RBTables& RB, int n_bin
   }
   long blocks = (n + 63) / 64;
   if (blocks > 8192) blocks = 8192;
-  const size_t lds = (size_t)NDET * (RB.nb + 1) * (MX ? sizeof(float2) : sizeof(double2));
-  hipLaunchKernelGGL((k_loglike_rb<NDET, MX>), dim3((unsigned)blocks), dim3(64), lds, st, Md, RB, u, n, out, terms);
+  hipLaunchKernelGGL((k_loglike_rb<NDET, MX>), dim3((unsigned)blocks), dim3(64), 0, st, Md, RB, u, n, out, terms);
   return hipGetLastError();
 }
 
@@ -209,8 +207,7 @@ hipError_t configure_slice_packed(const ModelDev& M, int rb_nb, LaunchCfg* C) {
   }
   C->lds_tables = false;
   C->lds_bytes = slice_lds_fixed(C->slice_threads);
-  if (M.likelihood == LK_RB)
-    C->lds_bytes += 2 * (size_t)M.n_det * (rb_nb + 1) * (M.mixed ? sizeof(float2) : sizeof(double2));
+  (void)rb_nb;
   return hipSuccess;
 }
 

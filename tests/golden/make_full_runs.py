@@ -7,7 +7,9 @@ iteration of every death) plus evenly spaced dead-point log-likelihoods, so
 that a GPU run with the same seeds can be checked end to end without
 re-running the oracle.
 
-    python tests/golden/make_full_runs.py [n_threads]
+    python tests/golden/make_full_runs.py [n_threads] [--only=key1,key2]
+
+--only recomputes the named entries and keeps the others as stored.
 """
 from __future__ import annotations
 
@@ -27,6 +29,12 @@ from paper_2509_24949_amd import synth  # noqa: E402
 
 OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "full_runs.json")
 SERVING_SAMPLE = (26, 45, 57, 61)   # short serving events (few active bins)
+# long serving events with many active bins, run at n_live 500 (k 250) to keep
+# the oracle's time down: 32 s three-detector (k_lim 2650 bins, tables read
+# through the caches), 16 s three-detector, 32 s one-detector at low chirp
+# mass (k_lim about 11 600 bins)
+SERVING_LONG = (32, 16, 39)
+LONG_OPTS = {"n_live": 500, "n_delete": 250}
 
 
 def digest(slot, it) -> str:
@@ -52,26 +60,40 @@ def full_run(w, n_threads: int, **kw) -> dict:
         "logZ": z["logZ"], "sigma": z["sigma"], "sigma_h": z["sigma_h"], "ess": z["ess"], "H": st["H"],
         "dead_digest": digest(d["slot"], d["iter"]),
         "logl_index": idx.tolist(), "logl_at": [float(d["logl"][i]) for i in idx],
-        "oracle_seconds": time.perf_counter() - t0, "oracle_threads": n_threads,
+        "oracle_seconds": time.perf_counter() - t0, "oracle_threads": n_threads, "opts": dict(kw),
     }
 
 
 def main():
-    n_threads = int(sys.argv[1]) if len(sys.argv) > 1 else (os.cpu_count() or 1)
+    args = [a for a in sys.argv[1:] if not a.startswith("--only=")]
+    only = [a.split("=", 1)[1].split(",") for a in sys.argv[1:] if a.startswith("--only=")]
+    only = set(only[0]) if only else None
+    n_threads = int(args[0]) if args else (os.cpu_count() or 1)
     out = {}
+    if only is not None and os.path.exists(OUT):
+        with open(OUT) as fh:
+            out = json.load(fh)
+    jobs = []
     for name in ("tf2_3det", "tf2_3det_rb"):
-        out[name] = full_run(synth.workload(name), n_threads)
-        print(name, out[name]["iterations"], out[name]["logZ"], flush=True)
-    # the large-population workload in double precision (the GPU's mixed form
-    # is compared statistically against it)
-    w = synth.workload("tf2_3det_mixed")
-    w.precision = 0
-    out["tf2_3det_n2000_fp64"] = full_run(w, n_threads)
-    print("tf2_3det_n2000_fp64", out["tf2_3det_n2000_fp64"]["logZ"], flush=True)
+        jobs.append((name, lambda name=name: full_run(synth.workload(name), n_threads)))
+
+    def large_population():
+        # the large-population workload in double precision (the GPU's mixed
+        # form is compared statistically against it)
+        w = synth.workload("tf2_3det_mixed")
+        w.precision = 0
+        return full_run(w, n_threads)
+
+    jobs.append(("tf2_3det_n2000_fp64", large_population))
     for i in SERVING_SAMPLE:
-        key = f"event/{i}"
-        out[key] = full_run(synth.serving_event(i), n_threads)
-        print(key, out[key]["iterations"], out[key]["logZ"], flush=True)
+        jobs.append((f"event/{i}", lambda i=i: full_run(synth.serving_event(i), n_threads)))
+    for i in SERVING_LONG:
+        jobs.append((f"event/{i}", lambda i=i: full_run(synth.serving_event(i), n_threads, **LONG_OPTS)))
+    for key, job in jobs:
+        if only is not None and key not in only:
+            continue
+        out[key] = job()
+        print(key, out[key]["iterations"], out[key]["logZ"], f"{out[key]['oracle_seconds']:.1f} s", flush=True)
     with open(OUT, "w") as fh:
         json.dump(out, fh, indent=1, sort_keys=True)
         fh.write("\n")

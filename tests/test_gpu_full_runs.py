@@ -73,13 +73,17 @@ def test_complete_run_matches_oracle(golden, name):
 
 
 def test_served_events_match_oracle(golden):
+    """Every stored serving event, short ones (4 s grids) and long ones (16 s
+    and 32 s grids, one and three detectors, run at the stored n_live),
+    served together and checked like single runs."""
     keys = sorted(k for k in golden if k.startswith("event/"))
-    assert len(keys) >= 4
+    assert len(keys) >= 7
     srv = binding.Server(max_runs=len(keys))
     tick = {}
     for k in keys:
         w = synth.serving_event(int(k.split("/")[1]))
-        tick[srv.submit(_data(w), binding.opts_for(w))] = k
+        print(f"serve {k}: {w.n_bins} bins, {w.n_det} detectors, opts {golden[k].get('opts', {})}", flush=True)
+        tick[srv.submit(_data(w), binding.opts_for(w, **golden[k].get("opts", {})))] = k
     done = {}
     for _ in range(10000):
         running, queued, _ = srv.tick(1)
@@ -91,6 +95,31 @@ def test_served_events_match_oracle(golden):
         _check(golden[k], done[k])
         done[k].close()
     srv.close()
+
+
+def test_rb_mixed_precision_agrees_with_double(golden):
+    """Relative binning at the large population: sixteen seeds in the mixed
+    form against sixteen in double precision (same n_live), means of log Z
+    within twice the spread of their difference.  (At 55-step chains a
+    run's log Z scatters by about 0.5 from seed to seed, several times its
+    prior-volume error, so the means need this many seeds.)"""
+    w = synth.workload("tf2_3det_rb_mixed")
+    spec = _data(w)
+    z = {0: [], 1: []}
+    sig = {0: [], 1: []}
+    R = 16
+    for prec in (0, 1):
+        for s in range(R):
+            run = binding.Run(spec, binding.opts_for(w, seed=9300 + s, precision=prec))
+            assert run.run(1000)
+            r = run.logZ(200)
+            z[prec].append(r["logZ"])
+            sig[prec].append(r["sigma"])
+            run.close()
+    m64, m32 = np.mean(z[0]), np.mean(z[1])
+    spread = math.sqrt(np.var(z[0], ddof=1) / R + np.var(z[1], ddof=1) / R)
+    print(f"rb mixed {m32:.4f} vs double {m64:.4f}; spread {spread:.4f}; sigma {np.mean(sig[1]):.4f}")
+    assert abs(m32 - m64) <= max(2.0 * spread, 0.05), (m32, m64, spread)
 
 
 def test_mixed_precision_agrees_with_double(golden):

@@ -59,10 +59,16 @@ def test_waveform_parity(torch_cuda, name):
                 assert np.array_equal(gr == 0, hr == 0)
 
 
-@pytest.mark.parametrize("name,n", [("tf2_1det", 4099), ("tf2_3det", 2053)])
+@pytest.mark.parametrize("name,n", [("tf2_1det", 4099), ("tf2_3det", 2053), ("event/16", 1031), ("event/32", 1031),
+                                    ("event/39", 517)])
 def test_loglike_parity(torch_cuda, name, n):
+    """Full-grid likelihood against the oracle's on the 473- and 4017-bin
+    workloads and on 16 s (16065 bins) and 32 s (32129 bins) serving events,
+    three detectors and one detector at low chirp mass (the largest active
+    prefix, about 11 600 bins, read from HBM)."""
     torch = torch_cuda
-    w = synth.workload(name)
+    w = synth.serving_event(int(name.split("/")[1])) if name.startswith("event/") else synth.workload(name)
+    print(f"loglike parity {name}: {w.n_bins} bins, {w.n_det} detectors, {n} probes", flush=True)
     orc, spec = _pair(w)
     u = synth.proposal_batch(w, n, seed=7)
     u[0] = 0.0                      # cube corners
@@ -277,6 +283,29 @@ def test_mixed_precision_loglike_error(torch_cuda, name):
     err = np.abs(got - lam_o)
     print(f"{name}: max |dlogL| = {err.max():.3e}, max relative {np.max(err / scale):.3e}")
     assert np.max(err / scale) <= 2e-5
+
+
+@pytest.mark.parametrize("name", ["tf2_3det_rb_mixed", "tf2_3det_mixed"])
+def test_mixed_chain_kernel_loglike_error(torch_cuda, name):
+    """The likelihoods the mixed-form chain kernel leaves in the refilled slots
+    after two iterations (its own in-sampler evaluation, relative binning or
+    full grid) against the double-precision oracle at the same points, to
+    2e-5 of the cancellation scale."""
+    w = synth.workload(name)
+    orc, spec = _pair(w)
+    run = binding.Run(spec, binding.opts_for(w, n_live=512, n_delete=256, precision=binding.NS_MIXED))
+    run.step(2)
+    u, lam = run.live()
+    refilled = np.unique(run.dead()["slot"])
+    assert len(refilled) >= 256
+    u, lam = u[refilled], lam[refilled]
+    wf = synth.workload("tf2_3det")
+    orc_full = oracle.OracleProblem(wf, orc.dre, orc.dim)
+    _, scale = _scale(wf, orc_full, u)
+    lam_o = orc.loglike_batch(u, NTHREADS)
+    err = np.abs(lam - lam_o) / scale
+    print(f"{name} chain kernel: max |dlogL| {np.max(np.abs(lam - lam_o)):.3e}, relative {err.max():.3e}")
+    assert err.max() <= 2e-5
 
 
 def test_mixed_precision_evidence_statistics(torch_cuda):
