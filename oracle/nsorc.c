@@ -585,16 +585,29 @@ static double lam_at(const orc_run* r, const double* u, long* evals) {
 
 /* Membership in the constrained slice: inside the unit cube first (no
  * likelihood call outside it), then lambda > L* strictly. */
+static int is_periodic(const orc_problem* p, int i) { return p->periodic && p->periodic[i]; }
+
+/* A point of the line is in the slice if it lies in the unit cube (a
+ * periodic coordinate always does, being wrapped) and its likelihood
+ * exceeds the threshold. */
 static int in_slice(const orc_run* r, const double* y, double lstar, double* lam_out, long* evals) {
     for (int i = 0; i < r->d; ++i)
-        if (!(y[i] >= 0.0 && y[i] <= 1.0)) return 0;
+        if (!is_periodic(&r->p, i) && !(y[i] >= 0.0 && y[i] <= 1.0)) return 0;
     double l = lam_at(r, y, evals);
     *lam_out = l;
     return l > lstar;
 }
 
-static void along(int d, const double* x, double t, const double* dir, double* y) {
-    for (int i = 0; i < d; ++i) y[i] = fma(t, dir[i], x[i]);
+/* The point x + t dir of the line.  A periodic coordinate (a phase or an
+ * angle whose prior covers one full period: the coalescence phase, the
+ * polarisation angle, the right ascension) is taken modulo 1, so that the
+ * line runs on the torus those coordinates form and the slice extends
+ * across the seam of their prior interval. */
+static void along(const orc_problem* p, int d, const double* x, double t, const double* dir, double* y) {
+    for (int i = 0; i < d; ++i) {
+        y[i] = fma(t, dir[i], x[i]);
+        if (is_periodic(p, i)) y[i] -= floor(y[i]);
+    }
 }
 
 /* One hit-and-run slice update (Neal 2003, stepping out and shrinkage) of
@@ -612,20 +625,20 @@ static void slice_update(const orc_run* r, double* x, double* lx, const double* 
     int J = (int)floor(r->o.max_stepout * uj);
     int K = r->o.max_stepout - 1 - J;
     while (J > 0) {
-        along(d, x, lo, dir, y);
+        along(&r->p, d, x, lo, dir, y);
         if (!in_slice(r, y, lstar, &ly, evals)) break;
         lo -= w;
         --J;
     }
     while (K > 0) {
-        along(d, x, hi, dir, y);
+        along(&r->p, d, x, hi, dir, y);
         if (!in_slice(r, y, lstar, &ly, evals)) break;
         hi += w;
         --K;
     }
     for (int a = 0; a < r->o.max_shrink; ++a) {
         double t = fma(ushr(uctx, a), hi - lo, lo);
-        along(d, x, t, dir, y);
+        along(&r->p, d, x, t, dir, y);
         if (in_slice(r, y, lstar, &ly, evals)) {
             memcpy(x, y, sizeof(double) * d);
             *lx = ly;

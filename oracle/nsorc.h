@@ -38,6 +38,7 @@ typedef struct {
     const double* rb_fiducial;  /* [n_dim] physical parameters */
     const double* gauss_mu;     /* [n_dim] */
     double gauss_sigma;
+    const int* periodic;        /* [n_dim] or NULL: 1 = the unit-cube coordinate wraps around */
 } orc_problem;
 
 typedef struct {

@@ -124,6 +124,9 @@ class Workload:
     sampler_seed: int = 1001
     gauss_mu: np.ndarray = field(default_factory=lambda: np.zeros(0))
     gauss_sigma: float = 0.0
+    # per coordinate: 1 = the unit-cube coordinate wraps around (its prior is
+    # uniform over one full period); empty = none
+    periodic: np.ndarray = field(default_factory=lambda: np.zeros(0, dtype=np.int32))
 
     @property
     def n_dim(self) -> int:
@@ -165,6 +168,9 @@ def workload(name: str, distance: float | None = None) -> Workload:
     ``tf2_3det_rb``  tf2_3det with the relative-binning likelihood (128 geometric bins).
     ``tf2_3det_mixed``  tf2_3det in the mixed-precision form with n 2000 / k 1000.
     ``tf2_3det_rb_mixed`` tf2_3det_rb in the mixed-precision form with n 2000 / k 1000.
+    ``tf2_3det_rb_paper`` tf2_3det_rb at the paper's own settings (Section 2):
+        n 3000 / k 1500, chains of 10 d = 110 steps, the coalescence phase,
+        the polarisation angle and the right ascension wrapped in the unit cube.
 
     ``distance`` overrides the stored SNR-scaled injection distance (used only
     by the script that derives those distances).
@@ -183,7 +189,7 @@ def workload(name: str, distance: float | None = None) -> Workload:
             noise_seed=101, fixed_dist_mpc=d_eff, snr_target=15.0,
             n_live=500, n_delete=250, n_steps=20, sampler_seed=1001,
         )
-    if name in ("tf2_3det", "tf2_3det_rb", "tf2_3det_mixed", "tf2_3det_rb_mixed"):
+    if name in ("tf2_3det", "tf2_3det_rb", "tf2_3det_mixed", "tf2_3det_rb_mixed", "tf2_3det_rb_paper"):
         d_inj = distance if distance is not None else inj.get("tf2_3det", {}).get("distance_mpc", 0.0)
         w = Workload(
             name=name, model=MODEL_TF2_11P, likelihood=LIKE_FULL, f_lo=20.0, df=0.25, n_bins=4017,
@@ -203,6 +209,11 @@ def workload(name: str, distance: float | None = None) -> Workload:
             w.sampler_seed = 4001
             if name == "tf2_3det_rb_mixed":
                 w.likelihood = LIKE_RB
+        if name == "tf2_3det_rb_paper":
+            w.likelihood = LIKE_RB
+            w.n_live, w.n_delete, w.n_steps = 3000, 1500, 10 * 11
+            w.periodic = np.array([0, 0, 0, 0, 0, 0, 1, 1, 0, 0, 1], dtype=np.int32)
+            w.sampler_seed = 8001
         return w
     raise KeyError(name)
 

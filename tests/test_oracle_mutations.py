@@ -47,7 +47,30 @@ MUTATIONS = [
     ("Kish ESS", "*ess = 1.0 / s2;", "*ess = 1.01 / s2;", "posterior"),
     ("resample positions", "((double)m + u0) / (double)n_out * acc",
      "((double)m + u0) / (double)n_out * acc * 0.99", "resample"),
+    ("no wrap of periodic coordinates", "if (is_periodic(p, i)) y[i] -= floor(y[i]);",
+     "if (is_periodic(p, i)) y[i] -= 0.0;", "wrap"),
+    ("wrap to the centred interval", "if (is_periodic(p, i)) y[i] -= floor(y[i]);",
+     "if (is_periodic(p, i)) y[i] -= floor(y[i] + 0.5);", "wrap"),
 ]
+
+
+def _wrap_bad(L):
+    """The hand-computed wrapped slice move (test_wrapped_slice_hand_computed),
+    driven through the build L: the accepted point must lie in [0, 1] and
+    equal the line point modulo 1, after a full step-out budget."""
+    w = synth.gauss_workload(1, 0.1, mu=[0.5])
+    w.slice_width = 0.15
+    w.periodic = np.array([1], dtype=np.int32)
+    p = oracle.OracleProblem(w)
+    o = oracle.opts_for(w)
+    x = np.array([0.95])
+    d = np.array([1.0])
+    us = np.array([0.3])
+    lx, ev = C.c_double(0.0), C.c_long()
+    L.orc_slice_update_fixed(p.ref, C.byref(o), x.ctypes.data_as(oracle._dp), C.byref(lx),
+                             d.ctypes.data_as(oracle._dp), -1e300, 0.5, 0.5, us.ctypes.data_as(oracle._dp), 1,
+                             C.byref(ev))
+    return not (0.0 <= x[0] <= 1.0 and ev.value == 100 and abs(x[0] - 0.875) < 1e-9)
 
 
 def _posterior_bad(L):
@@ -98,6 +121,7 @@ CHECKS = {
     "polarisation": lambda L: pins._polarisation_worst(L) >= 1e-11,
     "posterior": _posterior_bad,
     "resample": _resample_bad,
+    "wrap": _wrap_bad,
 }
 
 

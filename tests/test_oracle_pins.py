@@ -831,3 +831,75 @@ def test_two_dim_quadrature_evidence():
     r.run()
     res = r.logZ(200)
     assert abs(res["logZ"] - est[1]) < 3 * res["sigma"] + 1e-3, (res, est)
+
+
+def test_wrapped_slice_hand_computed():
+    """A periodic coordinate wraps around: with no constraint the step-out
+    never leaves the unit cube, so it spends its whole budget (50 steps left,
+    49 right for uj = 0.5), and the accepted point is the line point taken
+    modulo 1 (worked by hand below, with exact rational arithmetic for the
+    fused multiply-adds)."""
+    from fractions import Fraction
+
+    w = synth.gauss_workload(1, 0.1, mu=[0.5])
+    w.slice_width = 0.15
+    w.periodic = np.array([1], dtype=np.int32)
+    p = oracle.OracleProblem(w)
+    opts = oracle.opts_for(w)
+    x0, uw, uj, us = 0.95, 0.5, 0.5, 0.3
+    lo = -0.15 * uw
+    hi = lo + 0.15
+    for _ in range(50):
+        lo -= 0.15
+    for _ in range(49):
+        hi += 0.15
+    t = float(Fraction(us) * Fraction(hi - lo) + Fraction(lo))
+    y = x0 + t
+    want = y - math.floor(y)
+    x, lx, ev = oracle.slice_update_fixed(p, opts, [x0], 0.0, [1.0], -1e300, uw, uj, [us])
+    assert ev == 50 + 49 + 1
+    assert x[0] == want and 0.0 <= x[0] <= 1.0 and y < 0.0
+    # the same move without wrapping stops at the cube's faces
+    w.periodic = np.zeros(1, dtype=np.int32)
+    x2, _, ev2 = oracle.slice_update_fixed(oracle.OracleProblem(w), opts, [x0], 0.0, [1.0], -1e300, uw, uj, [us])
+    assert ev2 < 10 and 0.0 <= x2[0] <= 1.0
+
+
+def test_wrapped_moves_uniform_on_the_torus():
+    """Unconstrained chains on a periodic coordinate started next to the seam
+    become uniform on the circle (KS), stay in [0, 1], and cross the seam."""
+    d = 2
+    w = synth.gauss_workload(d, 0.1)
+    w.slice_width = 0.3
+    w.periodic = np.array([1, 0], dtype=np.int32)
+    p = oracle.OracleProblem(w)
+    opts = oracle.opts_for(w)
+    opts.max_stepout = 4
+    pts = _chains_from_point(p, opts, [0.02, 0.5], 0.0, -np.inf, 1500, 6, d, 9)
+    assert pts.min() >= 0.0 and pts.max() <= 1.0
+    for i in range(d):
+        assert stats.kstest(pts[:, i], "uniform").pvalue > 1e-3
+    one = _chains_from_point(p, opts, [0.02, 0.5], 0.0, -np.inf, 400, 1, d, 10)
+    assert np.mean(one[:, 0] > 0.5) > 0.2      # first moves already cross the seam
+
+
+def test_periodic_coordinates_cover_one_period():
+    """The coordinates the paper-setting workload wraps (coalescence phase,
+    polarisation angle, right ascension) have priors covering exactly one
+    period of the likelihood: u = 0 and u = 1 give the same lambda."""
+    w = synth.workload("tf2_3det_rb_paper")
+    re, im = oracle.make_data(w)
+    orc = oracle.OracleProblem(w, re, im)
+    per = np.flatnonzero(w.periodic)
+    assert sorted(per.tolist()) == [6, 7, 10]
+    rng = np.random.default_rng(12)
+    u = synth.proposal_batch(w, 40, seed=21)
+    for i in per:
+        a, b = u.copy(), u.copy()
+        a[:, i], b[:, i] = 0.0, 1.0
+        la, lb = orc.loglike_batch(a, 4), orc.loglike_batch(b, 4)
+        assert np.max(np.abs(la - lb) / (np.abs(la) + 1.0)) < 1e-9, i
+        c = u.copy()
+        c[:, i] = rng.random(len(u))
+        lc = orc.loglike_batch(c, 4)
+        assert np.max(np.abs(lc - la)) > 1e-3      # the coordinate matters
