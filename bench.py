@@ -50,6 +50,10 @@ WORKLOADS = {
     "tf2_3det_rb": _GRID2 + ", relative binning (128 geometric bins), n_live 1000, n_delete 500, 55 slice steps, FP64",
     "tf2_3det_mixed": _GRID2 + ", full-grid Whittle, n_live 2000, n_delete 1000, 55 slice steps, mixed precision",
     "tf2_3det_rb_mixed": _GRID2 + ", relative binning (128 bins), n_live 2000, n_delete 1000, 55 slice steps, mixed precision",
+    "tf2_3det_rb_paper": _GRID2 + ", relative binning (128 bins), the paper's settings: n_live 3000, n_delete 1500, "
+                         "110 slice steps (10 per dimension), phase, polarisation and right ascension wrapped, FP64",
+    "scaling": "runtime of complete tf2_3det_rb runs against n_live at n_delete = n_live/2 and against n_delete "
+               "at n_live 1000",
     "serving": "64 Poisson-arriving events, 4/8/16/32 s (4017-32129 bins per detector), 1-3 detectors, "
             "SNR U[8,40], Mc U[5,60], q U[0.125,1], 11 parameters, n_live U{500,1000,2000}, n_delete n_live/2, "
             "full-grid Whittle",
@@ -288,6 +292,77 @@ def serving(args, precision_name=None) -> dict:
     return out
 
 
+SCALING_N = (250, 500, 1000, 2000, 4000)       # n_live at n_delete = n_live / 2
+SCALING_K = (1, 10, 100, 500, 999)              # n_delete at n_live = 1000
+
+
+def scaling(args) -> dict:
+    """Runtime of complete runs against the population and against the
+    number deleted per iteration (the paper's runtime figure, Section 3), on
+    the relative-binning workload: one complete run per point, from ns_init
+    to the evidence, after a warm-up run; the oracle times the smallest
+    population on the host threads."""
+    import torch
+
+    from paper_2509_24949_amd import binding, synth
+
+    w = synth.workload("tf2_3det_rb")
+    log("bench: scaling: building data (library-injected waveform)")
+    re, im = binding.make_data(w)
+    spec = binding.ProblemSpec(w, re, im)
+    r = binding.Run(spec, binding.opts_for(w, n_live=250, n_delete=125, max_iter=3))
+    r.run(3)
+    r.close()
+    points = []
+    grid = [(n, n // 2) for n in SCALING_N] + [(1000, k) for k in SCALING_K if k != 500]
+    for n, k in grid:
+        max_iter = int(60 * n / k) + 200
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = binding.Run(spec, binding.opts_for(w, n_live=n, n_delete=k, max_iter=max_iter))
+        # iterations are enqueued in chunks of about two e-folds of prior
+        # volume, so that few run past termination
+        chunk, done, it = max(4, (2 * n) // k), False, 0
+        while not done and it < max_iter:
+            done = r.step(min(chunk, max_iter - it))
+            it += chunk
+        z = r.logZ(200)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        st = r.state()
+        r.close()
+        points.append({"n_live": n, "n_delete": k, "s_per_run": dt, "iterations": st["iter"],
+                       "evals": st["n_evals"], "evals_per_s": st["n_evals"] / dt, "logZ": z["logZ"],
+                       "sigma_logZ": z["sigma"], "terminated": bool(done)})
+        log(f"bench: scaling n_live {n} n_delete {k}: {dt:.3f} s, {st['iter']} iterations, "
+            f"{st['n_evals'] / dt / 1e6:.0f} M evals/s, logZ {z['logZ']:.3f} +- {z['sigma']:.3f}")
+    out = {"metric": "s/run", "value": next(p["s_per_run"] for p in points if p["n_live"] == 1000
+                                              and p["n_delete"] == 500),
+           "unit": "s", "n_gpus": 1, "steps": len(points), "warmup": 1, "higher_is_better": False,
+           "scaling": "strong", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic (seeded Gaussian noise plus an injected TaylorF2 signal; no real detector data)",
+           "config": {"workload": f"scaling: {WORKLOADS['scaling']}", "likelihood": "relative binning (128 bins)",
+                      "n_steps": w.n_steps},
+           "points": points}
+    if not args.no_cpu_baseline:
+        import oracle
+
+        threads = min(16, os.cpu_count() or 1)
+        n, k = SCALING_N[0], SCALING_N[0] // 2
+        log(f"bench: scaling: the oracle's complete run at n_live {n} on {threads} host threads")
+        ore, oim = oracle.make_data(w)
+        prob = oracle.OracleProblem(w, ore, oim)
+        t0 = time.perf_counter()
+        ro = oracle.Run(prob, oracle.opts_for(w, n_threads=threads, n_live=n, n_delete=k, max_iter=400))
+        ro.run(400)
+        dt = time.perf_counter() - t0
+        st = ro.state()
+        out["cpu_baseline"] = {"value": dt, "unit": "s/run", "cores": threads, "kind": "oracle",
+                               "sample": f"one complete run at n_live {n}, n_delete {k} ({st['iter']} iterations, "
+                                         f"{st['n_evals']} likelihood evaluations, OpenMP over chains)"}
+    return out
+
+
 def standalone_loglike(w, spec, n_probes: int = 65536, reps: int = 20) -> dict:
     """The fused waveform-plus-likelihood kernel alone on a batch of probes,
     half prior draws and half around the injection; HIP events on the
@@ -372,6 +447,9 @@ def main():
     binding.lib()
     if args.workload == "serving":
         print(json.dumps(serving(args)), flush=True)
+        return
+    if args.workload == "scaling":
+        print(json.dumps(scaling(args)), flush=True)
         return
     w = synth.workload(args.workload)
     log(f"bench: workload {args.workload}: building data (library-injected waveform)")
