@@ -54,6 +54,8 @@ WORKLOADS = {
                          "110 slice steps (10 per dimension), phase, polarisation and right ascension wrapped, FP64",
     "scaling": "runtime of complete tf2_3det_rb runs against n_live at n_delete = n_live/2 and against n_delete "
                "at n_live 1000",
+    "coverage": "seed-to-seed scatter of log Z against the sampler's error bar, at chains of 5, 10 and 20 steps per "
+                "dimension, for tf2_3det and serving events 28 and 51, and at the paper's settings",
     "serving": "64 Poisson-arriving events, 4/8/16/32 s (4017-32129 bins per detector), 1-3 detectors, "
             "SNR U[8,40], Mc U[5,60], q U[0.125,1], 11 parameters, n_live U{500,1000,2000}, n_delete n_live/2, "
             "full-grid Whittle",
@@ -363,6 +365,58 @@ def scaling(args) -> dict:
     return out
 
 
+COVERAGE_STEPS = (5, 10, 20)     # slice steps per dimension
+COVERAGE_SEEDS = 8
+
+
+def coverage(args) -> dict:
+    """Does the evidence error bar cover the run-to-run scatter?  For each
+    workload and chain length, COVERAGE_SEEDS complete runs with different
+    sampler seeds: the standard deviation of their log Z over the mean of
+    their error bars (the spread of log Z over prior-volume replicas) should
+    be about one when the chains are long enough to decorrelate."""
+    import numpy as np
+    import torch
+
+    from paper_2509_24949_amd import binding, synth
+
+    cases = [("tf2_3det", synth.workload("tf2_3det")), ("event/28", synth.serving_event(28)),
+             ("event/51", synth.serving_event(51))]
+    rows = []
+
+    def runs(name, w, spec, n_steps):
+        zs, sig, secs = [], [], []
+        for s in range(COVERAGE_SEEDS):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = binding.Run(spec, binding.opts_for(w, seed=w.sampler_seed + 100 + s, n_steps=n_steps, max_iter=400))
+            r.run(400)
+            z = r.logZ(200)
+            secs.append(time.perf_counter() - t0)
+            r.close()
+            zs.append(z["logZ"])
+            sig.append(z["sigma"])
+        sd, ms = float(np.std(zs, ddof=1)), float(np.mean(sig))
+        row = {"workload": name, "n_live": w.n_live, "n_delete": w.n_delete, "steps_per_dim": n_steps // w.n_dim,
+               "seeds": COVERAGE_SEEDS, "logZ_mean": float(np.mean(zs)), "logZ_std": sd, "sigma_mean": ms,
+               "std_over_sigma": sd / ms, "s_per_run": float(np.median(secs)), "logZ": zs}
+        log(f"bench: coverage {name} m = {n_steps // w.n_dim} d: log Z {row['logZ_mean']:.3f}, std {sd:.3f}, "
+            f"sigma {ms:.3f}, ratio {sd / ms:.2f}, {row['s_per_run']:.3f} s/run")
+        rows.append(row)
+
+    for name, w in cases:
+        re, im = binding.make_data(w)
+        spec = binding.ProblemSpec(w, re, im)
+        for k in COVERAGE_STEPS:
+            runs(name, w, spec, k * w.n_dim)
+    w = synth.workload("tf2_3det_rb_paper")
+    re, im = binding.make_data(w)
+    runs("tf2_3det_rb_paper", w, binding.ProblemSpec(w, re, im), w.n_steps)
+    return {"metric": "std(log Z) / mean(sigma)", "unit": "ratio", "n_gpus": 1, "higher_is_better": False,
+            "dtype": "f64", "data": "synthetic", "config": {"workload": f"coverage: {WORKLOADS['coverage']}"},
+            "rows": rows}
+
+
 def standalone_loglike(w, spec, n_probes: int = 65536, reps: int = 20) -> dict:
     """The fused waveform-plus-likelihood kernel alone on a batch of probes,
     half prior draws and half around the injection; HIP events on the
@@ -450,6 +504,9 @@ def main():
         return
     if args.workload == "scaling":
         print(json.dumps(scaling(args)), flush=True)
+        return
+    if args.workload == "coverage":
+        print(json.dumps(coverage(args)), flush=True)
         return
     w = synth.workload(args.workload)
     log(f"bench: workload {args.workload}: building data (library-injected waveform)")

@@ -107,6 +107,11 @@ typedef struct {
     const double* rb_fiducial; /* NS_LIKE_RB: host [n_dim] physical fiducial parameters */
     const double* gauss_mu;    /* NS_LIKE_GAUSS: host [n_dim] */
     double gauss_sigma;        /* NS_LIKE_GAUSS: > 0 */
+    const int* periodic;       /* host [n_dim] or NULL: 1 = the coordinate is an angle whose UNIFORM prior
+                                  covers one full period (coalescence phase, polarisation angle, right
+                                  ascension); slice moves take it modulo 1 in the unit cube, so the slice
+                                  extends across the seam of its interval (paper Section 2 names the
+                                  wrapped phase and polarisation as a tuning problem); 0 = bounded */
 } ns_problem;
 
 typedef struct {

@@ -39,6 +39,7 @@ class Problem(C.Structure):
         ("data_re", _dp), ("data_im", _dp), ("psd", _dp), ("det_geom", _dp),
         ("gmst", C.c_double), ("fixed_dist_mpc", C.c_double),
         ("rb_n_bins", C.c_int), ("rb_fiducial", _dp), ("gauss_mu", _dp), ("gauss_sigma", C.c_double),
+        ("periodic", _ip),
     ]
 
 
@@ -157,6 +158,7 @@ class ProblemSpec:
         self.dim = np.ascontiguousarray(z if data_im is None else data_im, dtype=np.float64)
         self.fid = np.ascontiguousarray(w.theta_inj if rb_fiducial is None else rb_fiducial, dtype=np.float64)
         self.mu = np.ascontiguousarray(w.gauss_mu if len(w.gauss_mu) else np.zeros(w.n_dim), dtype=np.float64)
+        self.per = np.ascontiguousarray(w.periodic, dtype=np.int32) if len(w.periodic) else None
         self.s = Problem(
             model=w.model, likelihood=w.likelihood, n_dim=w.n_dim,
             prior_kind=_i(self.kind), prior_lo=_d(self.lo), prior_hi=_d(self.hi),
@@ -164,6 +166,7 @@ class ProblemSpec:
             data_re=_d(self.dre), data_im=_d(self.dim), psd=_d(self.psd), det_geom=_d(self.geom),
             gmst=w.gmst, fixed_dist_mpc=w.fixed_dist_mpc, rb_n_bins=w.rb_n_bins, rb_fiducial=_d(self.fid),
             gauss_mu=_d(self.mu), gauss_sigma=w.gauss_sigma,
+            periodic=_i(self.per) if self.per is not None else None,
         )
 
     @property

@@ -58,6 +58,14 @@ int validate_and_model(const ns_problem* P, ModelDev* M) {
       default: return fail(NS_E_ARG, "prior %d: unknown kind %d", i, k);
     }
   }
+  if (P->periodic) {
+    for (int i = 0; i < P->n_dim; ++i) {
+      if (P->periodic[i] != 0 && P->periodic[i] != 1) return fail(NS_E_ARG, "periodic[%d] must be 0 or 1", i);
+      if (P->periodic[i] && P->prior_kind[i] != NS_PRIOR_UNIFORM)
+        return fail(NS_E_ARG, "prior %d: a periodic coordinate needs a UNIFORM prior", i);
+      if (P->periodic[i]) M->periodic |= 1u << i;
+    }
+  }
   if (P->likelihood == NS_LIKE_GAUSS) {
     if (!P->gauss_mu || !(P->gauss_sigma > 0.0)) return fail(NS_E_ARG, "Gaussian likelihood needs mu and sigma > 0");
     for (int i = 0; i < P->n_dim; ++i) M->gauss_mu[i] = P->gauss_mu[i];
@@ -646,7 +654,7 @@ int ns_noise_loglike(ns_run* r, double* out) {
 // ---- checkpoint format ------------------------------------------------------
 namespace {
 
-constexpr char kMagic[8] = {'N', 'S', 'R', 'U', 'N', 'v', '1', '\0'};
+constexpr char kMagic[8] = {'N', 'S', 'R', 'U', 'N', 'v', '2', '\0'};
 
 struct Writer {
   unsigned char* buf;
@@ -741,6 +749,7 @@ int ns_save(ns_run* r, void* buf, size_t cap, size_t* n_out) {
     w.vec(r->prob.geom);
     w.vec(r->prob.fid);
     w.vec(r->prob.mu);
+    w.vec(r->prob.per);
     w.val(st);
     w.vec(u);
     w.vec(lam);
@@ -779,6 +788,7 @@ int ns_load(ns_run** out, const void* buf, size_t size, void* stream) {
   pc.geom = rd.vec<double>(9 * MAX_DET);
   pc.fid = rd.vec<double>(MAX_DIM);
   pc.mu = rd.vec<double>(MAX_DIM);
+  pc.per = rd.vec<int>(MAX_DIM);
   const DevState st = rd.val<DevState>();
   auto u = rd.vec<double>(big), lam = rd.vec<double>(big), du = rd.vec<double>(big), dlam = rd.vec<double>(big),
        dlogx = rd.vec<double>(big), dlogw = rd.vec<double>(big);
@@ -800,6 +810,8 @@ int ns_load(ns_run** out, const void* buf, size_t size, void* stream) {
   P.det_geom = pc.geom.empty() ? nullptr : pc.geom.data();
   P.rb_fiducial = pc.fid.empty() ? nullptr : pc.fid.data();
   P.gauss_mu = pc.mu.empty() ? nullptr : pc.mu.data();
+  P.periodic = pc.per.empty() ? nullptr : pc.per.data();
+  if (!pc.per.empty() && pc.per.size() != nd) return fail(NS_E_ARG, "checkpoint periodic mask size");
   if (P.det_geom && pc.geom.size() != 9 * (size_t)P.n_det) return fail(NS_E_ARG, "checkpoint detector geometry size");
   if (P.rb_fiducial && pc.fid.size() != nd) return fail(NS_E_ARG, "checkpoint fiducial size");
   if (P.gauss_mu && pc.mu.size() != nd) return fail(NS_E_ARG, "checkpoint Gaussian mean size");

@@ -127,7 +127,13 @@ struct ModelDev {
   double gauss_inv2s2, gauss_norm;   // 1/(2 s^2), -d/2 ln(2 pi s^2)
   int mixed;                   // float bulk arithmetic (double phase, setup and evidence)
   double dw_scale;             // power of two: the float data table holds dw * dw_scale
+  unsigned periodic;           // bit i: unit-cube coordinate i wraps around (modulo 1)
 };
+
+// Coordinate i of a point on a slice line: taken modulo 1 when periodic.
+__device__ inline double cube_coord(unsigned periodic, int i, double y) {
+  return ((periodic >> i) & 1u) ? y - floor(y) : y;
+}
 
 // Physical quantities of one parameter point, reduced to what the strain needs.
 struct Phys {

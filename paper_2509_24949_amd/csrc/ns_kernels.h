@@ -1227,10 +1227,12 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
     bool cin = valid;
 #pragma unroll
     for (int i = 0; i < MAX_DIM; ++i) {
-      const double yi = fma(tt, dr[i], xr[i]);
+      // a periodic coordinate is taken modulo 1 and is always inside
+      const bool per = (M.periodic >> i) & 1u;
+      const double yi = cube_coord(M.periodic, i, fma(tt, dr[i], xr[i]));
       const bool act = i < d;
       y[i] = act ? yi : 0.0;
-      cin = cin && (!act || (yi >= 0.0 && yi <= 1.0));
+      cin = cin && (!act || per || (yi >= 0.0 && yi <= 1.0));
     }
     if (!cin) {
 #pragma unroll
@@ -1587,7 +1589,7 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
               count((int)res[NW + i]);
               const double li = res[i];
               if (li > lstar) {
-                if (tid < d) sX[tid] = fma(tq, dir[tid], sX[tid]);
+                if (tid < d) sX[tid] = cube_coord(M.periodic, tid, fma(tq, dir[tid], sX[tid]));
                 lx = li;
                 accepted = true;
                 break;
@@ -1613,7 +1615,7 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
           if (in1) {
             count(k1);
             if (l1 > lstar) {
-              if (tid < d) sX[tid] = fma(t1, dir[tid], sX[tid]);
+              if (tid < d) sX[tid] = cube_coord(M.periodic, tid, fma(t1, dir[tid], sX[tid]));
               lx = l1;
               accepted = true;
               break;
@@ -1626,7 +1628,7 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
           if (in2) {
             count(k2);
             if (l2 > lstar) {
-              if (tid < d) sX[tid] = fma(t2, dir[tid], sX[tid]);
+              if (tid < d) sX[tid] = cube_coord(M.periodic, tid, fma(t2, dir[tid], sX[tid]));
               lx = l2;
               accepted = true;
               break;
@@ -1643,7 +1645,7 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
           if (inside(q)) {
             const double ly = eval(q);
             if (ly > lstar) {
-              if (tid < d) sX[tid] = fma(tt, dir[tid], sX[tid]);
+              if (tid < d) sX[tid] = cube_coord(M.periodic, tid, fma(tt, dir[tid], sX[tid]));
               lx = ly;
               accepted = true;
               break;
@@ -1688,7 +1690,7 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
           if (inside(q)) {
             const double ly = eval(q);
             if (ly > lstar) {
-              if (tid < d) sX[tid] = fma(tt, dir[tid], sX[tid]);
+              if (tid < d) sX[tid] = cube_coord(M.periodic, tid, fma(tt, dir[tid], sX[tid]));
               lx = ly;
               accepted = true;
               ++a;

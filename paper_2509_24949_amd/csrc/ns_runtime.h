@@ -42,7 +42,7 @@ struct DevMem {
 // A problem with private copies of every host array it references.
 struct ProblemCopy {
   ns_problem P{};
-  std::vector<int> kind;
+  std::vector<int> kind, per;
   std::vector<double> lo, hi, dre, dim, psd, geom, fid, mu;
 
   // p must have passed validation (array lengths follow from its sizes).
@@ -57,6 +57,12 @@ struct ProblemCopy {
     P.prior_lo = lo.data();
     P.prior_hi = hi.data();
     P.data_re = P.data_im = P.psd = P.det_geom = P.rb_fiducial = P.gauss_mu = nullptr;
+    P.periodic = nullptr;
+    per.clear();
+    if (p.periodic) {
+      per.assign(p.periodic, p.periodic + nd);
+      P.periodic = per.data();
+    }
     if (nbd) {
       dre.assign(p.data_re, p.data_re + nbd);
       dim.assign(p.data_im, p.data_im + nbd);

@@ -258,6 +258,18 @@ def test_rb_iterations_lockstep(torch_cuda):
     _compare_runs(ro, rg)
 
 
+def test_paper_settings_lockstep(torch_cuda):
+    """The paper's settings (n_live 3000, n_delete 1500, chains of 10 d) with
+    the wrapped phase, polarisation and right ascension follow the oracle in
+    lockstep; the wrapped coordinates stay in the unit interval."""
+    w = synth.workload("tf2_3det_rb_paper")
+    orc, spec = _pair(w)
+    ro, rg = _lockstep(w, orc, spec, 2)
+    _compare_runs(ro, rg)
+    u, _ = rg.live()
+    assert u.min() >= 0.0 and u.max() <= 1.0
+
+
 def test_rb_rejects_degenerate_binning(torch_cuda):
     w = synth.workload("tf2_3det_rb")
     w.rb_n_bins = 1000                  # more coarse bins than the grid can separate at low frequency
