@@ -47,6 +47,7 @@ class Opts(C.Structure):
         ("n_live", C.c_int), ("n_delete", C.c_int), ("n_steps", C.c_int), ("slice_width", C.c_double),
         ("max_stepout", C.c_int), ("max_shrink", C.c_int), ("term_frac", C.c_double),
         ("seed", C.c_uint64), ("run_id", C.c_uint64), ("max_iter", C.c_int), ("n_threads", C.c_int),
+        ("kernel", C.c_int), ("walk_accept", C.c_int), ("walk_max", C.c_int),
     ]
 
 
@@ -86,6 +87,8 @@ def load(path: str):
     L.orc_logZ.argtypes = [C.c_void_p, C.c_int, _dp, _dp, _dp, _dp]
     L.orc_samples.argtypes = [C.c_void_p, C.c_long, _dp, _dp, _dp, C.POINTER(C.c_long)]
     L.orc_information.argtypes = [C.c_void_p, _dp, _dp]
+    L.orc_walk_from.argtypes = [C.c_void_p, C.c_void_p, _dp, C.c_int, C.c_int, _dp, _dp, C.c_double, C.c_uint64,
+                                C.c_uint64, C.POINTER(C.c_long)]
     L.orc_resample.argtypes = [C.c_void_p, C.c_long, _ip, _dp]
     L.orc_pn_params.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp]
     L.orc_free.argtypes = [C.c_void_p]
@@ -244,13 +247,16 @@ def antenna(geom9, ra, dec, psi, gmst):
 
 
 def opts_for(w, n_threads: int = 1, seed=None, run_id: int = 0, max_iter: int = 1000, term_frac=None,
-             n_live=None, n_delete=None, n_steps=None):
+             n_live=None, n_delete=None, n_steps=None, kernel=None, walk_accept=None, walk_max=None):
     return Opts(
         n_live=w.n_live if n_live is None else n_live, n_delete=w.n_delete if n_delete is None else n_delete,
         n_steps=w.n_steps if n_steps is None else n_steps, slice_width=w.slice_width,
         max_stepout=w.max_stepout, max_shrink=w.max_shrink,
         term_frac=w.term_frac if term_frac is None else term_frac,
         seed=w.sampler_seed if seed is None else seed, run_id=run_id, max_iter=max_iter, n_threads=n_threads,
+        kernel=w.kernel if kernel is None else kernel,
+        walk_accept=w.walk_accept if walk_accept is None else walk_accept,
+        walk_max=w.walk_max if walk_max is None else walk_max,
     )
 
 
@@ -345,6 +351,20 @@ class Run:
         if getattr(self, "h", None):
             lib().orc_free(self.h)
             self.h = None
+
+
+def walk_from(prob: OracleProblem, opts: Opts, pop, n_prop: int, x, lx, lstar, t: int = 0, j: int = 0):
+    """One random-walk chain of n_prop proposals from x over the population
+    pop (all survivors); returns (x, lambda, likelihood calls, accepted)."""
+    pop = np.ascontiguousarray(pop, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64).copy()
+    lxc = C.c_double(lx)
+    ev = C.c_long()
+    acc = lib().orc_walk_from(prob.ref, C.byref(opts), _d(pop), len(pop), n_prop, _d(x), C.byref(lxc), lstar, t, j,
+                              C.byref(ev))
+    if acc < 0:
+        raise ValueError("orc_walk_from failed")
+    return x, lxc.value, ev.value, acc
 
 
 def slice_update_fixed(prob: OracleProblem, opts: Opts, x, lx, direction, lstar, uw, uj, ushr):

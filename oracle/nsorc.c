@@ -50,7 +50,7 @@ static const double PC_M = 3.0856775814913673e16;          /* parsec, m */
 static const double EULER_GAMMA = 0.57721566490153286061;
 
 /* RNG purposes (high 16 bits of the last counter word). */
-enum { P_INIT = 1, P_PICK = 2, P_DIR = 3, P_WIDTH = 4, P_SHRINK = 5, P_RESAMPLE = 6, P_SIGMA = 7 };
+enum { P_INIT = 1, P_PICK = 2, P_DIR = 3, P_WIDTH = 4, P_SHRINK = 5, P_RESAMPLE = 6, P_SIGMA = 7, P_WALK = 8 };
 
 /* ------------------------------------------------------------ Philox4x64-10
  * Counter-based generator of Salmon, Moraes, Dror and Shaw (SC'11): ten
@@ -565,6 +565,7 @@ struct orc_run {
     double* lam;     /* [n] */
     double logX, logZ, H;
     int iter, done;
+    int walk_len;    /* random-walk kernel: proposals per chain this iteration */
     long n_evals;
     long cap, n_dead;
     double* du; double* dlam; double* dlogx; double* dlogw;
@@ -648,6 +649,53 @@ static void slice_update(const orc_run* r, double* x, double* lx, const double* 
     }
 }
 
+/* Random-walk alternative to the slice move: bilby's dynesty sampler evolves
+ * a particle with a customised random walk (paper Section 2); read here as
+ * differential-evolution proposals (ter Braak's DE-MC) from the surviving
+ * live points.  Proposal s of chain j in iteration t takes two distinct
+ * survivors a, b and moves to y = x + gamma (u_a - u_b), with gamma = 1 (a
+ * jump between modes) or 2.38 / sqrt(2 d) (the differential-evolution
+ * scale), each with probability 1/2; periodic coordinates wrap.  The
+ * proposal is symmetric, so under the constrained prior (flat on the slice
+ * {in the cube, lambda > L*}) it is accepted iff it lies in the slice.
+ * Every chain of an iteration makes the same number of proposals, n_prop
+ * (stopping at a count of acceptances instead would favour points where
+ * moves are easy); *n_acc receives the accepted ones. */
+static void walk_update(const orc_run* r, const int* surv, int ns, uint64_t t, uint64_t j, int n_prop, double* x,
+                        double* lx, double lstar, long* evals, long* n_acc) {
+    int d = r->d;
+    double y[32], ly = 0.0;
+    double g_de = 2.38 / sqrt(2.0 * d);
+    for (int s = 0; s < n_prop; ++s) {
+        uint64_t w[4];
+        draw(&r->key, t, j, (uint64_t)s, P_WALK, 0, w);
+        int ia = (int)floor(to_unif(w[0]) * ns);
+        int ib = (int)floor(to_unif(w[1]) * (ns - 1));
+        if (ib >= ia) ++ib;
+        double g = to_unif(w[2]) < 0.5 ? 1.0 : g_de;
+        const double* ua = r->u + (long)surv[ia] * d;
+        const double* ub = r->u + (long)surv[ib] * d;
+        for (int i = 0; i < d; ++i) {
+            y[i] = fma(g, ua[i] - ub[i], x[i]);
+            if (is_periodic(&r->p, i)) y[i] -= floor(y[i]);
+        }
+        if (in_slice(r, y, lstar, &ly, evals)) {
+            memcpy(x, y, sizeof(double) * d);
+            *lx = ly;
+            ++*n_acc;
+        }
+    }
+}
+
+/* Chain length of the next iteration: enough proposals for walk_accept
+ * acceptances at this iteration's acceptance rate (accepted / proposed over
+ * all chains), at least 1 and at most walk_max; integer arithmetic. */
+static int next_walk_len(const orc_opts* o, long accepted, long proposed) {
+    if (accepted <= 0) return o->walk_max;
+    long want = ((long)o->walk_accept * proposed + accepted - 1) / accepted;
+    return want < 1 ? 1 : (want > o->walk_max ? o->walk_max : (int)want);
+}
+
 typedef struct { const rngkey* key; uint64_t t, j, s; } shrink_ctx;
 
 static double shrink_uniform(void* vctx, int a) {
@@ -690,6 +738,8 @@ static int cholesky(int d, const double* A, double* L) {
 int orc_init(orc_run** out, const orc_problem* p, const orc_opts* o) {
     *out = NULL;
     if (p->n_dim < 1 || p->n_dim > 32 || o->n_live < 2 || o->n_delete < 1 || o->n_delete >= o->n_live) return -1;
+    if (o->kernel == ORC_KERNEL_WALK && (o->n_live - o->n_delete < 2 || o->walk_accept < 1 || o->walk_max < 1))
+        return -1;
     orc_run* r = (orc_run*)calloc(1, sizeof(orc_run));
     r->p = *p;
     r->o = *o;
@@ -718,6 +768,7 @@ int orc_init(orc_run** out, const orc_problem* p, const orc_opts* o) {
         evals += e;
     }
     r->n_evals = evals;
+    r->walk_len = o->walk_accept;
     r->logX = 0.0;
     r->logZ = -INFINITY;
     r->H = 0.0;
@@ -802,8 +853,8 @@ static void iterate(orc_run* r) {
     double* newu = (double*)malloc(sizeof(double) * k * d);
     double* newl = (double*)malloc(sizeof(double) * k);
     int nt = r->o.n_threads < 1 ? 1 : r->o.n_threads;
-    long evals = 0;
-#pragma omp parallel for schedule(dynamic, 1) num_threads(nt) reduction(+ : evals)
+    long evals = 0, acc_walk = 0;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nt) reduction(+ : evals, acc_walk)
     for (int j = 0; j < k; ++j) {
         uint64_t w[4];
         draw(&r->key, t, (uint64_t)j, 0, P_PICK, 0, w);
@@ -811,7 +862,9 @@ static void iterate(orc_run* r) {
         double x[32], lx = r->lam[start];
         memcpy(x, r->u + start * d, sizeof(double) * d);
         long e = 0;
-        for (int s = 0; s < r->o.n_steps; ++s) {
+        if (r->o.kernel == ORC_KERNEL_WALK)
+            walk_update(r, surv, n - k, t, (uint64_t)j, r->walk_len, x, &lx, lstar, &e, &acc_walk);
+        for (int s = 0; s < r->o.n_steps && r->o.kernel == ORC_KERNEL_SLICE; ++s) {
             double z[32], dir[32], nrm = 0.0;
             normals(&r->key, t, (uint64_t)j, (uint64_t)s, d, z);
             for (int i = 0; i < d; ++i) nrm += z[i] * z[i];
@@ -832,6 +885,7 @@ static void iterate(orc_run* r) {
         evals += e;
     }
     r->n_evals += evals;
+    if (r->o.kernel == ORC_KERNEL_WALK) r->walk_len = next_walk_len(&r->o, acc_walk, (long)k * r->walk_len);
     /* Refill: chain j's final state replaces the j-th lowest dead slot. */
     for (int j = 0; j < k; ++j) {
         memcpy(r->u + dead[j] * d, newu + j * d, sizeof(double) * d);
@@ -1037,6 +1091,26 @@ void orc_free(orc_run* r) {
     free(r->u); free(r->lam);
     free(r->du); free(r->dlam); free(r->dlogx); free(r->dlogw); free(r->diter); free(r->dslot); free(r->dnlive);
     free(r);
+}
+
+int orc_walk_from(const orc_problem* p, const orc_opts* o, const double* pop, int npop, int n_prop, double* x,
+                  double* lx, double lstar, uint64_t t, uint64_t j, long* evals) {
+    if (npop < 2 || n_prop < 0 || p->likelihood == ORC_LIKE_RB) return -1;
+    orc_run r;
+    memset(&r, 0, sizeof(r));
+    r.p = *p;
+    r.o = *o;
+    r.d = p->n_dim;
+    r.key.key[0] = o->seed;
+    r.key.key[1] = o->run_id;
+    r.u = (double*)pop;
+    int* surv = (int*)malloc(sizeof(int) * npop);
+    for (int i = 0; i < npop; ++i) surv[i] = i;
+    *evals = 0;
+    long acc = 0;
+    walk_update(&r, surv, npop, t, j, n_prop, x, lx, lstar, evals, &acc);
+    free(surv);
+    return (int)acc;
 }
 
 /* -------------------------------------------------------- test entry point

@@ -41,6 +41,8 @@ typedef struct {
     const int* periodic;        /* [n_dim] or NULL: 1 = the unit-cube coordinate wraps around */
 } orc_problem;
 
+enum { ORC_KERNEL_SLICE = 0, ORC_KERNEL_WALK = 1 };
+
 typedef struct {
     int n_live, n_delete, n_steps;
     double slice_width;
@@ -49,6 +51,8 @@ typedef struct {
     uint64_t seed, run_id;
     int max_iter;
     int n_threads;
+    int kernel;                 /* ORC_KERNEL_SLICE, or ORC_KERNEL_WALK (random-walk chains) */
+    int walk_accept, walk_max;  /* walk: target accepted proposals per chain, chain-length cap */
 } orc_opts;
 
 typedef struct orc_run orc_run;
@@ -120,6 +124,13 @@ int orc_samples(const orc_run* r, long cap, double* theta, double* logl, double*
 /* Equal-weight samples by systematic resampling of the weighted samples. */
 int orc_resample(const orc_run* r, long n_out, int* idx, double* theta);
 void orc_free(orc_run* r);
+
+/* One random-walk chain (ORC_KERNEL_WALK) of n_prop proposals from x over
+ * the population pop [npop][n_dim] (every point a survivor), with the draws
+ * of chain j in iteration t of the key (seed, run_id) (test hook); returns
+ * the accepted count, or -1. */
+int orc_walk_from(const orc_problem* p, const orc_opts* o, const double* pop, int npop, int n_prop, double* x,
+                  double* lx, double lstar, uint64_t t, uint64_t j, long* evals);
 
 /* One slice update with a caller-supplied direction and uniforms (test hook). */
 int orc_slice_update_fixed(const orc_problem* p, const orc_opts* o, double* x, double* lx, const double* dir,

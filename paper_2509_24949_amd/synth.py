@@ -127,6 +127,12 @@ class Workload:
     # per coordinate: 1 = the unit-cube coordinate wraps around (its prior is
     # uniform over one full period); empty = none
     periodic: np.ndarray = field(default_factory=lambda: np.zeros(0, dtype=np.int32))
+    # chain kernel: 0 slice sampling (the paper's), 1 random walk with
+    # differential-evolution proposals (walk_accept accepted proposals per
+    # chain, at most walk_max proposals)
+    kernel: int = 0
+    walk_accept: int = 20
+    walk_max: int = 400
 
     @property
     def n_dim(self) -> int:

@@ -51,7 +51,63 @@ MUTATIONS = [
      "if (is_periodic(p, i)) y[i] -= 0.0;", "wrap"),
     ("wrap to the centred interval", "if (is_periodic(p, i)) y[i] -= floor(y[i]);",
      "if (is_periodic(p, i)) y[i] -= floor(y[i] + 0.5);", "wrap"),
+    ("walk scale", "double g_de = 2.38 / sqrt(2.0 * d);", "double g_de = 2.4 / sqrt(2.0 * d);", "walk_step"),
+    ("walk pair not distinct", "if (ib >= ia) ++ib;", "if (ib > ia) ++ib;", "walk_step"),
+    ("walk stops at a count of acceptances", "for (int s = 0; s < n_prop; ++s) {",
+     "for (int s = 0; s < n_prop && *n_acc < 4; ++s) {", "walk_invariance"),
 ]
+
+
+def _walk(L, p, o, pop, n_prop, x0, lstar, t, j):
+    x = np.ascontiguousarray(x0, dtype=np.float64).copy()
+    lx, ev = C.c_double(0.0), C.c_long()
+    acc = L.orc_walk_from(p.ref, C.byref(o), pop.ctypes.data_as(oracle._dp), len(pop), n_prop,
+                          x.ctypes.data_as(oracle._dp), C.byref(lx), lstar, t, j, C.byref(ev))
+    return x, ev.value, acc
+
+
+def _walk_step_bad(L):
+    """The hand-computed single proposals of test_walk_step_by_hand."""
+    d = 2
+    w = synth.gauss_workload(d, 10.0)
+    w.kernel, w.walk_accept, w.walk_max = 1, 1, 1
+    o = oracle.opts_for(w)
+    p = oracle.OracleProblem(w)
+    pop = np.array([[0.1, 0.2], [0.7, 0.9], [0.4, 0.35], [0.55, 0.05]])
+    x0 = np.array([0.5, 0.5])
+    for j in range(12):
+        words = oracle.philox([0, j, 0, 8 << 48], [w.sampler_seed, 0])
+        u = [(x >> 11) * 2.0**-53 for x in words]
+        a = int(math.floor(u[0] * 4))
+        b = int(math.floor(u[1] * 3))
+        b += b >= a
+        g = 1.0 if u[2] < 0.5 else 2.38 / math.sqrt(2 * d)
+        y = x0 + g * (pop[a] - pop[b])
+        inside = bool(np.all((y >= 0) & (y <= 1)))
+        x, _, _ = _walk(L, p, o, pop, 1, x0, -np.inf, 0, j)
+        if np.max(np.abs(x - (y if inside else x0))) > 1e-15:
+            return True
+    return False
+
+
+def _walk_invariance_bad(L):
+    """The constrained-prior invariance of test_walk_chains_keep_the_constrained_prior."""
+    from scipy import stats
+
+    d, s, rho = 3, 0.1, 0.3
+    w = synth.gauss_workload(d, s)
+    w.kernel, w.walk_accept, w.walk_max = 1, 12, 400
+    o = oracle.opts_for(w)
+    p = oracle.OracleProblem(w)
+    rng = np.random.default_rng(4)
+    pop = rng.uniform(0.5 - rho, 0.5 + rho, (4000, d))
+    pop = np.ascontiguousarray(pop[np.linalg.norm(pop - 0.5, axis=1) < rho][:500])
+    c = 0.5 * d * math.log(2 * math.pi * s * s)
+    lstar = -(rho**2) / (2 * s * s) - c
+    starts = pop[rng.integers(0, len(pop), 1500)]
+    pts = np.array([_walk(L, p, o, pop, 30, starts[j], lstar, 2, j)[0] for j in range(1500)])
+    r = np.linalg.norm(pts - 0.5, axis=1)
+    return stats.kstest((r / rho) ** d, "uniform").pvalue <= 1e-3
 
 
 def _wrap_bad(L):
@@ -122,6 +178,8 @@ CHECKS = {
     "posterior": _posterior_bad,
     "resample": _resample_bad,
     "wrap": _wrap_bad,
+    "walk_step": _walk_step_bad,
+    "walk_invariance": _walk_invariance_bad,
 }
 
 

@@ -903,3 +903,83 @@ def test_periodic_coordinates_cover_one_period():
         c[:, i] = rng.random(len(u))
         lc = orc.loglike_batch(c, 4)
         assert np.max(np.abs(lc - la)) > 1e-3      # the coordinate matters
+
+
+def _walk_opts(w, accept, cap):
+    w.kernel, w.walk_accept, w.walk_max = 1, accept, cap
+    return oracle.opts_for(w)
+
+
+def test_walk_step_by_hand():
+    """One proposal of the random-walk kernel worked by hand from its three
+    draws (Philox block of purpose WALK for iteration 0, chain j, step 0):
+    survivors a and b, and the scale 1 or 2.38 / sqrt(2 d)."""
+    d = 2
+    w = synth.gauss_workload(d, 10.0)
+    o = _walk_opts(w, 1, 1)
+    p = oracle.OracleProblem(w)
+    pop = np.array([[0.1, 0.2], [0.7, 0.9], [0.4, 0.35], [0.55, 0.05]])
+    x0 = np.array([0.5, 0.5])
+    seen = set()
+    for j in range(12):
+        words = oracle.philox([0, j, 0, 8 << 48], [w.sampler_seed, 0])
+        u = [(x >> 11) * 2.0**-53 for x in words]
+        a = int(math.floor(u[0] * 4))
+        b = int(math.floor(u[1] * 3))
+        b += b >= a
+        g = 1.0 if u[2] < 0.5 else 2.38 / math.sqrt(2 * d)
+        y = x0 + g * (pop[a] - pop[b])
+        inside = bool(np.all((y >= 0) & (y <= 1)))
+        x, lx, ev, acc = oracle.walk_from(p, o, pop, 1, x0, 0.0, -np.inf, t=0, j=j)
+        assert ev == acc == (1 if inside else 0)
+        np.testing.assert_allclose(x, y if inside else x0, rtol=0, atol=1e-15)
+        seen.add((inside, g == 1.0))
+    assert len(seen) >= 3
+
+
+def test_walk_chains_keep_the_constrained_prior():
+    """Chains of a fixed number of proposals leave the constrained prior
+    invariant: started uniform in the slice {lambda > L*} of an isotropic
+    Gaussian (a ball of radius rho) with a population uniform in the ball,
+    they stay uniform in it, (r / rho)^d ~ U[0, 1] (KS); and with no
+    constraint, chains from one corner become uniform on the cube."""
+    d, s, rho = 3, 0.1, 0.3
+    w = synth.gauss_workload(d, s)
+    o = _walk_opts(w, 12, 400)
+    p = oracle.OracleProblem(w)
+    rng = np.random.default_rng(4)
+    pop = rng.uniform(0.5 - rho, 0.5 + rho, (4000, d))
+    pop = pop[np.linalg.norm(pop - 0.5, axis=1) < rho][:500]
+    c = 0.5 * d * math.log(2 * math.pi * s * s)
+    lstar = -(rho**2) / (2 * s * s) - c
+    starts = pop[rng.integers(0, len(pop), 1500)]
+    pts = np.array([oracle.walk_from(p, o, pop, 30, starts[j], 0.0, lstar, t=2, j=j)[0] for j in range(1500)])
+    r = np.linalg.norm(pts - 0.5, axis=1)
+    assert r.max() < rho
+    assert stats.kstest((r / rho) ** d, "uniform").pvalue > 1e-3
+    assert np.mean(np.any(pts != starts, axis=1)) > 0.9
+    pop = rng.random((400, d))
+    pts = np.array([oracle.walk_from(p, o, pop, 40, [0.15, 0.8, 0.5], 0.0, -np.inf, t=1, j=j)[0] for j in range(1500)])
+    for i in range(d):
+        assert stats.kstest(pts[:, i], "uniform").pvalue > 1e-3
+
+
+def test_walk_kernel_gauss_evidence_zscores():
+    """Nested sampling with the random-walk kernel: log Z of a Gaussian in the
+    unit cube against the erf closed form over 16 seeds (z-scores with the
+    sampler's error bar ~ N(0, 1))."""
+    d, s = 3, 0.08
+    mu = np.array([0.15, 0.5, 0.6])
+    w = synth.gauss_workload(d, s, mu=mu, n_live=200, n_delete=100)
+    w.kernel, w.walk_accept, w.walk_max = 1, 25, 500
+    p = oracle.OracleProblem(w)
+    zc = _closed_gauss(mu, s)
+    z = []
+    for seed in range(16):
+        r = oracle.Run(p, oracle.opts_for(w, seed=300 + seed, n_threads=4))
+        r.run()
+        res = r.logZ(200)
+        z.append((res["logZ"] - zc) / res["sigma"])
+    z = np.array(z)
+    assert abs(z.mean()) < 0.8, z
+    assert 0.4 < z.std() < 1.8, z
