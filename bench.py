@@ -50,6 +50,8 @@ WORKLOADS = {
     "tf2_3det_rb": _GRID2 + ", relative binning (128 geometric bins), n_live 1000, n_delete 500, 55 slice steps, FP64",
     "tf2_3det_mixed": _GRID2 + ", full-grid Whittle, n_live 2000, n_delete 1000, 55 slice steps, mixed precision",
     "tf2_3det_rb_mixed": _GRID2 + ", relative binning (128 bins), n_live 2000, n_delete 1000, 55 slice steps, mixed precision",
+    "tf2_3det_rb_walk": _GRID2 + ", relative binning (128 bins), n_live 1000, n_delete 500, random-walk chains "
+                        "(differential-evolution proposals, 60 accepted per chain), FP64",
     "tf2_3det_rb_paper": _GRID2 + ", relative binning (128 bins), the paper's settings: n_live 3000, n_delete 1500, "
                          "110 slice steps (10 per dimension), phase, polarisation and right ascension wrapped, FP64",
     "scaling": "runtime of complete tf2_3det_rb runs against n_live at n_delete = n_live/2 and against n_delete "

@@ -87,6 +87,23 @@ enum { NS_LIKE_FULL = 0, NS_LIKE_RB = 1, NS_LIKE_GAUSS = 2 };
 /* Arithmetic: all double, or the mixed form (float bulk, double phase and evidence). */
 enum { NS_FP64 = 0, NS_MIXED = 1 };
 
+/* Chain kernel that refills the deleted points (paper Section 2):
+ *   SLICE  constrained hit-and-run slice sampling, n_steps steps per chain,
+ *          directions tuned by the particle covariance (the paper's NSS);
+ *   WALK   the random-walk alternative of bilby's sampler, read as
+ *          differential-evolution moves: each proposal is x + g (u_a - u_b)
+ *          for two distinct surviving live points a, b, with g = 1 or
+ *          2.38 / sqrt(2 n_dim) with probability 1/2 each, times a factor
+ *          uniform on [0.9, 1.1], accepted iff
+ *          in the unit cube (periodic coordinates wrap) with lambda > L*
+ *          (a pair of survivors at one point is a null move, not evaluated).
+ *          Every chain of an iteration makes the same number of proposals,
+ *          set for the next iteration to walk_accept / (the iteration's
+ *          acceptance rate), rounded up, within [1, walk_max]; the first
+ *          iteration makes walk_accept.  Needs n_live - n_delete >= 2.
+ *          Not supported by the server. */
+enum { NS_KERNEL_SLICE = 0, NS_KERNEL_WALK = 1 };
+
 typedef struct {
     int model;                 /* NS_MODEL_*; ignored for NS_LIKE_GAUSS */
     int likelihood;            /* NS_LIKE_* */
@@ -126,6 +143,9 @@ typedef struct {
     uint64_t run_id;     /* Philox key word 1 */
     int max_iter;        /* iteration capacity of the dead-point record (>= 1) */
     int precision;       /* NS_FP64 or NS_MIXED */
+    int kernel;          /* NS_KERNEL_SLICE (the paper's), or NS_KERNEL_WALK */
+    int walk_accept;     /* NS_KERNEL_WALK: target accepted proposals per chain (>= 1) */
+    int walk_max;        /* NS_KERNEL_WALK: cap on proposals per chain (>= 1) */
 } ns_opts;
 
 typedef struct ns_run ns_run;

@@ -655,12 +655,17 @@ static void slice_update(const orc_run* r, double* x, double* lx, const double* 
  * live points.  Proposal s of chain j in iteration t takes two distinct
  * survivors a, b and moves to y = x + gamma (u_a - u_b), with gamma = 1 (a
  * jump between modes) or 2.38 / sqrt(2 d) (the differential-evolution
- * scale), each with probability 1/2; periodic coordinates wrap.  The
+ * scale), each with probability 1/2, times a factor uniform on [0.9, 1.1]
+ * (so that a move cannot land exactly on another live point); periodic
+ * coordinates wrap.  The
  * proposal is symmetric, so under the constrained prior (flat on the slice
  * {in the cube, lambda > L*}) it is accepted iff it lies in the slice.
  * Every chain of an iteration makes the same number of proposals, n_prop
  * (stopping at a count of acceptances instead would favour points where
- * moves are easy); *n_acc receives the accepted ones. */
+ * moves are easy); *n_acc receives the accepted ones.  Two survivors at the
+ * same point (a chain that never moved leaves a copy of its start) give a
+ * zero difference: that proposal is the current point itself, a null move,
+ * neither evaluated nor accepted. */
 static void walk_update(const orc_run* r, const int* surv, int ns, uint64_t t, uint64_t j, int n_prop, double* x,
                         double* lx, double lstar, long* evals, long* n_acc) {
     int d = r->d;
@@ -672,9 +677,12 @@ static void walk_update(const orc_run* r, const int* surv, int ns, uint64_t t, u
         int ia = (int)floor(to_unif(w[0]) * ns);
         int ib = (int)floor(to_unif(w[1]) * (ns - 1));
         if (ib >= ia) ++ib;
-        double g = to_unif(w[2]) < 0.5 ? 1.0 : g_de;
+        double g = (to_unif(w[2]) < 0.5 ? 1.0 : g_de) * fma(0.2, to_unif(w[3]), 0.9);
         const double* ua = r->u + (long)surv[ia] * d;
         const double* ub = r->u + (long)surv[ib] * d;
+        int same = 1;
+        for (int i = 0; i < d; ++i) same = same && ua[i] == ub[i];
+        if (same) continue;
         for (int i = 0; i < d; ++i) {
             y[i] = fma(g, ua[i] - ub[i], x[i]);
             if (is_periodic(&r->p, i)) y[i] -= floor(y[i]);
@@ -768,7 +776,7 @@ int orc_init(orc_run** out, const orc_problem* p, const orc_opts* o) {
         evals += e;
     }
     r->n_evals = evals;
-    r->walk_len = o->walk_accept;
+    r->walk_len = o->walk_accept < o->walk_max ? o->walk_accept : o->walk_max;   /* first iteration */
     r->logX = 0.0;
     r->logZ = -INFINITY;
     r->H = 0.0;

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libns.so")
 
 NS_OK, NS_E_ARG, NS_E_OOM, NS_E_HIP, NS_E_CAPACITY, NS_E_STATE = 0, -1, -2, -3, -4, -5
 NS_FP64, NS_MIXED = 0, 1
+NS_KERNEL_SLICE, NS_KERNEL_WALK = 0, 1
 NS_LOGLIKE_NOALLOC_MAX = 16384
 
 _dp = C.POINTER(C.c_double)
@@ -48,6 +49,7 @@ class Opts(C.Structure):
         ("n_live", C.c_int), ("n_delete", C.c_int), ("n_steps", C.c_int), ("slice_width", C.c_double),
         ("max_stepout", C.c_int), ("max_shrink", C.c_int), ("term_frac", C.c_double),
         ("seed", C.c_uint64), ("run_id", C.c_uint64), ("max_iter", C.c_int), ("precision", C.c_int),
+        ("kernel", C.c_int), ("walk_accept", C.c_int), ("walk_max", C.c_int),
     ]
 
 
@@ -175,7 +177,7 @@ class ProblemSpec:
 
 
 def opts_for(w: synth.Workload, seed=None, run_id: int = 0, max_iter: int = 1000, term_frac=None, n_live=None,
-             n_delete=None, n_steps=None, precision=None) -> Opts:
+             n_delete=None, n_steps=None, precision=None, kernel=None, walk_accept=None, walk_max=None) -> Opts:
     return Opts(
         n_live=w.n_live if n_live is None else n_live, n_delete=w.n_delete if n_delete is None else n_delete,
         n_steps=w.n_steps if n_steps is None else n_steps, slice_width=w.slice_width,
@@ -183,6 +185,9 @@ def opts_for(w: synth.Workload, seed=None, run_id: int = 0, max_iter: int = 1000
         term_frac=w.term_frac if term_frac is None else term_frac,
         seed=w.sampler_seed if seed is None else seed, run_id=run_id, max_iter=max_iter,
         precision=w.precision if precision is None else precision,
+        kernel=w.kernel if kernel is None else kernel,
+        walk_accept=w.walk_accept if walk_accept is None else walk_accept,
+        walk_max=w.walk_max if walk_max is None else walk_max,
     )
 
 

@@ -158,6 +158,13 @@ int validate_opts(const ns_opts* o) {
   if (o->max_stepout < 1 || o->max_shrink < 1) return fail(NS_E_ARG, "max_stepout and max_shrink must be >= 1");
   if (o->max_iter < 1) return fail(NS_E_ARG, "max_iter must be >= 1");
   if (o->precision != NS_FP64 && o->precision != NS_MIXED) return fail(NS_E_ARG, "precision must be NS_FP64 or NS_MIXED");
+  if (o->kernel != NS_KERNEL_SLICE && o->kernel != NS_KERNEL_WALK)
+    return fail(NS_E_ARG, "kernel must be NS_KERNEL_SLICE or NS_KERNEL_WALK");
+  if (o->kernel == NS_KERNEL_WALK) {
+    if (o->n_live - o->n_delete < 2) return fail(NS_E_ARG, "the random walk needs n_live - n_delete >= 2");
+    if (o->walk_accept < 1 || o->walk_max < 1 || o->walk_max > (1 << 20))
+      return fail(NS_E_ARG, "walk_accept must be >= 1 and walk_max in [1, 2^20]");
+  }
   return NS_OK;
 }
 
@@ -175,7 +182,7 @@ void run_footprint(const ns_problem* P, const ns_opts* O, size_t* resident, size
   const size_t n = O->n_live, k = O->n_delete, d = P->n_dim;
   const size_t cap = (size_t)O->max_iter * k;
   size_t b = rounded(sizeof(ModelDev)) + rounded(sizeof(DevState)) + rounded(n * d * 8) + rounded(n * 8) +
-             2 * rounded(n * 4) + 2 * rounded(k * 4) + rounded(d * d * 8) + rounded(k * 4) + rounded(k * 8) +
+             2 * rounded(n * 4) + 2 * rounded(k * 4) + rounded(d * d * 8) + 2 * rounded(k * 4) + rounded(k * 8) +
              rounded(cap * d * 8) + 3 * rounded(cap * 8) + 3 * rounded(cap * 4);
   size_t t = 0;
   if (P->likelihood != NS_LIKE_GAUSS) {
@@ -233,6 +240,9 @@ int run_create(ns_run** out, const ns_problem* P, const ns_opts* O, hipStream_t 
   R.key0 = O->seed;
   R.key1 = O->run_id;
   R.cap = (long long)O->max_iter * k;
+  R.kernel = O->kernel;
+  R.walk_accept = O->walk_accept;
+  R.walk_max = O->walk_max;
   auto cleanup = [&](int code) { delete r; return code; };
   DevMem& mem = r->mem;
 #define ALLOC(ptr, count) \
@@ -247,6 +257,7 @@ int run_create(ns_run** out, const ns_problem* P, const ns_opts* O, hipStream_t 
   ALLOC(R.start, k);
   ALLOC(R.chol, (size_t)d * d);
   ALLOC(R.probes, k);
+  ALLOC(R.acc, k);
   ALLOC(R.bins, k);
   ALLOC(R.du, (size_t)R.cap * d);
   ALLOC(R.dlam, R.cap);
@@ -359,6 +370,7 @@ int run_create(ns_run** out, const ns_problem* P, const ns_opts* O, hipStream_t 
   s0.n_evals = n;
   s0.iter = 0;
   s0.done = 0;
+  s0.walk_len = O->kernel == NS_KERNEL_WALK ? std::min(O->walk_accept, O->walk_max) : 0;
   *r->h_state = s0;
   e = hipMemcpyAsync(R.state, r->h_state, sizeof(DevState), hipMemcpyHostToDevice, r->st);
   if (e == hipSuccess) e = launch_init_live(R, r->st);

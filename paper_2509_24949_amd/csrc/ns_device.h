@@ -17,7 +17,7 @@ constexpr double MPC_S = 3.0856775814913673e22 / 299792458.0;  // 1 Mpc / c  (s)
 constexpr double EULER_GAMMA = 0.57721566490153286061;
 
 // RNG purposes: the high 16 bits of the last Philox counter word.
-enum Purpose : uint64_t { P_INIT = 1, P_PICK = 2, P_DIR = 3, P_WIDTH = 4, P_SHRINK = 5, P_RESAMPLE = 6, P_SIGMA = 7 };
+enum Purpose : uint64_t { P_INIT = 1, P_PICK = 2, P_DIR = 3, P_WIDTH = 4, P_SHRINK = 5, P_RESAMPLE = 6, P_SIGMA = 7, P_WALK = 8 };
 
 // ------------------------------------------------------------------ Philox
 // Philox4x64-10 (Salmon et al., SC'11): ten rounds of two 64x64->128-bit

@@ -16,7 +16,8 @@ struct DevState {
   long long n_bin_terms;   // sum over evaluations of the active bins
   int iter;
   int done;        // 0 running, 1 criterion met, 2 dead-point capacity reached
-  int pad[2];
+  int walk_len;    // random-walk kernel: proposals per chain in the next iteration
+  int pad;
 };
 
 // Likelihood tables in HBM (built once per run).
@@ -73,9 +74,12 @@ struct RunDev {
   double* lam;                // [n]
   int* rank;                  // [n]
   int* dead;                  // [k]
-  int* surv;                  // [n]
+  int* surv;                  // [n] survivors of the iteration in ascending slot order (first n - k)
   int* start;                 // [k]
   double* chol;               // [d][d]
+  int kernel;                 // 0 slice chains, 1 random-walk chains
+  int walk_accept, walk_max;  // random walk: target acceptances per chain, chain-length cap
+  int* acc;                   // [k] accepted proposals of each random-walk chain in the last iteration
   int* probes;                // [k] likelihood calls of each chain in the last iteration
   long long* bins;            // [k] active bins summed over the chain's probes in the last iteration
   double* du;                 // [cap][d]
@@ -134,6 +138,9 @@ hipError_t launch_select(const double* lam, int n, int k, int* rank, int* dead, 
 // ends).  The current device must be `device`; the address is looked up once
 // per device (hipGetSymbolAddress) and cached.
 hipError_t noalloc_probe_scratch(int device, Probe** out);
+// Random-walk chains of one iteration (launch after the preparation kernel).
+hipError_t launch_walk(const ModelDev& M, const ModelDev* Md, const Tables& T, const RBTables& RB, const RunDev& R,
+                       hipStream_t st);
 // ev (optional): five events recorded before select, after select, after
 // prep, after the chains and after the termination kernel.
 hipError_t launch_iteration(const ModelDev& M, const ModelDev* Md, const Tables& T, const RBTables& RB,

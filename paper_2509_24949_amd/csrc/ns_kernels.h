@@ -1119,7 +1119,11 @@ __device__ void prep_body(const RunDev& R) {
   const int icl = block_scan<1024, int>(cnt, sint, &all_surv);
   int pos = icl - cnt;
   for (int i = ib; i < ie; ++i)
-    if (R.rank[i] >= k) s_surv[pos++] = i;
+    if (R.rank[i] >= k) {
+      s_surv[pos] = i;
+      R.surv[pos] = i;   // the random-walk chains draw their proposal pairs from it
+      ++pos;
+    }
   __syncthreads();
   const int ns = n - k;
   for (int j = tid; j < k; j += 1024) {
@@ -1728,13 +1732,14 @@ __device__ void term_body(const RunDev& R) {
   double m = NEG_INF;
   for (int i = tid; i < n; i += 1024) m = fmax(m, order_value(R.lam[i]));
   m = block_max<1024>(m, sbuf);
-  double v[3] = {0.0, 0.0, 0.0};   // sum exp(lambda - max), probes, bins
+  double v[4] = {0.0, 0.0, 0.0, 0.0};   // sum exp(lambda - max), probes, bins, walk acceptances
   for (int i = tid; i < n; i += 1024) v[0] += exp(order_value(R.lam[i]) - m);
   for (int j = tid; j < R.k; j += 1024) {
     v[1] += (double)R.probes[j];
     v[2] += (double)R.bins[j];
+    if (R.kernel == 1) v[3] += (double)R.acc[j];
   }
-  block_sum_k<1024, 3>(v, sbuf);
+  block_sum_k<1024, 4>(v, sbuf);
   const double s = v[0], pe = v[1], pb = v[2];
   if (tid == 0) {
     const double logz_live = S->logX + m + log(s / n);
@@ -1743,12 +1748,182 @@ __device__ void term_body(const RunDev& R) {
     if (S->n_dead + R.k > R.cap) done = 2;
     S->n_evals += (long long)pe;
     S->n_bin_terms += (long long)pb;
+    if (R.kernel == 1) {
+      // next chain length: walk_accept acceptances at this iteration's rate
+      const long long acc = (long long)v[3], prop = (long long)R.k * S->walk_len;
+      long long want = acc > 0 ? ((long long)R.walk_accept * prop + acc - 1) / acc : R.walk_max;
+      S->walk_len = (int)(want < 1 ? 1 : (want > R.walk_max ? R.walk_max : want));
+    }
     S->iter += 1;
     S->done = done;
   }
 }
 
 __global__ __launch_bounds__(1024) void k_term(RunDev R) { term_body(R); }
+
+
+// ------------------------------------------------------- random-walk chains
+// The alternative inner kernel (the random walk of bilby's sampler, paper
+// Section 2, read as differential-evolution moves): chain j = blockIdx.x, one
+// wavefront, makes the iteration's walk_len proposals y = x + gamma (u_a -
+// u_b) from two distinct survivors a, b (gamma = 1 or 2.38 / sqrt(2 d), each
+// with probability 1/2, times a factor uniform on [0.9, 1.1]; periodic
+// coordinates wrap) and accepts y iff it lies
+// in the unit cube and lambda(y) > L* (two survivors at one point give the
+// current point itself: a null move, not evaluated).  Proposals are set up
+// 64 at a time:
+// lane i takes proposal s + i from the current point (its draws, its two
+// survivors, its probe's source set-up into a record in LDS); the wave then
+// evaluates them in order and, at the first acceptance, moves and sets up
+// the next batch from the new point.  The proposals evaluated and counted
+// are exactly those of the sequential chain.
+constexpr int WK_DOUBLES_FIXED = 64 * SL_PSTRIDE + 64 + 16;   // records, Gaussian values, position
+
+template <int NDET, int LK, bool LDS>
+__global__ __launch_bounds__(64, 2) void k_walk(const ModelDev* __restrict__ Mp, Tables T, RBTables RB, RunDev R) {
+  extern __shared__ double smem[];
+  const ModelDev& M = *Mp;
+  const DevState* S = R.state;
+  if (S->done) return;
+  const int lane = threadIdx.x, j = blockIdx.x, d = R.d;
+  const uint64_t t = (uint64_t)S->iter;
+  const double lstar = S->lstar;
+  const int len = S->walk_len;
+  const int ns = R.n - R.k;
+  double* sP = smem;
+  double* sG = sP + 64 * SL_PSTRIDE;
+  double* sX = sG + 64;
+  double* stab = sX + 16;
+  TabView V{};
+  if constexpr (lk_full(LK)) V = stage_tables<NDET, lk_mixed(LK)>(M, T, LDS, stab, lane, 64);
+  RBTables RBv = RB;
+  if constexpr (lk_rb(LK) && LDS) RBv = stage_rb<NDET, lk_mixed(LK)>(RB, stab, lane, 64);
+  const int start = R.start[j];
+  if (lane < d) sX[lane] = R.u[(size_t)start * d + lane];
+  double lx = R.lam[start];
+  const double g_de = 2.38 / sqrt(2.0 * d);
+  int nprobe = 0, nacc = 0;
+  long long nbins = 0;
+  __syncthreads();
+  ProbeRec* rec = reinterpret_cast<ProbeRec*>(sP + lane * SL_PSTRIDE);
+  for (int s = 0; s < len;) {
+    // ---- proposals s .. s+63 from the current point, one per lane
+    const int sp = s + lane;
+    double y[MAX_DIM];
+    bool cin = false;
+    if (sp < len) {
+      const u64x4 b = philox(t, (uint64_t)j, (uint64_t)sp, purpose_word(P_WALK, 0), R.key0, R.key1);
+      const int ia = (int)floor(unif53(b.x[0]) * (double)ns);
+      int ib = (int)floor(unif53(b.x[1]) * (double)(ns - 1));
+      ib += (ib >= ia) ? 1 : 0;
+      const double g = (unif53(b.x[2]) < 0.5 ? 1.0 : g_de) * fma(0.2, unif53(b.x[3]), 0.9);
+      const double* ua = R.u + (size_t)R.surv[ia] * d;
+      const double* ub = R.u + (size_t)R.surv[ib] * d;
+      cin = true;
+      bool same = true;   // two survivors at one point: a null move, not evaluated
+#pragma unroll
+      for (int i = 0; i < MAX_DIM; ++i) {
+        if (i < d) {
+          const double df = ua[i] - ub[i];
+          same = same && df == 0.0;
+          y[i] = cube_coord(M.periodic, i, fma(g, df, sX[i]));
+          cin = cin && (((M.periodic >> i) & 1u) || (y[i] >= 0.0 && y[i] <= 1.0));
+        } else {
+          y[i] = 0.0;
+        }
+      }
+      cin = cin && !same;
+      if (cin) {
+        if (LK == LK_GAUSS) {
+          sG[lane] = gauss_lambda(M, y);
+        } else {
+          const int ka = probe_intrinsic(M, y, rec);
+          if constexpr (lk_full(LK)) {
+#pragma unroll
+            for (int dd = 0; dd < NDET; ++dd) rec->hk[dd] = ka > 0 ? V.hpre[(size_t)dd * V.hstride + ka - 1] : 0.0;
+          }
+          probe_extrinsic<NDET>(M, y, rec);
+        }
+      }
+    }
+    const unsigned long long mask = __ballot(cin);
+    __syncthreads();
+    // ---- the batch in order, until the first acceptance
+    int i = 0;
+    bool moved = false;
+    for (; i < 64 && s + i < len; ++i) {
+      if (!((mask >> i) & 1ull)) continue;
+      double l;
+      int terms;
+      if constexpr (LK == LK_GAUSS) {
+        l = sG[i];
+        terms = 0;
+      } else {
+        const Probe pb = probe_from_rec<NDET>(*reinterpret_cast<const ProbeRec*>(sP + i * SL_PSTRIDE), lk_full(LK));
+        if constexpr (lk_rb(LK)) {
+          l = rb_wave<NDET, lk_mixed(LK)>(pb, RBv, M.n_bins, lane, &terms);
+        } else {
+          l = wave_sum(fullgrid_partial<NDET, lk_mixed(LK), true>(pb, V, lane, 64)) - 0.5 * pb.hh;
+          terms = pb.k_act;
+        }
+      }
+      ++nprobe;
+      nbins += terms;
+      if (l > lstar) {
+        if (lane == i) {
+#pragma unroll
+          for (int q = 0; q < MAX_DIM; ++q)
+            if (q < d) sX[q] = y[q];
+        }
+        lx = l;
+        ++nacc;
+        moved = true;
+        break;
+      }
+    }
+    s += moved ? i + 1 : i;
+    __syncthreads();
+  }
+  const int slot = R.dead[j];
+  if (lane < d) R.u[(size_t)slot * d + lane] = sX[lane];
+  if (lane == 0) {
+    R.lam[slot] = lx;
+    R.probes[j] = nprobe;
+    R.bins[j] = nbins;
+    R.acc[j] = nacc;
+  }
+}
+
+template <int NDET, int LK, bool LDS>
+hipError_t launch_walk_t(const ModelDev& M, const ModelDev* Md, const Tables& T, const RBTables& RB, const RunDev& R,
+                         hipStream_t st) {
+  size_t tab = 0;
+  if (LDS) tab = lk_rb(LK) ? rb_stage_doubles(RB.nb, NDET, lk_mixed(LK)) * sizeof(double)
+                           : staged_table_bytes(M.k_lim, NDET, lk_mixed(LK));
+  const size_t lds = WK_DOUBLES_FIXED * sizeof(double) + tab;
+  hipLaunchKernelGGL((k_walk<NDET, LK, LDS>), dim3(R.k), dim3(64), lds, st, Md, T, RB, R);
+  return hipGetLastError();
+}
+
+// Tables staged in LDS while a CU still holds four chains.
+template <int NDET>
+hipError_t launch_walk_det(const ModelDev& M, const ModelDev* Md, const Tables& T, const RBTables& RB,
+                           const RunDev& R, hipStream_t st) {
+  const bool rb = M.likelihood == LK_RB;
+  const size_t tab = rb ? rb_stage_doubles(RB.nb, NDET, M.mixed != 0) * sizeof(double)
+                        : staged_table_bytes(M.k_lim, NDET, M.mixed != 0);
+  const bool lds = WK_DOUBLES_FIXED * sizeof(double) + tab <= 40 * 1024;
+  if (rb) {
+    if (M.mixed) return lds ? launch_walk_t<NDET, LK_RB32, true>(M, Md, T, RB, R, st)
+                            : launch_walk_t<NDET, LK_RB32, false>(M, Md, T, RB, R, st);
+    return lds ? launch_walk_t<NDET, LK_RB, true>(M, Md, T, RB, R, st)
+               : launch_walk_t<NDET, LK_RB, false>(M, Md, T, RB, R, st);
+  }
+  if (M.mixed) return lds ? launch_walk_t<NDET, LK_FULL32, true>(M, Md, T, RB, R, st)
+                          : launch_walk_t<NDET, LK_FULL32, false>(M, Md, T, RB, R, st);
+  return lds ? launch_walk_t<NDET, LK_FULL, true>(M, Md, T, RB, R, st)
+             : launch_walk_t<NDET, LK_FULL, false>(M, Md, T, RB, R, st);
+}
 
 
 // ---------------------------------------------------------------- packed

@@ -180,7 +180,9 @@ hipError_t launch_iteration(const ModelDev& M, const ModelDev* Md, const Tables&
   hipLaunchKernelGGL(k_prep, dim3(1), dim3(1024), 0, st, R);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (ev && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;
-  if (M.likelihood == LK_GAUSS) {
+  if (R.kernel == 1) {
+    e = launch_walk(M, Md, T, RB, R, st);
+  } else if (M.likelihood == LK_GAUSS) {
     e = launch_slice_t<1, 64, LK_GAUSS, false>(Md, T, RB, R, C.lds_bytes, st);
   } else {
     switch (M.n_det) {

@@ -257,6 +257,7 @@ int ns_server_submit(ns_server* s, const ns_problem* P, const ns_opts* O, long l
   if (rc) return rc;
   if ((rc = validate_opts(O))) return rc;
   if (P->likelihood == NS_LIKE_GAUSS) return fail(NS_E_ARG, "the server takes the waveform likelihoods (FULL or RB)");
+  if (O->kernel != NS_KERNEL_SLICE) return fail(NS_E_ARG, "the server runs slice-sampling chains only");
   std::unique_ptr<Request> q(new (std::nothrow) Request());
   if (!q) return fail(NS_E_OOM, "host allocation failed");
   run_footprint(P, O, &q->resident, &q->transient);

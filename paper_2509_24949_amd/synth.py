@@ -131,8 +131,8 @@ class Workload:
     # differential-evolution proposals (walk_accept accepted proposals per
     # chain, at most walk_max proposals)
     kernel: int = 0
-    walk_accept: int = 20
-    walk_max: int = 400
+    walk_accept: int = 60
+    walk_max: int = 2000
 
     @property
     def n_dim(self) -> int:
@@ -174,6 +174,8 @@ def workload(name: str, distance: float | None = None) -> Workload:
     ``tf2_3det_rb``  tf2_3det with the relative-binning likelihood (128 geometric bins).
     ``tf2_3det_mixed``  tf2_3det in the mixed-precision form with n 2000 / k 1000.
     ``tf2_3det_rb_mixed`` tf2_3det_rb in the mixed-precision form with n 2000 / k 1000.
+    ``tf2_3det_rb_walk`` tf2_3det_rb with the random-walk chain kernel (60
+        accepted proposals per chain, at most 2000 proposals).
     ``tf2_3det_rb_paper`` tf2_3det_rb at the paper's own settings (Section 2):
         n 3000 / k 1500, chains of 10 d = 110 steps, the coalescence phase,
         the polarisation angle and the right ascension wrapped in the unit cube.
@@ -195,7 +197,8 @@ def workload(name: str, distance: float | None = None) -> Workload:
             noise_seed=101, fixed_dist_mpc=d_eff, snr_target=15.0,
             n_live=500, n_delete=250, n_steps=20, sampler_seed=1001,
         )
-    if name in ("tf2_3det", "tf2_3det_rb", "tf2_3det_mixed", "tf2_3det_rb_mixed", "tf2_3det_rb_paper"):
+    if name in ("tf2_3det", "tf2_3det_rb", "tf2_3det_mixed", "tf2_3det_rb_mixed", "tf2_3det_rb_paper",
+                "tf2_3det_rb_walk"):
         d_inj = distance if distance is not None else inj.get("tf2_3det", {}).get("distance_mpc", 0.0)
         w = Workload(
             name=name, model=MODEL_TF2_11P, likelihood=LIKE_FULL, f_lo=20.0, df=0.25, n_bins=4017,
@@ -215,6 +218,10 @@ def workload(name: str, distance: float | None = None) -> Workload:
             w.sampler_seed = 4001
             if name == "tf2_3det_rb_mixed":
                 w.likelihood = LIKE_RB
+        if name == "tf2_3det_rb_walk":
+            w.likelihood = LIKE_RB
+            w.kernel = 1
+            w.sampler_seed = 9001
         if name == "tf2_3det_rb_paper":
             w.likelihood = LIKE_RB
             w.n_live, w.n_delete, w.n_steps = 3000, 1500, 10 * 11

@@ -117,3 +117,23 @@ def test_noalloc_limit_and_null_run():
     lib = binding.lib()
     assert lib.ns_loglike_noalloc(None, None, 0, None, None) == binding.NS_E_ARG
     assert b"NULL" in lib.ns_last_error()
+
+
+def test_walk_kernel_options_are_validated():
+    lib = binding.lib()
+    out = C.c_void_p()
+    w = synth.gauss_workload(3, 0.1)
+    spec = binding.ProblemSpec(w)
+    bad = binding.opts_for(w, kernel=5)
+    assert lib.ns_init(C.byref(out), spec.ref, C.byref(bad), None) == binding.NS_E_ARG
+    assert b"kernel" in lib.ns_last_error()
+    bad = binding.opts_for(w, kernel=binding.NS_KERNEL_WALK, n_live=10, n_delete=9)
+    assert lib.ns_init(C.byref(out), spec.ref, C.byref(bad), None) == binding.NS_E_ARG
+    assert b"n_live - n_delete" in lib.ns_last_error()
+    bad = binding.opts_for(w, kernel=binding.NS_KERNEL_WALK, walk_accept=0)
+    assert lib.ns_init(C.byref(out), spec.ref, C.byref(bad), None) == binding.NS_E_ARG
+    w.periodic = np.array([1, 2, 0], dtype=np.int32)
+    spec = binding.ProblemSpec(w)
+    assert lib.ns_init(C.byref(out), spec.ref, C.byref(binding.opts_for(w)), None) == binding.NS_E_ARG
+    assert b"periodic" in lib.ns_last_error()
+    assert out.value is None

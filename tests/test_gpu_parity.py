@@ -270,6 +270,25 @@ def test_paper_settings_lockstep(torch_cuda):
     assert u.min() >= 0.0 and u.max() <= 1.0
 
 
+@pytest.mark.parametrize("name,iters", [("gauss", 6), ("tf2_1det", 1000), ("tf2_3det", 2), ("tf2_3det_rb", 2),
+                                        ("tf2_3det_rb_paper", 2)])
+def test_walk_kernel_lockstep(torch_cuda, name, iters):
+    """The random-walk chain kernel follows the oracle's in lockstep (same
+    proposals, dead points, evidence, chain lengths adapted from the same
+    acceptance counts); tf2_1det to the end of the run."""
+    if name == "gauss":
+        w = synth.gauss_workload(4, 0.05, mu=[0.1, 0.5, 0.6, 0.4], n_live=300, n_delete=150)
+        orc, spec = oracle.OracleProblem(w), binding.ProblemSpec(w)
+    else:
+        w = synth.workload(name)
+        orc, spec = _pair(w)
+    w.kernel, w.walk_accept, w.walk_max = 1, 15, 300
+    print(f"walk lockstep {name}: {iters} iterations", flush=True)
+    ro, rg = _lockstep(w, orc, spec, iters)
+    _compare_runs(ro, rg)
+    assert rg.state()["n_evals"] == ro.state()["n_evals"]
+
+
 def test_rb_rejects_degenerate_binning(torch_cuda):
     w = synth.workload("tf2_3det_rb")
     w.rb_n_bins = 1000                  # more coarse bins than the grid can separate at low frequency

@@ -81,7 +81,7 @@ def _walk_step_bad(L):
         a = int(math.floor(u[0] * 4))
         b = int(math.floor(u[1] * 3))
         b += b >= a
-        g = 1.0 if u[2] < 0.5 else 2.38 / math.sqrt(2 * d)
+        g = (1.0 if u[2] < 0.5 else 2.38 / math.sqrt(2 * d)) * (0.9 + 0.2 * u[3])
         y = x0 + g * (pop[a] - pop[b])
         inside = bool(np.all((y >= 0) & (y <= 1)))
         x, _, _ = _walk(L, p, o, pop, 1, x0, -np.inf, 0, j)

@@ -913,7 +913,8 @@ def _walk_opts(w, accept, cap):
 def test_walk_step_by_hand():
     """One proposal of the random-walk kernel worked by hand from its three
     draws (Philox block of purpose WALK for iteration 0, chain j, step 0):
-    survivors a and b, and the scale 1 or 2.38 / sqrt(2 d)."""
+    survivors a and b, the scale 1 or 2.38 / sqrt(2 d) and its factor on
+    [0.9, 1.1]."""
     d = 2
     w = synth.gauss_workload(d, 10.0)
     o = _walk_opts(w, 1, 1)
@@ -927,13 +928,13 @@ def test_walk_step_by_hand():
         a = int(math.floor(u[0] * 4))
         b = int(math.floor(u[1] * 3))
         b += b >= a
-        g = 1.0 if u[2] < 0.5 else 2.38 / math.sqrt(2 * d)
+        g = (1.0 if u[2] < 0.5 else 2.38 / math.sqrt(2 * d)) * (0.9 + 0.2 * u[3])
         y = x0 + g * (pop[a] - pop[b])
         inside = bool(np.all((y >= 0) & (y <= 1)))
         x, lx, ev, acc = oracle.walk_from(p, o, pop, 1, x0, 0.0, -np.inf, t=0, j=j)
         assert ev == acc == (1 if inside else 0)
         np.testing.assert_allclose(x, y if inside else x0, rtol=0, atol=1e-15)
-        seen.add((inside, g == 1.0))
+        seen.add((inside, u[2] < 0.5))
     assert len(seen) >= 3
 
 
