@@ -63,6 +63,9 @@ def load(path: str):
     L.orc_waveform.argtypes = [C.c_void_p, _dp, C.c_int, C.c_int, _dp, _dp]
     L.orc_tf2_phase.argtypes = [C.c_double] * 7
     L.orc_tf2_phase.restype = C.c_double
+    L.orc_tf2_phase_so.argtypes = [C.c_double] * 10
+    L.orc_tf2_phase_so.restype = C.c_double
+    L.orc_pn_params_so.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp]
     L.orc_inner.argtypes = [C.c_void_p, C.c_int, _dp, _dp, _dp, _dp]
     L.orc_inner.restype = C.c_double
     L.orc_noise_loglike.argtypes = [C.c_void_p]

@@ -134,13 +134,18 @@ void orc_antenna(const double* g, double ra, double dec, double psi, double gmst
 
 /* --------------------------------------------------------------- TaylorF2
  * Stationary-phase inspiral phase to 3.5PN with leading-order aligned-spin
- * terms (spin-orbit beta at 1.5PN, spin-spin sigma at 2PN):
+ * terms (spin-orbit beta at 1.5PN, spin-spin sigma at 2PN), and in the
+ * spin-orbit model the spin-orbit terms at 2.5PN (gamma5, which joins the
+ * 2.5PN coefficient inside its (1 + 3 ln v) factor), 3PN (so6) and 3.5PN
+ * (so7), linear in the spins, as energy balance gives them from the
+ * spin-orbit parts of the binding energy and flux through 3.5PN (tail term
+ * at 3PN included):
  *   Psi(f) = 2 pi f t_c - phi_c - pi/4 + 3/(128 eta v^5) sum_k psi_k v^k,
  *   v = (pi M f)^(1/3).
  * ln v is used at 2.5PN (a constant offset from ln(v/v_lso) that phi_c
  * absorbs). */
-double orc_tf2_phase(double f, double mc_msun, double eta, double beta, double sigma,
-                     double tc, double phic) {
+double orc_tf2_phase_so(double f, double mc_msun, double eta, double beta, double sigma, double gamma5,
+                        double so6, double so7, double tc, double phic) {
     double mc = mc_msun * TSUN_S;
     double m = mc * pow(eta, -0.6);
     double v = cbrt(PI * m * f);
@@ -152,21 +157,41 @@ double orc_tf2_phase(double f, double mc_msun, double eta, double beta, double s
     psi[2] = 3715.0 / 756.0 + 55.0 * eta / 9.0;
     psi[3] = -16.0 * PI + 4.0 * beta;
     psi[4] = 15293365.0 / 508032.0 + 27145.0 * eta / 504.0 + 3085.0 * e2 / 72.0 - 10.0 * sigma;
-    psi[5] = PI * (38645.0 / 756.0 - 65.0 * eta / 9.0) * (1.0 + 3.0 * lv);
+    psi[5] = (PI * (38645.0 / 756.0 - 65.0 * eta / 9.0) - gamma5) * (1.0 + 3.0 * lv);
     psi[6] = 11583231236531.0 / 4694215680.0 - 640.0 * PI * PI / 3.0 - 6848.0 * EULER_GAMMA / 21.0
              - (6848.0 / 21.0) * log(4.0 * v)
              + (-15737765635.0 / 3048192.0 + 2255.0 * PI * PI / 12.0) * eta
-             + 76055.0 * e2 / 1728.0 - 127825.0 * e3 / 1296.0;
-    psi[7] = PI * (77096675.0 / 254016.0 + 378515.0 * eta / 1512.0 - 74045.0 * e2 / 756.0);
+             + 76055.0 * e2 / 1728.0 - 127825.0 * e3 / 1296.0 + so6;
+    psi[7] = PI * (77096675.0 / 254016.0 + 378515.0 * eta / 1512.0 - 74045.0 * e2 / 756.0) + so7;
     double sum = 0.0, vk = 1.0;
     for (int k = 0; k < 8; ++k) { sum += psi[k] * vk; vk *= v; }
     double v5 = v * v * v * v * v;
     return 2.0 * PI * f * tc - phic - PI / 4.0 + 3.0 / (128.0 * eta * v5) * sum;
 }
 
+double orc_tf2_phase(double f, double mc_msun, double eta, double beta, double sigma, double tc, double phic) {
+    return orc_tf2_phase_so(f, mc_msun, eta, beta, sigma, 0.0, 0.0, 0.0, tc, phic);
+}
+
+/* Spin-orbit phase terms above 1.5PN, in the symmetric and antisymmetric
+ * spins chi_s = (chi1 + chi2)/2, chi_a = (chi1 - chi2)/2 and delta =
+ * (m1 - m2)/M. */
+static void spin_orbit_terms(double eta, double c1, double c2, double delta, double* g5, double* so6,
+                             double* so7) {
+    double e2 = eta * eta, e3 = e2 * eta;
+    double cs = 0.5 * (c1 + c2), ca = 0.5 * (c1 - c2);
+    *g5 = (732985.0 / 2268.0 - 24260.0 * eta / 81.0 - 340.0 * e2 / 9.0) * cs
+          + (732985.0 / 2268.0 + 140.0 * eta / 9.0) * delta * ca;
+    *so6 = PI * (2270.0 / 3.0 * delta * ca + (2270.0 / 3.0 - 520.0 * eta) * cs);
+    *so7 = (-25150083775.0 / 3048192.0 + 10566655595.0 * eta / 762048.0 - 1042165.0 * e2 / 3024.0
+            + 5345.0 * e3 / 36.0) * cs
+           + delta * (-25150083775.0 / 3048192.0 + 26804935.0 * eta / 6048.0 - 1985.0 * e2 / 48.0) * ca;
+}
+
 /* Source quantities shared by all frequencies for one parameter point. */
 typedef struct {
     double mc_msun, eta, beta, sigma, tc, phic;
+    double gamma5, so6, so7;   /* higher-order spin-orbit terms (spin-orbit model) */
     double amp;          /* sqrt(5/24) pi^(-2/3) Mc^(5/6) / D   (s) */
     double f_isco;       /* 1 / (6^(3/2) pi M)                   (Hz) */
     double hp_fac, hx_fac; /* plus: (1 + cos^2 i)/2, cross: cos i */
@@ -193,6 +218,7 @@ static void make_source(const orc_problem* p, const double* th, source* s) {
         double m1 = 1.0 / (1.0 + q), m2 = q / (1.0 + q);   /* component masses / M */
         s->beta = (c1 * (113.0 * m1 * m1 + 75.0 * s->eta) + c2 * (113.0 * m2 * m2 + 75.0 * s->eta)) / 12.0;
         s->sigma = 79.0 / 8.0 * s->eta * c1 * c2;
+        if (p->model == ORC_MODEL_TF2_11P_SO) spin_orbit_terms(s->eta, c1, c2, m1 - m2, &s->gamma5, &s->so6, &s->so7);
         dist_mpc = th[4];
         double ci = cos(th[5]);
         s->hp_fac = 0.5 * (1.0 + ci * ci);
@@ -210,8 +236,12 @@ static void make_source(const orc_problem* p, const double* th, source* s) {
     s->f_isco = 1.0 / (pow(6.0, 1.5) * PI * m);
 }
 
+static int known_model(int m) {
+    return m == ORC_MODEL_TF2_4P || m == ORC_MODEL_TF2_11P || m == ORC_MODEL_TF2_11P_SO;
+}
+
 int orc_pn_params(const orc_problem* p, const double* th, double* eta, double* beta, double* sigma) {
-    if (p->model != ORC_MODEL_TF2_4P && p->model != ORC_MODEL_TF2_11P) return -1;
+    if (!known_model(p->model)) return -1;
     source s;
     make_source(p, th, &s);
     *eta = s.eta;
@@ -220,10 +250,21 @@ int orc_pn_params(const orc_problem* p, const double* th, double* eta, double* b
     return 0;
 }
 
+int orc_pn_params_so(const orc_problem* p, const double* th, double* gamma5, double* so6, double* so7) {
+    if (!known_model(p->model)) return -1;
+    source s;
+    make_source(p, th, &s);
+    *gamma5 = s.gamma5;
+    *so6 = s.so6;
+    *so7 = s.so7;
+    return 0;
+}
+
 /* Detector strain at one frequency, without the ISCO cut. */
 static void strain_at(const orc_problem* p, const source* s, double fp, double fc, double dt, double f,
                       double* re, double* im) {
-    double psi = orc_tf2_phase(f, s->mc_msun, s->eta, s->beta, s->sigma, s->tc, s->phic);
+    double psi = orc_tf2_phase_so(f, s->mc_msun, s->eta, s->beta, s->sigma, s->gamma5, s->so6, s->so7, s->tc,
+                                  s->phic);
     double a = s->amp * pow(f, -7.0 / 6.0);
     /* base = a e^{-i Psi} */
     double br = a * cos(psi), bi = -a * sin(psi);
@@ -256,7 +297,7 @@ static void det_response(const orc_problem* p, const source* s, int det, double*
 }
 
 int orc_waveform(const orc_problem* p, const double* th, int det, int apply_cut, double* h_re, double* h_im) {
-    if (p->model != ORC_MODEL_TF2_4P && p->model != ORC_MODEL_TF2_11P) return -1;
+    if (!known_model(p->model)) return -1;
     if (det < 0 || det >= p->n_det) return -1;
     source s;
     make_source(p, th, &s);
@@ -365,7 +406,7 @@ static void rb_sums(const orc_rb* rb, int det, int b, int k_end, double* a0r, do
 }
 
 orc_rb* orc_rb_build(const orc_problem* p) {
-    if (p->model != ORC_MODEL_TF2_4P && p->model != ORC_MODEL_TF2_11P) return NULL;
+    if (!known_model(p->model)) return NULL;
     int nb = p->rb_n_bins, nd = p->n_det, n = p->n_bins;
     if (nb < 1 || nb >= n) return NULL;
     orc_rb* rb = (orc_rb*)calloc(1, sizeof(orc_rb));

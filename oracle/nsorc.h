@@ -18,7 +18,7 @@ extern "C" {
 #endif
 
 enum { ORC_PRIOR_UNIFORM = 0, ORC_PRIOR_COS = 1, ORC_PRIOR_SIN = 2, ORC_PRIOR_VOLUME = 3 };
-enum { ORC_MODEL_TF2_4P = 1, ORC_MODEL_TF2_11P = 2 };
+enum { ORC_MODEL_TF2_4P = 1, ORC_MODEL_TF2_11P = 2, ORC_MODEL_TF2_11P_SO = 3 };
 enum { ORC_LIKE_FULL = 0, ORC_LIKE_RB = 1, ORC_LIKE_GAUSS = 2 };
 
 typedef struct {
@@ -75,10 +75,16 @@ int orc_waveform(const orc_problem* p, const double* theta, int det, int apply_c
 /* TaylorF2 phase Psi(f) (radians) for the given masses/spins (test helper). */
 double orc_tf2_phase(double f, double mc_msun, double eta, double beta, double sigma,
                      double tc, double phic);
+/* The same with the higher-order spin-orbit terms: gamma5 (2.5PN), so6
+ * (3PN) and so7 (3.5PN) (test helper). */
+double orc_tf2_phase_so(double f, double mc_msun, double eta, double beta, double sigma, double gamma5,
+                        double so6, double so7, double tc, double phic);
 
 /* Symmetric mass ratio and the leading-order aligned-spin phase terms
  * (spin-orbit beta, spin-spin sigma) of a parameter point (test helper). */
 int orc_pn_params(const orc_problem* p, const double* theta, double* eta, double* beta, double* sigma);
+/* The higher-order spin-orbit phase terms (zero unless ORC_MODEL_TF2_11P_SO). */
+int orc_pn_params_so(const orc_problem* p, const double* theta, double* gamma5, double* so6, double* so7);
 
 /* Noise-weighted inner product 4 df Re sum conj(a) b / S over one detector. */
 double orc_inner(const orc_problem* p, int det, const double* a_re, const double* a_im,

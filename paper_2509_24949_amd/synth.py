@@ -24,8 +24,9 @@ PRIOR_UNIFORM, PRIOR_COS, PRIOR_SIN, PRIOR_VOLUME = 0, 1, 2, 3
 
 # Waveform models.  MODEL_TF2_4P: (Mc, eta, t_c, phi_c), one optimally oriented
 # detector at a fixed distance.  MODEL_TF2_11P: aligned-spin network model with
-# (Mc, q, chi1, chi2, d_L, theta_jn, psi, RA, Dec, t_c, phi_c).
-MODEL_TF2_4P, MODEL_TF2_11P = 1, 2
+# (Mc, q, chi1, chi2, d_L, theta_jn, psi, RA, Dec, t_c, phi_c); MODEL_TF2_11P_SO: the
+# same with the spin-orbit phase terms through 3.5PN.
+MODEL_TF2_4P, MODEL_TF2_11P, MODEL_TF2_11P_SO = 1, 2, 3
 
 # Likelihood forms.
 LIKE_FULL, LIKE_RB, LIKE_GAUSS = 0, 1, 2
@@ -174,6 +175,8 @@ def workload(name: str, distance: float | None = None) -> Workload:
     ``tf2_3det_rb``  tf2_3det with the relative-binning likelihood (128 geometric bins).
     ``tf2_3det_mixed``  tf2_3det in the mixed-precision form with n 2000 / k 1000.
     ``tf2_3det_rb_mixed`` tf2_3det_rb in the mixed-precision form with n 2000 / k 1000.
+    ``tf2_3det_so`` tf2_3det with the spin-orbit phase terms through 3.5PN
+        (waveform model 3).
     ``tf2_3det_rb_walk`` tf2_3det_rb with the random-walk chain kernel (60
         accepted proposals per chain, at most 2000 proposals).
     ``tf2_3det_rb_paper`` tf2_3det_rb at the paper's own settings (Section 2):
@@ -198,7 +201,7 @@ def workload(name: str, distance: float | None = None) -> Workload:
             n_live=500, n_delete=250, n_steps=20, sampler_seed=1001,
         )
     if name in ("tf2_3det", "tf2_3det_rb", "tf2_3det_mixed", "tf2_3det_rb_mixed", "tf2_3det_rb_paper",
-                "tf2_3det_rb_walk"):
+                "tf2_3det_rb_walk", "tf2_3det_so"):
         d_inj = distance if distance is not None else inj.get("tf2_3det", {}).get("distance_mpc", 0.0)
         w = Workload(
             name=name, model=MODEL_TF2_11P, likelihood=LIKE_FULL, f_lo=20.0, df=0.25, n_bins=4017,
@@ -218,6 +221,9 @@ def workload(name: str, distance: float | None = None) -> Workload:
             w.sampler_seed = 4001
             if name == "tf2_3det_rb_mixed":
                 w.likelihood = LIKE_RB
+        if name == "tf2_3det_so":
+            w.model = MODEL_TF2_11P_SO
+            w.sampler_seed = 9501
         if name == "tf2_3det_rb_walk":
             w.likelihood = LIKE_RB
             w.kernel = 1

@@ -51,6 +51,16 @@ MUTATIONS = [
      "if (is_periodic(p, i)) y[i] -= 0.0;", "wrap"),
     ("wrap to the centred interval", "if (is_periodic(p, i)) y[i] -= floor(y[i]);",
      "if (is_periodic(p, i)) y[i] -= floor(y[i] + 0.5);", "wrap"),
+    ("2.5PN spin-orbit (chi_s)", "*g5 = (732985.0 / 2268.0 - 24260.0 * eta / 81.0",
+     "*g5 = (1.01 * 732985.0 / 2268.0 - 24260.0 * eta / 81.0", "so_phase"),
+    ("2.5PN spin-orbit (chi_a)", "+ (732985.0 / 2268.0 + 140.0 * eta / 9.0) * delta * ca;",
+     "+ (732985.0 / 2268.0 + 1.01 * 140.0 * eta / 9.0) * delta * ca;", "so_phase"),
+    ("3PN spin-orbit tail", "*so6 = PI * (2270.0 / 3.0 * delta * ca + (2270.0 / 3.0 - 520.0 * eta) * cs);",
+     "*so6 = PI * (2270.0 / 3.0 * delta * ca + (2270.0 / 3.0 - 525.2 * eta) * cs);", "so_phase"),
+    ("3.5PN spin-orbit (chi_s)", "*so7 = (-25150083775.0 / 3048192.0 + 10566655595.0 * eta / 762048.0",
+     "*so7 = (-25150083775.0 / 3048192.0 + 1.01 * 10566655595.0 * eta / 762048.0", "so_phase"),
+    ("3.5PN spin-orbit (chi_a)", "+ delta * (-25150083775.0 / 3048192.0 + 26804935.0 * eta / 6048.0",
+     "+ delta * (-25150083775.0 / 3048192.0 + 1.01 * 26804935.0 * eta / 6048.0", "so_phase"),
     ("walk scale", "double g_de = 2.38 / sqrt(2.0 * d);", "double g_de = 2.4 / sqrt(2.0 * d);", "walk_step"),
     ("walk pair not distinct", "if (ib >= ia) ++ib;", "if (ib > ia) ++ib;", "walk_step"),
     ("walk stops at a count of acceptances", "for (int s = 0; s < n_prop; ++s) {",
@@ -179,6 +189,7 @@ CHECKS = {
     "resample": _resample_bad,
     "wrap": _wrap_bad,
     "walk_step": _walk_step_bad,
+    "so_phase": lambda L: pins._so_worst(L) >= 1.0,
     "walk_invariance": _walk_invariance_bad,
 }
 

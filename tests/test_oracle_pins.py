@@ -216,6 +216,112 @@ def test_phase_matches_energy_balance_to_3p5pn_with_spins():
     assert _eb_worst(oracle.lib()) < 1.0
 
 
+def _tau_spin_orbit_linear(eta, q, c1, c2):
+    """The part of the time-to-coalescence series linear in the spins, from
+    energy balance with the spin-orbit terms of the binding energy and the
+    flux through 3.5PN, written with S = m1^2 chi1 + m2^2 chi2 and
+    Sigma = M (m2 chi2 - m1 chi1) over M^2 and delta = (m1 - m2)/M:
+      E: (14/3 S + 2 delta Sigma) v^3 + [(11 - 61 eta/9) S + delta (3 - 10 eta/3) Sigma] v^5
+         + [(135/4 - 367 eta/4 + 29 eta^2/12) S + delta (27/4 - 39 eta + 5 eta^2/4) Sigma] v^7
+      F: -(4 S + 5/4 delta Sigma) v^3 + [(-9/2 + 272 eta/9) S + (-13/16 + 43 eta/4) delta Sigma] v^5
+         + (-16 pi S - 31 pi/6 delta Sigma) v^6 (the spin-orbit tail)
+         + [(476645/6804 + 6172 eta/189 - 2810 eta^2/27) S
+            + (9535/336 + 1849 eta/126 - 1501 eta^2/36) delta Sigma] v^7,
+    with the point-mass terms of _tau_series_from_energy_balance.  The ratio
+    E'/F is expanded to first order in the spins (the products of two
+    spin-orbit terms are left out, and so are spin-spin terms); returns the
+    spin-linear parts of tau_0 .. tau_7."""
+    pi = math.pi
+    x1, x2 = 1 / (1 + q), q / (1 + q)
+    S = x1 * x1 * c1 + x2 * x2 * c2
+    dSig = (x1 - x2) * (x2 * c2 - x1 * c1)
+    e = np.zeros(8)
+    fl = np.zeros(8)
+    e[0], e[2], e[4] = 1.0, -(3 / 4 + eta / 12), -(27 / 8 - 19 * eta / 8 + eta**2 / 24)
+    e[6] = -675 / 64 + (34445 / 576 - 205 * pi**2 / 96) * eta - 155 * eta**2 / 96 - 35 * eta**3 / 5184
+    fl[0], fl[2], fl[3] = 1.0, -(1247 / 336 + 35 * eta / 12), 4 * pi
+    fl[4] = -44711 / 9072 + 9271 * eta / 504 + 65 * eta**2 / 18
+    fl[5] = -(8191 / 672 + 583 * eta / 24) * pi
+    fl[7] = (-16285 / 504 + 214745 * eta / 1728 + 193385 * eta**2 / 3024) * pi
+    # spin-orbit parts (first order)
+    es = np.zeros(8)
+    fs = np.zeros(8)
+    es[3] = 14 / 3 * S + 2 * dSig
+    es[5] = (11 - 61 * eta / 9) * S + (3 - 10 * eta / 3) * dSig
+    es[7] = (135 / 4 - 367 * eta / 4 + 29 * eta**2 / 12) * S + (27 / 4 - 39 * eta + 5 * eta**2 / 4) * dSig
+    fs[3] = -4 * S - 5 / 4 * dSig
+    fs[5] = (-9 / 2 + 272 * eta / 9) * S + (-13 / 16 + 43 * eta / 4) * dSig
+    fs[6] = -16 * pi * S - 31 * pi / 6 * dSig
+    fs[7] = ((476645 / 6804 + 6172 * eta / 189 - 2810 * eta**2 / 27) * S
+             + (9535 / 336 + 1849 * eta / 126 - 1501 * eta**2 / 36) * dSig)
+    # a = num / F to first order: a0 + a1 with a0 F0 = num0 and a1 F0 = num1 - a0 F1 (series products;
+    # the log of F at v^6 has no spin part, and the spin-linear part has no log term at this order)
+    num0 = np.array([e[k] * (k + 2) / 2 for k in range(8)])
+    num1 = np.array([es[k] * (k + 2) / 2 for k in range(8)])
+
+    def div(nm, den):
+        out = np.zeros(8)
+        for k in range(8):
+            out[k] = nm[k] - sum(out[j] * den[k - j] for j in range(k))
+        return out
+
+    a0 = div(num0, fl)
+    conv = np.array([sum(a0[j] * fs[k - j] for j in range(k + 1)) for k in range(8)])
+    a1 = div(num1 - conv, fl)
+    return np.array([8 * a1[k] / (8 - k) for k in range(8)])
+
+
+_SO_CASES = [(24.0, 0.5, 0.02, -0.01), (31.0, 0.9, 0.015, 0.02), (18.0, 0.2, -0.01, 0.02)]
+
+
+def _so_worst(L):
+    """Largest ratio |fit - energy balance| / tolerance of the spin-linear
+    time-to-coalescence coefficients tau_3, tau_5, tau_6, tau_7 of the
+    spin-orbit model (11-parameter model with the higher-order spin-orbit
+    terms), read as the odd part in the spins of the fitted series."""
+    w = synth.workload("tf2_3det")
+    w.model = 3
+    prob = oracle.OracleProblem(w)
+    worst = 0.0
+    for mc, q, c1, c2 in _SO_CASES:
+        fits = []
+        for sgn in (1.0, -1.0):
+            th = np.array([mc, q, sgn * c1, sgn * c2, 400.0, 0.3, 0.2, 1.0, 0.1, 0.0, 0.0])
+            e, b, s = C.c_double(), C.c_double(), C.c_double()
+            L.orc_pn_params(prob.ref, th.ctypes.data_as(oracle._dp), C.byref(e), C.byref(b), C.byref(s))
+            g5, s6, s7 = C.c_double(), C.c_double(), C.c_double()
+            L.orc_pn_params_so(prob.ref, th.ctypes.data_as(oracle._dp), C.byref(g5), C.byref(s6), C.byref(s7))
+            eta = e.value
+            m = mc * TSUN * eta ** -0.6
+            vs = np.linspace(0.02, 0.3, 160)
+            r = []
+            for v in vs:
+                f = v**3 / (math.pi * m)
+                h = f * 2e-4
+                P = lambda x: L.orc_tf2_phase_so(x, mc, eta, b.value, s.value, g5.value, s6.value, s7.value,  # noqa: E731
+                                                 0.0, 0.0)
+                dpsi = (-P(f + 2 * h) + 8 * P(f + h) - 8 * P(f - h) + P(f - 2 * h)) / (12 * h)
+                r.append(-dpsi / (2 * math.pi) / (5 * m / (256 * eta * v**8)) - 1.0)
+            basis = np.stack([vs**2, vs**3, vs**4, vs**5, vs**6, vs**6 * np.log(vs), vs**7], axis=1)
+            fits.append(np.linalg.lstsq(basis, np.array(r), rcond=None)[0])
+        odd = 0.5 * (fits[0] - fits[1])
+        want = _tau_spin_orbit_linear(eta, q, c1, c2)
+        for i, k in ((1, 3), (3, 5), (4, 6), (6, 7)):
+            worst = max(worst, abs(odd[i] - want[k]) / (2e-5 * abs(want[k]) + 1e-8))
+    return worst
+
+
+def test_spin_orbit_phase_matches_energy_balance_to_3p5pn():
+    """The spin-orbit model's TaylorF2 phase (spin-orbit terms at 1.5, 2.5, 3
+    and 3.5PN): the part of its time to coalescence that is odd in the spins
+    (fitted at small spins, where it is linear in them) has the 1.5PN, 2.5PN,
+    3PN and 3.5PN coefficients that energy balance gives from the spin-orbit
+    terms of the binding energy and the flux, the 3PN spin-orbit tail
+    included.  A 1 percent change of any spin-orbit coefficient, or of one of
+    its mass-ratio terms, fails it."""
+    assert _so_worst(oracle.lib()) < 1.0
+
+
 def test_phase_shift_structure():
     """Psi(t_c, phi_c) - Psi(0, 0) = 2 pi f t_c - phi_c at every frequency."""
     for f in (20.0, 55.5, 300.0):
