@@ -75,8 +75,12 @@ enum { NS_PRIOR_UNIFORM = 0, NS_PRIOR_COS = 1, NS_PRIOR_SIN = 2, NS_PRIOR_VOLUME
  *            distance fixed_dist_mpc.
  *   TF2_11P  parameters (Mc [Msun], q = m2/m1 in (0,1], chi1, chi2 (aligned
  *            spins), d_L [Mpc], theta_jn [rad], psi [rad], RA [rad], Dec [rad],
- *            t_c [s], phi_c [rad]); a detector network. */
-enum { NS_MODEL_TF2_4P = 1, NS_MODEL_TF2_11P = 2 };
+ *            t_c [s], phi_c [rad]); a detector network.  Spin terms: spin-orbit
+ *            at 1.5PN, spin-spin (chi1 chi2) at 2PN.
+ *   TF2_11P_SO  TF2_11P with the spin-orbit phase terms above 1.5PN as
+ *            well (2.5PN, the 3PN tail term and 3.5PN, linear in the spins),
+ *            the richer aligned-spin waveform of paper Sections 2-3's family. */
+enum { NS_MODEL_TF2_4P = 1, NS_MODEL_TF2_11P = 2, NS_MODEL_TF2_11P_SO = 3 };
 
 /* Likelihood forms: full grid; relative binning (heterodyned coarse grid,
  * rb_n_bins geometric bins, fiducial waveform at rb_fiducial); and a

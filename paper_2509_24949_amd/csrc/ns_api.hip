@@ -76,11 +76,12 @@ int validate_and_model(const ns_problem* P, ModelDev* M) {
     M->n_bins = 0;
     return NS_OK;
   }
-  if (P->model != NS_MODEL_TF2_4P && P->model != NS_MODEL_TF2_11P) return fail(NS_E_ARG, "unknown waveform model");
+  if (P->model != NS_MODEL_TF2_4P && P->model != NS_MODEL_TF2_11P && P->model != NS_MODEL_TF2_11P_SO)
+    return fail(NS_E_ARG, "unknown waveform model");
   M->model = P->model;
   if (P->model == NS_MODEL_TF2_4P && (P->n_dim != 4 || P->n_det != 1))
     return fail(NS_E_ARG, "TF2_4P needs n_dim = 4 and n_det = 1");
-  if (P->model == NS_MODEL_TF2_11P && (P->n_dim != 11 || P->n_det < 1 || P->n_det > MAX_DET))
+  if (P->model != NS_MODEL_TF2_4P && (P->n_dim != 11 || P->n_det < 1 || P->n_det > MAX_DET))
     return fail(NS_E_ARG, "TF2_11P needs n_dim = 11 and 1 <= n_det <= %d", MAX_DET);
   if (!(P->f_lo > 0.0) || !(P->df > 0.0) || P->n_bins < 2) return fail(NS_E_ARG, "grid needs f_lo > 0, df > 0, n_bins >= 2");
   if (!P->data_re || !P->data_im || !P->psd) return fail(NS_E_ARG, "data and psd arrays are NULL");
@@ -125,9 +126,9 @@ int validate_and_model(const ns_problem* P, ModelDev* M) {
   for (int i = 0; i < P->n_dim; ++i) {
     const int k = P->prior_kind[i];
     bool ok = (k == NS_PRIOR_UNIFORM);
-    if (P->model == NS_MODEL_TF2_11P && i == 4) ok = ok || k == NS_PRIOR_VOLUME;
-    if (P->model == NS_MODEL_TF2_11P && i == 5) ok = ok || k == NS_PRIOR_COS;
-    if (P->model == NS_MODEL_TF2_11P && i == 8) ok = ok || k == NS_PRIOR_SIN;
+    if (P->model != NS_MODEL_TF2_4P && i == 4) ok = ok || k == NS_PRIOR_VOLUME;
+    if (P->model != NS_MODEL_TF2_4P && i == 5) ok = ok || k == NS_PRIOR_COS;
+    if (P->model != NS_MODEL_TF2_4P && i == 8) ok = ok || k == NS_PRIOR_SIN;
     if (!ok) return fail(NS_E_ARG, "prior %d: kind %d is not supported for this model coordinate", i, k);
   }
   const double m_min = mc_min * TSUN_S * pow(eta_max, -0.6);
@@ -143,7 +144,7 @@ int validate_and_model(const ns_problem* P, ModelDev* M) {
       if (!isfinite(th[i])) return fail(NS_E_ARG, "rb_fiducial[%d] is not finite", i);
     if (!(th[0] > 0.0)) return fail(NS_E_ARG, "fiducial chirp mass must be positive");
     if (P->model == NS_MODEL_TF2_4P && !(th[1] > 0.0 && th[1] <= 0.25)) return fail(NS_E_ARG, "fiducial eta must lie in (0, 0.25]");
-    if (P->model == NS_MODEL_TF2_11P && !(th[1] > 0.0 && th[1] <= 1.0 && th[4] > 0.0))
+    if (P->model != NS_MODEL_TF2_4P && !(th[1] > 0.0 && th[1] <= 1.0 && th[4] > 0.0))
       return fail(NS_E_ARG, "fiducial needs q in (0, 1] and a positive distance");
   }
   return NS_OK;

@@ -138,6 +138,7 @@ __device__ inline double cube_coord(unsigned periodic, int i, double y) {
 // Physical quantities of one parameter point, reduced to what the strain needs.
 struct Phys {
   double mc_msun, eta, beta, sigma, dist_s, tc, phic;
+  double so5, so6, so7;           // spin-orbit phase terms above 1.5PN (model 3; else 0)
   double hp, hx;                  // (1 + cos^2 i)/2 and cos i
   double sra, cra, sdec, cdec;    // sin/cos of (RA - GMST) and of Dec
   double s2psi, c2psi;            // sin/cos of 2 psi
@@ -184,12 +185,27 @@ __device__ inline double prior_plain(const PriorDev& P, int i, double u) {
 // Affine (uniform) transform of coordinate i.
 __device__ inline double prior_affine(const PriorDev& P, int i, double u) { return fma(u, P.b[i], P.a[i]); }
 
+// Spin-orbit phase terms of waveform model 3 above 1.5PN, linear in the
+// aligned spins: so5 joins the 2.5PN coefficient (inside its 1 + 3 ln v),
+// so6 the 3PN and so7 the 3.5PN coefficient; chi_s, chi_a are the symmetric
+// and antisymmetric spins and delta = (m1 - m2)/M.
+__device__ inline void spin_orbit_coefficients(double eta, double c1, double c2, double delta, double* so5,
+                                               double* so6, double* so7) {
+  const double e2 = eta * eta, e3 = e2 * eta;
+  const double cs = 0.5 * (c1 + c2), ca = 0.5 * (c1 - c2);
+  *so5 = (732985.0 / 2268.0 - 24260.0 / 81.0 * eta - 340.0 / 9.0 * e2) * cs + (732985.0 / 2268.0 + 140.0 / 9.0 * eta) * delta * ca;
+  *so6 = PI * (2270.0 / 3.0 * delta * ca + (2270.0 / 3.0 - 520.0 * eta) * cs);
+  *so7 = (-25150083775.0 / 3048192.0 + 10566655595.0 / 762048.0 * eta - 1042165.0 / 3024.0 * e2 + 5345.0 / 36.0 * e3) * cs +
+         delta * (-25150083775.0 / 3048192.0 + 26804935.0 / 6048.0 * eta - 1985.0 / 48.0 * e2) * ca;
+}
+
 // Unit-cube point -> physical quantities.  The model fixes which prior kinds
 // each coordinate may use (checked at run creation): uniform everywhere,
 // uniform-in-volume for the distance, isotropic (COS) for theta_jn and (SIN)
 // for the declination, whose cosine/sine then come straight from u.
 __device__ inline void phys_from_u(const ModelDev& M, const double* u, Phys* s) {
   s->beta = 0.0; s->sigma = 0.0; s->hp = 1.0; s->hx = 0.0;
+  s->so5 = 0.0; s->so6 = 0.0; s->so7 = 0.0;
   s->sra = 0; s->cra = 1; s->sdec = 0; s->cdec = 1; s->s2psi = 0; s->c2psi = 1;
   const PriorDev& P = M.prior;
   s->mc_msun = prior_affine(P, 0, u[0]);
@@ -208,6 +224,7 @@ __device__ inline void phys_from_u(const ModelDev& M, const double* u, Phys* s) 
   const double m1 = 1.0 / opq, m2 = q / opq;
   s->beta = (c1 * (113.0 * m1 * m1 + 75.0 * s->eta) + c2 * (113.0 * m2 * m2 + 75.0 * s->eta)) * (1.0 / 12.0);
   s->sigma = 79.0 / 8.0 * s->eta * c1 * c2;
+  if (M.model == 3) spin_orbit_coefficients(s->eta, c1, c2, m1 - m2, &s->so5, &s->so6, &s->so7);
   const double dv = prior_affine(P, 4, u[4]);
   s->dist_s = (P.kind[4] == 3 ? cbrt(dv) : dv) * MPC_S;
   const double ci = (P.kind[5] == 1) ? prior_affine(P, 5, u[5])
@@ -236,6 +253,7 @@ __device__ inline void phys_from_u(const ModelDev& M, const double* u, Phys* s) 
 // the heterodyne fiducial).
 __device__ inline void phys_from_theta(const ModelDev& M, const double* th, Phys* s) {
   s->beta = 0.0; s->sigma = 0.0; s->hp = 1.0; s->hx = 0.0;
+  s->so5 = 0.0; s->so6 = 0.0; s->so7 = 0.0;
   s->sra = 0; s->cra = 1; s->sdec = 0; s->cdec = 1; s->s2psi = 0; s->c2psi = 1;
   s->mc_msun = th[0];
   if (M.model == 1) {
@@ -248,6 +266,7 @@ __device__ inline void phys_from_theta(const ModelDev& M, const double* th, Phys
   double m1 = 1.0 / opq, m2 = q / opq;
   s->beta = (c1 * (113.0 * m1 * m1 + 75.0 * s->eta) + c2 * (113.0 * m2 * m2 + 75.0 * s->eta)) / 12.0;
   s->sigma = 79.0 / 8.0 * s->eta * c1 * c2;
+  if (M.model == 3) spin_orbit_coefficients(s->eta, c1, c2, m1 - m2, &s->so5, &s->so6, &s->so7);
   s->dist_s = th[4] * MPC_S;
   const double ci = sincos_cycles(th[5] / TWO_PI).y;
   s->hp = 0.5 * fma(ci, ci, 1.0);
@@ -266,23 +285,25 @@ __device__ inline void phys_from_theta(const ModelDev& M, const double* th, Phys
 }
 
 // Coefficients of the 3.5PN TaylorF2 phase with leading-order aligned-spin
-// terms (spin-orbit beta at 1.5PN, spin-spin sigma at 2PN):
+// terms (spin-orbit beta at 1.5PN, spin-spin sigma at 2PN) and the
+// spin-orbit terms so5, so6, so7 above them (zero except in model 3):
 //   Psi = 2 pi f t_c - phi_c - pi/4 + 3/(128 eta v^5) sum_k psi_k v^k,
 // with ln v at 2.5PN and psi_6 containing -(6848/21) ln(4 v).
-__device__ inline void pn_coefficients(double eta, double beta, double sigma, Probe* p) {
+__device__ inline void pn_coefficients(double eta, double beta, double sigma, double so5, double so6, double so7,
+                                       Probe* p) {
   double e2 = eta * eta, e3 = e2 * eta;
   p->c2 = 3715.0 / 756.0 + 55.0 / 9.0 * eta;
   p->c3 = -16.0 * PI + 4.0 * beta;
   p->c4 = 15293365.0 / 508032.0 + 27145.0 / 504.0 * eta + 3085.0 / 72.0 * e2 - 10.0 * sigma;
-  double a5 = PI * (38645.0 / 756.0 - 65.0 / 9.0 * eta);
+  double a5 = PI * (38645.0 / 756.0 - 65.0 / 9.0 * eta) - so5;
   p->c5 = a5;
   p->c5l = 3.0 * a5;
   p->c6 = 11583231236531.0 / 4694215680.0 - 640.0 / 3.0 * PI * PI - 6848.0 / 21.0 * EULER_GAMMA
           - 6848.0 / 21.0 * 1.3862943611198906
           + (-15737765635.0 / 3048192.0 + 2255.0 / 12.0 * PI * PI) * eta + 76055.0 / 1728.0 * e2
-          - 127825.0 / 1296.0 * e3;
+          - 127825.0 / 1296.0 * e3 + so6;
   p->c6l = -6848.0 / 21.0;
-  p->c7 = PI * (77096675.0 / 254016.0 + 378515.0 / 1512.0 * eta - 74045.0 / 756.0 * e2);
+  p->c7 = PI * (77096675.0 / 254016.0 + 378515.0 / 1512.0 * eta - 74045.0 / 756.0 * e2) + so7;
 }
 
 // Physical quantities -> probe coefficients: masses, amplitude
@@ -295,7 +316,7 @@ __device__ inline void probe_from_phys(const ModelDev& M, const Phys& s, const d
   p->lnx = ln_pim * (1.0 / 3.0);
   p->x = exp(p->lnx);
   p->pref = (3.0 / 128.0 / TWO_PI) / s.eta * exp(-5.0 * p->lnx);
-  pn_coefficients(s.eta, s.beta, s.sigma, p);
+  pn_coefficients(s.eta, s.beta, s.sigma, s.so5, s.so6, s.so7, p);
   p->tc = s.tc;
   p->ph0 = (-s.phic - 0.25 * PI) * (1.0 / TWO_PI);
   double x3 = p->x * p->x * p->x;                    // pi M
@@ -384,6 +405,8 @@ __device__ inline int probe_intrinsic(const ModelDev& M, const double* u, ProbeR
   const double eta = m4p ? v1 : eta_q;
   const double beta = m4p ? 0.0 : beta_q;
   const double sigma = m4p ? 0.0 : sigma_q;
+  double so5 = 0.0, so6 = 0.0, so7 = 0.0;
+  if (M.model == 3) spin_orbit_coefficients(eta_q, c1, c2, m1 - m2, &so5, &so6, &so7);
   const double tc = m4p ? v2 : v9;
   const double phic = m4p ? v3 : v10;
   const double ln_mc = log(mc_msun * TSUN_S);
@@ -393,7 +416,7 @@ __device__ inline int probe_intrinsic(const ModelDev& M, const double* u, ProbeR
   p.x = exp(p.lnx);
   const double x2 = p.x * p.x;
   p.pref = (3.0 / 128.0 / TWO_PI) / (eta * (x2 * x2 * p.x));
-  pn_coefficients(eta, beta, sigma, &p);
+  pn_coefficients(eta, beta, sigma, so5, so6, so7, &p);
   r->x = p.x; r->lnx = p.lnx; r->pref = p.pref;
   r->c2 = p.c2; r->c3 = p.c3; r->c4 = p.c4; r->c5 = p.c5; r->c5l = p.c5l; r->c6 = p.c6; r->c6l = p.c6l; r->c7 = p.c7;
   r->tc = tc;

@@ -71,7 +71,7 @@ struct ProblemCopy {
       P.data_im = dim.data();
       P.psd = psd.data();
     }
-    if (p.likelihood != NS_LIKE_GAUSS && p.model == NS_MODEL_TF2_11P && p.det_geom) {
+    if (p.likelihood != NS_LIKE_GAUSS && p.model != NS_MODEL_TF2_4P && p.det_geom) {
       geom.assign(p.det_geom, p.det_geom + 9 * (size_t)p.n_det);
       P.det_geom = geom.data();
     }

@@ -74,7 +74,7 @@ def main():
         with open(OUT) as fh:
             out = json.load(fh)
     jobs = []
-    for name in ("tf2_3det", "tf2_3det_rb"):
+    for name in ("tf2_3det", "tf2_3det_rb", "tf2_3det_so"):
         jobs.append((name, lambda name=name: full_run(synth.workload(name), n_threads)))
 
     def large_population():

@@ -63,7 +63,7 @@ def _data(w):
     return binding.ProblemSpec(w, re, im)
 
 
-@pytest.mark.parametrize("name", ["tf2_3det", "tf2_3det_rb"])
+@pytest.mark.parametrize("name", ["tf2_3det", "tf2_3det_rb", "tf2_3det_so"])
 def test_complete_run_matches_oracle(golden, name):
     w = synth.workload(name)
     run = binding.Run(_data(w), binding.opts_for(w))

@@ -42,7 +42,7 @@ def _scale(w, orc_prob, u):
     return lam, np.abs(lam + half_hh) + half_hh + 1.0
 
 
-@pytest.mark.parametrize("name", ["tf2_1det", "tf2_3det"])
+@pytest.mark.parametrize("name", ["tf2_1det", "tf2_3det", "tf2_3det_so"])
 def test_waveform_parity(torch_cuda, name):
     w = synth.workload(name)
     orc = oracle.OracleProblem(w)
@@ -59,8 +59,8 @@ def test_waveform_parity(torch_cuda, name):
                 assert np.array_equal(gr == 0, hr == 0)
 
 
-@pytest.mark.parametrize("name,n", [("tf2_1det", 4099), ("tf2_3det", 2053), ("event/16", 1031), ("event/32", 1031),
-                                    ("event/39", 517)])
+@pytest.mark.parametrize("name,n", [("tf2_1det", 4099), ("tf2_3det", 2053), ("tf2_3det_so", 2053), ("event/16", 1031),
+                                    ("event/32", 1031), ("event/39", 517)])
 def test_loglike_parity(torch_cuda, name, n):
     """Full-grid likelihood against the oracle's on the 473- and 4017-bin
     workloads and on 16 s (16065 bins) and 32 s (32129 bins) serving events,
@@ -195,8 +195,9 @@ def test_one_detector_full_run_lockstep(torch_cuda):
     assert abs(mean[0] - w.theta_inj[0]) < 0.5          # chirp mass recovered
 
 
-def test_three_detector_iterations_lockstep(torch_cuda):
-    w = synth.workload("tf2_3det")
+@pytest.mark.parametrize("name", ["tf2_3det", "tf2_3det_so"])
+def test_three_detector_iterations_lockstep(torch_cuda, name):
+    w = synth.workload(name)
     orc, spec = _pair(w)
     ro, rg = _lockstep(w, orc, spec, 2)
     _compare_runs(ro, rg)
