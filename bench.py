@@ -30,7 +30,10 @@ if ROOT not in sys.path:
 LANE_OPS = 256 * 4 * 16 * 2.4e9            # 39.3e12 lane-instructions/s
 FP64_PEAK_TFLOPS = 2 * LANE_OPS / 1e12     # FMA: 78.6 TFLOP/s
 FP32_PEAK_TFLOPS = 4 * LANE_OPS / 1e12     # packed FMA: 157.3 TFLOP/s
-TRANS_PEAK_TOPS = LANE_OPS / 4 / 1e12      # single-precision sin/cos/exp/log: quarter rate, 9.8 Tops/s
+# single-precision sine/cosine on the transcendental unit: half rate on gfx950,
+# 19.7 Tops/s (the rate probe, `bench.py --unit-rates`, measures 8.3 cycles per
+# wave64 instruction, dependent or not, against 4.3 for a double FMA)
+TRANS_PEAK_TOPS = LANE_OPS / 2 / 1e12
 SINCOS_FLOPS = 44                # flops of the double-precision sincos in cycles
 PHASE_FLOPS = 24                 # per (probe, bin): PN phase series, shared by the detectors
 DET_FLOPS = 2 + SINCOS_FLOPS + 8 # per (probe, bin, detector): delay, sincos, complex accumulate
@@ -111,7 +114,7 @@ def bins_per_edge(terms: int, probes: int) -> float:
 def peak_tflops(w, bins_per_edge=None) -> float:
     """Rate of the vector units on this workload's operation mix: its
     operations over the shortest time the units need for them (double FMA at
-    78.6 TFLOP/s, packed single FMA at 157.3, transcendentals at 9.8 Tops/s).
+    78.6 TFLOP/s, packed single FMA at 157.3, transcendentals at 19.7 Tops/s).
     Equals the double-precision peak for the double-precision forms."""
     f64, f32, tr = op_mix(w, bins_per_edge)
     t = f64 / FP64_PEAK_TFLOPS + f32 / FP32_PEAK_TFLOPS + tr / TRANS_PEAK_TOPS
@@ -473,9 +476,20 @@ def main():
     ap.add_argument("--load", type=float, default=2.0, help="serving: arrival rate / sequential service rate")
     ap.add_argument("--precision", default="fp64", choices=("fp64", "mixed"), help="serving: arithmetic")
     ap.add_argument("--max-iter", type=int, default=400, help="serving: iteration capacity per run")
+    ap.add_argument("--unit-rates", action="store_true",
+                    help="only run the vector-unit rate probe (cycles per instruction, core clock, chip FMA and "
+                         "sine/cosine throughput) and print its JSON")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (reference for HBM byte counters)")
     args = ap.parse_args()
+    if args.unit_rates:
+        import subprocess
+
+        exe = os.path.join(ROOT, "paper_2509_24949_amd", "unit_rates")
+        if not os.path.exists(exe):
+            print("bench.py: unit_rates is not built (python -m paper_2509_24949_amd.build)", file=sys.stderr)
+            sys.exit(1)
+        sys.exit(subprocess.run([exe]).returncode)
     if args.copy_calibration:
         import torch
 

@@ -15,6 +15,8 @@ SOURCES = [os.path.join(HERE, "csrc", f) for f in (
     "ns_api.hip", "ns_server.hip", "ns_kernels.hip", "ns_slice_d1.hip", "ns_slice_d2.hip", "ns_slice_d3.hip",
     "ns_slice_p64.hip", "ns_slice_p128.hip", "ns_walk.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+RATES_SRC = os.path.join(HERE, "csrc", "unit_rates.hip")
+RATES = os.path.join(HERE, "unit_rates")
 
 COMMON = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
@@ -61,6 +63,15 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
+    # the vector-unit rate probe the benchmark's peaks rest on (bench.py --unit-rates)
+    dev, host, obj = _objects(RATES_SRC, objdir)
+    run_all([dev])
+    run_all([host])
+    cmd = [HIPCC, "--offload-arch=gfx950", "-o", RATES + ".tmp", obj]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(RATES + ".tmp", RATES)
     return LIB
 
 

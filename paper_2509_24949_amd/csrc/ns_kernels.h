@@ -849,6 +849,60 @@ __global__ __launch_bounds__(256) void k_probe_setup(const ModelDev* __restrict_
   if (terms) terms[i] = pr.k_act;
 }
 
+// Set-up pass of the full-grid batch for the 11-parameter models: two
+// threads per probe, one computing the intrinsic half of its source and
+// the other the extrinsic half (as the chain kernel's candidates do).  The
+// block's unit-cube points are read into LDS with coalesced loads, and the
+// finished coefficient records leave through LDS, so consecutive threads
+// store consecutive 8-byte words.
+constexpr int SETUP2_PROBES = 128;    // probes per 256-thread block
+
+__host__ __device__ inline size_t setup2_lds_bytes() {
+  return SETUP2_PROBES * (MAX_DIM * sizeof(double) + sizeof(ProbeRec) + sizeof(Probe));
+}
+
+template <int NDET>
+__global__ __launch_bounds__(256) void k_probe_setup2(const ModelDev* __restrict__ Mp, const double* __restrict__ hpre,
+                                                      const double* __restrict__ u, long n, Probe* __restrict__ P,
+                                                      int* __restrict__ terms) {
+  extern __shared__ double smem[];
+  const ModelDev& M = *Mp;
+  const int tid = threadIdx.x;
+  const int d = M.n_dim;
+  const long p0 = (long)blockIdx.x * SETUP2_PROBES;
+  const int np = (int)min((long)SETUP2_PROBES, n - p0);
+  double* su = smem;                                                    // [np][d]
+  ProbeRec* recs = reinterpret_cast<ProbeRec*>(smem + SETUP2_PROBES * MAX_DIM);
+  Probe* out = reinterpret_cast<Probe*>(recs + SETUP2_PROBES);
+  for (int e = tid; e < np * d; e += 256) su[e] = u[p0 * d + e];
+  __syncthreads();
+  const int j = tid & (SETUP2_PROBES - 1);
+  if (j < np) {
+    double y[MAX_DIM];
+#pragma unroll
+    for (int q = 0; q < MAX_DIM; ++q) y[q] = (q < d) ? su[j * d + q] : 0.0;
+    ProbeRec* rec = recs + j;
+    if (tid < SETUP2_PROBES) {
+      const int ka = probe_intrinsic(M, y, rec);
+#pragma unroll
+      for (int dd = 0; dd < NDET; ++dd) rec->hk[dd] = ka > 0 ? hpre[(size_t)dd * M.n_bins + ka - 1] : 0.0;
+    } else {
+      probe_extrinsic<NDET>(M, y, rec);
+    }
+  }
+  __syncthreads();
+  if (tid < np) {
+    out[tid] = probe_from_rec<NDET>(recs[tid], true);
+    if (terms) terms[p0 + tid] = recs[tid].k_act;
+  }
+  __syncthreads();
+  static_assert(sizeof(Probe) % 8 == 0, "records move as 8-byte words");
+  const int words = np * (int)(sizeof(Probe) / 8);
+  const double* src = reinterpret_cast<const double*>(out);
+  double* dst = reinterpret_cast<double*>(P + p0);
+  for (int w = tid; w < words; w += 256) dst[w] = src[w];
+}
+
 template <int NDET, int LK, bool LDS>
 // 1024 threads share one staged copy of the tables, so a CU holds eight
 // waves per SIMD.
@@ -2178,8 +2232,12 @@ hipError_t launch_loglike_t(const ModelDev& M, const ModelDev* Md, const Tables&
                             const double* u, long n, double* out, int* terms, Probe* pbuf, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   if (LK != LK_GAUSS && pbuf) {
-    hipLaunchKernelGGL(k_probe_setup, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, Md, T.hpre, u, n, pbuf,
-                       terms);
+    if (M.model == 1)
+      hipLaunchKernelGGL(k_probe_setup, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, Md, T.hpre, u, n, pbuf,
+                         terms);
+    else
+      hipLaunchKernelGGL((k_probe_setup2<NDET>), dim3((unsigned)((n + SETUP2_PROBES - 1) / SETUP2_PROBES)), dim3(256),
+                         setup2_lds_bytes(), st, Md, T.hpre, u, n, pbuf, terms);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const size_t lds = LDS ? staged_table_bytes(M.k_lim, NDET, lk_mixed(LK)) : 0;
