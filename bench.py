@@ -53,6 +53,8 @@ WORKLOADS = {
     "tf2_3det_rb": _GRID2 + ", relative binning (128 geometric bins), n_live 1000, n_delete 500, 55 slice steps, FP64",
     "tf2_3det_mixed": _GRID2 + ", full-grid Whittle, n_live 2000, n_delete 1000, 55 slice steps, mixed precision",
     "tf2_3det_rb_mixed": _GRID2 + ", relative binning (128 bins), n_live 2000, n_delete 1000, 55 slice steps, mixed precision",
+    "tf2_3det_n2000": _GRID2 + ", full-grid Whittle, n_live 2000, n_delete 1000, 55 slice steps, FP64",
+    "tf2_3det_rb_n2000": _GRID2 + ", relative binning (128 bins), n_live 2000, n_delete 1000, 55 slice steps, FP64",
     "tf2_3det_rb_walk": _GRID2 + ", relative binning (128 bins), n_live 1000, n_delete 500, random-walk chains "
                         "(differential-evolution proposals, 60 accepted per chain), FP64",
     "tf2_3det_rb_paper": _GRID2 + ", relative binning (128 bins), the paper's settings: n_live 3000, n_delete 1500, "
@@ -139,9 +141,18 @@ def cpu_baseline(name: str, seconds: float, threads: int):
         iters += 1
     dt = time.perf_counter() - t0
     ev = run.state()["n_evals"] - e0
+    # one host thread on every 16th probe of the standalone batch
+    u = synth.proposal_batch(w, 65536, seed=77)[::16]
+    t1 = time.perf_counter()
+    prob.loglike_batch(u, 1)
+    dt1 = time.perf_counter() - t1
     return {"value": ev / dt, "unit": "evals/s", "cores": threads, "kind": "oracle",
             "sample": f"{iters} sampler iterations of the same workload from its initial population "
-                      f"({ev} likelihood evaluations in {dt:.1f} s, OpenMP over chains)"}
+                      f"({ev} likelihood evaluations in {dt:.1f} s, OpenMP over chains)",
+            "single_thread_batch": {"value": len(u) / dt1, "unit": "evals/s", "cores": 1,
+                                    "sample": f"every 16th of the standalone batch's 65536 probes ({len(u)} probes "
+                                              f"in {dt1:.2f} s)"},
+            "host": host_info()}
 
 
 def _pct(x, q):
@@ -291,7 +302,9 @@ def serving(args, precision_name=None) -> dict:
                        "evals_per_s": seq_evals / sum(service),
                        "note": "measured service time of each event run alone; latencies are those service "
                                "times queued first-in first-out at the same arrival times"},
-        "logZ_served_vs_sequential": {"max_abs_over_sigma": max(dz), "median_abs_over_sigma": _pct(dz, 50)},
+        "logZ_served_vs_sequential": {"max_abs_over_sigma": max(dz), "median_abs_over_sigma": _pct(dz, 50),
+                                      "within_2_sigma": bool(max(dz) <= 2.0),
+                                      "events_beyond_2_sigma": int(sum(1 for v in dz if v > 2.0))},
         "roofline": {"bound": "alu", "kernel": "whole serving loop (algorithmic flops over the makespan)",
                      "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": None},
@@ -422,6 +435,111 @@ def coverage(args) -> dict:
             "rows": rows}
 
 
+# stored complete oracle runs (tests/golden/full_runs.json) with the same
+# seeds as a workload, where the key differs from the workload's name
+GOLDEN_RUN = {"tf2_3det_n2000": "tf2_3det_n2000_fp64"}
+# (workload, its probes' stored oracle values, stored oracle run to compare
+# the complete run with): the configurations the error is reported for
+ACCURACY_CONFIGS = (
+    ("tf2_1det", "tf2_1det", "tf2_1det"),
+    ("tf2_3det", "tf2_3det", "tf2_3det"),
+    ("tf2_3det_rb", "tf2_3det_rb", "tf2_3det_rb"),
+    ("tf2_3det_mixed", "tf2_3det", "tf2_3det_n2000_fp64"),
+    ("tf2_3det_rb_mixed", "tf2_3det_rb", "tf2_3det_rb_n2000_fp64"),
+)
+
+
+def accuracy() -> dict:
+    """Error against the double-precision oracle per configuration, from the
+    oracle's stored values (tests/golden): the log-likelihood ratio on 512
+    seeded probes (all, and the half around the injection), and the complete
+    run's log Z against the stored oracle run of the same event and
+    population in double precision (same seeds: identical runs in double
+    precision; independent runs in the mixed form, so |d log Z| is also given
+    in units of the two runs' combined sigma).  Each side injects the signal
+    into the same seeded noise with its own waveform code.  Also the
+    relative-binning likelihood against the full grid on 4096 probes around
+    the injection, both on the GPU."""
+    import numpy as np
+    import torch
+
+    from paper_2509_24949_amd import binding, synth
+
+    gdir = os.path.join(ROOT, "tests", "golden")
+    with open(os.path.join(gdir, "loglike_samples.json")) as fh:
+        samples = json.load(fh)
+    with open(os.path.join(gdir, "full_runs.json")) as fh:
+        runs = json.load(fh)
+    out = {}
+    for name, lam_key, run_key in ACCURACY_CONFIGS:
+        w = synth.workload(name)
+        spec = binding.ProblemSpec(w, *binding.make_data(w))
+        r = binding.Run(spec, binding.opts_for(w))
+        n = samples["n_probes"]
+        u = torch.from_numpy(synth.proposal_batch(w, n, seed=samples["seed"])).cuda()
+        lam = torch.empty(n, dtype=torch.float64, device="cuda")
+        r.loglike(u, lam)
+        torch.cuda.synchronize()
+        d = np.abs(lam.cpu().numpy() - np.asarray(samples[lam_key]))
+        row = {"probes": n, "max_abs_dlogl": float(d.max()), "max_abs_dlogl_near_injection": float(d[: n // 2].max()),
+               "median_abs_dlogl": float(np.median(d))}
+        assert r.run(1000)
+        z = r.logZ(200)
+        r.close()
+        g = runs.get(run_key)
+        if g:
+            dz = abs(z["logZ"] - g["logZ"])
+            row.update({"logZ": z["logZ"], "sigma_logZ": z["sigma"], "logZ_oracle": g["logZ"], "oracle_run": run_key,
+                        "abs_dlogZ": dz, "abs_dlogZ_over_sigma": dz / math.hypot(z["sigma"], g["sigma"])})
+        out[name] = row
+    # relative binning against the full grid, both on the GPU, near the injection
+    w_full, w_rb = synth.workload("tf2_3det"), synth.workload("tf2_3det_rb")
+    re, im = binding.make_data(w_full)
+    u = torch.from_numpy(synth.proposal_batch(w_full, 4096, seed=99, frac_local=1.0)).cuda()
+    vals = []
+    for w in (w_full, w_rb):
+        r = binding.Run(binding.ProblemSpec(w, re, im), binding.opts_for(w))
+        lam = torch.empty(4096, dtype=torch.float64, device="cuda")
+        r.loglike(u, lam)
+        torch.cuda.synchronize()
+        vals.append(lam.cpu().numpy())
+        r.close()
+    d = np.abs(vals[1] - vals[0])
+    out["rb_vs_full_near_injection"] = {"probes": 4096, "max_abs_dlogl": float(d.max()),
+                                        "median_abs_dlogl": float(np.median(d)),
+                                        "logl_range": [float(vals[0].min()), float(vals[0].max())]}
+    return out
+
+
+def unit_rates():
+    """The vector-unit rate probe's JSON (None if it is not built)."""
+    import subprocess
+
+    exe = os.path.join(ROOT, "paper_2509_24949_amd", "unit_rates")
+    if not os.path.exists(exe):
+        return None
+    res = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    return json.loads(res.stdout) if res.returncode == 0 else None
+
+
+def host_info() -> dict:
+    """The host the CPU baseline ran on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = None
+    return {"nproc": os.cpu_count(), "usable_cpus": usable, "cpu_model": model}
+
+
 def standalone_loglike(w, spec, n_probes: int = 65536, reps: int = 20) -> dict:
     """The fused waveform-plus-likelihood kernel alone on a batch of probes,
     half prior draws and half around the injection; HIP events on the
@@ -467,6 +585,8 @@ def main():
     ap.add_argument("--no-run", action="store_true", help="skip the complete-run timing")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving summary")
     ap.add_argument("--no-standalone", action="store_true", help="skip the standalone likelihood kernel")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the per-configuration error against the stored oracle values")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "slice_kernel_traffic.json"))
     ap.add_argument("--events", type=int, default=64, help="serving: number of events")
     ap.add_argument("--max-runs", type=int, default=32, help="serving: resident-run slots")
@@ -483,13 +603,13 @@ def main():
                     help="only run a plain device copy of MIB MiB (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.unit_rates:
-        import subprocess
-
-        exe = os.path.join(ROOT, "paper_2509_24949_amd", "unit_rates")
-        if not os.path.exists(exe):
-            print("bench.py: unit_rates is not built (python -m paper_2509_24949_amd.build)", file=sys.stderr)
+        rates = unit_rates()
+        if rates is None:
+            print("bench.py: the rate probe is not built or failed (python -m paper_2509_24949_amd.build)",
+                  file=sys.stderr)
             sys.exit(1)
-        sys.exit(subprocess.run([exe]).returncode)
+        print(json.dumps(rates), flush=True)
+        return
     if args.copy_calibration:
         import torch
 
@@ -548,7 +668,7 @@ def main():
         golden = os.path.join(ROOT, "tests", "golden", "full_runs.json")
         if os.path.exists(golden):
             with open(golden) as fh:
-                g = json.load(fh).get(args.workload)
+                g = json.load(fh).get(GOLDEN_RUN.get(args.workload, args.workload))
             if g:   # the stored complete run of the double-precision oracle, same seeds
                 run_info["accuracy_vs_oracle"] = {
                     "logZ_oracle": g["logZ"], "abs_delta_logZ": abs(z["logZ"] - g["logZ"]),
@@ -617,11 +737,14 @@ def main():
             f"{out['standalone_loglike']['frac'] * 100:.1f}% of peak")
     if not args.no_serving and args.workload == "tf2_3det":
         keys = ("value", "unit", "latency_p50_s", "latency_p99_s", "makespan_s", "evals_per_s", "sequential",
-                "logZ_served_vs_sequential", "config")
+                "logZ_served_vs_sequential", "roofline", "config")
         sv = serving(args, "fp64")
         out["serving"] = {k: sv[k] for k in keys}
         sv = serving(args, "mixed")
         out["serving_mixed"] = {k: sv[k] for k in keys}
+    if not args.no_accuracy and args.workload == "tf2_3det":
+        out["accuracy_vs_oracle_per_config"] = accuracy()
+        out["unit_rates"] = unit_rates()
     if not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)
         log(f"bench: timing the oracle on {threads} host threads for about {args.cpu_seconds:.0f} s")

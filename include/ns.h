@@ -321,9 +321,12 @@ typedef struct {
 /* Create a server.  hbm_budget: device bytes the resident runs may hold
  * (0: 90% of the free memory now); max_runs: resident-run slots, 1..4096;
  * flags: 0 or NS_SERVER_GRAPH (needs a stream other than the null stream).
- * Runs are built and advanced on stream, which the caller keeps alive until
- * ns_server_free and while it uses runs taken from the server.
- * Errors: NS_E_ARG, NS_E_OOM, NS_E_HIP. */
+ * Resident runs are sorted into three lanes by the cost of one probe
+ * (detectors times the most bins a probe can have active: below 1024, below
+ * 4096, above), each advanced on a stream of its own; runs are built on a
+ * further stream (all four created by the server at the default priority).
+ * A run taken from the server is handed over on stream, which the caller
+ * keeps alive while it uses such runs.  Errors: NS_E_ARG, NS_E_OOM, NS_E_HIP. */
 NS_API int ns_server_create(ns_server** out, size_t hbm_budget, int max_runs, int flags, void* stream);
 
 /* Queue a request.  problem and opts are validated now and copied (the
@@ -332,10 +335,12 @@ NS_API int ns_server_create(ns_server** out, size_t hbm_budget, int max_runs, in
  * alone would exceed the budget. */
 NS_API int ns_server_submit(ns_server* server, const ns_problem* problem, const ns_opts* opts, long long* ticket);
 
-/* Admit what fits, run n_iters (1..1000) iterations of every resident run,
- * retire the runs that terminated, admit again.  Synchronises the stream
- * once.  Outputs (may be NULL): resident, queued, and finished-but-not-yet-
- * polled counts. */
+/* Admit what fits, start n_iters (1..1000) iterations of every resident run
+ * on each lane without a tick in flight, wait until some lane's tick has
+ * finished and retire its runs that terminated, admit again and start the
+ * idle lanes' next ticks.  A lane's tick covers the runs resident when it
+ * started; runs admitted meanwhile join its next one.  Outputs (may be
+ * NULL): resident, queued, and finished-but-not-yet-polled counts. */
 NS_API int ns_server_tick(ns_server* server, int n_iters, int* n_running, int* n_queued, int* n_finished);
 
 /* Report finished requests not reported before, up to cap, in the order

@@ -1,8 +1,18 @@
 // Serving scheduler: a queue of sampling requests (one per event), admission
 // of runs by device-memory footprint and slot count, and ticks that advance
-// every resident run by packed launches.  One launch per kernel covers the
-// chains of all resident runs that share a likelihood form, so small runs
-// fill the device together instead of one after another.
+// the resident runs by packed launches.  One launch per kernel covers the
+// chains of all resident runs of a lane that share a likelihood form, so
+// small runs fill the device together instead of one after another.
+//
+// Runs are sorted into lanes by the cost of one probe (detectors times the
+// most bins a probe can have active): a packed chain launch lasts as long as
+// its slowest chain, so a cheap run packed with a costly one would wait for
+// it every iteration.  Each lane has its own stream, descriptor arrays and
+// captured tick, and ticks on its own: a tick launches every idle lane and
+// returns once some lane's tick has finished, so cheap runs advance many
+// iterations while a costly lane works through one, and the lanes' launches
+// overlap on the device.  Runs are built on a further stream, so admission
+// does not wait for the lanes.
 //
 // Every resident run is built with the packed launch configuration (64
 // threads per chain, tables read through the caches) and each workgroup of a
@@ -14,6 +24,7 @@
 #include <chrono>
 #include <deque>
 #include <memory>
+#include <thread>
 
 #include "ns_runtime.h"
 
@@ -22,10 +33,20 @@ using namespace ns;
 namespace {
 
 constexpr int kMaxBypass = 16;   // admissions that may overtake the queue head
+constexpr int kLanes = 3;
+// lane boundaries in bin terms per probe (detectors x the most active bins)
+constexpr long long kLaneCost[kLanes - 1] = {1024, 4096};
 
 int lk_of(const ModelDev& M) {
   if (M.likelihood == NS_LIKE_RB) return M.mixed ? LK_RB32 : LK_RB;
   return M.mixed ? LK_FULL32 : LK_FULL;
+}
+
+int lane_of(const ModelDev& M) {
+  const long long cost = (long long)M.n_det * M.k_lim;
+  int l = 0;
+  while (l < kLanes - 1 && cost >= kLaneCost[l]) ++l;
+  return l;
 }
 
 // A submitted request with private copies of every host array it references.
@@ -58,20 +79,14 @@ struct Group {
   size_t lds;
 };
 
-}  // namespace
-
-struct ns_server {
+// One cost class of resident runs with its own stream and packed-launch
+// descriptors.  While a tick is in flight (busy) the descriptors and the
+// first n_launched entries of running belong to the device; runs admitted in
+// the meantime wait at the end of running for the next tick.
+struct Lane {
   hipStream_t st = nullptr;
-  size_t budget = 0;
-  int max_runs = 0;
-  bool graph = false;
-  size_t used = 0;   // resident and finished-but-not-taken runs
-  long long next_ticket = 1;
-  std::chrono::steady_clock::time_point t0;
-  std::deque<std::unique_ptr<Request>> queue;
+  hipEvent_t ev = nullptr;
   std::vector<Resident> running;
-  std::vector<Finished> finished;
-  // packed-launch descriptors: device arrays and their pinned host images
   PackedRun* d_runs = nullptr;
   int* d_off = nullptr;     // [2][max_runs]: chain-kernel then selection block offsets
   int* d_done = nullptr;    // [max_runs]
@@ -80,28 +95,60 @@ struct ns_server {
   int* h_done = nullptr;
   std::vector<Group> groups;
   bool dirty = true;
+  bool busy = false;
+  int n_launched = 0;
   hipGraphExec_t exec = nullptr;
   int exec_iters = 0;
 
-  double now() const {
-    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  }
   void drop_graph() {
     if (exec) (void)hipGraphExecDestroy(exec);
     exec = nullptr;
     exec_iters = 0;
   }
+};
+
+}  // namespace
+
+struct ns_server {
+  hipStream_t user_st = nullptr;   // runs taken from the server are handed over on it
+  hipStream_t adm_st = nullptr;    // construction of admitted runs
+  size_t budget = 0;
+  int max_runs = 0;
+  bool graph = false;
+  size_t used = 0;   // resident and finished-but-not-taken runs
+  long long next_ticket = 1;
+  std::chrono::steady_clock::time_point t0;
+  std::deque<std::unique_ptr<Request>> queue;
+  Lane lanes[kLanes];
+  std::vector<Finished> finished;
+
+  double now() const {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  int resident() const {
+    int c = 0;
+    for (const Lane& l : lanes) c += (int)l.running.size();
+    return c;
+  }
   ~ns_server() {
-    (void)hipStreamSynchronize(st);
-    drop_graph();
-    for (auto& r : running) delete r.run;
+    for (Lane& l : lanes)
+      if (l.st) (void)hipStreamSynchronize(l.st);
+    if (adm_st) (void)hipStreamSynchronize(adm_st);
+    for (Lane& l : lanes) {
+      l.drop_graph();
+      for (auto& r : l.running) delete r.run;
+      if (l.d_runs) (void)hipFree(l.d_runs);
+      if (l.d_off) (void)hipFree(l.d_off);
+      if (l.d_done) (void)hipFree(l.d_done);
+      if (l.h_runs) (void)hipHostFree(l.h_runs);
+      if (l.h_off) (void)hipHostFree(l.h_off);
+      if (l.h_done) (void)hipHostFree(l.h_done);
+      if (l.ev) (void)hipEventDestroy(l.ev);
+    }
     for (auto& f : finished) delete f.run;
-    if (d_runs) (void)hipFree(d_runs);
-    if (d_off) (void)hipFree(d_off);
-    if (d_done) (void)hipFree(d_done);
-    if (h_runs) (void)hipHostFree(h_runs);
-    if (h_off) (void)hipHostFree(h_off);
-    if (h_done) (void)hipHostFree(h_done);
+    for (Lane& l : lanes)
+      if (l.st) (void)hipStreamDestroy(l.st);
+    if (adm_st) (void)hipStreamDestroy(adm_st);
   }
 };
 
@@ -109,11 +156,12 @@ namespace {
 
 // Admit queued requests in arrival order while slots and memory allow; a
 // request that does not fit may be overtaken by later ones that do, until it
-// has been overtaken kMaxBypass times.
+// has been overtaken kMaxBypass times.  Runs are built on the admission
+// stream and join their lane's next tick.
 int admit(ns_server* s) {
   bool head_blocked = false;
   for (auto it = s->queue.begin(); it != s->queue.end();) {
-    if ((int)s->running.size() >= s->max_runs) break;
+    if (s->resident() >= s->max_runs) break;
     Request& q = **it;
     const bool fits = s->used + q.resident + q.transient <= s->budget;
     if (!fits) {
@@ -125,7 +173,7 @@ int admit(ns_server* s) {
     if (head_blocked) s->queue.front()->bypassed += 1;
     ns_run* r = nullptr;
     const double ta = s->now();
-    const int rc = run_create(&r, &q.prob.P, &q.O, s->st, true);
+    const int rc = run_create(&r, &q.prob.P, &q.O, s->adm_st, true);
     if (rc != NS_OK) {
       Finished f{};
       f.info.ticket = q.ticket;
@@ -137,32 +185,34 @@ int admit(ns_server* s) {
       f.reported = false;
       s->finished.push_back(f);
     } else {
-      s->running.push_back(Resident{q.ticket, r, q.resident, q.t_submit, ta, lk_of(r->M), r->C.slice_threads});
+      Lane& l = s->lanes[lane_of(r->M)];
+      r->st = l.st;      // built and synchronised on the admission stream; advanced on its lane's
+      l.running.push_back(Resident{q.ticket, r, q.resident, q.t_submit, ta, lk_of(r->M), r->C.slice_threads});
+      l.dirty = true;
       s->used += q.resident;
-      s->dirty = true;
     }
     it = s->queue.erase(it);
   }
   return NS_OK;
 }
 
-// Group the resident runs by likelihood form and chain-workgroup size and
+// Group an idle lane's runs by likelihood form and chain-workgroup size and
 // upload the descriptors.
-int rebuild(ns_server* s) {
-  s->drop_graph();
-  std::stable_sort(s->running.begin(), s->running.end(), [](const Resident& a, const Resident& b) {
+int rebuild(ns_server* s, Lane& L) {
+  L.drop_graph();
+  std::stable_sort(L.running.begin(), L.running.end(), [](const Resident& a, const Resident& b) {
     return a.lk != b.lk ? a.lk < b.lk : a.nt < b.nt;
   });
-  s->groups.clear();
-  const int nr = (int)s->running.size();
-  int* slice_off = s->h_off;
-  int* rank_off = s->h_off + s->max_runs;
+  L.groups.clear();
+  const int nr = (int)L.running.size();
+  int* slice_off = L.h_off;
+  int* rank_off = L.h_off + s->max_runs;
   for (int i = 0; i < nr; ++i) {
-    const ns_run* r = s->running[i].run;
-    s->h_runs[i] = PackedRun{r->Md, r->T, r->RB, r->R};
-    if (s->groups.empty() || s->groups.back().lk != s->running[i].lk || s->groups.back().nt != s->running[i].nt)
-      s->groups.push_back(Group{i, 0, s->running[i].lk, s->running[i].nt, 0, 0, 0});
-    Group& g = s->groups.back();
+    const ns_run* r = L.running[i].run;
+    L.h_runs[i] = PackedRun{r->Md, r->T, r->RB, r->R};
+    if (L.groups.empty() || L.groups.back().lk != L.running[i].lk || L.groups.back().nt != L.running[i].nt)
+      L.groups.push_back(Group{i, 0, L.running[i].lk, L.running[i].nt, 0, 0, 0});
+    Group& g = L.groups.back();
     slice_off[i] = g.slice_blocks;
     rank_off[i] = g.rank_blocks;
     g.count += 1;
@@ -171,48 +221,97 @@ int rebuild(ns_server* s) {
     g.lds = std::max(g.lds, r->C.lds_bytes);
   }
   if (nr > 0) {
-    HIP_OK(hipMemcpyAsync(s->d_runs, s->h_runs, nr * sizeof(PackedRun), hipMemcpyHostToDevice, s->st));
-    HIP_OK(hipMemcpyAsync(s->d_off, s->h_off, 2 * s->max_runs * sizeof(int), hipMemcpyHostToDevice, s->st));
+    HIP_OK(hipMemcpyAsync(L.d_runs, L.h_runs, nr * sizeof(PackedRun), hipMemcpyHostToDevice, L.st));
+    HIP_OK(hipMemcpyAsync(L.d_off, L.h_off, 2 * s->max_runs * sizeof(int), hipMemcpyHostToDevice, L.st));
   }
-  s->dirty = false;
+  L.dirty = false;
   return NS_OK;
 }
 
-hipError_t enqueue_iterations(ns_server* s, int n_iters) {
+hipError_t enqueue_iterations(ns_server* s, Lane& L, int n_iters) {
   for (int it = 0; it < n_iters; ++it)
-    for (const Group& g : s->groups) {
-      hipError_t e = launch_iteration_packed(s->d_runs + g.first, s->d_off + s->max_runs + g.first,
-                                             s->d_off + g.first, g.count, g.rank_blocks, g.slice_blocks, g.lk,
-                                             g.nt, g.lds, s->st);
+    for (const Group& g : L.groups) {
+      hipError_t e = launch_iteration_packed(L.d_runs + g.first, L.d_off + s->max_runs + g.first,
+                                             L.d_off + g.first, g.count, g.rank_blocks, g.slice_blocks, g.lk,
+                                             g.nt, g.lds, L.st);
       if (e != hipSuccess) return e;
     }
   return hipSuccess;
 }
 
-int launch_tick(ns_server* s, int n_iters) {
+int launch_tick(ns_server* s, Lane& L, int n_iters) {
   if (!s->graph) {
-    HIP_OK(enqueue_iterations(s, n_iters));
+    HIP_OK(enqueue_iterations(s, L, n_iters));
     return NS_OK;
   }
-  if (!s->exec || s->exec_iters != n_iters) {
-    s->drop_graph();
+  if (!L.exec || L.exec_iters != n_iters) {
+    L.drop_graph();
     hipGraph_t g = nullptr;
-    HIP_OK(hipStreamBeginCapture(s->st, hipStreamCaptureModeRelaxed));
-    const hipError_t e = enqueue_iterations(s, n_iters);
-    const hipError_t e2 = hipStreamEndCapture(s->st, &g);
+    HIP_OK(hipStreamBeginCapture(L.st, hipStreamCaptureModeRelaxed));
+    const hipError_t e = enqueue_iterations(s, L, n_iters);
+    const hipError_t e2 = hipStreamEndCapture(L.st, &g);
     if (e != hipSuccess || e2 != hipSuccess) {
       if (g) (void)hipGraphDestroy(g);
       return fail(NS_E_HIP, "capturing a tick: %s", hipGetErrorString(e != hipSuccess ? e : e2));
     }
-    const hipError_t e3 = hipGraphInstantiate(&s->exec, g, nullptr, nullptr, 0);
+    const hipError_t e3 = hipGraphInstantiate(&L.exec, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e3 != hipSuccess) {
-      s->exec = nullptr;
+      L.exec = nullptr;
       return fail(NS_E_HIP, "instantiating a tick: %s", hipGetErrorString(e3));
     }
-    s->exec_iters = n_iters;
+    L.exec_iters = n_iters;
   }
-  HIP_OK(hipGraphLaunch(s->exec, s->st));
+  HIP_OK(hipGraphLaunch(L.exec, L.st));
+  return NS_OK;
+}
+
+// Start a tick on an idle lane with resident runs: n_iters iterations of
+// every run, then the runs' termination flags to the host and the lane's
+// event.
+int start_lane(ns_server* s, Lane& L, int n_iters) {
+  int rc;
+  if (L.dirty && (rc = rebuild(s, L))) return rc;
+  const int nr = (int)L.running.size();
+  if ((rc = launch_tick(s, L, n_iters))) return rc;
+  HIP_OK(launch_gather_done(L.d_runs, nr, L.d_done, L.st));
+  HIP_OK(hipMemcpyAsync(L.h_done, L.d_done, nr * sizeof(int), hipMemcpyDeviceToHost, L.st));
+  HIP_OK(hipEventRecord(L.ev, L.st));
+  L.n_launched = nr;
+  L.busy = true;
+  return NS_OK;
+}
+
+// A lane's tick has finished: retire the runs that terminated.
+int finish_lane(ns_server* s, Lane& L) {
+  const double tf = s->now();
+  std::vector<Resident> keep;
+  keep.reserve(L.running.size());
+  for (int i = 0; i < (int)L.running.size(); ++i) {
+    Resident& r = L.running[i];
+    if (i >= L.n_launched || !L.h_done[i]) {
+      keep.push_back(r);
+      continue;
+    }
+    int rc;
+    if ((rc = sync_state(r.run))) return rc;
+    r.run->st = s->user_st;
+    Finished f{};
+    f.info.ticket = r.ticket;
+    f.info.status = NS_OK;
+    f.info.done = L.h_done[i];
+    f.info.iterations = r.run->h_state->iter;
+    f.info.t_submit = r.t_submit;
+    f.info.t_admit = r.t_admit;
+    f.info.t_finish = tf;
+    f.info.bytes = r.bytes;
+    f.run = r.run;
+    f.reported = false;
+    s->finished.push_back(f);
+    L.dirty = true;
+  }
+  L.running.swap(keep);
+  L.busy = false;
   return NS_OK;
 }
 
@@ -228,7 +327,7 @@ int ns_server_create(ns_server** out, size_t hbm_budget, int max_runs, int flags
   if ((flags & NS_SERVER_GRAPH) && !stream) return fail(NS_E_ARG, "NS_SERVER_GRAPH needs a stream other than the null stream");
   std::unique_ptr<ns_server> s(new (std::nothrow) ns_server());
   if (!s) return fail(NS_E_OOM, "host allocation failed");
-  s->st = static_cast<hipStream_t>(stream);
+  s->user_st = static_cast<hipStream_t>(stream);
   s->max_runs = max_runs;
   s->graph = (flags & NS_SERVER_GRAPH) != 0;
   s->t0 = std::chrono::steady_clock::now();
@@ -238,14 +337,20 @@ int ns_server_create(ns_server** out, size_t hbm_budget, int max_runs, int flags
     hbm_budget = free_b / 10 * 9;
   }
   s->budget = hbm_budget;
-  if (hipMalloc((void**)&s->d_runs, max_runs * sizeof(PackedRun)) != hipSuccess ||
-      hipMalloc((void**)&s->d_off, 2 * max_runs * sizeof(int)) != hipSuccess ||
-      hipMalloc((void**)&s->d_done, max_runs * sizeof(int)) != hipSuccess ||
-      hipHostMalloc((void**)&s->h_runs, max_runs * sizeof(PackedRun), hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&s->h_off, 2 * max_runs * sizeof(int), hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&s->h_done, max_runs * sizeof(int), hipHostMallocDefault) != hipSuccess)
-    return fail(NS_E_OOM, "allocating the server's descriptor arrays failed");
-  memset(s->h_off, 0, 2 * max_runs * sizeof(int));
+  // the lanes' and the admission stream, at the default priority
+  HIP_OK(hipStreamCreateWithFlags(&s->adm_st, hipStreamNonBlocking));
+  for (Lane& l : s->lanes) {
+    HIP_OK(hipStreamCreateWithFlags(&l.st, hipStreamNonBlocking));
+    HIP_OK(hipEventCreateWithFlags(&l.ev, hipEventDisableTiming));
+    if (hipMalloc((void**)&l.d_runs, max_runs * sizeof(PackedRun)) != hipSuccess ||
+        hipMalloc((void**)&l.d_off, 2 * max_runs * sizeof(int)) != hipSuccess ||
+        hipMalloc((void**)&l.d_done, max_runs * sizeof(int)) != hipSuccess ||
+        hipHostMalloc((void**)&l.h_runs, max_runs * sizeof(PackedRun), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&l.h_off, 2 * max_runs * sizeof(int), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&l.h_done, max_runs * sizeof(int), hipHostMallocDefault) != hipSuccess)
+      return fail(NS_E_OOM, "allocating the server's descriptor arrays failed");
+    memset(l.h_off, 0, 2 * max_runs * sizeof(int));
+  }
   *out = s.release();
   return NS_OK;
 }
@@ -278,41 +383,29 @@ int ns_server_tick(ns_server* s, int n_iters, int* n_running, int* n_queued, int
   if (n_iters < 1 || n_iters > 1000) return fail(NS_E_ARG, "n_iters must be in [1, 1000]");
   int rc = admit(s);
   if (rc) return rc;
-  if (s->dirty && (rc = rebuild(s))) return rc;
-  const int nr = (int)s->running.size();
-  if (nr > 0) {
-    if ((rc = launch_tick(s, n_iters))) return rc;
-    HIP_OK(launch_gather_done(s->d_runs, nr, s->d_done, s->st));
-    HIP_OK(hipMemcpyAsync(s->h_done, s->d_done, nr * sizeof(int), hipMemcpyDeviceToHost, s->st));
-    HIP_OK(hipStreamSynchronize(s->st));
-    const double tf = s->now();
-    std::vector<Resident> keep;
-    keep.reserve(nr);
-    for (int i = 0; i < nr; ++i) {
-      Resident& r = s->running[i];
-      if (!s->h_done[i]) {
-        keep.push_back(r);
-        continue;
-      }
-      if ((rc = sync_state(r.run))) return rc;
-      Finished f{};
-      f.info.ticket = r.ticket;
-      f.info.status = NS_OK;
-      f.info.done = s->h_done[i];
-      f.info.iterations = r.run->h_state->iter;
-      f.info.t_submit = r.t_submit;
-      f.info.t_admit = r.t_admit;
-      f.info.t_finish = tf;
-      f.info.bytes = r.bytes;
-      f.run = r.run;
-      f.reported = false;
-      s->finished.push_back(f);
-      s->dirty = true;
+  for (Lane& l : s->lanes)
+    if (!l.busy && !l.running.empty() && (rc = start_lane(s, l, n_iters))) return rc;
+  // wait until some lane's tick has finished
+  for (;;) {
+    bool any_busy = false, finished_one = false;
+    for (Lane& l : s->lanes) {
+      if (!l.busy) continue;
+      any_busy = true;
+      const hipError_t e = hipEventQuery(l.ev);
+      if (e == hipErrorNotReady) continue;
+      if (e != hipSuccess) return fail(NS_E_HIP, "a lane's tick: %s", hipGetErrorString(e));
+      if ((rc = finish_lane(s, l))) return rc;
+      finished_one = true;
     }
-    s->running.swap(keep);
+    if (finished_one || !any_busy) break;
+    std::this_thread::yield();
   }
   if ((rc = admit(s))) return rc;
-  if (n_running) *n_running = (int)s->running.size();
+  // keep the device busy: idle lanes start their next tick before the caller
+  // takes its results
+  for (Lane& l : s->lanes)
+    if (!l.busy && !l.running.empty() && (rc = start_lane(s, l, n_iters))) return rc;
+  if (n_running) *n_running = s->resident();
   if (n_queued) *n_queued = (int)s->queue.size();
   if (n_finished) {
     int c = 0;
@@ -351,8 +444,9 @@ int ns_server_take(ns_server* s, long long ticket, ns_run** out) {
     s->finished.erase(s->finished.begin() + i);
     return NS_OK;
   }
-  for (const auto& r : s->running)
-    if (r.ticket == ticket) return fail(NS_E_STATE, "ticket %lld is still running", ticket);
+  for (const Lane& l : s->lanes)
+    for (const auto& r : l.running)
+      if (r.ticket == ticket) return fail(NS_E_STATE, "ticket %lld is still running", ticket);
   for (const auto& q : s->queue)
     if (q->ticket == ticket) return fail(NS_E_STATE, "ticket %lld is still queued", ticket);
   return fail(NS_E_ARG, "unknown or already taken ticket %lld", ticket);
@@ -362,7 +456,7 @@ int ns_server_info(ns_server* s, size_t* budget, size_t* used, int* n_running, i
   if (!s) return fail(NS_E_ARG, "server is NULL");
   if (budget) *budget = s->budget;
   if (used) *used = s->used;
-  if (n_running) *n_running = (int)s->running.size();
+  if (n_running) *n_running = s->resident();
   if (n_queued) *n_queued = (int)s->queue.size();
   return NS_OK;
 }

@@ -175,6 +175,8 @@ def workload(name: str, distance: float | None = None) -> Workload:
     ``tf2_3det_rb``  tf2_3det with the relative-binning likelihood (128 geometric bins).
     ``tf2_3det_mixed``  tf2_3det in the mixed-precision form with n 2000 / k 1000.
     ``tf2_3det_rb_mixed`` tf2_3det_rb in the mixed-precision form with n 2000 / k 1000.
+    ``tf2_3det_n2000``, ``tf2_3det_rb_n2000``  the same two at n 2000 / k 1000 in
+        double precision (same seeds as the mixed forms).
     ``tf2_3det_so`` tf2_3det with the spin-orbit phase terms through 3.5PN
         (waveform model 3).
     ``tf2_3det_rb_walk`` tf2_3det_rb with the random-walk chain kernel (60
@@ -201,7 +203,7 @@ def workload(name: str, distance: float | None = None) -> Workload:
             n_live=500, n_delete=250, n_steps=20, sampler_seed=1001,
         )
     if name in ("tf2_3det", "tf2_3det_rb", "tf2_3det_mixed", "tf2_3det_rb_mixed", "tf2_3det_rb_paper",
-                "tf2_3det_rb_walk", "tf2_3det_so"):
+                "tf2_3det_rb_walk", "tf2_3det_so", "tf2_3det_n2000", "tf2_3det_rb_n2000"):
         d_inj = distance if distance is not None else inj.get("tf2_3det", {}).get("distance_mpc", 0.0)
         w = Workload(
             name=name, model=MODEL_TF2_11P, likelihood=LIKE_FULL, f_lo=20.0, df=0.25, n_bins=4017,
@@ -216,10 +218,11 @@ def workload(name: str, distance: float | None = None) -> Workload:
         if name == "tf2_3det_rb":
             w.likelihood = LIKE_RB
             w.sampler_seed = 3001
-        if name in ("tf2_3det_mixed", "tf2_3det_rb_mixed"):
-            w.n_live, w.n_delete, w.precision = 2000, 1000, 1
+        if name in ("tf2_3det_mixed", "tf2_3det_rb_mixed", "tf2_3det_n2000", "tf2_3det_rb_n2000"):
+            w.n_live, w.n_delete = 2000, 1000
+            w.precision = 1 if name.endswith("mixed") else 0
             w.sampler_seed = 4001
-            if name == "tf2_3det_rb_mixed":
+            if name in ("tf2_3det_rb_mixed", "tf2_3det_rb_n2000"):
                 w.likelihood = LIKE_RB
         if name == "tf2_3det_so":
             w.model = MODEL_TF2_11P_SO

@@ -1,5 +1,6 @@
-"""Write tests/golden/full_runs.json: complete oracle runs of the full-grid,
-relative-binning and large-population workloads and of a few serving events.
+"""Write tests/golden/full_runs.json: complete oracle runs of the one-detector,
+full-grid, relative-binning, spin-orbit and large-population workloads and of
+a few serving events.
 
 Calls only the oracle (on its own injected data).  For each run it stores
 the evidence summary and a digest of the dead-point sequence (slot and
@@ -74,17 +75,16 @@ def main():
         with open(OUT) as fh:
             out = json.load(fh)
     jobs = []
-    for name in ("tf2_3det", "tf2_3det_rb", "tf2_3det_so"):
+    for name in ("tf2_1det", "tf2_3det", "tf2_3det_rb", "tf2_3det_so"):
         jobs.append((name, lambda name=name: full_run(synth.workload(name), n_threads)))
 
     def large_population():
         # the large-population workload in double precision (the GPU's mixed
         # form is compared statistically against it)
-        w = synth.workload("tf2_3det_mixed")
-        w.precision = 0
-        return full_run(w, n_threads)
+        return full_run(synth.workload("tf2_3det_n2000"), n_threads)
 
     jobs.append(("tf2_3det_n2000_fp64", large_population))
+    jobs.append(("tf2_3det_rb_n2000_fp64", lambda: full_run(synth.workload("tf2_3det_rb_n2000"), n_threads)))
     for i in SERVING_SAMPLE:
         jobs.append((f"event/{i}", lambda i=i: full_run(synth.serving_event(i), n_threads)))
     for i in SERVING_LONG:
