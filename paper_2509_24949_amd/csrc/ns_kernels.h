@@ -761,6 +761,142 @@ __global__ __launch_bounds__(64) void k_loglike_rb(const ModelDev* __restrict__ 
   }
 }
 
+// Batched relative-binning likelihood, one probe per lane.  Every lane sets
+// up its probe and finds its active coarse bins (the bins whose first fine
+// bin lies below its k_act, by bisection of the ascending edge indices); the
+// wavefront then walks the edges e = 0, 1, ... together, so the edge and bin
+// tables are read with scalar loads, one per value for the whole wavefront,
+// and a lane whose probe has fewer active bins idles from its last edge on.
+// At edge e a lane forms the ratio to the fiducial for every detector and
+// adds coarse bin e - 1 from the ratios at edges e - 1 and e.  The bin that
+// straddles f_ISCO is left out of the loop and added afterwards from the
+// sums accumulated up to fine bin k_act - 1, with the ratios at its two
+// edges recomputed.  No cross-lane reduction is needed.
+template <int NDET, bool MX>
+__device__ inline void rb_ratio(const Probe& p, const double* gr, const double* gi, double psi, double f,
+                                double phi0, int d,
+                                typename std::conditional<MX, float, double>::type* rr,
+                                typename std::conditional<MX, float, double>::type* ri) {
+  const double dph = fma(f, p.dt[d], psi) - phi0;
+  if constexpr (MX) {
+    const float2 sc = sincos_cycles_f32((float)(dph - rint(dph)));
+    const float fr = (float)gr[d], fi = (float)gi[d];
+    *rr = fmaf(fr, sc.y, fi * sc.x);
+    *ri = fmaf(fi, sc.y, -fr * sc.x);
+  } else {
+    const double2 sc = sincos_cycles(dph);
+    *rr = gr[d] * sc.y + gi[d] * sc.x;
+    *ri = gi[d] * sc.y - gr[d] * sc.x;
+  }
+}
+
+template <typename RT>
+__device__ inline RT rb_bin_term(RT rr, RT ri, RT nr, RT ni, RT iw, RT a0r, RT a0i, RT a1r, RT a1i, RT b0, RT b1) {
+  const RT half = (RT)0.5, two = (RT)2;
+  const RT r0r = half * (rr + nr), r0i = half * (ri + ni);
+  const RT r1r = (nr - rr) * iw, r1i = (ni - ri) * iw;
+  const RT dh = (a0r * r0r - a0i * r0i) + (a1r * r1r - a1i * r1i);
+  const RT hh = b0 * (r0r * r0r + r0i * r0i) + two * b1 * (r0r * r1r + r0i * r1i);
+  return dh - half * hh;
+}
+
+template <int NDET, bool MX>
+__global__ __launch_bounds__(256) void k_rb_lane(const ModelDev* __restrict__ Mp, RBTables RB,
+                                                 const double* __restrict__ u, long n, double* __restrict__ out,
+                                                 int* __restrict__ terms) {
+  using RT = typename std::conditional<MX, float, double>::type;
+  const ModelDev& M = *Mp;
+  const long i = (long)blockIdx.x * 256 + threadIdx.x;
+  const bool own = i < n;
+  const int d = M.n_dim;
+  const long src = own ? i : 0;
+  double y[MAX_DIM];
+#pragma unroll
+  for (int q = 0; q < MAX_DIM; ++q) y[q] = (q < d) ? u[src * d + q] : 0.0;
+  Probe pr;
+  make_probe(M, nullptr, y, &pr);
+  const int nb = RB.nb, ne = nb + 1;
+  int n_act = 0;
+  if (own) {
+    int lo = 0, hi = nb;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (RB.edge[mid] < pr.k_act) lo = mid + 1;
+      else hi = mid;
+    }
+    n_act = lo;
+  }
+  const int sb = n_act - 1;
+  bool straddle = false;
+  if (n_act > 0) {
+    const int sb_last = (sb < nb - 1) ? RB.edge[sb + 1] - 1 : RB.edge[nb];
+    straddle = sb_last >= pr.k_act;
+  }
+  const int last_loop_bin = straddle ? sb - 1 : sb;   // bins 0 .. last_loop_bin in the loop
+  double gr[NDET], gi[NDET];
+#pragma unroll
+  for (int dd = 0; dd < NDET; ++dd) {
+    const double2 g = RB.g0[dd];
+    gr[dd] = pr.kre[dd] * g.x - pr.kim[dd] * g.y;
+    gi[dd] = pr.kre[dd] * g.y + pr.kim[dd] * g.x;
+  }
+  double part = 0.0;
+  RT pvr[NDET], pvi[NDET];
+#pragma unroll
+  for (int dd = 0; dd < NDET; ++dd) { pvr[dd] = (RT)0; pvi[dd] = (RT)0; }
+  // edges 0 .. last_loop_bin + 1 carry the loop's bins
+  const int last_edge = last_loop_bin + 1;
+  for (int e = 0; __builtin_amdgcn_ballot_w64(e <= last_edge) != 0; ++e) {
+    const bool has_edge = e <= last_edge;
+    const double f = RB.fe[e];
+    const double psi = phase_cycles(pr, f, RB.fe13[e], RB.lnfe3[e], RB.fem53[e]);
+    const int b = e - 1;
+    const RT iw = b >= 0 ? (RT)RB.inv_w[b] : (RT)0;
+#pragma unroll
+    for (int dd = 0; dd < NDET; ++dd) {
+      RT rr, ri;
+      rb_ratio<NDET, MX>(pr, gr, gi, psi, f, RB.phi0[dd * ne + e], dd, &rr, &ri);
+      if (b >= 0 && has_edge) {
+        RT a0r, a0i, a1r, a1i, b0, b1;
+        const size_t q = (size_t)dd * nb + b;
+        if constexpr (MX) {
+          const float2 a0 = RB.A0f[q], a1 = RB.A1f[q];
+          a0r = a0.x; a0i = a0.y; a1r = a1.x; a1i = a1.y;
+          b0 = RB.B0f[q]; b1 = RB.B1f[q];
+        } else {
+          const double2 a0 = RB.A0[q], a1 = RB.A1[q];
+          a0r = a0.x; a0i = a0.y; a1r = a1.x; a1i = a1.y;
+          b0 = RB.B0[q]; b1 = RB.B1[q];
+        }
+        part += (double)rb_bin_term<RT>(pvr[dd], pvi[dd], rr, ri, iw, a0r, a0i, a1r, a1i, b0, b1);
+      }
+      pvr[dd] = rr;
+      pvi[dd] = ri;
+    }
+  }
+  if (straddle) {
+    // the straddling bin sb: ratios at its edges sb and sb + 1, sums up to fine bin k_act - 1
+    const RT iw = (RT)RB.inv_w[sb];
+    const double f0 = RB.fe[sb], f1 = RB.fe[sb + 1];
+    const double psi0 = phase_cycles(pr, f0, RB.fe13[sb], RB.lnfe3[sb], RB.fem53[sb]);
+    const double psi1 = phase_cycles(pr, f1, RB.fe13[sb + 1], RB.lnfe3[sb + 1], RB.fem53[sb + 1]);
+#pragma unroll
+    for (int dd = 0; dd < NDET; ++dd) {
+      RT r0, i0, r1, i1;
+      rb_ratio<NDET, MX>(pr, gr, gi, psi0, f0, RB.phi0[dd * ne + sb], dd, &r0, &i0);
+      rb_ratio<NDET, MX>(pr, gr, gi, psi1, f1, RB.phi0[dd * ne + sb + 1], dd, &r1, &i1);
+      const size_t q = (size_t)dd * M.n_bins + pr.k_act - 1;
+      const double2 a0 = RB.cA0[q], a1 = RB.cA1[q];
+      part += (double)rb_bin_term<RT>(r0, i0, r1, i1, iw, (RT)a0.x, (RT)a0.y, (RT)a1.x, (RT)a1.y, (RT)RB.cB0[q],
+                                      (RT)RB.cB1[q]);
+    }
+  }
+  if (own) {
+    out[i] = part;
+    if (terms) terms[i] = n_act > 0 ? n_act + 1 : 0;
+  }
+}
+
 // Float copies for the mixed form.
 __global__ __launch_bounds__(1024) void k_noise_loglike(const double* __restrict__ dre, const double* __restrict__ dim,
                                                        const double* __restrict__ psd, long n, double df,

@@ -82,24 +82,11 @@ hipError_t launch_init_live(const RunDev& R, hipStream_t st) {
 template <int NDET, bool MX>
 hipError_t launch_loglike_rb_t(const ModelDev* Md, const RBTables& RB, int n_bins, const double* u, long n,
                                double* out, int* terms, Probe* pbuf, hipStream_t st) {
+  (void)n_bins;
+  (void)pbuf;
   if (n <= 0) return hipSuccess;
-  // the two-pass form stages the tables in LDS; coarse grids too large for
-  // a CU's 160 KB take the one-pass form, which reads them through the caches
-  const size_t lds = rb_stage_doubles(RB.nb, NDET, MX) * sizeof(double);
-  if (pbuf && lds <= 160 * 1024) {
-    hipLaunchKernelGGL(k_probe_setup, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, Md, nullptr, u, n, pbuf,
-                       nullptr);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    long blocks = (n + 7) / 8;
-    if (blocks > 256 * 2) blocks = 256 * 2;
-    hipLaunchKernelGGL((k_rb_bins<NDET, MX>), dim3((unsigned)blocks), dim3(512), lds, st, RB, n_bins, pbuf, n, out,
-                       terms);
-    return hipGetLastError();
-  }
-  long blocks = (n + 63) / 64;
-  if (blocks > 8192) blocks = 8192;
-  hipLaunchKernelGGL((k_loglike_rb<NDET, MX>), dim3((unsigned)blocks), dim3(64), 0, st, Md, RB, u, n, out, terms);
+  hipLaunchKernelGGL((k_rb_lane<NDET, MX>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, Md, RB, u, n, out,
+                     terms);
   return hipGetLastError();
 }
 
