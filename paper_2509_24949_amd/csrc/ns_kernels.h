@@ -764,9 +764,11 @@ __global__ __launch_bounds__(64) void k_loglike_rb(const ModelDev* __restrict__ 
 // Batched relative-binning likelihood, one probe per lane.  Every lane sets
 // up its probe and finds its active coarse bins (the bins whose first fine
 // bin lies below its k_act, by bisection of the ascending edge indices); the
-// wavefront then walks the edges e = 0, 1, ... together, so the edge and bin
-// tables are read with scalar loads, one per value for the whole wavefront,
-// and a lane whose probe has fewer active bins idles from its last edge on.
+// wavefront then walks the edges e = 0, 1, ... together, reading one record
+// per edge from a copy of the tables the block stages in LDS (every lane at
+// the same address, the next edge's record loading while this edge is
+// computed), and a lane whose probe has fewer active bins idles from its
+// last edge on.
 // At edge e a lane forms the ratio to the fiducial for every detector and
 // adds coarse bin e - 1 from the ratios at edges e - 1 and e.  The bin that
 // straddles f_ISCO is left out of the loop and added afterwards from the
@@ -800,22 +802,170 @@ __device__ inline RT rb_bin_term(RT rr, RT ri, RT nr, RT ni, RT iw, RT a0r, RT a
   return dh - half * hh;
 }
 
+// One LDS record per edge e for k_rb_lane: the edge's frequency terms, the
+// width of coarse bin e - 1, the fiducial phases at e, then per detector the
+// summary sums of bin e - 1 (zeros for e = 0); in the mixed form the sums are
+// floats, two to a double.
+__host__ __device__ constexpr int rb_lane_rec_doubles(int n_det, bool mixed) {
+  return mixed ? ((5 + 4 * n_det + 1) & ~1) : ((5 + 7 * n_det + 1) & ~1);
+}
+
 template <int NDET, bool MX>
+struct RBEdge {
+  using RT = typename std::conditional<MX, float, double>::type;
+  double f, f13, lnf3, fm53;
+  RT iw;
+  double phi0[NDET];
+  RT a0r[NDET], a0i[NDET], a1r[NDET], a1i[NDET], b0[NDET], b1[NDET];
+};
+
+template <int NDET, bool MX>
+__device__ inline void rb_lane_stage(const RBTables& B, double* lds, int tid, int nt) {
+  constexpr int RD = rb_lane_rec_doubles(NDET, MX);
+  const int nb = B.nb, ne = nb + 1;
+  for (int e = tid; e < ne; e += nt) {
+    double* r = lds + (size_t)e * RD;
+    r[0] = B.fe[e]; r[1] = B.fe13[e]; r[2] = B.lnfe3[e]; r[3] = B.fem53[e];
+    const int b = e - 1;
+#pragma unroll
+    for (int d = 0; d < NDET; ++d) r[5 + d] = B.phi0[d * ne + e];
+    if constexpr (MX) {
+      float* fr = reinterpret_cast<float*>(r + 5 + NDET);
+      reinterpret_cast<float*>(r + 4)[0] = b >= 0 ? (float)B.inv_w[b] : 0.0f;
+#pragma unroll
+      for (int d = 0; d < NDET; ++d) {
+        const size_t q = (size_t)d * nb + b;
+        const float2 a0 = b >= 0 ? B.A0f[q] : make_float2(0.f, 0.f);
+        const float2 a1 = b >= 0 ? B.A1f[q] : make_float2(0.f, 0.f);
+        fr[6 * d + 0] = a0.x; fr[6 * d + 1] = a0.y; fr[6 * d + 2] = a1.x; fr[6 * d + 3] = a1.y;
+        fr[6 * d + 4] = b >= 0 ? B.B0f[q] : 0.f;
+        fr[6 * d + 5] = b >= 0 ? B.B1f[q] : 0.f;
+      }
+    } else {
+      r[4] = b >= 0 ? B.inv_w[b] : 0.0;
+      double* dr = r + 5 + NDET;
+#pragma unroll
+      for (int d = 0; d < NDET; ++d) {
+        const size_t q = (size_t)d * nb + b;
+        const double2 a0 = b >= 0 ? B.A0[q] : make_double2(0.0, 0.0);
+        const double2 a1 = b >= 0 ? B.A1[q] : make_double2(0.0, 0.0);
+        dr[6 * d + 0] = a0.x; dr[6 * d + 1] = a0.y; dr[6 * d + 2] = a1.x; dr[6 * d + 3] = a1.y;
+        dr[6 * d + 4] = b >= 0 ? B.B0[q] : 0.0;
+        dr[6 * d + 5] = b >= 0 ? B.B1[q] : 0.0;
+      }
+    }
+  }
+}
+
+// The record of edge e, read from the tables themselves (coarse grids whose
+// records do not fit in LDS).
+template <int NDET, bool MX>
+__device__ inline void rb_lane_load_tables(const RBTables& B, int e, RBEdge<NDET, MX>& x) {
+  using RT = typename std::conditional<MX, float, double>::type;
+  const int nb = B.nb, ne = nb + 1, b = e - 1;
+  x.f = B.fe[e]; x.f13 = B.fe13[e]; x.lnf3 = B.lnfe3[e]; x.fm53 = B.fem53[e];
+  x.iw = b >= 0 ? (RT)B.inv_w[b] : (RT)0;
+#pragma unroll
+  for (int d = 0; d < NDET; ++d) {
+    x.phi0[d] = B.phi0[d * ne + e];
+    const size_t q = (size_t)d * nb + (b >= 0 ? b : 0);
+    if constexpr (MX) {
+      const float2 a0 = B.A0f[q], a1 = B.A1f[q];
+      x.a0r[d] = a0.x; x.a0i[d] = a0.y; x.a1r[d] = a1.x; x.a1i[d] = a1.y; x.b0[d] = B.B0f[q]; x.b1[d] = B.B1f[q];
+    } else {
+      const double2 a0 = B.A0[q], a1 = B.A1[q];
+      x.a0r[d] = a0.x; x.a0i[d] = a0.y; x.a1r[d] = a1.x; x.a1i[d] = a1.y; x.b0[d] = B.B0[q]; x.b1[d] = B.B1[q];
+    }
+  }
+}
+
+template <int NDET, bool MX>
+__device__ inline void rb_lane_load(const double* lds, int e, RBEdge<NDET, MX>& x) {
+  constexpr int RD = rb_lane_rec_doubles(NDET, MX);
+  const double* r = lds + (size_t)e * RD;
+  x.f = r[0]; x.f13 = r[1]; x.lnf3 = r[2]; x.fm53 = r[3];
+#pragma unroll
+  for (int d = 0; d < NDET; ++d) x.phi0[d] = r[5 + d];
+  if constexpr (MX) {
+    x.iw = reinterpret_cast<const float*>(r + 4)[0];
+    const float* fr = reinterpret_cast<const float*>(r + 5 + NDET);
+#pragma unroll
+    for (int d = 0; d < NDET; ++d) {
+      x.a0r[d] = fr[6 * d]; x.a0i[d] = fr[6 * d + 1]; x.a1r[d] = fr[6 * d + 2]; x.a1i[d] = fr[6 * d + 3];
+      x.b0[d] = fr[6 * d + 4]; x.b1[d] = fr[6 * d + 5];
+    }
+  } else {
+    x.iw = r[4];
+    const double* dr = r + 5 + NDET;
+#pragma unroll
+    for (int d = 0; d < NDET; ++d) {
+      x.a0r[d] = dr[6 * d]; x.a0i[d] = dr[6 * d + 1]; x.a1r[d] = dr[6 * d + 2]; x.a1i[d] = dr[6 * d + 3];
+      x.b0[d] = dr[6 * d + 4]; x.b1[d] = dr[6 * d + 5];
+    }
+  }
+}
+
+// One edge of k_rb_lane: the ratios at edge e and, when the lane has bin
+// e - 1 in its loop, that bin's terms.
+template <int NDET, bool MX>
+__device__ inline void rb_lane_edge(const Probe& pr, const double* gr, const double* gi, const RBEdge<NDET, MX>& x,
+                                    bool add_bin,
+                                    typename std::conditional<MX, float, double>::type* pvr,
+                                    typename std::conditional<MX, float, double>::type* pvi, double& part) {
+  using RT = typename std::conditional<MX, float, double>::type;
+  const double psi = phase_cycles(pr, x.f, x.f13, x.lnf3, x.fm53);
+#pragma unroll
+  for (int dd = 0; dd < NDET; ++dd) {
+    RT rr, ri;
+    rb_ratio<NDET, MX>(pr, gr, gi, psi, x.f, x.phi0[dd], dd, &rr, &ri);
+    if (add_bin)
+      part += (double)rb_bin_term<RT>(pvr[dd], pvi[dd], rr, ri, x.iw, x.a0r[dd], x.a0i[dd], x.a1r[dd], x.a1i[dd],
+                                      x.b0[dd], x.b1[dd]);
+    pvr[dd] = rr;
+    pvi[dd] = ri;
+  }
+}
+
+// H = 2: two lanes per probe, lanes j and j + 32 of a wavefront holding
+// probe j of the wavefront's 32; they set up the intrinsic and the extrinsic
+// half of its source (as the chain kernel's candidates do, meeting in a
+// record in LDS), then the lower lane walks edges 0 .. M and the
+// upper lane edges M .. of the probe's loop (M, half the wavefront's longest
+// loop, is common to the wavefront, so each load still has two addresses),
+// and the two halves' sums are added at the end.  Twice the wavefronts for
+// the same batch hide each other's latencies.
+template <int NDET, bool MX, bool LDS, int H>
 __global__ __launch_bounds__(256) void k_rb_lane(const ModelDev* __restrict__ Mp, RBTables RB,
                                                  const double* __restrict__ u, long n, double* __restrict__ out,
                                                  int* __restrict__ terms) {
   using RT = typename std::conditional<MX, float, double>::type;
+  constexpr int PW = 64 / H;                       // probes per wavefront
+  extern __shared__ double smem[];
   const ModelDev& M = *Mp;
-  const long i = (long)blockIdx.x * 256 + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int half = lane / PW;                      // 0: lower lane of the probe, 1: upper
+  const long i = ((long)blockIdx.x * 4 + (threadIdx.x >> 6)) * PW + (lane % PW);
   const bool own = i < n;
+  // the edge records first: their loads overlap the probe set-up
+  if (LDS) rb_lane_stage<NDET, MX>(RB, smem, threadIdx.x, 256);
   const int d = M.n_dim;
   const long src = own ? i : 0;
   double y[MAX_DIM];
 #pragma unroll
   for (int q = 0; q < MAX_DIM; ++q) y[q] = (q < d) ? u[src * d + q] : 0.0;
-  Probe pr;
-  make_probe(M, nullptr, y, &pr);
   const int nb = RB.nb, ne = nb + 1;
+  Probe pr;
+  if constexpr (H == 2) {
+    // the probe's two lanes set up its intrinsic and extrinsic halves side by side
+    ProbeRec* rec = reinterpret_cast<ProbeRec*>(smem + (LDS ? (size_t)ne * rb_lane_rec_doubles(NDET, MX) : 0)) +
+                    ((threadIdx.x >> 6) * PW + lane % PW);
+    if (half == 0) probe_intrinsic(M, y, rec);
+    else probe_extrinsic<NDET>(M, y, rec);
+    __syncthreads();
+    pr = probe_from_rec<NDET>(*rec, false);
+  } else {
+    make_probe(M, nullptr, y, &pr);
+  }
   int n_act = 0;
   if (own) {
     int lo = 0, hi = nb;
@@ -832,7 +982,18 @@ __global__ __launch_bounds__(256) void k_rb_lane(const ModelDev* __restrict__ Mp
     const int sb_last = (sb < nb - 1) ? RB.edge[sb + 1] - 1 : RB.edge[nb];
     straddle = sb_last >= pr.k_act;
   }
-  const int last_loop_bin = straddle ? sb - 1 : sb;   // bins 0 .. last_loop_bin in the loop
+  // the loop takes bins 0 .. last_edge - 1 from edges 0 .. last_edge
+  const int last_edge = straddle ? sb : sb + 1;
+  // this lane's edges: first .. last
+  int first = 0, last = last_edge;
+  if constexpr (H == 2) {
+    int mx = last_edge;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) mx = max(mx, __shfl_xor(mx, o, 64));
+    const int mid = (mx + 1) >> 1;
+    if (half == 0) last = min(last_edge, mid);
+    else first = mid;
+  }
   double gr[NDET], gi[NDET];
 #pragma unroll
   for (int dd = 0; dd < NDET; ++dd) {
@@ -840,41 +1001,29 @@ __global__ __launch_bounds__(256) void k_rb_lane(const ModelDev* __restrict__ Mp
     gr[dd] = pr.kre[dd] * g.x - pr.kim[dd] * g.y;
     gi[dd] = pr.kre[dd] * g.y + pr.kim[dd] * g.x;
   }
+  if (LDS && H == 1) __syncthreads();
   double part = 0.0;
   RT pvr[NDET], pvi[NDET];
 #pragma unroll
   for (int dd = 0; dd < NDET; ++dd) { pvr[dd] = (RT)0; pvi[dd] = (RT)0; }
-  // edges 0 .. last_loop_bin + 1 carry the loop's bins
-  const int last_edge = last_loop_bin + 1;
-  for (int e = 0; __builtin_amdgcn_ballot_w64(e <= last_edge) != 0; ++e) {
-    const bool has_edge = e <= last_edge;
-    const double f = RB.fe[e];
-    const double psi = phase_cycles(pr, f, RB.fe13[e], RB.lnfe3[e], RB.fem53[e]);
-    const int b = e - 1;
-    const RT iw = b >= 0 ? (RT)RB.inv_w[b] : (RT)0;
-#pragma unroll
-    for (int dd = 0; dd < NDET; ++dd) {
-      RT rr, ri;
-      rb_ratio<NDET, MX>(pr, gr, gi, psi, f, RB.phi0[dd * ne + e], dd, &rr, &ri);
-      if (b >= 0 && has_edge) {
-        RT a0r, a0i, a1r, a1i, b0, b1;
-        const size_t q = (size_t)dd * nb + b;
-        if constexpr (MX) {
-          const float2 a0 = RB.A0f[q], a1 = RB.A1f[q];
-          a0r = a0.x; a0i = a0.y; a1r = a1.x; a1i = a1.y;
-          b0 = RB.B0f[q]; b1 = RB.B1f[q];
-        } else {
-          const double2 a0 = RB.A0[q], a1 = RB.A1[q];
-          a0r = a0.x; a0i = a0.y; a1r = a1.x; a1i = a1.y;
-          b0 = RB.B0[q]; b1 = RB.B1[q];
-        }
-        part += (double)rb_bin_term<RT>(pvr[dd], pvi[dd], rr, ri, iw, a0r, a0i, a1r, a1i, b0, b1);
-      }
-      pvr[dd] = rr;
-      pvi[dd] = ri;
-    }
+  auto load = [&](int t, RBEdge<NDET, MX>& x) {
+    const int e = min(first + t, nb);
+    if constexpr (LDS) rb_lane_load<NDET, MX>(smem, e, x);
+    else rb_lane_load_tables<NDET, MX>(RB, e, x);
+  };
+  // step t takes edge first + t; two records in flight, the next edge's
+  // loads issued before this edge's arithmetic
+  const int steps = last - first;                  // this lane's last step (negative: none)
+  RBEdge<NDET, MX> xa, xb;
+  load(0, xa);
+  for (int t = 0; __builtin_amdgcn_ballot_w64(t <= steps) != 0; t += 2) {
+    load(t + 1, xb);
+    if (t <= steps) rb_lane_edge<NDET, MX>(pr, gr, gi, xa, t >= 1, pvr, pvi, part);
+    if (__builtin_amdgcn_ballot_w64(t + 1 <= steps) == 0) break;
+    load(t + 2, xa);
+    if (t + 1 <= steps) rb_lane_edge<NDET, MX>(pr, gr, gi, xb, true, pvr, pvi, part);
   }
-  if (straddle) {
+  if (straddle && half == 0) {
     // the straddling bin sb: ratios at its edges sb and sb + 1, sums up to fine bin k_act - 1
     const RT iw = (RT)RB.inv_w[sb];
     const double f0 = RB.fe[sb], f1 = RB.fe[sb + 1];
@@ -891,7 +1040,8 @@ __global__ __launch_bounds__(256) void k_rb_lane(const ModelDev* __restrict__ Mp
                                       (RT)RB.cB1[q]);
     }
   }
-  if (own) {
+  if constexpr (H == 2) part += __shfl_down(part, 32, 64);
+  if (own && half == 0) {
     out[i] = part;
     if (terms) terms[i] = n_act > 0 ? n_act + 1 : 0;
   }

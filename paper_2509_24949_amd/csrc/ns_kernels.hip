@@ -79,14 +79,25 @@ hipError_t launch_init_live(const RunDev& R, hipStream_t st) {
   return hipGetLastError();
 }
 
+// lanes per probe in the relative-binning batch (1 or 2)
+constexpr int RB_LANE_HALVES = 2;
+
 template <int NDET, bool MX>
 hipError_t launch_loglike_rb_t(const ModelDev* Md, const RBTables& RB, int n_bins, const double* u, long n,
                                double* out, int* terms, Probe* pbuf, hipStream_t st) {
   (void)n_bins;
   (void)pbuf;
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_rb_lane<NDET, MX>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, Md, RB, u, n, out,
-                     terms);
+  // the edge records in LDS when they fit in 64 KB (up to about 300 coarse
+  // bins), else read from the tables
+  const size_t lds = (size_t)(RB.nb + 1) * rb_lane_rec_doubles(NDET, MX) * sizeof(double);
+  constexpr int H = RB_LANE_HALVES;
+  const size_t recs = H == 2 ? (256 / H) * sizeof(ProbeRec) : 0;   // the split set-up's records
+  const dim3 grid((unsigned)((n + 256 / H - 1) / (256 / H)));
+  if (lds <= 64 * 1024)
+    hipLaunchKernelGGL((k_rb_lane<NDET, MX, true, H>), grid, dim3(256), lds + recs, st, Md, RB, u, n, out, terms);
+  else
+    hipLaunchKernelGGL((k_rb_lane<NDET, MX, false, H>), grid, dim3(256), recs, st, Md, RB, u, n, out, terms);
   return hipGetLastError();
 }
 

@@ -215,18 +215,32 @@ def test_capacity_and_no_termination(torch_cuda):
     assert rg.state()["iter"] == 40
 
 
-@pytest.mark.parametrize("n", [1031])
-def test_rb_loglike_parity(torch_cuda, n):
-    """Relative-binning likelihood (tf2_3det_rb) against the oracle's, to 1e-9 of the
+def _rb_workload(name, nb):
+    """A relative-binning workload and its full-grid twin (same event)."""
+    if name.startswith("event/"):
+        w, wf = synth.serving_event(int(name[6:])), synth.serving_event(int(name[6:]))
+        w.likelihood = synth.LIKE_RB
+    else:
+        w, wf = synth.workload(name), synth.workload(name.replace("_rb", ""))
+    w.rb_n_bins = nb
+    return w, wf
+
+
+# tf2_3det_rb: 128 coarse bins, the edge records staged in LDS; the 32 s
+# three-detector serving event 32 with 400 coarse bins, whose records do not
+# fit and are read from the tables
+@pytest.mark.parametrize("name,nb,n", [("tf2_3det_rb", 128, 1031), ("event/32", 400, 257)])
+def test_rb_loglike_parity(torch_cuda, name, nb, n):
+    """Relative-binning likelihood against the oracle's, to 1e-9 of the
     cancellation scale, including the fiducial point and cube corners."""
     torch = torch_cuda
-    w = synth.workload("tf2_3det_rb")
+    w, wf = _rb_workload(name, nb)
+    print(f"rb parity {name}: {nb} coarse bins, {n} probes", flush=True)
     orc, spec = _pair(w)
     u = synth.proposal_batch(w, n, seed=11)
     u[0] = 0.0
     u[1] = 1.0
     u[2] = synth.theta_to_cube_box(w, w.theta_inj)
-    wf = synth.workload("tf2_3det")
     orc_full = oracle.OracleProblem(wf, orc.dre, orc.dim)
     _, scale = _scale(wf, orc_full, u)
     lam_o = orc.loglike_batch(u, NTHREADS)
