@@ -44,6 +44,10 @@ DET_FLOPS = 2 + SINCOS_FLOPS + 8 # per (probe, bin, detector): delay, sincos, co
 # as (edges - probes) / edges of it
 RB_EDGE_DET = 2 + SINCOS_FLOPS + 6
 RB_BIN_DET = 27
+# the batched relative-binning kernel sums the same linear model per edge:
+# per (probe, edge, detector) |r|^2, Re(conj(r_prev) r), Re(W r), the G and E
+# terms and the accumulation (15) replace the per-bin terms
+RB_EDGE_FORM_DET = 15
 
 _GRID2 = "3-detector aligned-spin TaylorF2 (11 parameters), 4017 bins/detector (20-1024 Hz, df 0.25 Hz), network SNR 20"
 WORKLOADS = {
@@ -76,20 +80,21 @@ def log(msg: str):
     print(msg, file=sys.stderr, flush=True)
 
 
-def op_mix(w, bins_per_edge=None):
+def op_mix(w, bins_per_edge=None, edge_form=False):
     """Algorithmic work of one counted term (full grid: one active bin of one
     probe; relative binning: one edge read by one probe, with bins_per_edge
     active coarse bins per edge, by default nb/(nb+1)) as (double-precision
     flops, single-precision flops, single-precision transcendental ops).
     The mixed form keeps the phase, the delay and the cycle reduction in
     double (4 flops per detector) and takes sin and cos on the transcendental
-    unit."""
+    unit.  edge_form: the relative-binning linear model summed per edge (the
+    batched kernel) instead of per bin (the chain kernel)."""
     from paper_2509_24949_amd import synth
 
     nd = w.n_det
     if w.likelihood == synth.LIKE_RB:
         bpe = w.rb_n_bins / (w.rb_n_bins + 1) if bins_per_edge is None else bins_per_edge
-        bins = nd * RB_BIN_DET * bpe
+        bins = nd * (RB_EDGE_FORM_DET if edge_form else RB_BIN_DET * bpe)
         if w.precision == 1:
             return PHASE_FLOPS + 4 * nd, 6 * nd + bins, 2 * nd
         return PHASE_FLOPS + nd * RB_EDGE_DET + bins, 0.0, 0.0
@@ -98,15 +103,15 @@ def op_mix(w, bins_per_edge=None):
     return PHASE_FLOPS + nd * DET_FLOPS, 0.0, 0.0
 
 
-def seconds_per_term(w, bins_per_edge=None) -> float:
+def seconds_per_term(w, bins_per_edge=None, edge_form=False) -> float:
     """Shortest time the vector units need for one term of this workload."""
-    f64, f32, tr = op_mix(w, bins_per_edge)
+    f64, f32, tr = op_mix(w, bins_per_edge, edge_form)
     return (f64 / FP64_PEAK_TFLOPS + f32 / FP32_PEAK_TFLOPS + tr / TRANS_PEAK_TOPS) * 1e-12
 
 
-def flops_per_term(w, bins_per_edge=None) -> float:
+def flops_per_term(w, bins_per_edge=None, edge_form=False) -> float:
     """Algorithmic operations per counted term (all kinds together)."""
-    return sum(op_mix(w, bins_per_edge))
+    return sum(op_mix(w, bins_per_edge, edge_form))
 
 
 def bins_per_edge(terms: int, probes: int) -> float:
@@ -116,12 +121,12 @@ def bins_per_edge(terms: int, probes: int) -> float:
     return max(terms - probes, 0) / terms if terms > 0 else 0.0
 
 
-def peak_tflops(w, bins_per_edge=None) -> float:
+def peak_tflops(w, bins_per_edge=None, edge_form=False) -> float:
     """Rate of the vector units on this workload's operation mix: its
     operations over the shortest time the units need for them (double FMA at
     78.6 TFLOP/s, packed single FMA at 157.3, transcendentals at 19.7 Tops/s).
     Equals the double-precision peak for the double-precision forms."""
-    f64, f32, tr = op_mix(w, bins_per_edge)
+    f64, f32, tr = op_mix(w, bins_per_edge, edge_form)
     t = f64 / FP64_PEAK_TFLOPS + f32 / FP32_PEAK_TFLOPS + tr / TRANS_PEAK_TOPS
     return (f64 + f32 + tr) / t
 
@@ -598,10 +603,10 @@ def standalone_loglike(w, spec, n_probes: int = 65536, reps: int = 20) -> dict:
     n_terms = int(terms.sum().item())
     r.close()
     bpe = bins_per_edge(n_terms, n_probes)
-    flops = n_terms * flops_per_term(w, bpe)
-    peak = peak_tflops(w, bpe)
+    flops = n_terms * flops_per_term(w, bpe, edge_form=True)
+    peak = peak_tflops(w, bpe, edge_form=True)
     achieved = flops / launch_s / 1e12
-    return {"kernel": "k_loglike_rb" if w.likelihood == 1 else "k_loglike", "probes": n_probes,
+    return {"kernel": "k_rb_lane" if w.likelihood == 1 else "k_probe_setup2 + k_probe_bins", "probes": n_probes,
             "probe_mix": "half prior draws, half Gaussian (0.02) around the injection in the unit cube",
             "evals_per_s": n_probes / launch_s, "launch_ms": launch_s * 1e3, "terms_per_launch": n_terms,
             "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak}

@@ -196,6 +196,7 @@ void run_footprint(const ns_problem* P, const ns_opts* O, size_t* resident, size
            rounded((size_t)P->n_det * 16) + 2 * rounded(nbin * 16) + 2 * rounded(nbin * 8) + 2 * rounded(nbd * 16) +
            2 * rounded(nbd * 8) + rounded(MAX_DIM * 8);
       if (O->precision == NS_MIXED) b += 2 * rounded(nbin * 8) + 2 * rounded(nbin * 4);
+      b += rounded(rb_edge_record_doubles((int)q, P->n_det, O->precision == NS_MIXED) * 8);
     }
     t = rounded(4 * nbd * 8);
   }
@@ -355,6 +356,15 @@ int run_create(ns_run** out, const ns_problem* P, const ns_opts* O, hipStream_t 
       RB.A0 = B.A0; RB.A1 = B.A1; RB.B0 = B.B0; RB.B1 = B.B1;
       RB.cA0 = B.cA0; RB.cA1 = B.cA1; RB.cB0 = B.cB0; RB.cB1 = B.cB1;
       RB.A0f = B.A0f; RB.A1f = B.A1f; RB.B0f = B.B0f; RB.B1f = B.B1f;
+      if (e == hipSuccess) {
+        if (mem.alloc(&B.erec, rb_edge_record_doubles(nb, M.n_det, M.mixed != 0)) != hipSuccess) {
+          (void)hipFree(stage);
+          return cleanup(fail(NS_E_OOM, "hipMalloc failed for the edge records"));
+        }
+        e = launch_build_rb_edge_records(M, RB, B.erec, r->st);
+        if (e == hipSuccess) e = hipStreamSynchronize(r->st);
+        RB.erec = B.erec;
+      }
     }
     (void)hipFree(stage);
     if (e != hipSuccess) return cleanup(fail(NS_E_HIP, "building likelihood tables: %s", hipGetErrorString(e)));

@@ -59,6 +59,9 @@ struct RBTables {
   const float2* A1f;
   const float* B0f;
   const float* B1f;
+  // the batched kernel's per-edge records (the linear model summed per edge)
+  // and right-hand parts, [nb+1] each, layout fixed by the kernel
+  const double* erec;
 };
 
 // Device buffers of one run.
@@ -161,7 +164,11 @@ struct RBBuffers {
   int* edge; double *fe, *fe13, *lnfe3, *fem53, *phi0, *fm, *inv_w, *B0, *B1, *cB0, *cB1;
   double2 *g0, *A0, *A1, *cA0, *cA1;
   float2 *A0f, *A1f; float *B0f, *B1f;   // mixed form only
+  double* erec;
 };
+// Doubles of the batched relative-binning kernel's edge records for nb coarse bins.
+size_t rb_edge_record_doubles(int nb, int n_det, bool mixed);
+hipError_t launch_build_rb_edge_records(const ModelDev& M, const RBTables& RB, double* erec, hipStream_t st);
 // Mixed form: float copies of the data table (scaled) and of the bin sums.
 hipError_t launch_to_float(const double2* src, float2* dst, size_t n, double scale, hipStream_t st);
 hipError_t launch_to_float(const double* src, float* dst, size_t n, double scale, hipStream_t st);

@@ -765,14 +765,24 @@ __global__ __launch_bounds__(64) void k_loglike_rb(const ModelDev* __restrict__ 
 // up its probe and finds its active coarse bins (the bins whose first fine
 // bin lies below its k_act, by bisection of the ascending edge indices); the
 // wavefront then walks the edges e = 0, 1, ... together, reading one record
-// per edge from a copy of the tables the block stages in LDS (every lane at
-// the same address, the next edge's record loading while this edge is
-// computed), and a lane whose probe has fewer active bins idles from its
-// last edge on.
-// At edge e a lane forms the ratio to the fiducial for every detector and
-// adds coarse bin e - 1 from the ratios at edges e - 1 and e.  The bin that
-// straddles f_ISCO is left out of the loop and added afterwards from the
-// sums accumulated up to fine bin k_act - 1, with the ratios at its two
+// per edge (built at run construction, k_rb_edge_records) from a copy the
+// block stages in LDS (every lane at the same address, the next edge's
+// record loading while this edge is computed), and a lane whose probe has
+// fewer active bins idles from its last edge on.
+//
+// The linear model of coarse bin b, Re(A0 r0 + A1 r1) - 1/2 [B0 |r0|^2 +
+// 2 B1 Re(conj(r0) r1)] with r0 = (r_b + r_{b+1})/2 and r1 = (r_{b+1} - r_b) w_b
+// (w_b the inverse bin width), equals
+//   Re(P_b r_b + Q_b r_{b+1}) - 1/2 [C_b |r_b|^2 + D_b |r_{b+1}|^2 + E_b Re(conj(r_b) r_{b+1})]
+// with P = A0/2 - A1 w, Q = A0/2 + A1 w, C = B0/4 - B1 w, D = B0/4 + B1 w,
+// E = B0/2 (the cross term of 2 B1 Re(conj(r0) r1) cancels).  Summed over
+// consecutive bins, edge e contributes Re(W_e r_e) - 1/2 [G_e |r_e|^2 +
+// E_{e-1} Re(conj(r_{e-1}) r_e)] with W_e = Q_{e-1} + P_e and G_e = D_{e-1} + C_e,
+// so the record of edge e holds W, G and E_{e-1} per detector, and a lane's
+// first edge takes only the right-hand parts P, C (kept in a second table)
+// and its last edge has them taken off again.  The bin that straddles
+// f_ISCO is left out of the walk and added afterwards in the bin form from
+// the sums accumulated up to fine bin k_act - 1, with the ratios at its two
 // edges recomputed.  No cross-lane reduction is needed.
 template <int NDET, bool MX>
 __device__ inline void rb_ratio(const Probe& p, const double* gr, const double* gi, double psi, double f,
@@ -802,176 +812,184 @@ __device__ inline RT rb_bin_term(RT rr, RT ri, RT nr, RT ni, RT iw, RT a0r, RT a
   return dh - half * hh;
 }
 
-// One LDS record per edge e for k_rb_lane: the edge's frequency terms, the
-// width of coarse bin e - 1, the fiducial phases at e, then per detector the
-// summary sums of bin e - 1 (zeros for e = 0); in the mixed form the sums are
-// floats, two to a double.
+// Edge e's coefficients for detector d: W (complex), G, E_{e-1} and the
+// right-hand parts P_e (complex), C_e (bins outside 0 .. nb - 1 contribute 0).
+struct RBEdgeCoef {
+  double wr, wi, g, ep, pr, pi, c;
+};
+
+__device__ inline RBEdgeCoef rb_edge_coef(const RBTables& B, int e, int d) {
+  const int nb = B.nb;
+  RBEdgeCoef k{0, 0, 0, 0, 0, 0, 0};
+  if (e >= 1) {                           // bin e - 1 on the left: Q, D, E
+    const int b = e - 1;
+    const size_t q = (size_t)d * nb + b;
+    const double w = B.inv_w[b];
+    const double2 a0 = B.A0[q], a1 = B.A1[q];
+    k.wr = fma(a1.x, w, 0.5 * a0.x);
+    k.wi = fma(a1.y, w, 0.5 * a0.y);
+    k.g = fma(B.B1[q], w, 0.25 * B.B0[q]);
+    k.ep = 0.5 * B.B0[q];
+  }
+  if (e < nb) {                           // bin e on the right: P, C
+    const size_t q = (size_t)d * nb + e;
+    const double w = B.inv_w[e];
+    const double2 a0 = B.A0[q], a1 = B.A1[q];
+    k.pr = fma(-a1.x, w, 0.5 * a0.x);
+    k.pi = fma(-a1.y, w, 0.5 * a0.y);
+    k.c = fma(-B.B1[q], w, 0.25 * B.B0[q]);
+    k.wr += k.pr;
+    k.wi += k.pi;
+    k.g += k.c;
+  }
+  return k;
+}
+
+// Edge records of k_rb_lane: per edge its frequency terms and fiducial
+// phases and, per detector, W (2), G, E_{e-1}; then per edge and detector the
+// right-hand parts P (2), C.  The mixed form keeps the coefficients as floats.
 __host__ __device__ constexpr int rb_lane_rec_doubles(int n_det, bool mixed) {
-  return mixed ? ((5 + 4 * n_det + 1) & ~1) : ((5 + 7 * n_det + 1) & ~1);
+  return mixed ? ((4 + 3 * n_det + 1) & ~1) : ((4 + 5 * n_det + 1) & ~1);
+}
+__host__ __device__ constexpr int rb_lane_right_doubles(int n_det, bool mixed) {
+  return mixed ? ((3 * n_det + 1) / 2) : 3 * n_det;
 }
 
 template <int NDET, bool MX>
 struct RBEdge {
   using RT = typename std::conditional<MX, float, double>::type;
   double f, f13, lnf3, fm53;
-  RT iw;
   double phi0[NDET];
-  RT a0r[NDET], a0i[NDET], a1r[NDET], a1i[NDET], b0[NDET], b1[NDET];
+  RT wr[NDET], wi[NDET], g[NDET], ep[NDET];
 };
 
+// Builds the edge records (one thread per edge): records [nb+1][RD], then
+// the right-hand parts [nb+1][RR].
 template <int NDET, bool MX>
-__device__ inline void rb_lane_stage(const RBTables& B, double* lds, int tid, int nt) {
-  constexpr int RD = rb_lane_rec_doubles(NDET, MX);
-  const int nb = B.nb, ne = nb + 1;
-  for (int e = tid; e < ne; e += nt) {
-    double* r = lds + (size_t)e * RD;
-    r[0] = B.fe[e]; r[1] = B.fe13[e]; r[2] = B.lnfe3[e]; r[3] = B.fem53[e];
-    const int b = e - 1;
-#pragma unroll
-    for (int d = 0; d < NDET; ++d) r[5 + d] = B.phi0[d * ne + e];
-    if constexpr (MX) {
-      float* fr = reinterpret_cast<float*>(r + 5 + NDET);
-      reinterpret_cast<float*>(r + 4)[0] = b >= 0 ? (float)B.inv_w[b] : 0.0f;
-#pragma unroll
-      for (int d = 0; d < NDET; ++d) {
-        const size_t q = (size_t)d * nb + b;
-        const float2 a0 = b >= 0 ? B.A0f[q] : make_float2(0.f, 0.f);
-        const float2 a1 = b >= 0 ? B.A1f[q] : make_float2(0.f, 0.f);
-        fr[6 * d + 0] = a0.x; fr[6 * d + 1] = a0.y; fr[6 * d + 2] = a1.x; fr[6 * d + 3] = a1.y;
-        fr[6 * d + 4] = b >= 0 ? B.B0f[q] : 0.f;
-        fr[6 * d + 5] = b >= 0 ? B.B1f[q] : 0.f;
-      }
-    } else {
-      r[4] = b >= 0 ? B.inv_w[b] : 0.0;
-      double* dr = r + 5 + NDET;
-#pragma unroll
-      for (int d = 0; d < NDET; ++d) {
-        const size_t q = (size_t)d * nb + b;
-        const double2 a0 = b >= 0 ? B.A0[q] : make_double2(0.0, 0.0);
-        const double2 a1 = b >= 0 ? B.A1[q] : make_double2(0.0, 0.0);
-        dr[6 * d + 0] = a0.x; dr[6 * d + 1] = a0.y; dr[6 * d + 2] = a1.x; dr[6 * d + 3] = a1.y;
-        dr[6 * d + 4] = b >= 0 ? B.B0[q] : 0.0;
-        dr[6 * d + 5] = b >= 0 ? B.B1[q] : 0.0;
-      }
-    }
-  }
-}
-
-// The record of edge e, read from the tables themselves (coarse grids whose
-// records do not fit in LDS).
-template <int NDET, bool MX>
-__device__ inline void rb_lane_load_tables(const RBTables& B, int e, RBEdge<NDET, MX>& x) {
+__global__ void k_rb_edge_records(RBTables B, double* erec) {
   using RT = typename std::conditional<MX, float, double>::type;
-  const int nb = B.nb, ne = nb + 1, b = e - 1;
-  x.f = B.fe[e]; x.f13 = B.fe13[e]; x.lnf3 = B.lnfe3[e]; x.fm53 = B.fem53[e];
-  x.iw = b >= 0 ? (RT)B.inv_w[b] : (RT)0;
+  constexpr int RD = rb_lane_rec_doubles(NDET, MX), RR = rb_lane_right_doubles(NDET, MX);
+  const int nb = B.nb, ne = nb + 1;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  double* r = erec + (size_t)e * RD;
+  double* right = erec + (size_t)ne * RD + (size_t)e * RR;
+  for (int k = 0; k < RD; ++k) r[k] = 0.0;
+  for (int k = 0; k < RR; ++k) right[k] = 0.0;
+  r[0] = B.fe[e]; r[1] = B.fe13[e]; r[2] = B.lnfe3[e]; r[3] = B.fem53[e];
+  RT* c = reinterpret_cast<RT*>(r + 4 + NDET);
+  RT* rt = reinterpret_cast<RT*>(right);
 #pragma unroll
   for (int d = 0; d < NDET; ++d) {
-    x.phi0[d] = B.phi0[d * ne + e];
-    const size_t q = (size_t)d * nb + (b >= 0 ? b : 0);
-    if constexpr (MX) {
-      const float2 a0 = B.A0f[q], a1 = B.A1f[q];
-      x.a0r[d] = a0.x; x.a0i[d] = a0.y; x.a1r[d] = a1.x; x.a1i[d] = a1.y; x.b0[d] = B.B0f[q]; x.b1[d] = B.B1f[q];
-    } else {
-      const double2 a0 = B.A0[q], a1 = B.A1[q];
-      x.a0r[d] = a0.x; x.a0i[d] = a0.y; x.a1r[d] = a1.x; x.a1i[d] = a1.y; x.b0[d] = B.B0[q]; x.b1[d] = B.B1[q];
-    }
+    r[4 + d] = B.phi0[d * ne + e];
+    const RBEdgeCoef k = rb_edge_coef(B, e, d);
+    c[4 * d] = (RT)k.wr; c[4 * d + 1] = (RT)k.wi; c[4 * d + 2] = (RT)k.g; c[4 * d + 3] = (RT)k.ep;
+    rt[3 * d] = (RT)k.pr; rt[3 * d + 1] = (RT)k.pi; rt[3 * d + 2] = (RT)k.c;
   }
 }
 
+// The record of edge e (from the block's LDS copy or from the device array).
 template <int NDET, bool MX>
-__device__ inline void rb_lane_load(const double* lds, int e, RBEdge<NDET, MX>& x) {
+__device__ inline void rb_lane_load(const double* recs, int e, RBEdge<NDET, MX>& x) {
+  using RT = typename std::conditional<MX, float, double>::type;
   constexpr int RD = rb_lane_rec_doubles(NDET, MX);
-  const double* r = lds + (size_t)e * RD;
+  const double* r = recs + (size_t)e * RD;
   x.f = r[0]; x.f13 = r[1]; x.lnf3 = r[2]; x.fm53 = r[3];
+  const RT* c = reinterpret_cast<const RT*>(r + 4 + NDET);
 #pragma unroll
-  for (int d = 0; d < NDET; ++d) x.phi0[d] = r[5 + d];
-  if constexpr (MX) {
-    x.iw = reinterpret_cast<const float*>(r + 4)[0];
-    const float* fr = reinterpret_cast<const float*>(r + 5 + NDET);
-#pragma unroll
-    for (int d = 0; d < NDET; ++d) {
-      x.a0r[d] = fr[6 * d]; x.a0i[d] = fr[6 * d + 1]; x.a1r[d] = fr[6 * d + 2]; x.a1i[d] = fr[6 * d + 3];
-      x.b0[d] = fr[6 * d + 4]; x.b1[d] = fr[6 * d + 5];
-    }
-  } else {
-    x.iw = r[4];
-    const double* dr = r + 5 + NDET;
-#pragma unroll
-    for (int d = 0; d < NDET; ++d) {
-      x.a0r[d] = dr[6 * d]; x.a0i[d] = dr[6 * d + 1]; x.a1r[d] = dr[6 * d + 2]; x.a1i[d] = dr[6 * d + 3];
-      x.b0[d] = dr[6 * d + 4]; x.b1[d] = dr[6 * d + 5];
-    }
+  for (int d = 0; d < NDET; ++d) {
+    x.phi0[d] = r[4 + d];
+    x.wr[d] = c[4 * d]; x.wi[d] = c[4 * d + 1]; x.g[d] = c[4 * d + 2]; x.ep[d] = c[4 * d + 3];
   }
 }
 
-// One edge of k_rb_lane: the ratios at edge e and, when the lane has bin
-// e - 1 in its loop, that bin's terms.
+// The right-hand parts P, C of edge e for detector d.
 template <int NDET, bool MX>
-__device__ inline void rb_lane_edge(const Probe& pr, const double* gr, const double* gi, const RBEdge<NDET, MX>& x,
-                                    bool add_bin,
+__device__ inline void rb_lane_right(const double* recs, int ne, int e, int d,
+                                     typename std::conditional<MX, float, double>::type* pr,
+                                     typename std::conditional<MX, float, double>::type* pi,
+                                     typename std::conditional<MX, float, double>::type* c) {
+  using RT = typename std::conditional<MX, float, double>::type;
+  const RT* rt = reinterpret_cast<const RT*>(recs + (size_t)ne * rb_lane_rec_doubles(NDET, MX) +
+                                             (size_t)e * rb_lane_right_doubles(NDET, MX));
+  *pr = rt[3 * d]; *pi = rt[3 * d + 1]; *c = rt[3 * d + 2];
+}
+
+// One edge of the walk: the ratios r_e and the edge's terms; first: a lane's
+// first edge, which takes only the right-hand parts (pr0, pi0, c0).
+template <int NDET, bool MX>
+__device__ inline void rb_lane_edge(const Probe& p, const double* gr, const double* gi, const RBEdge<NDET, MX>& x,
+                                    bool first, const typename std::conditional<MX, float, double>::type* pr0,
+                                    const typename std::conditional<MX, float, double>::type* pi0,
+                                    const typename std::conditional<MX, float, double>::type* c0,
                                     typename std::conditional<MX, float, double>::type* pvr,
                                     typename std::conditional<MX, float, double>::type* pvi, double& part) {
   using RT = typename std::conditional<MX, float, double>::type;
-  const double psi = phase_cycles(pr, x.f, x.f13, x.lnf3, x.fm53);
+  const double psi = phase_cycles(p, x.f, x.f13, x.lnf3, x.fm53);
+  RT acc = (RT)0;
 #pragma unroll
   for (int dd = 0; dd < NDET; ++dd) {
     RT rr, ri;
-    rb_ratio<NDET, MX>(pr, gr, gi, psi, x.f, x.phi0[dd], dd, &rr, &ri);
-    if (add_bin)
-      part += (double)rb_bin_term<RT>(pvr[dd], pvi[dd], rr, ri, x.iw, x.a0r[dd], x.a0i[dd], x.a1r[dd], x.a1i[dd],
-                                      x.b0[dd], x.b1[dd]);
+    rb_ratio<NDET, MX>(p, gr, gi, psi, x.f, x.phi0[dd], dd, &rr, &ri);
+    const RT wr = first ? pr0[dd] : x.wr[dd], wi = first ? pi0[dd] : x.wi[dd], g = first ? c0[dd] : x.g[dd];
+    const RT m2 = rr * rr + ri * ri;
+    const RT cross = pvr[dd] * rr + pvi[dd] * ri;          // Re(conj(r_{e-1}) r_e); 0 at a first edge
+    acc += (wr * rr - wi * ri) - (RT)0.5 * (g * m2 + x.ep[dd] * cross);
     pvr[dd] = rr;
     pvi[dd] = ri;
   }
+  part += (double)acc;
 }
 
-// H = 2: two lanes per probe, lanes j and j + 32 of a wavefront holding
-// probe j of the wavefront's 32; they set up the intrinsic and the extrinsic
-// half of its source (as the chain kernel's candidates do, meeting in a
-// record in LDS), then the lower lane walks edges 0 .. M and the
-// upper lane edges M .. of the probe's loop (M, half the wavefront's longest
-// loop, is common to the wavefront, so each load still has two addresses),
-// and the two halves' sums are added at the end.  Twice the wavefronts for
-// the same batch hide each other's latencies.
 template <int NDET, bool MX, bool LDS, int H>
 __global__ __launch_bounds__(256) void k_rb_lane(const ModelDev* __restrict__ Mp, RBTables RB,
                                                  const double* __restrict__ u, long n, double* __restrict__ out,
                                                  int* __restrict__ terms) {
   using RT = typename std::conditional<MX, float, double>::type;
   constexpr int PW = 64 / H;                       // probes per wavefront
+  constexpr int RD = rb_lane_rec_doubles(NDET, MX);
   extern __shared__ double smem[];
   const ModelDev& M = *Mp;
   const int lane = threadIdx.x & 63;
   const int half = lane / PW;                      // 0: lower lane of the probe, 1: upper
   const long i = ((long)blockIdx.x * 4 + (threadIdx.x >> 6)) * PW + (lane % PW);
   const bool own = i < n;
-  // the edge records first: their loads overlap the probe set-up
-  if (LDS) rb_lane_stage<NDET, MX>(RB, smem, threadIdx.x, 256);
+  const int nb = RB.nb, ne = nb + 1;
+  // the edge records and indices first: their loads overlap the probe set-up
+  const size_t rec_words = (size_t)ne * (RD + rb_lane_right_doubles(NDET, MX));
+  const double* recs = RB.erec;
+  const int* edge = RB.edge;
+  if (LDS) {
+    for (size_t w = threadIdx.x; w < rec_words; w += 256) smem[w] = RB.erec[w];
+    int* se = reinterpret_cast<int*>(smem + rec_words);
+    for (int w = threadIdx.x; w < ne; w += 256) se[w] = RB.edge[w];
+    recs = smem;
+    edge = se;
+  }
   const int d = M.n_dim;
   const long src = own ? i : 0;
   double y[MAX_DIM];
 #pragma unroll
   for (int q = 0; q < MAX_DIM; ++q) y[q] = (q < d) ? u[src * d + q] : 0.0;
-  const int nb = RB.nb, ne = nb + 1;
+  const size_t staged = LDS ? rec_words + (size_t)(ne + 1) / 2 : 0;
   Probe pr;
   if constexpr (H == 2) {
     // the probe's two lanes set up its intrinsic and extrinsic halves side by side
-    ProbeRec* rec = reinterpret_cast<ProbeRec*>(smem + (LDS ? (size_t)ne * rb_lane_rec_doubles(NDET, MX) : 0)) +
-                    ((threadIdx.x >> 6) * PW + lane % PW);
+    ProbeRec* rec = reinterpret_cast<ProbeRec*>(smem + staged) + ((threadIdx.x >> 6) * PW + lane % PW);
     if (half == 0) probe_intrinsic(M, y, rec);
     else probe_extrinsic<NDET>(M, y, rec);
     __syncthreads();
     pr = probe_from_rec<NDET>(*rec, false);
   } else {
     make_probe(M, nullptr, y, &pr);
+    if (LDS) __syncthreads();
   }
   int n_act = 0;
   if (own) {
     int lo = 0, hi = nb;
     while (lo < hi) {
       const int mid = (lo + hi) >> 1;
-      if (RB.edge[mid] < pr.k_act) lo = mid + 1;
+      if (edge[mid] < pr.k_act) lo = mid + 1;
       else hi = mid;
     }
     n_act = lo;
@@ -979,10 +997,10 @@ __global__ __launch_bounds__(256) void k_rb_lane(const ModelDev* __restrict__ Mp
   const int sb = n_act - 1;
   bool straddle = false;
   if (n_act > 0) {
-    const int sb_last = (sb < nb - 1) ? RB.edge[sb + 1] - 1 : RB.edge[nb];
+    const int sb_last = (sb < nb - 1) ? edge[sb + 1] - 1 : edge[nb];
     straddle = sb_last >= pr.k_act;
   }
-  // the loop takes bins 0 .. last_edge - 1 from edges 0 .. last_edge
+  // the walk takes bins 0 .. last_edge - 1 from edges 0 .. last_edge
   const int last_edge = straddle ? sb : sb + 1;
   // this lane's edges: first .. last
   int first = 0, last = last_edge;
@@ -1001,27 +1019,40 @@ __global__ __launch_bounds__(256) void k_rb_lane(const ModelDev* __restrict__ Mp
     gr[dd] = pr.kre[dd] * g.x - pr.kim[dd] * g.y;
     gi[dd] = pr.kre[dd] * g.y + pr.kim[dd] * g.x;
   }
-  if (LDS && H == 1) __syncthreads();
   double part = 0.0;
-  RT pvr[NDET], pvi[NDET];
+  RT pvr[NDET], pvi[NDET], p0r[NDET], p0i[NDET], c0[NDET];
+  const int e0 = min(first, nb);
 #pragma unroll
-  for (int dd = 0; dd < NDET; ++dd) { pvr[dd] = (RT)0; pvi[dd] = (RT)0; }
-  auto load = [&](int t, RBEdge<NDET, MX>& x) {
-    const int e = min(first + t, nb);
-    if constexpr (LDS) rb_lane_load<NDET, MX>(smem, e, x);
-    else rb_lane_load_tables<NDET, MX>(RB, e, x);
-  };
+  for (int dd = 0; dd < NDET; ++dd) {
+    pvr[dd] = (RT)0;
+    pvi[dd] = (RT)0;
+    rb_lane_right<NDET, MX>(recs, ne, e0, dd, &p0r[dd], &p0i[dd], &c0[dd]);
+  }
+  auto load = [&](int t, RBEdge<NDET, MX>& x) { rb_lane_load<NDET, MX>(recs, min(first + t, nb), x); };
   // step t takes edge first + t; two records in flight, the next edge's
   // loads issued before this edge's arithmetic
   const int steps = last - first;                  // this lane's last step (negative: none)
   RBEdge<NDET, MX> xa, xb;
   load(0, xa);
-  for (int t = 0; __builtin_amdgcn_ballot_w64(t <= steps) != 0; t += 2) {
-    load(t + 1, xb);
-    if (t <= steps) rb_lane_edge<NDET, MX>(pr, gr, gi, xa, t >= 1, pvr, pvi, part);
+  load(1, xb);
+  if (0 <= steps) rb_lane_edge<NDET, MX>(pr, gr, gi, xa, true, p0r, p0i, c0, pvr, pvi, part);
+  for (int t = 1; __builtin_amdgcn_ballot_w64(t <= steps) != 0; t += 2) {
+    load(t + 1, xa);
+    if (t <= steps) rb_lane_edge<NDET, MX>(pr, gr, gi, xb, false, p0r, p0i, c0, pvr, pvi, part);
     if (__builtin_amdgcn_ballot_w64(t + 1 <= steps) == 0) break;
-    load(t + 2, xa);
-    if (t + 1 <= steps) rb_lane_edge<NDET, MX>(pr, gr, gi, xb, true, pvr, pvi, part);
+    load(t + 2, xb);
+    if (t + 1 <= steps) rb_lane_edge<NDET, MX>(pr, gr, gi, xa, false, p0r, p0i, c0, pvr, pvi, part);
+  }
+  if (0 <= steps) {
+    // the last edge's right-hand parts belong to a bin this lane does not take
+    RT acc = (RT)0;
+#pragma unroll
+    for (int dd = 0; dd < NDET; ++dd) {
+      RT qr, qi, qc;
+      rb_lane_right<NDET, MX>(recs, ne, last, dd, &qr, &qi, &qc);
+      acc += (qr * pvr[dd] - qi * pvi[dd]) - (RT)0.5 * qc * (pvr[dd] * pvr[dd] + pvi[dd] * pvi[dd]);
+    }
+    part -= (double)acc;
   }
   if (straddle && half == 0) {
     // the straddling bin sb: ratios at its edges sb and sb + 1, sums up to fine bin k_act - 1

@@ -79,6 +79,27 @@ hipError_t launch_init_live(const RunDev& R, hipStream_t st) {
   return hipGetLastError();
 }
 
+size_t rb_edge_record_doubles(int nb, int n_det, bool mixed) {
+  return (size_t)(nb + 1) * (rb_lane_rec_doubles(n_det, mixed) + rb_lane_right_doubles(n_det, mixed));
+}
+
+hipError_t launch_build_rb_edge_records(const ModelDev& M, const RBTables& RB, double* erec, hipStream_t st) {
+  const dim3 grid((unsigned)((RB.nb + 1 + 127) / 128)), block(128);
+  const bool mx = M.mixed != 0;
+  switch (M.n_det) {
+    case 1: if (mx) hipLaunchKernelGGL((k_rb_edge_records<1, true>), grid, block, 0, st, RB, erec);
+            else hipLaunchKernelGGL((k_rb_edge_records<1, false>), grid, block, 0, st, RB, erec);
+            break;
+    case 2: if (mx) hipLaunchKernelGGL((k_rb_edge_records<2, true>), grid, block, 0, st, RB, erec);
+            else hipLaunchKernelGGL((k_rb_edge_records<2, false>), grid, block, 0, st, RB, erec);
+            break;
+    default: if (mx) hipLaunchKernelGGL((k_rb_edge_records<3, true>), grid, block, 0, st, RB, erec);
+             else hipLaunchKernelGGL((k_rb_edge_records<3, false>), grid, block, 0, st, RB, erec);
+             break;
+  }
+  return hipGetLastError();
+}
+
 // lanes per probe in the relative-binning batch (1 or 2)
 constexpr int RB_LANE_HALVES = 2;
 
@@ -89,8 +110,10 @@ hipError_t launch_loglike_rb_t(const ModelDev* Md, const RBTables& RB, int n_bin
   (void)pbuf;
   if (n <= 0) return hipSuccess;
   // the edge records in LDS when they fit in 64 KB (up to about 300 coarse
-  // bins), else read from the tables
-  const size_t lds = (size_t)(RB.nb + 1) * rb_lane_rec_doubles(NDET, MX) * sizeof(double);
+  // bins), else read from the device array
+  const size_t ne = (size_t)RB.nb + 1;
+  const size_t lds = (ne * (rb_lane_rec_doubles(NDET, MX) + rb_lane_right_doubles(NDET, MX)) + (ne + 1) / 2) *
+                     sizeof(double);
   constexpr int H = RB_LANE_HALVES;
   const size_t recs = H == 2 ? (256 / H) * sizeof(ProbeRec) : 0;   // the split set-up's records
   const dim3 grid((unsigned)((n + 256 / H - 1) / (256 / H)));
