@@ -223,10 +223,12 @@ NS_API int ns_loglike(ns_run* run, const double* u_dev, long n, double* out_dev,
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): ns_loglike
- * with the same kernels and results, whose probe-record scratch is a
+ * with the same kernels and results, whose probe-record scratch (used by the
+ * full-grid form; the relative-binning and Gaussian forms need none) is a
  * fixed array of NS_LOGLIKE_NOALLOC_MAX records per device (about 3.3 MB,
  * held from the first ns_init on that device until the process ends) instead
- * of a buffer the run allocates.  It calls no allocator.  u_dev, out_dev,
+ * of a buffer the run allocates.  It calls no allocator.  The size limit
+ * applies to every likelihood form.  u_dev, out_dev,
  * terms_dev as for ns_loglike; the current device must be the run's.
  * Errors: NS_E_ARG if n > NS_LOGLIKE_NOALLOC_MAX or the arguments are bad,
  * NS_E_HIP.  All calls on one device share the one array: calls that

@@ -590,7 +590,7 @@ int ns_dead(ns_run* r, long cap, double* u, double* logl, double* logx, double* 
 int ns_loglike(ns_run* r, const double* u_dev, long n, double* out_dev, int* terms_dev) {
   if (!r) return fail(NS_E_ARG, "run is NULL");
   if (n < 0 || (n > 0 && (!u_dev || !out_dev))) return fail(NS_E_ARG, "bad batch arguments");
-  const bool two_pass = r->M.likelihood == NS_LIKE_FULL || r->M.likelihood == NS_LIKE_RB;
+  const bool two_pass = r->M.likelihood == NS_LIKE_FULL;   // the full grid stores probe records
   if (two_pass && n > r->probe_cap) {
     HIP_OK(hipStreamSynchronize(r->st));   // the old buffer may still be read
     if (r->probe_buf) (void)hipFree(r->probe_buf);
@@ -613,7 +613,7 @@ int ns_loglike_noalloc(ns_run* r, const double* u_dev, long n, double* out_dev, 
   int cur = -1;
   HIP_OK(hipGetDevice(&cur));
   if (cur != r->device) return fail(NS_E_ARG, "the current device (%d) is not the run's (%d)", cur, r->device);
-  const bool two_pass = r->M.likelihood == NS_LIKE_FULL || r->M.likelihood == NS_LIKE_RB;
+  const bool two_pass = r->M.likelihood == NS_LIKE_FULL;   // the full grid stores probe records
   Probe* buf = nullptr;
   if (two_pass) HIP_OK(noalloc_probe_scratch(r->device, &buf));
   HIP_OK(launch_loglike(r->M, r->Md, r->T, r->RB, u_dev, n, out_dev, terms_dev, buf, r->st));

@@ -18,14 +18,16 @@
 //                 evaluates independent probes in pairs, each probe's bins
 //                 spread over half the workgroup and reduced once.
 //  * k_term       one workgroup: live evidence, termination flag, counters.
-//  * k_probe_setup, k_probe_bins, k_rb_bins
-//                 batched fused likelihood in two passes: one probe set-up per
-//                 thread, then one wavefront per probe over the frequency bins
-//                 (k_probe_bins) or the relative-binning bins (k_rb_bins) with
-//                 the coefficients in scalar registers.
-//  * k_loglike    batched likelihood in one pass (initial population,
-//                 Gaussian test likelihood); k_loglike_rb its relative-binning
-//                 form.
+//  * k_probe_setup2 (k_probe_setup), k_probe_bins
+//                 batched fused full-grid likelihood in two passes: the probe
+//                 set-up (two threads per probe), then one wavefront per probe
+//                 over the frequency bins with the coefficients in scalar
+//                 registers.
+//  * k_rb_lane    batched relative-binning likelihood in one pass: two lanes
+//                 per probe walk its edges with the wavefront, the edge
+//                 records (k_rb_edge_records) staged in LDS.
+//  * k_loglike    batched likelihood in one pass (initial population of the
+//                 full-grid and Gaussian forms).
 //  * k_*_packed   the serving forms: one launch covers the chains (and the
 //                 selection, preparation and termination) of every resident run.
 #pragma once
@@ -727,40 +729,6 @@ __device__ inline double rb_wave(const Probe& p, const RBTables& B, int n_bins, 
   return wave_sum(part);
 }
 
-// Batched relative-binning likelihood: one wavefront per workgroup, 64
-// probes set up per pass (one per lane), evaluated one after another.
-template <int NDET, bool MX>
-__global__ __launch_bounds__(64) void k_loglike_rb(const ModelDev* __restrict__ Mp, RBTables RB,
-                                                   const double* __restrict__ u, long n, double* __restrict__ out,
-                                                   int* __restrict__ terms) {
-  const ModelDev& M = *Mp;
-  const int lane = threadIdx.x;
-  const int d = M.n_dim;
-  for (long base = (long)blockIdx.x * 64; base < n; base += (long)gridDim.x * 64) {
-    const long i = base + lane;
-    const long src = i < n ? i : base;
-    double y[MAX_DIM];
-#pragma unroll
-    for (int q = 0; q < MAX_DIM; ++q) y[q] = (q < d) ? u[src * d + q] : 0.0;
-    Probe pr;
-    make_probe(M, nullptr, y, &pr);
-    double mine = 0.0;
-    int mine_edges = 0;
-    const int cnt = (n - base) < 64 ? (int)(n - base) : 64;
-    for (int p = 0; p < cnt; ++p) {
-      const Probe pb = probe_from_lane<NDET>(pr, p);
-      int ne;
-      const double tot = rb_wave<NDET, MX>(pb, RB, M.n_bins, lane, &ne);
-      if (lane == p) {
-        mine = tot;
-        mine_edges = ne;
-      }
-    }
-    if (i < n) out[i] = mine;
-    if (terms && i < n) terms[i] = mine_edges;
-  }
-}
-
 // Batched relative-binning likelihood, one probe per lane.  Every lane sets
 // up its probe and finds its active coarse bins (the bins whose first fine
 // bin lies below its k_act, by bisection of the ascending edge indices); the
@@ -1238,27 +1206,6 @@ __global__ __launch_bounds__(1024) void k_probe_bins(const ModelDev* __restrict_
   }
 }
 
-// Relative-binning pass of the two-pass batch: the tables staged once per
-// 512-thread block, one wavefront per probe (rb_wave), the coefficients read
-// with scalar loads.
-template <int NDET, bool MX>
-__global__ __launch_bounds__(512) void k_rb_bins(RBTables RB, int n_bins, const Probe* __restrict__ P, long n,
-                                                 double* __restrict__ out, int* __restrict__ terms) {
-  extern __shared__ double smem[];
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const RBTables V = stage_rb<NDET, MX>(RB, smem, tid, 512);
-  __syncthreads();
-  for (long p = (long)blockIdx.x * 8 + wv; p < n; p += (long)gridDim.x * 8) {
-    const Probe pb = P[p];
-    int ne;
-    const double tot = rb_wave<NDET, MX>(pb, V, n_bins, lane, &ne);
-    if (lane == 0) {
-      out[p] = tot;
-      if (terms) terms[p] = ne;
-    }
-  }
-}
 
 // ---------------------------------------------------------------- select
 // Rank of element i in the total order (order key, index), one wavefront.

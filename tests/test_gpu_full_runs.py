@@ -98,16 +98,19 @@ def test_served_events_match_oracle(golden):
 
 
 def test_rb_mixed_precision_agrees_with_double(golden):
-    """Relative binning at the large population: sixteen seeds in the mixed
-    form against sixteen in double precision (same n_live), means of log Z
-    within twice the spread of their difference.  (At 55-step chains a
-    run's log Z scatters by about 0.5 from seed to seed, several times its
-    prior-volume error, so the means need this many seeds.)"""
+    """Relative binning at the large population: 48 seeds in the mixed form
+    against the same 48 in double precision (same n_live); the mean of the
+    per-seed differences of log Z is within three standard errors of zero.
+    At 55-step chains a run's log Z scatters by about 0.5 from seed to seed,
+    several times its prior-volume error, and a mixed run drifts away from
+    its double twin after a few flipped decisions (the pairs correlate by
+    about 0.3), so the test needs many seeds and a bound that a fixed set of
+    seeds does not cross by chance when the kernels change."""
     w = synth.workload("tf2_3det_rb_mixed")
     spec = _data(w)
     z = {0: [], 1: []}
     sig = {0: [], 1: []}
-    R = 16
+    R = 48
     for prec in (0, 1):
         for s in range(R):
             run = binding.Run(spec, binding.opts_for(w, seed=9300 + s, precision=prec))
@@ -116,10 +119,10 @@ def test_rb_mixed_precision_agrees_with_double(golden):
             z[prec].append(r["logZ"])
             sig[prec].append(r["sigma"])
             run.close()
-    m64, m32 = np.mean(z[0]), np.mean(z[1])
-    spread = math.sqrt(np.var(z[0], ddof=1) / R + np.var(z[1], ddof=1) / R)
-    print(f"rb mixed {m32:.4f} vs double {m64:.4f}; spread {spread:.4f}; sigma {np.mean(sig[1]):.4f}")
-    assert abs(m32 - m64) <= max(2.0 * spread, 0.05), (m32, m64, spread)
+    diff = np.asarray(z[1]) - np.asarray(z[0])
+    se = float(np.std(diff, ddof=1)) / math.sqrt(R)
+    print(f"rb mixed minus double: {diff.mean():.4f} +- {se:.4f}; sigma {np.mean(sig[1]):.4f}")
+    assert abs(diff.mean()) <= max(3.0 * se, 0.05), (diff.mean(), se)
 
 
 def test_mixed_precision_agrees_with_double(golden):
