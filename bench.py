@@ -467,6 +467,7 @@ def coverage(args) -> dict:
 # stored complete oracle runs (tests/golden/full_runs.json) with the same
 # seeds as a workload, where the key differs from the workload's name
 GOLDEN_RUN = {"tf2_3det_n2000": "tf2_3det_n2000_fp64"}
+PAIRED_SEEDS = 32
 # (workload, its probes' stored oracle values, stored oracle run to compare
 # the complete run with): the configurations the error is reported for
 ACCURACY_CONFIGS = (
@@ -524,6 +525,24 @@ def accuracy() -> dict:
             dz = abs(z["logZ"] - g["logZ"])
             row.update({"logZ": z["logZ"], "sigma_logZ": z["sigma"], "logZ_oracle": g["logZ"], "oracle_run": run_key,
                         "abs_dlogZ": dz, "abs_dlogZ_over_sigma": dz / math.hypot(z["sigma"], g["sigma"])})
+        if w.precision == 1:
+            # one mixed run is one draw of a stochastic estimate whose seed-to-seed
+            # scatter exceeds its prior-volume sigma; the evidence is compared over
+            # paired seeds with the double-precision GPU runs, which reproduce the
+            # oracle's runs of the same seeds
+            diffs = []
+            for sd in range(PAIRED_SEEDS):
+                zz = []
+                for prec in (1, 0):
+                    rr = binding.Run(spec, binding.opts_for(w, seed=7100 + sd, precision=prec))
+                    assert rr.run(1000)
+                    zz.append(rr.logZ(200)["logZ"])
+                    rr.close()
+                diffs.append(zz[0] - zz[1])
+            dd = np.asarray(diffs)
+            row["paired_seeds_vs_double"] = {"seeds": PAIRED_SEEDS, "mean_dlogZ": float(dd.mean()),
+                                             "stderr": float(dd.std(ddof=1) / math.sqrt(len(dd))),
+                                             "seed_to_seed_sd": float(dd.std(ddof=1))}
         out[name] = row
     # relative binning against the full grid, both on the GPU: on 4096
     # equal-weight posterior draws of the complete tf2_3det run, and on 4096
