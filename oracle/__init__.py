@@ -54,6 +54,17 @@ class Opts(C.Structure):
 _lib = None
 
 
+PROBE_HIST = 32
+
+
+class IterRec(C.Structure):
+    """orc_iter: one iteration's metrics."""
+    _fields_ = [("iter", C.c_int), ("probes_min", C.c_int), ("probes_max", C.c_int), ("pad", C.c_int),
+                ("lstar", C.c_double), ("logX", C.c_double), ("logZ", C.c_double), ("log_remaining", C.c_double),
+                ("probes", C.c_longlong), ("steps", C.c_longlong), ("accepted", C.c_longlong),
+                ("stepouts", C.c_longlong), ("shrinks", C.c_longlong), ("hist", C.c_int * PROBE_HIST)]
+
+
 def load(path: str):
     """A CDLL of an oracle build at ``path`` with every signature set."""
     L = C.CDLL(path)
@@ -96,7 +107,8 @@ def load(path: str):
     L.orc_pn_params.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp]
     L.orc_free.argtypes = [C.c_void_p]
     L.orc_slice_update_fixed.argtypes = [C.c_void_p, C.c_void_p, _dp, _dp, _dp, C.c_double, C.c_double,
-                                         C.c_double, _dp, C.c_int, C.POINTER(C.c_long)]
+                                         C.c_double, _dp, C.c_int, C.POINTER(C.c_long), _ip]
+    L.orc_trace.argtypes = [C.c_void_p, C.c_long, C.POINTER(IterRec), C.POINTER(C.c_long)]
     return L
 
 
@@ -341,6 +353,16 @@ class Run:
         lib().orc_samples(self.h, tot, _d(th), _d(l), _d(lw), C.byref(n_out))
         return th, l, lw
 
+    def trace(self):
+        """Per-iteration metrics of the iterations so far: a dict of arrays
+        (one entry per iteration; hist has one row per iteration)."""
+        n = self.state()["iter"]
+        recs = (IterRec * max(n, 1))()
+        n_out = C.c_long()
+        if lib().orc_trace(self.h, max(n, 1), recs, C.byref(n_out)):
+            raise ValueError("orc_trace failed")
+        return trace_dict(recs[: n_out.value])
+
     def resample(self, n_out: int):
         """Equal-weight samples by systematic resampling: (indices into the
         samples() order, physical parameters)."""
@@ -354,6 +376,14 @@ class Run:
         if getattr(self, "h", None):
             lib().orc_free(self.h)
             self.h = None
+
+
+def trace_dict(recs):
+    """Columns of a sequence of per-iteration records."""
+    names = [f[0] for f in IterRec._fields_ if f[0] not in ("pad", "hist")]
+    out = {k: np.array([getattr(r, k) for r in recs]) for k in names}
+    out["hist"] = np.array([list(r.hist) for r in recs], dtype=np.int64).reshape(len(recs), PROBE_HIST)
+    return out
 
 
 def walk_from(prob: OracleProblem, opts: Opts, pop, n_prop: int, x, lx, lstar, t: int = 0, j: int = 0):
@@ -370,12 +400,18 @@ def walk_from(prob: OracleProblem, opts: Opts, pop, n_prop: int, x, lx, lstar, t
     return x, lxc.value, ev.value, acc
 
 
-def slice_update_fixed(prob: OracleProblem, opts: Opts, x, lx, direction, lstar, uw, uj, ushr):
+def slice_update_fixed(prob: OracleProblem, opts: Opts, x, lx, direction, lstar, uw, uj, ushr, moves=False):
+    """One slice update with given direction and uniforms: (x, lambda,
+    likelihood calls), and with moves=True also (bracket expansions, rejected
+    shrink candidates, 1 if the point moved)."""
     x = np.ascontiguousarray(x, dtype=np.float64).copy()
     d = np.ascontiguousarray(direction, dtype=np.float64)
     us = np.ascontiguousarray(ushr, dtype=np.float64)
     lxc = C.c_double(lx)
     ev = C.c_long()
+    mv = np.zeros(3, dtype=np.int32)
     lib().orc_slice_update_fixed(prob.ref, C.byref(opts), _d(x), C.byref(lxc), _d(d), lstar, uw, uj, _d(us),
-                                 len(us), C.byref(ev))
+                                 len(us), C.byref(ev), _i(mv))
+    if moves:
+        return x, lxc.value, ev.value, tuple(int(v) for v in mv)
     return x, lxc.value, ev.value

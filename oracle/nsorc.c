@@ -29,12 +29,16 @@
  * patterns; the Whittle sums against quadrature; relative binning exact at
  * the fiducial and under extrinsic shifts; the evidence, the information H,
  * the Kish ESS and the systematic resampling against closed forms and
- * distribution tests.  Nothing of the oracle is left "parity unpinned";
+ * distribution tests; the per-iteration metrics (slice moves counted on
+ * hand-worked brackets, log X in closed form, a constant likelihood that
+ * rejects every probe, the random walk's chain-length rule, sums of the
+ * evaluation histogram).  Nothing of the oracle is left "parity unpinned";
  * relative binning away from the fiducial is an approximation, measured
  * against the full grid rather than pinned.
  */
 #include "nsorc.h"
 
+#include <limits.h>
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -611,6 +615,8 @@ struct orc_run {
     long cap, n_dead;
     double* du; double* dlam; double* dlogx; double* dlogw;
     int* diter; int* dslot; int* dnlive;
+    orc_iter* trace; /* [max_iter] per-iteration metrics */
+    long trace_cap;
 };
 
 static double logaddexp(double a, double b) {
@@ -656,11 +662,15 @@ static void along(const orc_problem* p, int d, const double* x, double t, const 
  * chain state (x, lx) along direction dir with initial width w.  The step-out
  * budget M is split between the two sides by the uniform uj (J = floor(M uj)
  * steps left, M-1-J right), which keeps the capped procedure exact.  Shrink
- * candidate a uses uniform ushr(a). */
+ * candidate a uses uniform ushr(a).  mv counts the update's moves: each
+ * widening of the bracket by w, each rejected shrink candidate (the bracket
+ * end it replaces), and whether the point moved (it stays where every shrink
+ * candidate of the budget is rejected). */
 typedef double (*ushr_fn)(void* ctx, int a);
+typedef struct { int expansions, shrinks, moved; } slice_moves;
 
 static void slice_update(const orc_run* r, double* x, double* lx, const double* dir, double lstar, double w,
-                         double uw, double uj, ushr_fn ushr, void* uctx, long* evals) {
+                         double uw, double uj, ushr_fn ushr, void* uctx, long* evals, slice_moves* mv) {
     int d = r->d;
     double y[32], ly = 0.0;
     double lo = -w * uw, hi = lo + w;
@@ -670,12 +680,14 @@ static void slice_update(const orc_run* r, double* x, double* lx, const double* 
         along(&r->p, d, x, lo, dir, y);
         if (!in_slice(r, y, lstar, &ly, evals)) break;
         lo -= w;
+        ++mv->expansions;
         --J;
     }
     while (K > 0) {
         along(&r->p, d, x, hi, dir, y);
         if (!in_slice(r, y, lstar, &ly, evals)) break;
         hi += w;
+        ++mv->expansions;
         --K;
     }
     for (int a = 0; a < r->o.max_shrink; ++a) {
@@ -684,9 +696,11 @@ static void slice_update(const orc_run* r, double* x, double* lx, const double* 
         if (in_slice(r, y, lstar, &ly, evals)) {
             memcpy(x, y, sizeof(double) * d);
             *lx = ly;
+            mv->moved = 1;
             return;
         }
         if (t < 0.0) lo = t; else hi = t;
+        ++mv->shrinks;
     }
 }
 
@@ -830,6 +844,8 @@ int orc_init(orc_run** out, const orc_problem* p, const orc_opts* o) {
     r->diter = (int*)malloc(sizeof(int) * r->cap);
     r->dslot = (int*)malloc(sizeof(int) * r->cap);
     r->dnlive = (int*)malloc(sizeof(int) * r->cap);
+    r->trace_cap = max_iter;
+    r->trace = (orc_iter*)calloc(max_iter, sizeof(orc_iter));
     *out = r;
     return 0;
 }
@@ -901,6 +917,10 @@ static void iterate(orc_run* r) {
 
     double* newu = (double*)malloc(sizeof(double) * k * d);
     double* newl = (double*)malloc(sizeof(double) * k);
+    /* per-chain metrics: evaluations, moves, evaluations-per-step histogram */
+    long* c_ev = (long*)calloc(k, sizeof(long));
+    slice_moves* c_mv = (slice_moves*)calloc(k, sizeof(slice_moves));
+    int* c_hist = (int*)calloc((size_t)k * ORC_PROBE_HIST, sizeof(int));
     int nt = r->o.n_threads < 1 ? 1 : r->o.n_threads;
     long evals = 0, acc_walk = 0;
 #pragma omp parallel for schedule(dynamic, 1) num_threads(nt) reduction(+ : evals, acc_walk)
@@ -911,8 +931,12 @@ static void iterate(orc_run* r) {
         double x[32], lx = r->lam[start];
         memcpy(x, r->u + start * d, sizeof(double) * d);
         long e = 0;
-        if (r->o.kernel == ORC_KERNEL_WALK)
-            walk_update(r, surv, n - k, t, (uint64_t)j, r->walk_len, x, &lx, lstar, &e, &acc_walk);
+        if (r->o.kernel == ORC_KERNEL_WALK) {
+            long a = 0;
+            walk_update(r, surv, n - k, t, (uint64_t)j, r->walk_len, x, &lx, lstar, &e, &a);
+            acc_walk += a;
+            c_mv[j].moved = (int)a;
+        }
         for (int s = 0; s < r->o.n_steps && r->o.kernel == ORC_KERNEL_SLICE; ++s) {
             double z[32], dir[32], nrm = 0.0;
             normals(&r->key, t, (uint64_t)j, (uint64_t)s, d, z);
@@ -926,14 +950,44 @@ static void iterate(orc_run* r) {
             uint64_t ww[4];
             draw(&r->key, t, (uint64_t)j, (uint64_t)s, P_WIDTH, 0, ww);
             shrink_ctx sc = {&r->key, t, (uint64_t)j, (uint64_t)s};
+            slice_moves mv = {0, 0, 0};
+            long e0 = e;
             slice_update(r, x, &lx, dir, lstar, r->o.slice_width, to_unif(ww[0]), to_unif(ww[1]), shrink_uniform,
-                         &sc, &e);
+                         &sc, &e, &mv);
+            c_mv[j].expansions += mv.expansions;
+            c_mv[j].shrinks += mv.shrinks;
+            c_mv[j].moved += mv.moved;
+            long pe = e - e0;
+            c_hist[(size_t)j * ORC_PROBE_HIST + (pe < ORC_PROBE_HIST - 1 ? pe : ORC_PROBE_HIST - 1)] += 1;
         }
         memcpy(newu + j * d, x, sizeof(double) * d);
         newl[j] = lx;
+        c_ev[j] = e;
         evals += e;
     }
     r->n_evals += evals;
+
+    /* The iteration's metrics record (its threshold and evidence state after
+     * the deaths; chain totals; the remaining-evidence term below). */
+    orc_iter spare;
+    orc_iter* rec = r->iter < r->trace_cap ? &r->trace[r->iter] : &spare;
+    memset(rec, 0, sizeof(*rec));
+    rec->iter = r->iter;
+    rec->lstar = lstar;
+    rec->logX = r->logX;
+    rec->logZ = r->logZ;
+    rec->steps = (long long)k * (r->o.kernel == ORC_KERNEL_WALK ? r->walk_len : r->o.n_steps);
+    rec->probes_min = INT_MAX;
+    for (int j = 0; j < k; ++j) {
+        rec->probes += c_ev[j];
+        if (c_ev[j] < rec->probes_min) rec->probes_min = (int)c_ev[j];
+        if (c_ev[j] > rec->probes_max) rec->probes_max = (int)c_ev[j];
+        rec->accepted += c_mv[j].moved;
+        rec->stepouts += c_mv[j].expansions;
+        rec->shrinks += c_mv[j].shrinks;
+        for (int b = 0; b < ORC_PROBE_HIST; ++b) rec->hist[b] += c_hist[(size_t)j * ORC_PROBE_HIST + b];
+    }
+    free(c_ev); free(c_mv); free(c_hist);
     if (r->o.kernel == ORC_KERNEL_WALK) r->walk_len = next_walk_len(&r->o, acc_walk, (long)k * r->walk_len);
     /* Refill: chain j's final state replaces the j-th lowest dead slot. */
     for (int j = 0; j < k; ++j) {
@@ -945,13 +999,14 @@ static void iterate(orc_run* r) {
 
     /* Termination: the evidence still held by the live points,
      * logX + log mean exp(lambda_live), relative to the accumulated log Z. */
-    if (r->o.term_frac > 0.0) {
+    {
         double m = -INFINITY;
         for (int i = 0; i < n; ++i) if (order_value(r->lam[i]) > m) m = order_value(r->lam[i]);
         double s = 0.0;
         for (int i = 0; i < n; ++i) s += exp(order_value(r->lam[i]) - m);
         double logz_live = r->logX + m + log(s / n);
-        if (logz_live - r->logZ < log(r->o.term_frac)) r->done = 1;
+        rec->log_remaining = logz_live - r->logZ;
+        if (r->o.term_frac > 0.0 && logz_live - r->logZ < log(r->o.term_frac)) r->done = 1;
     }
     if (r->n_dead + r->k > r->cap) r->done = 1;
 }
@@ -969,6 +1024,14 @@ int orc_state(const orc_run* r, double* logX, double* logZ, double* H, int* iter
     if (iter) *iter = r->iter;
     if (n_dead) *n_dead = r->n_dead;
     if (n_evals) *n_evals = r->n_evals;
+    return 0;
+}
+
+int orc_trace(const orc_run* r, long cap, orc_iter* out, long* n_out) {
+    long n = r->iter < r->trace_cap ? r->iter : r->trace_cap;
+    *n_out = n;
+    if (cap < n) return -3;
+    if (out && n) memcpy(out, r->trace, sizeof(orc_iter) * n);
     return 0;
 }
 
@@ -1139,6 +1202,7 @@ void orc_free(orc_run* r) {
     orc_rb_free(r->rb);
     free(r->u); free(r->lam);
     free(r->du); free(r->dlam); free(r->dlogx); free(r->dlogw); free(r->diter); free(r->dslot); free(r->dnlive);
+    free(r->trace);
     free(r);
 }
 
@@ -1173,7 +1237,8 @@ static double fixed_uniform(void* vctx, int a) {
 }
 
 int orc_slice_update_fixed(const orc_problem* p, const orc_opts* o, double* x, double* lx, const double* dir,
-                           double lstar, double uw, double uj, const double* ushr, int n_ushr, long* evals) {
+                           double lstar, double uw, double uj, const double* ushr, int n_ushr, long* evals,
+                           int* moves) {
     orc_run r;
     memset(&r, 0, sizeof(r));
     r.p = *p;
@@ -1182,6 +1247,12 @@ int orc_slice_update_fixed(const orc_problem* p, const orc_opts* o, double* x, d
     if (p->likelihood == ORC_LIKE_RB) return -1;
     fixed_u c = {ushr, n_ushr};
     *evals = 0;
-    slice_update(&r, x, lx, dir, lstar, o->slice_width, uw, uj, fixed_uniform, &c, evals);
+    slice_moves mv = {0, 0, 0};
+    slice_update(&r, x, lx, dir, lstar, o->slice_width, uw, uj, fixed_uniform, &c, evals, &mv);
+    if (moves) {
+        moves[0] = mv.expansions;
+        moves[1] = mv.shrinks;
+        moves[2] = mv.moved;
+    }
     return 0;
 }

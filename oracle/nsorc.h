@@ -116,6 +116,26 @@ int orc_loglike_batch(const orc_problem* p, const double* u, long n, double* out
 /* k lowest of n values in the sampler's total order. */
 int orc_select(int n, const double* logl, int k, int* dead_idx, double* lstar);
 
+/* Metrics of one iteration (Section 2's replace-the-k-lowest step), for
+ * checking the sampler's per-iteration record.  Counts are of the
+ * sequential walk: a probe outside the unit cube is no evaluation but its
+ * rejection still shrinks the bracket. */
+#define ORC_PROBE_HIST 32
+typedef struct {
+    int iter;                 /* iteration index, from 0 */
+    int probes_min, probes_max;   /* fewest and most evaluations of one chain */
+    int pad;
+    double lstar;             /* the threshold L*: the k-th lowest lambda */
+    double logX, logZ;        /* after the iteration's k deaths */
+    double log_remaining;     /* logX + log mean exp(lambda) of the refilled live set, minus logZ */
+    long long probes;         /* likelihood evaluations of all chains */
+    long long steps;          /* slice steps (k * n_steps); random walk: proposals (k * chain length) */
+    long long accepted;       /* slice steps that moved the chain; random walk: accepted proposals */
+    long long stepouts;       /* bracket expansions */
+    long long shrinks;        /* rejected shrink candidates */
+    int hist[ORC_PROBE_HIST]; /* slice steps by evaluations made (last bin: that many or more) */
+} orc_iter;
+
 /* Nested sampling run. */
 int orc_init(orc_run** out, const orc_problem* p, const orc_opts* o);
 int orc_step(orc_run* r, int max_iters, int* done);
@@ -126,6 +146,9 @@ int orc_dead(const orc_run* r, long cap, double* u, double* logl, double* logx, 
 int orc_logZ(const orc_run* r, int n_sim, double* logZ, double* sigma_sim, double* sigma_h, double* ess);
 /* Information H (unclipped) and Kish ESS of the final weighted samples. */
 int orc_information(const orc_run* r, double* H, double* ess);
+/* Per-iteration metrics of the iterations run so far, in order; n_out
+ * receives their count; -3 (nothing written) if cap is smaller. */
+int orc_trace(const orc_run* r, long cap, orc_iter* out, long* n_out);
 int orc_samples(const orc_run* r, long cap, double* theta, double* logl, double* logw, long* n_out);
 /* Equal-weight samples by systematic resampling of the weighted samples. */
 int orc_resample(const orc_run* r, long n_out, int* idx, double* theta);
@@ -138,9 +161,12 @@ void orc_free(orc_run* r);
 int orc_walk_from(const orc_problem* p, const orc_opts* o, const double* pop, int npop, int n_prop, double* x,
                   double* lx, double lstar, uint64_t t, uint64_t j, long* evals);
 
-/* One slice update with a caller-supplied direction and uniforms (test hook). */
+/* One slice update with a caller-supplied direction and uniforms (test
+ * hook); moves (may be NULL) receives the bracket expansions, the rejected
+ * shrink candidates and 1 if the point moved. */
 int orc_slice_update_fixed(const orc_problem* p, const orc_opts* o, double* x, double* lx, const double* dir,
-                           double lstar, double uw, double uj, const double* ushr, int n_ushr, long* evals);
+                           double lstar, double uw, double uj, const double* ushr, int n_ushr, long* evals,
+                           int* moves);
 
 #ifdef __cplusplus
 }

@@ -65,6 +65,13 @@ MUTATIONS = [
     ("walk pair not distinct", "if (ib >= ia) ++ib;", "if (ib > ia) ++ib;", "walk_step"),
     ("walk stops at a count of acceptances", "for (int s = 0; s < n_prop; ++s) {",
      "for (int s = 0; s < n_prop && *n_acc < 4; ++s) {", "walk_invariance"),
+    ("right expansions not counted", "hi += w;\n        ++mv->expansions;", "hi += w;", "moves"),
+    ("accepted candidate counted as a shrink", "mv->moved = 1;\n",
+     "mv->moved = 1;\n            ++mv->shrinks;\n", "moves"),
+    ("histogram bin off by one", "+ (pe < ORC_PROBE_HIST - 1 ? pe : ORC_PROBE_HIST - 1)] += 1;",
+     "+ (pe + 1 < ORC_PROBE_HIST - 1 ? pe + 1 : ORC_PROBE_HIST - 1)] += 1;", "trace"),
+    ("remaining evidence offset", "rec->log_remaining = logz_live - r->logZ;",
+     "rec->log_remaining = logz_live - r->logZ + 1e-9;", "trace"),
 ]
 
 
@@ -135,8 +142,58 @@ def _wrap_bad(L):
     lx, ev = C.c_double(0.0), C.c_long()
     L.orc_slice_update_fixed(p.ref, C.byref(o), x.ctypes.data_as(oracle._dp), C.byref(lx),
                              d.ctypes.data_as(oracle._dp), -1e300, 0.5, 0.5, us.ctypes.data_as(oracle._dp), 1,
-                             C.byref(ev))
+                             C.byref(ev), None)
     return not (0.0 <= x[0] <= 1.0 and ev.value == 100 and abs(x[0] - 0.875) < 1e-9)
+
+
+def _moves_bad(L):
+    """The hand-counted slice moves of test_slice_hand_computed, driven
+    through the build L."""
+    w = synth.gauss_workload(1, 0.1, mu=[0.5])
+    w.slice_width = 0.15
+    p = oracle.OracleProblem(w)
+    o = oracle.opts_for(w)
+    c = 0.5 * math.log(2 * math.pi * 0.01)
+    lstar = -0.04 / 0.02 - c
+    cases = [([0.5], lstar, 0.5, [0.0, 0.9, 0.25], (2, 1, 1)), ([0.5], lstar, 0.0, [0.0], (1, 0, 1)),
+             ([0.05], -1e300, 0.5, [0.01, 0.0, 0.5], (6, 2, 1))]
+    for x0, ls, uj, us, want in cases:
+        x = np.array(x0, dtype=np.float64)
+        d = np.array([1.0])
+        u = np.array(us, dtype=np.float64)
+        lx, ev = C.c_double(-c), C.c_long()
+        mv = np.zeros(3, dtype=np.int32)
+        L.orc_slice_update_fixed(p.ref, C.byref(o), x.ctypes.data_as(oracle._dp), C.byref(lx),
+                                 d.ctypes.data_as(oracle._dp), ls, 0.5, uj, u.ctypes.data_as(oracle._dp), len(u),
+                                 C.byref(ev), mv.ctypes.data_as(oracle._ip))
+        if tuple(int(v) for v in mv) != want:
+            return True
+    return False
+
+
+def _trace_bad(L):
+    """The per-iteration record's histogram sums and remaining-evidence
+    term (test_iteration_metrics_closed_forms_and_invariants), driven through
+    the build L."""
+    n, k = 100, 50
+    w = synth.gauss_workload(2, 0.05, n_live=n, n_delete=k)
+    p = oracle.OracleProblem(w)
+    o = oracle.opts_for(w, term_frac=0.0, max_iter=3)
+    h = C.c_void_p()
+    assert L.orc_init(C.byref(h), p.ref, C.byref(o)) == 0
+    done = C.c_int()
+    L.orc_step(h, 3, C.byref(done))
+    recs = (oracle.IterRec * 3)()
+    n_out = C.c_long()
+    L.orc_trace(h, 3, recs, C.byref(n_out))
+    u, lam = np.zeros((n, 2)), np.zeros(n)
+    L.orc_live(h, u.ctypes.data_as(oracle._dp), lam.ctypes.data_as(oracle._dp))
+    L.orc_free(h)
+    tr = oracle.trace_dict(recs[: n_out.value])
+    mx = lam.max()
+    rem = tr["logX"][-1] + mx + math.log(np.mean(np.exp(lam - mx))) - tr["logZ"][-1]
+    return (n_out.value != 3 or not np.array_equal(tr["hist"] @ np.arange(oracle.PROBE_HIST), tr["probes"])
+            or abs(tr["log_remaining"][-1] - rem) >= 1e-12 * max(1.0, abs(rem)))
 
 
 def _posterior_bad(L):
@@ -191,6 +248,8 @@ CHECKS = {
     "walk_step": _walk_step_bad,
     "so_phase": lambda L: pins._so_worst(L) >= 1.0,
     "walk_invariance": _walk_invariance_bad,
+    "moves": _moves_bad,
+    "trace": _trace_bad,
 }
 
 

@@ -783,6 +783,67 @@ def test_logx_closed_form_and_volume_partition():
     assert np.all(dd["iter"][::50] == np.arange(12))
 
 
+def test_iteration_metrics_closed_forms_and_invariants():
+    """Per-iteration metrics (the replace-the-k-lowest iteration of Section
+    2): log X in closed form, the threshold against the dead record, log Z
+    against the state, the remaining-evidence term against the refilled live
+    set, and the step counts' sums and bounds."""
+    n, k, iters = 100, 50, 12
+    w = synth.gauss_workload(2, 0.05, n_live=n, n_delete=k)
+    p = oracle.OracleProblem(w)
+    r = oracle.Run(p, oracle.opts_for(w, term_frac=0.0, max_iter=iters))
+    states, rem = [], []
+    for _ in range(iters):
+        r.step(1)
+        st = r.state()
+        _, lam = r.live()
+        mx = lam.max()
+        states.append(st)
+        rem.append(st["logX"] + mx + math.log(np.mean(np.exp(lam - mx))) - st["logZ"])
+    tr = r.trace()
+    dd = r.dead()
+    Hn = sum(1.0 / i for i in range(1, n + 1))
+    Hnk = sum(1.0 / i for i in range(1, n - k + 1))
+    assert np.array_equal(tr["iter"], np.arange(iters))
+    for t in range(iters):
+        assert abs(tr["logX"][t] + (t + 1) * (Hn - Hnk)) < 1e-12
+        assert tr["logZ"][t] == states[t]["logZ"]
+        assert tr["lstar"][t] == dd["logl"][dd["iter"] == t].max()
+        assert abs(tr["log_remaining"][t] - rem[t]) < 1e-12 * max(1.0, abs(rem[t]))
+    assert np.all(tr["steps"] == k * w.n_steps)
+    assert np.array_equal(tr["hist"].sum(axis=1), tr["steps"])
+    assert np.all(tr["hist"][:, -1] == 0)        # no step here takes 31 evaluations
+    assert np.array_equal(tr["hist"] @ np.arange(oracle.PROBE_HIST), tr["probes"])
+    assert tr["probes"].sum() == states[-1]["n_evals"] - n
+    # every expansion and every move is an evaluation; beyond them a step
+    # makes at most one failed step-out probe per side and its rejected
+    # shrink candidates
+    assert np.all(tr["probes"] >= tr["stepouts"] + tr["accepted"])
+    assert np.all(tr["probes"] <= tr["stepouts"] + tr["shrinks"] + tr["accepted"] + 2 * tr["steps"])
+    assert np.all(tr["accepted"] <= tr["steps"]) and np.all(tr["accepted"] > 0)
+    assert np.all(tr["probes_min"] * k <= tr["probes"]) and np.all(tr["probes"] <= tr["probes_max"] * k)
+
+
+def test_iteration_metrics_constant_likelihood():
+    """A constant likelihood: no probe beats L* (the inequality is strict), so
+    a step expands nothing, rejects all max_shrink shrink candidates and keeps
+    its point, and makes at most two step-out calls and max_shrink shrink
+    calls."""
+    w = synth.gauss_workload(3, 1e8, n_live=100, n_delete=50)
+    w.max_shrink = 6
+    p = oracle.OracleProblem(w)
+    r = oracle.Run(p, oracle.opts_for(w, max_iter=5, term_frac=0.0))
+    r.step(5)
+    tr = r.trace()
+    steps = 50 * w.n_steps
+    assert len(tr["iter"]) == 5
+    assert np.all(tr["steps"] == steps)
+    assert np.all(tr["stepouts"] == 0) and np.all(tr["accepted"] == 0)
+    assert np.all(tr["shrinks"] == steps * w.max_shrink)
+    assert np.all(tr["hist"][:, 2 + w.max_shrink + 1:] == 0)
+    assert np.array_equal(tr["hist"].sum(axis=1), tr["steps"])
+
+
 def test_resample_systematic_counts():
     """Systematic resampling: outputs are in sample order, every weighted
     sample is drawn about N p_i / W times (N outputs, W the sum of the
@@ -836,23 +897,32 @@ def test_slice_hand_computed():
     lstar = -0.04 / 0.02 - c
     # step out: left 0.425 in, 0.275 out; right 0.575 in, 0.725 out -> [-0.225, 0.225]
     # shrink: t=-0.225 (0.275 out, lo stays), t=-0.225+0.9*0.45=0.18 (0.68 in)
-    x, lx, ev = oracle.slice_update_fixed(p, opts, [0.5], -c, [1.0], lstar, 0.5, 0.5, [0.0, 0.9, 0.25])
-    assert abs(x[0] - 0.68) < 1e-15 and ev == 6
+    # moves: one expansion per side, one rejected shrink candidate, moved
+    x, lx, ev, mv = oracle.slice_update_fixed(p, opts, [0.5], -c, [1.0], lstar, 0.5, 0.5, [0.0, 0.9, 0.25],
+                                              moves=True)
+    assert abs(x[0] - 0.68) < 1e-15 and ev == 6 and mv == (2, 1, 1)
     assert abs(lx - (-(0.18**2) / 0.02 - c)) < 1e-12
     # shrink: t=0.2025 (0.7025 out -> hi), t=-0.225+0.1*0.4275=-0.18225 (0.31775 in)
-    x, lx, ev = oracle.slice_update_fixed(p, opts, [0.5], -c, [1.0], lstar, 0.5, 0.5, [0.95, 0.1])
-    assert abs(x[0] - 0.31775) < 1e-15 and ev == 6
+    x, lx, ev, mv = oracle.slice_update_fixed(p, opts, [0.5], -c, [1.0], lstar, 0.5, 0.5, [0.95, 0.1], moves=True)
+    assert abs(x[0] - 0.31775) < 1e-15 and ev == 6 and mv == (2, 1, 1)
     # uj = 0: no left step-out budget; bracket [-0.075, 0.225]; t=-0.075+0.0*0.3 -> 0.425 in
-    x, lx, ev = oracle.slice_update_fixed(p, opts, [0.5], -c, [1.0], lstar, 0.5, 0.0, [0.0])
-    assert abs(x[0] - 0.425) < 1e-15 and ev == 3
+    x, lx, ev, mv = oracle.slice_update_fixed(p, opts, [0.5], -c, [1.0], lstar, 0.5, 0.0, [0.0], moves=True)
+    assert abs(x[0] - 0.425) < 1e-15 and ev == 3 and mv == (1, 0, 1)
     # probes outside the unit cube cost no likelihood call: x = 0.05, left probe at -0.025
-    x, lx, ev = oracle.slice_update_fixed(p, opts, [0.05], -c, [1.0], -1e300, 0.5, 0.5, [0.5])
+    x, lx, ev, mv = oracle.slice_update_fixed(p, opts, [0.05], -c, [1.0], -1e300, 0.5, 0.5, [0.5], moves=True)
     # right step-out walks 0.125, 0.275, ..., 0.875 in, 1.025 out (no call); shrink one call
-    assert ev == 6 + 1
+    assert ev == 6 + 1 and mv == (6, 0, 1)
+    # a shrink candidate outside the cube is rejected without a call but
+    # still counts as a shrink: bracket [-0.075, 0.975]; u = 0.01 gives
+    # t = -0.0645 (point -0.0145, out; lo = -0.0645); u = 0 gives t = lo
+    # (out again); u = 0.5 gives t = -0.0645 + 0.5 * 1.0395 = 0.45525, point 0.50525 in
+    x, lx, ev, mv = oracle.slice_update_fixed(p, opts, [0.05], -c, [1.0], -1e300, 0.5, 0.5, [0.01, 0.0, 0.5],
+                                              moves=True)
+    assert ev == 6 + 1 and mv == (6, 2, 1) and abs(x[0] - 0.50525) < 1e-12
     # exhausted shrink keeps the state
     opts.max_shrink = 2
-    x, lx, ev = oracle.slice_update_fixed(p, opts, [0.5], -c, [1.0], 1e300, 0.5, 0.5, [0.1, 0.2])
-    assert x[0] == 0.5 and lx == -c and ev == 2 + 2
+    x, lx, ev, mv = oracle.slice_update_fixed(p, opts, [0.5], -c, [1.0], 1e300, 0.5, 0.5, [0.1, 0.2], moves=True)
+    assert x[0] == 0.5 and lx == -c and ev == 2 + 2 and mv == (0, 2, 0)
 
 
 def _chains_from_point(p, opts, x0, lam0, lstar, n_chains, n_steps, d, seed):
@@ -1090,3 +1160,27 @@ def test_walk_kernel_gauss_evidence_zscores():
     z = np.array(z)
     assert abs(z.mean()) < 0.8, z
     assert 0.4 < z.std() < 1.8, z
+
+
+def test_walk_iteration_metrics_follow_the_chain_length_rule():
+    """Random-walk kernel: iteration t makes k * len_t proposals, where len_0
+    = min(walk_accept, walk_max) and len_{t+1} = ceil(walk_accept * k len_t /
+    accepted_t) within [1, walk_max] (walk_max if nothing was accepted); the
+    slice counts stay zero."""
+    d, s = 3, 0.08
+    w = synth.gauss_workload(d, s, mu=[0.15, 0.5, 0.6], n_live=200, n_delete=100)
+    w.kernel, w.walk_accept, w.walk_max = 1, 25, 500
+    p = oracle.OracleProblem(w)
+    r = oracle.Run(p, oracle.opts_for(w, seed=301, n_threads=4, max_iter=15, term_frac=0.0))
+    r.step(15)
+    tr = r.trace()
+    k = 100
+    length = min(w.walk_accept, w.walk_max)
+    for t in range(15):
+        assert tr["steps"][t] == k * length
+        acc = int(tr["accepted"][t])
+        assert 0 <= acc <= tr["steps"][t] and acc <= tr["probes"][t] <= tr["steps"][t]
+        want = w.walk_max if acc == 0 else -(-w.walk_accept * int(tr["steps"][t]) // acc)
+        length = max(1, min(w.walk_max, want))
+    assert np.all(tr["stepouts"] == 0) and np.all(tr["shrinks"] == 0) and not tr["hist"].any()
+    assert len(set(tr["steps"].tolist())) > 1       # the rule changed the length
