@@ -150,6 +150,13 @@ typedef struct {
     int kernel;          /* NS_KERNEL_SLICE (the paper's), or NS_KERNEL_WALK */
     int walk_accept;     /* NS_KERNEL_WALK: target accepted proposals per chain (>= 1) */
     int walk_max;        /* NS_KERNEL_WALK: cap on proposals per chain (>= 1) */
+    int count_moves;     /* NS_KERNEL_SLICE, 0 or 1: the chains count their moves for the
+                            per-iteration metrics (ns_trace: bracket expansions, rejected
+                            shrink candidates, moved steps, evaluations per step).  The
+                            counting chain kernels run 64 threads per chain; without it the
+                            other chain kernels carry no counting code and those fields read
+                            -1 (the histogram 0).  Results are the same either way.  Served
+                            runs (ns_server) do not count. */
 } ns_opts;
 
 typedef struct ns_run ns_run;
@@ -271,6 +278,45 @@ typedef struct {
 
 /* Statistics of the profiled iterations (synchronises the stream). */
 NS_API int ns_stats(ns_run* run, ns_stats_t* out);
+
+/* Metrics of one "replace the k lowest" iteration (Section 2), written by
+ * the device at the end of the iteration.  Counts are those of the
+ * sequential slice walk the chains carry out (the batched evaluation of
+ * candidates does not change them): a probe outside the unit cube is no
+ * evaluation, but its rejection still shrinks the bracket. */
+#define NS_PROBE_HIST 32
+typedef struct {
+    int iter;                /* iteration index, from 0 */
+    int probes_min;          /* fewest likelihood evaluations of one chain */
+    int probes_max;          /* most evaluations of one chain */
+    int pad;
+    double lstar;            /* the threshold L*: the k-th lowest lambda of the iteration */
+    double logX;             /* log prior volume after the iteration's k deaths */
+    double logZ;             /* accumulated log evidence after them */
+    double log_remaining;    /* log X + log mean exp(lambda) of the refilled live
+                              * points, minus log Z: the log of the evidence still
+                              * held by the live points relative to log Z, the
+                              * quantity the termination test compares with
+                              * ln(term_frac) */
+    long long probes;        /* likelihood evaluations of all chains */
+    long long steps;         /* slice steps (k * n_steps); random walk: proposals (k * chain length) */
+    long long accepted;      /* slice steps that moved the chain (all but those whose
+                              * shrink budget ran out); random walk: accepted proposals */
+    long long stepouts;      /* slice: bracket expansions by w */
+    long long shrinks;       /* slice: rejected shrink candidates */
+    int hist[NS_PROBE_HIST]; /* slice: steps by the evaluations they made, hist[p]
+                              * for p evaluations, the last bin for
+                              * NS_PROBE_HIST - 1 or more; random walk: zeros.
+                              * accepted (slice), stepouts, shrinks and hist need
+                              * opts.count_moves; without it they read -1 and 0 */
+} ns_iter_t;
+
+/* Per-iteration metrics of the iterations run so far, in order, into out[cap]
+ * (host).  n_out receives their count (at most opts.max_iter); NS_E_CAPACITY
+ * (nothing written) if cap is smaller; out may be NULL to ask for the count.
+ * Synchronises the run's stream.  Restored runs (ns_load) carry the records
+ * of the iterations before the checkpoint. */
+NS_API int ns_trace(ns_run* run, long cap, ns_iter_t* out, long* n_out);
 
 /* Log-likelihood of the data under the noise-only model (Whittle: in every
  * bin the real and imaginary parts are Gaussian with variance S/(4 df)),

@@ -49,7 +49,7 @@ class Opts(C.Structure):
         ("n_live", C.c_int), ("n_delete", C.c_int), ("n_steps", C.c_int), ("slice_width", C.c_double),
         ("max_stepout", C.c_int), ("max_shrink", C.c_int), ("term_frac", C.c_double),
         ("seed", C.c_uint64), ("run_id", C.c_uint64), ("max_iter", C.c_int), ("precision", C.c_int),
-        ("kernel", C.c_int), ("walk_accept", C.c_int), ("walk_max", C.c_int),
+        ("kernel", C.c_int), ("walk_accept", C.c_int), ("walk_max", C.c_int), ("count_moves", C.c_int),
     ]
 
 
@@ -58,6 +58,19 @@ class Stats(C.Structure):
         ("iterations", C.c_long), ("ms_select", C.c_double), ("ms_prep", C.c_double),
         ("ms_slice", C.c_double), ("ms_term", C.c_double), ("evals", C.c_longlong),
         ("bin_terms", C.c_longlong), ("slice_threads", C.c_int), ("lds_tables", C.c_int),
+    ]
+
+
+PROBE_HIST = 32
+
+
+class IterRec(C.Structure):
+    """ns_iter_t: one iteration's metrics."""
+    _fields_ = [
+        ("iter", C.c_int), ("probes_min", C.c_int), ("probes_max", C.c_int), ("pad", C.c_int),
+        ("lstar", C.c_double), ("logX", C.c_double), ("logZ", C.c_double), ("log_remaining", C.c_double),
+        ("probes", C.c_longlong), ("steps", C.c_longlong), ("accepted", C.c_longlong),
+        ("stepouts", C.c_longlong), ("shrinks", C.c_longlong), ("hist", C.c_int * PROBE_HIST),
     ]
 
 
@@ -87,6 +100,7 @@ SIGNATURES = {
     "ns_select": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
     "ns_profile": (C.c_int, [C.c_void_p, C.c_int]),
     "ns_stats": (C.c_int, [C.c_void_p, C.POINTER(Stats)]),
+    "ns_trace": (C.c_int, [C.c_void_p, C.c_long, C.POINTER(IterRec), _lp]),
     "ns_noise_loglike": (C.c_int, [C.c_void_p, _dp]),
     "ns_save": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.POINTER(C.c_size_t)]),
     "ns_load": (C.c_int, [C.POINTER(C.c_void_p), C.c_void_p, C.c_size_t, C.c_void_p]),
@@ -177,7 +191,8 @@ class ProblemSpec:
 
 
 def opts_for(w: synth.Workload, seed=None, run_id: int = 0, max_iter: int = 1000, term_frac=None, n_live=None,
-             n_delete=None, n_steps=None, precision=None, kernel=None, walk_accept=None, walk_max=None) -> Opts:
+             n_delete=None, n_steps=None, precision=None, kernel=None, walk_accept=None, walk_max=None,
+             count_moves: bool = False) -> Opts:
     return Opts(
         n_live=w.n_live if n_live is None else n_live, n_delete=w.n_delete if n_delete is None else n_delete,
         n_steps=w.n_steps if n_steps is None else n_steps, slice_width=w.slice_width,
@@ -188,6 +203,7 @@ def opts_for(w: synth.Workload, seed=None, run_id: int = 0, max_iter: int = 1000
         kernel=w.kernel if kernel is None else kernel,
         walk_accept=w.walk_accept if walk_accept is None else walk_accept,
         walk_max=w.walk_max if walk_max is None else walk_max,
+        count_moves=1 if count_moves else 0,
     )
 
 
@@ -348,6 +364,19 @@ class Run:
 
     def profile(self, enable: bool = True):
         _check(lib().ns_profile(self.h, 1 if enable else 0))
+
+    def trace(self) -> dict:
+        """Per-iteration metrics of the iterations so far: a dict of arrays
+        with one entry per iteration (hist: one row per iteration)."""
+        n_out = C.c_long()
+        _check(lib().ns_trace(self.h, 0, None, C.byref(n_out)))
+        recs = (IterRec * max(n_out.value, 1))()
+        _check(lib().ns_trace(self.h, max(n_out.value, 1), recs, C.byref(n_out)))
+        recs = recs[: n_out.value]
+        out = {name: np.array([getattr(r, name) for r in recs])
+               for name, _ in IterRec._fields_ if name not in ("pad", "hist")}
+        out["hist"] = np.array([list(r.hist) for r in recs], dtype=np.int64).reshape(len(recs), PROBE_HIST)
+        return out
 
     def stats(self) -> dict:
         st = Stats()

@@ -13,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libns.so")
 SOURCES = [os.path.join(HERE, "csrc", f) for f in (
     "ns_api.hip", "ns_server.hip", "ns_kernels.hip", "ns_slice_d1.hip", "ns_slice_d2.hip", "ns_slice_d3.hip",
-    "ns_slice_p64.hip", "ns_slice_p128.hip", "ns_walk.hip")]
+    "ns_slice_m1.hip", "ns_slice_m2.hip", "ns_slice_m3.hip", "ns_slice_p64.hip", "ns_slice_p128.hip", "ns_walk.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 RATES_SRC = os.path.join(HERE, "csrc", "unit_rates.hip")
 RATES = os.path.join(HERE, "unit_rates")

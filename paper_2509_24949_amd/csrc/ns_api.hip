@@ -166,6 +166,7 @@ int validate_opts(const ns_opts* o) {
     if (o->walk_accept < 1 || o->walk_max < 1 || o->walk_max > (1 << 20))
       return fail(NS_E_ARG, "walk_accept must be >= 1 and walk_max in [1, 2^20]");
   }
+  if (o->count_moves != 0 && o->count_moves != 1) return fail(NS_E_ARG, "count_moves must be 0 or 1");
   return NS_OK;
 }
 
@@ -184,7 +185,8 @@ void run_footprint(const ns_problem* P, const ns_opts* O, size_t* resident, size
   const size_t cap = (size_t)O->max_iter * k;
   size_t b = rounded(sizeof(ModelDev)) + rounded(sizeof(DevState)) + rounded(n * d * 8) + rounded(n * 8) +
              2 * rounded(n * 4) + 2 * rounded(k * 4) + rounded(d * d * 8) + 2 * rounded(k * 4) + rounded(k * 8) +
-             rounded(cap * d * 8) + 3 * rounded(cap * 8) + 3 * rounded(cap * 4);
+             rounded(cap * d * 8) + 3 * rounded(cap * 8) + 3 * rounded(cap * 4) + 2 * rounded(k * 4) +
+             rounded((size_t)O->max_iter * sizeof(IterRec));
   size_t t = 0;
   if (P->likelihood != NS_LIKE_GAUSS) {
     const size_t nb = P->n_bins, nbd = (size_t)P->n_det * P->n_bins;
@@ -245,6 +247,7 @@ int run_create(ns_run** out, const ns_problem* P, const ns_opts* O, hipStream_t 
   R.kernel = O->kernel;
   R.walk_accept = O->walk_accept;
   R.walk_max = O->walk_max;
+  R.move_counts = (!packed && O->kernel == NS_KERNEL_SLICE && O->count_moves) ? 1 : 0;
   auto cleanup = [&](int code) { delete r; return code; };
   DevMem& mem = r->mem;
 #define ALLOC(ptr, count) \
@@ -261,6 +264,10 @@ int run_create(ns_run** out, const ns_problem* P, const ns_opts* O, hipStream_t 
   ALLOC(R.probes, k);
   ALLOC(R.acc, k);
   ALLOC(R.bins, k);
+  ALLOC(R.nso, k);
+  ALLOC(R.nsh, k);
+  R.trace_cap = O->max_iter;
+  ALLOC(R.trace, (size_t)O->max_iter);
   ALLOC(R.du, (size_t)R.cap * d);
   ALLOC(R.dlam, R.cap);
   ALLOC(R.dlogx, R.cap);
@@ -371,7 +378,7 @@ int run_create(ns_run** out, const ns_problem* P, const ns_opts* O, hipStream_t 
   }
 #undef ALLOC
   if (packed) (void)configure_slice_packed(r->M, r->RB.nb, &r->C);
-  else (void)configure_slice(r->M, r->RB.nb, R.k, &r->C);
+  else (void)configure_slice(r->M, r->RB.nb, R.k, R.move_counts != 0, &r->C);
   DevState s0{};
   s0.logX = 0.0;
   s0.logZ = -__builtin_inf();
@@ -450,6 +457,21 @@ int ns_stats(ns_run* r, ns_stats_t* out) {
   out->bin_terms = r->h_state->n_bin_terms;
   out->slice_threads = r->C.slice_threads;
   out->lds_tables = r->C.lds_tables ? 1 : 0;
+  return NS_OK;
+}
+
+int ns_trace(ns_run* r, long cap, ns_iter_t* out, long* n_out) {
+  if (!r || !n_out) return fail(NS_E_ARG, "NULL argument");
+  int rc = sync_state(r);
+  if (rc) return rc;
+  const long n = std::min<long>(r->h_state->iter, r->R.trace_cap);
+  *n_out = n;
+  if (!out) return NS_OK;
+  if (cap < n) return fail(NS_E_CAPACITY, "%ld iterations recorded, cap is %ld", n, cap);
+  if (n) {
+    HIP_OK(hipMemcpyAsync(out, r->R.trace, (size_t)n * sizeof(IterRec), hipMemcpyDeviceToHost, r->st));
+    HIP_OK(hipStreamSynchronize(r->st));
+  }
   return NS_OK;
 }
 
@@ -674,10 +696,17 @@ int ns_noise_loglike(ns_run* r, double* out) {
 
 }  // extern "C"
 
+// The device's metrics record is the public one.
+static_assert(sizeof(IterRec) == sizeof(ns_iter_t) && offsetof(IterRec, lstar) == offsetof(ns_iter_t, lstar) &&
+                  offsetof(IterRec, probes) == offsetof(ns_iter_t, probes) &&
+                  offsetof(IterRec, shrinks) == offsetof(ns_iter_t, shrinks) &&
+                  offsetof(IterRec, hist) == offsetof(ns_iter_t, hist) && PROBE_HIST == NS_PROBE_HIST,
+              "metrics record layout");
+
 // ---- checkpoint format ------------------------------------------------------
 namespace {
 
-constexpr char kMagic[8] = {'N', 'S', 'R', 'U', 'N', 'v', '2', '\0'};
+constexpr char kMagic[8] = {'N', 'S', 'R', 'U', 'N', 'v', '3', '\0'};
 
 struct Writer {
   unsigned char* buf;
@@ -736,6 +765,7 @@ int ns_save(ns_run* r, void* buf, size_t cap, size_t* n_out) {
   const size_t nd = (size_t)st.n_dead;
   std::vector<double> u((size_t)R.n * R.d), lam(R.n), du(nd * R.d), dlam(nd), dlogx(nd), dlogw(nd);
   std::vector<int> diter(nd), dslot(nd), dnlive(nd);
+  std::vector<IterRec> trace((size_t)std::min<long long>(st.iter, R.trace_cap));
   const bool fetch = buf != nullptr;
   Writer w{nullptr, 0};   // the first pass only measures
   const ns_problem& P = r->prob.P;
@@ -756,6 +786,8 @@ int ns_save(ns_run* r, void* buf, size_t cap, size_t* n_out) {
         HIP_OK(hipMemcpyAsync(dslot.data(), R.dslot, nd * sizeof(int), hipMemcpyDeviceToHost, r->st));
         HIP_OK(hipMemcpyAsync(dnlive.data(), R.dnlive, nd * sizeof(int), hipMemcpyDeviceToHost, r->st));
       }
+      if (!trace.empty())
+        HIP_OK(hipMemcpyAsync(trace.data(), R.trace, trace.size() * sizeof(IterRec), hipMemcpyDeviceToHost, r->st));
       HIP_OK(hipStreamSynchronize(r->st));
       w = Writer{static_cast<unsigned char*>(buf), cap};
     }
@@ -783,6 +815,7 @@ int ns_save(ns_run* r, void* buf, size_t cap, size_t* n_out) {
     w.vec(diter);
     w.vec(dslot);
     w.vec(dnlive);
+    w.vec(trace);
   }
   if (n_out) *n_out = w.n;
   if (!buf || w.n > cap) return fail(NS_E_CAPACITY, "the checkpoint needs %zu bytes, cap is %zu", w.n, buf ? cap : 0);
@@ -816,6 +849,7 @@ int ns_load(ns_run** out, const void* buf, size_t size, void* stream) {
   auto u = rd.vec<double>(big), lam = rd.vec<double>(big), du = rd.vec<double>(big), dlam = rd.vec<double>(big),
        dlogx = rd.vec<double>(big), dlogw = rd.vec<double>(big);
   auto diter = rd.vec<int>(big), dslot = rd.vec<int>(big), dnlive = rd.vec<int>(big);
+  auto trace = rd.vec<IterRec>(big);
   if (!rd.ok || rd.n != size) return fail(NS_E_ARG, "malformed checkpoint");
   ns_problem P{};
   P.model = ps.model; P.likelihood = ps.likelihood; P.n_dim = ps.n_dim; P.n_bins = ps.n_bins; P.n_det = ps.n_det;
@@ -843,7 +877,8 @@ int ns_load(ns_run** out, const void* buf, size_t size, void* stream) {
   if (ndead < 0 || u.size() != n * d || lam.size() != n || du.size() != (size_t)ndead * d ||
       dlam.size() != (size_t)ndead || dlogx.size() != (size_t)ndead || dlogw.size() != (size_t)ndead ||
       diter.size() != (size_t)ndead || dslot.size() != (size_t)ndead || dnlive.size() != (size_t)ndead ||
-      ndead > (long long)O.max_iter * O.n_delete)
+      ndead > (long long)O.max_iter * O.n_delete ||
+      (long long)trace.size() != std::min<long long>(std::max(st.iter, 0), std::max(O.max_iter, 0)))
     return fail(NS_E_ARG, "checkpoint state does not match the run sizes");
   ns_run* r = nullptr;
   int rc = run_create(&r, &P, &O, static_cast<hipStream_t>(stream), packed != 0);
@@ -862,6 +897,8 @@ int ns_load(ns_run** out, const void* buf, size_t size, void* stream) {
     if (e == hipSuccess) e = hipMemcpyAsync(R.dslot, dslot.data(), ndead * sizeof(int), hipMemcpyHostToDevice, r->st);
     if (e == hipSuccess) e = hipMemcpyAsync(R.dnlive, dnlive.data(), ndead * sizeof(int), hipMemcpyHostToDevice, r->st);
   }
+  if (e == hipSuccess && !trace.empty())
+    e = hipMemcpyAsync(R.trace, trace.data(), trace.size() * sizeof(IterRec), hipMemcpyHostToDevice, r->st);
   if (e == hipSuccess) e = hipStreamSynchronize(r->st);
   if (e != hipSuccess) {
     ns_free(r);

@@ -20,6 +20,16 @@ struct DevState {
   int pad;
 };
 
+// One iteration's metrics record as the termination kernel writes it; the
+// layout is the public ns_iter_t's (checked where both are visible).
+constexpr int PROBE_HIST = 32;
+struct IterRec {
+  int iter, probes_min, probes_max, pad;
+  double lstar, logX, logZ, log_remaining;
+  long long probes, steps, accepted, stepouts, shrinks;
+  int hist[PROBE_HIST];
+};
+
 // Likelihood tables in HBM (built once per run).
 struct Tables {
   const double* f;      // [n_bins] f_k
@@ -82,9 +92,15 @@ struct RunDev {
   double* chol;               // [d][d]
   int kernel;                 // 0 slice chains, 1 random-walk chains
   int walk_accept, walk_max;  // random walk: target acceptances per chain, chain-length cap
-  int* acc;                   // [k] accepted proposals of each random-walk chain in the last iteration
+  int* acc;                   // [k] per chain in the last iteration: random walk, accepted
+                              // proposals; slice, steps that moved
   int* probes;                // [k] likelihood calls of each chain in the last iteration
   long long* bins;            // [k] active bins summed over the chain's probes in the last iteration
+  int* nso;                   // [k] slice: bracket expansions of each chain in the last iteration
+  int* nsh;                   // [k] slice: rejected shrink candidates of each chain
+  int move_counts;            // slice: the chains count their moves (nso, nsh, acc and the histogram)
+  IterRec* trace;             // [trace_cap] per-iteration metrics
+  int trace_cap;
   double* du;                 // [cap][d]
   double* dlam;               // [cap]
   double* dlogx;              // [cap]
@@ -106,6 +122,7 @@ __host__ __device__ constexpr bool lk_mixed(int lk) { return lk == LK_FULL32 || 
 struct LaunchCfg {
   int slice_threads;          // 64, 128 or 256 threads per chain
   bool lds_tables;            // stage the full-grid tables in LDS
+  bool move_counts;           // the move-counting chain kernels (64 threads per chain)
   size_t lds_bytes;           // dynamic LDS of the chain kernel
 };
 
@@ -177,8 +194,9 @@ hipError_t launch_build_rb_sums(const ModelDev& M, const ModelDev* Md, const Tab
                                 const double* theta_fid_dev, int nb, const RBBuffers& B, hipStream_t st);
 // Chain-kernel set-up of a run with n_chains chains: staged tables if they
 // fit, then the widest workgroup (256, 128 or 64 threads) that keeps every
-// chain resident at once.
-hipError_t configure_slice(const ModelDev& M, int rb_nb, int n_chains, LaunchCfg* C);
+// chain resident at once; with count_moves, the move-counting kernels of 64
+// threads per chain.
+hipError_t configure_slice(const ModelDev& M, int rb_nb, int n_chains, bool count_moves, LaunchCfg* C);
 // Chain-kernel set-up of runs that take part in packed launches: 64
 // threads per chain (128 or 256 through NS_PACKED_THREADS, for tuning),
 // tables read through the caches (as in the packed kernel).

@@ -1258,6 +1258,9 @@ __device__ void prep_body(const RunDev& R) {
     if (tid == 0) S->done = 2;
     return;
   }
+  // the iteration's evaluations-per-step histogram, which the slice chains
+  // add to
+  if (tid < PROBE_HIST && it < R.trace_cap) R.trace[it].hist[tid] = 0;
 
   // ---- evidence: the j-th death shrinks log X by 1/(n-j); its weight is the
   // shell between consecutive volumes, X_{j-1} (1 - e^{-1/(n-j)}).
@@ -1475,9 +1478,10 @@ template <int NC> struct SliceBatch {
 constexpr int SL_CHUNK = 16;                          // steps drawn per chunk
 constexpr int SL_PSTRIDE = (int)((sizeof(ProbeRec) + 15) / 16) * 2;   // doubles per stored record
 constexpr int SL_NU = 10;                             // uniforms per step: width, split, 8 shrink
-__host__ __device__ constexpr size_t slice_fixed_doubles(int nt) {
+constexpr int SL_CNT = PROBE_HIST + 4 + 4 * SL_CHUNK;  // ints of the walk's move counters
+__host__ __device__ constexpr size_t slice_fixed_doubles(int nt, bool mv) {
   return MAX_DIM * MAX_DIM + 16 + SL_CHUNK * MAX_DIM + SL_CHUNK * SL_NU + (size_t)(nt / 2) * SL_PSTRIDE + nt + nt +
-         nt / 4 + 16;
+         nt / 4 + 16 + (mv ? SL_CNT / 2 : 0);
 }
 
 // One workgroup of NT threads runs chain j = blockIdx.x for all n_steps
@@ -1489,8 +1493,12 @@ __host__ __device__ constexpr size_t slice_fixed_doubles(int nt) {
 // computes the intrinsic half of every candidate's probe while the second
 // half computes the extrinsic one.  All threads then walk the batch in the
 // sequential order of the algorithm and split every probe's frequency bins.
-// Rarer outcomes fall back to further batches.
-template <int NDET, int NT, int LK, bool LDS>
+// Rarer outcomes fall back to further batches.  MV: also count the walk's
+// moves (bracket expansions, rejected shrink candidates, moved steps and
+// the evaluations of each step) for the iteration's metrics record; the
+// counting is a separate instantiation so that the other kernels carry none
+// of it.
+template <int NDET, int NT, int LK, bool LDS, bool MV = false>
 __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& RB, const RunDev& R, int j,
                            double* smem) {
   constexpr int NW = NT / 64;
@@ -1512,8 +1520,18 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
   double* sG = sT + NT;
   unsigned long long* sMask = reinterpret_cast<unsigned long long*>(sG + NT);   // in-cube bits per 64 candidates
   double* sX = sG + NT + NT / 4;     // chain position
-  double* stab = sX + 16;
+  // the walk's moves: steps by the evaluations they made ([0, PROBE_HIST),
+  // the last bin for that many or more), bracket expansions, rejected shrink
+  // candidates, steps that moved, and the evaluations made before the
+  // current chunk; then one record per step of the chunk (evaluations so
+  // far, expansions, rejected shrink candidates, moved), written by thread 0
+  // as the step ends and folded into the counts once per chunk
+  int* sCnt = reinterpret_cast<int*>(sX + 16);
+  int* sStep = sCnt + PROBE_HIST + 4;
+  double* stab = sX + 16 + (MV ? SL_CNT / 2 : 0);
   for (int i = tid; i < d * d; i += NT) sL[i] = R.chol[i];
+  if constexpr (MV)
+    for (int i = tid; i < SL_CNT; i += NT) sCnt[i] = 0;
   TabView V{};
   if (lk_full(LK)) V = stage_tables<NDET, lk_mixed(LK)>(M, T, LDS, stab, tid, NT);
   // relative binning: the tables, staged in LDS when LDS is set
@@ -1690,11 +1708,28 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
     return rb;
   };
 
+  // wave 0 folds the step records of a finished chunk of ns steps into the
+  // counts (after a barrier that follows the chunk's last step)
+  auto fold = [&](int ns) {
+    if (wv == 0 && lane < ns) {
+      const int* r = sStep + 4 * lane;
+      const int before = lane == 0 ? sCnt[PROBE_HIST + 3] : sStep[4 * (lane - 1)];
+      const int pe = r[0] - before;
+      atomicAdd(&sCnt[pe < PROBE_HIST - 1 ? pe : PROBE_HIST - 1], 1);
+      atomicAdd(&sCnt[PROBE_HIST], r[1]);
+      atomicAdd(&sCnt[PROBE_HIST + 1], r[2]);
+      atomicAdd(&sCnt[PROBE_HIST + 2], r[3]);
+      if (lane == ns - 1) sCnt[PROBE_HIST + 3] = r[0];
+    }
+  };
+
   for (int s0 = 0; s0 < R.m; s0 += SL_CHUNK) {
     const int cs = (R.m - s0) < SL_CHUNK ? (R.m - s0) : SL_CHUNK;
     // ---- draw the chunk: per step nbd direction blocks (two Box-Muller
     // pairs each), the width block and two shrink blocks
     __syncthreads();
+    if constexpr (MV)
+      if (s0 > 0) fold(SL_CHUNK);
     const int per = nbd + 3;
     for (int bI = tid; bI < cs * per; bI += NT) {
       const int sl = bI / per, r = bI - sl * per;
@@ -1890,8 +1925,11 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
         }
       }
 
+      if constexpr (MV)
+        if (tid == 0) sStep[4 * sl + 1] = na + nh;
+
       // ---- shrink
-      int a = 0;                   // attempts made
+      int a = 0;                   // shrink attempts rejected so far
       bool accepted = false;
       if (MULTI && combined && na < BL::H && nh < BL::H) {
         // attempts a .. a+NW-1 together (each under the hypothesis that the
@@ -2015,11 +2053,19 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
               if (tid < d) sX[tid] = cube_coord(M.periodic, tid, fma(tt, dir[tid], sX[tid]));
               lx = ly;
               accepted = true;
-              ++a;
+              if constexpr (!MV) ++a;
               break;
             }
           }
           if (tt < 0.0) lo = tt; else hi = tt;
+        }
+      }
+      // a now counts the rejected shrink candidates in every form above
+      if constexpr (MV) {
+        if (tid == 0) {
+          sStep[4 * sl + 0] = nprobe;
+          sStep[4 * sl + 2] = a;
+          sStep[4 * sl + 3] = accepted ? 1 : 0;
         }
       }
     }
@@ -2027,6 +2073,18 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
   __syncthreads();
   const int slot = R.dead[j];
   for (int i = tid; i < d; i += NT) R.u[(size_t)slot * d + i] = sX[i];
+  if constexpr (MV) {
+    fold(R.m - ((R.m - 1) / SL_CHUNK) * SL_CHUNK);   // the last chunk (wave 0 reads its own results below)
+    // the chain's histogram into the iteration's record (zeroed by the
+    // preparation kernel); integer sums, so the total is exact in any order
+    if (tid < PROBE_HIST && t < (uint64_t)R.trace_cap && sCnt[tid] != 0)
+      atomicAdd(&R.trace[t].hist[tid], sCnt[tid]);
+    if (tid == 0) {
+      R.nso[j] = sCnt[PROBE_HIST];
+      R.nsh[j] = sCnt[PROBE_HIST + 1];
+      R.acc[j] = sCnt[PROBE_HIST + 2];
+    }
+  }
   if (tid == 0) {
     R.lam[slot] = lx;
     R.probes[j] = nprobe;
@@ -2034,10 +2092,10 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
   }
 }
 
-template <int NDET, int NT, int LK, bool LDS>
+template <int NDET, int NT, int LK, bool LDS, bool MV = false>
 __global__ __launch_bounds__(NT, 2) void k_slice(const ModelDev* __restrict__ Mp, Tables T, RBTables RB, RunDev R) {
   extern __shared__ double smem[];
-  slice_body<NDET, NT, LK, LDS>(*Mp, T, RB, R, blockIdx.x, smem);
+  slice_body<NDET, NT, LK, LDS, MV>(*Mp, T, RB, R, blockIdx.x, smem);
 }
 
 
@@ -2047,32 +2105,97 @@ __device__ void term_body(const RunDev& R) {
   DevState* S = R.state;
   if (S->done) return;
   const int n = R.n, tid = threadIdx.x;
+  // the state, read once up front (thread 0 writes it back at the end, after
+  // the metrics record, so no load waits behind those stores)
+  const int it = S->iter, wl = S->walk_len;
+  const double lstar = S->lstar, logX = S->logX, logZ = S->logZ;
+  const long long n_dead = S->n_dead, n_evals = S->n_evals, n_bins = S->n_bin_terms;
+  const bool slice = R.kernel == 0;
+  const bool moves = !slice || R.move_counts;   // acc holds this iteration's values
   double m = NEG_INF;
   for (int i = tid; i < n; i += 1024) m = fmax(m, order_value(R.lam[i]));
   m = block_max<1024>(m, sbuf);
-  double v[4] = {0.0, 0.0, 0.0, 0.0};   // sum exp(lambda - max), probes, bins, walk acceptances
-  for (int i = tid; i < n; i += 1024) v[0] += exp(order_value(R.lam[i]) - m);
+  double e = 0.0;                  // sum exp(lambda - max)
+  for (int i = tid; i < n; i += 1024) e += exp(order_value(R.lam[i]) - m);
+  // per-chain totals (evaluations, bins, accepted walk proposals or moved
+  // slice steps, expansions, shrinks) and the fewest and most evaluations of
+  // a chain.  Only thread 0 needs them and the exponential sum: each wave
+  // reduces its own, then wave 0 combines the waves (the exponential sum
+  // in wave order; the counts are integers below 2^53, exact in any order)
+  constexpr int NW = 1024 / 64;
+  const int lane = tid & 63, wv = tid >> 6;
+  double c[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  double x[2] = {0.0, -2147483647.0};   // most and (negated) fewest evaluations
+#pragma unroll 1
   for (int j = tid; j < R.k; j += 1024) {
-    v[1] += (double)R.probes[j];
-    v[2] += (double)R.bins[j];
-    if (R.kernel == 1) v[3] += (double)R.acc[j];
+    const double p = (double)R.probes[j];
+    c[0] += p;
+    c[1] += (double)R.bins[j];
+    if (moves) c[2] += (double)R.acc[j];
+    if (slice && moves) {
+      c[3] += (double)R.nso[j];
+      c[4] += (double)R.nsh[j];
+    }
+    x[0] = fmax(x[0], p);
+    x[1] = fmax(x[1], -p);
   }
-  block_sum_k<1024, 4>(v, sbuf);
-  const double s = v[0], pe = v[1], pb = v[2];
+  e = wave_sum(e);
+#pragma unroll
+  for (int q = 0; q < 5; ++q) c[q] = wave_sum(c[q]);
+#pragma unroll
+  for (int q = 0; q < 2; ++q) x[q] = wave_max(x[q]);
+  __syncthreads();                 // every thread has read block_max's values
+  if (lane == 0) {
+    sbuf[wv] = e;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) sbuf[(1 + q) * NW + wv] = c[q];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) sbuf[(6 + q) * NW + wv] = x[q];
+  }
+  __syncthreads();
+  double s = 0.0;
+  if (wv == 0) {
+#pragma unroll
+    for (int w = 0; w < NW; ++w) s += sbuf[w];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) c[q] = wave_sum(lane < NW ? sbuf[(1 + q) * NW + lane] : 0.0);
+#pragma unroll
+    for (int q = 0; q < 2; ++q) x[q] = wave_max(lane < NW ? sbuf[(6 + q) * NW + lane] : NEG_INF);
+  }
+  const double pmax = x[0], nmin = x[1];
+  // (the record's histogram was summed by the chains themselves)
+  const bool rec_on = it < R.trace_cap;
+  const double pe = c[0], pb = c[1];
   if (tid == 0) {
-    const double logz_live = S->logX + m + log(s / n);
+    const double logz_live = logX + m + log(s / n);
+    if (rec_on) {
+      IterRec& rc = R.trace[it];
+      rc.iter = it;
+      rc.probes_min = (int)(-nmin);
+      rc.probes_max = (int)pmax;
+      rc.pad = 0;
+      rc.lstar = lstar;
+      rc.logX = logX;
+      rc.logZ = logZ;
+      rc.log_remaining = logz_live - logZ;
+      rc.probes = (long long)pe;
+      rc.steps = (long long)R.k * (slice ? R.m : wl);
+      rc.accepted = moves ? (long long)c[2] : -1;
+      rc.stepouts = moves ? (long long)c[3] : -1;
+      rc.shrinks = moves ? (long long)c[4] : -1;
+    }
     int done = 0;
-    if (R.log_term > NEG_INF && logz_live - S->logZ < R.log_term) done = 1;
-    if (S->n_dead + R.k > R.cap) done = 2;
-    S->n_evals += (long long)pe;
-    S->n_bin_terms += (long long)pb;
+    if (R.log_term > NEG_INF && logz_live - logZ < R.log_term) done = 1;
+    if (n_dead + R.k > R.cap) done = 2;
+    S->n_evals = n_evals + (long long)pe;
+    S->n_bin_terms = n_bins + (long long)pb;
     if (R.kernel == 1) {
       // next chain length: walk_accept acceptances at this iteration's rate
-      const long long acc = (long long)v[3], prop = (long long)R.k * S->walk_len;
+      const long long acc = (long long)c[2], prop = (long long)R.k * wl;
       long long want = acc > 0 ? ((long long)R.walk_accept * prop + acc - 1) / acc : R.walk_max;
       S->walk_len = (int)(want < 1 ? 1 : (want > R.walk_max ? R.walk_max : want));
     }
-    S->iter += 1;
+    S->iter = it + 1;
     S->done = done;
   }
 }
@@ -2519,29 +2642,29 @@ hipError_t launch_loglike_t(const ModelDev& M, const ModelDev* Md, const Tables&
   return hipGetLastError();
 }
 
-template <int NDET, int NT, int LK, bool LDS>
+template <int NDET, int NT, int LK, bool LDS, bool MV = false>
 hipError_t launch_slice_t(const ModelDev* Md, const Tables& T, const RBTables& RB, const RunDev& R, size_t lds,
                           hipStream_t st) {
-  hipLaunchKernelGGL((k_slice<NDET, NT, LK, LDS>), dim3(R.k), dim3(NT), lds, st, Md, T, RB, R);
+  hipLaunchKernelGGL((k_slice<NDET, NT, LK, LDS, MV>), dim3(R.k), dim3(NT), lds, st, Md, T, RB, R);
   return hipGetLastError();
 }
 
-template <int NDET, int NT>
+template <int NDET, int NT, bool MV = false>
 hipError_t launch_slice_nt(const ModelDev& M, const ModelDev* Md, const Tables& T, const RBTables& RB,
                            const RunDev& R, const LaunchCfg& C, hipStream_t st) {
   if (M.likelihood == LK_RB) {
     if (M.mixed)
-      return C.lds_tables ? launch_slice_t<NDET, NT, LK_RB32, true>(Md, T, RB, R, C.lds_bytes, st)
-                          : launch_slice_t<NDET, NT, LK_RB32, false>(Md, T, RB, R, C.lds_bytes, st);
-    return C.lds_tables ? launch_slice_t<NDET, NT, LK_RB, true>(Md, T, RB, R, C.lds_bytes, st)
-                        : launch_slice_t<NDET, NT, LK_RB, false>(Md, T, RB, R, C.lds_bytes, st);
+      return C.lds_tables ? launch_slice_t<NDET, NT, LK_RB32, true, MV>(Md, T, RB, R, C.lds_bytes, st)
+                          : launch_slice_t<NDET, NT, LK_RB32, false, MV>(Md, T, RB, R, C.lds_bytes, st);
+    return C.lds_tables ? launch_slice_t<NDET, NT, LK_RB, true, MV>(Md, T, RB, R, C.lds_bytes, st)
+                        : launch_slice_t<NDET, NT, LK_RB, false, MV>(Md, T, RB, R, C.lds_bytes, st);
   }
   if (M.mixed) {
-    if (C.lds_tables) return launch_slice_t<NDET, NT, LK_FULL32, true>(Md, T, RB, R, C.lds_bytes, st);
-    return launch_slice_t<NDET, NT, LK_FULL32, false>(Md, T, RB, R, C.lds_bytes, st);
+    if (C.lds_tables) return launch_slice_t<NDET, NT, LK_FULL32, true, MV>(Md, T, RB, R, C.lds_bytes, st);
+    return launch_slice_t<NDET, NT, LK_FULL32, false, MV>(Md, T, RB, R, C.lds_bytes, st);
   }
-  if (C.lds_tables) return launch_slice_t<NDET, NT, LK_FULL, true>(Md, T, RB, R, C.lds_bytes, st);
-  return launch_slice_t<NDET, NT, LK_FULL, false>(Md, T, RB, R, C.lds_bytes, st);
+  if (C.lds_tables) return launch_slice_t<NDET, NT, LK_FULL, true, MV>(Md, T, RB, R, C.lds_bytes, st);
+  return launch_slice_t<NDET, NT, LK_FULL, false, MV>(Md, T, RB, R, C.lds_bytes, st);
 }
 
 template <int NDET>
@@ -2554,7 +2677,7 @@ hipError_t launch_slice_det(const ModelDev& M, const ModelDev* Md, const Tables&
   }
 }
 
-size_t slice_lds_fixed(int nt) { return slice_fixed_doubles(nt) * sizeof(double); }
+size_t slice_lds_fixed(int nt, bool mv) { return slice_fixed_doubles(nt, mv) * sizeof(double); }
 
 template <int NT>
 hipError_t launch_slice_packed_nt(const PackedRun* runs, const int* slice_off, int nr, int slice_blocks, int lk,
@@ -2587,6 +2710,13 @@ hipError_t launch_slice_d2(const ModelDev& M, const ModelDev* Md, const Tables& 
                            const RunDev& R, const LaunchCfg& C, hipStream_t st);
 hipError_t launch_slice_d3(const ModelDev& M, const ModelDev* Md, const Tables& T, const RBTables& RB,
                            const RunDev& R, const LaunchCfg& C, hipStream_t st);
+// the move-counting chain kernels (64 threads per chain)
+hipError_t launch_slice_mv_d1(const ModelDev& M, const ModelDev* Md, const Tables& T, const RBTables& RB,
+                              const RunDev& R, const LaunchCfg& C, hipStream_t st);
+hipError_t launch_slice_mv_d2(const ModelDev& M, const ModelDev* Md, const Tables& T, const RBTables& RB,
+                              const RunDev& R, const LaunchCfg& C, hipStream_t st);
+hipError_t launch_slice_mv_d3(const ModelDev& M, const ModelDev* Md, const Tables& T, const RBTables& RB,
+                              const RunDev& R, const LaunchCfg& C, hipStream_t st);
 hipError_t launch_slice_packed64(const PackedRun* runs, const int* slice_off, int nr, int slice_blocks, int lk,
                                  size_t slice_lds, hipStream_t st);
 hipError_t launch_slice_packed128(const PackedRun* runs, const int* slice_off, int nr, int slice_blocks, int lk,

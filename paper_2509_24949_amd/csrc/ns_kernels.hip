@@ -9,18 +9,19 @@ namespace ns {
 
 int likelihood_kind(const ModelDev& M) { return M.likelihood; }
 
-hipError_t configure_slice(const ModelDev& M, int rb_nb, int n_chains, LaunchCfg* C) {
+hipError_t configure_slice(const ModelDev& M, int rb_nb, int n_chains, bool count_moves, LaunchCfg* C) {
+  C->move_counts = count_moves;
   if (M.likelihood == LK_GAUSS) {
     C->slice_threads = 64;
     C->lds_tables = false;
-    C->lds_bytes = slice_lds_fixed(64);
+    C->lds_bytes = slice_lds_fixed(64, count_moves);
     return hipSuccess;
   }
   const bool rb = M.likelihood == LK_RB;
   // LDS of a chain workgroup: its own data and the staged tables (optional)
   const size_t tab = rb ? rb_stage_doubles(rb_nb, M.n_det, M.mixed != 0) * sizeof(double)
                         : staged_table_bytes(M.k_lim, M.n_det, M.mixed != 0);
-  auto lds_of = [&](int nt, bool stage) { return slice_lds_fixed(nt) + (stage ? tab : 0); };
+  auto lds_of = [&](int nt, bool stage) { return slice_lds_fixed(nt, count_moves) + (stage ? tab : 0); };
   // every chain should be resident at once: a CU holds eight waves of the
   // chain kernel (its registers allow two per SIMD) and 160 KB of LDS
   auto resident = [&](int nt, bool stage) {
@@ -33,6 +34,7 @@ hipError_t configure_slice(const ModelDev& M, int rb_nb, int n_chains, LaunchCfg
     const int v = atoi(ev);
     if (v == 64 || v == 128 || v == 256) force_nt = v;
   }
+  if (count_moves) force_nt = 64;                          // the move-counting kernels' width
   bool allow_stage = true;
   if (const char* ev = getenv("NS_LDS_TABLES")) allow_stage = atoi(ev) != 0;   // tuning override
   // prefer staged tables, then the widest workgroup that keeps every chain resident
@@ -204,7 +206,14 @@ hipError_t launch_iteration(const ModelDev& M, const ModelDev* Md, const Tables&
   if (R.kernel == 1) {
     e = launch_walk(M, Md, T, RB, R, st);
   } else if (M.likelihood == LK_GAUSS) {
-    e = launch_slice_t<1, 64, LK_GAUSS, false>(Md, T, RB, R, C.lds_bytes, st);
+    e = C.move_counts ? launch_slice_t<1, 64, LK_GAUSS, false, true>(Md, T, RB, R, C.lds_bytes, st)
+                      : launch_slice_t<1, 64, LK_GAUSS, false>(Md, T, RB, R, C.lds_bytes, st);
+  } else if (C.move_counts) {
+    switch (M.n_det) {
+      case 1: e = launch_slice_mv_d1(M, Md, T, RB, R, C, st); break;
+      case 2: e = launch_slice_mv_d2(M, Md, T, RB, R, C, st); break;
+      default: e = launch_slice_mv_d3(M, Md, T, RB, R, C, st); break;
+    }
   } else {
     switch (M.n_det) {
       case 1: e = launch_slice_d1(M, Md, T, RB, R, C, st); break;
@@ -229,7 +238,8 @@ hipError_t configure_slice_packed(const ModelDev& M, int rb_nb, LaunchCfg* C) {
     if (v == 64 || v == 128 || v == 256) C->slice_threads = v;
   }
   C->lds_tables = false;
-  C->lds_bytes = slice_lds_fixed(C->slice_threads);
+  C->move_counts = false;
+  C->lds_bytes = slice_lds_fixed(C->slice_threads, false);
   (void)rb_nb;
   return hipSuccess;
 }

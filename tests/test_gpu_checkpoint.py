@@ -27,7 +27,7 @@ def _record(run):
     st = run.state()
     u, l = run.live()
     return dict(d, live_u=u, live_l=l, logZ=st["logZ"], H=st["H"], logX=st["logX"], n_evals=st["n_evals"],
-                iterations=st["iter"], done=st["done"], final=run.logZ(200))
+                iterations=st["iter"], done=st["done"], final=run.logZ(200), trace=run.trace())
 
 
 def _identical(a, b):
@@ -35,14 +35,19 @@ def _identical(a, b):
         np.testing.assert_array_equal(a[key], b[key], err_msg=key)
     for key in ("logZ", "H", "logX", "n_evals", "iterations", "done", "final"):
         assert a[key] == b[key], key
+    # the per-iteration metrics, those before the checkpoint included
+    assert len(a["trace"]["iter"]) == a["iterations"]
+    for key in a["trace"]:
+        np.testing.assert_array_equal(a["trace"][key], b["trace"][key], err_msg=key)
 
 
-@pytest.mark.parametrize("name,first,then", [("tf2_1det", 5, 200), ("tf2_3det_rb", 2, 2), ("tf2_3det_mixed", 1, 2)])
-def test_resume_is_bit_identical(torch_cuda, name, first, then):
+@pytest.mark.parametrize("name,first,then,count", [("tf2_1det", 5, 200, False), ("tf2_3det_rb", 2, 2, False),
+                                                  ("tf2_3det_mixed", 1, 2, False), ("tf2_3det", 1, 2, True)])
+def test_resume_is_bit_identical(torch_cuda, name, first, then, count):
     w = synth.workload(name)
     re, im = binding.make_data(w)
     spec = binding.ProblemSpec(w, re, im)
-    opts = binding.opts_for(w, max_iter=first + then)
+    opts = binding.opts_for(w, max_iter=first + then, count_moves=count)
     a = binding.Run(spec, opts)
     a.step(first)
     blob = a.save()

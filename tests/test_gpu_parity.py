@@ -6,6 +6,7 @@ relative in double precision (relative to the cancellation scale
 seeds follow the oracle in lockstep (identical dead-point slots, log-likelihoods
 and evidence to rounding).
 """
+import ctypes as C
 import math
 import os
 
@@ -119,11 +120,11 @@ def test_select_bit_exact(torch_cuda, n):
             assert ls.item() == ols
 
 
-def _lockstep(w, orc, spec, iters, n_live=None, n_delete=None, max_iter=1000, term_frac=None):
+def _lockstep(w, orc, spec, iters, n_live=None, n_delete=None, max_iter=1000, term_frac=None, count_moves=False):
     ro = oracle.Run(orc, oracle.opts_for(w, n_threads=NTHREADS, n_live=n_live, n_delete=n_delete, max_iter=max_iter,
                                          term_frac=term_frac))
     rg = binding.Run(spec, binding.opts_for(w, n_live=n_live, n_delete=n_delete, max_iter=max_iter,
-                                            term_frac=term_frac))
+                                            term_frac=term_frac, count_moves=count_moves))
     uo, lo = ro.live()
     ug, lg = rg.live()
     np.testing.assert_array_equal(ug, uo)        # same Philox draws
@@ -136,7 +137,28 @@ def _lockstep(w, orc, spec, iters, n_live=None, n_delete=None, max_iter=1000, te
         assert do == dg, it
         if do:
             break
+    _compare_traces(ro, rg)
     return ro, rg
+
+
+def _compare_traces(ro, rg):
+    """Per-iteration metrics: the walk's counts (evaluations per chain and
+    per step, expansions, rejected shrink candidates, moved steps) exactly;
+    the threshold to the likelihood tolerance; log X, log Z and the
+    remaining-evidence term to the evidence tolerances."""
+    a, b = ro.trace(), rg.trace()
+    assert len(a["iter"]) == len(b["iter"]) == ro.state()["iter"]
+    moves = ("accepted", "stepouts", "shrinks", "hist")
+    counted = len(b["iter"]) == 0 or b["stepouts"][0] != -1
+    if not counted:       # slice chains run without move counting
+        assert np.all(b["accepted"] == -1) and np.all(b["stepouts"] == -1) and np.all(b["shrinks"] == -1)
+        assert not b["hist"].any()
+    for key in ("iter", "probes", "probes_min", "probes_max", "steps") + (moves if counted else ()):
+        np.testing.assert_array_equal(b[key], a[key], err_msg=key)
+    assert np.all(np.abs(b["lstar"] - a["lstar"]) <= 1e-9 * (np.abs(a["lstar"]) + 1.0))
+    assert np.all(np.abs(b["logX"] - a["logX"]) <= 1e-12 * (np.abs(a["logX"]) + 1.0))
+    assert np.all(np.abs(b["logZ"] - a["logZ"]) <= 1e-9 * (np.abs(a["logZ"]) + 1.0))
+    assert np.all(np.abs(b["log_remaining"] - a["log_remaining"]) <= 1e-9 * (np.abs(a["logZ"]) + 1.0))
 
 
 def _compare_runs(ro, rg, tol=1e-9):
@@ -155,6 +177,7 @@ def _compare_runs(ro, rg, tol=1e-9):
     uo, lo = ro.live()
     ug, lg = rg.live()
     assert np.max(np.abs(ug - uo)) <= 1e-9
+    _compare_traces(ro, rg)
     zo, zg = ro.logZ(200), rg.logZ(200)
     assert abs(zo["logZ"] - zg["logZ"]) <= tol * (abs(zo["logZ"]) + 1)
     assert abs(zo["sigma"] - zg["sigma"]) <= 1e-6 * zo["sigma"] + 1e-12
@@ -210,6 +233,11 @@ def test_capacity_and_no_termination(torch_cuda):
     assert rg.step(10)
     st = rg.state()
     assert st["iter"] == 3 and st["n_dead"] == 150 and st["done"] == 2
+    # one metrics record per iteration; a short caller buffer gets the count only
+    assert np.array_equal(rg.trace()["iter"], np.arange(3))
+    recs = (binding.IterRec * 2)()
+    n_out = C.c_long()
+    assert binding.lib().ns_trace(rg.h, 2, recs, C.byref(n_out)) == binding.NS_E_CAPACITY and n_out.value == 3
     rg = binding.Run(spec, binding.opts_for(w, term_frac=0.0, max_iter=100))
     assert not rg.step(40)
     assert rg.state()["iter"] == 40
@@ -408,6 +436,28 @@ def test_chain_configurations_lockstep(torch_cuda, monkeypatch, name, threads, s
         assert st["lds_tables"] == 0
     _compare_runs(ro, rg)
     rg.close()
+
+
+@pytest.mark.parametrize("name,iters", [("gauss", 40), ("tf2_1det", 30), ("tf2_3det", 2), ("tf2_3det_rb", 2),
+                                        ("tf2_3det_so", 2), ("tf2_3det_rb_paper", 1)])
+def test_move_counts_lockstep(torch_cuda, name, iters):
+    """The move-counting chain kernels follow the oracle in lockstep, and
+    their per-iteration move counts (bracket expansions, rejected shrink
+    candidates, moved steps, the evaluations-per-step histogram) equal the
+    oracle's sequential walk exactly."""
+    if name == "gauss":
+        w = synth.gauss_workload(5, 0.05, mu=np.linspace(0.3, 0.7, 5), n_live=300, n_delete=150)
+        orc, spec = oracle.OracleProblem(w), binding.ProblemSpec(w)
+    else:
+        w = synth.workload(name)
+        orc, spec = _pair(w)
+    print(f"move counts {name}: {iters} iterations", flush=True)
+    ro, rg = _lockstep(w, orc, spec, iters, count_moves=True)
+    st = rg.stats()
+    assert st["slice_threads"] == 64
+    tr = rg.trace()
+    assert np.all(tr["stepouts"] >= 0) and np.array_equal(tr["hist"].sum(axis=1), tr["steps"])
+    _compare_runs(ro, rg)
 
 
 @pytest.mark.parametrize("d,n,k", [(12, 400, 200), (4, 16384, 8192)])
