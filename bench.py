@@ -631,6 +631,38 @@ def standalone_loglike(w, spec, n_probes: int = 65536, reps: int = 20) -> dict:
             "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak}
 
 
+def iteration_metrics(trace, K, k, spec, w, W):
+    """Per-iteration metrics of the K timed iterations (their records from
+    the device), and the walk's moves from a separate untimed run of the
+    move-counting chain kernels over the same iterations (same seeds, so the
+    same walk)."""
+    import numpy as np
+
+    from paper_2509_24949_amd import binding
+
+    probes = trace["probes"][-K:].astype(float)
+    steps = trace["steps"][-K:].astype(float)
+    out = {"iterations": K,
+           "evals_per_step": float(probes.sum() / steps.sum()),
+           "chain_evals_mean": float(probes.mean() / k),
+           "chain_evals_max_over_mean": float(np.mean(trace["probes_max"][-K:] / (probes / k))),
+           "chain_evals_min_over_mean": float(np.mean(trace["probes_min"][-K:] / (probes / k)))}
+    if w.kernel != 0:
+        return out
+    n_count = min(K, 3)
+    r = binding.Run(spec, binding.opts_for(w, term_frac=0.0, max_iter=W + n_count + 1, count_moves=True))
+    r.step(W + n_count)
+    tr = r.trace()
+    r.close()
+    st = tr["steps"][W:].astype(float).sum()
+    hist = tr["hist"][W:].sum(axis=0)
+    out["moves"] = {"iterations": n_count, "expansions_per_step": float(tr["stepouts"][W:].sum() / st),
+                    "rejected_shrinks_per_step": float(tr["shrinks"][W:].sum() / st),
+                    "moved_fraction": float(tr["accepted"][W:].sum() / st),
+                    "evals_per_step_hist": [int(v) for v in hist[:16]] + [int(hist[16:].sum())]}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -749,6 +781,7 @@ def main():
     log(f"bench: {K} timed iterations in {dt:.3f} s ({evals} evaluations); slice kernel "
         f"{stats['ms_slice'] / K:.3f} ms/iter, select {stats['ms_select'] / K:.3f}, prep {stats['ms_prep'] / K:.3f}, "
         f"term {stats['ms_term'] / K:.3f}")
+    metrics = iteration_metrics(r.trace(), K, w.n_delete, spec, w, W)
     r.close()
     bpe = bins_per_edge(bins_timed, evals)
     flops_launch = bins_timed / K * flops_per_term(w, bpe)
@@ -786,6 +819,7 @@ def main():
                      "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
                      "flops_per_launch": flops_launch, "launch_ms": slice_s * 1e3,
                      "bin_terms_per_launch": bins_timed / K},
+        "iteration_metrics": metrics,
         **run_info,
     }
     if not args.no_standalone:
