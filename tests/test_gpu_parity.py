@@ -438,13 +438,16 @@ def test_chain_configurations_lockstep(torch_cuda, monkeypatch, name, threads, s
     rg.close()
 
 
-@pytest.mark.parametrize("name,iters", [("gauss", 40), ("tf2_1det", 30), ("tf2_3det", 2), ("tf2_3det_rb", 2),
-                                        ("tf2_3det_so", 2), ("tf2_3det_rb_paper", 1)])
-def test_move_counts_lockstep(torch_cuda, name, iters):
-    """The move-counting chain kernels follow the oracle in lockstep, and
-    their per-iteration move counts (bracket expansions, rejected shrink
-    candidates, moved steps, the evaluations-per-step histogram) equal the
-    oracle's sequential walk exactly."""
+@pytest.mark.parametrize("name,iters,stage", [("gauss", 40, "1"), ("tf2_1det", 30, "1"), ("tf2_3det", 2, "1"),
+                                              ("tf2_3det", 2, "0"), ("tf2_3det_rb", 2, "1"), ("tf2_3det_rb", 2, "0"),
+                                              ("tf2_3det_so", 2, "1"), ("tf2_3det_rb_paper", 1, "1")])
+def test_move_counts_lockstep(torch_cuda, monkeypatch, name, iters, stage):
+    """The move-counting chain kernels (tables staged in LDS or read through
+    the caches) follow the oracle in lockstep, and their per-iteration move
+    counts (bracket expansions, rejected shrink candidates, moved steps, the
+    evaluations-per-step histogram) equal the oracle's sequential walk
+    exactly."""
+    monkeypatch.setenv("NS_LDS_TABLES", stage)
     if name == "gauss":
         w = synth.gauss_workload(5, 0.05, mu=np.linspace(0.3, 0.7, 5), n_live=300, n_delete=150)
         orc, spec = oracle.OracleProblem(w), binding.ProblemSpec(w)
@@ -455,9 +458,32 @@ def test_move_counts_lockstep(torch_cuda, name, iters):
     ro, rg = _lockstep(w, orc, spec, iters, count_moves=True)
     st = rg.stats()
     assert st["slice_threads"] == 64
+    if stage == "0":
+        assert st["lds_tables"] == 0
     tr = rg.trace()
     assert np.all(tr["stepouts"] >= 0) and np.array_equal(tr["hist"].sum(axis=1), tr["steps"])
     _compare_runs(ro, rg)
+
+
+@pytest.mark.parametrize("name", ["tf2_3det_mixed", "tf2_3det_rb_mixed"])
+def test_move_counts_mixed_precision(torch_cuda, name):
+    """The mixed-precision move-counting kernels (no oracle lockstep: their
+    decisions follow float sums) keep their records consistent: every step
+    in the histogram, its first moment the evaluation count, and each move
+    count bounded by the walk's structure."""
+    w = synth.workload(name)
+    spec = binding.ProblemSpec(w, *binding.make_data(w))
+    a = binding.Run(spec, binding.opts_for(w, max_iter=4, term_frac=0.0, count_moves=True))
+    a.step(2)
+    tr = a.trace()
+    assert len(tr["iter"]) == 2 and np.all(tr["steps"] == w.n_delete * w.n_steps)
+    assert np.array_equal(tr["hist"].sum(axis=1), tr["steps"])
+    if not tr["hist"][:, -1].any():
+        assert np.array_equal(tr["hist"] @ np.arange(binding.PROBE_HIST), tr["probes"])
+    assert np.all(tr["probes"] >= tr["stepouts"] + tr["accepted"])
+    assert np.all(tr["probes"] <= tr["stepouts"] + tr["shrinks"] + tr["accepted"] + 2 * tr["steps"])
+    assert np.all(tr["accepted"] <= tr["steps"]) and np.all(tr["accepted"] > 0)
+    a.close()
 
 
 @pytest.mark.parametrize("d,n,k", [(12, 400, 200), (4, 16384, 8192)])
