@@ -16,8 +16,11 @@
 //                 two halves of the workgroup computing the intrinsic and the
 //                 extrinsic half of every candidate's source; the walk then
 //                 evaluates independent probes in pairs, each probe's bins
-//                 spread over half the workgroup and reduced once.
-//  * k_term       one workgroup: live evidence, termination flag, counters.
+//                 spread over half the workgroup and reduced once.  A
+//                 separate 64-thread instantiation also counts the walk's
+//                 moves for the per-iteration metrics.
+//  * k_term       one workgroup: live evidence, termination flag, counters,
+//                 the iteration's metrics record.
 //  * k_probe_setup2 (k_probe_setup), k_probe_bins
 //                 batched fused full-grid likelihood in two passes: the probe
 //                 set-up (two threads per probe), then one wavefront per probe
