@@ -202,6 +202,11 @@ def test_gauss_lockstep_and_closed_form(torch_cuda, d, s, n, k):
     zo, zg = _compare_runs(ro, rg)
     if ro.state()["iter"] < iters:
         assert abs(zg["logZ"] - _closed_gauss(mu, s)) < 4 * zg["sigma"] + 0.05
+        # a run that stopped on its criterion (not on capacity) stopped at
+        # the first record below the stopping threshold
+        rem = rg.trace()["log_remaining"]
+        if len(rem) < 999:
+            assert rem[-1] < math.log(w.term_frac) and np.all(rem[:-1] >= math.log(w.term_frac))
     th, l, lw = rg.samples()
     assert abs(np.exp(lw).sum() - 1.0) < 1e-9
 

@@ -824,6 +824,20 @@ def test_iteration_metrics_closed_forms_and_invariants():
     assert np.all(tr["probes_min"] * k <= tr["probes"]) and np.all(tr["probes"] <= tr["probes_max"] * k)
 
 
+def test_iteration_metrics_record_the_stopping_rule():
+    """A run that stops on its remaining-evidence criterion stops at the
+    first iteration whose recorded remaining-evidence term falls below
+    ln(term_frac); every earlier record lies above it."""
+    w = synth.gauss_workload(3, 0.05, mu=[0.4, 0.5, 0.6], n_live=200, n_delete=100)
+    p = oracle.OracleProblem(w)
+    r = oracle.Run(p, oracle.opts_for(w, term_frac=1e-3, max_iter=200))
+    assert r.run()
+    tr = r.trace()
+    rem = tr["log_remaining"]
+    assert len(rem) == r.state()["iter"] < 200
+    assert rem[-1] < math.log(1e-3) and np.all(rem[:-1] >= math.log(1e-3))
+
+
 def test_iteration_metrics_constant_likelihood():
     """A constant likelihood: no probe beats L* (the inequality is strict), so
     a step expands nothing, rejects all max_shrink shrink candidates and keeps
