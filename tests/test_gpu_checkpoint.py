@@ -88,3 +88,40 @@ def test_noise_loglike_parity(torch_cuda, name):
     got = r.noise_loglike()
     r.close()
     assert abs(got - want) <= 1e-12 * abs(want)
+
+
+def test_nan_and_minus_inf_likelihoods_die_first(torch_cuda):
+    """Failure injection through a checkpoint: two live points' log-likelihoods
+    replaced by NaN and by -inf (the sampler orders NaN as -inf, ties going to
+    the lower slot) die first in the next iteration, add nothing to the
+    evidence, and the run still terminates with a finite evidence."""
+    w = synth.gauss_workload(3, 0.05, mu=[0.4, 0.5, 0.6], n_live=200, n_delete=100)
+    spec = binding.ProblemSpec(w)
+    opts = binding.opts_for(w)
+    a = binding.Run(spec, opts)
+    a.step(2)
+    st0 = a.state()
+    _, lam = a.live()
+    blob = bytearray(a.save())
+    a.close()
+    raw = np.ascontiguousarray(lam, dtype=np.float64).tobytes()
+    pos = blob.find(raw)
+    assert pos >= 0 and blob.find(raw, pos + 1) < 0      # the live log-likelihoods, stored once
+    bad = lam.copy()
+    bad[7] = np.nan
+    bad[3] = -np.inf
+    blob[pos:pos + len(raw)] = bad.tobytes()
+    b = binding.Run.load(bytes(blob), spec, opts)
+    b.step(1)
+    d = b.dead()
+    nd = st0["n_dead"]
+    np.testing.assert_array_equal(d["slot"][nd:nd + 2], [3, 7])
+    assert np.isneginf(d["logl"][nd]) and np.isnan(d["logl"][nd + 1])   # the record keeps the raw values
+    assert np.all(np.isneginf(d["logw"][nd:nd + 2]))
+    assert np.all(np.isfinite(d["logw"][nd + 2:nd + 100]))
+    assert np.isfinite(b.state()["logZ"])
+    assert b.run()
+    z = b.logZ(200)
+    assert np.isfinite(z["logZ"]) and np.isfinite(z["sigma"])
+    assert np.all(np.isfinite(b.live()[1]))
+    b.close()
