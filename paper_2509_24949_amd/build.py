@@ -58,7 +58,8 @@ def build(verbose: bool = False) -> str:
     run_all([dev for dev, _, _ in jobs])
     run_all([host for _, host, _ in jobs])
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *[obj for _, _, obj in jobs]]
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *[obj for _, _, obj in jobs],
+           "-lrocprofiler-sdk-roctx"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -412,10 +412,12 @@ extern "C" {
 const char* ns_last_error(void) { return g_err.c_str(); }
 
 int ns_init(ns_run** out, const ns_problem* P, const ns_opts* O, void* stream) {
+  TraceRange range_("ns_init");
   return run_create(out, P, O, static_cast<hipStream_t>(stream), false);
 }
 
 int ns_step_async(ns_run* r, int n_iters) {
+  TraceRange range_("ns_step_async");
   if (!r) return fail(NS_E_ARG, "run is NULL");
   if (n_iters < 0) return fail(NS_E_ARG, "n_iters must be >= 0");
   for (int i = 0; i < n_iters; ++i) {
@@ -476,6 +478,7 @@ int ns_trace(ns_run* r, long cap, ns_iter_t* out, long* n_out) {
 }
 
 int ns_step(ns_run* r, int max_iters, int* done) {
+  TraceRange range_("ns_step");
   int rc = ns_step_async(r, max_iters);
   if (rc) return rc;
   if ((rc = sync_state(r))) return rc;
@@ -499,6 +502,7 @@ int ns_state(ns_run* r, double* logX, double* logZ, double* H, int* iter, long* 
 }
 
 int ns_logZ(ns_run* r, int n_sim, double* logZ, double* sigma_sim, double* sigma_h, double* ess) {
+  TraceRange range_("ns_logZ");
   if (!r) return fail(NS_E_ARG, "run is NULL");
   if (n_sim < 0 || n_sim > 100000) return fail(NS_E_ARG, "n_sim must be in [0, 100000]");
   const int ns_ = n_sim >= 2 ? n_sim : 0;
@@ -528,6 +532,7 @@ int ns_logZ(ns_run* r, int n_sim, double* logZ, double* sigma_sim, double* sigma
 }
 
 int ns_samples(ns_run* r, long cap, double* theta, double* logl, double* logw, long* n_out) {
+  TraceRange range_("ns_samples");
   if (!r) return fail(NS_E_ARG, "run is NULL");
   int rc = sync_state(r);
   if (rc) return rc;
@@ -554,6 +559,7 @@ int ns_samples(ns_run* r, long cap, double* theta, double* logl, double* logw, l
 }
 
 int ns_resample(ns_run* r, long n_out, int* idx, double* theta) {
+  TraceRange range_("ns_resample");
   if (!r) return fail(NS_E_ARG, "run is NULL");
   if (n_out < 1 || n_out > (1L << 30)) return fail(NS_E_ARG, "n_out must be in 1..2^30");
   int rc = sync_state(r);
@@ -610,6 +616,7 @@ int ns_dead(ns_run* r, long cap, double* u, double* logl, double* logx, double* 
 }
 
 int ns_loglike(ns_run* r, const double* u_dev, long n, double* out_dev, int* terms_dev) {
+  TraceRange range_("ns_loglike");
   if (!r) return fail(NS_E_ARG, "run is NULL");
   if (n < 0 || (n > 0 && (!u_dev || !out_dev))) return fail(NS_E_ARG, "bad batch arguments");
   const bool two_pass = r->M.likelihood == NS_LIKE_FULL;   // the full grid stores probe records
@@ -757,6 +764,7 @@ struct ProblemScalars {
 extern "C" {
 
 int ns_save(ns_run* r, void* buf, size_t cap, size_t* n_out) {
+  TraceRange range_("ns_save");
   if (!r) return fail(NS_E_ARG, "run is NULL");
   int rc = sync_state(r);
   if (rc) return rc;
@@ -823,6 +831,7 @@ int ns_save(ns_run* r, void* buf, size_t cap, size_t* n_out) {
 }
 
 int ns_load(ns_run** out, const void* buf, size_t size, void* stream) {
+  TraceRange range_("ns_load");
   if (!out || !buf) return fail(NS_E_ARG, "NULL argument");
   *out = nullptr;
   Reader rd{static_cast<const unsigned char*>(buf), size};

@@ -9,10 +9,23 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "../../include/ns.h"
 #include "ns_internal.h"
 
 namespace ns {
+
+// A named range on the calling thread for the profiler's marker trace
+// (rocprofv3 --marker-trace): each public call of the library opens one for
+// its duration.  Without a profiler attached the calls cost a few
+// nanoseconds.
+struct TraceRange {
+  explicit TraceRange(const char* name) { roctxRangePushA(name); }
+  ~TraceRange() { roctxRangePop(); }
+  TraceRange(const TraceRange&) = delete;
+  TraceRange& operator=(const TraceRange&) = delete;
+};
 
 // Record a message for ns_last_error() and return code.
 int fail(int code, const char* fmt, ...);

@@ -379,6 +379,7 @@ int ns_server_submit(ns_server* s, const ns_problem* P, const ns_opts* O, long l
 }
 
 int ns_server_tick(ns_server* s, int n_iters, int* n_running, int* n_queued, int* n_finished) {
+  TraceRange range_("ns_server_tick");
   if (!s) return fail(NS_E_ARG, "server is NULL");
   if (n_iters < 1 || n_iters > 1000) return fail(NS_E_ARG, "n_iters must be in [1, 1000]");
   int rc = admit(s);
