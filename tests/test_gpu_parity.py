@@ -262,7 +262,8 @@ def _rb_workload(name, nb):
 # tf2_3det_rb: 128 coarse bins, the edge records staged in LDS; the 32 s
 # three-detector serving event 32 with 400 coarse bins, whose records do not
 # fit and are read from the tables
-@pytest.mark.parametrize("name,nb,n", [("tf2_3det_rb", 128, 1031), ("event/32", 400, 257)])
+@pytest.mark.parametrize("name,nb,n", [("tf2_3det_rb", 128, 1031), ("event/32", 400, 257), ("tf2_3det_rb", 1, 257),
+                                     ("tf2_3det_rb", 2, 257), ("tf2_3det_rb", 7, 131)])
 def test_rb_loglike_parity(torch_cuda, name, nb, n):
     """Relative-binning likelihood against the oracle's, to 1e-9 of the
     cancellation scale, including the fiducial point and cube corners."""
@@ -297,6 +298,17 @@ def test_rb_loglike_parity(torch_cuda, name, nb, n):
         k_act = int(np.count_nonzero((hr != 0.0) | (hi != 0.0)))
         n_act = int(np.count_nonzero(edges[:-1] < k_act))
         assert terms[i] == (n_act + 1 if n_act else 0), (i, k_act, n_act)
+
+
+@pytest.mark.parametrize("nb", [1, 3])
+def test_rb_few_coarse_bins_lockstep(torch_cuda, nb):
+    """Relative binning with one and with three coarse bins (every probe's
+    straddling bin among the first few) follows the oracle in lockstep."""
+    w, _ = _rb_workload("tf2_3det_rb", nb)
+    orc, spec = _pair(w)
+    print(f"rb lockstep with {nb} coarse bins", flush=True)
+    ro, rg = _lockstep(w, orc, spec, 2)
+    _compare_runs(ro, rg)
 
 
 def test_rb_iterations_lockstep(torch_cuda):
