@@ -231,6 +231,19 @@ def test_three_detector_iterations_lockstep(torch_cuda, name):
     _compare_runs(ro, rg)
 
 
+@pytest.mark.parametrize("event", [11, 10])
+def test_two_detector_event_lockstep(torch_cuda, event):
+    """Two-detector events run alone (the chain kernels of two-detector
+    networks, which the served runs reach only in their packed form): a 4 s
+    (4017-bin) and an 8 s (8033-bin) event follow the oracle in lockstep."""
+    w = synth.serving_event(event)
+    assert w.n_det == 2
+    orc, spec = _pair(w)
+    print(f"two-detector event {event}: {w.n_bins} bins", flush=True)
+    ro, rg = _lockstep(w, orc, spec, 2)
+    _compare_runs(ro, rg)
+
+
 def test_capacity_and_no_termination(torch_cuda):
     w = synth.gauss_workload(3, 0.05, n_live=100, n_delete=50)
     spec = binding.ProblemSpec(w)
