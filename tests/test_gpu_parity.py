@@ -389,13 +389,16 @@ def test_mixed_precision_loglike_error(torch_cuda, name):
     assert np.max(err / scale) <= 2e-5
 
 
-@pytest.mark.parametrize("name", ["tf2_3det_rb_mixed", "tf2_3det_mixed"])
+@pytest.mark.parametrize("name", ["tf2_3det_rb_mixed", "tf2_3det_mixed", "tf2_1det", "event/11"])
 def test_mixed_chain_kernel_loglike_error(torch_cuda, name):
     """The likelihoods the mixed-form chain kernel leaves in the refilled slots
     after two iterations (its own in-sampler evaluation, relative binning or
-    full grid) against the double-precision oracle at the same points, to
-    2e-5 of the cancellation scale."""
-    w = synth.workload(name)
+    full grid; three, one and two detectors) against the double-precision
+    oracle at the same points, to 2e-5 of the cancellation scale."""
+    if name.startswith("event/"):
+        w, wf = synth.serving_event(int(name[6:])), synth.serving_event(int(name[6:]))
+    else:
+        w, wf = synth.workload(name), synth.workload(name.replace("_rb", "").replace("_mixed", ""))
     orc, spec = _pair(w)
     run = binding.Run(spec, binding.opts_for(w, n_live=512, n_delete=256, precision=binding.NS_MIXED))
     run.step(2)
@@ -403,7 +406,6 @@ def test_mixed_chain_kernel_loglike_error(torch_cuda, name):
     refilled = np.unique(run.dead()["slot"])
     assert len(refilled) >= 256
     u, lam = u[refilled], lam[refilled]
-    wf = synth.workload("tf2_3det")
     orc_full = oracle.OracleProblem(wf, orc.dre, orc.dim)
     _, scale = _scale(wf, orc_full, u)
     lam_o = orc.loglike_batch(u, NTHREADS)
