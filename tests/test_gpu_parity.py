@@ -389,16 +389,18 @@ def test_mixed_precision_loglike_error(torch_cuda, name):
     assert np.max(err / scale) <= 2e-5
 
 
-@pytest.mark.parametrize("name", ["tf2_3det_rb_mixed", "tf2_3det_mixed", "tf2_1det", "event/11"])
+@pytest.mark.parametrize("name", ["tf2_3det_rb_mixed", "tf2_3det_mixed", "tf2_1det", "event/11", "tf2_3det_rb_walk"])
 def test_mixed_chain_kernel_loglike_error(torch_cuda, name):
-    """The likelihoods the mixed-form chain kernel leaves in the refilled slots
-    after two iterations (its own in-sampler evaluation, relative binning or
-    full grid; three, one and two detectors) against the double-precision
-    oracle at the same points, to 2e-5 of the cancellation scale."""
+    """The likelihoods the mixed-form chain kernels leave in the refilled
+    slots after two iterations (their own in-sampler evaluation, relative
+    binning or full grid; three, one and two detectors; slice and random-walk
+    chains) against the double-precision oracle at the same points, to 2e-5
+    of the cancellation scale."""
     if name.startswith("event/"):
         w, wf = synth.serving_event(int(name[6:])), synth.serving_event(int(name[6:]))
     else:
-        w, wf = synth.workload(name), synth.workload(name.replace("_rb", "").replace("_mixed", ""))
+        w = synth.workload(name)
+        wf = synth.workload("tf2_3det" if name.startswith("tf2_3det") else name)
     orc, spec = _pair(w)
     run = binding.Run(spec, binding.opts_for(w, n_live=512, n_delete=256, precision=binding.NS_MIXED))
     run.step(2)
