@@ -266,6 +266,9 @@ def _rb_workload(name, nb):
     if name.startswith("event/"):
         w, wf = synth.serving_event(int(name[6:])), synth.serving_event(int(name[6:]))
         w.likelihood = synth.LIKE_RB
+    elif name == "tf2_3det_so_rb":       # the spin-orbit model with relative binning
+        w, wf = synth.workload("tf2_3det_so"), synth.workload("tf2_3det_so")
+        w.likelihood = synth.LIKE_RB
     else:
         w, wf = synth.workload(name), synth.workload(name.replace("_rb", ""))
     w.rb_n_bins = nb
@@ -276,7 +279,7 @@ def _rb_workload(name, nb):
 # three-detector serving event 32 with 400 coarse bins, whose records do not
 # fit and are read from the tables
 @pytest.mark.parametrize("name,nb,n", [("tf2_3det_rb", 128, 1031), ("event/32", 400, 257), ("tf2_3det_rb", 1, 257),
-                                     ("tf2_3det_rb", 2, 257), ("tf2_3det_rb", 7, 131)])
+                                     ("tf2_3det_rb", 2, 257), ("tf2_3det_rb", 7, 131), ("tf2_3det_so_rb", 128, 515)])
 def test_rb_loglike_parity(torch_cuda, name, nb, n):
     """Relative-binning likelihood against the oracle's, to 1e-9 of the
     cancellation scale, including the fiducial point and cube corners."""
@@ -313,11 +316,12 @@ def test_rb_loglike_parity(torch_cuda, name, nb, n):
         assert terms[i] == (n_act + 1 if n_act else 0), (i, k_act, n_act)
 
 
-@pytest.mark.parametrize("nb", [1, 3])
-def test_rb_few_coarse_bins_lockstep(torch_cuda, nb):
+@pytest.mark.parametrize("name,nb", [("tf2_3det_rb", 1), ("tf2_3det_rb", 3), ("tf2_3det_so_rb", 128)])
+def test_rb_few_coarse_bins_lockstep(torch_cuda, name, nb):
     """Relative binning with one and with three coarse bins (every probe's
-    straddling bin among the first few) follows the oracle in lockstep."""
-    w, _ = _rb_workload("tf2_3det_rb", nb)
+    straddling bin among the first few), and with the spin-orbit waveform,
+    follows the oracle in lockstep."""
+    w, _ = _rb_workload(name, nb)
     orc, spec = _pair(w)
     print(f"rb lockstep with {nb} coarse bins", flush=True)
     ro, rg = _lockstep(w, orc, spec, 2)
