@@ -137,3 +137,16 @@ def test_walk_kernel_options_are_validated():
     assert lib.ns_init(C.byref(out), spec.ref, C.byref(binding.opts_for(w)), None) == binding.NS_E_ARG
     assert b"periodic" in lib.ns_last_error()
     assert out.value is None
+
+
+def test_binding_fails_loudly_without_the_library(monkeypatch):
+    """No fallback: with libns.so absent the binding raises instead of
+    computing anything another way."""
+    monkeypatch.setattr(binding, "_lib", None)
+    monkeypatch.setattr(binding, "LIB_PATH", binding.LIB_PATH + ".absent")
+    with pytest.raises(ImportError):
+        binding.lib()
+    w = synth.gauss_workload(2, 0.1)
+    spec = binding.ProblemSpec(w)
+    with pytest.raises(ImportError):
+        binding.Run(spec, binding.opts_for(w))
