@@ -155,7 +155,8 @@ typedef struct {
                             shrink candidates, moved steps, evaluations per step).  The
                             counting chain kernels run 64 threads per chain; without it the
                             other chain kernels carry no counting code and those fields read
-                            -1 (the histogram 0).  Results are the same either way.  Served
+                            -1 (the histogram 0).  Either way the run makes the same moves
+                            (its likelihood sums differ only in rounding order).  Served
                             runs (ns_server) do not count. */
 } ns_opts;
 
