@@ -155,9 +155,10 @@ typedef struct {
                             shrink candidates, moved steps, evaluations per step).  The
                             counting chain kernels run 64 threads per chain; without it the
                             other chain kernels carry no counting code and those fields read
-                            -1 (the histogram 0).  Either way the run makes the same moves
-                            (its likelihood sums differ only in rounding order).  Served
-                            runs (ns_server) do not count. */
+                            -1 (the histogram 0).  The counting kernels sum the likelihood in
+                            another order, so results agree to rounding (in double precision
+                            both follow the sequential walk; in the mixed form a decision at
+                            the threshold can differ).  Served runs (ns_server) do not count. */
 } ns_opts;
 
 typedef struct ns_run ns_run;
