@@ -1468,8 +1468,8 @@ __global__ __launch_bounds__(1024) void k_prep(RunDev R) { prep_body(R); }
 // with at most H-1 steps per side.
 template <int NC> struct SliceBatch {
   static constexpr int SO = NC / 8;
-  static constexpr int H = NC >= 64 ? 4 : 2;
-  static constexpr int SC = NC >= 128 ? 6 : (NC >= 64 ? 3 : 6);
+  static constexpr int H = NC >= 128 ? 3 : (NC >= 64 ? 4 : 2);
+  static constexpr int SC = NC >= 128 ? 10 : (NC >= 64 ? 3 : 6);
   static_assert(2 * SO + H * H * SC <= NC, "batch layout");
 };
 
@@ -1480,7 +1480,7 @@ template <int NC> struct SliceBatch {
 // they fit) or the edge ratios (relative binning).
 constexpr int SL_CHUNK = 16;                          // steps drawn per chunk
 constexpr int SL_PSTRIDE = (int)((sizeof(ProbeRec) + 15) / 16) * 2;   // doubles per stored record
-constexpr int SL_NU = 10;                             // uniforms per step: width, split, 8 shrink
+constexpr int SL_NU = 14;                             // uniforms per step: width, split, 12 shrink
 constexpr int SL_CNT = PROBE_HIST + 4 + 4 * SL_CHUNK;  // ints of the walk's move counters
 __host__ __device__ constexpr size_t slice_fixed_doubles(int nt, bool mv) {
   return MAX_DIM * MAX_DIM + 16 + SL_CHUNK * MAX_DIM + SL_CHUNK * SL_NU + (size_t)(nt / 2) * SL_PSTRIDE + nt + nt +
@@ -1729,11 +1729,11 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
   for (int s0 = 0; s0 < R.m; s0 += SL_CHUNK) {
     const int cs = (R.m - s0) < SL_CHUNK ? (R.m - s0) : SL_CHUNK;
     // ---- draw the chunk: per step nbd direction blocks (two Box-Muller
-    // pairs each), the width block and two shrink blocks
+    // pairs each), the width block and three shrink blocks
     __syncthreads();
     if constexpr (MV)
       if (s0 > 0) fold(SL_CHUNK);
-    const int per = nbd + 3;
+    const int per = nbd + 1 + (SL_NU - 2) / 4;
     for (int bI = tid; bI < cs * per; bI += NT) {
       const int sl = bI / per, r = bI - sl * per;
       const uint64_t s = (uint64_t)(s0 + sl);
@@ -2025,7 +2025,7 @@ __device__ void slice_body(const ModelDev& M, const Tables& T, const RBTables& R
         if (tid < FB) {
           const int aa = a + tid;
           double ua;
-          if (aa < 8) {
+          if (aa < SL_NU - 2) {
             ua = su[2 + aa];
           } else {
             const u64x4 b = philox(t, (uint64_t)j, (uint64_t)s, purpose_word(P_SHRINK, (uint64_t)(aa >> 2)),
