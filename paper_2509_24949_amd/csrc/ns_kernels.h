@@ -1465,11 +1465,15 @@ __global__ __launch_bounds__(1024) void k_prep(RunDev R) { prep_body(R); }
 // up by two threads (the intrinsic and the extrinsic half of the probe).
 // Slots [0, SO) hold left step-out points, [SO, 2 SO) right ones, the rest
 // the first SC shrink candidates of each bracket the step-out can end in
-// with at most H-1 steps per side.
+// with at most H-1 steps per side.  A step outside the batch (more step-outs
+// or shrink attempts) costs a further batch, so the slots go where steps
+// need them: a side rarely steps out more than twice at these widths, and a
+// step's rejected shrink candidates run past six far more often (measured:
+// 0.6 expansions and 1.7 rejected shrink candidates per step).
 template <int NC> struct SliceBatch {
-  static constexpr int SO = NC / 8;
-  static constexpr int H = NC >= 128 ? 3 : (NC >= 64 ? 4 : 2);
-  static constexpr int SC = NC >= 128 ? 10 : (NC >= 64 ? 3 : 6);
+  static constexpr int SO = NC >= 128 ? NC / 8 : 4;
+  static constexpr int H = NC >= 64 ? 3 : 2;
+  static constexpr int SC = NC >= 128 ? 10 : 6;
   static_assert(2 * SO + H * H * SC <= NC, "batch layout");
 };
 
